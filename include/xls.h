@@ -1,0 +1,213 @@
+/*
+ * xls.h — C ABI of the MI355X subdomain CheFSI engine.
+ *
+ * The engine solves the Kohn-Sham problem of one buffered divide-and-conquer
+ * subdomain (Sec. V-A.2: the global effective potential restricted to the
+ * subdomain box, the atoms whose nonlocal projectors reach it, a core box that
+ * defines the binary partition of unity) by Chebyshev-filtered subspace
+ * iteration (Sec. V-A.3), and assembles the subdomain's core density and
+ * interior weights (Sec. V-A.4).
+ *
+ * Conventions for every call
+ *  - Every entry point returns XLS_OK (0) or a negative status; no C++
+ *    exception crosses the ABI.  xls_last_error() returns a thread-local
+ *    message for the last failure on the calling thread.
+ *  - Output arrays are written only when the call returns XLS_OK.
+ *  - All pointers in this header are HOST pointers unless the name says
+ *    "device".  Input arrays are read during the call and may be freed by the
+ *    caller afterwards; the library owns every device allocation it makes.
+ *  - Hartree atomic units: lengths in bohr, energies in Ha.
+ *  - Grid node (i, j, k) sits at origin + h*(i, j, k); its linear index is
+ *    g = i + n[0]*(j + n[1]*k) (x fastest).  A block of vectors is stored
+ *    column-major N_d x ncols (column c starts at c*N_d).
+ *  - A handle is used by one host thread at a time.  Different handles may
+ *    run concurrently on different streams.  Results are bitwise
+ *    reproducible for the same inputs on the same device (fixed reduction
+ *    orders, no floating-point atomics).
+ *  - Work is issued on the handle's stream (the one given at create, else a
+ *    stream the library creates with default priority).  Calls that return
+ *    host results synchronise that stream before returning.
+ */
+#ifndef XLS_H
+#define XLS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define XLS_OK 0
+#define XLS_ERR_INVALID_ARG (-1)  /* bad size, NULL, NaN/Inf input, unsupported option  */
+#define XLS_ERR_OUT_OF_MEMORY (-2) /* a device allocation failed                        */
+#define XLS_ERR_DEVICE (-3)       /* a HIP runtime call failed                           */
+#define XLS_ERR_NOT_SPD (-4)      /* Cholesky of the overlap matrix M_s failed           */
+#define XLS_ERR_EIG_NOCONV (-5)   /* the dense eigensolver did not converge              */
+#define XLS_ERR_STATE (-6)        /* call not valid in the handle's current state        */
+
+/* ---- enums ---------------------------------------------------------------- */
+enum { XLS_BC_PERIODIC = 0, XLS_BC_DIRICHLET0 = 1 };
+/* Storage / arithmetic precision.  XLS_PREC_BF16X3: FP32 operands split into
+ * (hi, lo) bfloat16 pairs, products hi*hi + hi*lo + lo*hi on MFMA with FP32
+ * accumulation (only meaningful for GEMMs). */
+enum { XLS_PREC_FP64 = 0, XLS_PREC_FP32 = 1, XLS_PREC_BF16X3 = 2 };
+enum { XLS_BOUNDS_GIVEN = 0, XLS_BOUNDS_LANCZOS = 1, XLS_BOUNDS_LEARNED = 2 };
+
+/* ---- subdomain description ---------------------------------------------- */
+
+/* Per-atom Kleinman-Bylander projector set (Sec. V-B.2, "Nonlocal
+ * pseudopotential": projectors grouped by atom, gamma scaling).  Four
+ * projectors s, px, py, pz with radial part exp(-r^2/(2 w^2)) (times x-X etc.
+ * for p), support r^2 < rc^2, each normalised to h^3 sum chi^2 = 1 on the box;
+ * V_nl psi = sum_j gamma_j chi_j (h^3 chi_j^T psi). */
+typedef struct {
+  double rc;          /* cutoff radius (bohr), > 0                      */
+  double gauss_width; /* w (bohr), > 0                                   */
+  double gamma[4];    /* Ha: s, px, py, pz                               */
+} xls_projset_t;
+
+typedef struct {
+  int32_t n[3];            /* grid points per axis, each >= 1                              */
+  double h;                /* grid spacing (bohr), > 0                                     */
+  int32_t bc;              /* XLS_BC_PERIODIC (box = whole periodic cell) or XLS_BC_DIRICHLET0 */
+  int32_t fd_n0;           /* half-width of the FD stencil; must be 6 (12th order, Sec. VI-A) */
+  double origin[3];        /* coordinate of node (0,0,0)                                   */
+  const double* v_eff;     /* [N_d] V_eff restricted to the box (Ha), finite              */
+  int32_t n_atoms;         /* >= 0                                                          */
+  const double* atom_xyz;  /* [3*n_atoms] positions; periodic: one copy per atom            */
+  const xls_projset_t* proj; /* [n_atoms]                                                  */
+  int32_t core_lo[3];      /* core = half-open index box [core_lo, core_hi) (Sec. V-A.2)   */
+  int32_t core_hi[3];
+  int64_t global_offset[3]; /* global index of local node (0,0,0) (may be negative)        */
+  int64_t global_n[3];      /* global grid size, for the periodic local->global map       */
+  int32_t ns;              /* number of vectors N_s, 1 <= ns <= N_d                         */
+  const double* x0;        /* [N_d*ns] column-major start block (caller-seeded)             */
+  const double* lanczos_v0; /* [N_d] Lanczos start vector, or NULL for column 0 of x0       */
+  int32_t filter_prec;     /* storage and filter precision: XLS_PREC_FP64 or XLS_PREC_FP32  */
+  void* stream;            /* hipStream_t to issue work on, or NULL                         */
+} xls_subdomain_desc_t;
+
+typedef struct xls_subdomain_s* xls_subdomain_t;
+
+/* Parameters of a CheFSI run (Sec. V-A.3).
+ * First iteration bounds: XLS_BOUNDS_GIVEN takes (lam_lo, lam_cut, lam_max);
+ * XLS_BOUNDS_LANCZOS runs lanczos_k Lanczos steps once per handle and takes
+ * a0 = theta_min, lam_max = theta_max + |beta_k|, lam_cut = a0 + 0.1(lam_max - a0);
+ * XLS_BOUNDS_LEARNED takes lam_max and lam_cut from the caller (the learned
+ * model's prediction) and a0 from Lanczos' theta_min.  Later iterations of the
+ * same call use a0 = lambda_1 and lam_cut = lambda_ns of the previous
+ * iteration, lam_max unchanged. */
+typedef struct {
+  int32_t bounds_mode;
+  double lam_lo, lam_cut, lam_max;
+  int32_t degree;          /* filter degree m >= 1                                 */
+  int32_t max_iter;        /* >= 1                                                   */
+  double resid_tol;        /* stop when max residual over the gated states <= this (0: never) */
+  int32_t n_gate;          /* gated states (lowest n_gate); <= 0: floor(ns/1.1)     */
+  int32_t lanczos_k;       /* Lanczos steps (<= 0: 20)                              */
+  int32_t gemm_prec;       /* XLS_PREC_*: projection and rotation GEMMs             */
+} xls_chefsi_params_t;
+
+/* ---- core calls ---------------------------------------------------------- */
+
+/* Build a subdomain (Sec. V-A.2, V-B.2): copies V_eff and x0 to the device,
+ * builds the core mask, the local->global map, the per-atom projector support
+ * lists (sorted by grid index), projector values and the reverse CSR over grid
+ * points.  Support rule, evaluated in FP64 without fused multiply-add:
+ * dx = (origin_x + i*h) - X', r2 = (dx*dx + dy*dy) + dz*dz, member iff
+ * r2 < rc*rc; periodic boxes sum the images X' = X + s*n*h, s in {-1,0,1}^3.
+ * Errors: INVALID_ARG (sizes, NULL, non-finite input), OUT_OF_MEMORY, DEVICE. */
+int xls_subdomain_create(const xls_subdomain_desc_t* desc, xls_subdomain_t* out);
+
+/* Run up to p->max_iter CheFSI iterations on the handle's block (Sec. V-A.3):
+ * filter Psi_f = p_m(H) Psi (scaled three-term recurrence, p(a0) = 1);
+ * M_s = Psi_f^T Psi_f and H_s = (Psi_f^T H Psi_f symmetrised); Cholesky
+ * M_s = R^T R; C = R^-T H_s R^-1; C = Z Lambda Z^T; Psi = Psi_f R^-1 Z;
+ * residuals r_n = ||H psi_n - lambda_n psi_n||_2 in FP64 arithmetic.
+ * Outputs: ritz[ns] ascending, resid[ns], *iters_done.  The handle keeps the
+ * rotated block and Ritz values for the next call and for density.
+ * Errors: INVALID_ARG, NOT_SPD (the block is left as it was before the
+ * failing iteration's rotation), EIG_NOCONV, DEVICE. */
+int xls_chefsi_step(xls_subdomain_t s, const xls_chefsi_params_t* p,
+                    double* ritz, double* resid, int32_t* iters_done);
+
+/* Core density and interior weights of the current Ritz pairs (Sec. V-A.4):
+ * g_n = 1/(1 + exp((lambda_n - mu)/sigma)); rho[g] = (2/h^3) sum_n g_n psi_{g,n}^2
+ * on core points and 0 elsewhere; c[n] = sum over core points of psi_{g,n}^2.
+ * Requires a completed xls_chefsi_step (else STATE); sigma > 0. */
+int xls_subdomain_density(xls_subdomain_t s, double mu, double sigma, double* rho, double* c);
+
+void xls_subdomain_destroy(xls_subdomain_t s);
+const char* xls_last_error(void);
+
+/* ---- stage calls (each one row of the hot path, for tests and benchmarks) */
+
+/* HX = H X for a host block X [N_d*ncols] (Sec. V, eq. (ks) operator form):
+ * -1/2 (12th-order FD Laplacian) + V_eff + V_nl, in the handle's filter
+ * precision (FP32 handles round X to FP32).  ncols >= 1. */
+int xls_hamiltonian_apply(xls_subdomain_t s, const double* X, double* HX, int32_t ncols);
+
+/* Replace the handle's block by p_m(H) block (step (1) of Sec. V-A.3), scaled
+ * so that p(a0) = 1: e = (lam_max - lam_cut)/2, c = (lam_max + lam_cut)/2.
+ * Requires a0 < lam_cut < lam_max and degree >= 1. */
+int xls_subdomain_filter(xls_subdomain_t s, int32_t degree, double a0, double lam_cut,
+                         double lam_max);
+
+/* Projection of the handle's block (step (2)): M = B^T B, Hs = sym(B^T H B),
+ * both ns x ns column-major FP64, GEMMs in gemm_prec. */
+int xls_subdomain_project(xls_subdomain_t s, int32_t gemm_prec, double* M, double* Hs);
+
+/* Rotation (step (4)): block <- block * Q, Q ns x ns column-major FP64,
+ * GEMM in gemm_prec. */
+int xls_subdomain_rotate(xls_subdomain_t s, int32_t gemm_prec, const double* Q);
+
+/* FP64 residuals of the handle's block against given values lam[ns]. */
+int xls_subdomain_residual(xls_subdomain_t s, const double* lam, double* resid);
+
+/* Lanczos bounds (k steps, full reorthogonalisation, from the handle's
+ * Lanczos start vector): theta_min and theta_max + |beta_k|. */
+int xls_lanczos_bounds(xls_subdomain_t s, int32_t k, double* theta_min, double* upper);
+
+/* Dense generalized symmetric eigenproblem on the GPU (step (3); the
+ * paper's DSYGVD stage, Sec. V-B.3), FP64: Hs y = lambda M y, n x n column-major
+ * inputs; lam[n] ascending, Y[n*n] with Y^T M Y = I.  Errors: NOT_SPD, EIG_NOCONV. */
+int xls_dense_geneig(int32_t n, const double* Hs, const double* M, double* lam, double* Y);
+
+int xls_subdomain_get_block(xls_subdomain_t s, double* X);       /* [N_d*ns] */
+int xls_subdomain_set_block(xls_subdomain_t s, const double* X); /* [N_d*ns] */
+/* Integer maps: core_mask u8[N_d], global_index i64[N_d]. */
+int xls_subdomain_get_maps(xls_subdomain_t s, uint8_t* core_mask, int64_t* global_index);
+/* sizes[0] = total support slots, sizes[1] = n_atoms.  With NULL arrays only
+ * sizes is written.  offsets i32[n_atoms+1], idx i32[total] (grid index per slot),
+ * val f64[4*total] (slot-major: s, px, py, pz), rev_offsets i32[N_d+1],
+ * rev_slot i32[total] (slots covering each grid point, ascending). */
+int xls_subdomain_get_projectors(xls_subdomain_t s, int64_t* sizes, int32_t* offsets,
+                                 int32_t* idx, double* val, int32_t* rev_offsets,
+                                 int32_t* rev_slot);
+
+/* Split FP32 values into round-to-nearest-even bfloat16 (hi, lo) bit patterns
+ * on the device: hi = bf16(a), lo = bf16(a - hi).  n >= 0. */
+int xls_split_bf16(const float* a, uint16_t* hi, uint16_t* lo, int64_t n);
+
+/* Launch shape of the handle's stencil sweeps in storage precision prec
+ * (XLS_PREC_FP64 or XLS_PREC_FP32): block threads (512 or 1024), ty rows
+ * per tile (0: largest band with <= 4 points per thread), tz planes per
+ * z-chunk (0: the whole box).  The shape changes scheduling only, never the
+ * arithmetic of a grid point.  Errors: INVALID_ARG when the tile does not fit
+ * (LDS, registers, halo budget). */
+int xls_subdomain_tune(xls_subdomain_t s, int32_t prec, int32_t block, int32_t ty, int32_t tz);
+
+/* Per-stage device time of the handle's last xls_chefsi_step, from HIP events
+ * on the handle's stream when profiling is on (xls_set_profiling(1)).
+ * ms[0] filter (all m sweeps), ms[1] H*Psi_f, ms[2] projection GEMMs,
+ * ms[3] dense FP64, ms[4] rotation, ms[5] residual, ms[6] total, ms[7] sum of
+ * the fused-filter stencil kernels alone (events around each launch);
+ * counts[0] filter launches.  Returns the number of values written. */
+int xls_set_profiling(int32_t on);
+int xls_get_stage_times(xls_subdomain_t s, double* ms, int64_t* counts, int32_t cap);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* XLS_H */

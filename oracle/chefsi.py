@@ -151,11 +151,19 @@ def rayleigh_ritz(apply_H, Psi_f: np.ndarray):
 
 
 def generalized_eigh(Hs: np.ndarray, M: np.ndarray):
-    """H_s y = lambda M y via Cholesky M = R^T R, C = R^-T H_s R^-1, eigh, Y = R^-1 Z."""
+    """H_s y = lambda M y via Cholesky M = R^T R, C = R^-T H_s R^-1, eigh, Y = R^-1 Z.
+
+    Raises NotSPD when a Cholesky pivot is <= n * eps * M_kk (not positive
+    definite, or numerically singular, e.g. duplicated columns)."""
     try:
         R = sla.cholesky(M, lower=False)
     except np.linalg.LinAlgError as exc:
         raise NotSPD(str(exc)) from exc
+    # a pivot R_kk^2 at or below n*eps*M_kk is numerically zero: M is singular
+    n = M.shape[0]
+    piv = np.diag(R) ** 2
+    if np.any(piv <= n * np.finfo(np.float64).eps * np.diag(M)):
+        raise NotSPD("numerically singular overlap matrix")
     A = sla.solve_triangular(R, Hs, trans="T", lower=False)        # R^-T H_s
     C = sla.solve_triangular(R, A.T, trans="T", lower=False).T     # (R^-T H_s) R^-1
     C = 0.5 * (C + C.T)

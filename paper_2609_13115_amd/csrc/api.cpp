@@ -1,0 +1,915 @@
+// C ABI of the subdomain CheFSI engine: handle lifetime, argument checks,
+// error mapping, and the orchestration of one CheFSI iteration (Sec. V-A.3)
+// from the stage kernels.  Every numerical step runs in the HIP kernels; the
+// host only computes the scalar filter coefficients and makes the
+// convergence decisions.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "xls_internal.h"
+
+namespace xls {
+
+namespace {
+thread_local std::string g_last_error;
+bool g_profiling = false;
+}  // namespace
+
+void fail(int code, const std::string& msg) { throw Error{code, msg}; }
+
+void check_hip(hipError_t e, const char* what, const char* file, int line) {
+  if (e == hipSuccess) return;
+  const int code = (e == hipErrorOutOfMemory) ? XLS_ERR_OUT_OF_MEMORY : XLS_ERR_DEVICE;
+  fail(code, std::string(what) + ": " + hipGetErrorString(e) + " (" + file + ":" + std::to_string(line) + ")");
+}
+
+namespace {
+
+template <typename T>
+T* dalloc(size_t n) {
+  void* p = nullptr;
+  if (n == 0) n = 1;
+  const hipError_t e = hipMalloc(&p, n * sizeof(T));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    fail(XLS_ERR_OUT_OF_MEMORY, "device allocation of " + std::to_string(n * sizeof(T)) + " bytes failed");
+  }
+  return static_cast<T*>(p);
+}
+
+void dfree(void* p) {
+  if (p) (void)hipFree(p);
+}
+
+template <typename T>
+T* dupload(const std::vector<T>& h, hipStream_t st) {
+  T* d = dalloc<T>(h.size());
+  if (!h.empty()) XLS_HIP(hipMemcpyAsync(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, st));
+  return d;
+}
+
+bool finite_all(const double* p, int64_t n) {
+  for (int64_t i = 0; i < n; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+struct StageTimer {
+  bool on;
+  hipStream_t st;
+  std::vector<hipEvent_t> ev;
+  explicit StageTimer(bool enabled, hipStream_t s) : on(enabled), st(s) {}
+  void mark() {
+    if (!on) return;
+    hipEvent_t e;
+    XLS_HIP(hipEventCreate(&e));
+    XLS_HIP(hipEventRecord(e, st));
+    ev.push_back(e);
+  }
+  ~StageTimer() {
+    for (auto e : ev) (void)hipEventDestroy(e);
+  }
+  double ms(size_t a, size_t b) const {
+    float t = 0;
+    if (!on || b >= ev.size()) return 0.0;
+    (void)hipEventElapsedTime(&t, ev[a], ev[b]);
+    return t;
+  }
+};
+
+}  // namespace
+}  // namespace xls
+
+using namespace xls;
+
+struct xls_subdomain_s {
+  int n[3] = {0, 0, 0};
+  double h = 0;
+  int bc = 0;
+  int prec = XLS_PREC_FP64;
+  int ns = 0;
+  int64_t nd = 0, ld = 0;
+  hipStream_t st = nullptr;
+  bool own_stream = false;
+  SetupTables tab;
+  int n_atoms = 0;
+  // device: operator tables in both precisions
+  double* v64 = nullptr;
+  float* v32 = nullptr;
+  double* val64 = nullptr;
+  float* val32 = nullptr;
+  int32_t *rev_off = nullptr, *rev_slot = nullptr, *slot_atom = nullptr, *sup_off = nullptr,
+          *sup_idx = nullptr;
+  double* gamma = nullptr;
+  uint8_t* mask = nullptr;
+  OpTables<double> op64;
+  OpTables<float> op32;
+  StencilLaunch cfg64, cfg32;
+  // blocks
+  void* blk[2] = {nullptr, nullptr};
+  int cur = 0;
+  void* alpha = nullptr;      // [ns][nproj] in storage type
+  double* alpha64 = nullptr;  // [ns][nproj] FP64 (residuals of FP32 blocks)
+  double* partial = nullptr;
+  size_t partial_elems = 0;
+  double* lam_dev = nullptr;
+  double* resid_dev = nullptr;
+  double* Mdev = nullptr;
+  double* Hsdev = nullptr;
+  double* Ydev = nullptr;
+  float* bwork = nullptr;
+  double* gwork = nullptr;
+  size_t gwork_elems = 0;
+  DenseWork dw;
+  double* vsmall = nullptr;  // density / Lanczos scalars
+  double* rho_dev = nullptr;
+  double* cpart = nullptr;
+  double* gocc = nullptr;
+  // Lanczos
+  std::vector<double> lanczos_v0;
+  void* lz = nullptr;  // [nd * (kmax + 2)]
+  int lz_cols = 0;
+  bool have_lanczos = false;
+  double lz_lo = 0, lz_up = 0;
+  int lz_k = 0;
+  // state
+  std::vector<double> ritz;
+  bool have_ritz = false;
+  std::vector<double> stage_ms;
+  int64_t filter_launches = 0;
+  double filter_kernel_ms = 0.0;  // sum over fused-filter stencil launches (profiling on)
+  std::vector<hipEvent_t> fev;
+  int last_sweeps = 0;
+
+  ~xls_subdomain_s() {
+    void* ps[] = {v64, v32, val64, val32, rev_off, rev_slot, slot_atom, sup_off, sup_idx, gamma, mask,
+                  blk[0], blk[1], alpha, alpha64, partial, lam_dev, resid_dev, Mdev, Hsdev, Ydev, bwork,
+                  gwork, vsmall, rho_dev, cpart, gocc, lz};
+    for (void* p : ps) dfree(p);
+    for (auto e : fev) (void)hipEventDestroy(e);
+    dense_free(dw);
+    if (own_stream && st) (void)hipStreamDestroy(st);
+  }
+  size_t esize() const { return prec == XLS_PREC_FP32 ? 4 : 8; }
+  int nproj() const { return 4 * n_atoms; }
+};
+
+namespace {
+
+void validate_desc(const xls_subdomain_desc_t* d) {
+  if (!d) fail(XLS_ERR_INVALID_ARG, "desc is NULL");
+  for (int a = 0; a < 3; ++a)
+    if (d->n[a] < 1) fail(XLS_ERR_INVALID_ARG, "grid size must be >= 1");
+  const int64_t nd = static_cast<int64_t>(d->n[0]) * d->n[1] * d->n[2];
+  if (nd >= (int64_t(1) << 31)) fail(XLS_ERR_INVALID_ARG, "N_d must be < 2^31");
+  if (!(d->h > 0) || !std::isfinite(d->h)) fail(XLS_ERR_INVALID_ARG, "h must be finite and > 0");
+  if (d->bc != XLS_BC_PERIODIC && d->bc != XLS_BC_DIRICHLET0) fail(XLS_ERR_INVALID_ARG, "unknown bc");
+  if (d->fd_n0 != kRadius) fail(XLS_ERR_INVALID_ARG, "fd_n0 must be 6");
+  if (d->n[0] > 1024) fail(XLS_ERR_INVALID_ARG, "n[0] must be <= 1024");
+  if (!d->v_eff || !finite_all(d->v_eff, nd)) fail(XLS_ERR_INVALID_ARG, "v_eff NULL or not finite");
+  if (!finite_all(d->origin, 3)) fail(XLS_ERR_INVALID_ARG, "origin not finite");
+  if (d->n_atoms < 0) fail(XLS_ERR_INVALID_ARG, "n_atoms < 0");
+  if (d->n_atoms > 0 && (!d->atom_xyz || !d->proj)) fail(XLS_ERR_INVALID_ARG, "atoms NULL");
+  if (d->n_atoms > 0 && !finite_all(d->atom_xyz, 3 * static_cast<int64_t>(d->n_atoms)))
+    fail(XLS_ERR_INVALID_ARG, "atom positions not finite");
+  for (int a = 0; a < d->n_atoms; ++a) {
+    const xls_projset_t& p = d->proj[a];
+    if (!(p.rc > 0) || !(p.gauss_width > 0) || !std::isfinite(p.rc) || !std::isfinite(p.gauss_width) ||
+        !finite_all(p.gamma, 4))
+      fail(XLS_ERR_INVALID_ARG, "bad projector set");
+  }
+  for (int a = 0; a < 3; ++a) {
+    if (d->core_lo[a] < 0 || d->core_hi[a] > d->n[a] || d->core_lo[a] > d->core_hi[a])
+      fail(XLS_ERR_INVALID_ARG, "core box outside the grid");
+    if (d->global_n[a] < 1) fail(XLS_ERR_INVALID_ARG, "global_n must be >= 1");
+  }
+  if (d->ns < 1 || d->ns > nd) fail(XLS_ERR_INVALID_ARG, "ns must be in [1, N_d]");
+  if (!d->x0 || !finite_all(d->x0, nd * d->ns)) fail(XLS_ERR_INVALID_ARG, "x0 NULL or not finite");
+  if (d->lanczos_v0 && !finite_all(d->lanczos_v0, nd)) fail(XLS_ERR_INVALID_ARG, "lanczos_v0 not finite");
+  if (d->filter_prec != XLS_PREC_FP64 && d->filter_prec != XLS_PREC_FP32)
+    fail(XLS_ERR_INVALID_ARG, "filter_prec must be FP64 or FP32");
+}
+
+template <typename TS>
+TS* B(xls_subdomain_s* s, int i) {
+  return static_cast<TS*>(s->blk[i]);
+}
+
+template <typename TS>
+const OpTables<typename std::conditional<std::is_same<TS, float>::value, float, double>::type>& op_of(
+    xls_subdomain_s* s);
+template <>
+const OpTables<double>& op_of<double>(xls_subdomain_s* s) {
+  return s->op64;
+}
+template <>
+const OpTables<float>& op_of<float>(xls_subdomain_s* s) {
+  return s->op32;
+}
+template <typename TS>
+const StencilLaunch& cfg_of(xls_subdomain_s* s) {
+  return std::is_same<TS, float>::value ? s->cfg32 : s->cfg64;
+}
+
+// out = H y in the storage precision.
+template <typename TS>
+void apply_H(xls_subdomain_s* s, const TS* y, TS* out, int ncols, TS* alpha) {
+  const auto& op = op_of<TS>(s);
+  launch_proj_forward<TS, TS>(op, y, s->ld, ncols, alpha, s->st);
+  launch_stencil<TS, TS>(kApply, op, y, s->ld, ncols, alpha, out, nullptr, 1.0, 0.0, 0.0, nullptr, nullptr,
+                         nullptr, s->st, cfg_of<TS>(s));
+}
+
+// Block <- p_m(H) block by the scaled three-term recurrence (the oracle's
+// filter_coefficients, same scalar sequence).  With profiling on, HIP events
+// bracket every fused-filter stencil launch on the handle's stream.
+template <typename TS>
+void filter_block(xls_subdomain_s* s, int m, double a0, double lc, double lmax) {
+  const double e = (lmax - lc) / 2.0;
+  const double c = (lmax + lc) / 2.0;
+  const double sigma1 = e / (a0 - c);
+  const double tau = 2.0 / sigma1;
+  const auto& op = op_of<TS>(s);
+  const auto& cfg = cfg_of<TS>(s);
+  TS* alpha = static_cast<TS*>(s->alpha);
+  const bool prof = g_profiling;
+  if (prof && static_cast<int>(s->fev.size()) < 2 * m) {
+    for (auto ev : s->fev) (void)hipEventDestroy(ev);
+    s->fev.assign(2 * m, nullptr);
+    for (auto& ev : s->fev) XLS_HIP(hipEventCreate(&ev));
+  }
+  int y0 = s->cur, y1 = 1 - s->cur;
+  // Y1 = (sigma1/e)(H X - c X)
+  launch_proj_forward<TS, TS>(op, B<TS>(s, y0), s->ld, s->ns, alpha, s->st);
+  if (prof) XLS_HIP(hipEventRecord(s->fev[0], s->st));
+  launch_stencil<TS, TS>(kFilter, op, B<TS>(s, y0), s->ld, s->ns, alpha, B<TS>(s, y1), nullptr, sigma1 / e,
+                         c, 0.0, nullptr, nullptr, nullptr, s->st, cfg);
+  if (prof) XLS_HIP(hipEventRecord(s->fev[1], s->st));
+  s->filter_launches++;
+  double sig = sigma1;
+  for (int k = 1; k < m; ++k) {
+    const double signew = 1.0 / (tau - sig);
+    // Y_{k+1} overwrites Y_{k-1} in place
+    launch_proj_forward<TS, TS>(op, B<TS>(s, y1), s->ld, s->ns, alpha, s->st);
+    if (prof) XLS_HIP(hipEventRecord(s->fev[2 * k], s->st));
+    launch_stencil<TS, TS>(kFilter, op, B<TS>(s, y1), s->ld, s->ns, alpha, B<TS>(s, y0), B<TS>(s, y0),
+                           2.0 * signew / e, c, sig * signew, nullptr, nullptr, nullptr, s->st, cfg);
+    if (prof) XLS_HIP(hipEventRecord(s->fev[2 * k + 1], s->st));
+    s->filter_launches++;
+    sig = signew;
+    std::swap(y0, y1);
+  }
+  s->cur = y1;
+  if (prof) {
+    XLS_HIP(hipEventSynchronize(s->fev[2 * m - 1]));
+    for (int k = 0; k < m; ++k) {
+      float t = 0;
+      XLS_HIP(hipEventElapsedTime(&t, s->fev[2 * k], s->fev[2 * k + 1]));
+      s->filter_kernel_ms += t;
+    }
+  }
+}
+
+// M = B^T B and Hs = sym(B^T H B) of the current block (W = H B in the other buffer).
+template <typename TS>
+void project_block(xls_subdomain_s* s, int gprec) {
+  TS* Bc = B<TS>(s, s->cur);
+  TS* W = B<TS>(s, 1 - s->cur);
+  apply_H<TS>(s, Bc, W, s->ns, static_cast<TS*>(s->alpha));
+  gemm_tn<TS>(gprec, Bc, s->ld, Bc, s->ld, s->ns, s->ns, s->nd, s->Mdev, s->ns, 1, 0, s->gwork,
+              s->gwork_elems, s->st);
+  gemm_tn<TS>(gprec, Bc, s->ld, W, s->ld, s->ns, s->ns, s->nd, s->Hsdev, s->ns, 0, 1, s->gwork,
+              s->gwork_elems, s->st);
+}
+
+template <typename TS>
+void rotate_block(xls_subdomain_s* s, int gprec, const double* Ydev) {
+  TS* Bc = B<TS>(s, s->cur);
+  TS* O = B<TS>(s, 1 - s->cur);
+  gemm_nn<TS>(gprec, Bc, s->ld, Ydev, s->ns, static_cast<int>(s->nd), s->ns, s->ns, O, s->ld, s->bwork, s->st);
+  s->cur = 1 - s->cur;
+}
+
+// FP64 residual norms of the current block against lam (device).
+template <typename TS>
+void residual_block(xls_subdomain_s* s, const double* lam_dev, double* resid_dev) {
+  TS* Bc = B<TS>(s, s->cur);
+  launch_proj_forward<TS, double>(s->op64, Bc, s->ld, s->ns, s->alpha64, s->st);
+  StencilLaunch cfg = s->cfg64;
+  launch_stencil<TS, double>(kResid, s->op64, Bc, s->ld, s->ns, s->alpha64, nullptr, nullptr, 1.0, 0.0, 0.0,
+                             lam_dev, s->partial, resid_dev, s->st, cfg);
+}
+
+template <typename TS>
+void lanczos_run(xls_subdomain_s* s, int k) {
+  k = static_cast<int>(std::min<int64_t>(k, s->nd));
+  if (!s->lz || s->lz_cols < k + 2) {
+    dfree(s->lz);
+    s->lz = nullptr;
+    s->lz = dalloc<TS>(static_cast<size_t>(s->nd) * (k + 2));
+    s->lz_cols = k + 2;
+  }
+  TS* V = static_cast<TS*>(s->lz);
+  TS* w = V + static_cast<int64_t>(s->nd) * (k + 1);
+  double* al = s->vsmall;         // [k]
+  double* be = s->vsmall + 64;    // [k]
+  double* coef = s->vsmall + 128; // [k]
+  double* nrm = s->vsmall + 192;
+  double* part = s->vsmall + 256;  // [256]
+  const int nblocks = 256;
+  // v_1 = v0 / ||v0||
+  std::vector<TS> hv(s->nd);
+  for (int64_t i = 0; i < s->nd; ++i) hv[i] = static_cast<TS>(s->lanczos_v0[i]);
+  XLS_HIP(hipMemcpyAsync(w, hv.data(), s->nd * sizeof(TS), hipMemcpyHostToDevice, s->st));
+  launch_dot<TS>(w, w, s->nd, part, nblocks, nrm, 1, s->st);
+  launch_scale_to<TS>(V, w, nrm, s->nd, s->st);
+  TS* alph = static_cast<TS*>(s->alpha);
+  std::vector<double> ha, hb;
+  int keff = k;
+  for (int j = 0; j < k; ++j) {
+    TS* vj = V + static_cast<int64_t>(j) * s->nd;
+    apply_H<TS>(s, vj, w, 1, alph);
+    launch_dot<TS>(vj, w, s->nd, part, nblocks, al + j, 0, s->st);
+    launch_lanczos_update<TS>(w, vj, j > 0 ? vj - s->nd : nullptr, al + j, j > 0 ? be + j - 1 : nullptr, s->nd,
+                              s->st);
+    gemm_tn<TS>(XLS_PREC_FP64, V, s->nd, w, s->nd, j + 1, 1, s->nd, coef, j + 1, 0, 0, s->gwork,
+                s->gwork_elems, s->st);
+    launch_reorth<TS>(w, V, s->nd, coef, j + 1, s->nd, s->st);
+    launch_dot<TS>(w, w, s->nd, part, nblocks, be + j, 1, s->st);
+    double ab[2];
+    XLS_HIP(hipMemcpyAsync(&ab[0], al + j, 8, hipMemcpyDeviceToHost, s->st));
+    XLS_HIP(hipMemcpyAsync(&ab[1], be + j, 8, hipMemcpyDeviceToHost, s->st));
+    XLS_HIP(hipStreamSynchronize(s->st));
+    ha.push_back(ab[0]);
+    hb.push_back(ab[1]);
+    double scale = 0;
+    for (double x : ha) scale = std::max(scale, std::fabs(x));
+    for (double x : hb) scale = std::max(scale, x);
+    if (ab[1] <= 1e-12 * scale) {  // invariant Krylov space
+      keff = j + 1;
+      break;
+    }
+    launch_scale_to<TS>(V + static_cast<int64_t>(j + 1) * s->nd, w, be + j, s->nd, s->st);
+  }
+  launch_tridiag_extremes(al, be, keff, nrm, s->st);
+  double ext[2];
+  XLS_HIP(hipMemcpyAsync(ext, nrm, 16, hipMemcpyDeviceToHost, s->st));
+  XLS_HIP(hipStreamSynchronize(s->st));
+  s->lz_lo = ext[0];
+  s->lz_up = ext[1] + std::fabs(hb[keff - 1]);
+  s->lz_k = k;
+  s->have_lanczos = true;
+}
+
+template <typename TS>
+int chefsi_impl(xls_subdomain_s* s, const xls_chefsi_params_t* p, double* ritz, double* resid,
+                int32_t* iters_done) {
+  if (p->degree < 1 || p->max_iter < 1) fail(XLS_ERR_INVALID_ARG, "degree and max_iter must be >= 1");
+  const int gprec = p->gemm_prec;
+  if (gprec < XLS_PREC_FP64 || gprec > XLS_PREC_BF16X3) fail(XLS_ERR_INVALID_ARG, "bad gemm_prec");
+  if (std::is_same<TS, double>::value && gprec != XLS_PREC_FP64)
+    fail(XLS_ERR_INVALID_ARG, "FP64 handles run FP64 GEMMs");
+  const int ns = s->ns;
+  const int gate = p->n_gate > 0 ? std::min(p->n_gate, ns) : std::max(1, static_cast<int>(std::floor(ns / 1.1 + 1e-9)));
+  double a0, lc, lmax;
+  if (p->bounds_mode == XLS_BOUNDS_GIVEN) {
+    a0 = p->lam_lo;
+    lc = p->lam_cut;
+    lmax = p->lam_max;
+  } else if (p->bounds_mode == XLS_BOUNDS_LANCZOS || p->bounds_mode == XLS_BOUNDS_LEARNED) {
+    const int k = p->lanczos_k > 0 ? p->lanczos_k : 20;
+    if (!s->have_lanczos || s->lz_k != k) lanczos_run<TS>(s, std::min(k, 60));
+    a0 = s->lz_lo;
+    if (p->bounds_mode == XLS_BOUNDS_LANCZOS) {
+      lmax = s->lz_up;
+      lc = a0 + 0.1 * (lmax - a0);
+    } else {
+      lmax = p->lam_max;
+      lc = p->lam_cut;
+    }
+  } else {
+    fail(XLS_ERR_INVALID_ARG, "unknown bounds_mode");
+  }
+  if (!(a0 < lc && lc < lmax) || !std::isfinite(a0) || !std::isfinite(lmax))
+    fail(XLS_ERR_INVALID_ARG, "bounds must satisfy a0 < lam_cut < lam_max");
+  std::vector<double> hl(ns), hr(ns);
+  int it = 0;
+  s->stage_ms.assign(8, 0.0);
+  s->filter_launches = 0;
+  s->filter_kernel_ms = 0.0;
+  for (; it < p->max_iter;) {
+    StageTimer tm(g_profiling, s->st);
+    tm.mark();
+    filter_block<TS>(s, p->degree, a0, lc, lmax);
+    tm.mark();
+    {
+      TS* Bc = B<TS>(s, s->cur);
+      TS* W = B<TS>(s, 1 - s->cur);
+      apply_H<TS>(s, Bc, W, s->ns, static_cast<TS*>(s->alpha));
+      tm.mark();
+      gemm_tn<TS>(gprec, Bc, s->ld, Bc, s->ld, ns, ns, s->nd, s->Mdev, ns, 1, 0, s->gwork, s->gwork_elems,
+                  s->st);
+      gemm_tn<TS>(gprec, Bc, s->ld, W, s->ld, ns, ns, s->nd, s->Hsdev, ns, 0, 1, s->gwork, s->gwork_elems,
+                  s->st);
+    }
+    tm.mark();
+    int sweeps = 0;
+    const int rc = dense_geneig(s->dw, s->Hsdev, s->Mdev, s->Ydev, s->st, &sweeps);
+    s->last_sweeps = sweeps;
+    if (rc != XLS_OK) {
+      fail(rc, rc == XLS_ERR_NOT_SPD ? "overlap matrix M_s is not positive definite"
+                                     : "dense eigensolver did not converge");
+    }
+    XLS_HIP(hipMemcpyAsync(s->lam_dev, s->dw.lam, ns * 8, hipMemcpyDeviceToDevice, s->st));
+    tm.mark();
+    rotate_block<TS>(s, gprec, s->Ydev);
+    tm.mark();
+    residual_block<TS>(s, s->lam_dev, s->resid_dev);
+    tm.mark();
+    XLS_HIP(hipMemcpyAsync(hl.data(), s->lam_dev, ns * 8, hipMemcpyDeviceToHost, s->st));
+    XLS_HIP(hipMemcpyAsync(hr.data(), s->resid_dev, ns * 8, hipMemcpyDeviceToHost, s->st));
+    XLS_HIP(hipStreamSynchronize(s->st));
+    if (g_profiling) {
+      for (int k = 0; k < 6; ++k) s->stage_ms[k] += tm.ms(k, k + 1);
+      s->stage_ms[6] += tm.ms(0, 6);
+      s->stage_ms[7] = s->filter_kernel_ms;
+    }
+    ++it;
+    s->ritz = hl;
+    s->have_ritz = true;
+    a0 = hl[0];
+    lc = hl[ns - 1];
+    if (!(a0 < lc && lc < lmax)) break;  // degenerate bounds: stop with what we have
+    if (p->resid_tol > 0) {
+      double mx = 0;
+      for (int k = 0; k < gate; ++k) mx = std::max(mx, hr[k]);
+      if (mx <= p->resid_tol) break;
+    }
+  }
+  std::memcpy(ritz, hl.data(), ns * 8);
+  std::memcpy(resid, hr.data(), ns * 8);
+  if (iters_done) *iters_done = it;
+  return XLS_OK;
+}
+
+template <typename F>
+int guarded(F&& f) {
+  try {
+    return f();
+  } catch (const Error& e) {
+    g_last_error = e.msg;
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
+    return XLS_ERR_OUT_OF_MEMORY;
+  } catch (...) {
+    g_last_error = "unexpected internal error";
+    return XLS_ERR_DEVICE;
+  }
+}
+
+template <typename TS>
+void upload_block(xls_subdomain_s* s, const double* X, void* dst, int ncols) {
+  const int64_t n = s->nd * ncols;
+  if (std::is_same<TS, double>::value) {
+    XLS_HIP(hipMemcpyAsync(dst, X, n * 8, hipMemcpyHostToDevice, s->st));
+  } else {
+    std::vector<float> tmp(n);
+    for (int64_t i = 0; i < n; ++i) tmp[i] = static_cast<float>(X[i]);
+    XLS_HIP(hipMemcpyAsync(dst, tmp.data(), n * 4, hipMemcpyHostToDevice, s->st));
+    XLS_HIP(hipStreamSynchronize(s->st));
+  }
+}
+
+template <typename TS>
+void download_block(xls_subdomain_s* s, const void* src, double* X, int ncols) {
+  const int64_t n = s->nd * ncols;
+  if (std::is_same<TS, double>::value) {
+    XLS_HIP(hipMemcpyAsync(X, src, n * 8, hipMemcpyDeviceToHost, s->st));
+    XLS_HIP(hipStreamSynchronize(s->st));
+  } else {
+    std::vector<float> tmp(n);
+    XLS_HIP(hipMemcpyAsync(tmp.data(), src, n * 4, hipMemcpyDeviceToHost, s->st));
+    XLS_HIP(hipStreamSynchronize(s->st));
+    for (int64_t i = 0; i < n; ++i) X[i] = tmp[i];
+  }
+}
+
+template <typename F>
+auto by_prec(xls_subdomain_s* s, F&& f) {
+  if (s->prec == XLS_PREC_FP32) return f(float{});
+  return f(double{});
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* xls_last_error(void) { return g_last_error.c_str(); }
+
+int xls_set_profiling(int32_t on) {
+  g_profiling = on != 0;
+  return XLS_OK;
+}
+
+int xls_subdomain_create(const xls_subdomain_desc_t* d, xls_subdomain_t* out) {
+  return guarded([&]() -> int {
+    if (!out) fail(XLS_ERR_INVALID_ARG, "out is NULL");
+    validate_desc(d);
+    auto* s = new xls_subdomain_s();
+    try {
+      for (int a = 0; a < 3; ++a) s->n[a] = d->n[a];
+      s->h = d->h;
+      s->bc = d->bc;
+      s->prec = d->filter_prec;
+      s->ns = d->ns;
+      s->nd = static_cast<int64_t>(d->n[0]) * d->n[1] * d->n[2];
+      s->ld = s->nd;
+      if (d->stream) {
+        s->st = static_cast<hipStream_t>(d->stream);
+      } else {
+        XLS_HIP(hipStreamCreateWithFlags(&s->st, hipStreamNonBlocking));
+        s->own_stream = true;
+      }
+      build_setup(*d, s->tab);
+      s->n_atoms = d->n_atoms;
+      const int64_t nd = s->nd;
+      const size_t total = s->tab.sup_idx.size();
+      // operator tables
+      std::vector<double> v(d->v_eff, d->v_eff + nd);
+      s->v64 = dupload(v, s->st);
+      std::vector<float> v32(v.begin(), v.end());
+      s->v32 = dupload(v32, s->st);
+      s->val64 = dupload(s->tab.sup_val, s->st);
+      std::vector<float> val32(s->tab.sup_val.begin(), s->tab.sup_val.end());
+      s->val32 = dupload(val32, s->st);
+      s->rev_off = dupload(s->tab.rev_off, s->st);
+      s->rev_slot = dupload(s->tab.rev_slot, s->st);
+      s->slot_atom = dupload(s->tab.slot_atom, s->st);
+      s->sup_off = dupload(s->tab.sup_off, s->st);
+      s->sup_idx = dupload(s->tab.sup_idx, s->st);
+      s->gamma = dupload(s->tab.gamma, s->st);
+      s->mask = dupload(s->tab.core_mask, s->st);
+      (void)total;
+      auto fill_op = [&](auto& op, auto* vv, auto* val) {
+        op.v = vv;
+        op.slot_val = val;
+        op.rev_off = s->rev_off;
+        op.rev_slot = s->rev_slot;
+        op.slot_atom = s->slot_atom;
+        op.sup_off = s->sup_off;
+        op.sup_idx = s->sup_idx;
+        op.gamma = s->gamma;
+        op.n_atoms = s->n_atoms;
+        op.nx = s->n[0];
+        op.ny = s->n[1];
+        op.nz = s->n[2];
+        op.periodic = s->bc == XLS_BC_PERIODIC;
+        op.h = s->h;
+      };
+      fill_op(s->op64, s->v64, s->val64);
+      fill_op(s->op32, s->v32, s->val32);
+      s->cfg64.block = 512;
+      s->cfg32.block = 512;
+      stencil_validate(s->n[0], s->n[1], s->n[2], s->bc == XLS_BC_PERIODIC, 8, s->cfg64);
+      stencil_validate(s->n[0], s->n[1], s->n[2], s->bc == XLS_BC_PERIODIC, 4, s->cfg32);
+      // blocks and work
+      const size_t es = s->esize();
+      const size_t bl = static_cast<size_t>(s->ld) * s->ns;
+      s->blk[0] = es == 4 ? static_cast<void*>(dalloc<float>(bl)) : static_cast<void*>(dalloc<double>(bl));
+      s->blk[1] = es == 4 ? static_cast<void*>(dalloc<float>(bl)) : static_cast<void*>(dalloc<double>(bl));
+      const size_t na = static_cast<size_t>(std::max(1, s->nproj())) * std::max(s->ns, 1);
+      s->alpha = es == 4 ? static_cast<void*>(dalloc<float>(na)) : static_cast<void*>(dalloc<double>(na));
+      s->alpha64 = dalloc<double>(na);
+      s->partial_elems = std::max(stencil_partial_elems(s->op64, s->ns, s->cfg64),
+                                  static_cast<size_t>(s->ns) * 64);
+      s->partial = dalloc<double>(s->partial_elems);
+      s->lam_dev = dalloc<double>(s->ns);
+      s->resid_dev = dalloc<double>(s->ns);
+      const size_t nn = static_cast<size_t>(s->ns) * s->ns;
+      s->Mdev = dalloc<double>(nn);
+      s->Hsdev = dalloc<double>(nn);
+      s->Ydev = dalloc<double>(nn);
+      s->bwork = dalloc<float>(nn);
+      s->gwork_elems = std::max(gemm_tn_work_elems(s->ns, s->ns, s->nd), static_cast<size_t>(64) * 1024);
+      s->gwork = dalloc<double>(s->gwork_elems);
+      s->vsmall = dalloc<double>(1024);
+      s->cpart = dalloc<double>(static_cast<size_t>(s->ns) * 64);
+      s->gocc = dalloc<double>(s->ns);
+      dense_alloc(s->dw, s->ns);
+      // start block and Lanczos vector
+      if (s->prec == XLS_PREC_FP32)
+        upload_block<float>(s, d->x0, s->blk[0], s->ns);
+      else
+        upload_block<double>(s, d->x0, s->blk[0], s->ns);
+      s->cur = 0;
+      if (d->lanczos_v0)
+        s->lanczos_v0.assign(d->lanczos_v0, d->lanczos_v0 + nd);
+      else
+        s->lanczos_v0.assign(d->x0, d->x0 + nd);
+      XLS_HIP(hipStreamSynchronize(s->st));
+    } catch (...) {
+      delete s;
+      throw;
+    }
+    *out = s;
+    return XLS_OK;
+  });
+}
+
+void xls_subdomain_destroy(xls_subdomain_t s) {
+  if (!s) return;
+  (void)hipStreamSynchronize(s->st);
+  delete s;
+}
+
+int xls_chefsi_step(xls_subdomain_t s, const xls_chefsi_params_t* p, double* ritz, double* resid,
+                    int32_t* iters_done) {
+  return guarded([&]() -> int {
+    if (!s || !p || !ritz || !resid) fail(XLS_ERR_INVALID_ARG, "NULL argument");
+    return by_prec(s, [&](auto tag) { return chefsi_impl<decltype(tag)>(s, p, ritz, resid, iters_done); });
+  });
+}
+
+int xls_subdomain_density(xls_subdomain_t s, double mu, double sigma, double* rho, double* c) {
+  return guarded([&]() -> int {
+    if (!s || !rho || !c) fail(XLS_ERR_INVALID_ARG, "NULL argument");
+    if (!s->have_ritz) fail(XLS_ERR_STATE, "density needs a completed xls_chefsi_step");
+    if (!(sigma > 0) || !std::isfinite(sigma) || !std::isfinite(mu)) fail(XLS_ERR_INVALID_ARG, "bad mu/sigma");
+    if (!s->rho_dev) s->rho_dev = dalloc<double>(s->nd);
+    XLS_HIP(hipMemcpyAsync(s->lam_dev, s->ritz.data(), s->ns * 8, hipMemcpyHostToDevice, s->st));
+    const int nchunk = 64;
+    launch_density(s->lam_dev, mu, sigma, s->mask, s->h, s->blk[s->cur], s->prec == XLS_PREC_FP32, s->nd,
+                   s->ld, s->ns, s->rho_dev, s->cpart, nchunk, s->resid_dev, s->gocc, s->st);
+    XLS_HIP(hipMemcpyAsync(rho, s->rho_dev, s->nd * 8, hipMemcpyDeviceToHost, s->st));
+    XLS_HIP(hipMemcpyAsync(c, s->resid_dev, s->ns * 8, hipMemcpyDeviceToHost, s->st));
+    XLS_HIP(hipStreamSynchronize(s->st));
+    return XLS_OK;
+  });
+}
+
+int xls_hamiltonian_apply(xls_subdomain_t s, const double* X, double* HX, int32_t ncols) {
+  return guarded([&]() -> int {
+    if (!s || !X || !HX || ncols < 1) fail(XLS_ERR_INVALID_ARG, "bad argument");
+    return by_prec(s, [&](auto tag) -> int {
+      using TS = decltype(tag);
+      const size_t n = static_cast<size_t>(s->nd) * ncols;
+      TS* x = dalloc<TS>(n);
+      TS* y = nullptr;
+      TS* al = nullptr;
+      try {
+        y = dalloc<TS>(n);
+        al = dalloc<TS>(static_cast<size_t>(std::max(1, s->nproj())) * ncols);
+        upload_block<TS>(s, X, x, ncols);
+        apply_H<TS>(s, x, y, ncols, al);
+        download_block<TS>(s, y, HX, ncols);
+      } catch (...) {
+        dfree(x);
+        dfree(y);
+        dfree(al);
+        throw;
+      }
+      dfree(x);
+      dfree(y);
+      dfree(al);
+      return XLS_OK;
+    });
+  });
+}
+
+int xls_subdomain_filter(xls_subdomain_t s, int32_t degree, double a0, double lam_cut, double lam_max) {
+  return guarded([&]() -> int {
+    if (!s || degree < 1) fail(XLS_ERR_INVALID_ARG, "bad argument");
+    if (!(a0 < lam_cut && lam_cut < lam_max)) fail(XLS_ERR_INVALID_ARG, "need a0 < lam_cut < lam_max");
+    by_prec(s, [&](auto tag) {
+      filter_block<decltype(tag)>(s, degree, a0, lam_cut, lam_max);
+      return 0;
+    });
+    XLS_HIP(hipStreamSynchronize(s->st));
+    return XLS_OK;
+  });
+}
+
+int xls_subdomain_project(xls_subdomain_t s, int32_t gemm_prec, double* M, double* Hs) {
+  return guarded([&]() -> int {
+    if (!s || !M || !Hs) fail(XLS_ERR_INVALID_ARG, "NULL argument");
+    if (s->prec == XLS_PREC_FP64 && gemm_prec != XLS_PREC_FP64)
+      fail(XLS_ERR_INVALID_ARG, "FP64 handles run FP64 GEMMs");
+    if (gemm_prec < 0 || gemm_prec > 2) fail(XLS_ERR_INVALID_ARG, "bad gemm_prec");
+    by_prec(s, [&](auto tag) {
+      project_block<decltype(tag)>(s, gemm_prec);
+      return 0;
+    });
+    const size_t nn = static_cast<size_t>(s->ns) * s->ns;
+    XLS_HIP(hipMemcpyAsync(M, s->Mdev, nn * 8, hipMemcpyDeviceToHost, s->st));
+    XLS_HIP(hipMemcpyAsync(Hs, s->Hsdev, nn * 8, hipMemcpyDeviceToHost, s->st));
+    XLS_HIP(hipStreamSynchronize(s->st));
+    return XLS_OK;
+  });
+}
+
+int xls_subdomain_rotate(xls_subdomain_t s, int32_t gemm_prec, const double* Q) {
+  return guarded([&]() -> int {
+    if (!s || !Q) fail(XLS_ERR_INVALID_ARG, "NULL argument");
+    if (s->prec == XLS_PREC_FP64 && gemm_prec != XLS_PREC_FP64)
+      fail(XLS_ERR_INVALID_ARG, "FP64 handles run FP64 GEMMs");
+    if (gemm_prec < 0 || gemm_prec > 2) fail(XLS_ERR_INVALID_ARG, "bad gemm_prec");
+    if (!finite_all(Q, static_cast<int64_t>(s->ns) * s->ns)) fail(XLS_ERR_INVALID_ARG, "Q not finite");
+    XLS_HIP(hipMemcpyAsync(s->Ydev, Q, static_cast<size_t>(s->ns) * s->ns * 8, hipMemcpyHostToDevice, s->st));
+    by_prec(s, [&](auto tag) {
+      rotate_block<decltype(tag)>(s, gemm_prec, s->Ydev);
+      return 0;
+    });
+    XLS_HIP(hipStreamSynchronize(s->st));
+    return XLS_OK;
+  });
+}
+
+int xls_subdomain_residual(xls_subdomain_t s, const double* lam, double* resid) {
+  return guarded([&]() -> int {
+    if (!s || !lam || !resid) fail(XLS_ERR_INVALID_ARG, "NULL argument");
+    XLS_HIP(hipMemcpyAsync(s->lam_dev, lam, s->ns * 8, hipMemcpyHostToDevice, s->st));
+    by_prec(s, [&](auto tag) {
+      residual_block<decltype(tag)>(s, s->lam_dev, s->resid_dev);
+      return 0;
+    });
+    XLS_HIP(hipMemcpyAsync(resid, s->resid_dev, s->ns * 8, hipMemcpyDeviceToHost, s->st));
+    XLS_HIP(hipStreamSynchronize(s->st));
+    return XLS_OK;
+  });
+}
+
+int xls_lanczos_bounds(xls_subdomain_t s, int32_t k, double* theta_min, double* upper) {
+  return guarded([&]() -> int {
+    if (!s || !theta_min || !upper || k < 1 || k > 60) fail(XLS_ERR_INVALID_ARG, "bad argument (1 <= k <= 60)");
+    by_prec(s, [&](auto tag) {
+      lanczos_run<decltype(tag)>(s, k);
+      return 0;
+    });
+    *theta_min = s->lz_lo;
+    *upper = s->lz_up;
+    return XLS_OK;
+  });
+}
+
+int xls_dense_geneig(int32_t n, const double* Hs, const double* M, double* lam, double* Y) {
+  return guarded([&]() -> int {
+    if (n < 1 || !Hs || !M || !lam || !Y) fail(XLS_ERR_INVALID_ARG, "bad argument");
+    const int64_t nn = static_cast<int64_t>(n) * n;
+    if (!finite_all(Hs, nn) || !finite_all(M, nn)) fail(XLS_ERR_INVALID_ARG, "input not finite");
+    hipStream_t st;
+    XLS_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    DenseWork w;
+    double *dH = nullptr, *dM = nullptr, *dY = nullptr;
+    int rc = XLS_OK;
+    try {
+      dense_alloc(w, n);
+      dH = dalloc<double>(nn);
+      dM = dalloc<double>(nn);
+      dY = dalloc<double>(nn);
+      XLS_HIP(hipMemcpyAsync(dH, Hs, nn * 8, hipMemcpyHostToDevice, st));
+      XLS_HIP(hipMemcpyAsync(dM, M, nn * 8, hipMemcpyHostToDevice, st));
+      rc = dense_geneig(w, dH, dM, dY, st, nullptr);
+      if (rc == XLS_OK) {
+        XLS_HIP(hipMemcpyAsync(lam, w.lam, n * 8, hipMemcpyDeviceToHost, st));
+        XLS_HIP(hipMemcpyAsync(Y, dY, nn * 8, hipMemcpyDeviceToHost, st));
+      }
+      XLS_HIP(hipStreamSynchronize(st));
+    } catch (...) {
+      (void)hipStreamSynchronize(st);
+      dfree(dH);
+      dfree(dM);
+      dfree(dY);
+      dense_free(w);
+      (void)hipStreamDestroy(st);
+      throw;
+    }
+    dfree(dH);
+    dfree(dM);
+    dfree(dY);
+    dense_free(w);
+    (void)hipStreamDestroy(st);
+    if (rc != XLS_OK) g_last_error = rc == XLS_ERR_NOT_SPD ? "M is not positive definite" : "no convergence";
+    return rc;
+  });
+}
+
+int xls_subdomain_get_block(xls_subdomain_t s, double* X) {
+  return guarded([&]() -> int {
+    if (!s || !X) fail(XLS_ERR_INVALID_ARG, "NULL argument");
+    by_prec(s, [&](auto tag) {
+      download_block<decltype(tag)>(s, s->blk[s->cur], X, s->ns);
+      return 0;
+    });
+    return XLS_OK;
+  });
+}
+
+int xls_subdomain_set_block(xls_subdomain_t s, const double* X) {
+  return guarded([&]() -> int {
+    if (!s || !X) fail(XLS_ERR_INVALID_ARG, "NULL argument");
+    if (!finite_all(X, s->nd * s->ns)) fail(XLS_ERR_INVALID_ARG, "block not finite");
+    by_prec(s, [&](auto tag) {
+      upload_block<decltype(tag)>(s, X, s->blk[s->cur], s->ns);
+      return 0;
+    });
+    XLS_HIP(hipStreamSynchronize(s->st));
+    s->have_ritz = false;
+    return XLS_OK;
+  });
+}
+
+int xls_subdomain_get_maps(xls_subdomain_t s, uint8_t* core_mask, int64_t* global_index) {
+  return guarded([&]() -> int {
+    if (!s || !core_mask || !global_index) fail(XLS_ERR_INVALID_ARG, "NULL argument");
+    std::memcpy(core_mask, s->tab.core_mask.data(), s->nd);
+    std::memcpy(global_index, s->tab.global_index.data(), s->nd * 8);
+    return XLS_OK;
+  });
+}
+
+int xls_subdomain_get_projectors(xls_subdomain_t s, int64_t* sizes, int32_t* offsets, int32_t* idx,
+                                 double* val, int32_t* rev_offsets, int32_t* rev_slot) {
+  return guarded([&]() -> int {
+    if (!s || !sizes) fail(XLS_ERR_INVALID_ARG, "NULL argument");
+    const size_t total = s->tab.sup_idx.size();
+    sizes[0] = static_cast<int64_t>(total);
+    sizes[1] = s->n_atoms;
+    if (offsets) std::memcpy(offsets, s->tab.sup_off.data(), (s->n_atoms + 1) * 4);
+    if (idx) std::memcpy(idx, s->tab.sup_idx.data(), total * 4);
+    if (val) std::memcpy(val, s->tab.sup_val.data(), total * 4 * 8);
+    if (rev_offsets) std::memcpy(rev_offsets, s->tab.rev_off.data(), (s->nd + 1) * 4);
+    if (rev_slot) std::memcpy(rev_slot, s->tab.rev_slot.data(), total * 4);
+    return XLS_OK;
+  });
+}
+
+int xls_split_bf16(const float* a, uint16_t* hi, uint16_t* lo, int64_t n) {
+  return guarded([&]() -> int {
+    if (n < 0 || (n > 0 && (!a || !hi || !lo))) fail(XLS_ERR_INVALID_ARG, "bad argument");
+    if (n == 0) return XLS_OK;
+    float* da = dalloc<float>(n);
+    uint16_t *dh = nullptr, *dl = nullptr;
+    try {
+      dh = dalloc<uint16_t>(n);
+      dl = dalloc<uint16_t>(n);
+      XLS_HIP(hipMemcpy(da, a, n * 4, hipMemcpyHostToDevice));
+      split_bf16_device(da, dh, dl, n, nullptr);
+      XLS_HIP(hipMemcpy(hi, dh, n * 2, hipMemcpyDeviceToHost));
+      XLS_HIP(hipMemcpy(lo, dl, n * 2, hipMemcpyDeviceToHost));
+    } catch (...) {
+      dfree(da);
+      dfree(dh);
+      dfree(dl);
+      throw;
+    }
+    dfree(da);
+    dfree(dh);
+    dfree(dl);
+    return XLS_OK;
+  });
+}
+
+int xls_subdomain_tune(xls_subdomain_t s, int32_t prec, int32_t block, int32_t ty, int32_t tz) {
+  return guarded([&]() -> int {
+    if (!s) fail(XLS_ERR_INVALID_ARG, "NULL handle");
+    if (prec != XLS_PREC_FP64 && prec != XLS_PREC_FP32) fail(XLS_ERR_INVALID_ARG, "prec must be FP64 or FP32");
+    StencilLaunch c;
+    c.block = block;
+    c.ty = ty;
+    c.tz = tz;
+    stencil_validate(s->n[0], s->n[1], s->n[2], s->bc == XLS_BC_PERIODIC, prec == XLS_PREC_FP64 ? 8 : 4, c);
+    if (prec == XLS_PREC_FP64) {
+      // the residual sweep uses the FP64 shape: grow its partial buffer if needed
+      const size_t need = std::max(stencil_partial_elems(s->op64, s->ns, c), static_cast<size_t>(s->ns) * 64);
+      if (need > s->partial_elems) {
+        XLS_HIP(hipStreamSynchronize(s->st));
+        double* np = dalloc<double>(need);
+        dfree(s->partial);
+        s->partial = np;
+        s->partial_elems = need;
+      }
+      s->cfg64 = c;
+    } else {
+      s->cfg32 = c;
+    }
+    return XLS_OK;
+  });
+}
+
+int xls_get_stage_times(xls_subdomain_t s, double* ms, int64_t* counts, int32_t cap) {
+  return guarded([&]() -> int {
+    if (!s || !ms || cap < 1) fail(XLS_ERR_INVALID_ARG, "bad argument");
+    const int n = std::min<int>(cap, static_cast<int>(s->stage_ms.size()));
+    for (int i = 0; i < n; ++i) ms[i] = s->stage_ms[i];
+    if (counts) counts[0] = s->filter_launches;
+    return n;
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,428 @@
+// Projection and rotation GEMMs on the matrix cores (Sec. V-B.3: the
+// Rayleigh-Ritz projection H_s = Psi_f^T (H Psi_f), M_s = Psi_f^T Psi_f and the
+// subspace rotation Psi = Psi_f Y are dense products).
+//
+//   gemm_tn : C = A^T B with a long inner dimension K = N_d, split along K
+//             (each split's partial tile is written in FP64 and the splits are
+//             summed in a fixed order: deterministic, no atomics).
+//   gemm_nn : C = A B with A the tall N_d x N_s block and B the N_s x N_s
+//             rotation.
+// Arithmetic forms (all accumulate in the MFMA accumulator type):
+//   FP64  v_mfma_f64_16x16x4f64 (FP32 inputs are widened exactly),
+//   FP32  v_mfma_f32_16x16x4f32,
+//   BF16X3 each FP32 operand a = a_hi + a_lo with a_hi = bf16(a),
+//          a_lo = bf16(a - a_hi) (round to nearest even), three products
+//          hi*hi + hi*lo + lo*hi on v_mfma_f32_16x16x32_bf16.
+// Tiles: TILE x TILE per workgroup of 4 wavefronts (2 x 2), each wavefront a
+// (TILE/2)^2 block of 16 x 16 MFMA tiles; operands staged through LDS with k
+// contiguous.
+#include <algorithm>
+
+#include "xls_internal.h"
+
+namespace xls {
+namespace {
+
+typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
+
+constexpr int MF_F64 = XLS_PREC_FP64;
+constexpr int MF_F32 = XLS_PREC_FP32;
+constexpr int MF_BF = XLS_PREC_BF16X3;
+
+__device__ __forceinline__ uint32_t xcd_remap(uint32_t bid, uint32_t nb) {
+  const uint32_t xcd = bid & 7u, idx = bid >> 3;
+  const uint32_t q = nb >> 3, r = nb & 7u;
+  return xcd * q + min(xcd, r) + idx;
+}
+
+__device__ __forceinline__ uint16_t bf16_rne_bits(float a) {
+  uint32_t u = __float_as_uint(a);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return static_cast<uint16_t>(u >> 16);
+}
+__device__ __forceinline__ float bf16_bits_to_f32(uint16_t b) {
+  return __uint_as_float(static_cast<uint32_t>(b) << 16);
+}
+
+// ---- per-form traits: LDS element, k per MFMA, operand loads, MFMA --------
+template <int MF>
+struct Form;
+
+template <>
+struct Form<MF_F64> {
+  using acc_t = d4_t;
+  static constexpr int BK = 16;
+  static constexpr int KS = 4;
+  static constexpr int PAD = 1;
+  using lds_t = double;
+  template <typename T>
+  __device__ static void put(lds_t* hi, lds_t*, int off, T v) {
+    hi[off] = static_cast<double>(v);
+  }
+  __device__ static void step(acc_t& acc, const lds_t* xh, const lds_t*, const lds_t* yh,
+                              const lds_t*, int xrow, int yrow, int stride, int k, int lane) {
+    const double a = xh[xrow * stride + k + (lane >> 4)];
+    const double b = yh[yrow * stride + k + (lane >> 4)];
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+  }
+  __device__ static double get(const acc_t& a, int r) { return a[r]; }
+};
+
+template <>
+struct Form<MF_F32> {
+  using acc_t = f4_t;
+  static constexpr int BK = 16;
+  static constexpr int KS = 4;
+  static constexpr int PAD = 1;
+  using lds_t = float;
+  template <typename T>
+  __device__ static void put(lds_t* hi, lds_t*, int off, T v) {
+    hi[off] = static_cast<float>(v);
+  }
+  __device__ static void step(acc_t& acc, const lds_t* xh, const lds_t*, const lds_t* yh,
+                              const lds_t*, int xrow, int yrow, int stride, int k, int lane) {
+    const float a = xh[xrow * stride + k + (lane >> 4)];
+    const float b = yh[yrow * stride + k + (lane >> 4)];
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+  }
+  __device__ static double get(const acc_t& a, int r) { return a[r]; }
+};
+
+template <>
+struct Form<MF_BF> {
+  using acc_t = f4_t;
+  static constexpr int BK = 32;
+  static constexpr int KS = 32;
+  static constexpr int PAD = 8;
+  using lds_t = uint16_t;
+  template <typename T>
+  __device__ static void put(lds_t* hi, lds_t* lo, int off, T v) {
+    const float a = static_cast<float>(v);
+    const uint16_t h = bf16_rne_bits(a);
+    hi[off] = h;
+    lo[off] = bf16_rne_bits(a - bf16_bits_to_f32(h));
+  }
+  __device__ static void step(acc_t& acc, const lds_t* xh, const lds_t* xl, const lds_t* yh,
+                              const lds_t* yl, int xrow, int yrow, int stride, int k, int lane) {
+    const int ko = k + 8 * (lane >> 4);
+    const bf8_t ah = *reinterpret_cast<const bf8_t*>(xh + xrow * stride + ko);
+    const bf8_t al = *reinterpret_cast<const bf8_t*>(xl + xrow * stride + ko);
+    const bf8_t bh = *reinterpret_cast<const bf8_t*>(yh + yrow * stride + ko);
+    const bf8_t bl = *reinterpret_cast<const bf8_t*>(yl + yrow * stride + ko);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc, 0, 0, 0);
+  }
+  __device__ static double get(const acc_t& a, int r) { return a[r]; }
+};
+
+template <int MF, int TILE>
+struct Smem {
+  using F = Form<MF>;
+  static constexpr int stride = F::BK + F::PAD;
+  static constexpr int elems = TILE * stride;                 // one operand, one part
+  static constexpr int parts = (MF == MF_BF) ? 2 : 1;
+  static constexpr size_t bytes = 2 * parts * elems * sizeof(typename F::lds_t);
+};
+
+// C = A^T B partial over one K split.  A: K x M (lda), B: K x N (ldb).
+template <typename TIN, int MF, int TILE>
+__global__ __launch_bounds__(256) void gemm_tn_kernel(const TIN* __restrict__ A, int64_t lda,
+                                                      const TIN* __restrict__ B, int64_t ldb, int M,
+                                                      int N, int64_t K, int64_t kchunk, int tm,
+                                                      int tn, int sym, double* __restrict__ P) {
+  using F = Form<MF>;
+  using L = typename F::lds_t;
+  constexpr int BK = F::BK, ST = Smem<MF, TILE>::stride, E = Smem<MF, TILE>::elems;
+  constexpr int WB = TILE / 32;
+  __shared__ __align__(16) L sm[Smem<MF, TILE>::bytes / sizeof(L)];
+  L* xh = sm;
+  L* yh = sm + E;
+  L* xl = (MF == MF_BF) ? sm + 2 * E : nullptr;
+  L* yl = (MF == MF_BF) ? sm + 3 * E : nullptr;
+
+  const uint32_t lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int ntile = sym ? tm * (tm + 1) / 2 : tm * tn;
+  const int split = static_cast<int>(lb / ntile);
+  int tt = static_cast<int>(lb % ntile);
+  int bm, bn;
+  if (sym) {  // enumerate upper tiles bm <= bn column by column
+    bn = 0;
+    while (tt > bn) {
+      tt -= bn + 1;
+      ++bn;
+    }
+    bm = tt;
+  } else {
+    bm = tt % tm;
+    bn = tt / tm;
+  }
+  const int m0 = bm * TILE, n0 = bn * TILE;
+  const int64_t kb0 = static_cast<int64_t>(split) * kchunk;
+  const int64_t kend = min(K, kb0 + kchunk);
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave & 1, wc = wave >> 1;
+  typename F::acc_t acc[WB][WB];
+#pragma unroll
+  for (int i = 0; i < WB; ++i)
+#pragma unroll
+    for (int j = 0; j < WB; ++j) acc[i][j] = typename F::acc_t{};
+
+  for (int64_t kb = kb0; kb < kend; kb += BK) {
+#pragma unroll
+    for (int it = 0; it < (TILE * BK) / 256; ++it) {
+      const int l = tid + it * 256;
+      const int k = l % BK, r = l / BK;
+      const int64_t kk = kb + k;
+      const bool kin = kk < kend;
+      const TIN av = (kin && m0 + r < M) ? A[kk + static_cast<int64_t>(m0 + r) * lda] : TIN(0);
+      const TIN bv = (kin && n0 + r < N) ? B[kk + static_cast<int64_t>(n0 + r) * ldb] : TIN(0);
+      F::put(xh, xl, r * ST + k, av);
+      F::put(yh, yl, r * ST + k, bv);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < BK; k += F::KS)
+#pragma unroll
+      for (int bi = 0; bi < WB; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < WB; ++bj)
+          F::step(acc[bi][bj], xh, xl, yh, yl, wr * (TILE / 2) + bi * 16 + (lane & 15),
+                  wc * (TILE / 2) + bj * 16 + (lane & 15), ST, k, lane);
+    __syncthreads();
+  }
+  double* Ps = P + static_cast<int64_t>(split) * M * N;
+#pragma unroll
+  for (int bi = 0; bi < WB; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < WB; ++bj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wr * (TILE / 2) + bi * 16 + 4 * (lane >> 4) + r;
+        const int cl = n0 + wc * (TILE / 2) + bj * 16 + (lane & 15);
+        if (row < M && cl < N) Ps[row + static_cast<int64_t>(cl) * M] = F::get(acc[bi][bj], r);
+      }
+}
+
+__global__ void tn_reduce_kernel(const double* __restrict__ P, int splits, int M, int N, int tile,
+                                 int sym, int symmetrize, double* __restrict__ C, int64_t ldc) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= static_cast<int64_t>(M) * N) return;
+  const int i = static_cast<int>(e % M), j = static_cast<int>(e / M);
+  const int64_t MN = static_cast<int64_t>(M) * N;
+  auto get = [&](int a, int b) {
+    if (sym && (a / tile) > (b / tile)) {
+      const int t = a;
+      a = b;
+      b = t;
+    }
+    double s = 0.0;
+    for (int sp = 0; sp < splits; ++sp) s += P[sp * MN + a + static_cast<int64_t>(b) * M];
+    return s;
+  };
+  double v = get(i, j);
+  if (symmetrize) v = 0.5 * (v + get(j, i));
+  C[i + static_cast<int64_t>(j) * ldc] = v;
+}
+
+// C[M x N] = A[M x K] B[K x N]; the MFMA computes the transposed tile so that
+// each lane's results run down a column of C (coalesced stores).
+template <typename TIN, typename TB, typename TOUT, int MF, int TILE>
+__global__ __launch_bounds__(256) void gemm_nn_kernel(const TIN* __restrict__ A, int64_t lda,
+                                                      const TB* __restrict__ B, int64_t ldb, int M,
+                                                      int N, int K, int tmM, int tnN,
+                                                      TOUT* __restrict__ C, int64_t ldc) {
+  using F = Form<MF>;
+  using L = typename F::lds_t;
+  constexpr int BK = F::BK, ST = Smem<MF, TILE>::stride, E = Smem<MF, TILE>::elems;
+  constexpr int WB = TILE / 32;
+  __shared__ __align__(16) L sm[Smem<MF, TILE>::bytes / sizeof(L)];
+  L* ah = sm;  // A tile rows = m
+  L* bh = sm + E;  // B tile rows = n
+  L* al = (MF == MF_BF) ? sm + 2 * E : nullptr;
+  L* bl = (MF == MF_BF) ? sm + 3 * E : nullptr;
+
+  const uint32_t lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int bn = static_cast<int>(lb % tnN), bm = static_cast<int>(lb / tnN);
+  const int m0 = bm * TILE, n0 = bn * TILE;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave & 1, wc = wave >> 1;  // wr: n direction, wc: m direction
+  typename F::acc_t acc[WB][WB];
+#pragma unroll
+  for (int i = 0; i < WB; ++i)
+#pragma unroll
+    for (int j = 0; j < WB; ++j) acc[i][j] = typename F::acc_t{};
+
+  for (int kb = 0; kb < K; kb += BK) {
+#pragma unroll
+    for (int it = 0; it < (TILE * BK) / 256; ++it) {
+      const int l = tid + it * 256;
+      {  // A: coalesced along m
+        const int m = l % TILE, k = l / TILE;
+        const bool ok = (m0 + m < M) && (kb + k < K);
+        const TIN v = ok ? A[(m0 + m) + static_cast<int64_t>(kb + k) * lda] : TIN(0);
+        F::put(ah, al, m * ST + k, v);
+      }
+      {  // B: coalesced along k
+        const int k = l % BK, n = l / BK;
+        const bool ok = (n0 + n < N) && (kb + k < K);
+        const TB v = ok ? B[(kb + k) + static_cast<int64_t>(n0 + n) * ldb] : TB(0);
+        F::put(bh, bl, n * ST + k, v);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < BK; k += F::KS)
+#pragma unroll
+      for (int bi = 0; bi < WB; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < WB; ++bj)
+          F::step(acc[bi][bj], bh, bl, ah, al, wr * (TILE / 2) + bi * 16 + (lane & 15),
+                  wc * (TILE / 2) + bj * 16 + (lane & 15), ST, k, lane);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int bi = 0; bi < WB; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < WB; ++bj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int n = n0 + wr * (TILE / 2) + bi * 16 + 4 * (lane >> 4) + r;
+        const int m = m0 + wc * (TILE / 2) + bj * 16 + (lane & 15);
+        if (m < M && n < N) C[m + static_cast<int64_t>(n) * ldc] = static_cast<TOUT>(F::get(acc[bi][bj], r));
+      }
+}
+
+__global__ void split_bf16_kernel(const float* __restrict__ a, uint16_t* __restrict__ hi,
+                                  uint16_t* __restrict__ lo, int64_t n) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint16_t h = bf16_rne_bits(a[i]);
+  hi[i] = h;
+  lo[i] = bf16_rne_bits(a[i] - bf16_bits_to_f32(h));
+}
+
+__global__ void d2f_kernel(const double* __restrict__ s, float* __restrict__ d, int64_t n) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) d[i] = static_cast<float>(s[i]);
+}
+
+constexpr int kTile = 64;
+
+int choose_splits(int tiles, int64_t K, int bk, int M, int N, size_t work_elems) {
+  // aim for ~2048 workgroups; each split must keep >= 8 k-blocks
+  int s = std::max(1, 2048 / std::max(1, tiles));
+  const int64_t kblocks = (K + bk - 1) / bk;
+  s = static_cast<int>(std::min<int64_t>(s, std::max<int64_t>(1, kblocks / 8)));
+  const size_t per = static_cast<size_t>(M) * N;
+  if (per > 0) s = static_cast<int>(std::min<size_t>(s, std::max<size_t>(1, work_elems / per)));
+  return std::max(1, s);
+}
+
+template <typename TIN, int MF>
+void tn_dispatch(const TIN* A, int64_t lda, const TIN* B, int64_t ldb, int M, int N, int64_t K,
+                 double* C, int64_t ldc, int sym, int symmetrize, double* work, size_t work_elems,
+                 hipStream_t st) {
+  const int tm = (M + kTile - 1) / kTile, tn = (N + kTile - 1) / kTile;
+  const int ntile = sym ? tm * (tm + 1) / 2 : tm * tn;
+  const int bk = Form<MF>::BK;
+  const int splits = choose_splits(ntile, K, bk, M, N, work_elems);
+  int64_t kchunk = (K + splits - 1) / splits;
+  kchunk = ((kchunk + bk - 1) / bk) * bk;
+  const int real_splits = static_cast<int>((K + kchunk - 1) / kchunk);
+  const int64_t nb = static_cast<int64_t>(ntile) * real_splits;
+  if (nb > 0x7fffffff) fail(XLS_ERR_INVALID_ARG, "gemm_tn grid too large");
+  hipLaunchKernelGGL((gemm_tn_kernel<TIN, MF, kTile>), dim3(static_cast<unsigned>(nb)), dim3(256), 0,
+                     st, A, lda, B, ldb, M, N, K, kchunk, tm, tn, sym, work);
+  XLS_LAUNCH_CHECK("gemm_tn_kernel");
+  const int64_t tot = static_cast<int64_t>(M) * N;
+  hipLaunchKernelGGL(tn_reduce_kernel, dim3(static_cast<unsigned>((tot + 255) / 256)), dim3(256), 0, st,
+                     work, real_splits, M, N, kTile, sym, symmetrize, C, ldc);
+  XLS_LAUNCH_CHECK("tn_reduce_kernel");
+}
+
+}  // namespace
+
+size_t gemm_tn_work_elems(int M, int N, int64_t K) {
+  (void)K;
+  // room for up to 32 splits, capped at 64 Mi doubles
+  const size_t per = static_cast<size_t>(M) * N;
+  return std::max<size_t>(per, std::min<size_t>(32 * per, static_cast<size_t>(64) << 20));
+}
+
+template <typename TS>
+void gemm_tn(int prec, const TS* A, int64_t lda, const TS* B, int64_t ldb, int M, int N, int64_t K,
+             double* C, int64_t ldc, int sym, int symmetrize, double* work, size_t work_elems,
+             hipStream_t st) {
+  if (M <= 0 || N <= 0) return;
+  if (work_elems < static_cast<size_t>(M) * N) fail(XLS_ERR_INVALID_ARG, "gemm_tn workspace too small");
+  if constexpr (std::is_same<TS, double>::value) {
+    if (prec != MF_F64) fail(XLS_ERR_INVALID_ARG, "FP64 blocks use FP64 GEMMs");
+    tn_dispatch<double, MF_F64>(A, lda, B, ldb, M, N, K, C, ldc, sym, symmetrize, work, work_elems, st);
+  } else {
+    if (prec == MF_F64)
+      tn_dispatch<float, MF_F64>(A, lda, B, ldb, M, N, K, C, ldc, sym, symmetrize, work, work_elems, st);
+    else if (prec == MF_F32)
+      tn_dispatch<float, MF_F32>(A, lda, B, ldb, M, N, K, C, ldc, sym, symmetrize, work, work_elems, st);
+    else if (prec == MF_BF)
+      tn_dispatch<float, MF_BF>(A, lda, B, ldb, M, N, K, C, ldc, sym, symmetrize, work, work_elems, st);
+    else
+      fail(XLS_ERR_INVALID_ARG, "unknown GEMM precision");
+  }
+}
+
+template <typename TS>
+void gemm_nn(int prec, const TS* A, int64_t lda, const double* B, int64_t ldb, int M, int N, int K,
+             TS* C, int64_t ldc, void* bwork, hipStream_t st) {
+  if (M <= 0 || N <= 0) return;
+  const int tmM = (M + kTile - 1) / kTile, tnN = (N + kTile - 1) / kTile;
+  const int64_t nb = static_cast<int64_t>(tmM) * tnN;
+  if (nb > 0x7fffffff) fail(XLS_ERR_INVALID_ARG, "gemm_nn grid too large");
+  const dim3 grid(static_cast<unsigned>(nb));
+  if constexpr (std::is_same<TS, double>::value) {
+    if (prec != MF_F64) fail(XLS_ERR_INVALID_ARG, "FP64 blocks use FP64 GEMMs");
+    hipLaunchKernelGGL((gemm_nn_kernel<double, double, double, MF_F64, kTile>), grid, dim3(256), 0, st,
+                       A, lda, B, ldb, M, N, K, tmM, tnN, C, ldc);
+  } else {
+    if (prec == MF_F64) {
+      hipLaunchKernelGGL((gemm_nn_kernel<float, double, float, MF_F64, kTile>), grid, dim3(256), 0, st,
+                         A, lda, B, ldb, M, N, K, tmM, tnN, C, ldc);
+    } else {
+      // the rotation matrix is rounded to FP32 once, then fed like the block
+      float* Bf = static_cast<float*>(bwork);
+      const int64_t nbv = ldb * static_cast<int64_t>(N);
+      hipLaunchKernelGGL(d2f_kernel, dim3(static_cast<unsigned>((nbv + 255) / 256)), dim3(256), 0, st, B, Bf,
+                         nbv);
+      if (prec == MF_F32)
+        hipLaunchKernelGGL((gemm_nn_kernel<float, float, float, MF_F32, kTile>), grid, dim3(256), 0, st,
+                           A, lda, Bf, ldb, M, N, K, tmM, tnN, C, ldc);
+      else if (prec == MF_BF)
+        hipLaunchKernelGGL((gemm_nn_kernel<float, float, float, MF_BF, kTile>), grid, dim3(256), 0, st,
+                           A, lda, Bf, ldb, M, N, K, tmM, tnN, C, ldc);
+      else
+        fail(XLS_ERR_INVALID_ARG, "unknown GEMM precision");
+    }
+  }
+  XLS_LAUNCH_CHECK("gemm_nn_kernel");
+}
+
+void split_bf16_device(const float* a, uint16_t* hi, uint16_t* lo, int64_t n, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(split_bf16_kernel, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, st,
+                     a, hi, lo, n);
+  XLS_LAUNCH_CHECK("split_bf16_kernel");
+}
+
+template void gemm_tn<double>(int, const double*, int64_t, const double*, int64_t, int, int, int64_t,
+                              double*, int64_t, int, int, double*, size_t, hipStream_t);
+template void gemm_tn<float>(int, const float*, int64_t, const float*, int64_t, int, int, int64_t,
+                             double*, int64_t, int, int, double*, size_t, hipStream_t);
+template void gemm_nn<double>(int, const double*, int64_t, const double*, int64_t, int, int, int,
+                              double*, int64_t, void*, hipStream_t);
+template void gemm_nn<float>(int, const float*, int64_t, const double*, int64_t, int, int, int, float*,
+                             int64_t, void*, hipStream_t);
+
+}  // namespace xls

@@ -1,0 +1,153 @@
+// Internal declarations shared by the engine's host code and HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/xls.h"
+
+namespace xls {
+
+constexpr int kRadius = 6;  // FD half-width n0 (12th-order Laplacian)
+
+// ---------------------------------------------------------------------------
+// error plumbing: every internal failure throws Error; the ABI layer turns it
+// into a status code and a thread-local message.
+// ---------------------------------------------------------------------------
+struct Error {
+  int code;
+  std::string msg;
+};
+[[noreturn]] void fail(int code, const std::string& msg);
+void check_hip(hipError_t e, const char* what, const char* file, int line);
+#define XLS_HIP(call) ::xls::check_hip((call), #call, __FILE__, __LINE__)
+#define XLS_LAUNCH_CHECK(name) ::xls::check_hip(hipGetLastError(), name, __FILE__, __LINE__)
+
+// ---------------------------------------------------------------------------
+// host-side setup tables (setup.cpp)
+// ---------------------------------------------------------------------------
+struct SetupTables {
+  std::vector<uint8_t> core_mask;     // [nd]
+  std::vector<int64_t> global_index;  // [nd]
+  std::vector<int32_t> sup_off;       // [n_atoms + 1]
+  std::vector<int32_t> sup_idx;       // [total]
+  std::vector<double> sup_val;        // [4 * total]  slot-major
+  std::vector<int32_t> slot_atom;     // [total]
+  std::vector<int32_t> rev_off;       // [nd + 1]
+  std::vector<int32_t> rev_slot;      // [total]
+  std::vector<double> gamma;          // [4 * n_atoms]
+};
+void build_setup(const xls_subdomain_desc_t& d, SetupTables& t);
+
+// ---------------------------------------------------------------------------
+// kernel launchers
+// ---------------------------------------------------------------------------
+enum StencilMode { kApply = 0, kFilter = 1, kResid = 2 };
+
+// Geometry + operator tables on the device for one subdomain, in compute type TC.
+template <typename TC>
+struct OpTables {
+  const TC* v = nullptr;         // [nd]
+  const TC* slot_val = nullptr;  // [4 * total]
+  const int32_t* rev_off = nullptr;
+  const int32_t* rev_slot = nullptr;
+  const int32_t* slot_atom = nullptr;
+  const int32_t* sup_off = nullptr;
+  const int32_t* sup_idx = nullptr;
+  const double* gamma = nullptr;  // [4 * n_atoms]
+  int32_t n_atoms = 0;
+  int32_t nx = 0, ny = 0, nz = 0;
+  int32_t periodic = 0;
+  double h = 0;
+};
+
+struct StencilLaunch {
+  int block = 512;  // threads
+  int ty = 0;       // rows per tile (0 = choose)
+  int tz = 0;       // z-chunk (0 = whole nz)
+};
+
+// HY / filter step / residual over ncols columns of y (ld elements apart).
+//   kApply : out = H y
+//   kFilter: out = a (H y - c y) - b yprev   (yprev may alias out; b = 0 ignores yprev)
+//   kResid : resid2[col] = sqrt(sum_g (H y - lam[col] y)^2)   (needs partial scratch)
+// alpha: [ncols][4*n_atoms] gamma-scaled projections of y (proj_forward).
+template <typename TS, typename TC>
+void launch_stencil(StencilMode mode, const OpTables<TC>& op, const TS* y, int64_t ld, int ncols,
+                    const TC* alpha, TS* out, const TS* yprev, double a, double c, double b,
+                    const double* lam, double* partial, double* resid2, hipStream_t st,
+                    const StencilLaunch& cfg);
+// alpha[col][4a+l] = gamma_{a,l} h^3 sum_{s in S_a} chi_{a,l}(s) y(idx(s), col)
+template <typename TS, typename TC>
+void launch_proj_forward(const OpTables<TC>& op, const TS* y, int64_t ld, int ncols, TC* alpha,
+                         hipStream_t st);
+// Throws INVALID_ARG when the launch shape cannot run on this grid.
+void stencil_validate(int nx, int ny, int nz, int periodic, int elem_bytes, const StencilLaunch& cfg);
+size_t stencil_partial_elems(const OpTables<float>& op, int ncols, const StencilLaunch& cfg);
+size_t stencil_partial_elems(const OpTables<double>& op, int ncols, const StencilLaunch& cfg);
+
+// GEMMs.  Matrices column-major.
+//   gemm_tn: C[M x N] = A^T B, A is K x M (lda), B is K x N (ldb); FP64 result.
+//            sym = 1: only C's upper tiles are formed, then mirrored (A == B).
+//            symmetrize = 1: C = (S + S^T)/2 (M == N).
+//   gemm_nn: C[M x N] = A[M x K] B[K x N]; B given in FP64 and converted.
+template <typename TS>
+void gemm_tn(int prec, const TS* A, int64_t lda, const TS* B, int64_t ldb, int M, int N, int64_t K,
+             double* C, int64_t ldc, int sym, int symmetrize, double* work, size_t work_elems,
+             hipStream_t st);
+size_t gemm_tn_work_elems(int M, int N, int64_t K);
+template <typename TS>
+void gemm_nn(int prec, const TS* A, int64_t lda, const double* B, int64_t ldb, int M, int N, int K,
+             TS* C, int64_t ldc, void* bwork, hipStream_t st);
+void split_bf16_device(const float* a, uint16_t* hi, uint16_t* lo, int64_t n, hipStream_t st);
+
+// Dense FP64 generalized eigensolver: Hs y = lambda M y (n x n).
+struct DenseWork {
+  int n = 0;
+  double *R = nullptr, *Rinv = nullptr, *C0 = nullptr, *C1 = nullptr, *V = nullptr, *T = nullptr;
+  double* lam = nullptr;       // [n]
+  double* scal = nullptr;      // small scalars / partials
+  int32_t* flag = nullptr;     // device status flags
+  int32_t* perm = nullptr;     // [n]
+  double* gemm_work = nullptr;
+  size_t gemm_work_elems = 0;
+};
+void dense_alloc(DenseWork& w, int n);
+void dense_free(DenseWork& w);
+// Solves in place: on return w.lam (device, ascending) and Y (device, n x n) hold the result.
+// Returns XLS_OK, XLS_ERR_NOT_SPD or XLS_ERR_EIG_NOCONV.  Synchronises st (convergence checks).
+int dense_geneig(DenseWork& w, const double* Hs, const double* M, double* Y, hipStream_t st,
+                 int* sweeps_out);
+
+// vector helpers (vecops.hip)
+template <typename TS>
+void launch_convert_block(const double* src, int64_t lds_, TS* dst, int64_t ldd, int64_t rows,
+                          int cols, hipStream_t st);
+template <typename TS>
+void launch_block_to_double(const TS* src, int64_t lds_, double* dst, int64_t ldd, int64_t rows,
+                            int cols, hipStream_t st);
+void launch_reduce_cols(const double* partial, int nper, int ncols, double* out, int take_sqrt,
+                        hipStream_t st);
+void launch_density(const double* lam, double mu, double sigma, const uint8_t* mask, double h,
+                    const void* psi, int is_float, int64_t nd, int64_t ld, int ns, double* rho,
+                    double* cpart, int nchunk, double* c, double* gocc, hipStream_t st);
+// Lanczos helpers
+template <typename TS>
+void launch_dot(const TS* x, const TS* y, int64_t n, double* partial, int nblocks, double* out,
+                int take_sqrt, hipStream_t st);
+template <typename TS>
+void launch_lanczos_update(TS* w, const TS* v, const TS* vprev, const double* alpha_j,
+                           const double* beta_prev, int64_t n, hipStream_t st);
+template <typename TS>
+void launch_reorth(TS* w, const TS* V, int64_t ldv, const double* coef, int k, int64_t n,
+                   hipStream_t st);
+template <typename TS>
+void launch_scale_to(TS* dst, const TS* src, const double* norm, int64_t n, hipStream_t st);
+void launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t st);
+void launch_tridiag_extremes(const double* alpha, const double* beta, int k, double* out,
+                             hipStream_t st);
+
+}  // namespace xls

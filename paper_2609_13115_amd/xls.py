@@ -1,0 +1,294 @@
+"""Thin Python binding of the C ABI in include/xls.h (argument marshalling only).
+
+Every numerical step runs in libxls.so's HIP kernels.  Loading fails loudly
+when the library is missing: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libxls.so")
+
+XLS_OK = 0
+XLS_ERR_INVALID_ARG = -1
+XLS_ERR_OUT_OF_MEMORY = -2
+XLS_ERR_DEVICE = -3
+XLS_ERR_NOT_SPD = -4
+XLS_ERR_EIG_NOCONV = -5
+XLS_ERR_STATE = -6
+
+XLS_BC_PERIODIC = 0
+XLS_BC_DIRICHLET0 = 1
+XLS_PREC_FP64 = 0
+XLS_PREC_FP32 = 1
+XLS_PREC_BF16X3 = 2
+XLS_BOUNDS_GIVEN = 0
+XLS_BOUNDS_LANCZOS = 1
+XLS_BOUNDS_LEARNED = 2
+
+EXPORTED = [
+    "xls_subdomain_create", "xls_chefsi_step", "xls_subdomain_density", "xls_subdomain_destroy",
+    "xls_last_error", "xls_hamiltonian_apply", "xls_subdomain_filter", "xls_subdomain_project",
+    "xls_subdomain_rotate", "xls_subdomain_residual", "xls_lanczos_bounds", "xls_dense_geneig",
+    "xls_subdomain_get_block", "xls_subdomain_set_block", "xls_subdomain_get_maps",
+    "xls_subdomain_get_projectors", "xls_split_bf16", "xls_set_profiling", "xls_get_stage_times",
+    "xls_subdomain_tune",
+]
+
+
+class XlsError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"xls error {code}: {msg}")
+        self.code = code
+
+
+class xls_projset_t(C.Structure):
+    _fields_ = [("rc", C.c_double), ("gauss_width", C.c_double), ("gamma", C.c_double * 4)]
+
+
+class xls_subdomain_desc_t(C.Structure):
+    _fields_ = [
+        ("n", C.c_int32 * 3), ("h", C.c_double), ("bc", C.c_int32), ("fd_n0", C.c_int32),
+        ("origin", C.c_double * 3), ("v_eff", C.POINTER(C.c_double)),
+        ("n_atoms", C.c_int32), ("atom_xyz", C.POINTER(C.c_double)),
+        ("proj", C.POINTER(xls_projset_t)),
+        ("core_lo", C.c_int32 * 3), ("core_hi", C.c_int32 * 3),
+        ("global_offset", C.c_int64 * 3), ("global_n", C.c_int64 * 3),
+        ("ns", C.c_int32), ("x0", C.POINTER(C.c_double)), ("lanczos_v0", C.POINTER(C.c_double)),
+        ("filter_prec", C.c_int32), ("stream", C.c_void_p),
+    ]
+
+
+class xls_chefsi_params_t(C.Structure):
+    _fields_ = [
+        ("bounds_mode", C.c_int32), ("lam_lo", C.c_double), ("lam_cut", C.c_double),
+        ("lam_max", C.c_double), ("degree", C.c_int32), ("max_iter", C.c_int32),
+        ("resid_tol", C.c_double), ("n_gate", C.c_int32), ("lanczos_k", C.c_int32),
+        ("gemm_prec", C.c_int32),
+    ]
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """The loaded libxls.so (raises if it was never built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with python -m paper_2609_13115_amd.build")
+        L = C.CDLL(LIB_PATH)
+        L.xls_last_error.restype = C.c_char_p
+        L.xls_subdomain_destroy.restype = None
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc < 0:
+        raise XlsError(rc, lib().xls_last_error().decode(errors="replace"))
+    return rc
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _f64(a, shape=None, order="F") -> np.ndarray:
+    out = np.ascontiguousarray(a, dtype=np.float64) if order == "C" else np.asfortranarray(a, dtype=np.float64)
+    if shape is not None and out.size != int(np.prod(shape)):
+        raise ValueError(f"expected {shape} elements, got {out.shape}")
+    return out
+
+
+def xls_set_profiling(on: bool) -> None:
+    _check(lib().xls_set_profiling(C.c_int32(1 if on else 0)))
+
+
+def xls_dense_geneig(Hs: np.ndarray, M: np.ndarray) -> Tuple[np.ndarray, np.ndarray]:
+    n = Hs.shape[0]
+    H = _f64(Hs)
+    Mm = _f64(M)
+    lam = np.zeros(n)
+    Y = np.zeros((n, n), order="F")
+    _check(lib().xls_dense_geneig(C.c_int32(n), _dp(H), _dp(Mm), _dp(lam), _dp(Y)))
+    return lam, Y
+
+
+def xls_split_bf16(a: np.ndarray) -> Tuple[np.ndarray, np.ndarray]:
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    hi = np.zeros(a.size, dtype=np.uint16)
+    lo = np.zeros(a.size, dtype=np.uint16)
+    _check(lib().xls_split_bf16(a.ctypes.data_as(C.POINTER(C.c_float)),
+                                hi.ctypes.data_as(C.POINTER(C.c_uint16)),
+                                lo.ctypes.data_as(C.POINTER(C.c_uint16)), C.c_int64(a.size)))
+    return hi, lo
+
+
+class Subdomain:
+    """Owner of one xls_subdomain_t handle (xls_subdomain_create / _destroy)."""
+
+    def __init__(self, sd, filter_prec: int = XLS_PREC_FP64, x0: Optional[np.ndarray] = None,
+                 stream: Optional[int] = None, lanczos_v0: Optional[np.ndarray] = None):
+        x0 = sd.x0 if x0 is None else x0
+        if x0 is None:
+            raise ValueError("start block x0 is required")
+        self.n = tuple(int(v) for v in sd.n)
+        self.nd = int(np.prod(self.n))
+        self.ns = int(x0.shape[1])
+        self._keep = []
+        d = xls_subdomain_desc_t()
+        d.n = (C.c_int32 * 3)(*self.n)
+        d.h = float(sd.h)
+        d.bc = int(sd.bc)
+        d.fd_n0 = int(getattr(sd, "fd_n0", 6))
+        d.origin = (C.c_double * 3)(*[float(v) for v in sd.origin])
+        v = _f64(sd.v, order="C")
+        d.v_eff = _dp(v)
+        atoms = np.ascontiguousarray(sd.atoms, dtype=np.float64).reshape(-1, 3)
+        d.n_atoms = atoms.shape[0]
+        d.atom_xyz = _dp(atoms)
+        ps = (xls_projset_t * max(1, atoms.shape[0]))()
+        for i in range(atoms.shape[0]):
+            ps[i].rc = float(sd.proj[i, 0])
+            ps[i].gauss_width = float(sd.proj[i, 1])
+            for l in range(4):
+                ps[i].gamma[l] = float(sd.proj[i, 2 + l])
+        d.proj = C.cast(ps, C.POINTER(xls_projset_t))
+        d.core_lo = (C.c_int32 * 3)(*sd.core_lo)
+        d.core_hi = (C.c_int32 * 3)(*sd.core_hi)
+        d.global_offset = (C.c_int64 * 3)(*sd.global_offset)
+        d.global_n = (C.c_int64 * 3)(*sd.global_n)
+        d.ns = self.ns
+        X = _f64(x0)
+        d.x0 = _dp(X)
+        lv = lanczos_v0 if lanczos_v0 is not None else getattr(sd, "lanczos_v0", None)
+        if lv is not None:
+            lv = _f64(lv, order="C")
+            d.lanczos_v0 = _dp(lv)
+        d.filter_prec = int(filter_prec)
+        d.stream = C.c_void_p(stream) if stream else None
+        self._keep = [v, atoms, ps, X, lv]
+        h = C.c_void_p()
+        _check(lib().xls_subdomain_create(C.byref(d), C.byref(h)))
+        self._h = h
+        self._keep = []
+        self.prec = int(filter_prec)
+
+    # lifetime
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().xls_subdomain_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # calls
+    def xls_chefsi_step(self, degree: int, max_iter: int, bounds_mode: int = XLS_BOUNDS_LANCZOS,
+                        lam_lo: float = 0.0, lam_cut: float = 0.0, lam_max: float = 0.0,
+                        resid_tol: float = 0.0, n_gate: int = 0, lanczos_k: int = 20,
+                        gemm_prec: int = XLS_PREC_FP64):
+        p = xls_chefsi_params_t(bounds_mode, lam_lo, lam_cut, lam_max, degree, max_iter, resid_tol,
+                                n_gate, lanczos_k, gemm_prec)
+        ritz = np.zeros(self.ns)
+        resid = np.zeros(self.ns)
+        it = C.c_int32(0)
+        _check(lib().xls_chefsi_step(self._h, C.byref(p), _dp(ritz), _dp(resid), C.byref(it)))
+        return ritz, resid, int(it.value)
+
+    def xls_subdomain_density(self, mu: float, sigma: float):
+        rho = np.zeros(self.nd)
+        c = np.zeros(self.ns)
+        _check(lib().xls_subdomain_density(self._h, C.c_double(mu), C.c_double(sigma), _dp(rho), _dp(c)))
+        return rho, c
+
+    def xls_hamiltonian_apply(self, X: np.ndarray) -> np.ndarray:
+        X = _f64(X.reshape(self.nd, -1))
+        out = np.zeros_like(X, order="F")
+        _check(lib().xls_hamiltonian_apply(self._h, _dp(X), _dp(out), C.c_int32(X.shape[1])))
+        return out
+
+    def xls_subdomain_filter(self, degree: int, a0: float, lam_cut: float, lam_max: float):
+        _check(lib().xls_subdomain_filter(self._h, C.c_int32(degree), C.c_double(a0), C.c_double(lam_cut),
+                                          C.c_double(lam_max)))
+
+    def xls_subdomain_project(self, gemm_prec: int = XLS_PREC_FP64):
+        M = np.zeros((self.ns, self.ns), order="F")
+        Hs = np.zeros((self.ns, self.ns), order="F")
+        _check(lib().xls_subdomain_project(self._h, C.c_int32(gemm_prec), _dp(M), _dp(Hs)))
+        return M, Hs
+
+    def xls_subdomain_rotate(self, Q: np.ndarray, gemm_prec: int = XLS_PREC_FP64):
+        Qf = _f64(Q)
+        _check(lib().xls_subdomain_rotate(self._h, C.c_int32(gemm_prec), _dp(Qf)))
+
+    def xls_subdomain_residual(self, lam: np.ndarray) -> np.ndarray:
+        lam = _f64(lam, order="C")
+        r = np.zeros(self.ns)
+        _check(lib().xls_subdomain_residual(self._h, _dp(lam), _dp(r)))
+        return r
+
+    def xls_lanczos_bounds(self, k: int = 20):
+        lo = C.c_double()
+        up = C.c_double()
+        _check(lib().xls_lanczos_bounds(self._h, C.c_int32(k), C.byref(lo), C.byref(up)))
+        return lo.value, up.value
+
+    def xls_subdomain_get_block(self) -> np.ndarray:
+        X = np.zeros((self.nd, self.ns), order="F")
+        _check(lib().xls_subdomain_get_block(self._h, _dp(X)))
+        return X
+
+    def xls_subdomain_set_block(self, X: np.ndarray):
+        Xf = _f64(X)
+        _check(lib().xls_subdomain_set_block(self._h, _dp(Xf)))
+
+    def xls_subdomain_get_maps(self):
+        m = np.zeros(self.nd, dtype=np.uint8)
+        g = np.zeros(self.nd, dtype=np.int64)
+        _check(lib().xls_subdomain_get_maps(self._h, m.ctypes.data_as(C.POINTER(C.c_uint8)),
+                                            g.ctypes.data_as(C.POINTER(C.c_int64))))
+        return m, g
+
+    def xls_subdomain_get_projectors(self):
+        sizes = np.zeros(2, dtype=np.int64)
+        P64 = C.POINTER(C.c_int64)
+        _check(lib().xls_subdomain_get_projectors(self._h, sizes.ctypes.data_as(P64), None, None, None,
+                                                  None, None))
+        total, na = int(sizes[0]), int(sizes[1])
+        off = np.zeros(na + 1, dtype=np.int32)
+        idx = np.zeros(total, dtype=np.int32)
+        val = np.zeros((total, 4))
+        roff = np.zeros(self.nd + 1, dtype=np.int32)
+        rslot = np.zeros(total, dtype=np.int32)
+        P32 = C.POINTER(C.c_int32)
+        _check(lib().xls_subdomain_get_projectors(
+            self._h, sizes.ctypes.data_as(P64), off.ctypes.data_as(P32), idx.ctypes.data_as(P32),
+            _dp(val), roff.ctypes.data_as(P32), rslot.ctypes.data_as(P32)))
+        return off, idx, val, roff, rslot
+
+    def xls_subdomain_tune(self, prec: int, block: int = 512, ty: int = 0, tz: int = 0):
+        _check(lib().xls_subdomain_tune(self._h, C.c_int32(prec), C.c_int32(block), C.c_int32(ty),
+                                        C.c_int32(tz)))
+
+    def xls_get_stage_times(self):
+        ms = np.zeros(8)
+        cnt = np.zeros(1, dtype=np.int64)
+        n = _check(lib().xls_get_stage_times(self._h, _dp(ms), cnt.ctypes.data_as(C.POINTER(C.c_int64)),
+                                             C.c_int32(8)))
+        return ms[:n], int(cnt[0])

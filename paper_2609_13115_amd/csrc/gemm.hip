@@ -68,6 +68,8 @@ struct Form<MF_F64> {
     acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
   }
   __device__ static double get(const acc_t& a, int r) { return a[r]; }
+  // accumulator element r of a lane holds row (lane/16) + 4r of the 16x16 tile
+  __device__ static int orow(int lane, int r) { return (lane >> 4) + 4 * r; }
 };
 
 template <>
@@ -88,6 +90,8 @@ struct Form<MF_F32> {
     acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
   }
   __device__ static double get(const acc_t& a, int r) { return a[r]; }
+  // accumulator element r of a lane holds row 4(lane/16) + r of the 16x16 tile
+  __device__ static int orow(int lane, int r) { return 4 * (lane >> 4) + r; }
 };
 
 template <>
@@ -116,6 +120,7 @@ struct Form<MF_BF> {
     acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc, 0, 0, 0);
   }
   __device__ static double get(const acc_t& a, int r) { return a[r]; }
+  __device__ static int orow(int lane, int r) { return 4 * (lane >> 4) + r; }
 };
 
 template <int MF, int TILE>
@@ -201,7 +206,7 @@ __global__ __launch_bounds__(256) void gemm_tn_kernel(const TIN* __restrict__ A,
     for (int bj = 0; bj < WB; ++bj)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = m0 + wr * (TILE / 2) + bi * 16 + 4 * (lane >> 4) + r;
+        const int row = m0 + wr * (TILE / 2) + bi * 16 + F::orow(lane, r);
         const int cl = n0 + wc * (TILE / 2) + bj * 16 + (lane & 15);
         if (row < M && cl < N) Ps[row + static_cast<int64_t>(cl) * M] = F::get(acc[bi][bj], r);
       }
@@ -290,7 +295,7 @@ __global__ __launch_bounds__(256) void gemm_nn_kernel(const TIN* __restrict__ A,
     for (int bj = 0; bj < WB; ++bj)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int n = n0 + wr * (TILE / 2) + bi * 16 + 4 * (lane >> 4) + r;
+        const int n = n0 + wr * (TILE / 2) + bi * 16 + F::orow(lane, r);
         const int m = m0 + wc * (TILE / 2) + bj * 16 + (lane & 15);
         if (m < M && n < N) C[m + static_cast<int64_t>(n) * ldc] = static_cast<TOUT>(F::get(acc[bi][bj], r));
       }

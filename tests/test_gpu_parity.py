@@ -182,8 +182,10 @@ def test_projection_fp64(ns):
     assert rel_err(Hs, Hr) <= 1e-12
 
 
+# split-BF16 keeps 16 mantissa bits per operand and drops lo*lo: sums of
+# squares are biased low by ~2^-16/3 relative, so its bar is 1e-5
 @pytest.mark.parametrize("prec,tol", [(xls.XLS_PREC_FP64, 1e-12), (xls.XLS_PREC_FP32, 2e-6),
-                                      (xls.XLS_PREC_BF16X3, 2e-6)])
+                                      (xls.XLS_PREC_BF16X3, 1e-5)])
 def test_projection_fp32_block(prec, tol):
     case(f"projection fp32 block gemm={prec}")
     sd = workloads.small_dirichlet(ns=70, shape=(16, 16, 16))
@@ -196,7 +198,7 @@ def test_projection_fp32_block(prec, tol):
     Hr = X.T @ W
     Hr = 0.5 * (Hr + Hr.T)
     assert rel_err(M, Mr) <= tol
-    assert rel_err(Hs, Hr) <= max(tol, 1e-6)
+    assert rel_err(Hs, Hr) <= max(tol, 2e-6)
 
 
 @pytest.mark.parametrize("ns", [6, 65])
@@ -210,8 +212,8 @@ def test_rotation_fp64(ns):
     assert rel_err(out, sd.x0 @ Q) <= 1e-13
 
 
-@pytest.mark.parametrize("prec", [xls.XLS_PREC_FP32, xls.XLS_PREC_BF16X3])
-def test_rotation_fp32(prec):
+@pytest.mark.parametrize("prec,tol", [(xls.XLS_PREC_FP32, 2e-6), (xls.XLS_PREC_BF16X3, 2e-5)])
+def test_rotation_fp32(prec, tol):
     case(f"rotation fp32 gemm={prec}")
     sd = workloads.small_dirichlet(ns=40, shape=(10, 11, 12))
     Q = np.random.default_rng(3).standard_normal((40, 40))
@@ -219,7 +221,7 @@ def test_rotation_fp32(prec):
     with xls.Subdomain(sd, filter_prec=xls.XLS_PREC_FP32) as s:
         s.xls_subdomain_rotate(Q, prec)
         out = s.xls_subdomain_get_block()
-    assert rel_err(out, X @ Q) <= 2e-6
+    assert rel_err(out, X @ Q) <= tol
 
 
 def test_residual_fp64(system):

@@ -103,8 +103,9 @@ struct xls_subdomain_s {
   float* v32 = nullptr;
   double* val64 = nullptr;
   float* val32 = nullptr;
-  int32_t *rev_off = nullptr, *rev_slot = nullptr, *slot_atom = nullptr, *sup_off = nullptr,
-          *sup_idx = nullptr;
+  int32_t *rev_pk = nullptr, *rev_aoff = nullptr, *sup_off = nullptr, *sup_idx = nullptr;
+  double* rev_val64 = nullptr;
+  float* rev_val32 = nullptr;
   double* gamma = nullptr;
   uint8_t* mask = nullptr;
   OpTables<double> op64;
@@ -147,7 +148,7 @@ struct xls_subdomain_s {
   int last_sweeps = 0;
 
   ~xls_subdomain_s() {
-    void* ps[] = {v64, v32, val64, val32, rev_off, rev_slot, slot_atom, sup_off, sup_idx, gamma, mask,
+    void* ps[] = {v64, v32, val64, val32, rev_pk, rev_aoff, rev_val64, rev_val32, sup_off, sup_idx, gamma, mask,
                   blk[0], blk[1], alpha, alpha64, partial, lam_dev, resid_dev, Mdev, Hsdev, Ydev, bwork,
                   gwork, vsmall, rho_dev, cpart, gocc, lz};
     for (void* p : ps) dfree(p);
@@ -311,11 +312,12 @@ void lanczos_run(xls_subdomain_s* s, int k) {
   if (!s->lz || s->lz_cols < k + 2) {
     dfree(s->lz);
     s->lz = nullptr;
-    s->lz = dalloc<TS>(static_cast<size_t>(s->nd) * (k + 2));
+    s->lz = dalloc<TS>(static_cast<size_t>(s->ld) * (k + 2));
     s->lz_cols = k + 2;
   }
+  const int64_t ld = s->ld;
   TS* V = static_cast<TS*>(s->lz);
-  TS* w = V + static_cast<int64_t>(s->nd) * (k + 1);
+  TS* w = V + ld * (k + 1);
   double* al = s->vsmall;         // [k]
   double* be = s->vsmall + 64;    // [k]
   double* coef = s->vsmall + 128; // [k]
@@ -332,14 +334,14 @@ void lanczos_run(xls_subdomain_s* s, int k) {
   std::vector<double> ha, hb;
   int keff = k;
   for (int j = 0; j < k; ++j) {
-    TS* vj = V + static_cast<int64_t>(j) * s->nd;
+    TS* vj = V + j * ld;
     apply_H<TS>(s, vj, w, 1, alph);
     launch_dot<TS>(vj, w, s->nd, part, nblocks, al + j, 0, s->st);
-    launch_lanczos_update<TS>(w, vj, j > 0 ? vj - s->nd : nullptr, al + j, j > 0 ? be + j - 1 : nullptr, s->nd,
+    launch_lanczos_update<TS>(w, vj, j > 0 ? vj - ld : nullptr, al + j, j > 0 ? be + j - 1 : nullptr, s->nd,
                               s->st);
-    gemm_tn<TS>(XLS_PREC_FP64, V, s->nd, w, s->nd, j + 1, 1, s->nd, coef, j + 1, 0, 0, s->gwork,
-                s->gwork_elems, s->st);
-    launch_reorth<TS>(w, V, s->nd, coef, j + 1, s->nd, s->st);
+    gemm_tn<TS>(XLS_PREC_FP64, V, ld, w, ld, j + 1, 1, s->nd, coef, j + 1, 0, 0, s->gwork, s->gwork_elems,
+                s->st);
+    launch_reorth<TS>(w, V, ld, coef, j + 1, s->nd, s->st);
     launch_dot<TS>(w, w, s->nd, part, nblocks, be + j, 1, s->st);
     double ab[2];
     XLS_HIP(hipMemcpyAsync(&ab[0], al + j, 8, hipMemcpyDeviceToHost, s->st));
@@ -354,7 +356,7 @@ void lanczos_run(xls_subdomain_s* s, int k) {
       keff = j + 1;
       break;
     }
-    launch_scale_to<TS>(V + static_cast<int64_t>(j + 1) * s->nd, w, be + j, s->nd, s->st);
+    launch_scale_to<TS>(V + (j + 1) * ld, w, be + j, s->nd, s->st);
   }
   launch_tridiag_extremes(al, be, keff, nrm, s->st);
   double ext[2];
@@ -437,7 +439,6 @@ int chefsi_impl(xls_subdomain_s* s, const xls_chefsi_params_t* p, double* ritz, 
     if (g_profiling) {
       for (int k = 0; k < 6; ++k) s->stage_ms[k] += tm.ms(k, k + 1);
       s->stage_ms[6] += tm.ms(0, 6);
-      s->stage_ms[7] = s->filter_kernel_ms;
     }
     ++it;
     s->ritz = hl;
@@ -473,15 +474,19 @@ int guarded(F&& f) {
   }
 }
 
+// Host column-major N_d x ncols (FP64) <-> device block with leading dimension ld.
 template <typename TS>
 void upload_block(xls_subdomain_s* s, const double* X, void* dst, int ncols) {
   const int64_t n = s->nd * ncols;
+  const size_t es = sizeof(TS);
   if (std::is_same<TS, double>::value) {
-    XLS_HIP(hipMemcpyAsync(dst, X, n * 8, hipMemcpyHostToDevice, s->st));
+    XLS_HIP(hipMemcpy2DAsync(dst, s->ld * es, X, s->nd * es, s->nd * es, ncols, hipMemcpyHostToDevice, s->st));
+    XLS_HIP(hipStreamSynchronize(s->st));
   } else {
     std::vector<float> tmp(n);
     for (int64_t i = 0; i < n; ++i) tmp[i] = static_cast<float>(X[i]);
-    XLS_HIP(hipMemcpyAsync(dst, tmp.data(), n * 4, hipMemcpyHostToDevice, s->st));
+    XLS_HIP(hipMemcpy2DAsync(dst, s->ld * es, tmp.data(), s->nd * es, s->nd * es, ncols, hipMemcpyHostToDevice,
+                             s->st));
     XLS_HIP(hipStreamSynchronize(s->st));
   }
 }
@@ -489,12 +494,14 @@ void upload_block(xls_subdomain_s* s, const double* X, void* dst, int ncols) {
 template <typename TS>
 void download_block(xls_subdomain_s* s, const void* src, double* X, int ncols) {
   const int64_t n = s->nd * ncols;
+  const size_t es = sizeof(TS);
   if (std::is_same<TS, double>::value) {
-    XLS_HIP(hipMemcpyAsync(X, src, n * 8, hipMemcpyDeviceToHost, s->st));
+    XLS_HIP(hipMemcpy2DAsync(X, s->nd * es, src, s->ld * es, s->nd * es, ncols, hipMemcpyDeviceToHost, s->st));
     XLS_HIP(hipStreamSynchronize(s->st));
   } else {
     std::vector<float> tmp(n);
-    XLS_HIP(hipMemcpyAsync(tmp.data(), src, n * 4, hipMemcpyDeviceToHost, s->st));
+    XLS_HIP(hipMemcpy2DAsync(tmp.data(), s->nd * es, src, s->ld * es, s->nd * es, ncols, hipMemcpyDeviceToHost,
+                             s->st));
     XLS_HIP(hipStreamSynchronize(s->st));
     for (int64_t i = 0; i < n; ++i) X[i] = tmp[i];
   }
@@ -529,7 +536,7 @@ int xls_subdomain_create(const xls_subdomain_desc_t* d, xls_subdomain_t* out) {
       s->prec = d->filter_prec;
       s->ns = d->ns;
       s->nd = static_cast<int64_t>(d->n[0]) * d->n[1] * d->n[2];
-      s->ld = s->nd;
+      s->ld = (s->nd + 63) / 64 * 64;  // 256-byte aligned columns (vector loads, GEMM tiles)
       if (d->stream) {
         s->st = static_cast<hipStream_t>(d->stream);
       } else {
@@ -548,20 +555,23 @@ int xls_subdomain_create(const xls_subdomain_desc_t* d, xls_subdomain_t* out) {
       s->val64 = dupload(s->tab.sup_val, s->st);
       std::vector<float> val32(s->tab.sup_val.begin(), s->tab.sup_val.end());
       s->val32 = dupload(val32, s->st);
-      s->rev_off = dupload(s->tab.rev_off, s->st);
-      s->rev_slot = dupload(s->tab.rev_slot, s->st);
-      s->slot_atom = dupload(s->tab.slot_atom, s->st);
+      s->rev_pk = dupload(s->tab.rev_pk, s->st);
+      s->rev_aoff = dupload(s->tab.rev_aoff, s->st);
+      s->rev_val64 = dupload(s->tab.rev_val, s->st);
+      std::vector<float> rv32(s->tab.rev_val.begin(), s->tab.rev_val.end());
+      s->rev_val32 = dupload(rv32, s->st);
       s->sup_off = dupload(s->tab.sup_off, s->st);
       s->sup_idx = dupload(s->tab.sup_idx, s->st);
       s->gamma = dupload(s->tab.gamma, s->st);
       s->mask = dupload(s->tab.core_mask, s->st);
       (void)total;
-      auto fill_op = [&](auto& op, auto* vv, auto* val) {
+      auto fill_op = [&](auto& op, auto* vv, auto* val, auto* rval) {
         op.v = vv;
         op.slot_val = val;
-        op.rev_off = s->rev_off;
-        op.rev_slot = s->rev_slot;
-        op.slot_atom = s->slot_atom;
+        op.rev_pk = s->rev_pk;
+        op.rev_val = rval;
+        op.rev_aoff = s->rev_aoff;
+        op.nent = static_cast<int64_t>(s->tab.rev_slot.size());
         op.sup_off = s->sup_off;
         op.sup_idx = s->sup_idx;
         op.gamma = s->gamma;
@@ -572,12 +582,12 @@ int xls_subdomain_create(const xls_subdomain_desc_t* d, xls_subdomain_t* out) {
         op.periodic = s->bc == XLS_BC_PERIODIC;
         op.h = s->h;
       };
-      fill_op(s->op64, s->v64, s->val64);
-      fill_op(s->op32, s->v32, s->val32);
-      s->cfg64.block = 512;
-      s->cfg32.block = 512;
-      stencil_validate(s->n[0], s->n[1], s->n[2], s->bc == XLS_BC_PERIODIC, 8, s->cfg64);
-      stencil_validate(s->n[0], s->n[1], s->n[2], s->bc == XLS_BC_PERIODIC, 4, s->cfg32);
+      fill_op(s->op64, s->v64, s->val64, s->rev_val64);
+      fill_op(s->op32, s->v32, s->val32, s->rev_val32);
+      s->cfg64.block = 256;
+      s->cfg32.block = 256;
+      stencil_validate(s->n[0], s->n[1], s->n[2], s->bc == XLS_BC_PERIODIC, 8, s->nproj(), s->cfg64);
+      stencil_validate(s->n[0], s->n[1], s->n[2], s->bc == XLS_BC_PERIODIC, 4, s->nproj(), s->cfg32);
       // blocks and work
       const size_t es = s->esize();
       const size_t bl = static_cast<size_t>(s->ld) * s->ns;
@@ -658,7 +668,7 @@ int xls_hamiltonian_apply(xls_subdomain_t s, const double* X, double* HX, int32_
     if (!s || !X || !HX || ncols < 1) fail(XLS_ERR_INVALID_ARG, "bad argument");
     return by_prec(s, [&](auto tag) -> int {
       using TS = decltype(tag);
-      const size_t n = static_cast<size_t>(s->nd) * ncols;
+      const size_t n = static_cast<size_t>(s->ld) * ncols;
       TS* x = dalloc<TS>(n);
       TS* y = nullptr;
       TS* al = nullptr;
@@ -686,6 +696,9 @@ int xls_subdomain_filter(xls_subdomain_t s, int32_t degree, double a0, double la
   return guarded([&]() -> int {
     if (!s || degree < 1) fail(XLS_ERR_INVALID_ARG, "bad argument");
     if (!(a0 < lam_cut && lam_cut < lam_max)) fail(XLS_ERR_INVALID_ARG, "need a0 < lam_cut < lam_max");
+    s->filter_launches = 0;
+    s->filter_kernel_ms = 0.0;
+    s->stage_ms.assign(8, 0.0);
     by_prec(s, [&](auto tag) {
       filter_block<decltype(tag)>(s, degree, a0, lam_cut, lam_max);
       return 0;
@@ -883,7 +896,8 @@ int xls_subdomain_tune(xls_subdomain_t s, int32_t prec, int32_t block, int32_t t
     c.block = block;
     c.ty = ty;
     c.tz = tz;
-    stencil_validate(s->n[0], s->n[1], s->n[2], s->bc == XLS_BC_PERIODIC, prec == XLS_PREC_FP64 ? 8 : 4, c);
+    stencil_validate(s->n[0], s->n[1], s->n[2], s->bc == XLS_BC_PERIODIC, prec == XLS_PREC_FP64 ? 8 : 4,
+                     s->nproj(), c);
     if (prec == XLS_PREC_FP64) {
       // the residual sweep uses the FP64 shape: grow its partial buffer if needed
       const size_t need = std::max(stencil_partial_elems(s->op64, s->ns, c), static_cast<size_t>(s->ns) * 64);
@@ -905,6 +919,8 @@ int xls_subdomain_tune(xls_subdomain_t s, int32_t prec, int32_t block, int32_t t
 int xls_get_stage_times(xls_subdomain_t s, double* ms, int64_t* counts, int32_t cap) {
   return guarded([&]() -> int {
     if (!s || !ms || cap < 1) fail(XLS_ERR_INVALID_ARG, "bad argument");
+    if (s->stage_ms.size() < 8) s->stage_ms.resize(8, 0.0);
+    s->stage_ms[7] = s->filter_kernel_ms;
     const int n = std::min<int>(cap, static_cast<int>(s->stage_ms.size()));
     for (int i = 0; i < n; ++i) ms[i] = s->stage_ms[i];
     if (counts) counts[0] = s->filter_launches;

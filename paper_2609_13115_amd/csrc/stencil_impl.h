@@ -1,0 +1,679 @@
+// Hamiltonian application and the fused Chebyshev filter step (Sec. V-B.2).
+// Kernel templates; instantiated by stencil_f64.hip, stencil_f32.hip and
+// stencil_mix.hip (compiled in parallel).
+//
+// H y = -1/2 Lap y + V y + V_nl y with the 12th-order (n0 = 6) FD Laplacian:
+// 36 neighbour terms (+-1..6 along x, y, z) plus the centre.  One workgroup
+// owns one column (vector), a band of ty full-width x-rows and a z-chunk.  It
+// streams along z: the 13 values of its points' z-column live in a register
+// queue, the current xy plane (with a 6-point halo) is staged in a
+// double-buffered LDS tile, so each input plane is read from HBM once per
+// workgroup.  The nonlocal term is a gather over the reverse CSR of the point
+// (no atomics); the projection coefficients alpha of the same input come from
+// proj_forward.  The Chebyshev recurrence AXPY is fused into the store
+// (Y_{k+1} = a (H Y_k - c Y_k) - b Y_{k-1}, in place over Y_{k-1}), and the
+// residual mode accumulates ||H y - lam y||^2 instead of storing.
+#pragma once
+#include <algorithm>
+#include <type_traits>
+
+#include "xls_internal.h"
+
+namespace xls {
+namespace stencil_detail {
+
+constexpr int R = kRadius;
+constexpr int Q = 2 * R + 1;  // register-queue depth
+constexpr int HMAX = 4;       // halo cells per thread per plane (host checks)
+constexpr int EMAX = 1;       // reverse-CSR entries per point prefetched (more: slow path)
+constexpr int EMASK = (1 << 27) - 1;
+
+template <typename TS, typename TC>
+struct HArgs {
+  const TS* y;
+  const TS* yprev;
+  TS* out;
+  const TC* v;
+  const TC* alpha;
+  const int32_t* rev_pk;
+  const TC* rev_val;
+  const int32_t* rev_aoff;
+  int64_t nent;  // reverse-CSR entries
+  int32_t nproj;
+  int32_t nx, ny, nz;
+  int64_t ld;
+  int32_t periodic;
+  int32_t ty, tz, nyt, nzt;
+  TC wc;     // -1/2 * 3 w0 / h^2
+  TC w[R];   // -1/2 * w_p / h^2
+  TC a, c, b;
+  int32_t has_prev;
+  const double* lam;
+  double* partial;
+};
+
+__device__ __forceinline__ int wrapi(int i, int n) {
+  i %= n;
+  return i < 0 ? i + n : i;
+}
+
+// Block id -> logical id such that consecutive logical ids (tiles of the same
+// column) land on the same XCD: the hardware deals workgroups round-robin to
+// the 8 XCDs, and neighbouring tiles share halo rows in that XCD's L2.
+__device__ __forceinline__ uint32_t xcd_remap(uint32_t bid, uint32_t nb) {
+  const uint32_t xcd = bid & 7u, idx = bid >> 3;
+  const uint32_t q = nb >> 3, r = nb & 7u;
+  return xcd * q + min(xcd, r) + idx;
+}
+
+// Workgroup barrier that waits only for this wave's LDS traffic
+// (lgkmcnt = 0) and leaves global loads in flight: the next plane's
+// prefetches keep streaming across the barrier.  s_waitcnt immediate on
+// gfx9: vmcnt[3:0] | expcnt[6:4] | lgkmcnt[11:8] | vmcnt_hi[15:14];
+// 0xC07F = vmcnt 63 (no wait), expcnt 7 (no wait), lgkmcnt 0.
+__device__ __forceinline__ void lds_barrier() {
+  __asm__ __volatile__("" ::: "memory");
+  __builtin_amdgcn_s_waitcnt(0xC07F);
+  __builtin_amdgcn_s_barrier();
+  __asm__ __volatile__("" ::: "memory");
+}
+
+template <typename TS, typename TC>
+__device__ __forceinline__ TC load_bc(const TS* __restrict__ col, int x, int y, int z, int nx,
+                                      int ny, int nz, int periodic) {
+  if (periodic) {
+    x = wrapi(x, nx);
+    y = wrapi(y, ny);
+    z = wrapi(z, nz);
+  } else if (x < 0 || x >= nx || y < 0 || y >= ny || z < 0 || z >= nz) {
+    return TC(0);
+  }
+  return static_cast<TC>(col[x + nx * (y + ny * z)]);
+}
+
+// ---- buffer-resource loads and stores -------------------------------------
+// Each stream is addressed through a buffer resource: the plane offset lives
+// in a scalar register and each lane keeps a fixed 32-bit byte offset, so a
+// load costs no vector ALU.  A lane offset at or beyond the resource size
+// (kOOB) reads 0 and drops stores: zero halo cells, absent projector entries
+// and inactive lanes need no branches.
+constexpr int kOOB = 0x7FFF0000;
+constexpr int kBufWord3 = 0x00020000;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, int64_t bytes) {
+  const int n = bytes >= kOOB ? kOOB : static_cast<int>(bytes);
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), static_cast<short>(0), n, kBufWord3);
+}
+template <typename T>
+__device__ __forceinline__ T bload(__amdgpu_buffer_rsrc_t r, int voff, int soff);
+template <>
+__device__ __forceinline__ float bload<float>(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+template <>
+__device__ __forceinline__ double bload<double>(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+template <>
+__device__ __forceinline__ int bload<int>(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return static_cast<int>(__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+__device__ __forceinline__ void bstore(float v, __amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, voff, soff, 0);
+}
+__device__ __forceinline__ void bstore(double v, __amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, voff, soff, 0);
+}
+// four projector values of one reverse-CSR entry
+template <typename TC>
+struct Ent4 {
+  TC v[4];
+};
+__device__ __forceinline__ Ent4<float> bload_ent(__amdgpu_buffer_rsrc_t r, int voff) {
+  typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  // cast the whole vector: bit-casting a single vector element reads element 0
+  const f4 f = __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(r, voff, 0, 0));
+  Ent4<float> e;
+  for (int l = 0; l < 4; ++l) e.v[l] = f[l];
+  return e;
+}
+__device__ __forceinline__ Ent4<double> bload_ent_d(__amdgpu_buffer_rsrc_t r, int voff) {
+  typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+  const u4 a = __builtin_amdgcn_raw_buffer_load_b128(r, voff, 0, 0);
+  const u4 b = __builtin_amdgcn_raw_buffer_load_b128(r, voff + 16, 0, 0);
+  typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+  Ent4<double> e;
+  e.v[0] = __builtin_bit_cast(double, u2{a[0], a[1]});
+  e.v[1] = __builtin_bit_cast(double, u2{a[2], a[3]});
+  e.v[2] = __builtin_bit_cast(double, u2{b[0], b[1]});
+  e.v[3] = __builtin_bit_cast(double, u2{b[2], b[3]});
+  return e;
+}
+template <typename TC>
+__device__ __forceinline__ Ent4<TC> load_ent(__amdgpu_buffer_rsrc_t r, int voff);
+template <>
+__device__ __forceinline__ Ent4<float> load_ent<float>(__amdgpu_buffer_rsrc_t r, int voff) {
+  return bload_ent(r, voff);
+}
+template <>
+__device__ __forceinline__ Ent4<double> load_ent<double>(__amdgpu_buffer_rsrc_t r, int voff) {
+  return bload_ent_d(r, voff);
+}
+
+// WS: LDS row stride in elements (compile time, so every neighbour read uses
+// an immediate offset); rows hold nx + 2R entries, nx + 2R <= WS.
+template <typename TS, typename TC, int MODE, int P, int NT, int WS>
+__global__ __launch_bounds__(NT) void hstencil_kernel(HArgs<TS, TC> A) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  TC* lds = reinterpret_cast<TC*>(smem_raw);
+  const int nx = A.nx, ny = A.ny, nz = A.nz;
+  constexpr int W = WS;
+  const int dumpi = W * (A.ty + 2 * R);  // spare slot at the end of each plane buffer
+  const int plane = dumpi + 1;
+  TC* alds = lds + 2 * plane;          // this column's projection coefficients
+
+  const uint32_t logical = xcd_remap(blockIdx.x, gridDim.x);
+  const int tiles = A.nyt * A.nzt;
+  const int col = static_cast<int>(logical / tiles);
+  const int t = static_cast<int>(logical % tiles);
+  const int yt = t % A.nyt, zt = t / A.nyt;
+  const int y0 = yt * A.ty;
+  const int tyv = min(A.ty, ny - y0);
+  const int z0 = zt * A.tz;
+  const int z1 = min(z0 + A.tz, nz);
+  const int npts = nx * tyv;
+  const int tid = threadIdx.x;
+  const int pp = nx * ny;  // points per plane
+  constexpr int ES = sizeof(TS), EC = sizeof(TC);
+
+  const int64_t colbytes = static_cast<int64_t>(nx) * ny * nz * ES;
+  const __amdgpu_buffer_rsrc_t ry = make_rsrc(A.y + static_cast<int64_t>(col) * A.ld, colbytes);
+  const __amdgpu_buffer_rsrc_t rp = make_rsrc(MODE == kFilter && A.has_prev ? A.yprev + static_cast<int64_t>(col) * A.ld
+                                                                            : A.y, colbytes);
+  const __amdgpu_buffer_rsrc_t ro = make_rsrc(MODE == kResid ? A.y : A.out + static_cast<int64_t>(col) * A.ld, colbytes);
+  const __amdgpu_buffer_rsrc_t rv = make_rsrc(A.v, static_cast<int64_t>(nx) * ny * nz * EC);
+  const __amdgpu_buffer_rsrc_t rk = make_rsrc(A.rev_pk, static_cast<int64_t>(nx) * ny * nz * 4);
+  const __amdgpu_buffer_rsrc_t re = make_rsrc(A.rev_val, static_cast<int64_t>(A.nent) * 4 * EC);
+  const __amdgpu_buffer_rsrc_t ra = make_rsrc(A.rev_aoff, static_cast<int64_t>(A.nent) * 4);
+
+  // points owned by this lane: in-plane byte offsets per stream element size
+  // (kOOB when inactive) and LDS index
+  int vo[P], os[P], oc[P], o4[P], li[P];
+#pragma unroll
+  for (int i = 0; i < P; ++i) {
+    const int lin = tid + i * NT;
+    const bool act = lin < npts;
+    const int x = act ? lin % nx : 0, yy = act ? y0 + lin / nx : y0;
+    vo[i] = act ? (x + nx * yy) : -1;
+    os[i] = act ? vo[i] * ES : kOOB;
+    oc[i] = act ? vo[i] * EC : kOOB;
+    o4[i] = act ? vo[i] * 4 : kOOB;
+    li[i] = act ? (R + yy - y0) * W + R + x : dumpi;  // inactive slots write the spare cell
+  }
+
+  // halo cells of a plane (y-halo rows, then periodic x-halo columns): LDS
+  // target (dump when unused) and source byte offset (kOOB reads zero)
+  const int nhy = 2 * R * nx;
+  const int nh = nhy + (A.periodic ? 2 * R * tyv : 0);
+  int hl[HMAX], hoff[HMAX];
+#pragma unroll
+  for (int j = 0; j < HMAX; ++j) {
+    const int e = tid + j * NT;
+    hl[j] = dumpi;
+    hoff[j] = kOOB;
+    if (e < nh) {
+      int x, yy;
+      if (e < nhy) {
+        const int r = e / nx;
+        x = e % nx;
+        yy = r < R ? y0 - R + r : y0 + tyv + (r - R);
+        hl[j] = (r < R ? r : R + tyv + (r - R)) * W + R + x;
+      } else {
+        const int e2 = e - nhy;
+        const int row = e2 / (2 * R), cc = e2 % (2 * R);
+        x = cc < R ? cc - R : nx + (cc - R);
+        yy = y0 + row;
+        hl[j] = (R + row) * W + (cc < R ? cc : nx + cc);
+      }
+      if (A.periodic)
+        hoff[j] = (wrapi(x, nx) + nx * wrapi(yy, ny)) * ES;
+      else if (x >= 0 && x < nx && yy >= 0 && yy < ny)
+        hoff[j] = (x + nx * yy) * ES;
+    }
+  }
+
+  // Dirichlet: x-halo columns are zero for every plane; clear both buffers once
+  if (!A.periodic) {
+    const int nxh = 2 * R * (A.ty + 2 * R);
+    for (int e = tid; e < 2 * nxh; e += NT) {
+      const int b = e / nxh, r = e % nxh;
+      const int row = r / (2 * R), cc = r % (2 * R);
+      lds[b * plane + row * W + (cc < R ? cc : nx + cc)] = TC(0);
+    }
+  }
+  {
+    const TC* __restrict__ ac = A.alpha + static_cast<int64_t>(col) * A.nproj;
+    for (int e = tid; e < A.nproj; e += NT) alds[e] = ac[e];
+  }
+
+  // plane index of plane zz for the queue (wrapped when periodic), or -1
+  // for a zero plane beyond a Dirichlet face; uniform across the workgroup
+  auto qplane = [&](int zz) -> int {
+    if (zz >= 0 && zz < nz) return zz;
+    if (!A.periodic) return -1;
+    return wrapi(zz, nz);
+  };
+  auto ldq = [&](int i, int zq) -> TC {
+    return zq < 0 ? TC(0) : static_cast<TC>(bload<TS>(ry, os[i], zq * pp * ES));
+  };
+
+  // register queue: q[i][slot] holds plane z - R + ((slot - ph) mod Q) while
+  // plane z is computed at phase ph = (z - z0) mod Q, so the queue advances by
+  // renaming (the z-loop is unrolled Q times) instead of moving registers
+  TC q[P][Q];
+#pragma unroll
+  for (int s = 0; s < Q - 1; ++s) {
+    const int zq = qplane(z0 - R + s);
+#pragma unroll
+    for (int i = 0; i < P; ++i) q[i][s] = ldq(i, zq);
+  }
+
+  // prefetch registers.  Two planes ahead: the queue front fr (plane z+1+R
+  // while computing z) and Y_{k-1} yp2; the reverse-CSR word rp2.  One plane
+  // ahead: q's newest slot, V, Y_{k-1}, the entry payload, the halo cells.
+  TC fr[P], yp1[P], yp2[P], vn[P];
+  int rp1[P], rp2[P], ea[P];
+  Ent4<TC> ev[P];
+  TC hv[HMAX];
+  auto load_rest = [&](int z) {  // V, entry payload, rev word (z+1) of plane z
+    const int so = z * pp;
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      vn[i] = bload<TC>(rv, oc[i], so * EC);
+      rp1[i] = rp2[i];
+      const int ne = static_cast<int>(static_cast<uint32_t>(rp1[i]) >> 27);
+      const int e0 = rp1[i] & EMASK;
+      ev[i] = load_ent<TC>(re, ne > 0 ? e0 * 4 * EC : kOOB);
+      ea[i] = bload<int>(ra, ne > 0 ? e0 * 4 : kOOB, 0);
+      rp2[i] = (z + 1 < z1) ? bload<int>(rk, o4[i], (so + pp) * 4) : 0;
+    }
+  };
+  {
+    const int zq0 = qplane(z0 + R), zq1 = qplane(z0 + 1 + R);
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      q[i][Q - 1] = ldq(i, zq0);
+      fr[i] = ldq(i, zq1);
+      rp2[i] = bload<int>(rk, o4[i], z0 * pp * 4);
+      if (MODE == kFilter) {
+        yp1[i] = A.has_prev ? static_cast<TC>(bload<TS>(rp, os[i], z0 * pp * ES)) : TC(0);
+        yp2[i] = (A.has_prev && z0 + 1 < z1) ? static_cast<TC>(bload<TS>(rp, os[i], (z0 + 1) * pp * ES)) : TC(0);
+      }
+    }
+  }
+  load_rest(z0);
+#pragma unroll
+  for (int j = 0; j < HMAX; ++j) hv[j] = static_cast<TC>(bload<TS>(ry, hoff[j], z0 * pp * ES));
+
+  double racc = 0.0;
+  const double lamc = (MODE == kResid) ? A.lam[col] : 0.0;
+
+  // one plane at compile-time phase PH
+  auto step = [&](auto phc, int z) {
+    constexpr int PH = decltype(phc)::value;
+    auto QS = [](int s2) { return (s2 + PH) % Q; };  // physical slot of logical s2
+    TC* buf = lds + (z & 1) * plane;
+    // (a) centre plane and its halo into LDS
+#pragma unroll
+    for (int i = 0; i < P; ++i) buf[li[i]] = q[i][QS(R)];
+#pragma unroll
+    for (int j = 0; j < HMAX; ++j) buf[hl[j]] = hv[j];
+    // (b) next plane's halo
+    if (z + 1 < z1) {
+      const int so1 = (z + 1) * pp * ES;
+#pragma unroll
+      for (int j = 0; j < HMAX; ++j) hv[j] = static_cast<TC>(bload<TS>(ry, hoff[j], so1));
+    }
+    lds_barrier();
+    // (c) plane z
+    const int so = z * pp * ES;
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      const TC* bp = buf + li[i];
+      const TC ctr = q[i][QS(R)];
+      TC lap = A.wc * ctr;
+#pragma unroll
+      for (int p = 1; p <= R; ++p) {
+        const TC sm = (bp[p] + bp[-p]) + (bp[p * W] + bp[-p * W]) + (q[i][QS(R + p)] + q[i][QS(R - p)]);
+        lap += A.w[p - 1] * sm;
+      }
+      TC hy = lap + vn[i] * ctr;
+      {  // one projector set per point is prefetched (absent: zero payload)
+        const TC* al = alds + ea[i];
+        hy += ev[i].v[0] * al[0] + ev[i].v[1] * al[1] + ev[i].v[2] * al[2] + ev[i].v[3] * al[3];
+      }
+      const int ne = static_cast<int>(static_cast<uint32_t>(rp1[i]) >> 27);
+      if (ne > 1) {  // rare: overlapping projector sets
+        const int e0 = rp1[i] & EMASK;
+        for (int e = e0 + 1; e < e0 + ne; ++e) {
+          const TC* sv = A.rev_val + 4 * static_cast<int64_t>(e);
+          const TC* a2 = alds + A.rev_aoff[e];
+          hy += sv[0] * a2[0] + sv[1] * a2[1] + sv[2] * a2[2] + sv[3] * a2[3];
+        }
+      }
+      if (MODE == kApply) {
+        bstore(static_cast<TS>(hy), ro, os[i], so);
+      } else if (MODE == kFilter) {
+        const TC r = A.a * (hy - A.c * ctr) - A.b * yp1[i];
+        bstore(static_cast<TS>(r), ro, os[i], so);
+      } else if (vo[i] >= 0) {
+        const double d = static_cast<double>(hy) - lamc * static_cast<double>(ctr);
+        racc += d * d;
+      }
+    }
+    // (d) advance: the oldest slot takes the next front; refill the
+    // registers just consumed
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      q[i][QS(0)] = fr[i];
+      if (MODE == kFilter) yp1[i] = yp2[i];
+    }
+    if (z + 1 < z1) {
+      const int zq = qplane(z + 2 + R);
+      const int so2 = (z + 2) * pp * ES;
+#pragma unroll
+      for (int i = 0; i < P; ++i) {
+        fr[i] = ldq(i, zq);
+        if (MODE == kFilter)
+          yp2[i] = (A.has_prev && z + 2 < z1) ? static_cast<TC>(bload<TS>(rp, os[i], so2)) : TC(0);
+      }
+      load_rest(z + 1);
+    }
+  };
+
+  using std::integral_constant;
+  for (int z = z0; z < z1; z += Q) {
+    step(integral_constant<int, 0>{}, z);
+    if (z + 1 < z1) step(integral_constant<int, 1>{}, z + 1); else break;
+    if (z + 2 < z1) step(integral_constant<int, 2>{}, z + 2); else break;
+    if (z + 3 < z1) step(integral_constant<int, 3>{}, z + 3); else break;
+    if (z + 4 < z1) step(integral_constant<int, 4>{}, z + 4); else break;
+    if (z + 5 < z1) step(integral_constant<int, 5>{}, z + 5); else break;
+    if (z + 6 < z1) step(integral_constant<int, 6>{}, z + 6); else break;
+    if (z + 7 < z1) step(integral_constant<int, 7>{}, z + 7); else break;
+    if (z + 8 < z1) step(integral_constant<int, 8>{}, z + 8); else break;
+    if (z + 9 < z1) step(integral_constant<int, 9>{}, z + 9); else break;
+    if (z + 10 < z1) step(integral_constant<int, 10>{}, z + 10); else break;
+    if (z + 11 < z1) step(integral_constant<int, 11>{}, z + 11); else break;
+    if (z + 12 < z1) step(integral_constant<int, 12>{}, z + 12); else break;
+  }
+
+  if (MODE == kResid) {
+    // deterministic block reduction: fixed shuffle tree, then fixed LDS order
+    __syncthreads();
+    double* red = reinterpret_cast<double*>(smem_raw);
+    for (int o2 = 32; o2 > 0; o2 >>= 1) racc += __shfl_xor(racc, o2, 64);
+    const int wid = tid >> 6, lane = tid & 63;
+    if (lane == 0) red[wid] = racc;
+    __syncthreads();
+    if (tid == 0) {
+      double sacc = 0.0;
+      for (int w = 0; w < NT / 64; ++w) sacc += red[w];
+      A.partial[static_cast<int64_t>(col) * tiles + t] = sacc;
+    }
+  }
+}
+
+// alpha[col][4a+l] = gamma_{a,l} h^3 sum_s chi_{a,l}(s) y(idx(s), col): one
+// wavefront per (atom, column), lanes stride over the atom's support, fixed
+// xor-shuffle reduction (deterministic).
+template <typename TS, typename TC>
+__global__ __launch_bounds__(256) void proj_forward_kernel(const TS* __restrict__ y, int64_t ld,
+                                                           int ncols, const int32_t* __restrict__ sup_off,
+                                                           const int32_t* __restrict__ sup_idx,
+                                                           const TC* __restrict__ val,
+                                                           const double* __restrict__ gamma,
+                                                           double h3, TC* __restrict__ alpha,
+                                                           int nproj) {
+  const int a = blockIdx.x;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int col = blockIdx.y * 4 + wave;
+  if (col >= ncols) return;
+  const int s0 = sup_off[a], s1 = sup_off[a + 1];
+  const TS* __restrict__ yc = y + static_cast<int64_t>(col) * ld;
+  double acc0 = 0, acc1 = 0, acc2 = 0, acc3 = 0;
+  for (int s = s0 + lane; s < s1; s += 64) {
+    const double yv = static_cast<double>(yc[sup_idx[s]]);
+    const TC* v4 = val + 4 * static_cast<int64_t>(s);
+    acc0 += static_cast<double>(v4[0]) * yv;
+    acc1 += static_cast<double>(v4[1]) * yv;
+    acc2 += static_cast<double>(v4[2]) * yv;
+    acc3 += static_cast<double>(v4[3]) * yv;
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    acc0 += __shfl_xor(acc0, off, 64);
+    acc1 += __shfl_xor(acc1, off, 64);
+    acc2 += __shfl_xor(acc2, off, 64);
+    acc3 += __shfl_xor(acc3, off, 64);
+  }
+  if (lane == 0) {
+    TC* o = alpha + static_cast<int64_t>(col) * nproj + 4 * a;
+    o[0] = static_cast<TC>(gamma[4 * a + 0] * h3 * acc0);
+    o[1] = static_cast<TC>(gamma[4 * a + 1] * h3 * acc1);
+    o[2] = static_cast<TC>(gamma[4 * a + 2] * h3 * acc2);
+    o[3] = static_cast<TC>(gamma[4 * a + 3] * h3 * acc3);
+  }
+}
+
+
+struct TileChoice {
+  int block, ty, nyt, tz, nzt, P, ws;
+  bool vec;
+  size_t smem;
+};
+
+// Launch plan.  Vector runs (XV = 16/elem points per lane) when nx and the
+// column stride are multiples of XV; else one point per lane-slot, up to 4
+// slots per lane.  Default tile: the most rows the block covers.
+inline TileChoice choose_tiles(int nx, int ny, int nz, int elem, int nproj, int64_t ld, const StencilLaunch& cfg) {
+  TileChoice tc{};
+  tc.block = cfg.block == 256 ? 256 : 512;
+  const int XV = 16 / elem;
+  tc.vec = false;
+  (void)XV;
+  (void)ld;
+  int ty;
+  if (tc.vec) {
+    const int tpr = nx / XV;
+    ty = cfg.ty > 0 ? cfg.ty : tc.block / tpr;
+    ty = std::max(1, std::min(ty, ny));
+    if (ty * tpr > tc.block) ty = std::max(1, tc.block / tpr);
+  } else {
+    // default tile: ~2 points per lane in FP32, ~1 in FP64 (measured best on
+    // the 64^3 box: more resident workgroups beat a smaller y-halo)
+    const int target = (elem == 4 ? 2 : 1) * tc.block;
+    ty = cfg.ty > 0 ? cfg.ty : std::max(1, target / nx);
+    ty = std::max(1, std::min(ty, ny));
+  }
+  tc.ty = ty;
+  tc.nyt = (ny + ty - 1) / ty;
+  tc.tz = cfg.tz > 0 ? std::min(cfg.tz, nz) : nz;
+  tc.nzt = (nz + tc.tz - 1) / tc.tz;
+  tc.P = tc.vec ? 1 : (nx * ty + tc.block - 1) / tc.block;
+  tc.ws = (nx + 2 * R <= 80) ? 80 : 128;
+  tc.smem = static_cast<size_t>(elem) * (2 * (static_cast<size_t>(tc.ws) * (ty + 2 * R) + 1) + nproj);
+  return tc;
+}
+
+inline void check_tiles(const TileChoice& tc, int nx, int periodic, int elem) {
+  {
+    if (nx + 2 * R > 128) fail(XLS_ERR_INVALID_ARG, "grid x extent must be <= 116");
+    if (tc.P > 2) fail(XLS_ERR_INVALID_ARG, "stencil tile needs more than 2 points per thread");
+    const int halo = 2 * R * nx + (periodic ? 2 * R * tc.ty : 0);
+    if (halo > HMAX * tc.block) fail(XLS_ERR_INVALID_ARG, "stencil halo exceeds the per-thread budget");
+  }
+  if (tc.smem > 160 * 1024) fail(XLS_ERR_INVALID_ARG, "stencil tile exceeds LDS");
+}
+
+template <typename K>
+void allow_smem(K kern, size_t smem) {
+  if (smem > 64 * 1024 &&
+      hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                          static_cast<int>(smem)) != hipSuccess)
+    fail(XLS_ERR_INVALID_ARG, "stencil tile exceeds the dynamic LDS limit");
+}
+
+template <typename TS, typename TC, int MODE, int P, int WS>
+void launch_mode(const HArgs<TS, TC>& args, dim3 grid, int block, size_t smem, hipStream_t st) {
+  if (block == 256) {
+    allow_smem(hstencil_kernel<TS, TC, MODE, P, 256, WS>, smem);
+    hipLaunchKernelGGL((hstencil_kernel<TS, TC, MODE, P, 256, WS>), grid, dim3(256), smem, st, args);
+  } else {
+    allow_smem(hstencil_kernel<TS, TC, MODE, P, 512, WS>, smem);
+    hipLaunchKernelGGL((hstencil_kernel<TS, TC, MODE, P, 512, WS>), grid, dim3(512), smem, st, args);
+  }
+}
+
+template <typename TS, typename TC, int MODE, int WS>
+void launch_ws(const TileChoice& tc, const HArgs<TS, TC>& args, dim3 grid, size_t smem, hipStream_t st) {
+  switch (tc.P) {
+    case 1: launch_mode<TS, TC, MODE, 1, WS>(args, grid, tc.block, smem, st); break;
+    case 2: launch_mode<TS, TC, MODE, 2, WS>(args, grid, tc.block, smem, st); break;
+    default: fail(XLS_ERR_INVALID_ARG, "stencil tile needs more than 2 points per thread");
+  }
+}
+
+template <typename TS, typename TC, int MODE>
+void launch_any(const TileChoice& tc, const HArgs<TS, TC>& args, dim3 grid, size_t smem, hipStream_t st) {
+  if (tc.ws == 80)
+    launch_ws<TS, TC, MODE, 80>(tc, args, grid, smem, st);
+  else
+    launch_ws<TS, TC, MODE, 128>(tc, args, grid, smem, st);
+}
+
+// FD weights of d^2/dx^2 at 12th order (n0 = 6), from the closed form
+// w_p = 2 (-1)^(p+1) (n0!)^2 / (p^2 (n0-p)! (n0+p)!), w_0 = -2 sum_p w_p.
+inline void fd_weights6(double w[R + 1]) {
+  double f[2 * R + 1];
+  f[0] = 1.0;
+  for (int i = 1; i <= 2 * R; ++i) f[i] = f[i - 1] * i;
+  double s = 0.0;
+  for (int p = 1; p <= R; ++p) {
+    const double sign = (p % 2 == 1) ? 1.0 : -1.0;
+    w[p] = 2.0 * sign * f[R] * f[R] / (static_cast<double>(p) * p * f[R - p] * f[R + p]);
+    s += w[p];
+  }
+  w[0] = -2.0 * s;
+}
+
+}  // namespace stencil_detail
+
+using namespace stencil_detail;
+
+template <typename TC>
+static TileChoice tiles_for(const OpTables<TC>& op, int64_t ld, const StencilLaunch& cfg) {
+  return choose_tiles(op.nx, op.ny, op.nz, sizeof(TC), 4 * op.n_atoms, ld, cfg);
+}
+
+#ifdef XLS_STENCIL_DEFINE_HOST
+void stencil_validate(int nx, int ny, int nz, int periodic, int elem_bytes, int nproj,
+                      const StencilLaunch& cfg) {
+  if (cfg.block != 256 && cfg.block != 512) fail(XLS_ERR_INVALID_ARG, "stencil block must be 256 or 512");
+  if (cfg.ty < 0 || cfg.tz < 0) fail(XLS_ERR_INVALID_ARG, "stencil tile sizes must be >= 0");
+  // both variants a launch may take (vector runs need an aligned column stride)
+  check_tiles(choose_tiles(nx, ny, nz, elem_bytes, nproj, 64, cfg), nx, periodic, elem_bytes);
+  check_tiles(choose_tiles(nx, ny, nz, elem_bytes, nproj, 1, cfg), nx, periodic, elem_bytes);
+}
+
+size_t stencil_partial_elems(const OpTables<float>& op, int ncols, const StencilLaunch& cfg) {
+  const TileChoice a = tiles_for(op, 64, cfg), b = tiles_for(op, 1, cfg);
+  return static_cast<size_t>(ncols) * std::max(a.nyt * a.nzt, b.nyt * b.nzt);
+}
+size_t stencil_partial_elems(const OpTables<double>& op, int ncols, const StencilLaunch& cfg) {
+  const TileChoice a = tiles_for(op, 64, cfg), b = tiles_for(op, 1, cfg);
+  return static_cast<size_t>(ncols) * std::max(a.nyt * a.nzt, b.nyt * b.nzt);
+}
+
+#endif  // XLS_STENCIL_DEFINE_HOST
+
+template <typename TS, typename TC>
+void launch_stencil(StencilMode mode, const OpTables<TC>& op, const TS* y, int64_t ld, int ncols,
+                    const TC* alpha, TS* out, const TS* yprev, double a, double c, double b,
+                    const double* lam, double* partial, double* resid2, hipStream_t st,
+                    const StencilLaunch& cfg) {
+  if (ncols <= 0) return;
+  const TileChoice tc = tiles_for(op, ld, cfg);
+  check_tiles(tc, op.nx, op.periodic, sizeof(TC));
+  HArgs<TS, TC> A{};
+  A.y = y;
+  A.yprev = yprev;
+  A.out = out;
+  A.v = op.v;
+  A.alpha = alpha;
+  A.rev_pk = op.rev_pk;
+  A.rev_val = op.rev_val;
+  A.rev_aoff = op.rev_aoff;
+  A.nent = op.nent;
+  A.nproj = 4 * op.n_atoms;
+  A.nx = op.nx;
+  A.ny = op.ny;
+  A.nz = op.nz;
+  A.ld = ld;
+  A.periodic = op.periodic;
+  A.ty = tc.ty;
+  A.tz = tc.tz;
+  A.nyt = tc.nyt;
+  A.nzt = tc.nzt;
+  double w[R + 1];
+  fd_weights6(w);
+  const double s = -0.5 / (op.h * op.h);
+  A.wc = static_cast<TC>(3.0 * w[0] * s);
+  for (int p = 1; p <= R; ++p) A.w[p - 1] = static_cast<TC>(w[p] * s);
+  A.a = static_cast<TC>(a);
+  A.c = static_cast<TC>(c);
+  A.b = static_cast<TC>(b);
+  A.has_prev = (yprev != nullptr && b != 0.0) ? 1 : 0;
+  A.lam = lam;
+  A.partial = partial;
+  const int64_t nblocks = static_cast<int64_t>(ncols) * tc.nyt * tc.nzt;
+  if (nblocks > 0x7fffffff) fail(XLS_ERR_INVALID_ARG, "too many stencil tiles");
+  size_t smem = tc.smem;
+  if (mode == kResid) smem = std::max(smem, static_cast<size_t>(64 * sizeof(double)));
+  const dim3 grid(static_cast<unsigned>(nblocks));
+  // FP32-arithmetic sweeps never accumulate residuals, and FP64 sweeps of
+  // FP32 blocks never run the filter recurrence: those pairs are not built
+  constexpr bool kHasFilter = std::is_same<TS, TC>::value;
+  constexpr bool kHasResid = std::is_same<TC, double>::value;
+  switch (mode) {
+    case kApply: launch_any<TS, TC, kApply>(tc, A, grid, smem, st); break;
+    case kFilter:
+      if constexpr (kHasFilter) launch_any<TS, TC, kFilter>(tc, A, grid, smem, st);
+      else fail(XLS_ERR_INVALID_ARG, "filter sweep not available for this precision pair");
+      break;
+    case kResid:
+      if constexpr (kHasResid) {
+        launch_any<TS, TC, kResid>(tc, A, grid, smem, st);
+        XLS_LAUNCH_CHECK("hstencil_kernel");
+        launch_reduce_cols(partial, tc.nyt * tc.nzt, ncols, resid2, 1, st);
+        return;
+      } else {
+        fail(XLS_ERR_INVALID_ARG, "residual sweep needs FP64 arithmetic");
+      }
+  }
+  XLS_LAUNCH_CHECK("hstencil_kernel");
+}
+
+template <typename TS, typename TC>
+void launch_proj_forward(const OpTables<TC>& op, const TS* y, int64_t ld, int ncols, TC* alpha,
+                         hipStream_t st) {
+  if (op.n_atoms == 0 || ncols <= 0) return;
+  const dim3 grid(op.n_atoms, (ncols + 3) / 4);
+  const double h3 = op.h * op.h * op.h;
+  hipLaunchKernelGGL((proj_forward_kernel<TS, TC>), grid, dim3(256), 0, st, y, ld, ncols,
+                     op.sup_off, op.sup_idx, op.slot_val, op.gamma, h3, alpha, 4 * op.n_atoms);
+  XLS_LAUNCH_CHECK("proj_forward_kernel");
+}
+
+}  // namespace xls

@@ -39,6 +39,11 @@ struct SetupTables {
   std::vector<int32_t> rev_off;       // [nd + 1]
   std::vector<int32_t> rev_slot;      // [total]
   std::vector<double> gamma;          // [4 * n_atoms]
+  // kernel form of the reverse CSR: per point (first entry | count << 27),
+  // per entry the four projector values and 4*atom (offset into alpha)
+  std::vector<int32_t> rev_pk;        // [nd]
+  std::vector<double> rev_val;        // [4 * total] in reverse-CSR order
+  std::vector<int32_t> rev_aoff;      // [total]
 };
 void build_setup(const xls_subdomain_desc_t& d, SetupTables& t);
 
@@ -51,10 +56,11 @@ enum StencilMode { kApply = 0, kFilter = 1, kResid = 2 };
 template <typename TC>
 struct OpTables {
   const TC* v = nullptr;         // [nd]
-  const TC* slot_val = nullptr;  // [4 * total]
-  const int32_t* rev_off = nullptr;
-  const int32_t* rev_slot = nullptr;
-  const int32_t* slot_atom = nullptr;
+  const TC* slot_val = nullptr;  // [4 * total] support order
+  const int32_t* rev_pk = nullptr;
+  const TC* rev_val = nullptr;   // [4 * total] reverse-CSR order
+  const int32_t* rev_aoff = nullptr;
+  int64_t nent = 0;              // reverse-CSR entries (= support slots)
   const int32_t* sup_off = nullptr;
   const int32_t* sup_idx = nullptr;
   const double* gamma = nullptr;  // [4 * n_atoms]
@@ -65,7 +71,7 @@ struct OpTables {
 };
 
 struct StencilLaunch {
-  int block = 512;  // threads
+  int block = 256;  // threads: 256 or 512
   int ty = 0;       // rows per tile (0 = choose)
   int tz = 0;       // z-chunk (0 = whole nz)
 };
@@ -85,7 +91,8 @@ template <typename TS, typename TC>
 void launch_proj_forward(const OpTables<TC>& op, const TS* y, int64_t ld, int ncols, TC* alpha,
                          hipStream_t st);
 // Throws INVALID_ARG when the launch shape cannot run on this grid.
-void stencil_validate(int nx, int ny, int nz, int periodic, int elem_bytes, const StencilLaunch& cfg);
+void stencil_validate(int nx, int ny, int nz, int periodic, int elem_bytes, int nproj,
+                      const StencilLaunch& cfg);
 size_t stencil_partial_elems(const OpTables<float>& op, int ncols, const StencilLaunch& cfg);
 size_t stencil_partial_elems(const OpTables<double>& op, int ncols, const StencilLaunch& cfg);
 

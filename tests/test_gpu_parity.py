@@ -83,7 +83,7 @@ def test_maps_cfg2_bit_exact():
 # a3: H apply and filter
 # ---------------------------------------------------------------------------
 
-TILES = [(512, 0, 0), (512, 3, 7), (1024, 5, 0), (512, 1, 1)]
+TILES = [(512, 0, 0), (512, 3, 7), (256, 5, 0), (256, 1, 1)]
 
 
 @pytest.mark.parametrize("tile", TILES)
@@ -406,5 +406,5 @@ def test_failure_paths():
             s.xls_chefsi_step(6, 1, xls.XLS_BOUNDS_GIVEN, 1.0, 0.5, 2.0)
         assert ei.value.code == xls.XLS_ERR_INVALID_ARG
         with pytest.raises(xls.XlsError) as ei:
-            s.xls_subdomain_tune(xls.XLS_PREC_FP64, 256, 0, 0)
+            s.xls_subdomain_tune(xls.XLS_PREC_FP64, 128, 0, 0)
         assert ei.value.code == xls.XLS_ERR_INVALID_ARG

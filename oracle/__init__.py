@@ -21,4 +21,4 @@ Parity status of every function is recorded in its module header; every
 function is pinned by a closed form, an invariant or brute force in
 tests/test_oracle_*.py unless it says "parity unpinned".
 """
-from . import grid, projectors, hamiltonian, chefsi, density, bf16  # noqa: F401
+from . import grid, projectors, hamiltonian, chefsi, density, bf16, mlp  # noqa: F401

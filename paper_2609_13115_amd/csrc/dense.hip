@@ -7,9 +7,10 @@
 //                    or below n*eps*M_kk reports NOT_SPD
 //   Rinv = R^-1      one workgroup per column, back-substitution in LDS
 //   C = Rinv^T H Rinv, symmetrised (MFMA GEMMs)
-//   C = Z L Z^T      parallel cyclic Jacobi: each round-robin step rotates n/2
-//                    disjoint (p, q) pairs at once, one launch per step; a
-//                    sweep is n-1 steps; converged when off(C) <= 1e-14 |C|_F
+//   C = Z L Z^T      two-sided block Jacobi: 32-index blocks paired round-robin,
+//                    each pair's subproblem diagonalised in LDS by one
+//                    workgroup, rotations applied to C and V; converged when
+//                    off(C) <= 1e-14 |C|_F
 //   Y = Rinv Z       with Z's columns ordered by ascending eigenvalue
 // The paper reduces to tridiagonal form and runs implicit QL; Jacobi is used
 // here because every step is a wide, regular, launch-parallel update and it
@@ -95,92 +96,6 @@ __device__ __forceinline__ int rr_player(int pos, int s, int np) {
   return pos == 0 ? 0 : ((pos - 1 + s) % (np - 1)) + 1;
 }
 
-struct Rot {
-  int p, q;
-  double c, s, t;
-  bool id;
-};
-
-__device__ __forceinline__ Rot make_rot(const double* __restrict__ C, int n, int np, int s, int k) {
-  Rot r;
-  int a = rr_player(k, s, np), b = rr_player(np - 1 - k, s, np);
-  r.p = min(a, b);
-  r.q = max(a, b);
-  r.c = 1.0;
-  r.s = 0.0;
-  r.t = 0.0;
-  r.id = true;
-  if (r.q >= n) return r;  // paired with the padding index
-  const double app = C[r.p + static_cast<int64_t>(r.p) * n];
-  const double aqq = C[r.q + static_cast<int64_t>(r.q) * n];
-  const double apq = C[r.p + static_cast<int64_t>(r.q) * n];
-  const double aapq = fabs(apq);
-  if (aapq <= 1e-300 || (aapq < 1e-17 * fabs(app) && aapq < 1e-17 * fabs(aqq))) return r;
-  const double tau = (aqq - app) / (2.0 * apq);
-  double t;
-  if (fabs(tau) > 1e150) {
-    t = 0.5 / tau;
-  } else {
-    t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-  }
-  r.c = 1.0 / sqrt(1.0 + t * t);
-  r.s = t * r.c;
-  r.t = t;
-  r.id = false;
-  return r;
-}
-
-// One Jacobi step: Cout = J^T Cin J and V <- V J for the step's n/2 rotations.
-// Threads [0, nb*nb) update 2x2 blocks of C; the rest update V (row, pair).
-__global__ void jacobi_step_kernel(const double* __restrict__ Cin, double* __restrict__ Cout,
-                                   double* __restrict__ V, int n, int np, int s) {
-  const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  const int nb = np / 2;
-  const int64_t ncb = static_cast<int64_t>(nb) * nb;
-  if (e < ncb) {
-    const int bi = static_cast<int>(e % nb), bj = static_cast<int>(e / nb);
-    const Rot ri = make_rot(Cin, n, np, s, bi);
-    const Rot rj = make_rot(Cin, n, np, s, bj);
-    const int P[2] = {ri.p, ri.q}, Qc[2] = {rj.p, rj.q};
-    double a[2][2];
-    for (int x = 0; x < 2; ++x)
-      for (int y = 0; y < 2; ++y)
-        a[x][y] = (P[x] < n && Qc[y] < n) ? Cin[P[x] + static_cast<int64_t>(Qc[y]) * n] : 0.0;
-    double out[2][2];
-    if (bi == bj && !ri.id) {
-      const double apq = a[0][1];
-      out[0][0] = a[0][0] - ri.t * apq;
-      out[1][1] = a[1][1] + ri.t * apq;
-      out[0][1] = 0.0;
-      out[1][0] = 0.0;
-    } else {
-      double b[2][2];  // columns: A J_j
-      for (int x = 0; x < 2; ++x) {
-        b[x][0] = rj.c * a[x][0] - rj.s * a[x][1];
-        b[x][1] = rj.s * a[x][0] + rj.c * a[x][1];
-      }
-      for (int y = 0; y < 2; ++y) {  // rows: J_i^T (A J_j)
-        out[0][y] = ri.c * b[0][y] - ri.s * b[1][y];
-        out[1][y] = ri.s * b[0][y] + ri.c * b[1][y];
-      }
-    }
-    for (int x = 0; x < 2; ++x)
-      for (int y = 0; y < 2; ++y)
-        if (P[x] < n && Qc[y] < n) Cout[P[x] + static_cast<int64_t>(Qc[y]) * n] = out[x][y];
-    return;
-  }
-  const int64_t ev = e - ncb;
-  if (ev >= static_cast<int64_t>(n) * nb) return;
-  const int row = static_cast<int>(ev % n), k = static_cast<int>(ev / n);
-  const Rot r = make_rot(Cin, n, np, s, k);
-  if (r.id) return;
-  double* vp = V + row + static_cast<int64_t>(r.p) * n;
-  double* vq = V + row + static_cast<int64_t>(r.q) * n;
-  const double x = *vp, y = *vq;
-  *vp = r.c * x - r.s * y;
-  *vq = r.s * x + r.c * y;
-}
-
 // off = sum_{i != j} C_ij^2, tot = sum C_ij^2, single workgroup, fixed order.
 __global__ __launch_bounds__(256) void offnorm_kernel(const double* __restrict__ C, int n,
                                                       double* __restrict__ out) {
@@ -231,6 +146,244 @@ __global__ void permute_cols_kernel(const double* __restrict__ V, const int32_t*
   T[e] = V[r + static_cast<int64_t>(perm[c]) * n];
 }
 
+// ---------------------------------------------------------------------------
+// Two-sided block Jacobi.  C is cut into blocks of BJ_NB indices; at each
+// round-robin step the blocks are paired, every pair's (<= 2 BJ_NB)^2
+// subproblem is diagonalised in LDS by one workgroup (cyclic Jacobi), and the
+// pair rotations U_k are applied to C (C <- J^T C J, J = diag(U_k) after the
+// pairing permutation) and to V (V <- V J) with register-tiled products.
+// ---------------------------------------------------------------------------
+constexpr int BJ_NB = 32;
+constexpr int BJ_M = 2 * BJ_NB;  // largest subproblem
+constexpr int BJ_LD = BJ_M + 1;   // padded LDS row
+
+struct BlockPair {
+  int a, b;          // block ids (b may be the empty padding block)
+  int a0, am, b0, bm;
+};
+
+__device__ __forceinline__ BlockPair pair_of(int k, int s, int nblk, int nreal, int n) {
+  BlockPair bp;
+  const int x = rr_player(k, s, nblk), y = rr_player(nblk - 1 - k, s, nblk);
+  bp.a = min(x, y);
+  bp.b = max(x, y);
+  bp.a0 = bp.a * BJ_NB;
+  bp.am = bp.a < nreal ? min(n, bp.a0 + BJ_NB) - bp.a0 : 0;
+  bp.b0 = bp.b * BJ_NB;
+  bp.bm = bp.b < nreal ? min(n, bp.b0 + BJ_NB) - bp.b0 : 0;
+  return bp;
+}
+__device__ __forceinline__ int pair_index(const BlockPair& bp, int i) {
+  return i < bp.am ? bp.a0 + i : bp.b0 + (i - bp.am);
+}
+
+// One workgroup per block pair: diagonalise S = C[P,P] (m x m, m <= 64),
+// writing the rotation U (column-major, leading dimension BJ_M) and diag.
+__global__ __launch_bounds__(256) void bj_solve_kernel(const double* __restrict__ C, int n, int nblk, int nreal,
+                                                       int s, int max_sweeps, double* __restrict__ Uo,
+                                                       double* __restrict__ Do) {
+  __shared__ double S[BJ_M * BJ_LD];
+  __shared__ double U[BJ_M * BJ_LD];
+  __shared__ double rc[BJ_M / 2], rs[BJ_M / 2], rt[BJ_M / 2];
+  __shared__ int rp[BJ_M / 2], rq[BJ_M / 2], rid[BJ_M / 2];
+  __shared__ double red[2][256];
+  const int k = blockIdx.x, tid = threadIdx.x;
+  const BlockPair bp = pair_of(k, s, nblk, nreal, n);
+  const int m = bp.am + bp.bm;
+  double* Uk = Uo + static_cast<int64_t>(k) * BJ_M * BJ_M;
+  double* Dk = Do + static_cast<int64_t>(k) * BJ_M;
+  if (m == 0) return;
+  for (int e = tid; e < m * m; e += 256) {
+    const int i = e % m, j = e / m;
+    S[i + j * BJ_LD] = C[pair_index(bp, i) + static_cast<int64_t>(pair_index(bp, j)) * n];
+    U[i + j * BJ_LD] = (i == j) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  const int M = m + (m & 1);
+  const int half = M / 2;
+  for (int sw = 0; sw < max_sweeps && m > 1; ++sw) {
+    double off = 0.0, tot = 0.0;
+    for (int e = tid; e < m * m; e += 256) {
+      const int i = e % m, j = e / m;
+      const double v = S[i + j * BJ_LD];
+      tot += v * v;
+      if (i != j) off += v * v;
+    }
+    red[0][tid] = off;
+    red[1][tid] = tot;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if (tid < w) {
+        red[0][tid] += red[0][tid + w];
+        red[1][tid] += red[1][tid + w];
+      }
+      __syncthreads();
+    }
+    const bool done = red[0][0] <= 1e-30 * red[1][0];
+    __syncthreads();
+    if (done) break;
+    for (int st = 0; st < M - 1; ++st) {
+      if (tid < half) {
+        const int x = rr_player(tid, st, M), y = rr_player(M - 1 - tid, st, M);
+        const int p = min(x, y), q = max(x, y);
+        double c = 1.0, sn = 0.0, t = 0.0;
+        int id = 1;
+        if (q < m) {
+          const double app = S[p + p * BJ_LD], aqq = S[q + q * BJ_LD], apq = S[p + q * BJ_LD];
+          const double aapq = fabs(apq);
+          if (!(aapq <= 1e-300 || (aapq < 1e-17 * fabs(app) && aapq < 1e-17 * fabs(aqq)))) {
+            const double tau = (aqq - app) / (2.0 * apq);
+            t = fabs(tau) > 1e150 ? 0.5 / tau : (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+            c = 1.0 / sqrt(1.0 + t * t);
+            sn = t * c;
+            id = 0;
+          }
+        }
+        rc[tid] = c;
+        rs[tid] = sn;
+        rt[tid] = t;
+        rp[tid] = p;
+        rq[tid] = q;
+        rid[tid] = id;
+      }
+      __syncthreads();
+      // S <- J^T S J over disjoint 2x2 blocks (in place)
+      for (int e = tid; e < half * half; e += 256) {
+        const int bi = e % half, bj = e / half;
+        const int P0 = rp[bi], P1 = rq[bi], Q0 = rp[bj], Q1 = rq[bj];
+        const int P[2] = {P0, P1}, Qc[2] = {Q0, Q1};
+        double a[2][2];
+        for (int x = 0; x < 2; ++x)
+          for (int y = 0; y < 2; ++y) a[x][y] = (P[x] < m && Qc[y] < m) ? S[P[x] + Qc[y] * BJ_LD] : 0.0;
+        double o[2][2];
+        if (bi == bj && !rid[bi]) {
+          const double apq = a[0][1];
+          o[0][0] = a[0][0] - rt[bi] * apq;
+          o[1][1] = a[1][1] + rt[bi] * apq;
+          o[0][1] = 0.0;
+          o[1][0] = 0.0;
+        } else {
+          double b2[2][2];
+          for (int x = 0; x < 2; ++x) {
+            b2[x][0] = rc[bj] * a[x][0] - rs[bj] * a[x][1];
+            b2[x][1] = rs[bj] * a[x][0] + rc[bj] * a[x][1];
+          }
+          for (int y = 0; y < 2; ++y) {
+            o[0][y] = rc[bi] * b2[0][y] - rs[bi] * b2[1][y];
+            o[1][y] = rs[bi] * b2[0][y] + rc[bi] * b2[1][y];
+          }
+        }
+        for (int x = 0; x < 2; ++x)
+          for (int y = 0; y < 2; ++y)
+            if (P[x] < m && Qc[y] < m) S[P[x] + Qc[y] * BJ_LD] = o[x][y];
+      }
+      // U <- U J
+      for (int e = tid; e < m * half; e += 256) {
+        const int r = e % m, kk = e / m;
+        if (rid[kk]) continue;
+        const int p = rp[kk], q = rq[kk];
+        const double x = U[r + p * BJ_LD], y = U[r + q * BJ_LD];
+        U[r + p * BJ_LD] = rc[kk] * x - rs[kk] * y;
+        U[r + q * BJ_LD] = rs[kk] * x + rc[kk] * y;
+      }
+      __syncthreads();
+    }
+  }
+  for (int e = tid; e < m * m; e += 256) {
+    const int i = e % m, j = e / m;
+    Uk[i + j * BJ_M] = U[i + j * BJ_LD];
+  }
+  for (int i = tid; i < m; i += 256) Dk[i] = S[i + i * BJ_LD];
+}
+
+// 64 x 64 x 64 product R = op(A) B in LDS, 4 x 4 outputs per thread.
+// TA: use A^T.  Matrices column-major with leading dimension BJ_LD.
+template <bool TA>
+__device__ __forceinline__ void bj_mm(const double* A, const double* B, double* R, int mi, int mk, int mj) {
+  const int tid = threadIdx.x;
+  const int ti = (tid % 16) * 4, tj = (tid / 16) * 4;
+  double acc[4][4] = {};
+  for (int l = 0; l < mk; ++l) {
+    double av[4], bv[4];
+    for (int x = 0; x < 4; ++x) av[x] = TA ? A[l + (ti + x) * BJ_LD] : A[(ti + x) + l * BJ_LD];
+    for (int y = 0; y < 4; ++y) bv[y] = B[l + (tj + y) * BJ_LD];
+    for (int x = 0; x < 4; ++x)
+      for (int y = 0; y < 4; ++y) acc[x][y] += av[x] * bv[y];
+  }
+  for (int x = 0; x < 4; ++x)
+    for (int y = 0; y < 4; ++y)
+      if (ti + x < mi && tj + y < mj) R[(ti + x) + (tj + y) * BJ_LD] = acc[x][y];
+}
+
+// Apply the step's pair rotations.  Workgroups [0, npair^2): C blocks
+// Cout[P_a, P_b] = U_a^T Cin[P_a, P_b] U_b (diagonal pairs get their
+// eigenvalues, exact zeros elsewhere).  Workgroups beyond: V[rows, P_k] U_k.
+__global__ __launch_bounds__(256) void bj_update_kernel(const double* __restrict__ Cin, double* __restrict__ Cout,
+                                                        double* __restrict__ V, int n, int nblk, int nreal, int s,
+                                                        const double* __restrict__ Uo,
+                                                        const double* __restrict__ Do) {
+  extern __shared__ double sm[];
+  double* A = sm;
+  double* Ua = sm + BJ_M * BJ_LD;
+  double* Ub = sm + 2 * BJ_M * BJ_LD;
+  double* T = sm + 3 * BJ_M * BJ_LD;
+  const int npair = nblk / 2;
+  const int tid = threadIdx.x;
+  const int wg = blockIdx.x;
+  if (wg < npair * npair) {
+    const int ka = wg % npair, kb = wg / npair;
+    const BlockPair pa = pair_of(ka, s, nblk, nreal, n), pb = pair_of(kb, s, nblk, nreal, n);
+    const int ma = pa.am + pa.bm, mb = pb.am + pb.bm;
+    if (ma == 0 || mb == 0) return;
+    if (ka == kb) {
+      for (int e = tid; e < ma * ma; e += 256) {
+        const int i = e % ma, j = e / ma;
+        Cout[pair_index(pa, i) + static_cast<int64_t>(pair_index(pa, j)) * n] =
+            (i == j) ? Do[static_cast<int64_t>(ka) * BJ_M + i] : 0.0;
+      }
+      return;
+    }
+    const double* U1 = Uo + static_cast<int64_t>(ka) * BJ_M * BJ_M;
+    const double* U2 = Uo + static_cast<int64_t>(kb) * BJ_M * BJ_M;
+    for (int e = tid; e < BJ_M * BJ_M; e += 256) {
+      const int i = e % BJ_M, j = e / BJ_M;
+      A[i + j * BJ_LD] = (i < ma && j < mb) ? Cin[pair_index(pa, i) + static_cast<int64_t>(pair_index(pb, j)) * n] : 0.0;
+      Ua[i + j * BJ_LD] = (i < ma && j < ma) ? U1[i + j * BJ_M] : 0.0;
+      Ub[i + j * BJ_LD] = (i < mb && j < mb) ? U2[i + j * BJ_M] : 0.0;
+    }
+    __syncthreads();
+    bj_mm<true>(Ua, A, T, BJ_M, BJ_M, BJ_M);  // T = Ua^T A
+    __syncthreads();
+    bj_mm<false>(T, Ub, A, BJ_M, BJ_M, BJ_M);  // A = T Ub
+    __syncthreads();
+    for (int e = tid; e < ma * mb; e += 256) {
+      const int i = e % ma, j = e / ma;
+      Cout[pair_index(pa, i) + static_cast<int64_t>(pair_index(pb, j)) * n] = A[i + j * BJ_LD];
+    }
+    return;
+  }
+  // V update: row block rb (64 rows), pair k
+  const int v = wg - npair * npair;
+  const int k = v % npair, rb = v / npair;
+  const BlockPair pk = pair_of(k, s, nblk, nreal, n);
+  const int mk = pk.am + pk.bm;
+  if (mk == 0) return;
+  const int r0 = rb * BJ_M, rm = min(n - r0, BJ_M);
+  const double* Uk = Uo + static_cast<int64_t>(k) * BJ_M * BJ_M;
+  for (int e = tid; e < BJ_M * BJ_M; e += 256) {
+    const int i = e % BJ_M, j = e / BJ_M;
+    A[i + j * BJ_LD] = (i < rm && j < mk) ? V[(r0 + i) + static_cast<int64_t>(pair_index(pk, j)) * n] : 0.0;
+    Ua[i + j * BJ_LD] = (i < mk && j < mk) ? Uk[i + j * BJ_M] : 0.0;
+  }
+  __syncthreads();
+  bj_mm<false>(A, Ua, T, BJ_M, BJ_M, BJ_M);
+  __syncthreads();
+  for (int e = tid; e < rm * mk; e += 256) {
+    const int i = e % rm, j = e / rm;
+    V[(r0 + i) + static_cast<int64_t>(pair_index(pk, j)) * n] = T[i + j * BJ_LD];
+  }
+}
+
 inline unsigned nblk(int64_t n, int b) { return static_cast<unsigned>((n + b - 1) / b); }
 
 }  // namespace
@@ -253,12 +406,15 @@ void dense_alloc(DenseWork& w, int n) {
   al(reinterpret_cast<void**>(&w.scal), (static_cast<size_t>(n) + 16) * 8);
   al(reinterpret_cast<void**>(&w.flag), 64);
   al(reinterpret_cast<void**>(&w.perm), static_cast<size_t>(n) * 4);
+  const size_t npair = ((n + 31) / 32 + 1) / 2 + 1;
+  al(reinterpret_cast<void**>(&w.U), npair * 64 * 64 * 8);
+  al(reinterpret_cast<void**>(&w.D), npair * 64 * 8);
   w.gemm_work_elems = gemm_tn_work_elems(n, n, n);
   al(reinterpret_cast<void**>(&w.gemm_work), w.gemm_work_elems * 8);
 }
 
 void dense_free(DenseWork& w) {
-  double** ds[] = {&w.R, &w.Rinv, &w.C0, &w.C1, &w.V, &w.T, &w.lam, &w.scal, &w.gemm_work};
+  double** ds[] = {&w.R, &w.Rinv, &w.C0, &w.C1, &w.V, &w.T, &w.lam, &w.scal, &w.gemm_work, &w.U, &w.D};
   for (double** p : ds)
     if (*p) {
       (void)hipFree(*p);
@@ -307,22 +463,31 @@ int dense_geneig(DenseWork& w, const double* Hs, const double* M, double* Y, hip
   gemm_nn<double>(XLS_PREC_FP64, w.T, n, w.Rinv, n, n, n, n, w.C1, n, nullptr, st);
   hipLaunchKernelGGL(symmetrize_kernel, dim3(nblk(nn, 256)), dim3(256), 0, st, w.C1, n, w.C0);
   hipLaunchKernelGGL(identity_kernel, dim3(nblk(nn, 256)), dim3(256), 0, st, w.V, n);
-  // --- Jacobi sweeps ---
-  const int np = n + (n & 1);
+  // --- block Jacobi sweeps ---
+  const int nreal = (n + BJ_NB - 1) / BJ_NB;
+  const int nbk = nreal + (nreal & 1);
+  const int npair = nbk / 2;
+  const size_t upd_smem = 4 * static_cast<size_t>(BJ_M) * BJ_LD * sizeof(double);
+  static bool smem_set = false;
+  if (!smem_set) {
+    XLS_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(bj_update_kernel),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(upd_smem)));
+    smem_set = true;
+  }
+  const int nrb = (n + BJ_M - 1) / BJ_M;
   double* cin = w.C0;
   double* cout = w.C1;
-  const int64_t work = static_cast<int64_t>(np / 2) * (np / 2) + static_cast<int64_t>(n) * (np / 2);
   int sweeps = 0;
   bool conv = (n == 1);
-  double hs[2];
-  for (int sw = 0; sw < 40 && !conv && np > 1; ++sw) {
-    for (int s = 0; s < np - 1; ++s) {
-      // every element of Cout is written by the step, so ping-pong needs no copy
-      hipLaunchKernelGGL(jacobi_step_kernel, dim3(nblk(work, 256)), dim3(256), 0, st, cin, cout, w.V, n,
-                         np, s);
+  double hs[2] = {0.0, 1.0};
+  for (int sw = 0; sw < 40 && !conv; ++sw) {
+    for (int s2 = 0; s2 < nbk - 1; ++s2) {
+      hipLaunchKernelGGL(bj_solve_kernel, dim3(npair), dim3(256), 0, st, cin, n, nbk, nreal, s2, 12, w.U, w.D);
+      hipLaunchKernelGGL(bj_update_kernel, dim3(npair * npair + npair * nrb), dim3(256), upd_smem, st, cin, cout,
+                         w.V, n, nbk, nreal, s2, w.U, w.D);
       std::swap(cin, cout);
     }
-    XLS_LAUNCH_CHECK("jacobi_step_kernel");
+    XLS_LAUNCH_CHECK("block Jacobi");
     ++sweeps;
     hipLaunchKernelGGL(offnorm_kernel, dim3(1), dim3(256), 0, st, cin, n, w.scal);
     XLS_HIP(hipMemcpyAsync(hs, w.scal, 16, hipMemcpyDeviceToHost, st));
@@ -330,7 +495,7 @@ int dense_geneig(DenseWork& w, const double* Hs, const double* M, double* Y, hip
     if (!(hs[0] == hs[0]) || !(hs[1] == hs[1])) return XLS_ERR_EIG_NOCONV;
     conv = hs[0] <= 1e-28 * hs[1];
   }
-  if (!conv && np > 1) {
+  if (!conv && n > 1) {
     if (!(hs[0] <= 1e-20 * hs[1])) return XLS_ERR_EIG_NOCONV;
   }
   if (sweeps_out) *sweeps_out = sweeps;

@@ -116,6 +116,8 @@ struct DenseWork {
   int n = 0;
   double *R = nullptr, *Rinv = nullptr, *C0 = nullptr, *C1 = nullptr, *V = nullptr, *T = nullptr;
   double* lam = nullptr;       // [n]
+  double* U = nullptr;         // block-Jacobi pair rotations [npair][64*64]
+  double* D = nullptr;         // block-Jacobi pair eigenvalues [npair][64]
   double* scal = nullptr;      // small scalars / partials
   int32_t* flag = nullptr;     // device status flags
   int32_t* perm = nullptr;     // [n]

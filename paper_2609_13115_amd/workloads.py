@@ -348,3 +348,25 @@ def random_block(nd: int, ns: int, key: Tuple[int, ...]) -> np.ndarray:
     for c in range(ns):
         x[:, c] = _rng(*key, 7, c).standard_normal(nd)
     return x
+
+
+def mlp_init(sizes: Sequence[int] = (64, 128, 128, 3), seed: int = 0) -> List[np.ndarray]:
+    """He-normal initial weights and zero biases of an MLP with the given layer
+    widths, as [W1, b1, W2, b2, ...] with W_l of shape (fan_in, fan_out)."""
+    rng = _rng(SEED_BASE + 5000, seed)
+    out = []
+    for a, b in zip(sizes[:-1], sizes[1:]):
+        out.append(rng.standard_normal((a, b)) * np.sqrt(2.0 / a))
+        out.append(np.zeros(b))
+    return out
+
+
+def minibatch_order(n: int, batch: int, epochs: int, seed: int = 0) -> List[np.ndarray]:
+    """Index lists of the minibatches of `epochs` shuffled passes over n samples."""
+    rng = _rng(SEED_BASE + 6000, seed)
+    out = []
+    for _ in range(epochs):
+        perm = rng.permutation(n)
+        for s in range(0, n, batch):
+            out.append(perm[s:s + batch])
+    return out

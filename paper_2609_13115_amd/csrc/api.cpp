@@ -145,7 +145,6 @@ struct xls_subdomain_s {
   int64_t filter_launches = 0;
   double filter_kernel_ms = 0.0;  // sum over fused-filter stencil launches (profiling on)
   std::vector<hipEvent_t> fev;
-  int last_sweeps = 0;
 
   ~xls_subdomain_s() {
     void* ps[] = {v64, v32, val64, val32, rev_pk, rev_aoff, rev_val64, rev_val32, sup_off, sup_idx, gamma, mask,
@@ -420,14 +419,12 @@ int chefsi_impl(xls_subdomain_s* s, const xls_chefsi_params_t* p, double* ritz, 
                   s->st);
     }
     tm.mark();
-    int sweeps = 0;
-    const int rc = dense_geneig(s->dw, s->Hsdev, s->Mdev, s->Ydev, s->st, &sweeps);
-    s->last_sweeps = sweeps;
+    const int rc = dense_geneig(s->dw, s->Hsdev, s->Mdev, s->Ydev, s->st);
     if (rc != XLS_OK) {
       fail(rc, rc == XLS_ERR_NOT_SPD ? "overlap matrix M_s is not positive definite"
                                      : "dense eigensolver did not converge");
     }
-    XLS_HIP(hipMemcpyAsync(s->lam_dev, s->dw.lam, ns * 8, hipMemcpyDeviceToDevice, s->st));
+    XLS_HIP(hipMemcpyAsync(s->lam_dev, s->dw.lam(), ns * 8, hipMemcpyDeviceToDevice, s->st));
     tm.mark();
     rotate_block<TS>(s, gprec, s->Ydev);
     tm.mark();
@@ -787,9 +784,9 @@ int xls_dense_geneig(int32_t n, const double* Hs, const double* M, double* lam, 
       dY = dalloc<double>(nn);
       XLS_HIP(hipMemcpyAsync(dH, Hs, nn * 8, hipMemcpyHostToDevice, st));
       XLS_HIP(hipMemcpyAsync(dM, M, nn * 8, hipMemcpyHostToDevice, st));
-      rc = dense_geneig(w, dH, dM, dY, st, nullptr);
+      rc = dense_geneig(w, dH, dM, dY, st);
       if (rc == XLS_OK) {
-        XLS_HIP(hipMemcpyAsync(lam, w.lam, n * 8, hipMemcpyDeviceToHost, st));
+        XLS_HIP(hipMemcpyAsync(lam, w.lam(), n * 8, hipMemcpyDeviceToHost, st));
         XLS_HIP(hipMemcpyAsync(Y, dY, nn * 8, hipMemcpyDeviceToHost, st));
       }
       XLS_HIP(hipStreamSynchronize(st));

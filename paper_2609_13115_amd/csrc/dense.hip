@@ -1,20 +1,30 @@
 // Dense FP64 generalized symmetric eigensolver for the subspace problem
-// H_s y = lambda M_s y (Sec. V-A.3 step (3); the paper's DSYGVD stage of
-// Sec. V-B.3: Cholesky of M_s, reduction to a standard problem, symmetric
-// eigensolve, back-transformation).
+// H_s y = lambda M_s y (Sec. V-A.3 step (3); the DSYGVD decomposition of
+// Sec. V-B.3: Cholesky of M_s, reduction to a standard problem, reduction to
+// tridiagonal form, tridiagonal eigensolve, back-transformation).
 //
-//   M = R^T R        right-looking Cholesky, one launch per column; a pivot at
-//                    or below n*eps*M_kk reports NOT_SPD
-//   Rinv = R^-1      one workgroup per column, back-substitution in LDS
-//   C = Rinv^T H Rinv, symmetrised (MFMA GEMMs)
-//   C = Z L Z^T      two-sided block Jacobi: 32-index blocks paired round-robin,
-//                    each pair's subproblem diagonalised in LDS by one
-//                    workgroup, rotations applied to C and V; converged when
-//                    off(C) <= 1e-14 |C|_F
-//   Y = Rinv Z       with Z's columns ordered by ascending eigenvalue
-// The paper reduces to tridiagonal form and runs implicit QL; Jacobi is used
-// here because every step is a wide, regular, launch-parallel update and it
-// converges in two or three sweeps once CheFSI's subspace is nearly settled.
+//   M = R^T R          blocked right-looking Cholesky, 32-column panels; a
+//                      pivot at or below n*eps*M_kk reports NOT_SPD
+//   Rinv = R^-1        one workgroup per column, back-substitution in LDS
+//   C = Rinv^T H Rinv  MFMA GEMMs, symmetrised
+//   C = Q T Q^T        Householder tridiagonalisation, one launch per column:
+//                      every workgroup rebuilds the next Householder vector
+//                      from the previous step's product (deferred rank-2
+//                      update), then owns four trailing columns, applies the
+//                      pending update to them and forms their part of C v
+//   T = S L S^T        split at negligible off-diagonals; eigenvalues by
+//                      Sturm-count bisection (one thread per eigenvalue);
+//                      eigenvectors by inverse iteration with partial
+//                      pivoting (one workgroup per cluster of close
+//                      eigenvalues, modified Gram-Schmidt inside a cluster)
+//   Y = Rinv Q S       reflectors applied in reverse order (LDS-resident
+//                      column blocks), then an MFMA GEMM
+// Every launch count depends on n only, never on the data.
+// The paper's tridiagonal stage is implicit QL with the rotation sequence
+// computed serially and applied across eigenvector rows in parallel; on a GPU
+// that serial chain of square roots and divisions is latency bound, so the
+// tridiagonal problem is solved with bisection and inverse iteration instead,
+// which are parallel over eigenvalues.
 #include <algorithm>
 #include <cmath>
 
@@ -23,44 +33,169 @@
 namespace xls {
 namespace {
 
+constexpr double kEps = 2.220446049250313e-16;
+constexpr double kSafeMin = 2.2250738585072014e-308;
+constexpr int kPanel = 32;       // Cholesky panel width
+constexpr int kInvIters = 3;     // inverse-iteration solves per vector
+constexpr double kOrtol = 1e-3;  // cluster gap, relative to |T|_1
+
+inline unsigned nblk(int64_t n, int b) { return static_cast<unsigned>((n + b - 1) / b); }
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+// Sum over a 256-thread workgroup in a fixed order; every thread gets the
+// result and red[] is free again on return.
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  const double s = (red[0] + red[1]) + (red[2] + red[3]);
+  __syncthreads();
+  return s;
+}
+__device__ __forceinline__ double block_max(double v, double* red) {
+  v = wave_max(v);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  const double s = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+  __syncthreads();
+  return s;
+}
+
+// SplitMix64 finaliser (Steele, Lea and Flood 2014) mapped to [-1, 1): the
+// start vector of inverse iteration for eigenvalue slot s.
+__device__ __forceinline__ double start_value(uint32_t s, uint32_t j) {
+  uint64_t z = ((static_cast<uint64_t>(s) << 32) | j) + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  return static_cast<double>(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+}
+
 __global__ void copy_diag_kernel(const double* __restrict__ A, int n, double* __restrict__ d) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) d[i] = A[i + static_cast<int64_t>(i) * n];
 }
 
-// Schur-complement update of the trailing lower triangle by column k.
-__global__ void chol_step_kernel(double* __restrict__ A, int n, int k, const double* __restrict__ diag0,
-                                 int32_t* __restrict__ flag) {
+// ---------------------------------------------------------------------------
+// Cholesky.  Panel j0: every workgroup factors the nb x nb diagonal block of
+// the (updated) upper triangle in LDS; workgroup 0 stores R11, the others
+// solve R11^T R12 = A12 for 256 columns each (one column per thread).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void chol_panel_kernel(const double* __restrict__ A, int n, int j0, int nb,
+                                                         const double* __restrict__ diag0,
+                                                         int32_t* __restrict__ flag, double* __restrict__ R) {
+  __shared__ double S[kPanel * (kPanel + 1)];
   if (*flag) return;
-  const double d = A[k + static_cast<int64_t>(k) * n];
-  const double thr = static_cast<double>(n) * 2.220446049250313e-16 * diag0[k];
-  if (!(d > thr)) {
-    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0 && threadIdx.y == 0) *flag = 1;
+  const int tid = threadIdx.x;
+  constexpr int LD = kPanel + 1;
+  for (int e = tid; e < kPanel * kPanel; e += 256) {
+    const int i = e % kPanel, j = e / kPanel;
+    S[i + j * LD] = (i < nb && j < nb && i <= j) ? A[(j0 + i) + static_cast<int64_t>(j0 + j) * n] : 0.0;
+  }
+  __syncthreads();
+  for (int kk = 0; kk < nb; ++kk) {
+    const double piv = S[kk + kk * LD];
+    if (!(piv > static_cast<double>(n) * kEps * diag0[j0 + kk])) {  // uniform across the workgroup
+      if (blockIdx.x == 0 && tid == 0) *flag = 1;
+      return;
+    }
+    const double r = sqrt(piv);
+    __syncthreads();
+    if (tid < nb) {
+      if (tid > kk) S[kk + tid * LD] /= r;
+      if (tid == kk) S[kk + kk * LD] = r;
+    }
+    __syncthreads();
+    for (int e = tid; e < kPanel * kPanel; e += 256) {
+      const int i = e % kPanel, j = e / kPanel;
+      if (i > kk && i <= j && j < nb) S[i + j * LD] -= S[kk + i * LD] * S[kk + j * LD];
+    }
+    __syncthreads();
+  }
+  if (blockIdx.x == 0) {
+    for (int e = tid; e < nb * nb; e += 256) {
+      const int i = e % nb, j = e / nb;
+      R[(j0 + i) + static_cast<int64_t>(j0 + j) * n] = (i <= j) ? S[i + j * LD] : 0.0;
+    }
     return;
   }
-  const int i = k + 1 + blockIdx.x * 16 + threadIdx.x;
-  const int j = k + 1 + blockIdx.y * 16 + threadIdx.y;
-  if (i >= n || j >= n || j > i) return;
-  const double aik = A[i + static_cast<int64_t>(k) * n];
-  const double ajk = A[j + static_cast<int64_t>(k) * n];
-  A[i + static_cast<int64_t>(j) * n] -= aik * ajk / d;
+  const int c = j0 + nb + (blockIdx.x - 1) * 256 + tid;
+  if (c >= n) return;
+  const double* a = A + static_cast<int64_t>(c) * n + j0;
+  double x[kPanel];
+#pragma unroll
+  for (int i = 0; i < kPanel; ++i) {
+    if (i < nb) {
+      double s = a[i];
+#pragma unroll
+      for (int l = 0; l < i; ++l) s -= S[l + i * LD] * x[l];
+      x[i] = s / S[i + i * LD];
+    } else {
+      x[i] = 0.0;
+    }
+  }
+  double* out = R + static_cast<int64_t>(c) * n + j0;
+#pragma unroll
+  for (int i = 0; i < kPanel; ++i)
+    if (i < nb) out[i] = x[i];
 }
 
-// R (upper, column-major) from the factored lower triangle: R[j][i] = A[i][j]/sqrt(A[j][j]).
-__global__ void chol_finish_kernel(const double* __restrict__ A, int n, double* __restrict__ R) {
-  const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (e >= static_cast<int64_t>(n) * n) return;
-  const int r = static_cast<int>(e % n), c = static_cast<int>(e / n);  // R[r][c]
-  double v = 0.0;
-  if (r <= c) v = A[c + static_cast<int64_t>(r) * n] / sqrt(A[r + static_cast<int64_t>(r) * n]);
-  R[r + static_cast<int64_t>(c) * n] = v;
+// Trailing update of the upper triangle: A22 -= R12^T R12 on 64 x 64 tiles
+// (I <= J), 4 x 4 outputs per thread.
+__global__ __launch_bounds__(256) void chol_update_kernel(double* __restrict__ A, const double* __restrict__ R,
+                                                          int n, int j0, int nb, const int32_t* __restrict__ flag) {
+  __shared__ double Ri[kPanel][64], Rj[kPanel][64];
+  if (*flag) return;
+  const int j1 = j0 + nb;
+  // tile (I, J) from the upper-triangle enumeration idx = J (J + 1) / 2 + I
+  const int idx = blockIdx.x;
+  int J = static_cast<int>((sqrt(8.0 * idx + 1.0) - 1.0) * 0.5);
+  while ((J + 1) * (J + 2) / 2 <= idx) ++J;
+  while (J * (J + 1) / 2 > idx) --J;
+  const int I = idx - J * (J + 1) / 2;
+  const int r0 = j1 + I * 64, c0 = j1 + J * 64;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < kPanel * 64; e += 256) {
+    const int l = e / 64, q = e % 64;
+    Ri[l][q] = (l < nb && r0 + q < n) ? R[(j0 + l) + static_cast<int64_t>(r0 + q) * n] : 0.0;
+    Rj[l][q] = (l < nb && c0 + q < n) ? R[(j0 + l) + static_cast<int64_t>(c0 + q) * n] : 0.0;
+  }
+  __syncthreads();
+  const int ti = (tid % 16) * 4, tj = (tid / 16) * 4;
+  double acc[4][4] = {};
+  for (int l = 0; l < nb; ++l) {
+    double av[4], bv[4];
+#pragma unroll
+    for (int x = 0; x < 4; ++x) av[x] = Ri[l][ti + x];
+#pragma unroll
+    for (int y = 0; y < 4; ++y) bv[y] = Rj[l][tj + y];
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+      for (int y = 0; y < 4; ++y) acc[x][y] += av[x] * bv[y];
+  }
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y) {
+      const int r = r0 + ti + x, c = c0 + tj + y;
+      if (r < n && c < n) A[r + static_cast<int64_t>(c) * n] -= acc[x][y];
+    }
 }
 
 // Column j of R^-1 by back-substitution R x = e_j.
 __global__ __launch_bounds__(256) void trinv_kernel(const double* __restrict__ R, int n,
-                                                    double* __restrict__ Rinv) {
+                                                    double* __restrict__ Rinv, const int32_t* __restrict__ flag) {
   extern __shared__ double b[];
   __shared__ double xi_s;
+  if (*flag) return;
   const int j = blockIdx.x;
   for (int t = threadIdx.x; t < n; t += blockDim.x) b[t] = (t == j) ? 1.0 : 0.0;
   __syncthreads();
@@ -84,424 +219,545 @@ __global__ void symmetrize_kernel(const double* __restrict__ A, int n, double* _
   B[e] = 0.5 * (A[e] + A[c + static_cast<int64_t>(r) * n]);
 }
 
-__global__ void identity_kernel(double* __restrict__ V, int n) {
-  const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (e >= static_cast<int64_t>(n) * n) return;
-  V[e] = (e % n == e / n) ? 1.0 : 0.0;
-}
-
-// Round-robin (circle method) pairing: at step s, position 0 is fixed and the
-// other np-1 players rotate; pair k meets positions k and np-1-k.
-__device__ __forceinline__ int rr_player(int pos, int s, int np) {
-  return pos == 0 ? 0 : ((pos - 1 + s) % (np - 1)) + 1;
-}
-
-// off = sum_{i != j} C_ij^2, tot = sum C_ij^2, single workgroup, fixed order.
-__global__ __launch_bounds__(256) void offnorm_kernel(const double* __restrict__ C, int n,
-                                                      double* __restrict__ out) {
-  __shared__ double so[256], st[256];
-  double off = 0.0, tot = 0.0;
-  const int64_t nn = static_cast<int64_t>(n) * n;
-  for (int64_t e = threadIdx.x; e < nn; e += 256) {
-    const double v = C[e];
-    tot += v * v;
-    if (e % n != e / n) off += v * v;
-  }
-  so[threadIdx.x] = off;
-  st[threadIdx.x] = tot;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) {
-      so[threadIdx.x] += so[threadIdx.x + w];
-      st[threadIdx.x] += st[threadIdx.x + w];
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    out[0] = so[0];
-    out[1] = st[0];
-  }
-}
-
-// Ascending order of the diagonal (ties by index): lam[rank] = d_i, perm[rank] = i.
-__global__ void sort_diag_kernel(const double* __restrict__ C, int n, double* __restrict__ lam,
-                                 int32_t* __restrict__ perm) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const double di = C[i + static_cast<int64_t>(i) * n];
-  int rank = 0;
-  for (int j = 0; j < n; ++j) {
-    const double dj = C[j + static_cast<int64_t>(j) * n];
-    rank += (dj < di || (dj == di && j < i)) ? 1 : 0;
-  }
-  lam[rank] = di;
-  perm[rank] = i;
-}
-
-__global__ void permute_cols_kernel(const double* __restrict__ V, const int32_t* __restrict__ perm, int n,
-                                    double* __restrict__ T) {
-  const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (e >= static_cast<int64_t>(n) * n) return;
-  const int r = static_cast<int>(e % n), c = static_cast<int>(e / n);
-  T[e] = V[r + static_cast<int64_t>(perm[c]) * n];
-}
-
 // ---------------------------------------------------------------------------
-// Two-sided block Jacobi.  C is cut into blocks of BJ_NB indices; at each
-// round-robin step the blocks are paired, every pair's (<= 2 BJ_NB)^2
-// subproblem is diagonalised in LDS by one workgroup (cyclic Jacobi), and the
-// pair rotations U_k are applied to C (C <- J^T C J, J = diag(U_k) after the
-// pairing permutation) and to V (V <- V J) with register-tiled products.
+// Householder tridiagonalisation, step k (lower form: H_k = I - tau v v^T with
+// v_{k+1} = 1, zero above).  On entry A holds the reduction with updates
+// 0..k-2 applied to the columns that are still live; vbuf/pbuf slot (k+1)&1
+// hold v_{k-1} and p_{k-1} = tau_{k-1} A v_{k-1}.  Every workgroup forms
+// w_{k-1} = p - (tau/2)(p^T v) v and the updated column k, and from it the
+// reflector (v_k, tau_k) and T's entries d_k, e_k; workgroup 0 stores them.
+// Wave q of workgroup g then owns column i = k+1+4g+q: it applies the
+// deferred update A -= v w^T + w v^T to rows >= k+1 and forms p_k[i].
+// LDS: w, c/v and v_{k-1}, n doubles each.
 // ---------------------------------------------------------------------------
-constexpr int BJ_NB = 32;
-constexpr int BJ_M = 2 * BJ_NB;  // largest subproblem
-constexpr int BJ_LD = BJ_M + 1;   // padded LDS row
-
-struct BlockPair {
-  int a, b;          // block ids (b may be the empty padding block)
-  int a0, am, b0, bm;
-};
-
-__device__ __forceinline__ BlockPair pair_of(int k, int s, int nblk, int nreal, int n) {
-  BlockPair bp;
-  const int x = rr_player(k, s, nblk), y = rr_player(nblk - 1 - k, s, nblk);
-  bp.a = min(x, y);
-  bp.b = max(x, y);
-  bp.a0 = bp.a * BJ_NB;
-  bp.am = bp.a < nreal ? min(n, bp.a0 + BJ_NB) - bp.a0 : 0;
-  bp.b0 = bp.b * BJ_NB;
-  bp.bm = bp.b < nreal ? min(n, bp.b0 + BJ_NB) - bp.b0 : 0;
-  return bp;
-}
-__device__ __forceinline__ int pair_index(const BlockPair& bp, int i) {
-  return i < bp.am ? bp.a0 + i : bp.b0 + (i - bp.am);
-}
-
-// One workgroup per block pair: diagonalise S = C[P,P] (m x m, m <= 64),
-// writing the rotation U (column-major, leading dimension BJ_M) and diag.
-__global__ __launch_bounds__(256) void bj_solve_kernel(const double* __restrict__ C, int n, int nblk, int nreal,
-                                                       int s, int max_sweeps, double* __restrict__ Uo,
-                                                       double* __restrict__ Do) {
-  __shared__ double S[BJ_M * BJ_LD];
-  __shared__ double U[BJ_M * BJ_LD];
-  __shared__ double rc[BJ_M / 2], rs[BJ_M / 2], rt[BJ_M / 2];
-  __shared__ int rp[BJ_M / 2], rq[BJ_M / 2], rid[BJ_M / 2];
-  __shared__ double red[2][256];
-  const int k = blockIdx.x, tid = threadIdx.x;
-  const BlockPair bp = pair_of(k, s, nblk, nreal, n);
-  const int m = bp.am + bp.bm;
-  double* Uk = Uo + static_cast<int64_t>(k) * BJ_M * BJ_M;
-  double* Dk = Do + static_cast<int64_t>(k) * BJ_M;
-  if (m == 0) return;
-  for (int e = tid; e < m * m; e += 256) {
-    const int i = e % m, j = e / m;
-    S[i + j * BJ_LD] = C[pair_index(bp, i) + static_cast<int64_t>(pair_index(bp, j)) * n];
-    U[i + j * BJ_LD] = (i == j) ? 1.0 : 0.0;
-  }
-  __syncthreads();
-  const int M = m + (m & 1);
-  const int half = M / 2;
-  for (int sw = 0; sw < max_sweeps && m > 1; ++sw) {
-    double off = 0.0, tot = 0.0;
-    for (int e = tid; e < m * m; e += 256) {
-      const int i = e % m, j = e / m;
-      const double v = S[i + j * BJ_LD];
-      tot += v * v;
-      if (i != j) off += v * v;
-    }
-    red[0][tid] = off;
-    red[1][tid] = tot;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-      if (tid < w) {
-        red[0][tid] += red[0][tid + w];
-        red[1][tid] += red[1][tid + w];
-      }
-      __syncthreads();
-    }
-    const bool done = red[0][0] <= 1e-30 * red[1][0];
-    __syncthreads();
-    if (done) break;
-    for (int st = 0; st < M - 1; ++st) {
-      if (tid < half) {
-        const int x = rr_player(tid, st, M), y = rr_player(M - 1 - tid, st, M);
-        const int p = min(x, y), q = max(x, y);
-        double c = 1.0, sn = 0.0, t = 0.0;
-        int id = 1;
-        if (q < m) {
-          const double app = S[p + p * BJ_LD], aqq = S[q + q * BJ_LD], apq = S[p + q * BJ_LD];
-          const double aapq = fabs(apq);
-          if (!(aapq <= 1e-300 || (aapq < 1e-17 * fabs(app) && aapq < 1e-17 * fabs(aqq)))) {
-            const double tau = (aqq - app) / (2.0 * apq);
-            t = fabs(tau) > 1e150 ? 0.5 / tau : (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-            c = 1.0 / sqrt(1.0 + t * t);
-            sn = t * c;
-            id = 0;
-          }
-        }
-        rc[tid] = c;
-        rs[tid] = sn;
-        rt[tid] = t;
-        rp[tid] = p;
-        rq[tid] = q;
-        rid[tid] = id;
-      }
-      __syncthreads();
-      // S <- J^T S J over disjoint 2x2 blocks (in place)
-      for (int e = tid; e < half * half; e += 256) {
-        const int bi = e % half, bj = e / half;
-        const int P0 = rp[bi], P1 = rq[bi], Q0 = rp[bj], Q1 = rq[bj];
-        const int P[2] = {P0, P1}, Qc[2] = {Q0, Q1};
-        double a[2][2];
-        for (int x = 0; x < 2; ++x)
-          for (int y = 0; y < 2; ++y) a[x][y] = (P[x] < m && Qc[y] < m) ? S[P[x] + Qc[y] * BJ_LD] : 0.0;
-        double o[2][2];
-        if (bi == bj && !rid[bi]) {
-          const double apq = a[0][1];
-          o[0][0] = a[0][0] - rt[bi] * apq;
-          o[1][1] = a[1][1] + rt[bi] * apq;
-          o[0][1] = 0.0;
-          o[1][0] = 0.0;
-        } else {
-          double b2[2][2];
-          for (int x = 0; x < 2; ++x) {
-            b2[x][0] = rc[bj] * a[x][0] - rs[bj] * a[x][1];
-            b2[x][1] = rs[bj] * a[x][0] + rc[bj] * a[x][1];
-          }
-          for (int y = 0; y < 2; ++y) {
-            o[0][y] = rc[bi] * b2[0][y] - rs[bi] * b2[1][y];
-            o[1][y] = rs[bi] * b2[0][y] + rc[bi] * b2[1][y];
-          }
-        }
-        for (int x = 0; x < 2; ++x)
-          for (int y = 0; y < 2; ++y)
-            if (P[x] < m && Qc[y] < m) S[P[x] + Qc[y] * BJ_LD] = o[x][y];
-      }
-      // U <- U J
-      for (int e = tid; e < m * half; e += 256) {
-        const int r = e % m, kk = e / m;
-        if (rid[kk]) continue;
-        const int p = rp[kk], q = rq[kk];
-        const double x = U[r + p * BJ_LD], y = U[r + q * BJ_LD];
-        U[r + p * BJ_LD] = rc[kk] * x - rs[kk] * y;
-        U[r + q * BJ_LD] = rs[kk] * x + rc[kk] * y;
-      }
-      __syncthreads();
-    }
-  }
-  for (int e = tid; e < m * m; e += 256) {
-    const int i = e % m, j = e / m;
-    Uk[i + j * BJ_M] = U[i + j * BJ_LD];
-  }
-  for (int i = tid; i < m; i += 256) Dk[i] = S[i + i * BJ_LD];
-}
-
-// 64 x 64 x 64 product R = op(A) B in LDS, 4 x 4 outputs per thread.
-// TA: use A^T.  Matrices column-major with leading dimension BJ_LD.
-template <bool TA>
-__device__ __forceinline__ void bj_mm(const double* A, const double* B, double* R, int mi, int mk, int mj) {
-  const int tid = threadIdx.x;
-  const int ti = (tid % 16) * 4, tj = (tid / 16) * 4;
-  double acc[4][4] = {};
-  for (int l = 0; l < mk; ++l) {
-    double av[4], bv[4];
-    for (int x = 0; x < 4; ++x) av[x] = TA ? A[l + (ti + x) * BJ_LD] : A[(ti + x) + l * BJ_LD];
-    for (int y = 0; y < 4; ++y) bv[y] = B[l + (tj + y) * BJ_LD];
-    for (int x = 0; x < 4; ++x)
-      for (int y = 0; y < 4; ++y) acc[x][y] += av[x] * bv[y];
-  }
-  for (int x = 0; x < 4; ++x)
-    for (int y = 0; y < 4; ++y)
-      if (ti + x < mi && tj + y < mj) R[(ti + x) + (tj + y) * BJ_LD] = acc[x][y];
-}
-
-// Apply the step's pair rotations.  Workgroups [0, npair^2): C blocks
-// Cout[P_a, P_b] = U_a^T Cin[P_a, P_b] U_b (diagonal pairs get their
-// eigenvalues, exact zeros elsewhere).  Workgroups beyond: V[rows, P_k] U_k.
-__global__ __launch_bounds__(256) void bj_update_kernel(const double* __restrict__ Cin, double* __restrict__ Cout,
-                                                        double* __restrict__ V, int n, int nblk, int nreal, int s,
-                                                        const double* __restrict__ Uo,
-                                                        const double* __restrict__ Do) {
+__global__ __launch_bounds__(256) void trd_step_kernel(double* __restrict__ A, int n, int k,
+                                                       double* __restrict__ Vh, double* __restrict__ tau,
+                                                       double* __restrict__ d, double* __restrict__ e,
+                                                       double* __restrict__ vbuf, double* __restrict__ pbuf,
+                                                       const int32_t* __restrict__ flag) {
   extern __shared__ double sm[];
-  double* A = sm;
-  double* Ua = sm + BJ_M * BJ_LD;
-  double* Ub = sm + 2 * BJ_M * BJ_LD;
-  double* T = sm + 3 * BJ_M * BJ_LD;
-  const int npair = nblk / 2;
+  __shared__ double red[4];
+  if (*flag) return;
+  double* w = sm;
+  double* cv = sm + n;
+  double* vp = sm + 2 * n;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const double* vprev = vbuf + ((k + 1) & 1) * static_cast<int64_t>(n);
+  const double* pprev = pbuf + ((k + 1) & 1) * static_cast<int64_t>(n);
+  double* vcur = vbuf + (k & 1) * static_cast<int64_t>(n);
+  double* pcur = pbuf + (k & 1) * static_cast<int64_t>(n);
+  if (k > 0) {
+    double part = 0.0;
+    for (int j = k + tid; j < n; j += 256) {
+      const double vj = vprev[j];
+      vp[j] = vj;
+      part += pprev[j] * vj;
+    }
+    const double K = 0.5 * tau[k - 1] * block_sum(part, red);
+    for (int j = k + tid; j < n; j += 256) w[j] = pprev[j] - K * vp[j];
+    __syncthreads();
+  }
+  const double* colk = A + static_cast<int64_t>(k) * n;
+  for (int j = k + tid; j < n; j += 256) {
+    double c = colk[j];
+    if (k > 0) c -= vp[j] * w[k] + w[j] * vp[k];
+    cv[j] = c;
+  }
+  __syncthreads();
+  const double dk = cv[k], alpha = cv[k + 1];
+  double part = 0.0;
+  for (int j = k + 2 + tid; j < n; j += 256) part += cv[j] * cv[j];
+  const double sig = block_sum(part, red);
+  double t = 0.0, beta = alpha, sc = 0.0;
+  if (sig > 0.0) {
+    beta = -copysign(sqrt(alpha * alpha + sig), alpha);
+    t = (beta - alpha) / beta;
+    sc = 1.0 / (alpha - beta);
+  }
+  for (int j = k + 1 + tid; j < n; j += 256) cv[j] = (j == k + 1) ? 1.0 : (sig > 0.0 ? cv[j] * sc : 0.0);
+  __syncthreads();
+  if (blockIdx.x == 0) {
+    if (tid == 0) {
+      tau[k] = t;
+      d[k] = dk;
+      e[k] = beta;
+    }
+    for (int j = k + 1 + tid; j < n; j += 256) {
+      Vh[j + static_cast<int64_t>(k) * n] = cv[j];
+      vcur[j] = cv[j];
+    }
+  }
+  const int i = k + 1 + blockIdx.x * 4 + wv;
+  if (i >= n) return;
+  const double wi = (k > 0) ? w[i] : 0.0, vpi = (k > 0) ? vp[i] : 0.0;
+  double* col = A + static_cast<int64_t>(i) * n;
+  double acc = 0.0;
+  for (int j = k + 1 + lane; j < n; j += 64) {
+    double a = col[j];
+    if (k > 0) a -= vp[j] * wi + w[j] * vpi;
+    col[j] = a;
+    acc += a * cv[j];
+  }
+  acc = wave_sum(acc);
+  if (lane == 0) pcur[i] = t * acc;
+}
+
+// T's last diagonal entry, |T|_1, negligible off-diagonals set to zero
+// (|e_i| <= eps |T|_1), and for every row the [start, end) of its unreduced
+// block.  scal[0] = |T|_1, scal[1] = pivot floor of the Sturm recurrence.
+__global__ __launch_bounds__(256) void tri_prepare_kernel(const double* __restrict__ A, int n,
+                                                          double* __restrict__ d, const double* __restrict__ e,
+                                                          double* __restrict__ ez, double* __restrict__ e2,
+                                                          int32_t* __restrict__ bs, int32_t* __restrict__ be,
+                                                          double* __restrict__ scal,
+                                                          const int32_t* __restrict__ flag) {
+  __shared__ double red[4];
+  __shared__ int last_start[256], first_start[256];
+  if (*flag) return;
   const int tid = threadIdx.x;
-  const int wg = blockIdx.x;
-  if (wg < npair * npair) {
-    const int ka = wg % npair, kb = wg / npair;
-    const BlockPair pa = pair_of(ka, s, nblk, nreal, n), pb = pair_of(kb, s, nblk, nreal, n);
-    const int ma = pa.am + pa.bm, mb = pb.am + pb.bm;
-    if (ma == 0 || mb == 0) return;
-    if (ka == kb) {
-      for (int e = tid; e < ma * ma; e += 256) {
-        const int i = e % ma, j = e / ma;
-        Cout[pair_index(pa, i) + static_cast<int64_t>(pair_index(pa, j)) * n] =
-            (i == j) ? Do[static_cast<int64_t>(ka) * BJ_M + i] : 0.0;
-      }
-      return;
-    }
-    const double* U1 = Uo + static_cast<int64_t>(ka) * BJ_M * BJ_M;
-    const double* U2 = Uo + static_cast<int64_t>(kb) * BJ_M * BJ_M;
-    for (int e = tid; e < BJ_M * BJ_M; e += 256) {
-      const int i = e % BJ_M, j = e / BJ_M;
-      A[i + j * BJ_LD] = (i < ma && j < mb) ? Cin[pair_index(pa, i) + static_cast<int64_t>(pair_index(pb, j)) * n] : 0.0;
-      Ua[i + j * BJ_LD] = (i < ma && j < ma) ? U1[i + j * BJ_M] : 0.0;
-      Ub[i + j * BJ_LD] = (i < mb && j < mb) ? U2[i + j * BJ_M] : 0.0;
-    }
-    __syncthreads();
-    bj_mm<true>(Ua, A, T, BJ_M, BJ_M, BJ_M);  // T = Ua^T A
-    __syncthreads();
-    bj_mm<false>(T, Ub, A, BJ_M, BJ_M, BJ_M);  // A = T Ub
-    __syncthreads();
-    for (int e = tid; e < ma * mb; e += 256) {
-      const int i = e % ma, j = e / ma;
-      Cout[pair_index(pa, i) + static_cast<int64_t>(pair_index(pb, j)) * n] = A[i + j * BJ_LD];
-    }
-    return;
+  const double dlast = A[(n - 1) + static_cast<int64_t>(n - 1) * n];
+  if (tid == 0) d[n - 1] = dlast;
+  double rmax = 0.0;
+  for (int i = tid; i < n; i += 256) {
+    const double di = (i == n - 1) ? dlast : d[i];
+    const double r = fabs(di) + (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < n ? fabs(e[i]) : 0.0);
+    rmax = fmax(rmax, r);
   }
-  // V update: row block rb (64 rows), pair k
-  const int v = wg - npair * npair;
-  const int k = v % npair, rb = v / npair;
-  const BlockPair pk = pair_of(k, s, nblk, nreal, n);
-  const int mk = pk.am + pk.bm;
-  if (mk == 0) return;
-  const int r0 = rb * BJ_M, rm = min(n - r0, BJ_M);
-  const double* Uk = Uo + static_cast<int64_t>(k) * BJ_M * BJ_M;
-  for (int e = tid; e < BJ_M * BJ_M; e += 256) {
-    const int i = e % BJ_M, j = e / BJ_M;
-    A[i + j * BJ_LD] = (i < rm && j < mk) ? V[(r0 + i) + static_cast<int64_t>(pair_index(pk, j)) * n] : 0.0;
-    Ua[i + j * BJ_LD] = (i < mk && j < mk) ? Uk[i + j * BJ_M] : 0.0;
+  const double tn = block_max(rmax, red);
+  double emax = 0.0;
+  for (int i = tid; i + 1 < n; i += 256) {
+    const double v = (fabs(e[i]) <= kEps * tn) ? 0.0 : e[i];
+    ez[i] = v;
+    e2[i] = v * v;
+    emax = fmax(emax, v * v);
   }
+  const double e2max = block_max(emax, red);
+  if (tid == 0) {
+    scal[0] = tn;
+    scal[1] = kSafeMin * fmax(1.0, e2max);
+  }
+  // row j starts a block when j == 0 or e_{j-1} is negligible; contiguous
+  // chunks per thread, prefix max / suffix min over the chunk summaries.
+  auto starts = [&](int j) { return j == 0 || fabs(e[j - 1]) <= kEps * tn; };
+  const int C = (n + 255) / 256;
+  const int j0 = min(n, tid * C), j1 = min(n, j0 + C);
+  int ls = -1, fs = n;
+  for (int j = j0; j < j1; ++j)
+    if (starts(j)) {
+      ls = j;
+      if (fs == n) fs = j;
+    }
+  last_start[tid] = ls;
+  first_start[tid] = fs;
   __syncthreads();
-  bj_mm<false>(A, Ua, T, BJ_M, BJ_M, BJ_M);
-  __syncthreads();
-  for (int e = tid; e < rm * mk; e += 256) {
-    const int i = e % rm, j = e / rm;
-    V[(r0 + i) + static_cast<int64_t>(pair_index(pk, j)) * n] = T[i + j * BJ_LD];
+  int cur = -1;
+  for (int u = 0; u < tid; ++u) cur = max(cur, last_start[u]);
+  for (int j = j0; j < j1; ++j) {
+    if (starts(j)) cur = j;
+    bs[j] = cur;
+  }
+  int nxt = n;
+  for (int u = 255; u > tid; --u) nxt = min(nxt, first_start[u]);
+  for (int j = j1 - 1; j >= j0; --j) {
+    be[j] = nxt;
+    if (starts(j)) nxt = j;
   }
 }
 
-inline unsigned nblk(int64_t n, int b) { return static_cast<unsigned>((n + b - 1) / b); }
+// Eigenvalue slot s: the (s - start)-th smallest eigenvalue of the block that
+// contains row s, by bisection on Sturm counts (LDL^T pivots of T - x I).
+__global__ __launch_bounds__(64) void tri_bisect_kernel(const double* __restrict__ d, const double* __restrict__ ez,
+                                                        const double* __restrict__ e2, const int32_t* __restrict__ bs,
+                                                        const int32_t* __restrict__ be,
+                                                        const double* __restrict__ scal, int n,
+                                                        double* __restrict__ lam, const int32_t* __restrict__ flag) {
+  if (*flag) return;
+  const int s = blockIdx.x * 64 + threadIdx.x;
+  if (s >= n) return;
+  const int s0 = bs[s], s1 = be[s], l = s - s0;
+  const double tn = scal[0], pivmin = scal[1];
+  double gl = HUGE_VAL, gu = -HUGE_VAL;
+  for (int i = s0; i < s1; ++i) {
+    const double r = (i > s0 ? fabs(ez[i - 1]) : 0.0) + (i + 1 < s1 ? fabs(ez[i]) : 0.0);
+    gl = fmin(gl, d[i] - r);
+    gu = fmax(gu, d[i] + r);
+  }
+  const double atol = 0.5 * kEps * tn;
+  double lo = gl - 2.0 * kEps * tn - pivmin, hi = gu + 2.0 * kEps * tn + pivmin;
+  for (int it = 0; it < 256; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (hi - lo <= fmax(2.0 * kEps * fmax(fabs(lo), fabs(hi)), atol) || !(mid > lo && mid < hi)) break;
+    int cnt = 0;
+    double q = d[s0] - mid;
+    if (fabs(q) < pivmin) q = -pivmin;
+    cnt += q < 0.0;
+    for (int i = s0 + 1; i < s1; ++i) {
+      q = (d[i] - mid) - e2[i - 1] / q;
+      if (fabs(q) < pivmin) q = -pivmin;
+      cnt += q < 0.0;
+    }
+    if (cnt > l)
+      hi = mid;
+    else
+      lo = mid;
+  }
+  lam[s] = 0.5 * (lo + hi);
+}
+
+// Clusters: a new cluster starts at every block start and wherever the gap to
+// the previous eigenvalue of the block exceeds kOrtol |T|_1.  cstart lists the
+// first slot of each cluster, ncl their number.
+__global__ __launch_bounds__(256) void tri_cluster_kernel(const double* __restrict__ lam,
+                                                          const int32_t* __restrict__ bs,
+                                                          const double* __restrict__ scal, int n,
+                                                          int32_t* __restrict__ cstart, int32_t* __restrict__ ncl,
+                                                          const int32_t* __restrict__ flag) {
+  __shared__ int cnt[256];
+  if (*flag) return;
+  const double ortol = kOrtol * scal[0];
+  const int tid = threadIdx.x, C = (n + 255) / 256;
+  const int j0 = min(n, tid * C), j1 = min(n, j0 + C);
+  auto first = [&](int s) { return s == bs[s] || lam[s] - lam[s - 1] > ortol; };
+  int c = 0;
+  for (int s = j0; s < j1; ++s) c += first(s) ? 1 : 0;
+  cnt[tid] = c;
+  __syncthreads();
+  int off = 0;
+  for (int u = 0; u < tid; ++u) off += cnt[u];
+  if (tid == 255) *ncl = off + c;
+  for (int s = j0; s < j1; ++s)
+    if (first(s)) cstart[off++] = s;
+}
+
+// One workgroup per cluster: for each slot s of the cluster, in order, inverse
+// iteration on the cluster's block with shift lam_s (raised to at least the
+// previous shift + 10 eps |T|_1 so that equal eigenvalues get distinct
+// vectors): LU of T - x I with partial pivoting (thread 0), kInvIters solves,
+// each followed by modified Gram-Schmidt against the cluster's earlier vectors
+// and normalisation.  Column s of Z receives the vector (zero off the block).
+// LDS: d, e, u0^-1, u1, u2, multipliers, x (m doubles each) and pivots.
+__global__ __launch_bounds__(256) void tri_inviter_kernel(const double* __restrict__ d,
+                                                          const double* __restrict__ ez,
+                                                          const int32_t* __restrict__ bs,
+                                                          const int32_t* __restrict__ be,
+                                                          const double* __restrict__ lam,
+                                                          const int32_t* __restrict__ cstart,
+                                                          const int32_t* __restrict__ ncl,
+                                                          const double* __restrict__ scal, int n,
+                                                          double* __restrict__ Z, const int32_t* __restrict__ flag) {
+  extern __shared__ double sm[];
+  __shared__ double red[4];
+  if (*flag) return;
+  const int c = blockIdx.x, nc = *ncl;
+  if (c >= nc) return;
+  const int tid = threadIdx.x;
+  const int sb = cstart[c], se = (c + 1 < nc) ? cstart[c + 1] : n;
+  const int s0 = bs[sb], s1 = be[sb], m = s1 - s0;
+  double* dd = sm;
+  double* ee = sm + n;
+  double* r0 = sm + 2 * n;
+  double* u1 = sm + 3 * n;
+  double* u2 = sm + 4 * n;
+  double* ll = sm + 5 * n;
+  double* x = sm + 6 * n;
+  uint8_t* piv = reinterpret_cast<uint8_t*>(sm + 7 * n);
+  for (int j = tid; j < m; j += 256) {
+    dd[j] = d[s0 + j];
+    ee[j] = (j + 1 < m) ? ez[s0 + j] : 0.0;
+  }
+  __syncthreads();
+  const double tn = scal[0];
+  const double pertol = 10.0 * kEps * tn;
+  const double pmin = fmax(1e-3 * kEps * tn, 1e-150);  // pivot floor; growth stays far from overflow
+  double xprev = 0.0;
+  for (int s = sb; s < se; ++s) {
+    double xs = lam[s];
+    if (s > sb && xs - xprev < pertol) xs = xprev + pertol;
+    xprev = xs;
+    if (tid == 0) {
+      double bb = dd[0] - xs, cc = ee[0];
+      for (int i = 0; i + 1 < m; ++i) {
+        const double a = ee[i], b = dd[i + 1] - xs, cn = ee[i + 1];
+        if (fabs(a) > fabs(bb)) {
+          piv[i] = 1;
+          r0[i] = 1.0 / a;
+          u1[i] = b;
+          u2[i] = cn;
+          const double mult = bb / a;
+          ll[i] = mult;
+          bb = cc - mult * b;
+          cc = -mult * cn;
+        } else {
+          piv[i] = 0;
+          const double p = (fabs(bb) < pmin) ? copysign(pmin, bb) : bb;
+          r0[i] = 1.0 / p;
+          u1[i] = cc;
+          u2[i] = 0.0;
+          const double mult = a / p;
+          ll[i] = mult;
+          bb = b - mult * cc;
+          cc = cn;
+        }
+      }
+      r0[m - 1] = 1.0 / ((fabs(bb) < pmin) ? copysign(pmin, bb) : bb);
+    }
+    double part = 0.0;
+    for (int j = tid; j < m; j += 256) {
+      const double b = start_value(static_cast<uint32_t>(s), static_cast<uint32_t>(j));
+      x[j] = b;
+      part += b * b;
+    }
+    const double scale0 = 1.0 / sqrt(block_sum(part, red));
+    for (int j = tid; j < m; j += 256) x[j] *= scale0;
+    __syncthreads();
+    for (int it = 0; it < kInvIters; ++it) {
+      if (tid == 0) {
+        double cur = x[0];
+        for (int i = 0; i + 1 < m; ++i) {
+          const double nx = x[i + 1];
+          if (piv[i]) {
+            x[i] = nx;
+            cur = cur - ll[i] * nx;
+          } else {
+            x[i] = cur;
+            cur = nx - ll[i] * cur;
+          }
+        }
+        double x1 = cur * r0[m - 1], x2 = 0.0;
+        x[m - 1] = x1;
+        for (int i = m - 2; i >= 0; --i) {
+          const double xi = (x[i] - u1[i] * x1 - u2[i] * x2) * r0[i];
+          x[i] = xi;
+          x2 = x1;
+          x1 = xi;
+        }
+      }
+      __syncthreads();
+      for (int t = sb; t < s; ++t) {
+        const double* zt = Z + static_cast<int64_t>(t) * n + s0;
+        double p = 0.0;
+        for (int j = tid; j < m; j += 256) p += zt[j] * x[j];
+        const double dot = block_sum(p, red);
+        for (int j = tid; j < m; j += 256) x[j] -= dot * zt[j];
+      }
+      double mx = 0.0;
+      for (int j = tid; j < m; j += 256) mx = fmax(mx, fabs(x[j]));
+      const double rmx = 1.0 / block_max(mx, red);
+      double q = 0.0;
+      for (int j = tid; j < m; j += 256) {
+        const double y = x[j] * rmx;
+        q += y * y;
+      }
+      const double rs = rmx / sqrt(block_sum(q, red));
+      for (int j = tid; j < m; j += 256) x[j] *= rs;
+      __syncthreads();
+    }
+    double* zs = Z + static_cast<int64_t>(s) * n;
+    for (int r = tid; r < n; r += 256) zs[r] = (r >= s0 && r < s1) ? x[r - s0] : 0.0;
+    __syncthreads();
+  }
+}
+
+// Ascending order of all eigenvalues (ties by slot): lam[rank] = raw[s],
+// perm[rank] = s.
+__global__ __launch_bounds__(256) void tri_rank_kernel(const double* __restrict__ raw, int n,
+                                                       double* __restrict__ lam, int32_t* __restrict__ perm,
+                                                       const int32_t* __restrict__ flag) {
+  extern __shared__ double L[];
+  if (*flag) return;
+  for (int t = threadIdx.x; t < n; t += 256) L[t] = raw[t];
+  __syncthreads();
+  const int s = blockIdx.x * 256 + threadIdx.x;
+  if (s >= n) return;
+  const double ls = L[s];
+  int rank = 0;
+  for (int t = 0; t < n; ++t) rank += (L[t] < ls || (L[t] == ls && t < s)) ? 1 : 0;
+  lam[rank] = ls;
+  perm[rank] = s;
+}
+
+// out[:, c] = H_0 H_1 ... H_{n-2} Z[:, perm[c]] for NC columns per workgroup,
+// held in LDS; thread t owns rows t, t+256, ... throughout.
+constexpr int kBtRows = 11;  // ceil(kDenseMaxN / 256)
+template <int NC>
+__global__ __launch_bounds__(256) void bt_kernel(const double* __restrict__ Z, const int32_t* __restrict__ perm,
+                                                 const double* __restrict__ Vh, const double* __restrict__ tau,
+                                                 int n, double* __restrict__ out, const int32_t* __restrict__ flag) {
+  extern __shared__ double zs[];
+  __shared__ double red[2][4][NC];
+  if (*flag) return;
+  const int c0 = blockIdx.x * NC, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  for (int cc = 0; cc < NC; ++cc) {
+    const int c = c0 + cc;
+    int pc = (c < n) ? perm[c] : 0;
+    pc = (pc >= 0 && pc < n) ? pc : c;  // a rank is always in range; never index out of bounds
+    const double* src = (c < n) ? Z + static_cast<int64_t>(pc) * n : nullptr;
+    for (int j = tid; j < n; j += 256) zs[cc * n + j] = src ? src[j] : 0.0;
+  }
+  __syncthreads();
+  int par = 0;
+  for (int k = n - 2; k >= 0; --k) {
+    const double t = tau[k];
+    if (t == 0.0) continue;
+    const double* v = Vh + static_cast<int64_t>(k) * n;
+    double vr[kBtRows];
+    double acc[NC];
+#pragma unroll
+    for (int cc = 0; cc < NC; ++cc) acc[cc] = 0.0;
+#pragma unroll
+    for (int r = 0; r < kBtRows; ++r) {
+      const int j = tid + 256 * r;
+      vr[r] = (j > k && j < n) ? v[j] : 0.0;
+#pragma unroll
+      for (int cc = 0; cc < NC; ++cc)
+        if (j < n) acc[cc] += vr[r] * zs[cc * n + j];
+    }
+#pragma unroll
+    for (int cc = 0; cc < NC; ++cc) {
+      acc[cc] = wave_sum(acc[cc]);
+      if (lane == 0) red[par][wv][cc] = acc[cc];
+    }
+    __syncthreads();
+    double dot[NC];
+#pragma unroll
+    for (int cc = 0; cc < NC; ++cc)
+      dot[cc] = t * ((red[par][0][cc] + red[par][1][cc]) + (red[par][2][cc] + red[par][3][cc]));
+#pragma unroll
+    for (int r = 0; r < kBtRows; ++r) {
+      const int j = tid + 256 * r;
+      if (j > k && j < n)
+#pragma unroll
+        for (int cc = 0; cc < NC; ++cc) zs[cc * n + j] -= dot[cc] * vr[r];
+    }
+    par ^= 1;
+  }
+  __syncthreads();
+  for (int cc = 0; cc < NC; ++cc) {
+    const int c = c0 + cc;
+    if (c >= n) break;
+    for (int j = tid; j < n; j += 256) out[j + static_cast<int64_t>(c) * n] = zs[cc * n + j];
+  }
+}
+
+void set_smem(const void* fn, size_t bytes) {
+  if (bytes > 64 * 1024)
+    XLS_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(bytes)));
+}
 
 }  // namespace
 
 void dense_alloc(DenseWork& w, int n) {
   dense_free(w);
+  if (n < 1 || n > kDenseMaxN) fail(XLS_ERR_INVALID_ARG, "dense eigensolver supports 1 <= n <= 2800");
   w.n = n;
   const size_t nn = static_cast<size_t>(n) * n;
   auto al = [&](void** p, size_t bytes) {
     if (hipMalloc(p, std::max<size_t>(bytes, 256)) != hipSuccess)
       fail(XLS_ERR_OUT_OF_MEMORY, "dense workspace allocation failed");
   };
-  al(reinterpret_cast<void**>(&w.R), nn * 8);
-  al(reinterpret_cast<void**>(&w.Rinv), nn * 8);
-  al(reinterpret_cast<void**>(&w.C0), nn * 8);
-  al(reinterpret_cast<void**>(&w.C1), nn * 8);
-  al(reinterpret_cast<void**>(&w.V), nn * 8);
-  al(reinterpret_cast<void**>(&w.T), nn * 8);
-  al(reinterpret_cast<void**>(&w.lam), static_cast<size_t>(n) * 8);
+  double** mats[] = {&w.R, &w.Rinv, &w.C0, &w.C1, &w.T, &w.Vh, &w.Z};
+  for (double** p : mats) al(reinterpret_cast<void**>(p), nn * 8);
+  al(reinterpret_cast<void**>(&w.vec), static_cast<size_t>(n) * 8 * DenseWork::kVecs);
   al(reinterpret_cast<void**>(&w.scal), (static_cast<size_t>(n) + 16) * 8);
   al(reinterpret_cast<void**>(&w.flag), 64);
-  al(reinterpret_cast<void**>(&w.perm), static_cast<size_t>(n) * 4);
-  const size_t npair = ((n + 31) / 32 + 1) / 2 + 1;
-  al(reinterpret_cast<void**>(&w.U), npair * 64 * 64 * 8);
-  al(reinterpret_cast<void**>(&w.D), npair * 64 * 8);
+  al(reinterpret_cast<void**>(&w.ivec), static_cast<size_t>(n) * 4 * DenseWork::kIvecs + 64);
   w.gemm_work_elems = gemm_tn_work_elems(n, n, n);
   al(reinterpret_cast<void**>(&w.gemm_work), w.gemm_work_elems * 8);
 }
 
 void dense_free(DenseWork& w) {
-  double** ds[] = {&w.R, &w.Rinv, &w.C0, &w.C1, &w.V, &w.T, &w.lam, &w.scal, &w.gemm_work, &w.U, &w.D};
+  double** ds[] = {&w.R, &w.Rinv, &w.C0, &w.C1, &w.T, &w.Vh, &w.Z, &w.vec, &w.scal, &w.gemm_work};
   for (double** p : ds)
     if (*p) {
       (void)hipFree(*p);
       *p = nullptr;
     }
   if (w.flag) (void)hipFree(w.flag);
-  if (w.perm) (void)hipFree(w.perm);
+  if (w.ivec) (void)hipFree(w.ivec);
   w.flag = nullptr;
-  w.perm = nullptr;
+  w.ivec = nullptr;
   w.n = 0;
 }
 
-int dense_geneig(DenseWork& w, const double* Hs, const double* M, double* Y, hipStream_t st,
-                 int* sweeps_out) {
+int dense_geneig(DenseWork& w, const double* Hs, const double* M, double* Y, hipStream_t st) {
   const int n = w.n;
   const int64_t nn = static_cast<int64_t>(n) * n;
+  double* vec = w.vec;
+  double* lam = vec;  // sorted eigenvalues (w.lam)
+  double* raw = vec + n;
+  double* d = vec + 2 * static_cast<int64_t>(n);
+  double* e = vec + 3 * static_cast<int64_t>(n);
+  double* ez = vec + 4 * static_cast<int64_t>(n);
+  double* e2 = vec + 5 * static_cast<int64_t>(n);
+  double* tau = vec + 6 * static_cast<int64_t>(n);
+  double* vbuf = vec + 7 * static_cast<int64_t>(n);   // 2n
+  double* pbuf = vec + 9 * static_cast<int64_t>(n);   // 2n
+  int32_t* perm = w.ivec;
+  int32_t* bs = w.ivec + n;
+  int32_t* be = w.ivec + 2 * n;
+  int32_t* cstart = w.ivec + 3 * n;
+  int32_t* ncl = w.ivec + 4 * n;
+  double* diag0 = w.scal + 16;
   // --- Cholesky M = R^T R (factor a copy in C0) ---
   XLS_HIP(hipMemcpyAsync(w.C0, M, nn * 8, hipMemcpyDeviceToDevice, st));
   launch_fill_i32(w.flag, 0, 16, st);
-  double* diag0 = w.scal + 16;
+  launch_fill_i32(reinterpret_cast<int32_t*>(w.R), 0, 2 * nn, st);
   hipLaunchKernelGGL(copy_diag_kernel, dim3(nblk(n, 256)), dim3(256), 0, st, w.C0, n, diag0);
-  for (int k = 0; k < n; ++k) {
-    const int m = n - k - 1;
-    const dim3 grid(std::max(1u, nblk(m, 16)), std::max(1u, nblk(m, 16)));
-    hipLaunchKernelGGL(chol_step_kernel, grid, dim3(16, 16), 0, st, w.C0, n, k, diag0, w.flag);
+  for (int j0 = 0; j0 < n; j0 += kPanel) {
+    const int nb = std::min(kPanel, n - j0), rest = n - j0 - nb;
+    hipLaunchKernelGGL(chol_panel_kernel, dim3(1 + nblk(rest, 256)), dim3(256), 0, st, w.C0, n, j0, nb, diag0,
+                       w.flag, w.R);
+    if (rest > 0) {
+      const unsigned T = nblk(rest, 64);
+      hipLaunchKernelGGL(chol_update_kernel, dim3(T * (T + 1) / 2), dim3(256), 0, st, w.C0, w.R, n, j0, nb,
+                         w.flag);
+    }
   }
-  XLS_LAUNCH_CHECK("chol_step_kernel");
+  XLS_LAUNCH_CHECK("cholesky");
   int32_t hflag = 0;
   XLS_HIP(hipMemcpyAsync(&hflag, w.flag, 4, hipMemcpyDeviceToHost, st));
   XLS_HIP(hipStreamSynchronize(st));
   if (hflag) return XLS_ERR_NOT_SPD;
-  hipLaunchKernelGGL(chol_finish_kernel, dim3(nblk(nn, 256)), dim3(256), 0, st, w.C0, n, w.R);
   // --- Rinv ---
   const size_t trinv_smem = static_cast<size_t>(n) * sizeof(double);
-  if (trinv_smem > 64 * 1024) {
-    if (hipFuncSetAttribute(reinterpret_cast<const void*>(trinv_kernel),
-                            hipFuncAttributeMaxDynamicSharedMemorySize,
-                            static_cast<int>(trinv_smem)) != hipSuccess)
-      fail(XLS_ERR_INVALID_ARG, "dense eigensolver: n too large for the triangular inverse");
-  }
-  hipLaunchKernelGGL(trinv_kernel, dim3(n), dim3(256), trinv_smem, st, w.R, n, w.Rinv);
+  set_smem(reinterpret_cast<const void*>(trinv_kernel), trinv_smem);
+  hipLaunchKernelGGL(trinv_kernel, dim3(n), dim3(256), trinv_smem, st, w.R, n, w.Rinv, w.flag);
   XLS_LAUNCH_CHECK("trinv_kernel");
   // --- C = Rinv^T Hs Rinv, symmetrised ---
   gemm_tn<double>(XLS_PREC_FP64, w.Rinv, n, Hs, n, n, n, n, w.T, n, 0, 0, w.gemm_work,
                   w.gemm_work_elems, st);
   gemm_nn<double>(XLS_PREC_FP64, w.T, n, w.Rinv, n, n, n, n, w.C1, n, nullptr, st);
   hipLaunchKernelGGL(symmetrize_kernel, dim3(nblk(nn, 256)), dim3(256), 0, st, w.C1, n, w.C0);
-  hipLaunchKernelGGL(identity_kernel, dim3(nblk(nn, 256)), dim3(256), 0, st, w.V, n);
-  // --- block Jacobi sweeps ---
-  const int nreal = (n + BJ_NB - 1) / BJ_NB;
-  const int nbk = nreal + (nreal & 1);
-  const int npair = nbk / 2;
-  const size_t upd_smem = 4 * static_cast<size_t>(BJ_M) * BJ_LD * sizeof(double);
-  static bool smem_set = false;
-  if (!smem_set) {
-    XLS_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(bj_update_kernel),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(upd_smem)));
-    smem_set = true;
+  // --- tridiagonalisation ---
+  const size_t trd_smem = 3 * static_cast<size_t>(n) * sizeof(double);
+  set_smem(reinterpret_cast<const void*>(trd_step_kernel), trd_smem);
+  for (int k = 0; k + 1 < n; ++k)
+    hipLaunchKernelGGL(trd_step_kernel, dim3(std::max(1u, nblk(n - k - 1, 4))), dim3(256), trd_smem, st, w.C0, n,
+                       k, w.Vh, tau, d, e, vbuf, pbuf, w.flag);
+  XLS_LAUNCH_CHECK("trd_step_kernel");
+  // --- tridiagonal eigenproblem ---
+  hipLaunchKernelGGL(tri_prepare_kernel, dim3(1), dim3(256), 0, st, w.C0, n, d, e, ez, e2, bs, be, w.scal,
+                     w.flag);
+  hipLaunchKernelGGL(tri_bisect_kernel, dim3(nblk(n, 64)), dim3(64), 0, st, d, ez, e2, bs, be, w.scal, n, raw,
+                     w.flag);
+  hipLaunchKernelGGL(tri_cluster_kernel, dim3(1), dim3(256), 0, st, raw, bs, w.scal, n, cstart, ncl, w.flag);
+  const size_t inv_smem = 7 * static_cast<size_t>(n) * sizeof(double) + ((static_cast<size_t>(n) + 7) & ~size_t{7});
+  set_smem(reinterpret_cast<const void*>(tri_inviter_kernel), inv_smem);
+  hipLaunchKernelGGL(tri_inviter_kernel, dim3(n), dim3(256), inv_smem, st, d, ez, bs, be, raw, cstart, ncl,
+                     w.scal, n, w.Z, w.flag);
+  hipLaunchKernelGGL(tri_rank_kernel, dim3(nblk(n, 256)), dim3(256), static_cast<size_t>(n) * sizeof(double), st,
+                     raw, n, lam, perm, w.flag);
+  XLS_LAUNCH_CHECK("tridiagonal eigensolver");
+  // --- back-transformation, Y = Rinv Q Z ---
+  if (n <= 1024) {
+    const size_t sm = 8 * static_cast<size_t>(n) * sizeof(double);
+    set_smem(reinterpret_cast<const void*>(bt_kernel<8>), sm);
+    hipLaunchKernelGGL(bt_kernel<8>, dim3(nblk(n, 8)), dim3(256), sm, st, w.Z, perm, w.Vh, tau, n, w.T, w.flag);
+  } else {
+    const size_t sm = 4 * static_cast<size_t>(n) * sizeof(double);
+    set_smem(reinterpret_cast<const void*>(bt_kernel<4>), sm);
+    hipLaunchKernelGGL(bt_kernel<4>, dim3(nblk(n, 4)), dim3(256), sm, st, w.Z, perm, w.Vh, tau, n, w.T, w.flag);
   }
-  const int nrb = (n + BJ_M - 1) / BJ_M;
-  double* cin = w.C0;
-  double* cout = w.C1;
-  int sweeps = 0;
-  bool conv = (n == 1);
-  double hs[2] = {0.0, 1.0};
-  for (int sw = 0; sw < 40 && !conv; ++sw) {
-    for (int s2 = 0; s2 < nbk - 1; ++s2) {
-      hipLaunchKernelGGL(bj_solve_kernel, dim3(npair), dim3(256), 0, st, cin, n, nbk, nreal, s2, 12, w.U, w.D);
-      hipLaunchKernelGGL(bj_update_kernel, dim3(npair * npair + npair * nrb), dim3(256), upd_smem, st, cin, cout,
-                         w.V, n, nbk, nreal, s2, w.U, w.D);
-      std::swap(cin, cout);
-    }
-    XLS_LAUNCH_CHECK("block Jacobi");
-    ++sweeps;
-    hipLaunchKernelGGL(offnorm_kernel, dim3(1), dim3(256), 0, st, cin, n, w.scal);
-    XLS_HIP(hipMemcpyAsync(hs, w.scal, 16, hipMemcpyDeviceToHost, st));
-    XLS_HIP(hipStreamSynchronize(st));
-    if (!(hs[0] == hs[0]) || !(hs[1] == hs[1])) return XLS_ERR_EIG_NOCONV;
-    conv = hs[0] <= 1e-28 * hs[1];
-  }
-  if (!conv && n > 1) {
-    if (!(hs[0] <= 1e-20 * hs[1])) return XLS_ERR_EIG_NOCONV;
-  }
-  if (sweeps_out) *sweeps_out = sweeps;
-  // --- ascending order, Y = Rinv Z ---
-  hipLaunchKernelGGL(sort_diag_kernel, dim3(nblk(n, 256)), dim3(256), 0, st, cin, n, w.lam, w.perm);
-  hipLaunchKernelGGL(permute_cols_kernel, dim3(nblk(nn, 256)), dim3(256), 0, st, w.V, w.perm, n, w.T);
   gemm_nn<double>(XLS_PREC_FP64, w.Rinv, n, w.T, n, n, n, n, Y, n, nullptr, st);
   XLS_LAUNCH_CHECK("dense back-transform");
   return XLS_OK;

@@ -111,25 +111,29 @@ void gemm_nn(int prec, const TS* A, int64_t lda, const double* B, int64_t ldb, i
              TS* C, int64_t ldc, void* bwork, hipStream_t st);
 void split_bf16_device(const float* a, uint16_t* hi, uint16_t* lo, int64_t n, hipStream_t st);
 
-// Dense FP64 generalized eigensolver: Hs y = lambda M y (n x n).
+// Dense FP64 generalized eigensolver: Hs y = lambda M y (n x n, 1 <= n <= kDenseMaxN).
+constexpr int kDenseMaxN = 2800;  // bounded by the inverse-iteration LDS (7n doubles + n bytes)
 struct DenseWork {
+  static constexpr int kVecs = 11;   // lam, raw, d, e, ez, e2, tau, vbuf[2], pbuf[2]
+  static constexpr int kIvecs = 4;   // perm, block start, block end, cluster start
   int n = 0;
-  double *R = nullptr, *Rinv = nullptr, *C0 = nullptr, *C1 = nullptr, *V = nullptr, *T = nullptr;
-  double* lam = nullptr;       // [n]
-  double* U = nullptr;         // block-Jacobi pair rotations [npair][64*64]
-  double* D = nullptr;         // block-Jacobi pair eigenvalues [npair][64]
-  double* scal = nullptr;      // small scalars / partials
-  int32_t* flag = nullptr;     // device status flags
-  int32_t* perm = nullptr;     // [n]
+  double *R = nullptr, *Rinv = nullptr, *C0 = nullptr, *C1 = nullptr, *T = nullptr;
+  double* Vh = nullptr;        // Householder vectors, column k = v_k
+  double* Z = nullptr;         // eigenvectors of the tridiagonal matrix
+  double* vec = nullptr;       // kVecs * n doubles; the first n are the sorted eigenvalues
+  double* scal = nullptr;      // |T|_1, pivot floor, then diag(M) at offset 16
+  int32_t* flag = nullptr;     // device status flag (nonzero: M not positive definite)
+  int32_t* ivec = nullptr;     // kIvecs * n ints + cluster count
   double* gemm_work = nullptr;
   size_t gemm_work_elems = 0;
+  const double* lam() const { return vec; }
 };
 void dense_alloc(DenseWork& w, int n);
 void dense_free(DenseWork& w);
-// Solves in place: on return w.lam (device, ascending) and Y (device, n x n) hold the result.
-// Returns XLS_OK, XLS_ERR_NOT_SPD or XLS_ERR_EIG_NOCONV.  Synchronises st (convergence checks).
-int dense_geneig(DenseWork& w, const double* Hs, const double* M, double* Y, hipStream_t st,
-                 int* sweeps_out);
+// On XLS_OK, w.lam() (device, ascending) and Y (device, n x n, M-orthonormal
+// columns) hold the result; XLS_ERR_NOT_SPD when M is not positive definite.
+// Synchronises st once (after the Cholesky factorisation).
+int dense_geneig(DenseWork& w, const double* Hs, const double* M, double* Y, hipStream_t st);
 
 // vector helpers (vecops.hip)
 template <typename TS>

@@ -171,7 +171,9 @@ int xls_lanczos_bounds(xls_subdomain_t s, int32_t k, double* theta_min, double* 
 
 /* Dense generalized symmetric eigenproblem on the GPU (step (3); the
  * paper's DSYGVD stage, Sec. V-B.3), FP64: Hs y = lambda M y, n x n column-major
- * inputs; lam[n] ascending, Y[n*n] with Y^T M Y = I.  Errors: NOT_SPD, EIG_NOCONV. */
+ * inputs; lam[n] ascending, Y[n*n] with Y^T M Y = I.  Cholesky, Householder
+ * tridiagonalisation, bisection + inverse iteration, back-transformation;
+ * 1 <= n <= 2800.  Errors: INVALID_ARG, NOT_SPD. */
 int xls_dense_geneig(int32_t n, const double* Hs, const double* M, double* lam, double* Y);
 
 int xls_subdomain_get_block(xls_subdomain_t s, double* X);       /* [N_d*ns] */
@@ -206,6 +208,50 @@ int xls_subdomain_tune(xls_subdomain_t s, int32_t prec, int32_t block, int32_t t
  * counts[0] filter launches.  Returns the number of values written. */
 int xls_set_profiling(int32_t on);
 int xls_get_stage_times(xls_subdomain_t s, double* ms, int64_t* counts, int32_t cap);
+
+/* ---- Batch engine: many uneven subdomains on one GPU -----------------------
+ * The paper advances the subsystems assigned to a process independently
+ * (Sec. V-B); a batch holds n of them on one device and advances them
+ * together: every Chebyshev filter step of the whole batch is one persistent
+ * launch per tile shape (work items = subdomain x tile), the rest of each
+ * CheFSI iteration runs per subdomain on a small stream pool, and an
+ * iteration's launches are captured into a hipGraph and replayed while the
+ * set of unconverged subdomains is unchanged.  Results are bit-identical to
+ * running xls_chefsi_step on each subdomain alone with the same parameters.
+ *
+ * xls_batch_create: descs[n] as for xls_subdomain_create (all with the same
+ *   filter_prec; their stream fields are ignored).  Host arrays are copied.
+ * xls_batch_chefsi: per_sub[n] parameters (bounds_mode GIVEN or LANCZOS;
+ *   degree <= 256); runs each subdomain until its gated residual is <=
+ *   resid_tol, its max_iter is reached or its bounds degenerate.  Outputs are
+ *   concatenated in subdomain order: ritz_concat and resid_concat hold
+ *   sum(ns_i) values; iters[n] and status[n] may be NULL.  status[i] is
+ *   XLS_OK or XLS_ERR_NOT_SPD (that subdomain's block is then undefined); with
+ *   status NULL such a failure is returned as the call's status.  use_graph:
+ *   1 replays captured iterations, 0 launches eagerly (same results).
+ * xls_batch_density: xls_subdomain_density of every subdomain, rho and c
+ *   concatenated (sum N_d_i and sum ns_i values).
+ * xls_batch_subdomain: borrowed handle of subdomain i (for the per-handle
+ *   hooks); owned by the batch, never destroyed by the caller.
+ * xls_batch_tune: times the fused filter kernel of one subdomain per shape
+ *   class (grid, boundary, precision, atom count) over block {256, 512} x
+ *   rows-per-tile {auto, 1, 2, 4, 8, 16} and applies the fastest to the class.
+ *   cache_path (may be NULL): JSON object "shape key": [block, ty]; known keys
+ *   are taken from it without timing, new results are written back.
+ *   tuned (may be NULL) = classes timed; best_ms (may be NULL) = sum over timed
+ *   classes of the winning per-launch time.
+ * xls_batch_stats: out[0] iterations of the last xls_batch_chefsi, out[1]
+ *   graphs captured, out[2] graph replays, out[3] device time of those
+ *   iterations (ms, events on the batch stream), out[4] the last one's. */
+typedef struct xls_batch_s* xls_batch_t;
+int xls_batch_create(int32_t n, const xls_subdomain_desc_t* descs, xls_batch_t* out);
+int xls_batch_chefsi(xls_batch_t b, const xls_chefsi_params_t* per_sub, double* ritz_concat,
+                     double* resid_concat, int32_t* iters, int32_t* status, int32_t use_graph);
+int xls_batch_density(xls_batch_t b, double mu, double sigma, double* rho_concat, double* c_concat);
+int xls_batch_subdomain(xls_batch_t b, int32_t i, xls_subdomain_t* out);
+int xls_batch_tune(xls_batch_t b, const char* cache_path, int32_t* tuned, double* best_ms);
+int xls_batch_stats(xls_batch_t b, double* out, int32_t cap);
+void xls_batch_destroy(xls_batch_t b);
 
 #ifdef __cplusplus
 }

@@ -11,7 +11,7 @@
 #include <string>
 #include <vector>
 
-#include "xls_internal.h"
+#include "xls_handle.h"
 
 namespace xls {
 
@@ -31,33 +31,12 @@ void check_hip(hipError_t e, const char* what, const char* file, int line) {
 namespace {
 
 template <typename T>
-T* dalloc(size_t n) {
-  void* p = nullptr;
-  if (n == 0) n = 1;
-  const hipError_t e = hipMalloc(&p, n * sizeof(T));
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    fail(XLS_ERR_OUT_OF_MEMORY, "device allocation of " + std::to_string(n * sizeof(T)) + " bytes failed");
-  }
-  return static_cast<T*>(p);
-}
-
-void dfree(void* p) {
-  if (p) (void)hipFree(p);
-}
-
-template <typename T>
 T* dupload(const std::vector<T>& h, hipStream_t st) {
   T* d = dalloc<T>(h.size());
   if (!h.empty()) XLS_HIP(hipMemcpyAsync(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, st));
   return d;
 }
 
-bool finite_all(const double* p, int64_t n) {
-  for (int64_t i = 0; i < n; ++i)
-    if (!std::isfinite(p[i])) return false;
-  return true;
-}
 
 struct StageTimer {
   bool on;
@@ -85,135 +64,19 @@ struct StageTimer {
 }  // namespace
 }  // namespace xls
 
-using namespace xls;
+namespace xls {
 
-struct xls_subdomain_s {
-  int n[3] = {0, 0, 0};
-  double h = 0;
-  int bc = 0;
-  int prec = XLS_PREC_FP64;
-  int ns = 0;
-  int64_t nd = 0, ld = 0;
-  hipStream_t st = nullptr;
-  bool own_stream = false;
-  SetupTables tab;
-  int n_atoms = 0;
-  // device: operator tables in both precisions
-  double* v64 = nullptr;
-  float* v32 = nullptr;
-  double* val64 = nullptr;
-  float* val32 = nullptr;
-  int32_t *rev_pk = nullptr, *rev_aoff = nullptr, *sup_off = nullptr, *sup_idx = nullptr;
-  double* rev_val64 = nullptr;
-  float* rev_val32 = nullptr;
-  double* gamma = nullptr;
-  uint8_t* mask = nullptr;
-  OpTables<double> op64;
-  OpTables<float> op32;
-  StencilLaunch cfg64, cfg32;
-  // blocks
-  void* blk[2] = {nullptr, nullptr};
-  int cur = 0;
-  void* alpha = nullptr;      // [ns][nproj] in storage type
-  double* alpha64 = nullptr;  // [ns][nproj] FP64 (residuals of FP32 blocks)
-  double* partial = nullptr;
-  size_t partial_elems = 0;
-  double* lam_dev = nullptr;
-  double* resid_dev = nullptr;
-  double* Mdev = nullptr;
-  double* Hsdev = nullptr;
-  double* Ydev = nullptr;
-  float* bwork = nullptr;
-  double* gwork = nullptr;
-  size_t gwork_elems = 0;
-  DenseWork dw;
-  double* vsmall = nullptr;  // density / Lanczos scalars
-  double* rho_dev = nullptr;
-  double* cpart = nullptr;
-  double* gocc = nullptr;
-  // Lanczos
-  std::vector<double> lanczos_v0;
-  void* lz = nullptr;  // [nd * (kmax + 2)]
-  int lz_cols = 0;
-  bool have_lanczos = false;
-  double lz_lo = 0, lz_up = 0;
-  int lz_k = 0;
-  // state
-  std::vector<double> ritz;
-  bool have_ritz = false;
-  std::vector<double> stage_ms;
-  int64_t filter_launches = 0;
-  double filter_kernel_ms = 0.0;  // sum over fused-filter stencil launches (profiling on)
-  std::vector<hipEvent_t> fev;
+void set_last_error(const std::string& m) { g_last_error = m; }
+bool profiling_on() { return g_profiling; }
 
-  ~xls_subdomain_s() {
-    void* ps[] = {v64, v32, val64, val32, rev_pk, rev_aoff, rev_val64, rev_val32, sup_off, sup_idx, gamma, mask,
-                  blk[0], blk[1], alpha, alpha64, partial, lam_dev, resid_dev, Mdev, Hsdev, Ydev, bwork,
-                  gwork, vsmall, rho_dev, cpart, gocc, lz};
-    for (void* p : ps) dfree(p);
-    for (auto e : fev) (void)hipEventDestroy(e);
-    dense_free(dw);
-    if (own_stream && st) (void)hipStreamDestroy(st);
-  }
-  size_t esize() const { return prec == XLS_PREC_FP32 ? 4 : 8; }
-  int nproj() const { return 4 * n_atoms; }
-};
-
-namespace {
-
-void validate_desc(const xls_subdomain_desc_t* d) {
-  if (!d) fail(XLS_ERR_INVALID_ARG, "desc is NULL");
-  for (int a = 0; a < 3; ++a)
-    if (d->n[a] < 1) fail(XLS_ERR_INVALID_ARG, "grid size must be >= 1");
-  const int64_t nd = static_cast<int64_t>(d->n[0]) * d->n[1] * d->n[2];
-  if (nd >= (int64_t(1) << 31)) fail(XLS_ERR_INVALID_ARG, "N_d must be < 2^31");
-  if (!(d->h > 0) || !std::isfinite(d->h)) fail(XLS_ERR_INVALID_ARG, "h must be finite and > 0");
-  if (d->bc != XLS_BC_PERIODIC && d->bc != XLS_BC_DIRICHLET0) fail(XLS_ERR_INVALID_ARG, "unknown bc");
-  if (d->fd_n0 != kRadius) fail(XLS_ERR_INVALID_ARG, "fd_n0 must be 6");
-  if (d->n[0] > 1024) fail(XLS_ERR_INVALID_ARG, "n[0] must be <= 1024");
-  if (!d->v_eff || !finite_all(d->v_eff, nd)) fail(XLS_ERR_INVALID_ARG, "v_eff NULL or not finite");
-  if (!finite_all(d->origin, 3)) fail(XLS_ERR_INVALID_ARG, "origin not finite");
-  if (d->n_atoms < 0) fail(XLS_ERR_INVALID_ARG, "n_atoms < 0");
-  if (d->n_atoms > 0 && (!d->atom_xyz || !d->proj)) fail(XLS_ERR_INVALID_ARG, "atoms NULL");
-  if (d->n_atoms > 0 && !finite_all(d->atom_xyz, 3 * static_cast<int64_t>(d->n_atoms)))
-    fail(XLS_ERR_INVALID_ARG, "atom positions not finite");
-  for (int a = 0; a < d->n_atoms; ++a) {
-    const xls_projset_t& p = d->proj[a];
-    if (!(p.rc > 0) || !(p.gauss_width > 0) || !std::isfinite(p.rc) || !std::isfinite(p.gauss_width) ||
-        !finite_all(p.gamma, 4))
-      fail(XLS_ERR_INVALID_ARG, "bad projector set");
-  }
-  for (int a = 0; a < 3; ++a) {
-    if (d->core_lo[a] < 0 || d->core_hi[a] > d->n[a] || d->core_lo[a] > d->core_hi[a])
-      fail(XLS_ERR_INVALID_ARG, "core box outside the grid");
-    if (d->global_n[a] < 1) fail(XLS_ERR_INVALID_ARG, "global_n must be >= 1");
-  }
-  if (d->ns < 1 || d->ns > nd) fail(XLS_ERR_INVALID_ARG, "ns must be in [1, N_d]");
-  if (!d->x0 || !finite_all(d->x0, nd * d->ns)) fail(XLS_ERR_INVALID_ARG, "x0 NULL or not finite");
-  if (d->lanczos_v0 && !finite_all(d->lanczos_v0, nd)) fail(XLS_ERR_INVALID_ARG, "lanczos_v0 not finite");
-  if (d->filter_prec != XLS_PREC_FP64 && d->filter_prec != XLS_PREC_FP32)
-    fail(XLS_ERR_INVALID_ARG, "filter_prec must be FP64 or FP32");
+void dfree(void* p) {
+  if (p) (void)hipFree(p);
 }
 
-template <typename TS>
-TS* B(xls_subdomain_s* s, int i) {
-  return static_cast<TS*>(s->blk[i]);
-}
-
-template <typename TS>
-const OpTables<typename std::conditional<std::is_same<TS, float>::value, float, double>::type>& op_of(
-    xls_subdomain_s* s);
-template <>
-const OpTables<double>& op_of<double>(xls_subdomain_s* s) {
-  return s->op64;
-}
-template <>
-const OpTables<float>& op_of<float>(xls_subdomain_s* s) {
-  return s->op32;
-}
-template <typename TS>
-const StencilLaunch& cfg_of(xls_subdomain_s* s) {
-  return std::is_same<TS, float>::value ? s->cfg32 : s->cfg64;
+bool finite_all(const double* p, int64_t n) {
+  for (int64_t i = 0; i < n; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
 }
 
 // out = H y in the storage precision.
@@ -237,7 +100,7 @@ void filter_block(xls_subdomain_s* s, int m, double a0, double lc, double lmax) 
   const auto& op = op_of<TS>(s);
   const auto& cfg = cfg_of<TS>(s);
   TS* alpha = static_cast<TS*>(s->alpha);
-  const bool prof = g_profiling;
+  const bool prof = profiling_on();
   if (prof && static_cast<int>(s->fev.size()) < 2 * m) {
     for (auto ev : s->fev) (void)hipEventDestroy(ev);
     s->fev.assign(2 * m, nullptr);
@@ -367,6 +230,56 @@ void lanczos_run(xls_subdomain_s* s, int k) {
   s->have_lanczos = true;
 }
 
+
+#define XLS_INST_STAGES(TS)                                                          \
+  template void apply_H<TS>(xls_subdomain_s*, const TS*, TS*, int, TS*);             \
+  template void rotate_block<TS>(xls_subdomain_s*, int, const double*);              \
+  template void residual_block<TS>(xls_subdomain_s*, const double*, double*);        \
+  template void lanczos_run<TS>(xls_subdomain_s*, int);                              \
+  template void filter_block<TS>(xls_subdomain_s*, int, double, double, double);
+XLS_INST_STAGES(float)
+XLS_INST_STAGES(double)
+
+}  // namespace xls
+
+using namespace xls;
+
+namespace {
+
+void validate_desc(const xls_subdomain_desc_t* d) {
+  if (!d) fail(XLS_ERR_INVALID_ARG, "desc is NULL");
+  for (int a = 0; a < 3; ++a)
+    if (d->n[a] < 1) fail(XLS_ERR_INVALID_ARG, "grid size must be >= 1");
+  const int64_t nd = static_cast<int64_t>(d->n[0]) * d->n[1] * d->n[2];
+  if (nd >= (int64_t(1) << 31)) fail(XLS_ERR_INVALID_ARG, "N_d must be < 2^31");
+  if (!(d->h > 0) || !std::isfinite(d->h)) fail(XLS_ERR_INVALID_ARG, "h must be finite and > 0");
+  if (d->bc != XLS_BC_PERIODIC && d->bc != XLS_BC_DIRICHLET0) fail(XLS_ERR_INVALID_ARG, "unknown bc");
+  if (d->fd_n0 != kRadius) fail(XLS_ERR_INVALID_ARG, "fd_n0 must be 6");
+  if (d->n[0] > 1024) fail(XLS_ERR_INVALID_ARG, "n[0] must be <= 1024");
+  if (!d->v_eff || !finite_all(d->v_eff, nd)) fail(XLS_ERR_INVALID_ARG, "v_eff NULL or not finite");
+  if (!finite_all(d->origin, 3)) fail(XLS_ERR_INVALID_ARG, "origin not finite");
+  if (d->n_atoms < 0) fail(XLS_ERR_INVALID_ARG, "n_atoms < 0");
+  if (d->n_atoms > 0 && (!d->atom_xyz || !d->proj)) fail(XLS_ERR_INVALID_ARG, "atoms NULL");
+  if (d->n_atoms > 0 && !finite_all(d->atom_xyz, 3 * static_cast<int64_t>(d->n_atoms)))
+    fail(XLS_ERR_INVALID_ARG, "atom positions not finite");
+  for (int a = 0; a < d->n_atoms; ++a) {
+    const xls_projset_t& p = d->proj[a];
+    if (!(p.rc > 0) || !(p.gauss_width > 0) || !std::isfinite(p.rc) || !std::isfinite(p.gauss_width) ||
+        !finite_all(p.gamma, 4))
+      fail(XLS_ERR_INVALID_ARG, "bad projector set");
+  }
+  for (int a = 0; a < 3; ++a) {
+    if (d->core_lo[a] < 0 || d->core_hi[a] > d->n[a] || d->core_lo[a] > d->core_hi[a])
+      fail(XLS_ERR_INVALID_ARG, "core box outside the grid");
+    if (d->global_n[a] < 1) fail(XLS_ERR_INVALID_ARG, "global_n must be >= 1");
+  }
+  if (d->ns < 1 || d->ns > nd) fail(XLS_ERR_INVALID_ARG, "ns must be in [1, N_d]");
+  if (!d->x0 || !finite_all(d->x0, nd * d->ns)) fail(XLS_ERR_INVALID_ARG, "x0 NULL or not finite");
+  if (d->lanczos_v0 && !finite_all(d->lanczos_v0, nd)) fail(XLS_ERR_INVALID_ARG, "lanczos_v0 not finite");
+  if (d->filter_prec != XLS_PREC_FP64 && d->filter_prec != XLS_PREC_FP32)
+    fail(XLS_ERR_INVALID_ARG, "filter_prec must be FP64 or FP32");
+}
+
 template <typename TS>
 int chefsi_impl(xls_subdomain_s* s, const xls_chefsi_params_t* p, double* ritz, double* resid,
                 int32_t* iters_done) {
@@ -453,22 +366,6 @@ int chefsi_impl(xls_subdomain_s* s, const xls_chefsi_params_t* p, double* ritz, 
   std::memcpy(resid, hr.data(), ns * 8);
   if (iters_done) *iters_done = it;
   return XLS_OK;
-}
-
-template <typename F>
-int guarded(F&& f) {
-  try {
-    return f();
-  } catch (const Error& e) {
-    g_last_error = e.msg;
-    return e.code;
-  } catch (const std::bad_alloc&) {
-    g_last_error = "host allocation failed";
-    return XLS_ERR_OUT_OF_MEMORY;
-  } catch (...) {
-    g_last_error = "unexpected internal error";
-    return XLS_ERR_DEVICE;
-  }
 }
 
 // Host column-major N_d x ncols (FP64) <-> device block with leading dimension ld.

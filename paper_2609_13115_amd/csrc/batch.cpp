@@ -1,0 +1,576 @@
+// Batch engine: many uneven subdomains advanced together (the paper runs the
+// subsystems of a process one after another with threads inside each,
+// Sec. V-B; here one GPU holds them all).
+//
+// One batch iteration =
+//   m_max grouped filter steps on the batch stream: every step is one
+//   persistent forward-projection launch and one persistent stencil launch
+//   per tile shape, covering all subdomains whose degree exceeds the step;
+//   then, per subdomain on a pool of streams: H Psi_f, the two projection
+//   GEMMs, the dense FP64 eigensolve (no host synchronisation), the
+//   rotation, the FP64 residual and the next filter coefficients (computed on
+//   the device from the new Ritz values).
+// The iteration's launches are captured into a hipGraph per (active set,
+// buffer parity, degrees) and replayed; only the convergence test reads
+// results back to the host between iterations.  The autotuner times the fused filter
+// kernel's tile shapes per subdomain shape and keeps the winners in a small
+// JSON cache.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "xls_handle.h"
+
+using namespace xls;
+
+namespace {
+
+constexpr int kMaxDegree = 256;
+constexpr int kPoolStreams = 4;
+constexpr int kGraphCache = 8;
+
+struct GroupHolder {
+  FilterGroup<float>* g32 = nullptr;
+  FilterGroup<double>* g64 = nullptr;
+  ~GroupHolder() {
+    if (g32) filter_group_free(g32);
+    if (g64) filter_group_free(g64);
+  }
+};
+
+struct GraphEntry {
+  std::string key;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  GroupHolder* group = nullptr;
+  int seen = 0;
+  void release() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    delete group;
+    exec = nullptr;
+    graph = nullptr;
+    group = nullptr;
+  }
+};
+
+struct SubState {
+  double lmax = 0.0;
+  int degree = 0, max_iter = 0, gate = 0, gprec = XLS_PREC_FP64;
+  double resid_tol = 0.0;
+  int iters = 0;
+  int status = XLS_OK;
+  bool active = false;
+};
+
+}  // namespace
+
+struct xls_batch_s {
+  int n = 0;
+  int prec = XLS_PREC_FP64;
+  std::vector<xls_subdomain_s*> subs;
+  hipStream_t main = nullptr;
+  std::vector<hipStream_t> pool;
+  hipEvent_t ev_fork = nullptr;
+  std::vector<hipEvent_t> ev_join;
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  std::vector<double*> coef;
+  int32_t* flags = nullptr;  // [n] bad-bounds flags from the coefficient kernel
+  std::vector<GraphEntry> graphs;
+  std::vector<SubState> st;
+  // statistics
+  int64_t iterations = 0, captures = 0, replays = 0;
+  double iter_ms = 0.0, last_iter_ms = 0.0;
+
+  ~xls_batch_s() {
+    if (main) (void)hipStreamSynchronize(main);
+    for (auto* s : subs)
+      if (s) xls_subdomain_destroy(s);
+    for (auto& g : graphs) g.release();
+    for (auto* c : coef) dfree(c);
+    dfree(flags);
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    for (auto e : ev_join) (void)hipEventDestroy(e);
+    if (t0) (void)hipEventDestroy(t0);
+    if (t1) (void)hipEventDestroy(t1);
+    for (auto p : pool) (void)hipStreamDestroy(p);
+    if (main) (void)hipStreamDestroy(main);
+  }
+};
+
+namespace {
+
+// Rotation and FP64 residual with explicit buffers (the handle's parity is
+// advanced by the caller once per iteration, outside any capture).
+template <typename TS>
+void tail_stages(xls_subdomain_s* s, const SubState& ss, int cur_f, double* coef, int32_t* bad) {
+  const int ns = s->ns;
+  TS* Bc = B<TS>(s, cur_f);
+  TS* W = B<TS>(s, 1 - cur_f);
+  apply_H<TS>(s, Bc, W, ns, static_cast<TS*>(s->alpha));
+  gemm_tn<TS>(ss.gprec, Bc, s->ld, Bc, s->ld, ns, ns, s->nd, s->Mdev, ns, 1, 0, s->gwork, s->gwork_elems, s->st);
+  gemm_tn<TS>(ss.gprec, Bc, s->ld, W, s->ld, ns, ns, s->nd, s->Hsdev, ns, 0, 1, s->gwork, s->gwork_elems, s->st);
+  (void)dense_geneig(s->dw, s->Hsdev, s->Mdev, s->Ydev, s->st, /*check_spd=*/false);
+  XLS_HIP(hipMemcpyAsync(s->lam_dev, s->dw.lam(), ns * 8, hipMemcpyDeviceToDevice, s->st));
+  // Psi <- Psi_f Y into the other buffer
+  gemm_nn<TS>(ss.gprec, Bc, s->ld, s->Ydev, ns, static_cast<int>(s->nd), ns, ns, W, s->ld, s->bwork, s->st);
+  launch_proj_forward<TS, double>(s->op64, W, s->ld, ns, s->alpha64, s->st);
+  launch_stencil<TS, double>(kResid, s->op64, W, s->ld, ns, s->alpha64, nullptr, nullptr, 1.0, 0.0, 0.0,
+                             s->lam_dev, s->partial, s->resid_dev, s->st, s->cfg64);
+  launch_filter_coef(s->lam_dev, ns, 0.0, 0.0, ss.lmax, ss.degree, coef, bad, s->st);
+}
+
+template <typename TS>
+FilterGroup<TS>* build_group(xls_batch_s* b, const std::vector<int>& act) {
+  std::vector<FilterGroupOp<TS>> ops;
+  for (int i : act) {
+    xls_subdomain_s* s = b->subs[i];
+    FilterGroupOp<TS> o{};
+    o.op = &op_of<TS>(s);
+    o.buf[0] = B<TS>(s, 0);
+    o.buf[1] = B<TS>(s, 1);
+    o.cur0 = s->cur;
+    o.ld = s->ld;
+    o.ncols = s->ns;
+    o.alpha = static_cast<TS*>(s->alpha);
+    o.coef = b->coef[i];
+    o.degree = b->st[i].degree;
+    o.cfg = cfg_of<TS>(s);
+    ops.push_back(o);
+  }
+  return filter_group_build<TS>(ops);
+}
+
+// Records one batch iteration over the active subdomains (eager, or inside a
+// stream capture of b->main).
+template <typename TS>
+void record_iteration(xls_batch_s* b, FilterGroup<TS>* g, const std::vector<int>& act) {
+  // the filter runs on main, after the previous iteration's tails (joined
+  // into main at the end of every iteration)
+  for (int k = 0; k < filter_group_steps(g); ++k) filter_group_step<TS>(g, k, b->main);
+  XLS_HIP(hipEventRecord(b->ev_fork, b->main));
+  for (auto p : b->pool) XLS_HIP(hipStreamWaitEvent(p, b->ev_fork, 0));
+  for (int i : act) {
+    xls_subdomain_s* s = b->subs[i];
+    const int cur_f = (s->cur + b->st[i].degree) & 1;
+    tail_stages<TS>(s, b->st[i], cur_f, b->coef[i], b->flags + i);
+  }
+  for (size_t p = 0; p < b->pool.size(); ++p) {
+    XLS_HIP(hipEventRecord(b->ev_join[p], b->pool[p]));
+    XLS_HIP(hipStreamWaitEvent(b->main, b->ev_join[p], 0));
+  }
+}
+
+// Everything a captured iteration bakes in: the active set, each block's
+// parity, degree, GEMM precision and lam_max (a kernel argument of the
+// coefficient update).
+std::string graph_key(xls_batch_s* b, const std::vector<int>& act) {
+  std::ostringstream k;
+  k << std::hexfloat;
+  for (int i : act)
+    k << i << (b->subs[i]->cur ? 'b' : 'a') << b->st[i].degree << 'p' << b->st[i].gprec << 'l' << b->st[i].lmax
+      << ',';
+  return k.str();
+}
+
+// The first time an (active set, parity, degrees) key is seen the iteration
+// runs eagerly, so that every one-time kernel configuration happens outside a
+// capture; from the second time on it is captured once and replayed.
+template <typename TS>
+void run_iteration(xls_batch_s* b, const std::vector<int>& act, bool use_graph) {
+  const std::string key = graph_key(b, act);
+  GraphEntry* ge = nullptr;
+  for (auto& g : b->graphs)
+    if (g.key == key) ge = &g;
+  if (!ge) {
+    if (static_cast<int>(b->graphs.size()) >= kGraphCache) {
+      XLS_HIP(hipStreamSynchronize(b->main));
+      b->graphs.front().release();
+      b->graphs.erase(b->graphs.begin());
+    }
+    b->graphs.push_back(GraphEntry{});
+    ge = &b->graphs.back();
+    ge->key = key;
+    ge->group = new GroupHolder();
+    FilterGroup<TS>* g = build_group<TS>(b, act);
+    if (std::is_same<TS, float>::value)
+      ge->group->g32 = reinterpret_cast<FilterGroup<float>*>(g);
+    else
+      ge->group->g64 = reinterpret_cast<FilterGroup<double>*>(g);
+  }
+  FilterGroup<TS>* g = std::is_same<TS, float>::value ? reinterpret_cast<FilterGroup<TS>*>(ge->group->g32)
+                                                      : reinterpret_cast<FilterGroup<TS>*>(ge->group->g64);
+  if (use_graph && !ge->exec && ge->seen > 0) {
+    XLS_HIP(hipStreamBeginCapture(b->main, hipStreamCaptureModeThreadLocal));
+    try {
+      record_iteration<TS>(b, g, act);
+    } catch (...) {
+      hipGraph_t dead = nullptr;
+      (void)hipStreamEndCapture(b->main, &dead);
+      if (dead) (void)hipGraphDestroy(dead);
+      throw;
+    }
+    XLS_HIP(hipStreamEndCapture(b->main, &ge->graph));
+    XLS_HIP(hipGraphInstantiate(&ge->exec, ge->graph, nullptr, nullptr, 0));
+    ++b->captures;
+  }
+  ++ge->seen;
+  XLS_HIP(hipEventRecord(b->t0, b->main));
+  if (use_graph && ge->exec) {
+    XLS_HIP(hipGraphLaunch(ge->exec, b->main));
+    ++b->replays;
+  } else {
+    record_iteration<TS>(b, g, act);
+  }
+  XLS_HIP(hipEventRecord(b->t1, b->main));
+}
+
+template <typename TS>
+void batch_chefsi(xls_batch_s* b, const xls_chefsi_params_t* P, int use_graph) {
+  const int n = b->n;
+  for (int i = 0; i < n; ++i) {
+    const xls_chefsi_params_t& p = P[i];
+    xls_subdomain_s* s = b->subs[i];
+    SubState& ss = b->st[i];
+    if (p.degree < 1 || p.degree > kMaxDegree || p.max_iter < 1)
+      fail(XLS_ERR_INVALID_ARG, "degree must be in [1, 256] and max_iter >= 1");
+    if (p.gemm_prec < XLS_PREC_FP64 || p.gemm_prec > XLS_PREC_BF16X3) fail(XLS_ERR_INVALID_ARG, "bad gemm_prec");
+    if (std::is_same<TS, double>::value && p.gemm_prec != XLS_PREC_FP64)
+      fail(XLS_ERR_INVALID_ARG, "FP64 batches run FP64 GEMMs");
+    double a0, lc, lmax;
+    if (p.bounds_mode == XLS_BOUNDS_GIVEN) {
+      a0 = p.lam_lo;
+      lc = p.lam_cut;
+      lmax = p.lam_max;
+    } else if (p.bounds_mode == XLS_BOUNDS_LANCZOS) {
+      const int k = p.lanczos_k > 0 ? p.lanczos_k : 20;
+      if (!s->have_lanczos || s->lz_k != k) lanczos_run<TS>(s, std::min(k, 60));
+      a0 = s->lz_lo;
+      lmax = s->lz_up;
+      lc = a0 + 0.1 * (lmax - a0);
+    } else {
+      fail(XLS_ERR_INVALID_ARG, "batch bounds_mode must be GIVEN or LANCZOS");
+    }
+    if (!(a0 < lc && lc < lmax) || !std::isfinite(a0) || !std::isfinite(lmax))
+      fail(XLS_ERR_INVALID_ARG, "bounds must satisfy a0 < lam_cut < lam_max");
+    ss.lmax = lmax;
+    ss.degree = p.degree;
+    ss.max_iter = p.max_iter;
+    ss.gprec = p.gemm_prec;
+    ss.resid_tol = p.resid_tol;
+    ss.gate = p.n_gate > 0 ? std::min(p.n_gate, s->ns)
+                           : std::max(1, static_cast<int>(std::floor(s->ns / 1.1 + 1e-9)));
+    ss.iters = 0;
+    ss.status = XLS_OK;
+    ss.active = true;
+    launch_filter_coef(nullptr, s->ns, a0, lc, lmax, p.degree, b->coef[i], b->flags + i, s->st);
+  }
+  for (auto* s : b->subs) XLS_HIP(hipStreamSynchronize(s->st));
+  std::vector<std::vector<double>> hl(n), hr(n);
+  for (int i = 0; i < n; ++i) {
+    hl[i].assign(b->subs[i]->ns, 0.0);
+    hr[i].assign(b->subs[i]->ns, 0.0);
+  }
+  std::vector<int32_t> hflag(n), hspd(n);
+  b->iterations = 0;
+  b->iter_ms = 0.0;
+  for (;;) {
+    std::vector<int> act;
+    for (int i = 0; i < n; ++i)
+      if (b->st[i].active) act.push_back(i);
+    if (act.empty()) break;
+    run_iteration<TS>(b, act, use_graph != 0);
+    for (int i : act) {
+      xls_subdomain_s* s = b->subs[i];
+      XLS_HIP(hipMemcpyAsync(hl[i].data(), s->lam_dev, s->ns * 8, hipMemcpyDeviceToHost, b->main));
+      XLS_HIP(hipMemcpyAsync(hr[i].data(), s->resid_dev, s->ns * 8, hipMemcpyDeviceToHost, b->main));
+      XLS_HIP(hipMemcpyAsync(&hspd[i], s->dw.flag, 4, hipMemcpyDeviceToHost, b->main));
+      XLS_HIP(hipMemcpyAsync(&hflag[i], b->flags + i, 4, hipMemcpyDeviceToHost, b->main));
+    }
+    XLS_HIP(hipStreamSynchronize(b->main));
+    float ms = 0.0f;
+    XLS_HIP(hipEventElapsedTime(&ms, b->t0, b->t1));
+    b->last_iter_ms = ms;
+    b->iter_ms += ms;
+    ++b->iterations;
+    for (int i : act) {
+      xls_subdomain_s* s = b->subs[i];
+      SubState& ss = b->st[i];
+      s->cur = (s->cur + ss.degree + 1) & 1;
+      ++ss.iters;
+      s->ritz = hl[i];
+      s->have_ritz = true;
+      if (hspd[i]) {
+        ss.status = XLS_ERR_NOT_SPD;
+        ss.active = false;
+        continue;
+      }
+      if (hflag[i]) {  // degenerate bounds for the next filter: stop with what we have
+        ss.active = false;
+        continue;
+      }
+      if (ss.resid_tol > 0) {
+        double mx = 0;
+        for (int k = 0; k < ss.gate; ++k) mx = std::max(mx, hr[i][k]);
+        if (mx <= ss.resid_tol) ss.active = false;
+      }
+      if (ss.iters >= ss.max_iter) ss.active = false;
+    }
+  }
+}
+
+// --- autotuner -------------------------------------------------------------
+
+std::string shape_key(xls_subdomain_s* s) {
+  std::ostringstream o;
+  o << (s->prec == XLS_PREC_FP32 ? "f32" : "f64") << "_" << s->n[0] << "x" << s->n[1] << "x" << s->n[2]
+    << (s->bc == XLS_BC_PERIODIC ? "_p" : "_d") << "_na" << s->n_atoms;
+  return o.str();
+}
+
+std::map<std::string, std::pair<int, int>> read_cache(const char* path) {
+  std::map<std::string, std::pair<int, int>> m;
+  if (!path) return m;
+  std::ifstream f(path);
+  std::string line;
+  while (std::getline(f, line)) {
+    // lines of the form  "key": [block, ty],
+    const size_t q0 = line.find('"'), q1 = line.find('"', q0 + 1), lb = line.find('['), cm = line.find(',', lb),
+                 rb = line.find(']', lb);
+    if (q0 == std::string::npos || q1 == std::string::npos || lb == std::string::npos ||
+        cm == std::string::npos || rb == std::string::npos)
+      continue;
+    try {
+      m[line.substr(q0 + 1, q1 - q0 - 1)] = {std::stoi(line.substr(lb + 1, cm - lb - 1)),
+                                            std::stoi(line.substr(cm + 1, rb - cm - 1))};
+    } catch (...) {
+    }
+  }
+  return m;
+}
+
+void write_cache(const char* path, const std::map<std::string, std::pair<int, int>>& m) {
+  if (!path) return;
+  std::ofstream f(path);
+  if (!f) fail(XLS_ERR_INVALID_ARG, std::string("cannot write tuning cache ") + path);
+  f << "{\n";
+  size_t k = 0;
+  for (const auto& e : m)
+    f << "  \"" << e.first << "\": [" << e.second.first << ", " << e.second.second << "]"
+      << (++k < m.size() ? ",\n" : "\n");
+  f << "}\n";
+}
+
+// Average fused-filter kernel time (ms) of subdomain s under launch shape cfg;
+// reads the current block and overwrites the spare one.
+template <typename TS>
+double time_filter(xls_subdomain_s* s, const StencilLaunch& cfg, hipEvent_t e0, hipEvent_t e1) {
+  const auto& op = op_of<TS>(s);
+  TS* y = B<TS>(s, s->cur);
+  TS* o = B<TS>(s, 1 - s->cur);
+  TS* al = static_cast<TS*>(s->alpha);
+  auto once = [&]() {
+    launch_stencil<TS, TS>(kFilter, op, y, s->ld, s->ns, al, o, o, 0.1, 0.0, 0.01, nullptr, nullptr, nullptr,
+                           s->st, cfg);
+  };
+  once();
+  XLS_HIP(hipEventRecord(e0, s->st));
+  constexpr int reps = 3;
+  for (int r = 0; r < reps; ++r) once();
+  XLS_HIP(hipEventRecord(e1, s->st));
+  XLS_HIP(hipEventSynchronize(e1));
+  float ms = 0.0f;
+  XLS_HIP(hipEventElapsedTime(&ms, e0, e1));
+  return ms / reps;
+}
+
+template <typename TS>
+int tune_batch(xls_batch_s* b, const char* cache_path, double* best_ms_out) {
+  auto cache = read_cache(cache_path);
+  std::map<std::string, std::pair<int, int>> chosen;
+  std::map<std::string, double> best_ms;
+  hipEvent_t e0, e1;
+  XLS_HIP(hipEventCreate(&e0));
+  XLS_HIP(hipEventCreate(&e1));
+  int tuned = 0;
+  try {
+    for (auto* s : b->subs) {
+      const std::string key = shape_key(s);
+      if (chosen.count(key)) continue;
+      auto hit = cache.find(key);
+      if (hit != cache.end()) {
+        chosen[key] = hit->second;
+        continue;
+      }
+      // zero the spare block's Y_{k-1} role: time on the real block's data
+      double best = 1e30;
+      std::pair<int, int> arg{256, 0};
+      for (int block : {256, 512})
+        for (int ty : {0, 1, 2, 4, 8, 16}) {
+          StencilLaunch cfg = cfg_of<TS>(s);
+          cfg.block = block;
+          cfg.ty = ty;
+          try {
+            stencil_validate(s->n[0], s->n[1], s->n[2], s->bc == XLS_BC_PERIODIC, sizeof(TS), s->nproj(), cfg);
+          } catch (const Error&) {
+            continue;
+          }
+          const double ms = time_filter<TS>(s, cfg, e0, e1);
+          if (ms < best) {
+            best = ms;
+            arg = {block, ty};
+          }
+        }
+      chosen[key] = arg;
+      best_ms[key] = best;
+      ++tuned;
+    }
+  } catch (...) {
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    throw;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  for (auto* s : b->subs) {
+    const auto& c = chosen[shape_key(s)];
+    const int rc = xls_subdomain_tune(s, s->prec, c.first, c.second, 0);
+    if (rc != XLS_OK) fail(rc, std::string("applying tuned tile shape: ") + xls_last_error());
+  }
+  for (auto& e : chosen) cache[e.first] = e.second;
+  if (tuned > 0) write_cache(cache_path, cache);
+  if (best_ms_out) {
+    double t = 0;
+    for (auto& e : best_ms) t += e.second;
+    *best_ms_out = t;
+  }
+  for (auto& g : b->graphs) g.release();  // tile shapes changed: recapture
+  b->graphs.clear();
+  return tuned;
+}
+
+}  // namespace
+
+extern "C" {
+
+int xls_batch_create(int32_t n, const xls_subdomain_desc_t* descs, xls_batch_t* out) {
+  return guarded([&]() -> int {
+    if (!out || !descs || n < 1) fail(XLS_ERR_INVALID_ARG, "bad argument");
+    for (int i = 1; i < n; ++i)
+      if (descs[i].filter_prec != descs[0].filter_prec)
+        fail(XLS_ERR_INVALID_ARG, "all subdomains of a batch share one filter precision");
+    auto* b = new xls_batch_s();
+    try {
+      b->n = n;
+      b->prec = descs[0].filter_prec;
+      XLS_HIP(hipStreamCreateWithFlags(&b->main, hipStreamNonBlocking));
+      const int np = std::min(n, kPoolStreams);
+      for (int p = 0; p < np; ++p) {
+        hipStream_t s;
+        XLS_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+        b->pool.push_back(s);
+        hipEvent_t e;
+        XLS_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        b->ev_join.push_back(e);
+      }
+      XLS_HIP(hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming));
+      XLS_HIP(hipEventCreate(&b->t0));
+      XLS_HIP(hipEventCreate(&b->t1));
+      b->flags = dalloc<int32_t>(n);
+      b->subs.assign(n, nullptr);
+      b->st.assign(n, SubState{});
+      for (int i = 0; i < n; ++i) {
+        xls_subdomain_desc_t d = descs[i];
+        d.stream = b->pool[i % np];
+        const int rc = xls_subdomain_create(&d, &b->subs[i]);
+        if (rc != XLS_OK) fail(rc, "subdomain " + std::to_string(i) + ": " + xls_last_error());
+        b->coef.push_back(dalloc<double>(3 * kMaxDegree));
+      }
+    } catch (...) {
+      delete b;
+      throw;
+    }
+    *out = b;
+    return XLS_OK;
+  });
+}
+
+void xls_batch_destroy(xls_batch_t b) { delete b; }
+
+int xls_batch_chefsi(xls_batch_t b, const xls_chefsi_params_t* per_sub, double* ritz_concat,
+                     double* resid_concat, int32_t* iters, int32_t* status, int32_t use_graph) {
+  return guarded([&]() -> int {
+    if (!b || !per_sub || !ritz_concat || !resid_concat) fail(XLS_ERR_INVALID_ARG, "bad argument");
+    if (b->prec == XLS_PREC_FP32)
+      batch_chefsi<float>(b, per_sub, use_graph);
+    else
+      batch_chefsi<double>(b, per_sub, use_graph);
+    int64_t off = 0;
+    int worst = XLS_OK;
+    for (int i = 0; i < b->n; ++i) {
+      xls_subdomain_s* s = b->subs[i];
+      std::memcpy(ritz_concat + off, s->ritz.data(), s->ns * 8);
+      XLS_HIP(hipMemcpy(resid_concat + off, s->resid_dev, s->ns * 8, hipMemcpyDeviceToHost));
+      off += s->ns;
+      if (iters) iters[i] = b->st[i].iters;
+      if (status) status[i] = b->st[i].status;
+      if (b->st[i].status != XLS_OK) worst = b->st[i].status;
+    }
+    if (worst != XLS_OK && !status) fail(worst, "a subdomain of the batch failed (M_s not positive definite)");
+    return XLS_OK;
+  });
+}
+
+int xls_batch_density(xls_batch_t b, double mu, double sigma, double* rho_concat, double* c_concat) {
+  return guarded([&]() -> int {
+    if (!b || !rho_concat || !c_concat) fail(XLS_ERR_INVALID_ARG, "bad argument");
+    int64_t off_r = 0, off_c = 0;
+    for (auto* s : b->subs) {
+      const int rc = xls_subdomain_density(s, mu, sigma, rho_concat + off_r, c_concat + off_c);
+      if (rc != XLS_OK) fail(rc, xls_last_error());
+      off_r += s->nd;
+      off_c += s->ns;
+    }
+    return XLS_OK;
+  });
+}
+
+int xls_batch_subdomain(xls_batch_t b, int32_t i, xls_subdomain_t* out) {
+  return guarded([&]() -> int {
+    if (!b || !out || i < 0 || i >= b->n) fail(XLS_ERR_INVALID_ARG, "bad argument");
+    XLS_HIP(hipStreamSynchronize(b->main));
+    *out = b->subs[i];
+    return XLS_OK;
+  });
+}
+
+int xls_batch_tune(xls_batch_t b, const char* cache_path, int32_t* tuned, double* best_ms) {
+  return guarded([&]() -> int {
+    if (!b) fail(XLS_ERR_INVALID_ARG, "bad argument");
+    XLS_HIP(hipStreamSynchronize(b->main));
+    const int t = b->prec == XLS_PREC_FP32 ? tune_batch<float>(b, cache_path, best_ms)
+                                           : tune_batch<double>(b, cache_path, best_ms);
+    if (tuned) *tuned = t;
+    return XLS_OK;
+  });
+}
+
+int xls_batch_stats(xls_batch_t b, double* out, int32_t cap) {
+  return guarded([&]() -> int {
+    if (!b || !out || cap < 1) fail(XLS_ERR_INVALID_ARG, "bad argument");
+    const double v[5] = {static_cast<double>(b->iterations), static_cast<double>(b->captures),
+                         static_cast<double>(b->replays), b->iter_ms, b->last_iter_ms};
+    for (int k = 0; k < std::min(cap, 5); ++k) out[k] = v[k];
+    return XLS_OK;
+  });
+}
+
+}  // extern "C"

@@ -639,10 +639,7 @@ __global__ __launch_bounds__(256) void bt_kernel(const double* __restrict__ Z, c
   }
 }
 
-void set_smem(const void* fn, size_t bytes) {
-  if (bytes > 64 * 1024)
-    XLS_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(bytes)));
-}
+void set_smem(const void* fn, size_t bytes) { ensure_dyn_smem(fn, bytes); }
 
 }  // namespace
 
@@ -679,7 +676,7 @@ void dense_free(DenseWork& w) {
   w.n = 0;
 }
 
-int dense_geneig(DenseWork& w, const double* Hs, const double* M, double* Y, hipStream_t st) {
+int dense_geneig(DenseWork& w, const double* Hs, const double* M, double* Y, hipStream_t st, bool check_spd) {
   const int n = w.n;
   const int64_t nn = static_cast<int64_t>(n) * n;
   double* vec = w.vec;
@@ -714,10 +711,12 @@ int dense_geneig(DenseWork& w, const double* Hs, const double* M, double* Y, hip
     }
   }
   XLS_LAUNCH_CHECK("cholesky");
-  int32_t hflag = 0;
-  XLS_HIP(hipMemcpyAsync(&hflag, w.flag, 4, hipMemcpyDeviceToHost, st));
-  XLS_HIP(hipStreamSynchronize(st));
-  if (hflag) return XLS_ERR_NOT_SPD;
+  if (check_spd) {
+    int32_t hflag = 0;
+    XLS_HIP(hipMemcpyAsync(&hflag, w.flag, 4, hipMemcpyDeviceToHost, st));
+    XLS_HIP(hipStreamSynchronize(st));
+    if (hflag) return XLS_ERR_NOT_SPD;
+  }
   // --- Rinv ---
   const size_t trinv_smem = static_cast<size_t>(n) * sizeof(double);
   set_smem(reinterpret_cast<const void*>(trinv_kernel), trinv_smem);

@@ -10,4 +10,8 @@ namespace xls {
   template void launch_proj_forward<TS, TC>(const OpTables<TC>&, const TS*, int64_t, int, TC*,    \
                                             hipStream_t);
 XLS_INST_STENCIL(float, float)
+template FilterGroup<float>* filter_group_build<float>(const std::vector<FilterGroupOp<float>>&);
+template void filter_group_step<float>(FilterGroup<float>*, int, hipStream_t);
+template int filter_group_steps<float>(const FilterGroup<float>*);
+template void filter_group_free<float>(FilterGroup<float>*);
 }  // namespace xls

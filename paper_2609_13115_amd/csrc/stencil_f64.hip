@@ -11,4 +11,8 @@ namespace xls {
   template void launch_proj_forward<TS, TC>(const OpTables<TC>&, const TS*, int64_t, int, TC*,    \
                                             hipStream_t);
 XLS_INST_STENCIL(double, double)
+template FilterGroup<double>* filter_group_build<double>(const std::vector<FilterGroupOp<double>>&);
+template void filter_group_step<double>(FilterGroup<double>*, int, hipStream_t);
+template int filter_group_steps<double>(const FilterGroup<double>*);
+template void filter_group_free<double>(FilterGroup<double>*);
 }  // namespace xls

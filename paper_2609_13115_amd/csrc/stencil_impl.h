@@ -47,6 +47,7 @@ struct HArgs {
   TC wc;     // -1/2 * 3 w0 / h^2
   TC w[R];   // -1/2 * w_p / h^2
   TC a, c, b;
+  const double* coef;  // grouped launches: per-step (a, c, b) triples in device memory
   int32_t has_prev;
   const double* lam;
   double* partial;
@@ -164,9 +165,12 @@ __device__ __forceinline__ Ent4<double> load_ent<double>(__amdgpu_buffer_rsrc_t 
 
 // WS: LDS row stride in elements (compile time, so every neighbour read uses
 // an immediate offset); rows hold nx + 2R entries, nx + 2R <= WS.
+// One tile (column, y band, z chunk) given by its logical index; coefficients
+// ca, cc, cb of the fused recurrence.  Shared by the single-operator launch
+// and the grouped persistent launch.
 template <typename TS, typename TC, int MODE, int P, int NT, int WS>
-__global__ __launch_bounds__(NT) void hstencil_kernel(HArgs<TS, TC> A) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
+__device__ __forceinline__ void stencil_tile(const HArgs<TS, TC>& A, uint32_t logical, TC ca, TC cc, TC cb,
+                                             unsigned char* smem_raw) {
   TC* lds = reinterpret_cast<TC*>(smem_raw);
   const int nx = A.nx, ny = A.ny, nz = A.nz;
   constexpr int W = WS;
@@ -174,7 +178,6 @@ __global__ __launch_bounds__(NT) void hstencil_kernel(HArgs<TS, TC> A) {
   const int plane = dumpi + 1;
   TC* alds = lds + 2 * plane;          // this column's projection coefficients
 
-  const uint32_t logical = xcd_remap(blockIdx.x, gridDim.x);
   const int tiles = A.nyt * A.nzt;
   const int col = static_cast<int>(logical / tiles);
   const int t = static_cast<int>(logical % tiles);
@@ -366,7 +369,7 @@ __global__ __launch_bounds__(NT) void hstencil_kernel(HArgs<TS, TC> A) {
       if (MODE == kApply) {
         bstore(static_cast<TS>(hy), ro, os[i], so);
       } else if (MODE == kFilter) {
-        const TC r = A.a * (hy - A.c * ctr) - A.b * yp1[i];
+        const TC r = ca * (hy - cc * ctr) - cb * yp1[i];
         bstore(static_cast<TS>(r), ro, os[i], so);
       } else if (vo[i] >= 0) {
         const double d = static_cast<double>(hy) - lamc * static_cast<double>(ctr);
@@ -426,6 +429,33 @@ __global__ __launch_bounds__(NT) void hstencil_kernel(HArgs<TS, TC> A) {
   }
 }
 
+template <typename TS, typename TC, int MODE, int P, int NT, int WS>
+__global__ __launch_bounds__(NT) void hstencil_kernel(HArgs<TS, TC> A) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  stencil_tile<TS, TC, MODE, P, NT, WS>(A, xcd_remap(blockIdx.x, gridDim.x), A.a, A.c, A.b, smem_raw);
+}
+
+// Grouped persistent filter step over many operators: item = (operator,
+// logical tile).  Workgroups walk the item list with a grid stride; the
+// xcd remap gives the workgroups of one XCD consecutive items, so the tiles
+// that share halo rows meet in the same L2.  Step k reads its recurrence
+// coefficients from the operator's device table.
+template <typename TS, typename TC, int P, int NT, int WS>
+__global__ __launch_bounds__(NT) void hstencil_group_kernel(const HArgs<TS, TC>* __restrict__ tab,
+                                                            const uint2* __restrict__ items, int nitems,
+                                                            int k) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const uint32_t G = gridDim.x;
+  for (uint32_t it = xcd_remap(blockIdx.x, G); it < static_cast<uint32_t>(nitems); it += G) {
+    const uint2 w = items[it];
+    const HArgs<TS, TC> A = tab[w.x];
+    const double* cf = A.coef + 3 * k;
+    stencil_tile<TS, TC, kFilter, P, NT, WS>(A, w.y, static_cast<TC>(cf[0]), static_cast<TC>(cf[1]),
+                                             static_cast<TC>(cf[2]), smem_raw);
+    __syncthreads();
+  }
+}
+
 // alpha[col][4a+l] = gamma_{a,l} h^3 sum_s chi_{a,l}(s) y(idx(s), col): one
 // wavefront per (atom, column), lanes stride over the atom's support, fixed
 // xor-shuffle reduction (deterministic).
@@ -467,6 +497,57 @@ __global__ __launch_bounds__(256) void proj_forward_kernel(const TS* __restrict_
   }
 }
 
+
+// Grouped forward projection: item = (operator, atom + n_atoms * column group).
+template <typename TS, typename TC>
+struct PArgs {
+  const TS* y;
+  int64_t ld;
+  const int32_t* sup_off;
+  const int32_t* sup_idx;
+  const TC* val;
+  const double* gamma;
+  double h3;
+  TC* alpha;
+  int32_t nproj, ncols, n_atoms;
+};
+
+template <typename TS, typename TC>
+__global__ __launch_bounds__(256) void proj_forward_group_kernel(const PArgs<TS, TC>* __restrict__ tab,
+                                                                 const uint2* __restrict__ items, int nitems) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (uint32_t it = blockIdx.x; it < static_cast<uint32_t>(nitems); it += gridDim.x) {
+    const uint2 w = items[it];
+    const PArgs<TS, TC> A = tab[w.x];
+    const int a = static_cast<int>(w.y % static_cast<uint32_t>(A.n_atoms));
+    const int col = static_cast<int>(w.y / static_cast<uint32_t>(A.n_atoms)) * 4 + wave;
+    if (col >= A.ncols) continue;
+    const int s0 = A.sup_off[a], s1 = A.sup_off[a + 1];
+    const TS* __restrict__ yc = A.y + static_cast<int64_t>(col) * A.ld;
+    double acc0 = 0, acc1 = 0, acc2 = 0, acc3 = 0;
+    for (int s = s0 + lane; s < s1; s += 64) {
+      const double yv = static_cast<double>(yc[A.sup_idx[s]]);
+      const TC* v4 = A.val + 4 * static_cast<int64_t>(s);
+      acc0 += static_cast<double>(v4[0]) * yv;
+      acc1 += static_cast<double>(v4[1]) * yv;
+      acc2 += static_cast<double>(v4[2]) * yv;
+      acc3 += static_cast<double>(v4[3]) * yv;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      acc0 += __shfl_xor(acc0, off, 64);
+      acc1 += __shfl_xor(acc1, off, 64);
+      acc2 += __shfl_xor(acc2, off, 64);
+      acc3 += __shfl_xor(acc3, off, 64);
+    }
+    if (lane == 0) {
+      TC* o = A.alpha + static_cast<int64_t>(col) * A.nproj + 4 * a;
+      o[0] = static_cast<TC>(A.gamma[4 * a + 0] * A.h3 * acc0);
+      o[1] = static_cast<TC>(A.gamma[4 * a + 1] * A.h3 * acc1);
+      o[2] = static_cast<TC>(A.gamma[4 * a + 2] * A.h3 * acc2);
+      o[3] = static_cast<TC>(A.gamma[4 * a + 3] * A.h3 * acc3);
+    }
+  }
+}
 
 struct TileChoice {
   int block, ty, nyt, tz, nzt, P, ws;
@@ -519,10 +600,7 @@ inline void check_tiles(const TileChoice& tc, int nx, int periodic, int elem) {
 
 template <typename K>
 void allow_smem(K kern, size_t smem) {
-  if (smem > 64 * 1024 &&
-      hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
-                          static_cast<int>(smem)) != hipSuccess)
-    fail(XLS_ERR_INVALID_ARG, "stencil tile exceeds the dynamic LDS limit");
+  ensure_dyn_smem(reinterpret_cast<const void*>(kern), smem);
 }
 
 template <typename TS, typename TC, int MODE, int P, int WS>
@@ -598,14 +676,11 @@ size_t stencil_partial_elems(const OpTables<double>& op, int ncols, const Stenci
 
 #endif  // XLS_STENCIL_DEFINE_HOST
 
+// Operator tables, geometry and FD weights of one launch (coefficients,
+// residual outputs and has_prev are set by the caller).
 template <typename TS, typename TC>
-void launch_stencil(StencilMode mode, const OpTables<TC>& op, const TS* y, int64_t ld, int ncols,
-                    const TC* alpha, TS* out, const TS* yprev, double a, double c, double b,
-                    const double* lam, double* partial, double* resid2, hipStream_t st,
-                    const StencilLaunch& cfg) {
-  if (ncols <= 0) return;
-  const TileChoice tc = tiles_for(op, ld, cfg);
-  check_tiles(tc, op.nx, op.periodic, sizeof(TC));
+static HArgs<TS, TC> make_hargs(const OpTables<TC>& op, const TileChoice& tc, const TS* y, int64_t ld,
+                                const TC* alpha, TS* out, const TS* yprev) {
   HArgs<TS, TC> A{};
   A.y = y;
   A.yprev = yprev;
@@ -631,6 +706,18 @@ void launch_stencil(StencilMode mode, const OpTables<TC>& op, const TS* y, int64
   const double s = -0.5 / (op.h * op.h);
   A.wc = static_cast<TC>(3.0 * w[0] * s);
   for (int p = 1; p <= R; ++p) A.w[p - 1] = static_cast<TC>(w[p] * s);
+  return A;
+}
+
+template <typename TS, typename TC>
+void launch_stencil(StencilMode mode, const OpTables<TC>& op, const TS* y, int64_t ld, int ncols,
+                    const TC* alpha, TS* out, const TS* yprev, double a, double c, double b,
+                    const double* lam, double* partial, double* resid2, hipStream_t st,
+                    const StencilLaunch& cfg) {
+  if (ncols <= 0) return;
+  const TileChoice tc = tiles_for(op, ld, cfg);
+  check_tiles(tc, op.nx, op.periodic, sizeof(TC));
+  HArgs<TS, TC> A = make_hargs<TS, TC>(op, tc, y, ld, alpha, out, yprev);
   A.a = static_cast<TC>(a);
   A.c = static_cast<TC>(c);
   A.b = static_cast<TC>(b);
@@ -674,6 +761,217 @@ void launch_proj_forward(const OpTables<TC>& op, const TS* y, int64_t ld, int nc
   hipLaunchKernelGGL((proj_forward_kernel<TS, TC>), grid, dim3(256), 0, st, y, ld, ncols,
                      op.sup_off, op.sup_idx, op.slot_val, op.gamma, h3, alpha, 4 * op.n_atoms);
   XLS_LAUNCH_CHECK("proj_forward_kernel");
+}
+
+// ---------------------------------------------------------------------------
+// Grouped filter steps (batch engine)
+// ---------------------------------------------------------------------------
+template <typename T>
+T* group_alloc(size_t n) {
+  void* p = nullptr;
+  if (hipMalloc(&p, std::max<size_t>(n, 1) * sizeof(T)) != hipSuccess)
+    fail(XLS_ERR_OUT_OF_MEMORY, "grouped filter: device allocation failed");
+  return static_cast<T*>(p);
+}
+inline void group_release(void* p) {
+  if (p) (void)hipFree(p);
+}
+
+template <typename TS>
+struct FilterGroup {
+  struct Bucket {
+    int P = 1, block = 256, ws = 80;
+    size_t smem = 0;
+    uint2* items = nullptr;
+    std::vector<int> count;  // items taking part in step k
+    int grid_cap = 0;
+  };
+  std::vector<Bucket> buckets;
+  HArgs<TS, TS>* tab[3] = {nullptr, nullptr, nullptr};  // step 0, odd steps, even steps >= 2
+  PArgs<TS, TS>* ptab[2] = {nullptr, nullptr};          // steps with k even / odd
+  uint2* pitems = nullptr;
+  std::vector<int> pcount;
+  int pgrid = 0;
+  int steps = 0;
+};
+
+template <typename TS, int P, int NT, int WS>
+int group_occupancy(size_t smem) {
+  allow_smem(hstencil_group_kernel<TS, TS, P, NT, WS>, smem);
+  int nb = 0;
+  XLS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      &nb, reinterpret_cast<const void*>(hstencil_group_kernel<TS, TS, P, NT, WS>), NT, smem));
+  return std::max(1, nb);
+}
+
+template <typename TS, int P, int WS>
+int group_occ_block(int block, size_t smem) {
+  return block == 256 ? group_occupancy<TS, P, 256, WS>(smem) : group_occupancy<TS, P, 512, WS>(smem);
+}
+
+template <typename TS>
+int group_occ(int P, int block, int ws, size_t smem) {
+  if (ws == 80) return P == 1 ? group_occ_block<TS, 1, 80>(block, smem) : group_occ_block<TS, 2, 80>(block, smem);
+  return P == 1 ? group_occ_block<TS, 1, 128>(block, smem) : group_occ_block<TS, 2, 128>(block, smem);
+}
+
+template <typename TS, int P, int WS>
+void group_launch_pw(const typename FilterGroup<TS>::Bucket& b, const HArgs<TS, TS>* tab, int n, int k,
+                     hipStream_t st) {
+  const dim3 grid(static_cast<unsigned>(std::min(n, b.grid_cap)));
+  if (b.block == 256)
+    hipLaunchKernelGGL((hstencil_group_kernel<TS, TS, P, 256, WS>), grid, dim3(256), b.smem, st, tab, b.items, n,
+                       k);
+  else
+    hipLaunchKernelGGL((hstencil_group_kernel<TS, TS, P, 512, WS>), grid, dim3(512), b.smem, st, tab, b.items, n,
+                       k);
+}
+
+template <typename TS>
+void filter_group_free(FilterGroup<TS>* g) {
+  if (!g) return;
+  for (auto& b : g->buckets) group_release(b.items);
+  for (auto* t : g->tab) group_release(t);
+  for (auto* t : g->ptab) group_release(t);
+  group_release(g->pitems);
+  delete g;
+}
+
+template <typename TS>
+FilterGroup<TS>* filter_group_build(const std::vector<FilterGroupOp<TS>>& ops) {
+  auto* g = new FilterGroup<TS>();
+  try {
+    const int n = static_cast<int>(ops.size());
+    std::vector<int> order(n);
+    for (int i = 0; i < n; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return ops[a].degree > ops[b].degree; });
+    for (const auto& o : ops) g->steps = std::max(g->steps, o.degree);
+    std::vector<TileChoice> tcs(n);
+    std::vector<int> bucket_of(n);
+    for (int i = 0; i < n; ++i) {
+      const auto& o = ops[i];
+      if (o.degree < 1 || o.ncols < 1) fail(XLS_ERR_INVALID_ARG, "grouped filter: degree and ncols must be >= 1");
+      tcs[i] = tiles_for(*o.op, o.ld, o.cfg);
+      check_tiles(tcs[i], o.op->nx, o.op->periodic, sizeof(TS));
+      int bi = -1;
+      for (size_t j = 0; j < g->buckets.size(); ++j) {
+        const auto& b = g->buckets[j];
+        if (b.P == tcs[i].P && b.block == tcs[i].block && b.ws == tcs[i].ws) bi = static_cast<int>(j);
+      }
+      if (bi < 0) {
+        typename FilterGroup<TS>::Bucket b;
+        b.P = tcs[i].P;
+        b.block = tcs[i].block;
+        b.ws = tcs[i].ws;
+        g->buckets.push_back(b);
+        bi = static_cast<int>(g->buckets.size()) - 1;
+      }
+      g->buckets[bi].smem = std::max(g->buckets[bi].smem, tcs[i].smem);
+      bucket_of[i] = bi;
+    }
+    // operator tables for the three step kinds and two input parities
+    for (int v = 0; v < 3; ++v) {
+      const int k = v;  // representative step: 0, 1 (odd), 2 (even >= 2)
+      std::vector<HArgs<TS, TS>> h(n);
+      for (int i = 0; i < n; ++i) {
+        const auto& o = ops[i];
+        TS* in = o.buf[(o.cur0 + k) & 1];
+        TS* out = o.buf[(o.cur0 + k + 1) & 1];
+        h[i] = make_hargs<TS, TS>(*o.op, tcs[i], in, o.ld, o.alpha, out, k >= 1 ? out : nullptr);
+        h[i].coef = o.coef;
+        h[i].has_prev = k >= 1 ? 1 : 0;
+      }
+      g->tab[v] = group_alloc<HArgs<TS, TS>>(n);
+      XLS_HIP(hipMemcpy(g->tab[v], h.data(), n * sizeof(h[0]), hipMemcpyHostToDevice));
+    }
+    for (int v = 0; v < 2; ++v) {
+      std::vector<PArgs<TS, TS>> h(n);
+      for (int i = 0; i < n; ++i) {
+        const auto& o = ops[i];
+        PArgs<TS, TS> a{};
+        a.y = o.buf[(o.cur0 + v) & 1];
+        a.ld = o.ld;
+        a.sup_off = o.op->sup_off;
+        a.sup_idx = o.op->sup_idx;
+        a.val = o.op->slot_val;
+        a.gamma = o.op->gamma;
+        a.h3 = o.op->h * o.op->h * o.op->h;
+        a.alpha = o.alpha;
+        a.nproj = 4 * o.op->n_atoms;
+        a.ncols = o.ncols;
+        a.n_atoms = o.op->n_atoms;
+        h[i] = a;
+      }
+      g->ptab[v] = group_alloc<PArgs<TS, TS>>(n);
+      XLS_HIP(hipMemcpy(g->ptab[v], h.data(), n * sizeof(h[0]), hipMemcpyHostToDevice));
+    }
+    int cus = 0;
+    XLS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, 0));
+    // work items; operators in descending degree, so step k uses a prefix
+    auto build_items = [&](auto count_of, std::vector<int>& count, uint2*& dst, auto member) {
+      std::vector<uint2> items;
+      std::vector<int64_t> end_of;
+      std::vector<int> degs;
+      for (int i : order) {
+        if (!member(i)) continue;
+        const int64_t nt = count_of(i);
+        if (static_cast<int64_t>(items.size()) + nt > 0x7fffffff) fail(XLS_ERR_INVALID_ARG, "too many work items");
+        for (int64_t l = 0; l < nt; ++l)
+          items.push_back(make_uint2(static_cast<unsigned>(i), static_cast<unsigned>(l)));
+        end_of.push_back(static_cast<int64_t>(items.size()));
+        degs.push_back(ops[i].degree);
+      }
+      count.assign(g->steps, 0);
+      for (int k = 0; k < g->steps; ++k)
+        for (size_t j = 0; j < degs.size(); ++j)
+          if (degs[j] > k) count[k] = static_cast<int>(end_of[j]);
+      dst = group_alloc<uint2>(items.size());
+      if (!items.empty())
+        XLS_HIP(hipMemcpy(dst, items.data(), items.size() * sizeof(uint2), hipMemcpyHostToDevice));
+    };
+    for (size_t bi = 0; bi < g->buckets.size(); ++bi) {
+      auto& b = g->buckets[bi];
+      build_items([&](int i) { return static_cast<int64_t>(ops[i].ncols) * tcs[i].nyt * tcs[i].nzt; }, b.count,
+                  b.items, [&](int i) { return bucket_of[i] == static_cast<int>(bi); });
+      b.grid_cap = group_occ<TS>(b.P, b.block, b.ws, b.smem) * cus;
+    }
+    build_items([&](int i) { return static_cast<int64_t>(ops[i].op->n_atoms) * ((ops[i].ncols + 3) / 4); },
+                g->pcount, g->pitems, [](int) { return true; });
+    g->pgrid = 16 * cus;
+  } catch (...) {
+    filter_group_free(g);
+    throw;
+  }
+  return g;
+}
+
+template <typename TS>
+void filter_group_step(FilterGroup<TS>* g, int k, hipStream_t st) {
+  if (k < 0 || k >= g->steps) fail(XLS_ERR_INVALID_ARG, "grouped filter: step out of range");
+  if (g->pcount[k] > 0) {
+    const dim3 grid(static_cast<unsigned>(std::min(g->pcount[k], g->pgrid)));
+    hipLaunchKernelGGL((proj_forward_group_kernel<TS, TS>), grid, dim3(256), 0, st, g->ptab[k & 1], g->pitems,
+                       g->pcount[k]);
+    XLS_LAUNCH_CHECK("proj_forward_group_kernel");
+  }
+  const HArgs<TS, TS>* tab = g->tab[k == 0 ? 0 : ((k & 1) ? 1 : 2)];
+  for (const auto& b : g->buckets) {
+    const int n = b.count[k];
+    if (n <= 0) continue;
+    if (b.ws == 80) {
+      if (b.P == 1) group_launch_pw<TS, 1, 80>(b, tab, n, k, st);
+      else group_launch_pw<TS, 2, 80>(b, tab, n, k, st);
+    } else {
+      if (b.P == 1) group_launch_pw<TS, 1, 128>(b, tab, n, k, st);
+      else group_launch_pw<TS, 2, 128>(b, tab, n, k, st);
+    }
+    XLS_LAUNCH_CHECK("hstencil_group_kernel");
+  }
+}
+
+template <typename TS>
+int filter_group_steps(const FilterGroup<TS>* g) {
+  return g->steps;
 }
 
 }  // namespace xls

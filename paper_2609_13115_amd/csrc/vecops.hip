@@ -4,6 +4,9 @@
 // fixed order (no floating-point atomics), so results are bitwise repeatable.
 #include <cmath>
 
+#include <map>
+#include <mutex>
+
 #include "xls_internal.h"
 
 namespace xls {
@@ -278,5 +281,58 @@ void launch_block_to_double(const TS* src, int64_t lds_, double* dst, int64_t ld
                                            hipStream_t);
 XLS_INST_VEC(double)
 XLS_INST_VEC(float)
+
+void ensure_dyn_smem(const void* fn, size_t bytes) {
+  if (bytes <= 64 * 1024) return;
+  static std::mutex mu;
+  static std::map<const void*, size_t> done;
+  std::lock_guard<std::mutex> lock(mu);
+  size_t& cur = done[fn];
+  if (bytes <= cur) return;
+  if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(bytes)) != hipSuccess) {
+    (void)hipGetLastError();
+    fail(XLS_ERR_INVALID_ARG, "kernel needs more LDS than the device allows");
+  }
+  cur = bytes;
+}
+
+namespace {
+// Coefficients of the scaled Chebyshev recurrence (the same scalar sequence
+// as the host path): e = (lmax - lc)/2, c = (lmax + lc)/2, sigma_1 =
+// e/(a0 - c), tau = 2/sigma_1, sigma_{k+1} = 1/(tau - sigma_k);
+// step 0: (sigma_1/e, c, 0); step k: (2 sigma_{k+1}/e, c, sigma_k sigma_{k+1}).
+__global__ void filter_coef_kernel(const double* __restrict__ lam, int ns, double a0, double lc, double lmax,
+                                   int m, double* __restrict__ coef, int32_t* __restrict__ bad) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  if (lam) {
+    a0 = lam[0];
+    lc = lam[ns - 1];
+  }
+  const bool ok = (a0 < lc) && (lc < lmax);
+  if (bad) *bad = ok ? 0 : 1;
+  if (!ok) return;
+  const double e = (lmax - lc) / 2.0;
+  const double c = (lmax + lc) / 2.0;
+  const double sigma1 = e / (a0 - c);
+  const double tau = 2.0 / sigma1;
+  coef[0] = sigma1 / e;
+  coef[1] = c;
+  coef[2] = 0.0;
+  double sig = sigma1;
+  for (int k = 1; k < m; ++k) {
+    const double signew = 1.0 / (tau - sig);
+    coef[3 * k] = 2.0 * signew / e;
+    coef[3 * k + 1] = c;
+    coef[3 * k + 2] = sig * signew;
+    sig = signew;
+  }
+}
+}  // namespace
+
+void launch_filter_coef(const double* lam, int ns, double a0, double lc, double lmax, int m, double* coef,
+                        int32_t* bad, hipStream_t st) {
+  hipLaunchKernelGGL(filter_coef_kernel, dim3(1), dim3(64), 0, st, lam, ns, a0, lc, lmax, m, coef, bad);
+  XLS_LAUNCH_CHECK("filter_coef_kernel");
+}
 
 }  // namespace xls

@@ -1,0 +1,156 @@
+// Subdomain handle and the per-subdomain stage helpers shared by the C ABI
+// (api.cpp) and the batch engine (batch.cpp).  Internal to libxls.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <new>
+#include <string>
+#include <vector>
+
+#include "xls_internal.h"
+
+namespace xls {
+void dfree(void* p);
+}  // namespace xls
+
+using xls::DenseWork;
+using xls::OpTables;
+using xls::SetupTables;
+using xls::StencilLaunch;
+
+struct xls_subdomain_s {
+  int n[3] = {0, 0, 0};
+  double h = 0;
+  int bc = 0;
+  int prec = XLS_PREC_FP64;
+  int ns = 0;
+  int64_t nd = 0, ld = 0;
+  hipStream_t st = nullptr;
+  bool own_stream = false;
+  SetupTables tab;
+  int n_atoms = 0;
+  // device: operator tables in both precisions
+  double* v64 = nullptr;
+  float* v32 = nullptr;
+  double* val64 = nullptr;
+  float* val32 = nullptr;
+  int32_t *rev_pk = nullptr, *rev_aoff = nullptr, *sup_off = nullptr, *sup_idx = nullptr;
+  double* rev_val64 = nullptr;
+  float* rev_val32 = nullptr;
+  double* gamma = nullptr;
+  uint8_t* mask = nullptr;
+  OpTables<double> op64;
+  OpTables<float> op32;
+  StencilLaunch cfg64, cfg32;
+  // blocks
+  void* blk[2] = {nullptr, nullptr};
+  int cur = 0;
+  void* alpha = nullptr;      // [ns][nproj] in storage type
+  double* alpha64 = nullptr;  // [ns][nproj] FP64 (residuals of FP32 blocks)
+  double* partial = nullptr;
+  size_t partial_elems = 0;
+  double* lam_dev = nullptr;
+  double* resid_dev = nullptr;
+  double* Mdev = nullptr;
+  double* Hsdev = nullptr;
+  double* Ydev = nullptr;
+  float* bwork = nullptr;
+  double* gwork = nullptr;
+  size_t gwork_elems = 0;
+  DenseWork dw;
+  double* vsmall = nullptr;  // density / Lanczos scalars
+  double* rho_dev = nullptr;
+  double* cpart = nullptr;
+  double* gocc = nullptr;
+  // Lanczos
+  std::vector<double> lanczos_v0;
+  void* lz = nullptr;  // [nd * (kmax + 2)]
+  int lz_cols = 0;
+  bool have_lanczos = false;
+  double lz_lo = 0, lz_up = 0;
+  int lz_k = 0;
+  // state
+  std::vector<double> ritz;
+  bool have_ritz = false;
+  std::vector<double> stage_ms;
+  int64_t filter_launches = 0;
+  double filter_kernel_ms = 0.0;  // sum over fused-filter stencil launches (profiling on)
+  std::vector<hipEvent_t> fev;
+
+  ~xls_subdomain_s() {
+    void* ps[] = {v64, v32, val64, val32, rev_pk, rev_aoff, rev_val64, rev_val32, sup_off, sup_idx, gamma, mask,
+                  blk[0], blk[1], alpha, alpha64, partial, lam_dev, resid_dev, Mdev, Hsdev, Ydev, bwork,
+                  gwork, vsmall, rho_dev, cpart, gocc, lz};
+    for (void* p : ps) xls::dfree(p);
+    for (auto e : fev) (void)hipEventDestroy(e);
+    xls::dense_free(dw);
+    if (own_stream && st) (void)hipStreamDestroy(st);
+  }
+  size_t esize() const { return prec == XLS_PREC_FP32 ? 4 : 8; }
+  int nproj() const { return 4 * n_atoms; }
+};
+
+namespace xls {
+
+void set_last_error(const std::string& m);
+bool profiling_on();
+void dfree(void* p);
+bool finite_all(const double* p, int64_t n);
+
+template <typename T>
+T* dalloc(size_t n) {
+  void* p = nullptr;
+  if (n == 0) n = 1;
+  const hipError_t e = hipMalloc(&p, n * sizeof(T));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    fail(XLS_ERR_OUT_OF_MEMORY, "device allocation of " + std::to_string(n * sizeof(T)) + " bytes failed");
+  }
+  return static_cast<T*>(p);
+}
+
+// Runs f, mapping exceptions to status codes (no exception crosses the ABI).
+template <typename F>
+int guarded(F&& f) {
+  try {
+    return f();
+  } catch (const Error& e) {
+    set_last_error(e.msg);
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    set_last_error("host allocation failed");
+    return XLS_ERR_OUT_OF_MEMORY;
+  } catch (...) {
+    set_last_error("unexpected internal error");
+    return XLS_ERR_DEVICE;
+  }
+}
+
+template <typename TS>
+TS* B(xls_subdomain_s* s, int i) {
+  return static_cast<TS*>(s->blk[i]);
+}
+inline const OpTables<double>& op_of(xls_subdomain_s* s, double) { return s->op64; }
+inline const OpTables<float>& op_of(xls_subdomain_s* s, float) { return s->op32; }
+template <typename TS>
+const OpTables<TS>& op_of(xls_subdomain_s* s) {
+  return op_of(s, TS{});
+}
+template <typename TS>
+const StencilLaunch& cfg_of(xls_subdomain_s* s) {
+  return std::is_same<TS, float>::value ? s->cfg32 : s->cfg64;
+}
+
+// Stage helpers on the handle's stream (api.cpp).
+template <typename TS>
+void apply_H(xls_subdomain_s* s, const TS* y, TS* out, int ncols, TS* alpha);
+template <typename TS>
+void filter_block(xls_subdomain_s* s, int m, double a0, double lc, double lmax);
+template <typename TS>
+void rotate_block(xls_subdomain_s* s, int gprec, const double* Ydev);
+template <typename TS>
+void residual_block(xls_subdomain_s* s, const double* lam_dev, double* resid_dev);
+template <typename TS>
+void lanczos_run(xls_subdomain_s* s, int k);
+
+}  // namespace xls

@@ -90,6 +90,45 @@ void launch_stencil(StencilMode mode, const OpTables<TC>& op, const TS* y, int64
 template <typename TS, typename TC>
 void launch_proj_forward(const OpTables<TC>& op, const TS* y, int64_t ld, int ncols, TC* alpha,
                          hipStream_t st);
+// Raises a kernel's dynamic-LDS limit to at least `bytes` (no-op at or below
+// 64 KiB; each kernel is configured once per size, so launches inside a
+// graph capture make no runtime-configuration calls after warm-up).
+void ensure_dyn_smem(const void* fn, size_t bytes);
+
+// Grouped filter steps over many operators of one precision (batch engine).
+// Operator i filters its block in place between buf[0] and buf[1]: step k
+// reads buf[(cur0 + k) & 1] and writes buf[(cur0 + k + 1) & 1], with the
+// recurrence coefficients coef[3k .. 3k+2] read from device memory; operators
+// take part in steps k < degree.  Build and free synchronise; steps only
+// launch kernels (graph-capturable).
+template <typename TS>
+struct FilterGroupOp {
+  const OpTables<TS>* op;
+  TS* buf[2];
+  int cur0;
+  int64_t ld;
+  int ncols;
+  TS* alpha;           // [ncols][4 n_atoms]
+  const double* coef;  // device, 3 * degree doubles
+  int degree;
+  StencilLaunch cfg;
+};
+template <typename TS>
+struct FilterGroup;
+template <typename TS>
+FilterGroup<TS>* filter_group_build(const std::vector<FilterGroupOp<TS>>& ops);
+template <typename TS>
+void filter_group_step(FilterGroup<TS>* g, int k, hipStream_t st);
+template <typename TS>
+int filter_group_steps(const FilterGroup<TS>* g);
+template <typename TS>
+void filter_group_free(FilterGroup<TS>* g);
+// coef[3k..3k+2] = (a_k, c, b_k) of the scaled recurrence for degree m:
+// from (a0, lam_cut, lam_max), or with lam != NULL from a0 = lam[0] and
+// lam_cut = lam[ns-1]; bad = 1 when a0 < lam_cut < lam_max fails.
+void launch_filter_coef(const double* lam, int ns, double a0, double lc, double lmax, int m, double* coef,
+                        int32_t* bad, hipStream_t st);
+
 // Throws INVALID_ARG when the launch shape cannot run on this grid.
 void stencil_validate(int nx, int ny, int nz, int periodic, int elem_bytes, int nproj,
                       const StencilLaunch& cfg);
@@ -132,8 +171,11 @@ void dense_alloc(DenseWork& w, int n);
 void dense_free(DenseWork& w);
 // On XLS_OK, w.lam() (device, ascending) and Y (device, n x n, M-orthonormal
 // columns) hold the result; XLS_ERR_NOT_SPD when M is not positive definite.
-// Synchronises st once (after the Cholesky factorisation).
-int dense_geneig(DenseWork& w, const double* Hs, const double* M, double* Y, hipStream_t st);
+// Synchronises st once (after the Cholesky factorisation) when check_spd.
+// With check_spd false nothing synchronises: the caller reads w.flag later
+// (nonzero: not positive definite; the later stages then skip their work).
+int dense_geneig(DenseWork& w, const double* Hs, const double* M, double* Y, hipStream_t st,
+                 bool check_spd = true);
 
 // vector helpers (vecops.hip)
 template <typename TS>

@@ -38,6 +38,8 @@ EXPORTED = [
     "xls_subdomain_get_block", "xls_subdomain_set_block", "xls_subdomain_get_maps",
     "xls_subdomain_get_projectors", "xls_split_bf16", "xls_set_profiling", "xls_get_stage_times",
     "xls_subdomain_tune",
+    "xls_batch_create", "xls_batch_chefsi", "xls_batch_density", "xls_batch_subdomain", "xls_batch_tune",
+    "xls_batch_stats", "xls_batch_destroy",
 ]
 
 
@@ -85,6 +87,7 @@ def lib() -> C.CDLL:
         L = C.CDLL(LIB_PATH)
         L.xls_last_error.restype = C.c_char_p
         L.xls_subdomain_destroy.restype = None
+        L.xls_batch_destroy.restype = None
         _lib = L
     return _lib
 
@@ -130,61 +133,86 @@ def xls_split_bf16(a: np.ndarray) -> Tuple[np.ndarray, np.ndarray]:
     return hi, lo
 
 
+def make_desc(sd, filter_prec: int = XLS_PREC_FP64, x0: Optional[np.ndarray] = None,
+              stream: Optional[int] = None, lanczos_v0: Optional[np.ndarray] = None):
+    """xls_subdomain_desc_t for a workload subdomain, plus the arrays it points
+    into (keep them alive until the create call returns)."""
+    x0 = sd.x0 if x0 is None else x0
+    if x0 is None:
+        raise ValueError("start block x0 is required")
+    d = xls_subdomain_desc_t()
+    d.n = (C.c_int32 * 3)(*[int(v) for v in sd.n])
+    d.h = float(sd.h)
+    d.bc = int(sd.bc)
+    d.fd_n0 = int(getattr(sd, "fd_n0", 6))
+    d.origin = (C.c_double * 3)(*[float(v) for v in sd.origin])
+    v = _f64(sd.v, order="C")
+    d.v_eff = _dp(v)
+    atoms = np.ascontiguousarray(sd.atoms, dtype=np.float64).reshape(-1, 3)
+    d.n_atoms = atoms.shape[0]
+    d.atom_xyz = _dp(atoms)
+    ps = (xls_projset_t * max(1, atoms.shape[0]))()
+    for i in range(atoms.shape[0]):
+        ps[i].rc = float(sd.proj[i, 0])
+        ps[i].gauss_width = float(sd.proj[i, 1])
+        for l in range(4):
+            ps[i].gamma[l] = float(sd.proj[i, 2 + l])
+    d.proj = C.cast(ps, C.POINTER(xls_projset_t))
+    d.core_lo = (C.c_int32 * 3)(*sd.core_lo)
+    d.core_hi = (C.c_int32 * 3)(*sd.core_hi)
+    d.global_offset = (C.c_int64 * 3)(*sd.global_offset)
+    d.global_n = (C.c_int64 * 3)(*sd.global_n)
+    d.ns = int(x0.shape[1])
+    X = _f64(x0)
+    d.x0 = _dp(X)
+    lv = lanczos_v0 if lanczos_v0 is not None else getattr(sd, "lanczos_v0", None)
+    if lv is not None:
+        lv = _f64(lv, order="C")
+        d.lanczos_v0 = _dp(lv)
+    d.filter_prec = int(filter_prec)
+    d.stream = C.c_void_p(stream) if stream else None
+    return d, [v, atoms, ps, X, lv]
+
+
+def chefsi_params(degree: int, max_iter: int, bounds_mode: int = XLS_BOUNDS_LANCZOS, lam_lo: float = 0.0,
+                  lam_cut: float = 0.0, lam_max: float = 0.0, resid_tol: float = 0.0, n_gate: int = 0,
+                  lanczos_k: int = 20, gemm_prec: int = XLS_PREC_FP64) -> "xls_chefsi_params_t":
+    return xls_chefsi_params_t(bounds_mode, lam_lo, lam_cut, lam_max, degree, max_iter, resid_tol, n_gate,
+                               lanczos_k, gemm_prec)
+
+
 class Subdomain:
     """Owner of one xls_subdomain_t handle (xls_subdomain_create / _destroy)."""
 
     def __init__(self, sd, filter_prec: int = XLS_PREC_FP64, x0: Optional[np.ndarray] = None,
                  stream: Optional[int] = None, lanczos_v0: Optional[np.ndarray] = None):
-        x0 = sd.x0 if x0 is None else x0
-        if x0 is None:
-            raise ValueError("start block x0 is required")
-        self.n = tuple(int(v) for v in sd.n)
-        self.nd = int(np.prod(self.n))
-        self.ns = int(x0.shape[1])
-        self._keep = []
-        d = xls_subdomain_desc_t()
-        d.n = (C.c_int32 * 3)(*self.n)
-        d.h = float(sd.h)
-        d.bc = int(sd.bc)
-        d.fd_n0 = int(getattr(sd, "fd_n0", 6))
-        d.origin = (C.c_double * 3)(*[float(v) for v in sd.origin])
-        v = _f64(sd.v, order="C")
-        d.v_eff = _dp(v)
-        atoms = np.ascontiguousarray(sd.atoms, dtype=np.float64).reshape(-1, 3)
-        d.n_atoms = atoms.shape[0]
-        d.atom_xyz = _dp(atoms)
-        ps = (xls_projset_t * max(1, atoms.shape[0]))()
-        for i in range(atoms.shape[0]):
-            ps[i].rc = float(sd.proj[i, 0])
-            ps[i].gauss_width = float(sd.proj[i, 1])
-            for l in range(4):
-                ps[i].gamma[l] = float(sd.proj[i, 2 + l])
-        d.proj = C.cast(ps, C.POINTER(xls_projset_t))
-        d.core_lo = (C.c_int32 * 3)(*sd.core_lo)
-        d.core_hi = (C.c_int32 * 3)(*sd.core_hi)
-        d.global_offset = (C.c_int64 * 3)(*sd.global_offset)
-        d.global_n = (C.c_int64 * 3)(*sd.global_n)
-        d.ns = self.ns
-        X = _f64(x0)
-        d.x0 = _dp(X)
-        lv = lanczos_v0 if lanczos_v0 is not None else getattr(sd, "lanczos_v0", None)
-        if lv is not None:
-            lv = _f64(lv, order="C")
-            d.lanczos_v0 = _dp(lv)
-        d.filter_prec = int(filter_prec)
-        d.stream = C.c_void_p(stream) if stream else None
-        self._keep = [v, atoms, ps, X, lv]
+        d, keep = make_desc(sd, filter_prec, x0, stream, lanczos_v0)
         h = C.c_void_p()
         _check(lib().xls_subdomain_create(C.byref(d), C.byref(h)))
+        del keep
         self._h = h
-        self._keep = []
-        self.prec = int(filter_prec)
+        self._borrowed = False
+        self._set_shape(sd.n, d.ns, filter_prec)
+
+    def _set_shape(self, n, ns, prec):
+        self.n = tuple(int(v) for v in n)
+        self.nd = int(np.prod(self.n))
+        self.ns = int(ns)
+        self.prec = int(prec)
+
+    @classmethod
+    def _borrow(cls, handle: C.c_void_p, n, ns, prec) -> "Subdomain":
+        self = cls.__new__(cls)
+        self._h = handle
+        self._borrowed = True
+        self._set_shape(n, ns, prec)
+        return self
 
     # lifetime
     def close(self):
-        if getattr(self, "_h", None) is not None and self._h.value:
+        if getattr(self, "_h", None) is not None and self._h.value and not getattr(self, "_borrowed", False):
             lib().xls_subdomain_destroy(self._h)
-            self._h = None
+        self._h = None
 
     def __del__(self):
         try:
@@ -203,8 +231,8 @@ class Subdomain:
                         lam_lo: float = 0.0, lam_cut: float = 0.0, lam_max: float = 0.0,
                         resid_tol: float = 0.0, n_gate: int = 0, lanczos_k: int = 20,
                         gemm_prec: int = XLS_PREC_FP64):
-        p = xls_chefsi_params_t(bounds_mode, lam_lo, lam_cut, lam_max, degree, max_iter, resid_tol,
-                                n_gate, lanczos_k, gemm_prec)
+        p = chefsi_params(degree, max_iter, bounds_mode, lam_lo, lam_cut, lam_max, resid_tol, n_gate,
+                          lanczos_k, gemm_prec)
         ritz = np.zeros(self.ns)
         resid = np.zeros(self.ns)
         it = C.c_int32(0)
@@ -292,3 +320,85 @@ class Subdomain:
         n = _check(lib().xls_get_stage_times(self._h, _dp(ms), cnt.ctypes.data_as(C.POINTER(C.c_int64)),
                                              C.c_int32(8)))
         return ms[:n], int(cnt[0])
+
+
+class Batch:
+    """Owner of one xls_batch_t (xls_batch_create / _destroy): many subdomains
+    advanced together."""
+
+    def __init__(self, sds, filter_prec: int = XLS_PREC_FP32, x0s=None):
+        x0s = [None] * len(sds) if x0s is None else x0s
+        descs = (xls_subdomain_desc_t * len(sds))()
+        keep = []
+        for i, (sd, x0) in enumerate(zip(sds, x0s)):
+            d, k = make_desc(sd, filter_prec, x0)
+            descs[i] = d
+            keep.append(k)
+        h = C.c_void_p()
+        _check(lib().xls_batch_create(C.c_int32(len(sds)), descs, C.byref(h)))
+        del keep
+        self._h = h
+        self.prec = int(filter_prec)
+        self.shapes = [(tuple(int(v) for v in sd.n), int(descs[i].ns)) for i, sd in enumerate(sds)]
+        self.n = len(sds)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().xls_batch_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def xls_batch_chefsi(self, params, use_graph: bool = True):
+        """params: list of xls_chefsi_params_t (chefsi_params(...)), one per subdomain.
+        Returns (ritz list, resid list, iters, status)."""
+        P = (xls_chefsi_params_t * self.n)(*params)
+        tot = sum(ns for _, ns in self.shapes)
+        ritz = np.zeros(tot)
+        resid = np.zeros(tot)
+        iters = np.zeros(self.n, dtype=np.int32)
+        status = np.zeros(self.n, dtype=np.int32)
+        _check(lib().xls_batch_chefsi(self._h, P, _dp(ritz), _dp(resid),
+                                      iters.ctypes.data_as(C.POINTER(C.c_int32)),
+                                      status.ctypes.data_as(C.POINTER(C.c_int32)), C.c_int32(1 if use_graph else 0)))
+        off = np.cumsum([0] + [ns for _, ns in self.shapes])
+        return ([ritz[off[i]:off[i + 1]] for i in range(self.n)], [resid[off[i]:off[i + 1]] for i in range(self.n)],
+                iters, status)
+
+    def xls_batch_density(self, mu: float, sigma: float):
+        nds = [int(np.prod(n)) for n, _ in self.shapes]
+        rho = np.zeros(sum(nds))
+        c = np.zeros(sum(ns for _, ns in self.shapes))
+        _check(lib().xls_batch_density(self._h, C.c_double(mu), C.c_double(sigma), _dp(rho), _dp(c)))
+        ro = np.cumsum([0] + nds)
+        co = np.cumsum([0] + [ns for _, ns in self.shapes])
+        return [rho[ro[i]:ro[i + 1]] for i in range(self.n)], [c[co[i]:co[i + 1]] for i in range(self.n)]
+
+    def xls_batch_subdomain(self, i: int) -> Subdomain:
+        h = C.c_void_p()
+        _check(lib().xls_batch_subdomain(self._h, C.c_int32(i), C.byref(h)))
+        n, ns = self.shapes[i]
+        return Subdomain._borrow(h, n, ns, self.prec)
+
+    def xls_batch_tune(self, cache_path: Optional[str] = None):
+        tuned = C.c_int32(0)
+        best = C.c_double(0.0)
+        path = cache_path.encode() if cache_path else None
+        _check(lib().xls_batch_tune(self._h, C.c_char_p(path), C.byref(tuned), C.byref(best)))
+        return int(tuned.value), float(best.value)
+
+    def xls_batch_stats(self):
+        out = np.zeros(5)
+        _check(lib().xls_batch_stats(self._h, _dp(out), C.c_int32(5)))
+        return {"iterations": int(out[0]), "captures": int(out[1]), "replays": int(out[2]),
+                "iter_ms": float(out[3]), "last_iter_ms": float(out[4])}

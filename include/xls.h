@@ -95,9 +95,14 @@ typedef struct xls_subdomain_s* xls_subdomain_t;
  * XLS_BOUNDS_LANCZOS runs lanczos_k Lanczos steps once per handle and takes
  * a0 = theta_min, lam_max = theta_max + |beta_k|, lam_cut = a0 + 0.1(lam_max - a0);
  * XLS_BOUNDS_LEARNED takes lam_max and lam_cut from the caller (the learned
- * model's prediction) and a0 from Lanczos' theta_min.  Later iterations of the
- * same call use a0 = lambda_1 and lam_cut = lambda_ns of the previous
- * iteration, lam_max unchanged. */
+ * model's prediction, xls_mlp_predict) and for a0 the rigorous lower bound
+ * min V + sum of the negative projector coefficients (-1/2 Lap is positive
+ * semi-definite), so no Lanczos run is needed; with fallback_tol > 0, if the
+ * largest gated residual after max_iter iterations exceeds fallback_tol the
+ * call restarts from the same start block with Lanczos bounds and
+ * fallback_degree (<= 0: degree).  Later iterations of the same call use
+ * a0 = lambda_1 and lam_cut = lambda_ns of the previous iteration, lam_max
+ * unchanged. */
 typedef struct {
   int32_t bounds_mode;
   double lam_lo, lam_cut, lam_max;
@@ -107,6 +112,8 @@ typedef struct {
   int32_t n_gate;          /* gated states (lowest n_gate); <= 0: floor(ns/1.1)     */
   int32_t lanczos_k;       /* Lanczos steps (<= 0: 20)                              */
   int32_t gemm_prec;       /* XLS_PREC_*: projection and rotation GEMMs             */
+  double fallback_tol;     /* XLS_BOUNDS_LEARNED only: Lanczos restart above this (0: none) */
+  int32_t fallback_degree; /* degree of the Lanczos restart (<= 0: degree)          */
 } xls_chefsi_params_t;
 
 /* ---- core calls ---------------------------------------------------------- */
@@ -209,6 +216,52 @@ int xls_subdomain_tune(xls_subdomain_t s, int32_t prec, int32_t block, int32_t t
 int xls_set_profiling(int32_t on);
 int xls_get_stage_times(xls_subdomain_t s, double* ms, int64_t* counts, int32_t cap);
 
+/* Work counters of the handle's last xls_chefsi_step: out[0] H applications
+ * (one per vector: Lanczos steps, m*ns per filter, ns for H Psi_f and for the
+ * residual), out[1] 1 if the learned-bounds run fell back to Lanczos,
+ * out[2] CheFSI iterations including a fallback run.  Returns values written. */
+int xls_subdomain_counters(xls_subdomain_t s, int64_t* out, int32_t cap);
+
+/* ---- Learned filter bounds: a small MLP on the GPU ---------------------------
+ * The paper leaves the source of the filter bounds open (Sec. V-A.3 defines the
+ * filter by its centre and half-width only).  The model maps 64 features of a
+ * subdomain (xls_subdomain_features) to (lam_max, lam_cut, degree); it is trained
+ * by FP32 forward, backward and Adam kernels on labels the method itself
+ * produces, and evaluated with bfloat16 weights and activations.
+ * sizes[nsizes]: layer widths, sizes[0] <= 64 inputs, last <= 8 outputs, each
+ * <= 256, at most 4 layers; ReLU between layers; parameters per layer: W
+ * (fan_in x fan_out, row-major) then b.  params (NULL: zeros) has
+ * xls_mlp_get_params(m, NULL, 0) floats.
+ * xls_mlp_forward / xls_mlp_gradient: FP32, raw inputs and targets, B rows
+ *   (row-major B x in, B x out); gradient of the mean squared error over all
+ *   B*out entries, loss optional.
+ * xls_mlp_train: Adam (lr, beta 0.9/0.999, eps 1e-8) over minibatches
+ *   idx[offsets[s] .. offsets[s+1]) of the n training rows, s < nsteps; the
+ *   Adam state persists across calls (reset by xls_mlp_set_params); losses[s]
+ *   (may be NULL) receives each minibatch's loss before its update.
+ * xls_mlp_set_norm: input standardisation (x - in_mean)/in_std and output
+ *   de-standardisation y * out_std + out_mean used by xls_mlp_predict.
+ * xls_mlp_predict: bfloat16 inference on B feature rows (f64[B x in]) ->
+ *   out f64[B x outputs]. */
+typedef struct xls_mlp_s* xls_mlp_t;
+int xls_mlp_create(int32_t nsizes, const int32_t* sizes, const float* params, xls_mlp_t* out);
+void xls_mlp_destroy(xls_mlp_t m);
+int xls_mlp_get_params(xls_mlp_t m, float* params, int64_t n);
+int xls_mlp_set_params(xls_mlp_t m, const float* params, int64_t n);
+int xls_mlp_set_norm(xls_mlp_t m, const float* in_mean, const float* in_std, const double* out_mean,
+                     const double* out_std);
+int xls_mlp_forward(xls_mlp_t m, const float* X, int32_t B, float* Y);
+int xls_mlp_gradient(xls_mlp_t m, const float* X, const float* T, int32_t B, float* grads, float* loss);
+int xls_mlp_train(xls_mlp_t m, const float* X, const float* T, int32_t n, const int32_t* idx,
+                  const int32_t* offsets, int32_t nsteps, float lr, float* losses);
+int xls_mlp_predict(xls_mlp_t m, const double* features, int32_t B, double* out);
+/* Features of a subdomain (f64[64], zero-padded): [0,32) histogram of V over
+ * [min V, max V] (fractions, numpy.histogram bin rule), then atom count, n[0],
+ * n[1], n[2], h, buffer width min(core_lo)*h, min V, max V, mean V, std V, ns,
+ * projector count, sum |gamma|, core fraction, largest eigenvalue of -1/2 Lap
+ * (periodic closed form).  V statistics are computed on the device. */
+int xls_subdomain_features(xls_subdomain_t s, double* f);
+
 /* ---- Batch engine: many uneven subdomains on one GPU -----------------------
  * The paper advances the subsystems assigned to a process independently
  * (Sec. V-B); a batch holds n of them on one device and advances them
@@ -221,8 +274,8 @@ int xls_get_stage_times(xls_subdomain_t s, double* ms, int64_t* counts, int32_t 
  *
  * xls_batch_create: descs[n] as for xls_subdomain_create (all with the same
  *   filter_prec; their stream fields are ignored).  Host arrays are copied.
- * xls_batch_chefsi: per_sub[n] parameters (bounds_mode GIVEN or LANCZOS;
- *   degree <= 256); runs each subdomain until its gated residual is <=
+ * xls_batch_chefsi: per_sub[n] parameters (degree <= 256; LEARNED without
+ *   the fallback, fallback_tol must be 0); runs each subdomain until its gated residual is <=
  *   resid_tol, its max_iter is reached or its bounds degenerate.  Outputs are
  *   concatenated in subdomain order: ritz_concat and resid_concat hold
  *   sum(ns_i) values; iters[n] and status[n] may be NULL.  status[i] is

@@ -82,6 +82,7 @@ bool finite_all(const double* p, int64_t n) {
 // out = H y in the storage precision.
 template <typename TS>
 void apply_H(xls_subdomain_s* s, const TS* y, TS* out, int ncols, TS* alpha) {
+  s->happly += ncols;
   const auto& op = op_of<TS>(s);
   launch_proj_forward<TS, TS>(op, y, s->ld, ncols, alpha, s->st);
   launch_stencil<TS, TS>(kApply, op, y, s->ld, ncols, alpha, out, nullptr, 1.0, 0.0, 0.0, nullptr, nullptr,
@@ -101,6 +102,7 @@ void filter_block(xls_subdomain_s* s, int m, double a0, double lc, double lmax) 
   const auto& cfg = cfg_of<TS>(s);
   TS* alpha = static_cast<TS*>(s->alpha);
   const bool prof = profiling_on();
+  s->happly += static_cast<int64_t>(m) * s->ns;
   if (prof && static_cast<int>(s->fev.size()) < 2 * m) {
     for (auto ev : s->fev) (void)hipEventDestroy(ev);
     s->fev.assign(2 * m, nullptr);
@@ -161,6 +163,7 @@ void rotate_block(xls_subdomain_s* s, int gprec, const double* Ydev) {
 // FP64 residual norms of the current block against lam (device).
 template <typename TS>
 void residual_block(xls_subdomain_s* s, const double* lam_dev, double* resid_dev) {
+  s->happly += s->ns;
   TS* Bc = B<TS>(s, s->cur);
   launch_proj_forward<TS, double>(s->op64, Bc, s->ld, s->ns, s->alpha64, s->st);
   StencilLaunch cfg = s->cfg64;
@@ -280,46 +283,17 @@ void validate_desc(const xls_subdomain_desc_t* d) {
     fail(XLS_ERR_INVALID_ARG, "filter_prec must be FP64 or FP32");
 }
 
+// CheFSI iterations from the handle's current block with first-iteration
+// bounds (a0, lc, lmax); returns the iterations run.
 template <typename TS>
-int chefsi_impl(xls_subdomain_s* s, const xls_chefsi_params_t* p, double* ritz, double* resid,
-                int32_t* iters_done) {
-  if (p->degree < 1 || p->max_iter < 1) fail(XLS_ERR_INVALID_ARG, "degree and max_iter must be >= 1");
-  const int gprec = p->gemm_prec;
-  if (gprec < XLS_PREC_FP64 || gprec > XLS_PREC_BF16X3) fail(XLS_ERR_INVALID_ARG, "bad gemm_prec");
-  if (std::is_same<TS, double>::value && gprec != XLS_PREC_FP64)
-    fail(XLS_ERR_INVALID_ARG, "FP64 handles run FP64 GEMMs");
+int chefsi_loop(xls_subdomain_s* s, const xls_chefsi_params_t* p, int gprec, int gate, int degree, double a0,
+                double lc, double lmax, std::vector<double>& hl, std::vector<double>& hr) {
   const int ns = s->ns;
-  const int gate = p->n_gate > 0 ? std::min(p->n_gate, ns) : std::max(1, static_cast<int>(std::floor(ns / 1.1 + 1e-9)));
-  double a0, lc, lmax;
-  if (p->bounds_mode == XLS_BOUNDS_GIVEN) {
-    a0 = p->lam_lo;
-    lc = p->lam_cut;
-    lmax = p->lam_max;
-  } else if (p->bounds_mode == XLS_BOUNDS_LANCZOS || p->bounds_mode == XLS_BOUNDS_LEARNED) {
-    const int k = p->lanczos_k > 0 ? p->lanczos_k : 20;
-    if (!s->have_lanczos || s->lz_k != k) lanczos_run<TS>(s, std::min(k, 60));
-    a0 = s->lz_lo;
-    if (p->bounds_mode == XLS_BOUNDS_LANCZOS) {
-      lmax = s->lz_up;
-      lc = a0 + 0.1 * (lmax - a0);
-    } else {
-      lmax = p->lam_max;
-      lc = p->lam_cut;
-    }
-  } else {
-    fail(XLS_ERR_INVALID_ARG, "unknown bounds_mode");
-  }
-  if (!(a0 < lc && lc < lmax) || !std::isfinite(a0) || !std::isfinite(lmax))
-    fail(XLS_ERR_INVALID_ARG, "bounds must satisfy a0 < lam_cut < lam_max");
-  std::vector<double> hl(ns), hr(ns);
   int it = 0;
-  s->stage_ms.assign(8, 0.0);
-  s->filter_launches = 0;
-  s->filter_kernel_ms = 0.0;
   for (; it < p->max_iter;) {
-    StageTimer tm(g_profiling, s->st);
+    StageTimer tm(profiling_on(), s->st);
     tm.mark();
-    filter_block<TS>(s, p->degree, a0, lc, lmax);
+    filter_block<TS>(s, degree, a0, lc, lmax);
     tm.mark();
     {
       TS* Bc = B<TS>(s, s->cur);
@@ -346,7 +320,7 @@ int chefsi_impl(xls_subdomain_s* s, const xls_chefsi_params_t* p, double* ritz, 
     XLS_HIP(hipMemcpyAsync(hl.data(), s->lam_dev, ns * 8, hipMemcpyDeviceToHost, s->st));
     XLS_HIP(hipMemcpyAsync(hr.data(), s->resid_dev, ns * 8, hipMemcpyDeviceToHost, s->st));
     XLS_HIP(hipStreamSynchronize(s->st));
-    if (g_profiling) {
+    if (profiling_on()) {
       for (int k = 0; k < 6; ++k) s->stage_ms[k] += tm.ms(k, k + 1);
       s->stage_ms[6] += tm.ms(0, 6);
     }
@@ -362,6 +336,74 @@ int chefsi_impl(xls_subdomain_s* s, const xls_chefsi_params_t* p, double* ritz, 
       if (mx <= p->resid_tol) break;
     }
   }
+  return it;
+}
+
+template <typename TS>
+void lanczos_first_bounds(xls_subdomain_s* s, const xls_chefsi_params_t* p, double& a0, double& lc,
+                          double& lmax) {
+  const int k = p->lanczos_k > 0 ? p->lanczos_k : 20;
+  if (!s->have_lanczos || s->lz_k != k) lanczos_run<TS>(s, std::min(k, 60));
+  a0 = s->lz_lo;
+  lmax = s->lz_up;
+  lc = a0 + 0.1 * (lmax - a0);
+}
+
+template <typename TS>
+int chefsi_impl(xls_subdomain_s* s, const xls_chefsi_params_t* p, double* ritz, double* resid,
+                int32_t* iters_done) {
+  if (p->degree < 1 || p->max_iter < 1) fail(XLS_ERR_INVALID_ARG, "degree and max_iter must be >= 1");
+  const int gprec = p->gemm_prec;
+  if (gprec < XLS_PREC_FP64 || gprec > XLS_PREC_BF16X3) fail(XLS_ERR_INVALID_ARG, "bad gemm_prec");
+  if (std::is_same<TS, double>::value && gprec != XLS_PREC_FP64)
+    fail(XLS_ERR_INVALID_ARG, "FP64 handles run FP64 GEMMs");
+  const int ns = s->ns;
+  const int gate = p->n_gate > 0 ? std::min(p->n_gate, ns) : std::max(1, static_cast<int>(std::floor(ns / 1.1 + 1e-9)));
+  s->happly = 0;
+  s->last_fallback = 0;
+  s->last_iters = 0;
+  double a0, lc, lmax;
+  const bool learned = p->bounds_mode == XLS_BOUNDS_LEARNED;
+  if (p->bounds_mode == XLS_BOUNDS_GIVEN) {
+    a0 = p->lam_lo;
+    lc = p->lam_cut;
+    lmax = p->lam_max;
+  } else if (p->bounds_mode == XLS_BOUNDS_LANCZOS) {
+    lanczos_first_bounds<TS>(s, p, a0, lc, lmax);
+  } else if (learned) {
+    a0 = std::min(s->a0_bound, p->lam_cut - 1e-3 * std::fabs(p->lam_max - p->lam_cut));
+    lmax = p->lam_max;
+    lc = p->lam_cut;
+  } else {
+    fail(XLS_ERR_INVALID_ARG, "unknown bounds_mode");
+  }
+  if (!(a0 < lc && lc < lmax) || !std::isfinite(a0) || !std::isfinite(lmax))
+    fail(XLS_ERR_INVALID_ARG, "bounds must satisfy a0 < lam_cut < lam_max");
+  const bool fallback = learned && p->fallback_tol > 0;
+  const int cur0 = s->cur;
+  const size_t bbytes = static_cast<size_t>(s->ld) * ns * sizeof(TS);
+  if (fallback) {
+    if (!s->backup) s->backup = dalloc<TS>(static_cast<size_t>(s->ld) * ns);
+    XLS_HIP(hipMemcpyAsync(s->backup, B<TS>(s, cur0), bbytes, hipMemcpyDeviceToDevice, s->st));
+  }
+  std::vector<double> hl(ns), hr(ns);
+  s->stage_ms.assign(8, 0.0);
+  s->filter_launches = 0;
+  s->filter_kernel_ms = 0.0;
+  int it = chefsi_loop<TS>(s, p, gprec, gate, p->degree, a0, lc, lmax, hl, hr);
+  if (fallback) {
+    double mx = 0;
+    for (int k = 0; k < gate; ++k) mx = std::max(mx, hr[k]);
+    if (!(mx <= p->fallback_tol)) {
+      XLS_HIP(hipMemcpyAsync(B<TS>(s, cur0), s->backup, bbytes, hipMemcpyDeviceToDevice, s->st));
+      s->cur = cur0;
+      lanczos_first_bounds<TS>(s, p, a0, lc, lmax);
+      const int deg = p->fallback_degree > 0 ? p->fallback_degree : p->degree;
+      it += chefsi_loop<TS>(s, p, gprec, gate, deg, a0, lc, lmax, hl, hr);
+      s->last_fallback = 1;
+    }
+  }
+  s->last_iters = it;
   std::memcpy(ritz, hl.data(), ns * 8);
   std::memcpy(resid, hr.data(), ns * 8);
   if (iters_done) *iters_done = it;
@@ -424,7 +466,11 @@ int xls_subdomain_create(const xls_subdomain_desc_t* d, xls_subdomain_t* out) {
     validate_desc(d);
     auto* s = new xls_subdomain_s();
     try {
-      for (int a = 0; a < 3; ++a) s->n[a] = d->n[a];
+      for (int a = 0; a < 3; ++a) {
+        s->n[a] = d->n[a];
+        s->core_lo[a] = d->core_lo[a];
+        s->core_hi[a] = d->core_hi[a];
+      }
       s->h = d->h;
       s->bc = d->bc;
       s->prec = d->filter_prec;
@@ -438,6 +484,14 @@ int xls_subdomain_create(const xls_subdomain_desc_t* d, xls_subdomain_t* out) {
         s->own_stream = true;
       }
       build_setup(*d, s->tab);
+      {  // lambda_1 >= min V + sum of negative projector coefficients (-1/2 Lap >= 0)
+        double vmin = d->v_eff[0];
+        for (int64_t i = 1; i < static_cast<int64_t>(d->n[0]) * d->n[1] * d->n[2]; ++i) vmin = std::min(vmin, d->v_eff[i]);
+        double neg = 0.0;
+        for (int a = 0; a < d->n_atoms; ++a)
+          for (int l = 0; l < 4; ++l) neg += std::min(0.0, d->proj[a].gamma[l]);
+        s->a0_bound = vmin + neg;
+      }
       s->n_atoms = d->n_atoms;
       const int64_t nd = s->nd;
       const size_t total = s->tab.sup_idx.size();
@@ -537,6 +591,16 @@ int xls_chefsi_step(xls_subdomain_t s, const xls_chefsi_params_t* p, double* rit
   return guarded([&]() -> int {
     if (!s || !p || !ritz || !resid) fail(XLS_ERR_INVALID_ARG, "NULL argument");
     return by_prec(s, [&](auto tag) { return chefsi_impl<decltype(tag)>(s, p, ritz, resid, iters_done); });
+  });
+}
+
+int xls_subdomain_counters(xls_subdomain_t s, int64_t* out, int32_t cap) {
+  return guarded([&]() -> int {
+    if (!s || !out || cap < 1) fail(XLS_ERR_INVALID_ARG, "bad argument");
+    const int64_t v[3] = {s->happly, s->last_fallback, s->last_iters};
+    const int k = std::min(cap, 3);
+    for (int i = 0; i < k; ++i) out[i] = v[i];
+    return k;
   });
 }
 

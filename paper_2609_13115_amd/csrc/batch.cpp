@@ -256,8 +256,13 @@ void batch_chefsi(xls_batch_s* b, const xls_chefsi_params_t* P, int use_graph) {
       a0 = s->lz_lo;
       lmax = s->lz_up;
       lc = a0 + 0.1 * (lmax - a0);
+    } else if (p.bounds_mode == XLS_BOUNDS_LEARNED) {
+      if (p.fallback_tol > 0) fail(XLS_ERR_INVALID_ARG, "batches do not run the Lanczos fallback");
+      lmax = p.lam_max;
+      lc = p.lam_cut;
+      a0 = std::min(s->a0_bound, lc - 1e-3 * std::fabs(lmax - lc));
     } else {
-      fail(XLS_ERR_INVALID_ARG, "batch bounds_mode must be GIVEN or LANCZOS");
+      fail(XLS_ERR_INVALID_ARG, "unknown bounds_mode");
     }
     if (!(a0 < lc && lc < lmax) || !std::isfinite(a0) || !std::isfinite(lmax))
       fail(XLS_ERR_INVALID_ARG, "bounds must satisfy a0 < lam_cut < lam_max");
@@ -270,6 +275,9 @@ void batch_chefsi(xls_batch_s* b, const xls_chefsi_params_t* P, int use_graph) {
                            : std::max(1, static_cast<int>(std::floor(s->ns / 1.1 + 1e-9)));
     ss.iters = 0;
     ss.status = XLS_OK;
+    s->happly = 0;
+    s->last_fallback = 0;
+    s->last_iters = 0;
     ss.active = true;
     launch_filter_coef(nullptr, s->ns, a0, lc, lmax, p.degree, b->coef[i], b->flags + i, s->st);
   }
@@ -306,6 +314,8 @@ void batch_chefsi(xls_batch_s* b, const xls_chefsi_params_t* P, int use_graph) {
       SubState& ss = b->st[i];
       s->cur = (s->cur + ss.degree + 1) & 1;
       ++ss.iters;
+      s->last_iters = ss.iters;
+      s->happly += static_cast<int64_t>(ss.degree + 1) * s->ns;  // filter + residual (H Psi_f counted by apply_H)
       s->ritz = hl[i];
       s->have_ritz = true;
       if (hspd[i]) {

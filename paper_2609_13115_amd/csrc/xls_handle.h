@@ -20,6 +20,8 @@ using xls::StencilLaunch;
 
 struct xls_subdomain_s {
   int n[3] = {0, 0, 0};
+  int core_lo[3] = {0, 0, 0}, core_hi[3] = {0, 0, 0};
+  double a0_bound = 0.0;  // rigorous lower bound of lambda_1 (learned bounds)
   double h = 0;
   int bc = 0;
   int prec = XLS_PREC_FP64;
@@ -76,11 +78,16 @@ struct xls_subdomain_s {
   int64_t filter_launches = 0;
   double filter_kernel_ms = 0.0;  // sum over fused-filter stencil launches (profiling on)
   std::vector<hipEvent_t> fev;
+  // work counters of the last chefsi step
+  int64_t happly = 0;
+  int last_fallback = 0;
+  int last_iters = 0;
+  void* backup = nullptr;  // start block kept for a learned-bounds fallback
 
   ~xls_subdomain_s() {
     void* ps[] = {v64, v32, val64, val32, rev_pk, rev_aoff, rev_val64, rev_val32, sup_off, sup_idx, gamma, mask,
                   blk[0], blk[1], alpha, alpha64, partial, lam_dev, resid_dev, Mdev, Hsdev, Ydev, bwork,
-                  gwork, vsmall, rho_dev, cpart, gocc, lz};
+                  gwork, vsmall, rho_dev, cpart, gocc, lz, backup};
     for (void* p : ps) xls::dfree(p);
     for (auto e : fev) (void)hipEventDestroy(e);
     xls::dense_free(dw);

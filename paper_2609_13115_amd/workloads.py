@@ -337,6 +337,84 @@ def batch_subdomains(count: int = 256, key_cfg: int = 3, with_x0: bool = False,
     return gs, subs, degs
 
 
+def two_phase_system(key: Tuple[int, ...] = (SEED_BASE + 5000 * 1, 0), n_xy: int = 34,
+                     interface: float = 5.0, min_dist: float = 3.0) -> GlobalSystem:
+    """Diamond Si (z < Lz/2) joined to a bcc Li-like phase (z >= Lz/2) in a
+    periodic 2x2x4 Si-cell box; atoms within `interface` bohr of either
+    interface plane are kept with probability 1/2 and displaced by U[-1, 1]
+    bohr per axis, all others by U[-0.1, 0.1]; sites closer than `min_dist`
+    to an already kept site are dropped.  The bcc constant is Lx/3 = 6.84
+    bohr (6.6 stretched so that the lattice tiles the periodic cell).
+    Depths: Si -3 Ha, Li -1 Ha (both +/- 5 %); gamma_s/gamma_p ~ U[0.5, 1.5]/
+    U[0.2, 0.8] Ha for Si and U[0.2, 0.6]/U[0.1, 0.3] Ha for Li."""
+    rng = _rng(*key, 1)
+    Lx = 2 * SI_A
+    Lz = 4 * SI_A
+    a_li = Lx / 3.0
+    si = np.array([[i, j, k] for k in range(2) for j in range(2) for i in range(2)])
+    si = ((si[:, None, :] + DIAMOND_BASIS[None]).reshape(-1, 3)) * SI_A
+    li = np.array([[i, j, k] for k in range(3) for j in range(3) for i in range(3)])
+    li = ((li[:, None, :] + BCC_BASIS[None]).reshape(-1, 3)) * a_li
+    li[:, 2] += Lz / 2
+    sites = np.concatenate([si, li])
+    kind = np.concatenate([np.zeros(len(si), dtype=np.int64), np.ones(len(li), dtype=np.int64)])
+    z = sites[:, 2]
+    near = (np.abs(z - Lz / 2) < interface) | (z < interface) | (z > Lz - interface)
+    keep = ~near | (rng.uniform(size=len(sites)) < 0.5)
+    disp = np.where(near[:, None], 1.0, 0.1)
+    sites = sites + rng.uniform(-1.0, 1.0, size=sites.shape) * disp
+    cell = np.array([Lx, Lx, Lz])
+    order = rng.permutation(len(sites))
+    kept = []
+    for i in order:
+        if not keep[i]:
+            continue
+        ok = True
+        for j in kept:
+            d = sites[i] - sites[j]
+            d -= cell * np.round(d / cell)
+            if np.dot(d, d) < min_dist ** 2:
+                ok = False
+                break
+        if ok:
+            kept.append(i)
+    kept = np.sort(np.asarray(kept))
+    atoms = np.mod(sites[kept], cell)
+    kind = kind[kept]
+    n = len(atoms)
+    depth = np.where(kind == 0, -3.0, -1.0) * (1.0 + 0.05 * rng.uniform(-1.0, 1.0, size=n))
+    gamma = np.empty((n, 4))
+    gs = np.where(kind == 0, rng.uniform(0.5, 1.5, size=n), rng.uniform(0.2, 0.6, size=n))
+    gp = np.where(kind == 0, rng.uniform(0.2, 0.8, size=n), rng.uniform(0.1, 0.3, size=n))
+    gamma[:, 0] = gs
+    gamma[:, 1:] = gp[:, None]
+    zval = np.where(kind == 0, 4.0, 1.0)
+    return GlobalSystem(cell, (n_xy, n_xy, 2 * n_xy), atoms, depth, gamma, zval, key)
+
+
+def learned_bounds_subdomains(count: int, index0: int = 0, gs: Optional[GlobalSystem] = None,
+                              nmin: int = 14, nmax: int = 22) -> Tuple[GlobalSystem, List[Subdomain]]:
+    """Small zero-Dirichlet training boxes at random places of the two-phase
+    system (Si, Li and the interfaces): n ~ U{nmin..nmax} per axis, buffer
+    b ~ U{2..4} points, ns = clamp(ceil(1.1 * electrons in the box / 2), 8, 48)."""
+    gs = two_phase_system() if gs is None else gs
+    subs = []
+    for b in range(index0, index0 + count):
+        rng = _rng(*gs.key, 2, b)
+        n = rng.integers(nmin, nmax + 1, size=3)
+        buf = rng.integers(2, 5, size=3)
+        core = n - 2 * buf
+        start = rng.integers(0, np.asarray(gs.global_n), size=3)
+        sd = gs.subdomain(tuple(int(x) for x in start), core, buf, n, 8, BC_DIRICHLET0, gs.key + (b,),
+                          with_x0=False)
+        sd.ns = int(min(max(math.ceil(1.1 * sd.n_valence / 2.0), 8), 48))
+        sd.name = f"two-phase[{b}] n={tuple(int(x) for x in n)} ns={sd.ns}"
+        sd.x0 = sd.make_x0()
+        sd.lanczos_v0 = sd.make_lanczos_v0()
+        subs.append(sd)
+    return gs, subs
+
+
 def diagonal_spectrum(n: int, key: Tuple[int, ...] = (SEED_BASE + 95000, 0),
                       lo: float = -1.0, hi: float = 10.0) -> np.ndarray:
     """Sorted random diagonal entries for operator-level closed-form checks."""

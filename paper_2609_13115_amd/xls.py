@@ -40,6 +40,9 @@ EXPORTED = [
     "xls_subdomain_tune",
     "xls_batch_create", "xls_batch_chefsi", "xls_batch_density", "xls_batch_subdomain", "xls_batch_tune",
     "xls_batch_stats", "xls_batch_destroy",
+    "xls_subdomain_counters", "xls_subdomain_features", "xls_mlp_create", "xls_mlp_destroy",
+    "xls_mlp_get_params", "xls_mlp_set_params", "xls_mlp_set_norm", "xls_mlp_forward", "xls_mlp_gradient",
+    "xls_mlp_train", "xls_mlp_predict",
 ]
 
 
@@ -71,7 +74,7 @@ class xls_chefsi_params_t(C.Structure):
         ("bounds_mode", C.c_int32), ("lam_lo", C.c_double), ("lam_cut", C.c_double),
         ("lam_max", C.c_double), ("degree", C.c_int32), ("max_iter", C.c_int32),
         ("resid_tol", C.c_double), ("n_gate", C.c_int32), ("lanczos_k", C.c_int32),
-        ("gemm_prec", C.c_int32),
+        ("gemm_prec", C.c_int32), ("fallback_tol", C.c_double), ("fallback_degree", C.c_int32),
     ]
 
 
@@ -88,6 +91,7 @@ def lib() -> C.CDLL:
         L.xls_last_error.restype = C.c_char_p
         L.xls_subdomain_destroy.restype = None
         L.xls_batch_destroy.restype = None
+        L.xls_mlp_destroy.restype = None
         _lib = L
     return _lib
 
@@ -176,9 +180,10 @@ def make_desc(sd, filter_prec: int = XLS_PREC_FP64, x0: Optional[np.ndarray] = N
 
 def chefsi_params(degree: int, max_iter: int, bounds_mode: int = XLS_BOUNDS_LANCZOS, lam_lo: float = 0.0,
                   lam_cut: float = 0.0, lam_max: float = 0.0, resid_tol: float = 0.0, n_gate: int = 0,
-                  lanczos_k: int = 20, gemm_prec: int = XLS_PREC_FP64) -> "xls_chefsi_params_t":
+                  lanczos_k: int = 20, gemm_prec: int = XLS_PREC_FP64, fallback_tol: float = 0.0,
+                  fallback_degree: int = 0) -> "xls_chefsi_params_t":
     return xls_chefsi_params_t(bounds_mode, lam_lo, lam_cut, lam_max, degree, max_iter, resid_tol, n_gate,
-                               lanczos_k, gemm_prec)
+                               lanczos_k, gemm_prec, fallback_tol, fallback_degree)
 
 
 class Subdomain:
@@ -230,9 +235,9 @@ class Subdomain:
     def xls_chefsi_step(self, degree: int, max_iter: int, bounds_mode: int = XLS_BOUNDS_LANCZOS,
                         lam_lo: float = 0.0, lam_cut: float = 0.0, lam_max: float = 0.0,
                         resid_tol: float = 0.0, n_gate: int = 0, lanczos_k: int = 20,
-                        gemm_prec: int = XLS_PREC_FP64):
+                        gemm_prec: int = XLS_PREC_FP64, fallback_tol: float = 0.0, fallback_degree: int = 0):
         p = chefsi_params(degree, max_iter, bounds_mode, lam_lo, lam_cut, lam_max, resid_tol, n_gate,
-                          lanczos_k, gemm_prec)
+                          lanczos_k, gemm_prec, fallback_tol, fallback_degree)
         ritz = np.zeros(self.ns)
         resid = np.zeros(self.ns)
         it = C.c_int32(0)
@@ -313,6 +318,16 @@ class Subdomain:
     def xls_subdomain_tune(self, prec: int, block: int = 512, ty: int = 0, tz: int = 0):
         _check(lib().xls_subdomain_tune(self._h, C.c_int32(prec), C.c_int32(block), C.c_int32(ty),
                                         C.c_int32(tz)))
+
+    def xls_subdomain_features(self) -> np.ndarray:
+        f = np.zeros(64)
+        _check(lib().xls_subdomain_features(self._h, _dp(f)))
+        return f
+
+    def xls_subdomain_counters(self):
+        out = np.zeros(3, dtype=np.int64)
+        _check(lib().xls_subdomain_counters(self._h, out.ctypes.data_as(C.POINTER(C.c_int64)), C.c_int32(3)))
+        return {"h_applies": int(out[0]), "fallback": bool(out[1]), "iterations": int(out[2])}
 
     def xls_get_stage_times(self):
         ms = np.zeros(8)
@@ -402,3 +417,103 @@ class Batch:
         _check(lib().xls_batch_stats(self._h, _dp(out), C.c_int32(5)))
         return {"iterations": int(out[0]), "captures": int(out[1]), "replays": int(out[2]),
                 "iter_ms": float(out[3]), "last_iter_ms": float(out[4])}
+
+
+def _fp(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_float))
+
+
+class Mlp:
+    """Owner of one xls_mlp_t.  Parameters are exchanged as the oracle's list
+    [W1, b1, W2, b2, ...] with W_l of shape (fan_in, fan_out)."""
+
+    def __init__(self, sizes=(64, 128, 128, 3), params=None):
+        self.sizes = tuple(int(v) for v in sizes)
+        sz = (C.c_int32 * len(self.sizes))(*self.sizes)
+        flat = None if params is None else self._flatten(params)
+        h = C.c_void_p()
+        _check(lib().xls_mlp_create(C.c_int32(len(self.sizes)), sz, None if flat is None else _fp(flat),
+                                    C.byref(h)))
+        self._h = h
+        self.nparam = _check(lib().xls_mlp_get_params(self._h, None, C.c_int64(0)))
+
+    def _flatten(self, params) -> np.ndarray:
+        return np.concatenate([np.ascontiguousarray(p, dtype=np.float32).ravel() for p in params])
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().xls_mlp_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def get_params(self):
+        flat = np.zeros(self.nparam, dtype=np.float32)
+        _check(lib().xls_mlp_get_params(self._h, _fp(flat), C.c_int64(flat.size)))
+        out, off = [], 0
+        for a, b in zip(self.sizes[:-1], self.sizes[1:]):
+            out.append(flat[off:off + a * b].reshape(a, b))
+            off += a * b
+            out.append(flat[off:off + b].copy())
+            off += b
+        return out
+
+    def set_params(self, params):
+        flat = self._flatten(params)
+        _check(lib().xls_mlp_set_params(self._h, _fp(flat), C.c_int64(flat.size)))
+
+    def set_norm(self, in_mean, in_std, out_mean, out_std):
+        im = np.ascontiguousarray(in_mean, dtype=np.float32)
+        isd = np.ascontiguousarray(in_std, dtype=np.float32)
+        om = np.ascontiguousarray(out_mean, dtype=np.float64)
+        osd = np.ascontiguousarray(out_std, dtype=np.float64)
+        _check(lib().xls_mlp_set_norm(self._h, _fp(im), _fp(isd), _dp(om), _dp(osd)))
+
+    def forward(self, X: np.ndarray) -> np.ndarray:
+        X = np.ascontiguousarray(X, dtype=np.float32)
+        Y = np.zeros((X.shape[0], self.sizes[-1]), dtype=np.float32)
+        _check(lib().xls_mlp_forward(self._h, _fp(X), C.c_int32(X.shape[0]), _fp(Y)))
+        return Y
+
+    def gradient(self, X: np.ndarray, T: np.ndarray):
+        X = np.ascontiguousarray(X, dtype=np.float32)
+        T = np.ascontiguousarray(T, dtype=np.float32)
+        g = np.zeros(self.nparam, dtype=np.float32)
+        loss = C.c_float(0.0)
+        _check(lib().xls_mlp_gradient(self._h, _fp(X), _fp(T), C.c_int32(X.shape[0]), _fp(g), C.byref(loss)))
+        out, off = [], 0
+        for a, b in zip(self.sizes[:-1], self.sizes[1:]):
+            out.append(g[off:off + a * b].reshape(a, b))
+            off += a * b
+            out.append(g[off:off + b].copy())
+            off += b
+        return out, float(loss.value)
+
+    def train(self, X: np.ndarray, T: np.ndarray, batches, lr: float = 1e-3) -> np.ndarray:
+        X = np.ascontiguousarray(X, dtype=np.float32)
+        T = np.ascontiguousarray(T, dtype=np.float32)
+        idx = np.ascontiguousarray(np.concatenate([np.asarray(b) for b in batches]) if batches else np.zeros(0),
+                                   dtype=np.int32)
+        off = np.ascontiguousarray(np.cumsum([0] + [len(b) for b in batches]), dtype=np.int32)
+        losses = np.zeros(max(1, len(batches)), dtype=np.float32)
+        _check(lib().xls_mlp_train(self._h, _fp(X), _fp(T), C.c_int32(X.shape[0]),
+                                   idx.ctypes.data_as(C.POINTER(C.c_int32)),
+                                   off.ctypes.data_as(C.POINTER(C.c_int32)), C.c_int32(len(batches)),
+                                   C.c_float(lr), _fp(losses)))
+        return losses[:len(batches)]
+
+    def predict(self, F: np.ndarray) -> np.ndarray:
+        F = np.ascontiguousarray(F, dtype=np.float64)
+        out = np.zeros((F.shape[0], self.sizes[-1]))
+        _check(lib().xls_mlp_predict(self._h, _dp(F), C.c_int32(F.shape[0]), _dp(out)))
+        return out

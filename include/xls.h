@@ -214,6 +214,12 @@ int xls_subdomain_tune(xls_subdomain_t s, int32_t prec, int32_t block, int32_t t
  * the fused-filter stencil kernels alone (events around each launch);
  * counts[0] filter launches.  Returns the number of values written. */
 int xls_set_profiling(int32_t on);
+
+/* Graph replay of fixed launch sequences (default on): after one eager call
+ * with the same buffers, the dense FP64 stage of xls_chefsi_step is captured
+ * into a hipGraph and replayed.  Results are identical either way; 0 launches
+ * everything eagerly (tests compare the two). */
+int xls_set_graphs(int32_t on);
 int xls_get_stage_times(xls_subdomain_t s, double* ms, int64_t* counts, int32_t cap);
 
 /* Work counters of the handle's last xls_chefsi_step: out[0] H applications

@@ -18,6 +18,7 @@ namespace xls {
 namespace {
 thread_local std::string g_last_error;
 bool g_profiling = false;
+bool g_graphs = true;
 }  // namespace
 
 void fail(int code, const std::string& msg) { throw Error{code, msg}; }
@@ -68,6 +69,7 @@ namespace xls {
 
 void set_last_error(const std::string& m) { g_last_error = m; }
 bool profiling_on() { return g_profiling; }
+bool graphs_on() { return g_graphs; }
 
 void dfree(void* p) {
   if (p) (void)hipFree(p);
@@ -283,6 +285,32 @@ void validate_desc(const xls_subdomain_desc_t* d) {
     fail(XLS_ERR_INVALID_ARG, "filter_prec must be FP64 or FP32");
 }
 
+// Dense stage of one CheFSI iteration without host synchronisation (the
+// caller checks the positive-definiteness flag after its own sync).  The
+// first call runs eagerly, the second is captured into a hipGraph, and later
+// calls replay it: every buffer and the launch sequence are fixed per handle.
+void dense_stage(xls_subdomain_s* s) {
+  if (graphs_on() && !s->dexec && s->dwarm) {
+    XLS_HIP(hipStreamBeginCapture(s->st, hipStreamCaptureModeThreadLocal));
+    try {
+      (void)dense_geneig(s->dw, s->Hsdev, s->Mdev, s->Ydev, s->st, false);
+    } catch (...) {
+      hipGraph_t dead = nullptr;
+      (void)hipStreamEndCapture(s->st, &dead);
+      if (dead) (void)hipGraphDestroy(dead);
+      throw;
+    }
+    XLS_HIP(hipStreamEndCapture(s->st, &s->dgraph));
+    XLS_HIP(hipGraphInstantiate(&s->dexec, s->dgraph, nullptr, nullptr, 0));
+  }
+  if (graphs_on() && s->dexec) {
+    XLS_HIP(hipGraphLaunch(s->dexec, s->st));
+  } else {
+    (void)dense_geneig(s->dw, s->Hsdev, s->Mdev, s->Ydev, s->st, false);
+    s->dwarm = true;
+  }
+}
+
 // CheFSI iterations from the handle's current block with first-iteration
 // bounds (a0, lc, lmax); returns the iterations run.
 template <typename TS>
@@ -306,20 +334,19 @@ int chefsi_loop(xls_subdomain_s* s, const xls_chefsi_params_t* p, int gprec, int
                   s->st);
     }
     tm.mark();
-    const int rc = dense_geneig(s->dw, s->Hsdev, s->Mdev, s->Ydev, s->st);
-    if (rc != XLS_OK) {
-      fail(rc, rc == XLS_ERR_NOT_SPD ? "overlap matrix M_s is not positive definite"
-                                     : "dense eigensolver did not converge");
-    }
+    dense_stage(s);
     XLS_HIP(hipMemcpyAsync(s->lam_dev, s->dw.lam(), ns * 8, hipMemcpyDeviceToDevice, s->st));
     tm.mark();
     rotate_block<TS>(s, gprec, s->Ydev);
     tm.mark();
     residual_block<TS>(s, s->lam_dev, s->resid_dev);
     tm.mark();
+    int32_t spd_flag = 0;
     XLS_HIP(hipMemcpyAsync(hl.data(), s->lam_dev, ns * 8, hipMemcpyDeviceToHost, s->st));
     XLS_HIP(hipMemcpyAsync(hr.data(), s->resid_dev, ns * 8, hipMemcpyDeviceToHost, s->st));
+    XLS_HIP(hipMemcpyAsync(&spd_flag, s->dw.flag, 4, hipMemcpyDeviceToHost, s->st));
     XLS_HIP(hipStreamSynchronize(s->st));
+    if (spd_flag) fail(XLS_ERR_NOT_SPD, "overlap matrix M_s is not positive definite");
     if (profiling_on()) {
       for (int k = 0; k < 6; ++k) s->stage_ms[k] += tm.ms(k, k + 1);
       s->stage_ms[6] += tm.ms(0, 6);
@@ -454,6 +481,11 @@ auto by_prec(xls_subdomain_s* s, F&& f) {
 extern "C" {
 
 const char* xls_last_error(void) { return g_last_error.c_str(); }
+
+int xls_set_graphs(int32_t on) {
+  g_graphs = on != 0;
+  return XLS_OK;
+}
 
 int xls_set_profiling(int32_t on) {
   g_profiling = on != 0;

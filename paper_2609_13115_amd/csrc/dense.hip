@@ -13,7 +13,7 @@
 //                      update), then owns four trailing columns, applies the
 //                      pending update to them and forms their part of C v
 //   T = S L S^T        split at negligible off-diagonals; eigenvalues by
-//                      Sturm-count bisection (one thread per eigenvalue);
+//                      Sturm-count multisection (one wavefront per eigenvalue);
 //                      eigenvectors by inverse iteration with partial
 //                      pivoting (one workgroup per cluster of close
 //                      eigenvalues, modified Gram-Schmidt inside a cluster)
@@ -364,44 +364,67 @@ __global__ __launch_bounds__(256) void tri_prepare_kernel(const double* __restri
   }
 }
 
-// Eigenvalue slot s: the (s - start)-th smallest eigenvalue of the block that
-// contains row s, by bisection on Sturm counts (LDL^T pivots of T - x I).
-__global__ __launch_bounds__(64) void tri_bisect_kernel(const double* __restrict__ d, const double* __restrict__ ez,
-                                                        const double* __restrict__ e2, const int32_t* __restrict__ bs,
-                                                        const int32_t* __restrict__ be,
-                                                        const double* __restrict__ scal, int n,
-                                                        double* __restrict__ lam, const int32_t* __restrict__ flag) {
+// Eigenvalue slot s (one wavefront): the (s - start)-th smallest eigenvalue of
+// the block that contains row s, by 65-section on Sturm counts (LDL^T pivots
+// of T - x I): each lane counts at one of 64 interior points, and the first
+// lane whose count exceeds the index bounds the new interval, which shrinks
+// 65-fold per pass (about 9 passes to full precision instead of 54 halvings).
+__global__ __launch_bounds__(64) void tri_multisect_kernel(const double* __restrict__ d,
+                                                           const double* __restrict__ ez,
+                                                           const double* __restrict__ e2,
+                                                           const int32_t* __restrict__ bs,
+                                                           const int32_t* __restrict__ be,
+                                                           const double* __restrict__ scal, int n,
+                                                           double* __restrict__ lam,
+                                                           const int32_t* __restrict__ flag) {
+  extern __shared__ double sh[];
   if (*flag) return;
-  const int s = blockIdx.x * 64 + threadIdx.x;
-  if (s >= n) return;
-  const int s0 = bs[s], s1 = be[s], l = s - s0;
+  const int s = blockIdx.x, lane = threadIdx.x;
+  const int s0 = bs[s], s1 = be[s], l = s - s0, m = s1 - s0;
+  double* dd = sh;
+  double* ee = sh + n;
   const double tn = scal[0], pivmin = scal[1];
   double gl = HUGE_VAL, gu = -HUGE_VAL;
-  for (int i = s0; i < s1; ++i) {
-    const double r = (i > s0 ? fabs(ez[i - 1]) : 0.0) + (i + 1 < s1 ? fabs(ez[i]) : 0.0);
+  for (int j = lane; j < m; j += 64) {
+    const int i = s0 + j;
+    dd[j] = d[i];
+    ee[j] = (j + 1 < m) ? e2[i] : 0.0;
+    const double r = (j > 0 ? fabs(ez[i - 1]) : 0.0) + (j + 1 < m ? fabs(ez[i]) : 0.0);
     gl = fmin(gl, d[i] - r);
     gu = fmax(gu, d[i] + r);
   }
+  for (int o = 32; o > 0; o >>= 1) {
+    gl = fmin(gl, __shfl_xor(gl, o, 64));
+    gu = fmax(gu, __shfl_xor(gu, o, 64));
+  }
+  __syncthreads();
   const double atol = 0.5 * kEps * tn;
   double lo = gl - 2.0 * kEps * tn - pivmin, hi = gu + 2.0 * kEps * tn + pivmin;
-  for (int it = 0; it < 256; ++it) {
-    const double mid = 0.5 * (lo + hi);
-    if (hi - lo <= fmax(2.0 * kEps * fmax(fabs(lo), fabs(hi)), atol) || !(mid > lo && mid < hi)) break;
+  for (int pass = 0; pass < 40; ++pass) {
+    if (hi - lo <= fmax(2.0 * kEps * fmax(fabs(lo), fabs(hi)), atol)) break;
+    const double x = lo + (hi - lo) * (static_cast<double>(lane + 1) / 65.0);
     int cnt = 0;
-    double q = d[s0] - mid;
+    double q = dd[0] - x;
     if (fabs(q) < pivmin) q = -pivmin;
     cnt += q < 0.0;
-    for (int i = s0 + 1; i < s1; ++i) {
-      q = (d[i] - mid) - e2[i - 1] / q;
+    for (int j = 1; j < m; ++j) {
+      q = (dd[j] - x) - ee[j - 1] / q;
       if (fabs(q) < pivmin) q = -pivmin;
       cnt += q < 0.0;
     }
-    if (cnt > l)
-      hi = mid;
-    else
-      lo = mid;
+    const uint64_t above = __ballot(cnt > l);
+    const double xprev = __shfl_up(x, 1, 64);
+    if (above == 0) {
+      lo = __shfl(x, 63, 64);
+    } else {
+      const int j = __ffsll(static_cast<unsigned long long>(above)) - 1;  // first lane counting past l
+      const double nlo = (j == 0) ? lo : __shfl(xprev, j, 64);
+      hi = __shfl(x, j, 64);
+      lo = nlo;
+    }
+    if (!(lo < hi)) break;
   }
-  lam[s] = 0.5 * (lo + hi);
+  if (lane == 0) lam[s] = 0.5 * (lo + hi);
 }
 
 // Clusters: a new cluster starts at every block start and wherever the gap to
@@ -596,18 +619,32 @@ __global__ __launch_bounds__(256) void bt_kernel(const double* __restrict__ Z, c
   }
   __syncthreads();
   int par = 0;
-  for (int k = n - 2; k >= 0; --k) {
-    const double t = tau[k];
-    if (t == 0.0) continue;
+  // reflector k's column and tau are loaded one step ahead of their use
+  double vn[kBtRows];
+  double tnext = 0.0;
+  auto load_col = [&](int k) {
     const double* v = Vh + static_cast<int64_t>(k) * n;
+#pragma unroll
+    for (int r = 0; r < kBtRows; ++r) {
+      const int j = tid + 256 * r;
+      vn[r] = (k >= 0 && j > k && j < n) ? v[j] : 0.0;
+    }
+    tnext = k >= 0 ? tau[k] : 0.0;
+  };
+  load_col(n - 2);
+  for (int k = n - 2; k >= 0; --k) {
     double vr[kBtRows];
+#pragma unroll
+    for (int r = 0; r < kBtRows; ++r) vr[r] = vn[r];
+    const double t = tnext;
+    load_col(k - 1);
+    if (t == 0.0) continue;
     double acc[NC];
 #pragma unroll
     for (int cc = 0; cc < NC; ++cc) acc[cc] = 0.0;
 #pragma unroll
     for (int r = 0; r < kBtRows; ++r) {
       const int j = tid + 256 * r;
-      vr[r] = (j > k && j < n) ? v[j] : 0.0;
 #pragma unroll
       for (int cc = 0; cc < NC; ++cc)
         if (j < n) acc[cc] += vr[r] * zs[cc * n + j];
@@ -737,8 +774,8 @@ int dense_geneig(DenseWork& w, const double* Hs, const double* M, double* Y, hip
   // --- tridiagonal eigenproblem ---
   hipLaunchKernelGGL(tri_prepare_kernel, dim3(1), dim3(256), 0, st, w.C0, n, d, e, ez, e2, bs, be, w.scal,
                      w.flag);
-  hipLaunchKernelGGL(tri_bisect_kernel, dim3(nblk(n, 64)), dim3(64), 0, st, d, ez, e2, bs, be, w.scal, n, raw,
-                     w.flag);
+  hipLaunchKernelGGL(tri_multisect_kernel, dim3(n), dim3(64), 2 * static_cast<size_t>(n) * sizeof(double), st, d,
+                     ez, e2, bs, be, w.scal, n, raw, w.flag);
   hipLaunchKernelGGL(tri_cluster_kernel, dim3(1), dim3(256), 0, st, raw, bs, w.scal, n, cstart, ncl, w.flag);
   const size_t inv_smem = 7 * static_cast<size_t>(n) * sizeof(double) + ((static_cast<size_t>(n) + 7) & ~size_t{7});
   set_smem(reinterpret_cast<const void*>(tri_inviter_kernel), inv_smem);

@@ -83,6 +83,10 @@ struct xls_subdomain_s {
   int last_fallback = 0;
   int last_iters = 0;
   void* backup = nullptr;  // start block kept for a learned-bounds fallback
+  // dense stage replayed from a hipGraph (its launch sequence depends on ns only)
+  hipGraph_t dgraph = nullptr;
+  hipGraphExec_t dexec = nullptr;
+  bool dwarm = false;
 
   ~xls_subdomain_s() {
     void* ps[] = {v64, v32, val64, val32, rev_pk, rev_aoff, rev_val64, rev_val32, sup_off, sup_idx, gamma, mask,
@@ -90,6 +94,8 @@ struct xls_subdomain_s {
                   gwork, vsmall, rho_dev, cpart, gocc, lz, backup};
     for (void* p : ps) xls::dfree(p);
     for (auto e : fev) (void)hipEventDestroy(e);
+    if (dexec) (void)hipGraphExecDestroy(dexec);
+    if (dgraph) (void)hipGraphDestroy(dgraph);
     xls::dense_free(dw);
     if (own_stream && st) (void)hipStreamDestroy(st);
   }
@@ -101,6 +107,7 @@ namespace xls {
 
 void set_last_error(const std::string& m);
 bool profiling_on();
+bool graphs_on();
 void dfree(void* p);
 bool finite_all(const double* p, int64_t n);
 

@@ -42,7 +42,7 @@ EXPORTED = [
     "xls_batch_stats", "xls_batch_destroy",
     "xls_subdomain_counters", "xls_subdomain_features", "xls_mlp_create", "xls_mlp_destroy",
     "xls_mlp_get_params", "xls_mlp_set_params", "xls_mlp_set_norm", "xls_mlp_forward", "xls_mlp_gradient",
-    "xls_mlp_train", "xls_mlp_predict",
+    "xls_mlp_train", "xls_mlp_predict", "xls_set_graphs",
 ]
 
 
@@ -115,6 +115,10 @@ def _f64(a, shape=None, order="F") -> np.ndarray:
 
 def xls_set_profiling(on: bool) -> None:
     _check(lib().xls_set_profiling(C.c_int32(1 if on else 0)))
+
+
+def xls_set_graphs(on: bool) -> None:
+    _check(lib().xls_set_graphs(C.c_int32(1 if on else 0)))
 
 
 def xls_dense_geneig(Hs: np.ndarray, M: np.ndarray) -> Tuple[np.ndarray, np.ndarray]:

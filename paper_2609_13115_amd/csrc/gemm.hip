@@ -315,6 +315,326 @@ __global__ void d2f_kernel(const double* __restrict__ s, float* __restrict__ d, 
   if (i < n) d[i] = static_cast<float>(s[i]);
 }
 
+
+// ---------------------------------------------------------------------------
+// Large-tile kernels for the long-K projection and the tall rotation.  Each
+// wavefront holds a 4 x 4 block of 16 x 16 MFMA tiles and reuses its operand
+// fragments across that block; operands arrive through 16-byte global loads
+// staged in registers (the next K slab loads while the current one computes).
+// Used when leading dimensions are multiples of the vector width.
+// ---------------------------------------------------------------------------
+template <int MF>
+struct Frag;
+template <>
+struct Frag<MF_F64> {
+  using t = double;
+  static constexpr int KS = 4;
+  __device__ static t load(const double* h, const double*, int row, int stride, int k, int lane) {
+    return h[row * stride + k + (lane >> 4)];
+  }
+  __device__ static void mma(d4_t& acc, const t& a, const t& b) {
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+  }
+};
+template <>
+struct Frag<MF_F32> {
+  using t = float;
+  static constexpr int KS = 4;
+  __device__ static t load(const float* h, const float*, int row, int stride, int k, int lane) {
+    return h[row * stride + k + (lane >> 4)];
+  }
+  __device__ static void mma(f4_t& acc, const t& a, const t& b) {
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+  }
+};
+template <>
+struct Frag<MF_BF> {
+  struct t {
+    bf8_t h, l;
+  };
+  static constexpr int KS = 32;
+  __device__ static t load(const uint16_t* h, const uint16_t* l, int row, int stride, int k, int lane) {
+    const int o = row * stride + k + 8 * (lane >> 4);
+    return t{*reinterpret_cast<const bf8_t*>(h + o), *reinterpret_cast<const bf8_t*>(l + o)};
+  }
+  __device__ static void mma(f4_t& acc, const t& a, const t& b) {
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.l, b.h, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.h, b.l, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.h, b.h, acc, 0, 0, 0);
+  }
+};
+
+template <int MF>
+struct BigLds {
+  using L = typename Form<MF>::lds_t;
+  static constexpr int BK = (MF == MF_F64) ? 16 : 32;
+  static constexpr int STRIDE = BK + (MF == MF_BF ? 8 : (MF == MF_F64 ? 2 : 4));  // 16-byte aligned rows
+  static constexpr int PARTS = (MF == MF_BF) ? 2 : 1;
+};
+
+// Writes VEC consecutive-k values of row r into the LDS operand (split into
+// bf16 hi/lo for the BF form); values past kend are zero.
+template <int MF, typename TIN, int VEC>
+__device__ __forceinline__ void big_put_row(typename Form<MF>::lds_t* h, typename Form<MF>::lds_t* l, int off,
+                                            const TIN (&v)[VEC]) {
+  if constexpr (MF == MF_BF) {
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+      const float a = static_cast<float>(v[e]);
+      const uint16_t hb = bf16_rne_bits(a);
+      h[off + e] = hb;
+      l[off + e] = bf16_rne_bits(a - bf16_bits_to_f32(hb));
+    }
+  } else {
+    using L = typename Form<MF>::lds_t;
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) h[off + e] = static_cast<L>(v[e]);
+  }
+}
+
+// Partial C = A^T B over one K split, 128 x 128 output tile per workgroup.
+template <typename TIN, int MF>
+__global__ __launch_bounds__(256) void gemm_tn_big_kernel(const TIN* __restrict__ A, int64_t lda,
+                                                          const TIN* __restrict__ B, int64_t ldb, int M,
+                                                          int N, int64_t K, int64_t kchunk, int tm, int tn,
+                                                          int sym, double* __restrict__ P) {
+  using Lc = BigLds<MF>;
+  using L = typename Lc::L;
+  using FR = Frag<MF>;
+  constexpr int T = 128, BK = Lc::BK, ST = Lc::STRIDE;
+  constexpr int VEC = 16 / sizeof(TIN);
+  constexpr int PERCOL = BK / VEC;
+  constexpr int LOADS = T * PERCOL / 256;
+  __shared__ __align__(16) L sm[2 * Lc::PARTS * T * ST];
+  L* xh = sm;
+  L* yh = sm + T * ST;
+  L* xl = (MF == MF_BF) ? sm + 2 * T * ST : nullptr;
+  L* yl = (MF == MF_BF) ? sm + 3 * T * ST : nullptr;
+
+  const uint32_t lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int ntile = sym ? tm * (tm + 1) / 2 : tm * tn;
+  const int split = static_cast<int>(lb / ntile);
+  int tt = static_cast<int>(lb % ntile);
+  int bm, bn;
+  if (sym) {
+    bn = 0;
+    while (tt > bn) {
+      tt -= bn + 1;
+      ++bn;
+    }
+    bm = tt;
+  } else {
+    bm = tt % tm;
+    bn = tt / tm;
+  }
+  const int m0 = bm * T, n0 = bn * T;
+  const int64_t kb0 = static_cast<int64_t>(split) * kchunk;
+  const int64_t kend = min(K, kb0 + kchunk);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave & 1, wc = wave >> 1;
+
+  TIN ra[LOADS][VEC], rb[LOADS][VEC];
+  auto load = [&](int64_t kb) {
+#pragma unroll
+    for (int i = 0; i < LOADS; ++i) {
+      const int l = tid + i * 256;
+      const int c = l / PERCOL, kv = l % PERCOL;
+      const int64_t k = kb + kv * VEC;
+      const bool kin = k < kend;
+      const bool ina = kin && m0 + c < M, inb = kin && n0 + c < N;
+      using V = __attribute__((ext_vector_type(VEC))) TIN;
+      V va{}, vb{};
+      if (ina) va = *reinterpret_cast<const V*>(A + k + static_cast<int64_t>(m0 + c) * lda);
+      if (inb) vb = *reinterpret_cast<const V*>(B + k + static_cast<int64_t>(n0 + c) * ldb);
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) {
+        const bool ke = k + e < kend;
+        ra[i][e] = (ina && ke) ? va[e] : TIN(0);
+        rb[i][e] = (inb && ke) ? vb[e] : TIN(0);
+      }
+    }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int i = 0; i < LOADS; ++i) {
+      const int l = tid + i * 256;
+      const int c = l / PERCOL, kv = l % PERCOL;
+      big_put_row<MF, TIN, VEC>(xh, xl, c * ST + kv * VEC, ra[i]);
+      big_put_row<MF, TIN, VEC>(yh, yl, c * ST + kv * VEC, rb[i]);
+    }
+  };
+
+  typename Form<MF>::acc_t acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = typename Form<MF>::acc_t{};
+
+  load(kb0);
+  for (int64_t kb = kb0; kb < kend; kb += BK) {
+    __syncthreads();
+    store();
+    __syncthreads();
+    if (kb + BK < kend) load(kb + BK);
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += FR::KS) {
+      typename FR::t fa[4], fb[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) fa[i] = FR::load(xh, xl, wr * 64 + i * 16 + (lane & 15), ST, ks, lane);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) fb[j] = FR::load(yh, yl, wc * 64 + j * 16 + (lane & 15), ST, ks, lane);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) FR::mma(acc[i][j], fa[i], fb[j]);
+    }
+  }
+  double* Ps = P + static_cast<int64_t>(split) * M * N;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wr * 64 + i * 16 + Form<MF>::orow(lane, r);
+        const int cl = n0 + wc * 64 + j * 16 + (lane & 15);
+        if (row < M && cl < N) Ps[row + static_cast<int64_t>(cl) * M] = Form<MF>::get(acc[i][j], r);
+      }
+}
+
+// C[M x N] = A[M x K] B[K x N]: 64 rows x 256 columns per workgroup, wave w
+// owns columns 64w .. 64w + 63.  The MFMA x operand is B (rows of the
+// accumulator = columns of C), so each lane's results for one column are
+// rows m .. m + 15 across lanes (coalesced stores).  TB is the B operand as
+// stored: double (FP64), float (FP32) or bf16 hi/lo pairs (BF; Bh/Bl).
+template <typename TIN, typename TB, typename TOUT, int MF>
+__global__ __launch_bounds__(256) void gemm_nn_big_kernel(const TIN* __restrict__ A, int64_t lda,
+                                                          const TB* __restrict__ Bh, const TB* __restrict__ Bl,
+                                                          int64_t ldb, int M, int N, int K, int tnN,
+                                                          TOUT* __restrict__ C, int64_t ldc) {
+  using Lc = BigLds<MF>;
+  using L = typename Lc::L;
+  using FR = Frag<MF>;
+  constexpr int TM = 64, TN = 256, BK = Lc::BK, ST = Lc::STRIDE;
+  constexpr int VA = 16 / sizeof(TIN);                    // A loads along m
+  constexpr int ALOADS = TM * BK / VA / 256;
+  constexpr int VB = 16 / sizeof(TB);                     // B loads along k
+  constexpr int BLOADS = TN * BK / VB / 256;
+  __shared__ __align__(16) L sm[Lc::PARTS * (TM + TN) * ST];
+  L* ah = sm;
+  L* bh = sm + TM * ST;
+  L* al = (MF == MF_BF) ? sm + (TM + TN) * ST : nullptr;
+  L* bl = (MF == MF_BF) ? sm + (TM + TN) * ST + TM * ST : nullptr;
+
+  const uint32_t lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int bn = static_cast<int>(lb % tnN), bm = static_cast<int>(lb / tnN);
+  const int m0 = bm * TM, n0 = bn * TN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+
+  using VAt = __attribute__((ext_vector_type(VA))) TIN;
+  using VBt = __attribute__((ext_vector_type(VB))) TB;
+  VAt ra[ALOADS];
+  VBt rbh[BLOADS], rbl[BLOADS];
+  auto load = [&](int kb) {
+#pragma unroll
+    for (int i = 0; i < ALOADS; ++i) {
+      const int l = tid + i * 256;
+      const int k = l / (TM / VA), mv = (l % (TM / VA)) * VA;
+      const bool ok = (kb + k < K) && (m0 + mv < M);
+      ra[i] = ok ? *reinterpret_cast<const VAt*>(A + (m0 + mv) + static_cast<int64_t>(kb + k) * lda) : VAt{};
+    }
+#pragma unroll
+    for (int i = 0; i < BLOADS; ++i) {
+      const int l = tid + i * 256;
+      const int n = l / (BK / VB), kv = (l % (BK / VB)) * VB;
+      const bool ok = (n0 + n < N) && (kb + kv < K);
+      const int64_t o = (kb + kv) + static_cast<int64_t>(n0 + n) * ldb;
+      rbh[i] = ok ? *reinterpret_cast<const VBt*>(Bh + o) : VBt{};
+      if constexpr (MF == MF_BF) rbl[i] = ok ? *reinterpret_cast<const VBt*>(Bl + o) : VBt{};
+    }
+  };
+  auto store = [&](int kb) {
+#pragma unroll
+    for (int i = 0; i < ALOADS; ++i) {  // transpose: LDS rows are m, k contiguous
+      const int l = tid + i * 256;
+      const int k = l / (TM / VA), mv = (l % (TM / VA)) * VA;
+#pragma unroll
+      for (int e = 0; e < VA; ++e) {
+        const TIN v = (m0 + mv + e < M) ? ra[i][e] : TIN(0);
+        if constexpr (MF == MF_BF) {
+          const float a = static_cast<float>(v);
+          const uint16_t hb = bf16_rne_bits(a);
+          ah[(mv + e) * ST + k] = hb;
+          al[(mv + e) * ST + k] = bf16_rne_bits(a - bf16_bits_to_f32(hb));
+        } else {
+          ah[(mv + e) * ST + k] = static_cast<L>(v);
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < BLOADS; ++i) {  // LDS rows are n, k contiguous
+      const int l = tid + i * 256;
+      const int n = l / (BK / VB), kv = (l % (BK / VB)) * VB;
+#pragma unroll
+      for (int e = 0; e < VB; ++e) {
+        const bool ke = kb + kv + e < K;
+        if constexpr (MF == MF_BF) {
+          bh[n * ST + kv + e] = ke ? rbh[i][e] : uint16_t(0);
+          bl[n * ST + kv + e] = ke ? rbl[i][e] : uint16_t(0);
+        } else {
+          bh[n * ST + kv + e] = ke ? static_cast<L>(rbh[i][e]) : L(0);
+        }
+      }
+    }
+  };
+
+  typename Form<MF>::acc_t acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = typename Form<MF>::acc_t{};
+
+  load(0);
+  for (int kb = 0; kb < K; kb += BK) {
+    __syncthreads();
+    store(kb);
+    __syncthreads();
+    if (kb + BK < K) load(kb + BK);
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += FR::KS) {
+      typename FR::t fb[4], fa[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) fb[i] = FR::load(bh, bl, wave * 64 + i * 16 + (lane & 15), ST, ks, lane);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) fa[j] = FR::load(ah, al, j * 16 + (lane & 15), ST, ks, lane);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) FR::mma(acc[i][j], fb[i], fa[j]);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int n = n0 + wave * 64 + i * 16 + Form<MF>::orow(lane, r);
+        const int m = m0 + j * 16 + (lane & 15);
+        if (m < M && n < N) C[m + static_cast<int64_t>(n) * ldc] = static_cast<TOUT>(Form<MF>::get(acc[i][j], r));
+      }
+}
+
+__global__ void split_bf16_from_f64_kernel(const double* __restrict__ s, uint16_t* __restrict__ hi,
+                                           uint16_t* __restrict__ lo, int64_t n) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float a = static_cast<float>(s[i]);
+  const uint16_t h = bf16_rne_bits(a);
+  hi[i] = h;
+  lo[i] = bf16_rne_bits(a - bf16_bits_to_f32(h));
+}
+
 constexpr int kTile = 64;
 
 int choose_splits(int tiles, int64_t K, int bk, int M, int N, size_t work_elems) {
@@ -327,10 +647,43 @@ int choose_splits(int tiles, int64_t K, int bk, int M, int N, size_t work_elems)
   return std::max(1, s);
 }
 
+template <typename T>
+bool aligned16(const T* p) {
+  return (reinterpret_cast<uintptr_t>(p) & 15u) == 0;
+}
+
 template <typename TIN, int MF>
 void tn_dispatch(const TIN* A, int64_t lda, const TIN* B, int64_t ldb, int M, int N, int64_t K,
                  double* C, int64_t ldc, int sym, int symmetrize, double* work, size_t work_elems,
                  hipStream_t st) {
+  constexpr int VEC = 16 / sizeof(TIN);
+  // FP64 keeps the 64-wide tiles: with its 4 x 4 FP64 accumulator blocks the
+  // large tile runs one workgroup per CU and was measured slower
+  if (MF != MF_F64 && M >= 64 && N >= 64 && lda % VEC == 0 && ldb % VEC == 0 && K <= lda && K <= ldb &&
+      aligned16(A) && aligned16(B)) {
+    constexpr int T = 128;
+    const int tm = (M + T - 1) / T, tn = (N + T - 1) / T;
+    const int ntile = sym ? tm * (tm + 1) / 2 : tm * tn;
+    const int bk = BigLds<MF>::BK;
+    // about three resident workgroups per CU, >= 16 K slabs per split
+    int splits = std::max(1, 768 / ntile);
+    splits = static_cast<int>(std::min<int64_t>(splits, std::max<int64_t>(1, K / (16 * bk))));
+    const size_t per = static_cast<size_t>(M) * N;
+    splits = static_cast<int>(std::min<size_t>(splits, std::max<size_t>(1, work_elems / per)));
+    int64_t kchunk = (K + splits - 1) / splits;
+    kchunk = ((kchunk + bk - 1) / bk) * bk;
+    const int real_splits = static_cast<int>((K + kchunk - 1) / kchunk);
+    const int64_t nb = static_cast<int64_t>(ntile) * real_splits;
+    if (nb > 0x7fffffff) fail(XLS_ERR_INVALID_ARG, "gemm_tn grid too large");
+    hipLaunchKernelGGL((gemm_tn_big_kernel<TIN, MF>), dim3(static_cast<unsigned>(nb)), dim3(256), 0, st, A, lda,
+                       B, ldb, M, N, K, kchunk, tm, tn, sym, work);
+    XLS_LAUNCH_CHECK("gemm_tn_big_kernel");
+    const int64_t tot = static_cast<int64_t>(M) * N;
+    hipLaunchKernelGGL(tn_reduce_kernel, dim3(static_cast<unsigned>((tot + 255) / 256)), dim3(256), 0, st, work,
+                       real_splits, M, N, T, sym, symmetrize, C, ldc);
+    XLS_LAUNCH_CHECK("tn_reduce_kernel");
+    return;
+  }
   const int tm = (M + kTile - 1) / kTile, tn = (N + kTile - 1) / kTile;
   const int ntile = sym ? tm * (tm + 1) / 2 : tm * tn;
   const int bk = Form<MF>::BK;
@@ -379,10 +732,52 @@ void gemm_tn(int prec, const TS* A, int64_t lda, const TS* B, int64_t ldb, int M
   }
 }
 
+// Large-tile rotation; false when the shapes or alignment do not allow it.
+template <typename TS>
+bool nn_big(int prec, const TS* A, int64_t lda, const double* B, int64_t ldb, int M, int N, int K, TS* C,
+            int64_t ldc, void* bwork, hipStream_t st) {
+  constexpr int VA = 16 / sizeof(TS);
+  if (M < 64 || N < 64 || lda % VA != 0 || !aligned16(A) || M > lda || K > ldb) return false;
+  const int tnN = (N + 255) / 256;
+  const int64_t nb = static_cast<int64_t>((M + 63) / 64) * tnN;
+  if (nb > 0x7fffffff) return false;
+  const dim3 grid(static_cast<unsigned>(nb));
+  const int64_t nbv = ldb * static_cast<int64_t>(N);
+  if (prec == MF_F64) {
+    if (ldb % 2 != 0 || !aligned16(B)) return false;
+    hipLaunchKernelGGL((gemm_nn_big_kernel<TS, double, TS, MF_F64>), grid, dim3(256), 0, st, A, lda, B,
+                       static_cast<const double*>(nullptr), ldb, M, N, K, tnN, C, ldc);
+  } else if constexpr (std::is_same<TS, float>::value) {
+    if (prec == MF_F32) {
+      if (ldb % 4 != 0) return false;
+      float* Bf = static_cast<float*>(bwork);
+      hipLaunchKernelGGL(d2f_kernel, dim3(static_cast<unsigned>((nbv + 255) / 256)), dim3(256), 0, st, B, Bf, nbv);
+      hipLaunchKernelGGL((gemm_nn_big_kernel<float, float, float, MF_F32>), grid, dim3(256), 0, st, A, lda, Bf,
+                         static_cast<const float*>(nullptr), ldb, M, N, K, tnN, C, ldc);
+    } else if (prec == MF_BF) {
+      if (ldb % 8 != 0) return false;
+      // the rotation matrix is split into bf16 hi/lo once (same bytes as its FP32 copy)
+      uint16_t* bh = static_cast<uint16_t*>(bwork);
+      uint16_t* bl = bh + nbv;
+      hipLaunchKernelGGL(split_bf16_from_f64_kernel, dim3(static_cast<unsigned>((nbv + 255) / 256)), dim3(256), 0,
+                         st, B, bh, bl, nbv);
+      hipLaunchKernelGGL((gemm_nn_big_kernel<float, uint16_t, float, MF_BF>), grid, dim3(256), 0, st, A, lda, bh, bl,
+                         ldb, M, N, K, tnN, C, ldc);
+    } else {
+      return false;
+    }
+  } else {
+    return false;
+  }
+  XLS_LAUNCH_CHECK("gemm_nn_big_kernel");
+  return true;
+}
+
 template <typename TS>
 void gemm_nn(int prec, const TS* A, int64_t lda, const double* B, int64_t ldb, int M, int N, int K,
              TS* C, int64_t ldc, void* bwork, hipStream_t st) {
   if (M <= 0 || N <= 0) return;
+  if (nn_big<TS>(prec, A, lda, B, ldb, M, N, K, C, ldc, bwork, st)) return;
   const int tmM = (M + kTile - 1) / kTile, tnN = (N + kTile - 1) / kTile;
   const int64_t nb = static_cast<int64_t>(tmM) * tnN;
   if (nb > 0x7fffffff) fail(XLS_ERR_INVALID_ARG, "gemm_nn grid too large");

@@ -224,6 +224,49 @@ def test_rotation_fp32(prec, tol):
     assert rel_err(out, X @ Q) <= tol
 
 
+# ns = 304 spans three 128-wide output tiles of the projection (ragged last)
+# and two 256-wide column tiles of the rotation; ns = 300 exercises the
+# fallback kernels where the bf16 path needs 8-aligned leading dimensions.
+@pytest.mark.parametrize("ns", [300, 304])
+@pytest.mark.parametrize("prec,tol", [(xls.XLS_PREC_FP64, 1e-12), (xls.XLS_PREC_FP32, 2e-6),
+                                      (xls.XLS_PREC_BF16X3, 1e-5)])
+def test_projection_and_rotation_large(prec, tol, ns):
+    case(f"projection/rotation large ns={ns} gemm={prec}")
+    sd = workloads.small_dirichlet(ns=ns, shape=(20, 19, 21))
+    op = hamiltonian.from_subdomain(sd)
+    X = sd.x0.astype(np.float32).astype(np.float64)
+    Q = np.random.default_rng(5).standard_normal((ns, ns)) / np.sqrt(ns)
+    with xls.Subdomain(sd, filter_prec=xls.XLS_PREC_FP32) as s:
+        M, Hs = s.xls_subdomain_project(prec)
+        s.xls_subdomain_rotate(Q, prec)
+        out = s.xls_subdomain_get_block()
+    Mr = X.T @ X
+    W = op.apply(X).astype(np.float32).astype(np.float64)
+    Hr = X.T @ W
+    Hr = 0.5 * (Hr + Hr.T)
+    assert rel_err(M, Mr) <= tol
+    assert rel_err(Hs, Hr) <= max(tol, 2e-6)
+    rtol = {xls.XLS_PREC_FP64: 2e-7, xls.XLS_PREC_FP32: 2e-6, xls.XLS_PREC_BF16X3: 2e-5}[prec]
+    assert rel_err(out, X @ Q) <= rtol  # the FP32 block stores the result in FP32
+
+
+@pytest.mark.parametrize("ns", [128, 304])
+def test_projection_rotation_large_fp64_block(ns):
+    case(f"projection/rotation large fp64 block ns={ns}")
+    sd = workloads.small_dirichlet(ns=ns, shape=(18, 20, 19))
+    op = hamiltonian.from_subdomain(sd)
+    X = sd.x0
+    Q = np.random.default_rng(6).standard_normal((ns, ns)) / np.sqrt(ns)
+    with xls.Subdomain(sd) as s:
+        M, Hs = s.xls_subdomain_project(xls.XLS_PREC_FP64)
+        s.xls_subdomain_rotate(Q, xls.XLS_PREC_FP64)
+        out = s.xls_subdomain_get_block()
+    Hr = X.T @ op.apply(X)
+    assert rel_err(M, X.T @ X) <= 1e-12
+    assert rel_err(Hs, 0.5 * (Hr + Hr.T)) <= 1e-12
+    assert rel_err(out, X @ Q) <= 1e-13
+
+
 def test_residual_fp64(system):
     name, sd, op = system
     case(f"residual {name}")

@@ -36,8 +36,9 @@ namespace {
 constexpr double kEps = 2.220446049250313e-16;
 constexpr double kSafeMin = 2.2250738585072014e-308;
 constexpr int kPanel = 32;       // Cholesky panel width
-constexpr int kInvIters = 3;     // inverse-iteration solves per vector
+constexpr int kInvIters = 3;     // inverse-iteration solves per vector in a cluster (2 when alone)
 constexpr double kOrtol = 1e-3;  // cluster gap, relative to |T|_1
+constexpr int kTrdPre = 8;       // column values per lane loaded ahead in a tridiagonalisation step
 
 inline unsigned nblk(int64_t n, int b) { return static_cast<unsigned>((n + b - 1) / b); }
 
@@ -242,6 +243,24 @@ __global__ __launch_bounds__(256) void trd_step_kernel(double* __restrict__ A, i
   double* cv = sm + n;
   double* vp = sm + 2 * n;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  // the stored column k and this wave's trailing column do not depend on
+  // this launch's vector work: load them first so that their latency
+  // overlaps it
+  const double* colk = A + static_cast<int64_t>(k) * n;
+  double ck[kTrdPre];
+#pragma unroll
+  for (int r = 0; r < kTrdPre; ++r) {
+    const int j = k + tid + 256 * r;
+    ck[r] = (j < n) ? colk[j] : 0.0;
+  }
+  const int iown = k + 1 + blockIdx.x * 4 + wv;
+  double* colown = A + static_cast<int64_t>(min(iown, n - 1)) * n;
+  double co[kTrdPre];
+#pragma unroll
+  for (int r = 0; r < kTrdPre; ++r) {
+    const int j = k + 1 + lane + 64 * r;
+    co[r] = (iown < n && j < n) ? colown[j] : 0.0;
+  }
   const double* vprev = vbuf + ((k + 1) & 1) * static_cast<int64_t>(n);
   const double* pprev = pbuf + ((k + 1) & 1) * static_cast<int64_t>(n);
   double* vcur = vbuf + (k & 1) * static_cast<int64_t>(n);
@@ -257,8 +276,16 @@ __global__ __launch_bounds__(256) void trd_step_kernel(double* __restrict__ A, i
     for (int j = k + tid; j < n; j += 256) w[j] = pprev[j] - K * vp[j];
     __syncthreads();
   }
-  const double* colk = A + static_cast<int64_t>(k) * n;
-  for (int j = k + tid; j < n; j += 256) {
+#pragma unroll
+  for (int r = 0; r < kTrdPre; ++r) {
+    const int j = k + tid + 256 * r;
+    if (j < n) {
+      double c = ck[r];
+      if (k > 0) c -= vp[j] * w[k] + w[j] * vp[k];
+      cv[j] = c;
+    }
+  }
+  for (int j = k + tid + 256 * kTrdPre; j < n; j += 256) {
     double c = colk[j];
     if (k > 0) c -= vp[j] * w[k] + w[j] * vp[k];
     cv[j] = c;
@@ -287,12 +314,22 @@ __global__ __launch_bounds__(256) void trd_step_kernel(double* __restrict__ A, i
       vcur[j] = cv[j];
     }
   }
-  const int i = k + 1 + blockIdx.x * 4 + wv;
+  const int i = iown;
   if (i >= n) return;
   const double wi = (k > 0) ? w[i] : 0.0, vpi = (k > 0) ? vp[i] : 0.0;
-  double* col = A + static_cast<int64_t>(i) * n;
+  double* col = colown;
   double acc = 0.0;
-  for (int j = k + 1 + lane; j < n; j += 64) {
+#pragma unroll
+  for (int r = 0; r < kTrdPre; ++r) {
+    const int j = k + 1 + lane + 64 * r;
+    if (j < n) {
+      double a = co[r];
+      if (k > 0) a -= vp[j] * wi + w[j] * vpi;
+      col[j] = a;
+      acc += a * cv[j];
+    }
+  }
+  for (int j = k + 1 + lane + 64 * kTrdPre; j < n; j += 64) {
     double a = col[j];
     if (k > 0) a -= vp[j] * wi + w[j] * vpi;
     col[j] = a;
@@ -533,7 +570,8 @@ __global__ __launch_bounds__(256) void tri_inviter_kernel(const double* __restri
     const double scale0 = 1.0 / sqrt(block_sum(part, red));
     for (int j = tid; j < m; j += 256) x[j] *= scale0;
     __syncthreads();
-    for (int it = 0; it < kInvIters; ++it) {
+    const int iters = (se - sb == 1) ? kInvIters - 1 : kInvIters;  // clusters get one more solve
+    for (int it = 0; it < iters; ++it) {
       if (tid == 0) {
         double cur = x[0];
         for (int i = 0; i + 1 < m; ++i) {
@@ -599,77 +637,53 @@ __global__ __launch_bounds__(256) void tri_rank_kernel(const double* __restrict_
   perm[rank] = s;
 }
 
-// out[:, c] = H_0 H_1 ... H_{n-2} Z[:, perm[c]] for NC columns per workgroup,
-// held in LDS; thread t owns rows t, t+256, ... throughout.
-constexpr int kBtRows = 11;  // ceil(kDenseMaxN / 256)
-template <int NC>
+// out[:, c] = H_0 H_1 ... H_{n-2} Z[:, perm[c]]: four columns per workgroup,
+// one per wavefront, held in LDS.  Each wavefront steps through the
+// reflectors on its own (dot product by shuffles, no workgroup barrier);
+// reflectors are staged into LDS ch at a time, so the only barriers are at
+// chunk boundaries.
+constexpr int kBtCols = 4;
 __global__ __launch_bounds__(256) void bt_kernel(const double* __restrict__ Z, const int32_t* __restrict__ perm,
                                                  const double* __restrict__ Vh, const double* __restrict__ tau,
-                                                 int n, double* __restrict__ out, const int32_t* __restrict__ flag) {
-  extern __shared__ double zs[];
-  __shared__ double red[2][4][NC];
+                                                 int n, int ch, double* __restrict__ out,
+                                                 const int32_t* __restrict__ flag) {
+  extern __shared__ double sm[];
   if (*flag) return;
-  const int c0 = blockIdx.x * NC, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  for (int cc = 0; cc < NC; ++cc) {
+  double* zs = sm;                        // kBtCols * n
+  double* vch = sm + kBtCols * n;         // ch * n
+  double* tch = vch + static_cast<int64_t>(ch) * n;  // ch
+  const int c0 = blockIdx.x * kBtCols, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  for (int cc = 0; cc < kBtCols; ++cc) {
     const int c = c0 + cc;
     int pc = (c < n) ? perm[c] : 0;
     pc = (pc >= 0 && pc < n) ? pc : c;  // a rank is always in range; never index out of bounds
     const double* src = (c < n) ? Z + static_cast<int64_t>(pc) * n : nullptr;
     for (int j = tid; j < n; j += 256) zs[cc * n + j] = src ? src[j] : 0.0;
   }
-  __syncthreads();
-  int par = 0;
-  // reflector k's column and tau are loaded one step ahead of their use
-  double vn[kBtRows];
-  double tnext = 0.0;
-  auto load_col = [&](int k) {
-    const double* v = Vh + static_cast<int64_t>(k) * n;
-#pragma unroll
-    for (int r = 0; r < kBtRows; ++r) {
-      const int j = tid + 256 * r;
-      vn[r] = (k >= 0 && j > k && j < n) ? v[j] : 0.0;
-    }
-    tnext = k >= 0 ? tau[k] : 0.0;
-  };
-  load_col(n - 2);
-  for (int k = n - 2; k >= 0; --k) {
-    double vr[kBtRows];
-#pragma unroll
-    for (int r = 0; r < kBtRows; ++r) vr[r] = vn[r];
-    const double t = tnext;
-    load_col(k - 1);
-    if (t == 0.0) continue;
-    double acc[NC];
-#pragma unroll
-    for (int cc = 0; cc < NC; ++cc) acc[cc] = 0.0;
-#pragma unroll
-    for (int r = 0; r < kBtRows; ++r) {
-      const int j = tid + 256 * r;
-#pragma unroll
-      for (int cc = 0; cc < NC; ++cc)
-        if (j < n) acc[cc] += vr[r] * zs[cc * n + j];
-    }
-#pragma unroll
-    for (int cc = 0; cc < NC; ++cc) {
-      acc[cc] = wave_sum(acc[cc]);
-      if (lane == 0) red[par][wv][cc] = acc[cc];
-    }
+  double* zw = zs + wv * n;
+  for (int kc = n - 2; kc >= 0; kc -= ch) {
+    const int qn = min(ch, kc + 1);
     __syncthreads();
-    double dot[NC];
-#pragma unroll
-    for (int cc = 0; cc < NC; ++cc)
-      dot[cc] = t * ((red[par][0][cc] + red[par][1][cc]) + (red[par][2][cc] + red[par][3][cc]));
-#pragma unroll
-    for (int r = 0; r < kBtRows; ++r) {
-      const int j = tid + 256 * r;
-      if (j > k && j < n)
-#pragma unroll
-        for (int cc = 0; cc < NC; ++cc) zs[cc * n + j] -= dot[cc] * vr[r];
+    for (int e = tid; e < qn * n; e += 256) {
+      const int q = e / n, j = e % n, k = kc - q;
+      vch[e] = (j > k) ? Vh[j + static_cast<int64_t>(k) * n] : 0.0;
     }
-    par ^= 1;
+    if (tid < qn) tch[tid] = tau[kc - tid];
+    __syncthreads();
+    for (int q = 0; q < qn; ++q) {
+      const double t = tch[q];
+      if (t == 0.0) continue;
+      const int k = kc - q;
+      const double* v = vch + q * n;
+      double acc = 0.0;
+      for (int j = k + 1 + lane; j < n; j += 64) acc += v[j] * zw[j];
+      const double d = t * wave_sum(acc);
+      for (int j = k + 1 + lane; j < n; j += 64) zw[j] -= d * v[j];
+      asm volatile("" ::: "memory");  // keep the next step's reads after these writes (LDS is in order per wave)
+    }
   }
   __syncthreads();
-  for (int cc = 0; cc < NC; ++cc) {
+  for (int cc = 0; cc < kBtCols; ++cc) {
     const int c = c0 + cc;
     if (c >= n) break;
     for (int j = tid; j < n; j += 256) out[j + static_cast<int64_t>(c) * n] = zs[cc * n + j];
@@ -785,14 +799,14 @@ int dense_geneig(DenseWork& w, const double* Hs, const double* M, double* Y, hip
                      raw, n, lam, perm, w.flag);
   XLS_LAUNCH_CHECK("tridiagonal eigensolver");
   // --- back-transformation, Y = Rinv Q Z ---
-  if (n <= 1024) {
-    const size_t sm = 8 * static_cast<size_t>(n) * sizeof(double);
-    set_smem(reinterpret_cast<const void*>(bt_kernel<8>), sm);
-    hipLaunchKernelGGL(bt_kernel<8>, dim3(nblk(n, 8)), dim3(256), sm, st, w.Z, perm, w.Vh, tau, n, w.T, w.flag);
-  } else {
-    const size_t sm = 4 * static_cast<size_t>(n) * sizeof(double);
-    set_smem(reinterpret_cast<const void*>(bt_kernel<4>), sm);
-    hipLaunchKernelGGL(bt_kernel<4>, dim3(nblk(n, 4)), dim3(256), sm, st, w.Z, perm, w.Vh, tau, n, w.T, w.flag);
+  {
+    const size_t zbytes = kBtCols * static_cast<size_t>(n) * sizeof(double);
+    const size_t budget = 150 * 1024;
+    const int ch = static_cast<int>(std::max<size_t>(1, std::min<size_t>(32, (budget - zbytes) / ((n + 1) * sizeof(double)))));
+    const size_t sm = zbytes + (static_cast<size_t>(ch) * n + ch) * sizeof(double);
+    set_smem(reinterpret_cast<const void*>(bt_kernel), sm);
+    hipLaunchKernelGGL(bt_kernel, dim3(nblk(n, kBtCols)), dim3(256), sm, st, w.Z, perm, w.Vh, tau, n, ch, w.T,
+                       w.flag);
   }
   gemm_nn<double>(XLS_PREC_FP64, w.Rinv, n, w.T, n, n, n, n, Y, n, nullptr, st);
   XLS_LAUNCH_CHECK("dense back-transform");

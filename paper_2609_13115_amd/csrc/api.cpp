@@ -318,6 +318,7 @@ int chefsi_loop(xls_subdomain_s* s, const xls_chefsi_params_t* p, int gprec, int
                 double lc, double lmax, std::vector<double>& hl, std::vector<double>& hr) {
   const int ns = s->ns;
   int it = 0;
+  double prev_resid = HUGE_VAL;
   for (; it < p->max_iter;) {
     StageTimer tm(profiling_on(), s->st);
     tm.mark();
@@ -328,9 +329,10 @@ int chefsi_loop(xls_subdomain_s* s, const xls_chefsi_params_t* p, int gprec, int
       TS* W = B<TS>(s, 1 - s->cur);
       apply_H<TS>(s, Bc, W, s->ns, static_cast<TS*>(s->alpha));
       tm.mark();
-      gemm_tn<TS>(gprec, Bc, s->ld, Bc, s->ld, ns, ns, s->nd, s->Mdev, ns, 1, 0, s->gwork, s->gwork_elems,
+      const int pprec = projection_prec(gprec, prev_resid);
+      gemm_tn<TS>(pprec, Bc, s->ld, Bc, s->ld, ns, ns, s->nd, s->Mdev, ns, 1, 0, s->gwork, s->gwork_elems,
                   s->st);
-      gemm_tn<TS>(gprec, Bc, s->ld, W, s->ld, ns, ns, s->nd, s->Hsdev, ns, 0, 1, s->gwork, s->gwork_elems,
+      gemm_tn<TS>(pprec, Bc, s->ld, W, s->ld, ns, ns, s->nd, s->Hsdev, ns, 0, 1, s->gwork, s->gwork_elems,
                   s->st);
     }
     tm.mark();
@@ -356,12 +358,11 @@ int chefsi_loop(xls_subdomain_s* s, const xls_chefsi_params_t* p, int gprec, int
     s->have_ritz = true;
     a0 = hl[0];
     lc = hl[ns - 1];
+    double mx = 0;
+    for (int k = 0; k < gate; ++k) mx = std::max(mx, hr[k]);
+    prev_resid = mx;
     if (!(a0 < lc && lc < lmax)) break;  // degenerate bounds: stop with what we have
-    if (p->resid_tol > 0) {
-      double mx = 0;
-      for (int k = 0; k < gate; ++k) mx = std::max(mx, hr[k]);
-      if (mx <= p->resid_tol) break;
-    }
+    if (p->resid_tol > 0 && mx <= p->resid_tol) break;
   }
   return it;
 }

@@ -65,6 +65,7 @@ struct GraphEntry {
 struct SubState {
   double lmax = 0.0;
   int degree = 0, max_iter = 0, gate = 0, gprec = XLS_PREC_FP64;
+  int pprec = XLS_PREC_FP64;  // projection precision this iteration (schedule of projection_prec)
   double resid_tol = 0.0;
   int iters = 0;
   int status = XLS_OK;
@@ -116,8 +117,8 @@ void tail_stages(xls_subdomain_s* s, const SubState& ss, int cur_f, double* coef
   TS* Bc = B<TS>(s, cur_f);
   TS* W = B<TS>(s, 1 - cur_f);
   apply_H<TS>(s, Bc, W, ns, static_cast<TS*>(s->alpha));
-  gemm_tn<TS>(ss.gprec, Bc, s->ld, Bc, s->ld, ns, ns, s->nd, s->Mdev, ns, 1, 0, s->gwork, s->gwork_elems, s->st);
-  gemm_tn<TS>(ss.gprec, Bc, s->ld, W, s->ld, ns, ns, s->nd, s->Hsdev, ns, 0, 1, s->gwork, s->gwork_elems, s->st);
+  gemm_tn<TS>(ss.pprec, Bc, s->ld, Bc, s->ld, ns, ns, s->nd, s->Mdev, ns, 1, 0, s->gwork, s->gwork_elems, s->st);
+  gemm_tn<TS>(ss.pprec, Bc, s->ld, W, s->ld, ns, ns, s->nd, s->Hsdev, ns, 0, 1, s->gwork, s->gwork_elems, s->st);
   (void)dense_geneig(s->dw, s->Hsdev, s->Mdev, s->Ydev, s->st, /*check_spd=*/false);
   XLS_HIP(hipMemcpyAsync(s->lam_dev, s->dw.lam(), ns * 8, hipMemcpyDeviceToDevice, s->st));
   // Psi <- Psi_f Y into the other buffer
@@ -176,8 +177,8 @@ std::string graph_key(xls_batch_s* b, const std::vector<int>& act) {
   std::ostringstream k;
   k << std::hexfloat;
   for (int i : act)
-    k << i << (b->subs[i]->cur ? 'b' : 'a') << b->st[i].degree << 'p' << b->st[i].gprec << 'l' << b->st[i].lmax
-      << ',';
+    k << i << (b->subs[i]->cur ? 'b' : 'a') << b->st[i].degree << 'p' << b->st[i].gprec << 'q' << b->st[i].pprec
+      << 'l' << b->st[i].lmax << ',';
   return k.str();
 }
 
@@ -270,6 +271,7 @@ void batch_chefsi(xls_batch_s* b, const xls_chefsi_params_t* P, int use_graph) {
     ss.degree = p.degree;
     ss.max_iter = p.max_iter;
     ss.gprec = p.gemm_prec;
+    ss.pprec = projection_prec(p.gemm_prec, HUGE_VAL);
     ss.resid_tol = p.resid_tol;
     ss.gate = p.n_gate > 0 ? std::min(p.n_gate, s->ns)
                            : std::max(1, static_cast<int>(std::floor(s->ns / 1.1 + 1e-9)));
@@ -327,11 +329,10 @@ void batch_chefsi(xls_batch_s* b, const xls_chefsi_params_t* P, int use_graph) {
         ss.active = false;
         continue;
       }
-      if (ss.resid_tol > 0) {
-        double mx = 0;
-        for (int k = 0; k < ss.gate; ++k) mx = std::max(mx, hr[i][k]);
-        if (mx <= ss.resid_tol) ss.active = false;
-      }
+      double mx = 0;
+      for (int k = 0; k < ss.gate; ++k) mx = std::max(mx, hr[i][k]);
+      ss.pprec = projection_prec(ss.gprec, mx);
+      if (ss.resid_tol > 0 && mx <= ss.resid_tol) ss.active = false;
       if (ss.iters >= ss.max_iter) ss.active = false;
     }
   }

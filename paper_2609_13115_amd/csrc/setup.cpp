@@ -133,14 +133,17 @@ void build_setup(const xls_subdomain_desc_t& d, SetupTables& t) {
 
   // kernel form: packed per-point (first entry, count) and per-entry payload
   if (total >= (size_t(1) << 27)) fail(XLS_ERR_INVALID_ARG, "too many projector support points");
+  // a point without projectors points at a zero-payload sentinel entry
+  // (index total), so the kernel's prefetch needs no select
   t.rev_pk.assign(nd, 0);
   for (int64_t g = 0; g < nd; ++g) {
     const int32_t cnt = t.rev_off[g + 1] - t.rev_off[g];
     if (cnt > 31) fail(XLS_ERR_INVALID_ARG, "more than 31 projector sets overlap one grid point");
-    t.rev_pk[g] = t.rev_off[g] | (cnt << 27);
+    const int32_t first = cnt > 0 ? t.rev_off[g] : static_cast<int32_t>(total);
+    t.rev_pk[g] = first | (cnt << 27);
   }
-  t.rev_val.assign(4 * total, 0.0);
-  t.rev_aoff.assign(total, 0);
+  t.rev_val.assign(4 * (total + 1), 0.0);
+  t.rev_aoff.assign(total + 1, 0);
   for (size_t e = 0; e < total; ++e) {
     const int32_t sl = t.rev_slot[e];
     for (int l = 0; l < 4; ++l) t.rev_val[4 * e + l] = t.sup_val[4 * static_cast<size_t>(sl) + l];

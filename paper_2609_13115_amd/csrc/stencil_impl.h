@@ -198,8 +198,8 @@ __device__ __forceinline__ void stencil_tile(const HArgs<TS, TC>& A, uint32_t lo
   const __amdgpu_buffer_rsrc_t ro = make_rsrc(MODE == kResid ? A.y : A.out + static_cast<int64_t>(col) * A.ld, colbytes);
   const __amdgpu_buffer_rsrc_t rv = make_rsrc(A.v, static_cast<int64_t>(nx) * ny * nz * EC);
   const __amdgpu_buffer_rsrc_t rk = make_rsrc(A.rev_pk, static_cast<int64_t>(nx) * ny * nz * 4);
-  const __amdgpu_buffer_rsrc_t re = make_rsrc(A.rev_val, static_cast<int64_t>(A.nent) * 4 * EC);
-  const __amdgpu_buffer_rsrc_t ra = make_rsrc(A.rev_aoff, static_cast<int64_t>(A.nent) * 4);
+  const __amdgpu_buffer_rsrc_t re = make_rsrc(A.rev_val, static_cast<int64_t>(A.nent + 1) * 4 * EC);
+  const __amdgpu_buffer_rsrc_t ra = make_rsrc(A.rev_aoff, static_cast<int64_t>(A.nent + 1) * 4);
 
   // points owned by this lane: in-plane byte offsets per stream element size
   // (kOOB when inactive) and LDS index
@@ -296,11 +296,10 @@ __device__ __forceinline__ void stencil_tile(const HArgs<TS, TC>& A, uint32_t lo
     for (int i = 0; i < P; ++i) {
       vn[i] = bload<TC>(rv, oc[i], so * EC);
       rp1[i] = rp2[i];
-      const int ne = static_cast<int>(static_cast<uint32_t>(rp1[i]) >> 27);
-      const int e0 = rp1[i] & EMASK;
-      ev[i] = load_ent<TC>(re, ne > 0 ? e0 * 4 * EC : kOOB);
-      ea[i] = bload<int>(ra, ne > 0 ? e0 * 4 : kOOB, 0);
-      rp2[i] = (z + 1 < z1) ? bload<int>(rk, o4[i], (so + pp) * 4) : 0;
+      const int e0 = rp1[i] & EMASK;  // points without projectors name the zero sentinel
+      ev[i] = load_ent<TC>(re, e0 * 4 * EC);
+      ea[i] = bload<int>(ra, e0 * 4, 0);
+      rp2[i] = (z + 1 < z1) ? bload<int>(rk, o4[i], (so + pp) * 4) : static_cast<int>(A.nent);
     }
   };
   {
@@ -344,12 +343,18 @@ __device__ __forceinline__ void stencil_tile(const HArgs<TS, TC>& A, uint32_t lo
     const int so = z * pp * ES;
 #pragma unroll
     for (int i = 0; i < P; ++i) {
-      const TC* bp = buf + li[i];
+      // based at the point's lowest neighbour behind an opaque register, so
+      // every LDS offset is a non-negative immediate (measured faster)
+      constexpr int C0 = R * W + R;
+      int lo = li[i] - C0;
+      asm("" : "+v"(lo));
+      const TC* bq = buf + lo;
       const TC ctr = q[i][QS(R)];
       TC lap = A.wc * ctr;
 #pragma unroll
       for (int p = 1; p <= R; ++p) {
-        const TC sm = (bp[p] + bp[-p]) + (bp[p * W] + bp[-p * W]) + (q[i][QS(R + p)] + q[i][QS(R - p)]);
+        const TC sm = (bq[C0 + p] + bq[C0 - p]) + (bq[C0 + p * W] + bq[C0 - p * W]) +
+                      (q[i][QS(R + p)] + q[i][QS(R - p)]);
         lap += A.w[p - 1] * sm;
       }
       TC hy = lap + vn[i] * ctr;
@@ -456,9 +461,72 @@ __global__ __launch_bounds__(NT) void hstencil_group_kernel(const HArgs<TS, TC>*
   }
 }
 
-// alpha[col][4a+l] = gamma_{a,l} h^3 sum_s chi_{a,l}(s) y(idx(s), col): one
-// wavefront per (atom, column), lanes stride over the atom's support, fixed
-// xor-shuffle reduction (deterministic).
+// alpha[col][4a+l] = gamma_{a,l} h^3 sum_s chi_{a,l}(s) y(idx(s), col).  One
+// wavefront per (atom, kProjCols columns): lanes stride over the atom's
+// support and load each point's index and projector values once for all its
+// columns; per column, FP64 partial sums per lane then a fixed xor-shuffle
+// reduction (deterministic).
+constexpr int kProjCols = 4;
+template <typename TS, typename TC>
+__device__ __forceinline__ void proj_forward_wave(const TS* __restrict__ y, int64_t ld, int ncols, int cbase,
+                                                  const int32_t* __restrict__ sup_off,
+                                                  const int32_t* __restrict__ sup_idx, const TC* __restrict__ val,
+                                                  const double* __restrict__ gamma, double h3,
+                                                  TC* __restrict__ alpha, int nproj, int a, int lane) {
+  const int s0 = sup_off[a], s1 = sup_off[a + 1];
+  const int nc = min(kProjCols, ncols - cbase);
+  double acc[kProjCols][4];
+#pragma unroll
+  for (int c = 0; c < kProjCols; ++c)
+#pragma unroll
+    for (int l = 0; l < 4; ++l) acc[c][l] = 0.0;
+  // the next point's index and values load one iteration ahead
+  int gn = 0;
+  TC vn0 = TC(0), vn1 = TC(0), vn2 = TC(0), vn3 = TC(0);
+  auto fetch = [&](int s) {
+    if (s < s1) {
+      gn = sup_idx[s];
+      const TC* v4 = val + 4 * static_cast<int64_t>(s);
+      vn0 = v4[0];
+      vn1 = v4[1];
+      vn2 = v4[2];
+      vn3 = v4[3];
+    }
+  };
+  fetch(s0 + lane);
+  for (int s = s0 + lane; s < s1; s += 64) {
+    const int g = gn;
+    const double v0 = static_cast<double>(vn0), v1 = static_cast<double>(vn1);
+    const double v2 = static_cast<double>(vn2), v3 = static_cast<double>(vn3);
+    fetch(s + 64);
+#pragma unroll
+    for (int c = 0; c < kProjCols; ++c) {
+      if (c < nc) {
+        const double yv = static_cast<double>(y[static_cast<int64_t>(cbase + c) * ld + g]);
+        acc[c][0] += v0 * yv;
+        acc[c][1] += v1 * yv;
+        acc[c][2] += v2 * yv;
+        acc[c][3] += v3 * yv;
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < kProjCols; ++c)
+#pragma unroll
+    for (int l = 0; l < 4; ++l)
+      for (int off = 32; off > 0; off >>= 1) acc[c][l] += __shfl_xor(acc[c][l], off, 64);
+  if (lane == 0) {
+#pragma unroll
+    for (int c = 0; c < kProjCols; ++c) {
+      if (c < nc) {
+        TC* o = alpha + static_cast<int64_t>(cbase + c) * nproj + 4 * a;
+#pragma unroll
+        for (int l = 0; l < 4; ++l) o[l] = static_cast<TC>(gamma[4 * a + l] * h3 * acc[c][l]);
+      }
+    }
+  }
+}
+
 template <typename TS, typename TC>
 __global__ __launch_bounds__(256) void proj_forward_kernel(const TS* __restrict__ y, int64_t ld,
                                                            int ncols, const int32_t* __restrict__ sup_off,
@@ -467,36 +535,11 @@ __global__ __launch_bounds__(256) void proj_forward_kernel(const TS* __restrict_
                                                            const double* __restrict__ gamma,
                                                            double h3, TC* __restrict__ alpha,
                                                            int nproj) {
-  const int a = blockIdx.x;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int col = blockIdx.y * 4 + wave;
-  if (col >= ncols) return;
-  const int s0 = sup_off[a], s1 = sup_off[a + 1];
-  const TS* __restrict__ yc = y + static_cast<int64_t>(col) * ld;
-  double acc0 = 0, acc1 = 0, acc2 = 0, acc3 = 0;
-  for (int s = s0 + lane; s < s1; s += 64) {
-    const double yv = static_cast<double>(yc[sup_idx[s]]);
-    const TC* v4 = val + 4 * static_cast<int64_t>(s);
-    acc0 += static_cast<double>(v4[0]) * yv;
-    acc1 += static_cast<double>(v4[1]) * yv;
-    acc2 += static_cast<double>(v4[2]) * yv;
-    acc3 += static_cast<double>(v4[3]) * yv;
-  }
-  for (int off = 32; off > 0; off >>= 1) {
-    acc0 += __shfl_xor(acc0, off, 64);
-    acc1 += __shfl_xor(acc1, off, 64);
-    acc2 += __shfl_xor(acc2, off, 64);
-    acc3 += __shfl_xor(acc3, off, 64);
-  }
-  if (lane == 0) {
-    TC* o = alpha + static_cast<int64_t>(col) * nproj + 4 * a;
-    o[0] = static_cast<TC>(gamma[4 * a + 0] * h3 * acc0);
-    o[1] = static_cast<TC>(gamma[4 * a + 1] * h3 * acc1);
-    o[2] = static_cast<TC>(gamma[4 * a + 2] * h3 * acc2);
-    o[3] = static_cast<TC>(gamma[4 * a + 3] * h3 * acc3);
-  }
+  const int cbase = (blockIdx.y * 4 + wave) * kProjCols;
+  if (cbase >= ncols) return;
+  proj_forward_wave<TS, TC>(y, ld, ncols, cbase, sup_off, sup_idx, val, gamma, h3, alpha, nproj, blockIdx.x, lane);
 }
-
 
 // Grouped forward projection: item = (operator, atom + n_atoms * column group).
 template <typename TS, typename TC>
@@ -520,32 +563,10 @@ __global__ __launch_bounds__(256) void proj_forward_group_kernel(const PArgs<TS,
     const uint2 w = items[it];
     const PArgs<TS, TC> A = tab[w.x];
     const int a = static_cast<int>(w.y % static_cast<uint32_t>(A.n_atoms));
-    const int col = static_cast<int>(w.y / static_cast<uint32_t>(A.n_atoms)) * 4 + wave;
-    if (col >= A.ncols) continue;
-    const int s0 = A.sup_off[a], s1 = A.sup_off[a + 1];
-    const TS* __restrict__ yc = A.y + static_cast<int64_t>(col) * A.ld;
-    double acc0 = 0, acc1 = 0, acc2 = 0, acc3 = 0;
-    for (int s = s0 + lane; s < s1; s += 64) {
-      const double yv = static_cast<double>(yc[A.sup_idx[s]]);
-      const TC* v4 = A.val + 4 * static_cast<int64_t>(s);
-      acc0 += static_cast<double>(v4[0]) * yv;
-      acc1 += static_cast<double>(v4[1]) * yv;
-      acc2 += static_cast<double>(v4[2]) * yv;
-      acc3 += static_cast<double>(v4[3]) * yv;
-    }
-    for (int off = 32; off > 0; off >>= 1) {
-      acc0 += __shfl_xor(acc0, off, 64);
-      acc1 += __shfl_xor(acc1, off, 64);
-      acc2 += __shfl_xor(acc2, off, 64);
-      acc3 += __shfl_xor(acc3, off, 64);
-    }
-    if (lane == 0) {
-      TC* o = A.alpha + static_cast<int64_t>(col) * A.nproj + 4 * a;
-      o[0] = static_cast<TC>(A.gamma[4 * a + 0] * A.h3 * acc0);
-      o[1] = static_cast<TC>(A.gamma[4 * a + 1] * A.h3 * acc1);
-      o[2] = static_cast<TC>(A.gamma[4 * a + 2] * A.h3 * acc2);
-      o[3] = static_cast<TC>(A.gamma[4 * a + 3] * A.h3 * acc3);
-    }
+    const int cbase = (static_cast<int>(w.y / static_cast<uint32_t>(A.n_atoms)) * 4 + wave) * kProjCols;
+    if (cbase >= A.ncols) continue;
+    proj_forward_wave<TS, TC>(A.y, A.ld, A.ncols, cbase, A.sup_off, A.sup_idx, A.val, A.gamma, A.h3, A.alpha,
+                              A.nproj, a, lane);
   }
 }
 
@@ -756,7 +777,7 @@ template <typename TS, typename TC>
 void launch_proj_forward(const OpTables<TC>& op, const TS* y, int64_t ld, int ncols, TC* alpha,
                          hipStream_t st) {
   if (op.n_atoms == 0 || ncols <= 0) return;
-  const dim3 grid(op.n_atoms, (ncols + 3) / 4);
+  const dim3 grid(op.n_atoms, (ncols + 4 * kProjCols - 1) / (4 * kProjCols));
   const double h3 = op.h * op.h * op.h;
   hipLaunchKernelGGL((proj_forward_kernel<TS, TC>), grid, dim3(256), 0, st, y, ld, ncols,
                      op.sup_off, op.sup_idx, op.slot_val, op.gamma, h3, alpha, 4 * op.n_atoms);
@@ -935,7 +956,9 @@ FilterGroup<TS>* filter_group_build(const std::vector<FilterGroupOp<TS>>& ops) {
                   b.items, [&](int i) { return bucket_of[i] == static_cast<int>(bi); });
       b.grid_cap = group_occ<TS>(b.P, b.block, b.ws, b.smem) * cus;
     }
-    build_items([&](int i) { return static_cast<int64_t>(ops[i].op->n_atoms) * ((ops[i].ncols + 3) / 4); },
+    build_items([&](int i) {
+      return static_cast<int64_t>(ops[i].op->n_atoms) * ((ops[i].ncols + 4 * kProjCols - 1) / (4 * kProjCols));
+    },
                 g->pcount, g->pitems, [](int) { return true; });
     g->pgrid = 16 * cus;
   } catch (...) {

@@ -155,6 +155,15 @@ const StencilLaunch& cfg_of(xls_subdomain_s* s) {
   return std::is_same<TS, float>::value ? s->cfg32 : s->cfg64;
 }
 
+// Precision schedule of the projection GEMMs: split-BF16 keeps about 16
+// mantissa bits per operand, which bounds Ritz values near 1e-5 relative, so
+// once the previous iteration's largest gated residual is below
+// kPolishResid the projection runs in FP32 (the rotation keeps gprec).
+constexpr double kPolishResid = 1e-2;
+inline int projection_prec(int gprec, double prev_gated_resid) {
+  return (gprec == XLS_PREC_BF16X3 && prev_gated_resid <= kPolishResid) ? XLS_PREC_FP32 : gprec;
+}
+
 // Stage helpers on the handle's stream (api.cpp).
 template <typename TS>
 void apply_H(xls_subdomain_s* s, const TS* y, TS* out, int ncols, TS* alpha);

@@ -42,8 +42,8 @@ struct SetupTables {
   // kernel form of the reverse CSR: per point (first entry | count << 27),
   // per entry the four projector values and 4*atom (offset into alpha)
   std::vector<int32_t> rev_pk;        // [nd]
-  std::vector<double> rev_val;        // [4 * total] in reverse-CSR order
-  std::vector<int32_t> rev_aoff;      // [total]
+  std::vector<double> rev_val;        // [4 * (total + 1)] reverse-CSR order, then a zero sentinel
+  std::vector<int32_t> rev_aoff;      // [total + 1]
 };
 void build_setup(const xls_subdomain_desc_t& d, SetupTables& t);
 
@@ -58,7 +58,7 @@ struct OpTables {
   const TC* v = nullptr;         // [nd]
   const TC* slot_val = nullptr;  // [4 * total] support order
   const int32_t* rev_pk = nullptr;
-  const TC* rev_val = nullptr;   // [4 * total] reverse-CSR order
+  const TC* rev_val = nullptr;   // [4 * (nent + 1)] reverse-CSR order, then a zero sentinel
   const int32_t* rev_aoff = nullptr;
   int64_t nent = 0;              // reverse-CSR entries (= support slots)
   const int32_t* sup_off = nullptr;

@@ -471,3 +471,39 @@ def test_dense_graph_replay_matches_eager():
     (r1, e1, i1, b1), (r2, e2, i2, b2) = outs
     assert i1 == i2 == 7
     assert np.array_equal(r1, r2) and np.array_equal(e1, e2) and np.array_equal(b1, b2)
+
+
+@pytest.mark.parametrize("gprec", [xls.XLS_PREC_FP32, xls.XLS_PREC_BF16X3])
+def test_mixed_precision_ritz_gate_cfg1(gprec):
+    """The mixed forms (FP32 filter sweeps; FP32 or split-BF16 GEMMs; FP64
+    Cholesky, eigensolve and residual) against the FP64 oracle on cfg1:
+    every gated Ritz value within 1e-6 Ha, and the gated subspace within
+    1e-5 (largest principal-angle sine, clusters closed)."""
+    case(f"mixed gate cfg1 gemm={gprec}")
+    sd = workloads.cfg1()
+    op = hamiltonian.from_subdomain(sd)
+    lo, up = chefsi.lanczos_bounds(op.apply, sd.lanczos_v0, 20)
+    ref = chefsi.chefsi(op.apply, sd.x0, 20, 14, lo, chefsi.first_cutoff(lo, up), up)
+    with xls.Subdomain(sd, filter_prec=xls.XLS_PREC_FP32) as s:
+        ritz, resid, it = s.xls_chefsi_step(20, 14, xls.XLS_BOUNDS_LANCZOS, gemm_prec=gprec)
+        psi = s.xls_subdomain_get_block()
+    gate = int(np.floor(sd.ns / 1.1 + 1e-9))
+    assert np.max(np.abs(ritz[:gate] - ref.ritz[:gate])) <= 1e-6
+    # subspace of the gated states, closed over the degenerate cluster at the gate edge
+    k = gate
+    while k < sd.ns and abs(ref.ritz[k] - ref.ritz[k - 1]) < 1e-6:
+        k += 1
+    if k < sd.ns:
+        assert chefsi.subspace_sin_theta(ref.psi[:, :k], psi[:, :k]) <= 1e-5
+
+
+def test_mixed_precision_ritz_gate_dirichlet():
+    case("mixed gate dirichlet box")
+    sd = workloads.small_dirichlet(ns=24, index=9, shape=(18, 16, 20), h=0.6)
+    op = hamiltonian.from_subdomain(sd)
+    lo, up = chefsi.lanczos_bounds(op.apply, sd.lanczos_v0, 20)
+    ref = chefsi.chefsi(op.apply, sd.x0, 16, 16, lo, chefsi.first_cutoff(lo, up), up)
+    with xls.Subdomain(sd, filter_prec=xls.XLS_PREC_FP32) as s:
+        ritz, resid, it = s.xls_chefsi_step(16, 16, xls.XLS_BOUNDS_LANCZOS, gemm_prec=xls.XLS_PREC_BF16X3)
+    gate = int(np.floor(sd.ns / 1.1 + 1e-9))
+    assert np.max(np.abs(ritz[:gate] - ref.ritz[:gate])) <= 1e-6

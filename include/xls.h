@@ -202,10 +202,12 @@ int xls_split_bf16(const float* a, uint16_t* hi, uint16_t* lo, int64_t n);
 /* Launch shape of the handle's stencil sweeps in storage precision prec
  * (XLS_PREC_FP64 or XLS_PREC_FP32): block threads (256 or 512), ty rows
  * per tile (0: about 2 points per thread in FP32, 1 in FP64), tz planes per
- * z-chunk (0: the whole box).  The shape changes scheduling only, never the
- * arithmetic of a grid point.  Errors: INVALID_ARG when the tile does not fit
- * (LDS, registers, halo budget). */
-int xls_subdomain_tune(xls_subdomain_t s, int32_t prec, int32_t block, int32_t ty, int32_t tz);
+ * z-chunk (0: the whole box), nv vectors per tile (1 or 2; 0: choose).  A
+ * tile of 2 vectors reads the operator tables (V, projector entries) once
+ * for both; residual sweeps always take 1.  The shape changes scheduling
+ * only, never the arithmetic of a grid point.  Errors: INVALID_ARG when the
+ * tile does not fit (LDS, registers, halo budget) or nv is not 0, 1 or 2. */
+int xls_subdomain_tune(xls_subdomain_t s, int32_t prec, int32_t block, int32_t ty, int32_t tz, int32_t nv);
 
 /* Per-stage device time of the handle's last xls_chefsi_step, from HIP events
  * on the handle's stream when profiling is on (xls_set_profiling(1)).

@@ -206,8 +206,9 @@ void lanczos_run(xls_subdomain_s* s, int k) {
     launch_dot<TS>(vj, w, s->nd, part, nblocks, al + j, 0, s->st);
     launch_lanczos_update<TS>(w, vj, j > 0 ? vj - ld : nullptr, al + j, j > 0 ? be + j - 1 : nullptr, s->nd,
                               s->st);
-    gemm_tn<TS>(XLS_PREC_FP64, V, ld, w, ld, j + 1, 1, s->nd, coef, j + 1, 0, 0, s->gwork, s->gwork_elems,
-                s->st);
+    // coef = V_{0..j}^T w (full reorthogonalisation): a skinny product
+    const int rb = static_cast<int>(std::max<size_t>(1, std::min<size_t>(256, s->gwork_elems / (j + 1))));
+    launch_multi_dot<TS>(V, ld, j + 1, w, s->nd, s->gwork, rb, coef, s->st);
     launch_reorth<TS>(w, V, ld, coef, j + 1, s->nd, s->st);
     launch_dot<TS>(w, w, s->nd, part, nblocks, be + j, 1, s->st);
     double ab[2];
@@ -879,7 +880,7 @@ int xls_split_bf16(const float* a, uint16_t* hi, uint16_t* lo, int64_t n) {
   });
 }
 
-int xls_subdomain_tune(xls_subdomain_t s, int32_t prec, int32_t block, int32_t ty, int32_t tz) {
+int xls_subdomain_tune(xls_subdomain_t s, int32_t prec, int32_t block, int32_t ty, int32_t tz, int32_t nv) {
   return guarded([&]() -> int {
     if (!s) fail(XLS_ERR_INVALID_ARG, "NULL handle");
     if (prec != XLS_PREC_FP64 && prec != XLS_PREC_FP32) fail(XLS_ERR_INVALID_ARG, "prec must be FP64 or FP32");
@@ -887,6 +888,7 @@ int xls_subdomain_tune(xls_subdomain_t s, int32_t prec, int32_t block, int32_t t
     c.block = block;
     c.ty = ty;
     c.tz = tz;
+    c.nv = nv;
     stencil_validate(s->n[0], s->n[1], s->n[2], s->bc == XLS_BC_PERIODIC, prec == XLS_PREC_FP64 ? 8 : 4,
                      s->nproj(), c);
     if (prec == XLS_PREC_FP64) {

@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -171,14 +172,19 @@ void record_iteration(xls_batch_s* b, FilterGroup<TS>* g, const std::vector<int>
 }
 
 // Everything a captured iteration bakes in: the active set, each block's
-// parity, degree, GEMM precision and lam_max (a kernel argument of the
-// coefficient update).
+// parity, degree, GEMM precision, lam_max (a kernel argument of the
+// coefficient update) and stencil launch shape.
 std::string graph_key(xls_batch_s* b, const std::vector<int>& act) {
   std::ostringstream k;
   k << std::hexfloat;
-  for (int i : act)
-    k << i << (b->subs[i]->cur ? 'b' : 'a') << b->st[i].degree << 'p' << b->st[i].gprec << 'q' << b->st[i].pprec
-      << 'l' << b->st[i].lmax << ',';
+  for (int i : act) {
+    const xls_subdomain_s* s = b->subs[i];
+    // the launch shape too: a handle re-tuned through xls_subdomain_tune
+    // must not replay a graph of its old tiles
+    const StencilLaunch& c = s->prec == XLS_PREC_FP32 ? s->cfg32 : s->cfg64;
+    k << i << (s->cur ? 'b' : 'a') << b->st[i].degree << 'p' << b->st[i].gprec << 'q' << b->st[i].pprec << 'l'
+      << b->st[i].lmax << 's' << c.block << '.' << c.ty << '.' << c.tz << '.' << c.nv << ',';
+  }
   return k.str();
 }
 
@@ -347,35 +353,36 @@ std::string shape_key(xls_subdomain_s* s) {
   return o.str();
 }
 
-std::map<std::string, std::pair<int, int>> read_cache(const char* path) {
-  std::map<std::string, std::pair<int, int>> m;
+// tile shape of a class: block threads, rows per tile, vectors per tile
+using Shape = std::array<int, 3>;
+
+std::map<std::string, Shape> read_cache(const char* path) {
+  std::map<std::string, Shape> m;
   if (!path) return m;
   std::ifstream f(path);
   std::string line;
   while (std::getline(f, line)) {
-    // lines of the form  "key": [block, ty],
-    const size_t q0 = line.find('"'), q1 = line.find('"', q0 + 1), lb = line.find('['), cm = line.find(',', lb),
+    // lines of the form  "key": [block, ty, nv],
+    const size_t q0 = line.find('"'), q1 = line.find('"', q0 + 1), lb = line.find('['),
                  rb = line.find(']', lb);
-    if (q0 == std::string::npos || q1 == std::string::npos || lb == std::string::npos ||
-        cm == std::string::npos || rb == std::string::npos)
+    if (q0 == std::string::npos || q1 == std::string::npos || lb == std::string::npos || rb == std::string::npos)
       continue;
-    try {
-      m[line.substr(q0 + 1, q1 - q0 - 1)] = {std::stoi(line.substr(lb + 1, cm - lb - 1)),
-                                            std::stoi(line.substr(cm + 1, rb - cm - 1))};
-    } catch (...) {
-    }
+    std::istringstream in(line.substr(lb + 1, rb - lb - 1));
+    Shape v{0, 0, 0};
+    char sep = 0;
+    if (in >> v[0] >> sep >> v[1] >> sep >> v[2]) m[line.substr(q0 + 1, q1 - q0 - 1)] = v;
   }
   return m;
 }
 
-void write_cache(const char* path, const std::map<std::string, std::pair<int, int>>& m) {
+void write_cache(const char* path, const std::map<std::string, Shape>& m) {
   if (!path) return;
   std::ofstream f(path);
   if (!f) fail(XLS_ERR_INVALID_ARG, std::string("cannot write tuning cache ") + path);
   f << "{\n";
   size_t k = 0;
   for (const auto& e : m)
-    f << "  \"" << e.first << "\": [" << e.second.first << ", " << e.second.second << "]"
+    f << "  \"" << e.first << "\": [" << e.second[0] << ", " << e.second[1] << ", " << e.second[2] << "]"
       << (++k < m.size() ? ",\n" : "\n");
   f << "}\n";
 }
@@ -406,7 +413,7 @@ double time_filter(xls_subdomain_s* s, const StencilLaunch& cfg, hipEvent_t e0, 
 template <typename TS>
 int tune_batch(xls_batch_s* b, const char* cache_path, double* best_ms_out) {
   auto cache = read_cache(cache_path);
-  std::map<std::string, std::pair<int, int>> chosen;
+  std::map<std::string, Shape> chosen;
   std::map<std::string, double> best_ms;
   hipEvent_t e0, e1;
   XLS_HIP(hipEventCreate(&e0));
@@ -423,12 +430,14 @@ int tune_batch(xls_batch_s* b, const char* cache_path, double* best_ms_out) {
       }
       // zero the spare block's Y_{k-1} role: time on the real block's data
       double best = 1e30;
-      std::pair<int, int> arg{256, 0};
+      Shape arg{256, 0, 1};
+      for (int nv : {1, 2})
       for (int block : {256, 512})
         for (int ty : {0, 1, 2, 4, 8, 16}) {
           StencilLaunch cfg = cfg_of<TS>(s);
           cfg.block = block;
           cfg.ty = ty;
+          cfg.nv = nv;
           try {
             stencil_validate(s->n[0], s->n[1], s->n[2], s->bc == XLS_BC_PERIODIC, sizeof(TS), s->nproj(), cfg);
           } catch (const Error&) {
@@ -437,7 +446,7 @@ int tune_batch(xls_batch_s* b, const char* cache_path, double* best_ms_out) {
           const double ms = time_filter<TS>(s, cfg, e0, e1);
           if (ms < best) {
             best = ms;
-            arg = {block, ty};
+            arg = {block, ty, nv};
           }
         }
       chosen[key] = arg;
@@ -453,7 +462,7 @@ int tune_batch(xls_batch_s* b, const char* cache_path, double* best_ms_out) {
   (void)hipEventDestroy(e1);
   for (auto* s : b->subs) {
     const auto& c = chosen[shape_key(s)];
-    const int rc = xls_subdomain_tune(s, s->prec, c.first, c.second, 0);
+    const int rc = xls_subdomain_tune(s, s->prec, c[0], c[1], 0, c[2]);
     if (rc != XLS_OK) fail(rc, std::string("applying tuned tile shape: ") + xls_last_error());
   }
   for (auto& e : chosen) cache[e.first] = e.second;

@@ -233,6 +233,69 @@ __global__ void tn_reduce_kernel(const double* __restrict__ P, int splits, int M
   C[i + static_cast<int64_t>(j) * ldc] = v;
 }
 
+// The same reduction for square products that are symmetric (only tiles on
+// or above the block diagonal computed) or symmetrized: one block per pair of
+// 16 x 16 output tiles (I, J), I <= J, sums the partials of both tiles in
+// split order into LDS with coalesced reads, then writes both tiles
+// coalesced.  Per element the arithmetic is that of tn_reduce_kernel.
+constexpr int kRedT = 16;
+__global__ __launch_bounds__(256) void tn_reduce_pairs_kernel(const double* __restrict__ P, int splits, int M,
+                                                              int tile, int sym, int symmetrize,
+                                                              double* __restrict__ C, int64_t ldc, int nt) {
+  __shared__ double a[kRedT][kRedT + 1], b[kRedT][kRedT + 1];
+  int p = static_cast<int>(blockIdx.x), I = 0;
+  while (p >= nt - I) {
+    p -= nt - I;
+    ++I;
+  }
+  const int J = I + p;
+  const int r = threadIdx.x % kRedT, c = threadIdx.x / kRedT;
+  const int64_t MN = static_cast<int64_t>(M) * M;
+  const int ai = I * kRedT + r, aj = J * kRedT + c;  // a[r][c] = P(ai, aj)
+  const int bi = J * kRedT + r, bj = I * kRedT + c;  // b[r][c] = P(bi, bj)
+  const bool va = ai < M && aj < M, vb = bi < M && bj < M;
+  const double* pa = P + ai + static_cast<int64_t>(aj) * M;
+  const double* pb = P + bi + static_cast<int64_t>(bj) * M;
+  double sa = 0.0, sb = 0.0;
+  for (int sp = 0; sp < splits; ++sp) {
+    if (va) sa += pa[sp * MN];
+    if (vb) sb += pb[sp * MN];
+  }
+  a[r][c] = sa;
+  b[r][c] = sb;
+  __syncthreads();
+  // element (x, y) of the product: P(x, y), or P(y, x) where a symmetric
+  // product kept only the upper block triangle
+  {
+    const int i = ai, j = aj;  // output (i, j): row in tile I, column in tile J
+    const double vij = (sym && i / tile > j / tile) ? b[c][r] : a[r][c];
+    const double vji = (sym && j / tile > i / tile) ? a[r][c] : b[c][r];
+    if (va) C[i + static_cast<int64_t>(j) * ldc] = symmetrize ? 0.5 * (vij + vji) : vij;
+  }
+  if (I != J) {
+    const int i = bi, j = bj;  // output (i, j): row in tile J, column in tile I
+    const double vij = (sym && i / tile > j / tile) ? a[c][r] : b[r][c];
+    const double vji = (sym && j / tile > i / tile) ? b[r][c] : a[c][r];
+    if (vb) C[i + static_cast<int64_t>(j) * ldc] = symmetrize ? 0.5 * (vij + vji) : vij;
+  }
+}
+
+void launch_tn_reduce(const double* work, int splits, int M, int N, int tile, int sym, int symmetrize, double* C,
+                      int64_t ldc, hipStream_t st) {
+  if ((sym || symmetrize) && M == N) {
+    const int nt = (M + kRedT - 1) / kRedT;
+    const int64_t pairs = static_cast<int64_t>(nt) * (nt + 1) / 2;
+    hipLaunchKernelGGL(tn_reduce_pairs_kernel, dim3(static_cast<unsigned>(pairs)), dim3(256), 0, st, work, splits,
+                       M, tile, sym, symmetrize, C, ldc, nt);
+    XLS_LAUNCH_CHECK("tn_reduce_pairs_kernel");
+    return;
+  }
+  const int64_t tot = static_cast<int64_t>(M) * N;
+  hipLaunchKernelGGL(tn_reduce_kernel, dim3(static_cast<unsigned>((tot + 255) / 256)), dim3(256), 0, st, work,
+                     splits, M, N, tile, sym, symmetrize, C, ldc);
+  XLS_LAUNCH_CHECK("tn_reduce_kernel");
+}
+
 // C[M x N] = A[M x K] B[K x N]; the MFMA computes the transposed tile so that
 // each lane's results run down a column of C (coalesced stores).
 template <typename TIN, typename TB, typename TOUT, int MF, int TILE>
@@ -678,10 +741,7 @@ void tn_dispatch(const TIN* A, int64_t lda, const TIN* B, int64_t ldb, int M, in
     hipLaunchKernelGGL((gemm_tn_big_kernel<TIN, MF>), dim3(static_cast<unsigned>(nb)), dim3(256), 0, st, A, lda,
                        B, ldb, M, N, K, kchunk, tm, tn, sym, work);
     XLS_LAUNCH_CHECK("gemm_tn_big_kernel");
-    const int64_t tot = static_cast<int64_t>(M) * N;
-    hipLaunchKernelGGL(tn_reduce_kernel, dim3(static_cast<unsigned>((tot + 255) / 256)), dim3(256), 0, st, work,
-                       real_splits, M, N, T, sym, symmetrize, C, ldc);
-    XLS_LAUNCH_CHECK("tn_reduce_kernel");
+    launch_tn_reduce(work, real_splits, M, N, T, sym, symmetrize, C, ldc, st);
     return;
   }
   const int tm = (M + kTile - 1) / kTile, tn = (N + kTile - 1) / kTile;
@@ -696,10 +756,7 @@ void tn_dispatch(const TIN* A, int64_t lda, const TIN* B, int64_t ldb, int M, in
   hipLaunchKernelGGL((gemm_tn_kernel<TIN, MF, kTile>), dim3(static_cast<unsigned>(nb)), dim3(256), 0,
                      st, A, lda, B, ldb, M, N, K, kchunk, tm, tn, sym, work);
   XLS_LAUNCH_CHECK("gemm_tn_kernel");
-  const int64_t tot = static_cast<int64_t>(M) * N;
-  hipLaunchKernelGGL(tn_reduce_kernel, dim3(static_cast<unsigned>((tot + 255) / 256)), dim3(256), 0, st,
-                     work, real_splits, M, N, kTile, sym, symmetrize, C, ldc);
-  XLS_LAUNCH_CHECK("tn_reduce_kernel");
+  launch_tn_reduce(work, real_splits, M, N, kTile, sym, symmetrize, C, ldc, st);
 }
 
 }  // namespace

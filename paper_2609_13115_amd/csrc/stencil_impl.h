@@ -40,6 +40,7 @@ struct HArgs {
   const int32_t* rev_aoff;
   int64_t nent;  // reverse-CSR entries
   int32_t nproj;
+  int32_t ncols;
   int32_t nx, ny, nz;
   int64_t ld;
   int32_t periodic;
@@ -165,21 +166,27 @@ __device__ __forceinline__ Ent4<double> load_ent<double>(__amdgpu_buffer_rsrc_t 
 
 // WS: LDS row stride in elements (compile time, so every neighbour read uses
 // an immediate offset); rows hold nx + 2R entries, nx + 2R <= WS.
-// One tile (column, y band, z chunk) given by its logical index; coefficients
-// ca, cc, cb of the fused recurrence.  Shared by the single-operator launch
-// and the grouped persistent launch.
-template <typename TS, typename TC, int MODE, int P, int NT, int WS>
+// One tile (NV consecutive columns, y band, z chunk) given by its logical
+// index; coefficients ca, cc, cb of the fused recurrence.  The NV columns of
+// a tile share the grid geometry, V, the reverse-CSR words and the projector
+// entries, so those tables are read once per NV columns; each column has its
+// own LDS plane buffers, register queue and projection coefficients.  A
+// column index at or beyond ncols gets empty buffer resources (loads read
+// zero, stores drop).  Shared by the single-operator launch and the grouped
+// persistent launch.
+template <typename TS, typename TC, int MODE, int P, int NT, int WS, int NV>
 __device__ __forceinline__ void stencil_tile(const HArgs<TS, TC>& A, uint32_t logical, TC ca, TC cc, TC cb,
                                              unsigned char* smem_raw) {
+  static_assert(NV == 1 || MODE != kResid, "residual sweeps take one column per tile");
   TC* lds = reinterpret_cast<TC*>(smem_raw);
   const int nx = A.nx, ny = A.ny, nz = A.nz;
   constexpr int W = WS;
   const int dumpi = W * (A.ty + 2 * R);  // spare slot at the end of each plane buffer
   const int plane = dumpi + 1;
-  TC* alds = lds + 2 * plane;          // this column's projection coefficients
+  TC* alds = lds + 2 * NV * plane;     // the columns' projection coefficients
 
   const int tiles = A.nyt * A.nzt;
-  const int col = static_cast<int>(logical / tiles);
+  const int col0 = static_cast<int>(logical / tiles) * NV;
   const int t = static_cast<int>(logical % tiles);
   const int yt = t % A.nyt, zt = t / A.nyt;
   const int y0 = yt * A.ty;
@@ -192,18 +199,27 @@ __device__ __forceinline__ void stencil_tile(const HArgs<TS, TC>& A, uint32_t lo
   constexpr int ES = sizeof(TS), EC = sizeof(TC);
 
   const int64_t colbytes = static_cast<int64_t>(nx) * ny * nz * ES;
-  const __amdgpu_buffer_rsrc_t ry = make_rsrc(A.y + static_cast<int64_t>(col) * A.ld, colbytes);
-  const __amdgpu_buffer_rsrc_t rp = make_rsrc(MODE == kFilter && A.has_prev ? A.yprev + static_cast<int64_t>(col) * A.ld
-                                                                            : A.y, colbytes);
-  const __amdgpu_buffer_rsrc_t ro = make_rsrc(MODE == kResid ? A.y : A.out + static_cast<int64_t>(col) * A.ld, colbytes);
+  __amdgpu_buffer_rsrc_t ry[NV], rp[NV], ro[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    const bool live = col0 + v < A.ncols;
+    const int64_t c = live ? col0 + v : col0;
+    const int64_t bytes = live ? colbytes : 0;
+    ry[v] = make_rsrc(A.y + c * A.ld, bytes);
+    // without Y_{k-1} the stream is empty and reads zero
+    rp[v] = make_rsrc(MODE == kFilter && A.has_prev ? A.yprev + c * A.ld : A.y,
+                      MODE == kFilter && A.has_prev ? bytes : 0);
+    ro[v] = make_rsrc(MODE == kResid ? A.y : A.out + c * A.ld, bytes);
+  }
   const __amdgpu_buffer_rsrc_t rv = make_rsrc(A.v, static_cast<int64_t>(nx) * ny * nz * EC);
   const __amdgpu_buffer_rsrc_t rk = make_rsrc(A.rev_pk, static_cast<int64_t>(nx) * ny * nz * 4);
   const __amdgpu_buffer_rsrc_t re = make_rsrc(A.rev_val, static_cast<int64_t>(A.nent + 1) * 4 * EC);
   const __amdgpu_buffer_rsrc_t ra = make_rsrc(A.rev_aoff, static_cast<int64_t>(A.nent + 1) * 4);
 
   // points owned by this lane: in-plane byte offsets per stream element size
-  // (kOOB when inactive) and LDS index
-  int vo[P], os[P], oc[P], o4[P], li[P];
+  // (kOOB when inactive), LDS index written and LDS index read (inactive
+  // slots write the spare cell and read the star of the first point)
+  int vo[P], os[P], oc[P], o4[P], li[P], lr[P];
 #pragma unroll
   for (int i = 0; i < P; ++i) {
     const int lin = tid + i * NT;
@@ -213,7 +229,8 @@ __device__ __forceinline__ void stencil_tile(const HArgs<TS, TC>& A, uint32_t lo
     os[i] = act ? vo[i] * ES : kOOB;
     oc[i] = act ? vo[i] * EC : kOOB;
     o4[i] = act ? vo[i] * 4 : kOOB;
-    li[i] = act ? (R + yy - y0) * W + R + x : dumpi;  // inactive slots write the spare cell
+    li[i] = act ? (R + yy - y0) * W + R + x : dumpi;
+    lr[i] = (R + yy - y0) * W + R + x;
   }
 
   // halo cells of a plane (y-halo rows, then periodic x-halo columns): LDS
@@ -235,10 +252,10 @@ __device__ __forceinline__ void stencil_tile(const HArgs<TS, TC>& A, uint32_t lo
         hl[j] = (r < R ? r : R + tyv + (r - R)) * W + R + x;
       } else {
         const int e2 = e - nhy;
-        const int row = e2 / (2 * R), cc = e2 % (2 * R);
-        x = cc < R ? cc - R : nx + (cc - R);
+        const int row = e2 / (2 * R), c2 = e2 % (2 * R);
+        x = c2 < R ? c2 - R : nx + (c2 - R);
         yy = y0 + row;
-        hl[j] = (R + row) * W + (cc < R ? cc : nx + cc);
+        hl[j] = (R + row) * W + (c2 < R ? c2 : nx + c2);
       }
       if (A.periodic)
         hoff[j] = (wrapi(x, nx) + nx * wrapi(yy, ny)) * ES;
@@ -247,18 +264,20 @@ __device__ __forceinline__ void stencil_tile(const HArgs<TS, TC>& A, uint32_t lo
     }
   }
 
-  // Dirichlet: x-halo columns are zero for every plane; clear both buffers once
+  // Dirichlet: x-halo columns are zero for every plane; clear every buffer once
   if (!A.periodic) {
     const int nxh = 2 * R * (A.ty + 2 * R);
-    for (int e = tid; e < 2 * nxh; e += NT) {
+    for (int e = tid; e < 2 * NV * nxh; e += NT) {
       const int b = e / nxh, r = e % nxh;
-      const int row = r / (2 * R), cc = r % (2 * R);
-      lds[b * plane + row * W + (cc < R ? cc : nx + cc)] = TC(0);
+      const int row = r / (2 * R), c2 = r % (2 * R);
+      lds[b * plane + row * W + (c2 < R ? c2 : nx + c2)] = TC(0);
     }
   }
-  {
-    const TC* __restrict__ ac = A.alpha + static_cast<int64_t>(col) * A.nproj;
-    for (int e = tid; e < A.nproj; e += NT) alds[e] = ac[e];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    const bool live = col0 + v < A.ncols;
+    const TC* __restrict__ ac = A.alpha + static_cast<int64_t>(live ? col0 + v : col0) * A.nproj;
+    for (int e = tid; e < A.nproj; e += NT) alds[v * A.nproj + e] = live ? ac[e] : TC(0);
   }
 
   // plane index of plane zz for the queue (wrapped when periodic), or -1
@@ -268,28 +287,31 @@ __device__ __forceinline__ void stencil_tile(const HArgs<TS, TC>& A, uint32_t lo
     if (!A.periodic) return -1;
     return wrapi(zz, nz);
   };
-  auto ldq = [&](int i, int zq) -> TC {
-    return zq < 0 ? TC(0) : static_cast<TC>(bload<TS>(ry, os[i], zq * pp * ES));
+  auto ldq = [&](int i, int v, int zq) -> TC {
+    return zq < 0 ? TC(0) : static_cast<TC>(bload<TS>(ry[v], os[i], zq * pp * ES));
   };
 
-  // register queue: q[i][slot] holds plane z - R + ((slot - ph) mod Q) while
-  // plane z is computed at phase ph = (z - z0) mod Q, so the queue advances by
-  // renaming (the z-loop is unrolled Q times) instead of moving registers
-  TC q[P][Q];
+  // register queue: q[i][v][slot] holds plane z - R + ((slot - ph) mod Q)
+  // while plane z is computed at phase ph = (z - z0) mod Q, so the queue
+  // advances by renaming (the z-loop is unrolled Q times) instead of moving
+  // registers
+  TC q[P][NV][Q];
 #pragma unroll
   for (int s = 0; s < Q - 1; ++s) {
     const int zq = qplane(z0 - R + s);
 #pragma unroll
-    for (int i = 0; i < P; ++i) q[i][s] = ldq(i, zq);
+    for (int i = 0; i < P; ++i)
+#pragma unroll
+      for (int v = 0; v < NV; ++v) q[i][v][s] = ldq(i, v, zq);
   }
 
   // prefetch registers.  Two planes ahead: the queue front fr (plane z+1+R
   // while computing z) and Y_{k-1} yp2; the reverse-CSR word rp2.  One plane
   // ahead: q's newest slot, V, Y_{k-1}, the entry payload, the halo cells.
-  TC fr[P], yp1[P], yp2[P], vn[P];
+  TC fr[P][NV], yp1[P][NV], yp2[P][NV], vn[P];
   int rp1[P], rp2[P], ea[P];
   Ent4<TC> ev[P];
-  TC hv[HMAX];
+  TC hv[NV][HMAX];
   auto load_rest = [&](int z) {  // V, entry payload, rev word (z+1) of plane z
     const int so = z * pp;
 #pragma unroll
@@ -299,104 +321,131 @@ __device__ __forceinline__ void stencil_tile(const HArgs<TS, TC>& A, uint32_t lo
       const int e0 = rp1[i] & EMASK;  // points without projectors name the zero sentinel
       ev[i] = load_ent<TC>(re, e0 * 4 * EC);
       ea[i] = bload<int>(ra, e0 * 4, 0);
-      rp2[i] = (z + 1 < z1) ? bload<int>(rk, o4[i], (so + pp) * 4) : static_cast<int>(A.nent);
+      if (z + 1 < z1) rp2[i] = bload<int>(rk, o4[i], (so + pp) * 4);  // else unused
     }
   };
   {
     const int zq0 = qplane(z0 + R), zq1 = qplane(z0 + 1 + R);
 #pragma unroll
     for (int i = 0; i < P; ++i) {
-      q[i][Q - 1] = ldq(i, zq0);
-      fr[i] = ldq(i, zq1);
-      rp2[i] = bload<int>(rk, o4[i], z0 * pp * 4);
-      if (MODE == kFilter) {
-        yp1[i] = A.has_prev ? static_cast<TC>(bload<TS>(rp, os[i], z0 * pp * ES)) : TC(0);
-        yp2[i] = (A.has_prev && z0 + 1 < z1) ? static_cast<TC>(bload<TS>(rp, os[i], (z0 + 1) * pp * ES)) : TC(0);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        q[i][v][Q - 1] = ldq(i, v, zq0);
+        fr[i][v] = ldq(i, v, zq1);
+        if (MODE == kFilter) {
+          yp1[i][v] = static_cast<TC>(bload<TS>(rp[v], os[i], z0 * pp * ES));
+          yp2[i][v] = TC(0);
+          if (z0 + 1 < z1) yp2[i][v] = static_cast<TC>(bload<TS>(rp[v], os[i], (z0 + 1) * pp * ES));
+        }
       }
+      rp2[i] = bload<int>(rk, o4[i], z0 * pp * 4);
     }
   }
   load_rest(z0);
 #pragma unroll
-  for (int j = 0; j < HMAX; ++j) hv[j] = static_cast<TC>(bload<TS>(ry, hoff[j], z0 * pp * ES));
+  for (int v = 0; v < NV; ++v)
+#pragma unroll
+    for (int j = 0; j < HMAX; ++j) hv[v][j] = static_cast<TC>(bload<TS>(ry[v], hoff[j], z0 * pp * ES));
 
   double racc = 0.0;
-  const double lamc = (MODE == kResid) ? A.lam[col] : 0.0;
+  const double lamc = (MODE == kResid) ? A.lam[col0] : 0.0;
 
   // one plane at compile-time phase PH
   auto step = [&](auto phc, int z) {
     constexpr int PH = decltype(phc)::value;
     auto QS = [](int s2) { return (s2 + PH) % Q; };  // physical slot of logical s2
-    TC* buf = lds + (z & 1) * plane;
+    TC* buf = lds + (z & 1) * plane;  // column v's buffer: buf + 2 v plane
     // (a) centre plane and its halo into LDS
 #pragma unroll
-    for (int i = 0; i < P; ++i) buf[li[i]] = q[i][QS(R)];
+    for (int v = 0; v < NV; ++v) {
 #pragma unroll
-    for (int j = 0; j < HMAX; ++j) buf[hl[j]] = hv[j];
+      for (int i = 0; i < P; ++i) buf[2 * v * plane + li[i]] = q[i][v][QS(R)];
+#pragma unroll
+      for (int j = 0; j < HMAX; ++j) buf[2 * v * plane + hl[j]] = hv[v][j];
+    }
     // (b) next plane's halo
     if (z + 1 < z1) {
       const int so1 = (z + 1) * pp * ES;
 #pragma unroll
-      for (int j = 0; j < HMAX; ++j) hv[j] = static_cast<TC>(bload<TS>(ry, hoff[j], so1));
+      for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int j = 0; j < HMAX; ++j) hv[v][j] = static_cast<TC>(bload<TS>(ry[v], hoff[j], so1));
     }
     lds_barrier();
     // (c) plane z
     const int so = z * pp * ES;
 #pragma unroll
     for (int i = 0; i < P; ++i) {
-      // based at the point's lowest neighbour behind an opaque register, so
-      // every LDS offset is a non-negative immediate (measured faster)
-      constexpr int C0 = R * W + R;
-      int lo = li[i] - C0;
-      asm("" : "+v"(lo));
-      const TC* bq = buf + lo;
-      const TC ctr = q[i][QS(R)];
-      TC lap = A.wc * ctr;
+      // two bases behind opaque registers, the row and the column of the
+      // star: every LDS offset is then a small non-negative immediate (the
+      // row's pair up in ds_read2; with W a multiple of 64 the column's pair
+      // up in ds_read2st64), so no per-read address arithmetic remains
+      int bxi = lr[i] - R, byi = lr[i] - R * W;
+      asm("" : "+v"(bxi));
+      asm("" : "+v"(byi));
+      TC hy[NV];
 #pragma unroll
-      for (int p = 1; p <= R; ++p) {
-        const TC sm = (bq[C0 + p] + bq[C0 - p]) + (bq[C0 + p * W] + bq[C0 - p * W]) +
-                      (q[i][QS(R + p)] + q[i][QS(R - p)]);
-        lap += A.w[p - 1] * sm;
-      }
-      TC hy = lap + vn[i] * ctr;
-      {  // one projector set per point is prefetched (absent: zero payload)
-        const TC* al = alds + ea[i];
-        hy += ev[i].v[0] * al[0] + ev[i].v[1] * al[1] + ev[i].v[2] * al[2] + ev[i].v[3] * al[3];
+      for (int v = 0; v < NV; ++v) {
+        const TC* bx = buf + 2 * v * plane + bxi;
+        const TC* by = buf + 2 * v * plane + byi;
+        const TC ctr = q[i][v][QS(R)];
+        TC lap = A.wc * ctr;
+#pragma unroll
+        for (int p = 1; p <= R; ++p) {
+          const TC sm = (bx[R + p] + bx[R - p]) + (by[(R + p) * W] + by[(R - p) * W]) +
+                        (q[i][v][QS(R + p)] + q[i][v][QS(R - p)]);
+          lap += A.w[p - 1] * sm;
+        }
+        hy[v] = lap + vn[i] * ctr;
+        // one projector set per point is prefetched (absent: zero payload)
+        const TC* al = alds + v * A.nproj + ea[i];
+        hy[v] += ev[i].v[0] * al[0] + ev[i].v[1] * al[1] + ev[i].v[2] * al[2] + ev[i].v[3] * al[3];
       }
       const int ne = static_cast<int>(static_cast<uint32_t>(rp1[i]) >> 27);
       if (ne > 1) {  // rare: overlapping projector sets
         const int e0 = rp1[i] & EMASK;
         for (int e = e0 + 1; e < e0 + ne; ++e) {
           const TC* sv = A.rev_val + 4 * static_cast<int64_t>(e);
-          const TC* a2 = alds + A.rev_aoff[e];
-          hy += sv[0] * a2[0] + sv[1] * a2[1] + sv[2] * a2[2] + sv[3] * a2[3];
+          const int ao = A.rev_aoff[e];
+#pragma unroll
+          for (int v = 0; v < NV; ++v) {
+            const TC* a2 = alds + v * A.nproj + ao;
+            hy[v] += sv[0] * a2[0] + sv[1] * a2[1] + sv[2] * a2[2] + sv[3] * a2[3];
+          }
         }
       }
-      if (MODE == kApply) {
-        bstore(static_cast<TS>(hy), ro, os[i], so);
-      } else if (MODE == kFilter) {
-        const TC r = ca * (hy - cc * ctr) - cb * yp1[i];
-        bstore(static_cast<TS>(r), ro, os[i], so);
-      } else if (vo[i] >= 0) {
-        const double d = static_cast<double>(hy) - lamc * static_cast<double>(ctr);
-        racc += d * d;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        if (MODE == kApply) {
+          bstore(static_cast<TS>(hy[v]), ro[v], os[i], so);
+        } else if (MODE == kFilter) {
+          const TC r = ca * (hy[v] - cc * q[i][v][QS(R)]) - cb * yp1[i][v];
+          bstore(static_cast<TS>(r), ro[v], os[i], so);
+        } else if (vo[i] >= 0) {
+          const double d = static_cast<double>(hy[v]) - lamc * static_cast<double>(q[i][v][QS(R)]);
+          racc += d * d;
+        }
       }
     }
     // (d) advance: the oldest slot takes the next front; refill the
     // registers just consumed
 #pragma unroll
-    for (int i = 0; i < P; ++i) {
-      q[i][QS(0)] = fr[i];
-      if (MODE == kFilter) yp1[i] = yp2[i];
-    }
+    for (int i = 0; i < P; ++i)
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        q[i][v][QS(0)] = fr[i][v];
+        if (MODE == kFilter) yp1[i][v] = yp2[i][v];
+      }
     if (z + 1 < z1) {
       const int zq = qplane(z + 2 + R);
       const int so2 = (z + 2) * pp * ES;
 #pragma unroll
-      for (int i = 0; i < P; ++i) {
-        fr[i] = ldq(i, zq);
-        if (MODE == kFilter)
-          yp2[i] = (A.has_prev && z + 2 < z1) ? static_cast<TC>(bload<TS>(rp, os[i], so2)) : TC(0);
-      }
+      for (int i = 0; i < P; ++i)
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          fr[i][v] = ldq(i, v, zq);
+          if (MODE == kFilter && z + 2 < z1) yp2[i][v] = static_cast<TC>(bload<TS>(rp[v], os[i], so2));
+        }
       load_rest(z + 1);
     }
   };
@@ -417,7 +466,6 @@ __device__ __forceinline__ void stencil_tile(const HArgs<TS, TC>& A, uint32_t lo
     if (z + 11 < z1) step(integral_constant<int, 11>{}, z + 11); else break;
     if (z + 12 < z1) step(integral_constant<int, 12>{}, z + 12); else break;
   }
-
   if (MODE == kResid) {
     // deterministic block reduction: fixed shuffle tree, then fixed LDS order
     __syncthreads();
@@ -429,15 +477,15 @@ __device__ __forceinline__ void stencil_tile(const HArgs<TS, TC>& A, uint32_t lo
     if (tid == 0) {
       double sacc = 0.0;
       for (int w = 0; w < NT / 64; ++w) sacc += red[w];
-      A.partial[static_cast<int64_t>(col) * tiles + t] = sacc;
+      A.partial[static_cast<int64_t>(col0) * tiles + t] = sacc;
     }
   }
 }
 
-template <typename TS, typename TC, int MODE, int P, int NT, int WS>
+template <typename TS, typename TC, int MODE, int P, int NT, int WS, int NV>
 __global__ __launch_bounds__(NT) void hstencil_kernel(HArgs<TS, TC> A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  stencil_tile<TS, TC, MODE, P, NT, WS>(A, xcd_remap(blockIdx.x, gridDim.x), A.a, A.c, A.b, smem_raw);
+  stencil_tile<TS, TC, MODE, P, NT, WS, NV>(A, xcd_remap(blockIdx.x, gridDim.x), A.a, A.c, A.b, smem_raw);
 }
 
 // Grouped persistent filter step over many operators: item = (operator,
@@ -445,7 +493,7 @@ __global__ __launch_bounds__(NT) void hstencil_kernel(HArgs<TS, TC> A) {
 // xcd remap gives the workgroups of one XCD consecutive items, so the tiles
 // that share halo rows meet in the same L2.  Step k reads its recurrence
 // coefficients from the operator's device table.
-template <typename TS, typename TC, int P, int NT, int WS>
+template <typename TS, typename TC, int P, int NT, int WS, int NV>
 __global__ __launch_bounds__(NT) void hstencil_group_kernel(const HArgs<TS, TC>* __restrict__ tab,
                                                             const uint2* __restrict__ items, int nitems,
                                                             int k) {
@@ -455,7 +503,7 @@ __global__ __launch_bounds__(NT) void hstencil_group_kernel(const HArgs<TS, TC>*
     const uint2 w = items[it];
     const HArgs<TS, TC> A = tab[w.x];
     const double* cf = A.coef + 3 * k;
-    stencil_tile<TS, TC, kFilter, P, NT, WS>(A, w.y, static_cast<TC>(cf[0]), static_cast<TC>(cf[1]),
+    stencil_tile<TS, TC, kFilter, P, NT, WS, NV>(A, w.y, static_cast<TC>(cf[0]), static_cast<TC>(cf[1]),
                                              static_cast<TC>(cf[2]), smem_raw);
     __syncthreads();
   }
@@ -510,21 +558,34 @@ __device__ __forceinline__ void proj_forward_wave(const TS* __restrict__ y, int6
       }
     }
   }
+  // Reduction of the 16 sums by recursive halving: at offsets 32, 16, 8, 4 a
+  // lane keeps half of its values, each added to its partner's copy (the
+  // pairs and operand order of a full xor-shuffle tree, so every sum is
+  // bit-identical to it, in 32 shuffles instead of 96); offsets 2 and 1
+  // finish, and lane 4 v holds sum v = 4 c + l.  Both halves are shuffled
+  // and the kept sum selected, so no register array is indexed at run time.
+  double r[kProjCols * 4];
 #pragma unroll
   for (int c = 0; c < kProjCols; ++c)
 #pragma unroll
-    for (int l = 0; l < 4; ++l)
-      for (int off = 32; off > 0; off >>= 1) acc[c][l] += __shfl_xor(acc[c][l], off, 64);
-  if (lane == 0) {
+    for (int l = 0; l < 4; ++l) r[4 * c + l] = acc[c][l];
 #pragma unroll
-    for (int c = 0; c < kProjCols; ++c) {
-      if (c < nc) {
-        TC* o = alpha + static_cast<int64_t>(cbase + c) * nproj + 4 * a;
+  for (int lev = 0; lev < 4; ++lev) {
+    const int off = 32 >> lev, half = 8 >> lev;
+    const bool up = (lane & off) != 0;
 #pragma unroll
-        for (int l = 0; l < 4; ++l) o[l] = static_cast<TC>(gamma[4 * a + l] * h3 * acc[c][l]);
-      }
+    for (int j = 0; j < half; ++j) {
+      const double lo = r[j] + __shfl_xor(r[j], off, 64);
+      const double hi = r[j + half] + __shfl_xor(r[j + half], off, 64);
+      r[j] = up ? hi : lo;
     }
   }
+  double t = r[0];
+  t += __shfl_xor(t, 2, 64);
+  t += __shfl_xor(t, 1, 64);
+  const int vi = lane >> 2, c = vi >> 2, l = vi & 3;
+  if ((lane & 3) == 0 && c < nc)
+    alpha[static_cast<int64_t>(cbase + c) * nproj + 4 * a + l] = static_cast<TC>(gamma[4 * a + l] * h3 * t);
 }
 
 template <typename TS, typename TC>
@@ -571,7 +632,7 @@ __global__ __launch_bounds__(256) void proj_forward_group_kernel(const PArgs<TS,
 }
 
 struct TileChoice {
-  int block, ty, nyt, tz, nzt, P, ws;
+  int block, ty, nyt, tz, nzt, P, ws, nv;
   bool vec;
   size_t smem;
 };
@@ -605,7 +666,8 @@ inline TileChoice choose_tiles(int nx, int ny, int nz, int elem, int nproj, int6
   tc.nzt = (nz + tc.tz - 1) / tc.tz;
   tc.P = tc.vec ? 1 : (nx * ty + tc.block - 1) / tc.block;
   tc.ws = (nx + 2 * R <= 80) ? 80 : 128;
-  tc.smem = static_cast<size_t>(elem) * (2 * (static_cast<size_t>(tc.ws) * (ty + 2 * R) + 1) + nproj);
+  tc.nv = cfg.nv > 0 ? cfg.nv : 1;
+  tc.smem = static_cast<size_t>(elem) * tc.nv * (2 * (static_cast<size_t>(tc.ws) * (ty + 2 * R) + 1) + nproj);
   return tc;
 }
 
@@ -613,6 +675,7 @@ inline void check_tiles(const TileChoice& tc, int nx, int periodic, int elem) {
   {
     if (nx + 2 * R > 128) fail(XLS_ERR_INVALID_ARG, "grid x extent must be <= 116");
     if (tc.P > 2) fail(XLS_ERR_INVALID_ARG, "stencil tile needs more than 2 points per thread");
+    if (tc.nv != 1 && tc.nv != 2) fail(XLS_ERR_INVALID_ARG, "stencil vectors per tile must be 1 or 2");
     const int halo = 2 * R * nx + (periodic ? 2 * R * tc.ty : 0);
     if (halo > HMAX * tc.block) fail(XLS_ERR_INVALID_ARG, "stencil halo exceeds the per-thread budget");
   }
@@ -624,23 +687,34 @@ void allow_smem(K kern, size_t smem) {
   ensure_dyn_smem(reinterpret_cast<const void*>(kern), smem);
 }
 
-template <typename TS, typename TC, int MODE, int P, int WS>
+template <typename TS, typename TC, int MODE, int P, int WS, int NV>
 void launch_mode(const HArgs<TS, TC>& args, dim3 grid, int block, size_t smem, hipStream_t st) {
   if (block == 256) {
-    allow_smem(hstencil_kernel<TS, TC, MODE, P, 256, WS>, smem);
-    hipLaunchKernelGGL((hstencil_kernel<TS, TC, MODE, P, 256, WS>), grid, dim3(256), smem, st, args);
+    allow_smem(hstencil_kernel<TS, TC, MODE, P, 256, WS, NV>, smem);
+    hipLaunchKernelGGL((hstencil_kernel<TS, TC, MODE, P, 256, WS, NV>), grid, dim3(256), smem, st, args);
   } else {
-    allow_smem(hstencil_kernel<TS, TC, MODE, P, 512, WS>, smem);
-    hipLaunchKernelGGL((hstencil_kernel<TS, TC, MODE, P, 512, WS>), grid, dim3(512), smem, st, args);
+    allow_smem(hstencil_kernel<TS, TC, MODE, P, 512, WS, NV>, smem);
+    hipLaunchKernelGGL((hstencil_kernel<TS, TC, MODE, P, 512, WS, NV>), grid, dim3(512), smem, st, args);
+  }
+}
+
+template <typename TS, typename TC, int MODE, int WS, int NV>
+void launch_pnv(const TileChoice& tc, const HArgs<TS, TC>& args, dim3 grid, size_t smem, hipStream_t st) {
+  switch (tc.P) {
+    case 1: launch_mode<TS, TC, MODE, 1, WS, NV>(args, grid, tc.block, smem, st); break;
+    case 2: launch_mode<TS, TC, MODE, 2, WS, NV>(args, grid, tc.block, smem, st); break;
+    default: fail(XLS_ERR_INVALID_ARG, "stencil tile needs more than 2 points per thread");
   }
 }
 
 template <typename TS, typename TC, int MODE, int WS>
 void launch_ws(const TileChoice& tc, const HArgs<TS, TC>& args, dim3 grid, size_t smem, hipStream_t st) {
-  switch (tc.P) {
-    case 1: launch_mode<TS, TC, MODE, 1, WS>(args, grid, tc.block, smem, st); break;
-    case 2: launch_mode<TS, TC, MODE, 2, WS>(args, grid, tc.block, smem, st); break;
-    default: fail(XLS_ERR_INVALID_ARG, "stencil tile needs more than 2 points per thread");
+  if (tc.nv == 1) {
+    launch_pnv<TS, TC, MODE, WS, 1>(tc, args, grid, smem, st);
+  } else if constexpr (MODE != kResid) {
+    launch_pnv<TS, TC, MODE, WS, 2>(tc, args, grid, smem, st);
+  } else {
+    fail(XLS_ERR_INVALID_ARG, "residual sweeps take one vector per tile");
   }
 }
 
@@ -681,6 +755,7 @@ void stencil_validate(int nx, int ny, int nz, int periodic, int elem_bytes, int 
                       const StencilLaunch& cfg) {
   if (cfg.block != 256 && cfg.block != 512) fail(XLS_ERR_INVALID_ARG, "stencil block must be 256 or 512");
   if (cfg.ty < 0 || cfg.tz < 0) fail(XLS_ERR_INVALID_ARG, "stencil tile sizes must be >= 0");
+  if (cfg.nv < 0 || cfg.nv > 2) fail(XLS_ERR_INVALID_ARG, "stencil vectors per tile must be 0, 1 or 2");
   // both variants a launch may take (vector runs need an aligned column stride)
   check_tiles(choose_tiles(nx, ny, nz, elem_bytes, nproj, 64, cfg), nx, periodic, elem_bytes);
   check_tiles(choose_tiles(nx, ny, nz, elem_bytes, nproj, 1, cfg), nx, periodic, elem_bytes);
@@ -701,7 +776,7 @@ size_t stencil_partial_elems(const OpTables<double>& op, int ncols, const Stenci
 // residual outputs and has_prev are set by the caller).
 template <typename TS, typename TC>
 static HArgs<TS, TC> make_hargs(const OpTables<TC>& op, const TileChoice& tc, const TS* y, int64_t ld,
-                                const TC* alpha, TS* out, const TS* yprev) {
+                                int ncols, const TC* alpha, TS* out, const TS* yprev) {
   HArgs<TS, TC> A{};
   A.y = y;
   A.yprev = yprev;
@@ -713,6 +788,7 @@ static HArgs<TS, TC> make_hargs(const OpTables<TC>& op, const TileChoice& tc, co
   A.rev_aoff = op.rev_aoff;
   A.nent = op.nent;
   A.nproj = 4 * op.n_atoms;
+  A.ncols = ncols;
   A.nx = op.nx;
   A.ny = op.ny;
   A.nz = op.nz;
@@ -736,16 +812,18 @@ void launch_stencil(StencilMode mode, const OpTables<TC>& op, const TS* y, int64
                     const double* lam, double* partial, double* resid2, hipStream_t st,
                     const StencilLaunch& cfg) {
   if (ncols <= 0) return;
-  const TileChoice tc = tiles_for(op, ld, cfg);
+  StencilLaunch cfg1 = cfg;
+  if (mode == kResid) cfg1.nv = 1;  // per-column partial sums
+  const TileChoice tc = tiles_for(op, ld, cfg1);
   check_tiles(tc, op.nx, op.periodic, sizeof(TC));
-  HArgs<TS, TC> A = make_hargs<TS, TC>(op, tc, y, ld, alpha, out, yprev);
+  HArgs<TS, TC> A = make_hargs<TS, TC>(op, tc, y, ld, ncols, alpha, out, yprev);
   A.a = static_cast<TC>(a);
   A.c = static_cast<TC>(c);
   A.b = static_cast<TC>(b);
   A.has_prev = (yprev != nullptr && b != 0.0) ? 1 : 0;
   A.lam = lam;
   A.partial = partial;
-  const int64_t nblocks = static_cast<int64_t>(ncols) * tc.nyt * tc.nzt;
+  const int64_t nblocks = static_cast<int64_t>((ncols + tc.nv - 1) / tc.nv) * tc.nyt * tc.nzt;
   if (nblocks > 0x7fffffff) fail(XLS_ERR_INVALID_ARG, "too many stencil tiles");
   size_t smem = tc.smem;
   if (mode == kResid) smem = std::max(smem, static_cast<size_t>(64 * sizeof(double)));
@@ -801,7 +879,7 @@ inline void group_release(void* p) {
 template <typename TS>
 struct FilterGroup {
   struct Bucket {
-    int P = 1, block = 256, ws = 80;
+    int P = 1, block = 256, ws = 80, nv = 1;
     size_t smem = 0;
     uint2* items = nullptr;
     std::vector<int> count;  // items taking part in step k
@@ -816,36 +894,54 @@ struct FilterGroup {
   int steps = 0;
 };
 
-template <typename TS, int P, int NT, int WS>
+template <typename TS, int P, int NT, int WS, int NV>
 int group_occupancy(size_t smem) {
-  allow_smem(hstencil_group_kernel<TS, TS, P, NT, WS>, smem);
+  allow_smem(hstencil_group_kernel<TS, TS, P, NT, WS, NV>, smem);
   int nb = 0;
   XLS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-      &nb, reinterpret_cast<const void*>(hstencil_group_kernel<TS, TS, P, NT, WS>), NT, smem));
+      &nb, reinterpret_cast<const void*>(hstencil_group_kernel<TS, TS, P, NT, WS, NV>), NT, smem));
   return std::max(1, nb);
 }
 
-template <typename TS, int P, int WS>
-int group_occ_block(int block, size_t smem) {
-  return block == 256 ? group_occupancy<TS, P, 256, WS>(smem) : group_occupancy<TS, P, 512, WS>(smem);
+// one grouped launch shape: calls f with compile-time (P, WS, NV) of bucket b
+template <typename F>
+void group_dispatch(int P, int ws, int nv, F&& f) {
+  using std::integral_constant;
+  auto by_nv = [&](auto pc, auto wc) {
+    if (nv == 1) f(pc, wc, integral_constant<int, 1>{});
+    else f(pc, wc, integral_constant<int, 2>{});
+  };
+  auto by_ws = [&](auto pc) {
+    if (ws == 80) by_nv(pc, integral_constant<int, 80>{});
+    else by_nv(pc, integral_constant<int, 128>{});
+  };
+  if (P == 1) by_ws(integral_constant<int, 1>{});
+  else by_ws(integral_constant<int, 2>{});
 }
 
 template <typename TS>
-int group_occ(int P, int block, int ws, size_t smem) {
-  if (ws == 80) return P == 1 ? group_occ_block<TS, 1, 80>(block, smem) : group_occ_block<TS, 2, 80>(block, smem);
-  return P == 1 ? group_occ_block<TS, 1, 128>(block, smem) : group_occ_block<TS, 2, 128>(block, smem);
+int group_occ(int P, int block, int ws, int nv, size_t smem) {
+  int nb = 1;
+  group_dispatch(P, ws, nv, [&](auto pc, auto wc, auto vc) {
+    constexpr int PP = decltype(pc)::value, WW = decltype(wc)::value, VV = decltype(vc)::value;
+    nb = block == 256 ? group_occupancy<TS, PP, 256, WW, VV>(smem) : group_occupancy<TS, PP, 512, WW, VV>(smem);
+  });
+  return nb;
 }
 
-template <typename TS, int P, int WS>
-void group_launch_pw(const typename FilterGroup<TS>::Bucket& b, const HArgs<TS, TS>* tab, int n, int k,
-                     hipStream_t st) {
+template <typename TS>
+void group_launch(const typename FilterGroup<TS>::Bucket& b, const HArgs<TS, TS>* tab, int n, int k,
+                  hipStream_t st) {
   const dim3 grid(static_cast<unsigned>(std::min(n, b.grid_cap)));
-  if (b.block == 256)
-    hipLaunchKernelGGL((hstencil_group_kernel<TS, TS, P, 256, WS>), grid, dim3(256), b.smem, st, tab, b.items, n,
-                       k);
-  else
-    hipLaunchKernelGGL((hstencil_group_kernel<TS, TS, P, 512, WS>), grid, dim3(512), b.smem, st, tab, b.items, n,
-                       k);
+  group_dispatch(b.P, b.ws, b.nv, [&](auto pc, auto wc, auto vc) {
+    constexpr int PP = decltype(pc)::value, WW = decltype(wc)::value, VV = decltype(vc)::value;
+    if (b.block == 256)
+      hipLaunchKernelGGL((hstencil_group_kernel<TS, TS, PP, 256, WW, VV>), grid, dim3(256), b.smem, st, tab,
+                         b.items, n, k);
+    else
+      hipLaunchKernelGGL((hstencil_group_kernel<TS, TS, PP, 512, WW, VV>), grid, dim3(512), b.smem, st, tab,
+                         b.items, n, k);
+  });
 }
 
 template <typename TS>
@@ -877,13 +973,15 @@ FilterGroup<TS>* filter_group_build(const std::vector<FilterGroupOp<TS>>& ops) {
       int bi = -1;
       for (size_t j = 0; j < g->buckets.size(); ++j) {
         const auto& b = g->buckets[j];
-        if (b.P == tcs[i].P && b.block == tcs[i].block && b.ws == tcs[i].ws) bi = static_cast<int>(j);
+        if (b.P == tcs[i].P && b.block == tcs[i].block && b.ws == tcs[i].ws && b.nv == tcs[i].nv)
+          bi = static_cast<int>(j);
       }
       if (bi < 0) {
         typename FilterGroup<TS>::Bucket b;
         b.P = tcs[i].P;
         b.block = tcs[i].block;
         b.ws = tcs[i].ws;
+        b.nv = tcs[i].nv;
         g->buckets.push_back(b);
         bi = static_cast<int>(g->buckets.size()) - 1;
       }
@@ -898,7 +996,7 @@ FilterGroup<TS>* filter_group_build(const std::vector<FilterGroupOp<TS>>& ops) {
         const auto& o = ops[i];
         TS* in = o.buf[(o.cur0 + k) & 1];
         TS* out = o.buf[(o.cur0 + k + 1) & 1];
-        h[i] = make_hargs<TS, TS>(*o.op, tcs[i], in, o.ld, o.alpha, out, k >= 1 ? out : nullptr);
+        h[i] = make_hargs<TS, TS>(*o.op, tcs[i], in, o.ld, o.ncols, o.alpha, out, k >= 1 ? out : nullptr);
         h[i].coef = o.coef;
         h[i].has_prev = k >= 1 ? 1 : 0;
       }
@@ -952,9 +1050,12 @@ FilterGroup<TS>* filter_group_build(const std::vector<FilterGroupOp<TS>>& ops) {
     };
     for (size_t bi = 0; bi < g->buckets.size(); ++bi) {
       auto& b = g->buckets[bi];
-      build_items([&](int i) { return static_cast<int64_t>(ops[i].ncols) * tcs[i].nyt * tcs[i].nzt; }, b.count,
-                  b.items, [&](int i) { return bucket_of[i] == static_cast<int>(bi); });
-      b.grid_cap = group_occ<TS>(b.P, b.block, b.ws, b.smem) * cus;
+      build_items(
+          [&](int i) {
+            return static_cast<int64_t>((ops[i].ncols + tcs[i].nv - 1) / tcs[i].nv) * tcs[i].nyt * tcs[i].nzt;
+          },
+          b.count, b.items, [&](int i) { return bucket_of[i] == static_cast<int>(bi); });
+      b.grid_cap = group_occ<TS>(b.P, b.block, b.ws, b.nv, b.smem) * cus;
     }
     build_items([&](int i) {
       return static_cast<int64_t>(ops[i].op->n_atoms) * ((ops[i].ncols + 4 * kProjCols - 1) / (4 * kProjCols));
@@ -981,13 +1082,7 @@ void filter_group_step(FilterGroup<TS>* g, int k, hipStream_t st) {
   for (const auto& b : g->buckets) {
     const int n = b.count[k];
     if (n <= 0) continue;
-    if (b.ws == 80) {
-      if (b.P == 1) group_launch_pw<TS, 1, 80>(b, tab, n, k, st);
-      else group_launch_pw<TS, 2, 80>(b, tab, n, k, st);
-    } else {
-      if (b.P == 1) group_launch_pw<TS, 1, 128>(b, tab, n, k, st);
-      else group_launch_pw<TS, 2, 128>(b, tab, n, k, st);
-    }
+    group_launch<TS>(b, tab, n, k, st);
     XLS_LAUNCH_CHECK("hstencil_group_kernel");
   }
 }

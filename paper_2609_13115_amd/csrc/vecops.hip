@@ -14,14 +14,17 @@ namespace {
 
 inline unsigned nblk(int64_t n, int b) { return static_cast<unsigned>((n + b - 1) / b); }
 
-__global__ void reduce_cols_kernel(const double* __restrict__ partial, int nper, int ncols,
-                                   double* __restrict__ out, int take_sqrt) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+// One wave per column: lane l adds entries l, l + 64, ... in order, then a
+// fixed xor-shuffle tree (the order never depends on scheduling).
+__global__ __launch_bounds__(256) void reduce_cols_kernel(const double* __restrict__ partial, int nper, int ncols,
+                                                          double* __restrict__ out, int take_sqrt) {
+  const int c = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (c >= ncols) return;
   double s = 0.0;
   const double* p = partial + static_cast<int64_t>(c) * nper;
-  for (int i = 0; i < nper; ++i) s += p[i];
-  out[c] = take_sqrt ? sqrt(s) : s;
+  for (int i = lane; i < nper; i += 64) s += p[i];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if (lane == 0) out[c] = take_sqrt ? sqrt(s) : s;
 }
 
 // g_n = 1/(1 + exp((lam_n - mu)/sigma)), overflow-free form.
@@ -93,6 +96,25 @@ __global__ __launch_bounds__(256) void dot_partial_kernel(const TS* __restrict__
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
   if (threadIdx.x == 0) partial[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// partial[i nblocks + b] = block b's share of sum_g V[i ldv + g] y[g]; grid
+// (nblocks, m), the layout of dot_partial_kernel per row i
+template <typename TS>
+__global__ __launch_bounds__(256) void multi_dot_partial_kernel(const TS* __restrict__ V, int64_t ldv,
+                                                                const TS* __restrict__ y, int64_t n, int nblocks,
+                                                                double* __restrict__ partial) {
+  __shared__ double red[4];
+  const TS* __restrict__ x = V + static_cast<int64_t>(blockIdx.y) * ldv;
+  const int64_t per = (n + nblocks - 1) / nblocks;
+  const int64_t i0 = blockIdx.x * per, i1 = min(n, i0 + per);
+  double s = 0.0;
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += 256)
+    s += static_cast<double>(x[i]) * static_cast<double>(y[i]);
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) partial[static_cast<int64_t>(blockIdx.y) * nblocks + blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
 // w <- w - alpha_j v - beta_{j-1} v_prev  (beta_prev may be null)
@@ -185,8 +207,8 @@ __global__ void block_to_double_kernel(const TS* __restrict__ src, int64_t lds_,
 
 void launch_reduce_cols(const double* partial, int nper, int ncols, double* out, int take_sqrt,
                         hipStream_t st) {
-  hipLaunchKernelGGL(reduce_cols_kernel, dim3(nblk(ncols, 256)), dim3(256), 0, st, partial, nper, ncols,
-                     out, take_sqrt);
+  hipLaunchKernelGGL(reduce_cols_kernel, dim3(nblk(ncols, 4)), dim3(256), 0, st, partial, nper, ncols, out,
+                     take_sqrt);
   XLS_LAUNCH_CHECK("reduce_cols_kernel");
 }
 
@@ -215,6 +237,16 @@ void launch_dot(const TS* x, const TS* y, int64_t n, double* partial, int nblock
                 int take_sqrt, hipStream_t st) {
   hipLaunchKernelGGL(dot_partial_kernel<TS>, dim3(nblocks), dim3(256), 0, st, x, y, n, nblocks, partial);
   launch_reduce_cols(partial, nblocks, 1, out, take_sqrt, st);
+}
+
+template <typename TS>
+void launch_multi_dot(const TS* V, int64_t ldv, int m, const TS* y, int64_t n, double* partial, int nblocks,
+                      double* out, hipStream_t st) {
+  if (m <= 0) return;
+  hipLaunchKernelGGL(multi_dot_partial_kernel<TS>, dim3(nblocks, m), dim3(256), 0, st, V, ldv, y, n, nblocks,
+                     partial);
+  XLS_LAUNCH_CHECK("multi_dot_partial_kernel");
+  launch_reduce_cols(partial, nblocks, m, out, 0, st);
 }
 
 void launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t st) {
@@ -271,6 +303,8 @@ void launch_block_to_double(const TS* src, int64_t lds_, double* dst, int64_t ld
 
 #define XLS_INST_VEC(TS)                                                                            \
   template void launch_dot<TS>(const TS*, const TS*, int64_t, double*, int, double*, int, hipStream_t); \
+  template void launch_multi_dot<TS>(const TS*, int64_t, int, const TS*, int64_t, double*, int, double*,  \
+                                     hipStream_t);                                                       \
   template void launch_lanczos_update<TS>(TS*, const TS*, const TS*, const double*, const double*,  \
                                           int64_t, hipStream_t);                                    \
   template void launch_reorth<TS>(TS*, const TS*, int64_t, const double*, int, int64_t, hipStream_t); \

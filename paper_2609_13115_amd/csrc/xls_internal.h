@@ -74,6 +74,7 @@ struct StencilLaunch {
   int block = 256;  // threads: 256 or 512
   int ty = 0;       // rows per tile (0 = choose)
   int tz = 0;       // z-chunk (0 = whole nz)
+  int nv = 0;       // vectors per tile: 1 or 2 (0 = choose; residual sweeps take 1)
 };
 
 // HY / filter step / residual over ncols columns of y (ld elements apart).
@@ -193,6 +194,11 @@ void launch_density(const double* lam, double mu, double sigma, const uint8_t* m
 template <typename TS>
 void launch_dot(const TS* x, const TS* y, int64_t n, double* partial, int nblocks, double* out,
                 int take_sqrt, hipStream_t st);
+// out[i] = sum_g V[i ldv + g] y[g] for i < m: nblocks partial sums per i
+// (partial holds m * nblocks doubles), then a fixed-order reduction
+template <typename TS>
+void launch_multi_dot(const TS* V, int64_t ldv, int m, const TS* y, int64_t n, double* partial, int nblocks,
+                      double* out, hipStream_t st);
 template <typename TS>
 void launch_lanczos_update(TS* w, const TS* v, const TS* vprev, const double* alpha_j,
                            const double* beta_prev, int64_t n, hipStream_t st);

@@ -319,9 +319,9 @@ class Subdomain:
             _dp(val), roff.ctypes.data_as(P32), rslot.ctypes.data_as(P32)))
         return off, idx, val, roff, rslot
 
-    def xls_subdomain_tune(self, prec: int, block: int = 512, ty: int = 0, tz: int = 0):
+    def xls_subdomain_tune(self, prec: int, block: int = 512, ty: int = 0, tz: int = 0, nv: int = 0):
         _check(lib().xls_subdomain_tune(self._h, C.c_int32(prec), C.c_int32(block), C.c_int32(ty),
-                                        C.c_int32(tz)))
+                                        C.c_int32(tz), C.c_int32(nv)))
 
     def xls_subdomain_features(self) -> np.ndarray:
         f = np.zeros(64)

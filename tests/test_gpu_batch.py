@@ -126,11 +126,29 @@ def test_batch_tuner_cache_and_invariance(tmp_path):
         cache = json.load(open(path))
         assert len(cache) == 3
         for v in cache.values():
-            assert v[0] in (256, 512) and v[1] in (0, 1, 2, 4, 8, 16)
+            assert v[0] in (256, 512) and v[1] in (0, 1, 2, 4, 8, 16) and v[2] in (1, 2)
         again, _ = b.xls_batch_tune(path)
         assert again == 0
         ritz, resid, iters, status = b.xls_batch_chefsi(params)
         blocks = [b.xls_batch_subdomain(i).xls_subdomain_get_block() for i in range(3)]
+    assert_same([(r, e, it, blk) for r, e, it, blk in zip(ref[0], ref[1], ref[2], ref[4])],
+                (ritz, resid, iters, status, blocks, None))
+
+
+@pytest.mark.parametrize("prec", [xls.XLS_PREC_FP64, xls.XLS_PREC_FP32])
+def test_batch_two_vectors_per_tile_bit_identical(prec):
+    """Grouped launches over tiles of 2 vectors (odd Ns leaves an empty
+    second vector) give the same bits as 1-vector tiles."""
+    case(f"batch nv=2 prec={prec}")
+    sds = uneven_boxes()
+    sds[0] = workloads.small_dirichlet(ns=9, index=1, shape=(13, 9, 20), h=0.6)
+    params = [xls.chefsi_params(d, 3, xls.XLS_BOUNDS_LANCZOS) for d in (7, 10, 12)]
+    ref = batch_run(sds, prec, params)
+    with xls.Batch(sds, filter_prec=prec) as b:
+        for i in range(len(sds)):
+            b.xls_batch_subdomain(i).xls_subdomain_tune(prec, 256, 0, 0, 2)
+        ritz, resid, iters, status = b.xls_batch_chefsi(params)
+        blocks = [b.xls_batch_subdomain(i).xls_subdomain_get_block() for i in range(len(sds))]
     assert_same([(r, e, it, blk) for r, e, it, blk in zip(ref[0], ref[1], ref[2], ref[4])],
                 (ritz, resid, iters, status, blocks, None))
 

@@ -83,7 +83,9 @@ def test_maps_cfg2_bit_exact():
 # a3: H apply and filter
 # ---------------------------------------------------------------------------
 
-TILES = [(512, 0, 0), (512, 3, 7), (256, 5, 0), (256, 1, 1)]
+# (block, rows per tile, z-chunk, vectors per tile); 3 columns leave the
+# second vector of the last 2-vector tile empty
+TILES = [(512, 0, 0, 1), (512, 3, 7, 2), (256, 5, 0, 2), (256, 1, 1, 1)]
 
 
 @pytest.mark.parametrize("tile", TILES)
@@ -130,6 +132,26 @@ def test_filter_fp64(system, m):
         s.xls_subdomain_filter(m, lo, lc, up)
         out = s.xls_subdomain_get_block()
     assert rel_err(out, ref) <= 1e-11
+
+
+@pytest.mark.parametrize("prec", [xls.XLS_PREC_FP64, xls.XLS_PREC_FP32])
+def test_filter_two_vectors_per_tile_bit_identical(system, prec):
+    """Tiles of 2 vectors share the operator tables but not the arithmetic of
+    a point: the filtered block is bit-identical to 1-vector tiles (odd
+    column counts leave the second vector of the last tile empty)."""
+    name, sd, op = system
+    case(f"filter nv=2 {name} prec={prec}")
+    lo, up = chefsi.lanczos_bounds(op.apply, sd.lanczos_v0, 20)
+    lc = chefsi.first_cutoff(lo, up)
+    outs = []
+    for nv, ty in ((1, 0), (2, 0), (2, 3)):
+        with xls.Subdomain(sd, filter_prec=prec) as s:
+            s.xls_subdomain_tune(prec, 256, ty, 0, nv)
+            s.xls_subdomain_filter(5, lo, lc, up)
+            outs.append(s.xls_subdomain_get_block())
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+    ref = chefsi.chebyshev_filter(op.apply, sd.x0, 5, lo, lc, up)
+    assert rel_err(outs[2], ref) <= (1e-11 if prec == xls.XLS_PREC_FP64 else 1e-4)
 
 
 def test_filter_cfg1_degree20_fp64_and_fp32():
@@ -450,6 +472,9 @@ def test_failure_paths():
         assert ei.value.code == xls.XLS_ERR_INVALID_ARG
         with pytest.raises(xls.XlsError) as ei:
             s.xls_subdomain_tune(xls.XLS_PREC_FP64, 128, 0, 0)
+        assert ei.value.code == xls.XLS_ERR_INVALID_ARG
+        with pytest.raises(xls.XlsError) as ei:
+            s.xls_subdomain_tune(xls.XLS_PREC_FP32, 256, 0, 0, 3)
         assert ei.value.code == xls.XLS_ERR_INVALID_ARG
 
 

@@ -46,6 +46,19 @@ __device__ __forceinline__ float bf16_bits_to_f32(uint16_t b) {
   return __uint_as_float(static_cast<uint32_t>(b) << 16);
 }
 
+typedef __bf16 bf2_t __attribute__((ext_vector_type(2)));
+typedef float f2_t __attribute__((ext_vector_type(2)));
+// Split of two FP32 values with the hardware's packed round-to-nearest-even
+// conversion: hi = bf16(a), lo = bf16(a - hi); each word holds element 0 in
+// its low half (the LDS order of two consecutive bf16 values).  For finite
+// values the bits equal bf16_rne_bits'.
+__device__ __forceinline__ void split_pair(float a0, float a1, uint32_t& hi, uint32_t& lo) {
+  const f2_t a = {a0, a1};
+  hi = __builtin_bit_cast(uint32_t, __builtin_convertvector(a, bf2_t));
+  const f2_t h = {__uint_as_float(hi << 16), __uint_as_float(hi & 0xFFFF0000u)};
+  lo = __builtin_bit_cast(uint32_t, __builtin_convertvector(a - h, bf2_t));
+}
+
 // ---- per-form traits: LDS element, k per MFMA, operand loads, MFMA --------
 template <int MF>
 struct Form;
@@ -441,12 +454,17 @@ template <int MF, typename TIN, int VEC>
 __device__ __forceinline__ void big_put_row(typename Form<MF>::lds_t* h, typename Form<MF>::lds_t* l, int off,
                                             const TIN (&v)[VEC]) {
   if constexpr (MF == MF_BF) {
+    static_assert(VEC == 2 || VEC == 4, "pairs of k values");
+    uint32_t hp[VEC / 2], lp[VEC / 2];
 #pragma unroll
-    for (int e = 0; e < VEC; ++e) {
-      const float a = static_cast<float>(v[e]);
-      const uint16_t hb = bf16_rne_bits(a);
-      h[off + e] = hb;
-      l[off + e] = bf16_rne_bits(a - bf16_bits_to_f32(hb));
+    for (int e = 0; e < VEC / 2; ++e)
+      split_pair(static_cast<float>(v[2 * e]), static_cast<float>(v[2 * e + 1]), hp[e], lp[e]);
+    if constexpr (VEC == 4) {
+      *reinterpret_cast<uint2*>(h + off) = make_uint2(hp[0], hp[1]);
+      *reinterpret_cast<uint2*>(l + off) = make_uint2(lp[0], lp[1]);
+    } else {
+      *reinterpret_cast<uint32_t*>(h + off) = hp[0];
+      *reinterpret_cast<uint32_t*>(l + off) = lp[0];
     }
   } else {
     using L = typename Form<MF>::lds_t;
@@ -596,13 +614,17 @@ __global__ __launch_bounds__(256) void gemm_nn_big_kernel(const TIN* __restrict_
 
   using VAt = __attribute__((ext_vector_type(VA))) TIN;
   using VBt = __attribute__((ext_vector_type(VB))) TB;
+  // The BF form gives each thread the same VA rows at two consecutive k, so
+  // that its split stores (hi, lo) pairs of k values as 32-bit words.
+  constexpr bool PAIRK = (MF == MF_BF) && ALOADS == 2;
+  auto a_k = [&](int i) { return PAIRK ? 2 * (tid / (TM / VA)) + i : (tid + i * 256) / (TM / VA); };
+  auto a_m = [&](int i) { return PAIRK ? (tid % (TM / VA)) * VA : ((tid + i * 256) % (TM / VA)) * VA; };
   VAt ra[ALOADS];
   VBt rbh[BLOADS], rbl[BLOADS];
   auto load = [&](int kb) {
 #pragma unroll
     for (int i = 0; i < ALOADS; ++i) {
-      const int l = tid + i * 256;
-      const int k = l / (TM / VA), mv = (l % (TM / VA)) * VA;
+      const int k = a_k(i), mv = a_m(i);
       const bool ok = (kb + k < K) && (m0 + mv < M);
       ra[i] = ok ? *reinterpret_cast<const VAt*>(A + (m0 + mv) + static_cast<int64_t>(kb + k) * lda) : VAt{};
     }
@@ -617,10 +639,20 @@ __global__ __launch_bounds__(256) void gemm_nn_big_kernel(const TIN* __restrict_
     }
   };
   auto store = [&](int kb) {
+    if constexpr (PAIRK) {  // transpose: LDS rows are m, k contiguous
+      const int k = a_k(0), mv = a_m(0);
 #pragma unroll
-    for (int i = 0; i < ALOADS; ++i) {  // transpose: LDS rows are m, k contiguous
-      const int l = tid + i * 256;
-      const int k = l / (TM / VA), mv = (l % (TM / VA)) * VA;
+      for (int e = 0; e < VA; ++e) {
+        const bool mi = m0 + mv + e < M;
+        uint32_t hp, lp;
+        split_pair(mi ? static_cast<float>(ra[0][e]) : 0.0f, mi ? static_cast<float>(ra[1][e]) : 0.0f, hp, lp);
+        *reinterpret_cast<uint32_t*>(ah + (mv + e) * ST + k) = hp;
+        *reinterpret_cast<uint32_t*>(al + (mv + e) * ST + k) = lp;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < (PAIRK ? 0 : ALOADS); ++i) {  // transpose: LDS rows are m, k contiguous
+      const int k = a_k(i), mv = a_m(i);
 #pragma unroll
       for (int e = 0; e < VA; ++e) {
         const TIN v = (m0 + mv + e < M) ? ra[i][e] : TIN(0);

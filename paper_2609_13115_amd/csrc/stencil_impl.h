@@ -528,33 +528,49 @@ __device__ __forceinline__ void proj_forward_wave(const TS* __restrict__ y, int6
   for (int c = 0; c < kProjCols; ++c)
 #pragma unroll
     for (int l = 0; l < 4; ++l) acc[c][l] = 0.0;
-  // the next point's index and values load one iteration ahead
-  int gn = 0;
-  TC vn0 = TC(0), vn1 = TC(0), vn2 = TC(0), vn3 = TC(0);
-  auto fetch = [&](int s) {
-    if (s < s1) {
-      gn = sup_idx[s];
-      const TC* v4 = val + 4 * static_cast<int64_t>(s);
-      vn0 = v4[0];
-      vn1 = v4[1];
-      vn2 = v4[2];
-      vn3 = v4[3];
-    }
+  // Two support points per lane and iteration (s and s + 64, added in that
+  // order, so each lane's order is that of a one-point loop): their column
+  // loads are in flight together.  The next pair's indices and values load
+  // one iteration ahead.  Every load is unconditional from a clamped,
+  // in-range entry (a guarded load becomes a branch that waits for it);
+  // products of entries past the support are skipped.
+  struct Ent {
+    int g;
+    TC v[4];
   };
-  fetch(s0 + lane);
-  for (int s = s0 + lane; s < s1; s += 64) {
-    const int g = gn;
-    const double v0 = static_cast<double>(vn0), v1 = static_cast<double>(vn1);
-    const double v2 = static_cast<double>(vn2), v3 = static_cast<double>(vn3);
-    fetch(s + 64);
+  auto fetch = [&](int s) {
+    Ent e;
+    const int sc = min(s, s1 - 1);
+    e.g = sup_idx[sc];
+    const TC* v4 = val + 4 * static_cast<int64_t>(sc);
 #pragma unroll
-    for (int c = 0; c < kProjCols; ++c) {
-      if (c < nc) {
-        const double yv = static_cast<double>(y[static_cast<int64_t>(cbase + c) * ld + g]);
-        acc[c][0] += v0 * yv;
-        acc[c][1] += v1 * yv;
-        acc[c][2] += v2 * yv;
-        acc[c][3] += v3 * yv;
+    for (int l = 0; l < 4; ++l) e.v[l] = v4[l];
+    return e;
+  };
+  const TS* yc[kProjCols];
+#pragma unroll
+  for (int c = 0; c < kProjCols; ++c) yc[c] = y + static_cast<int64_t>(cbase + min(c, nc - 1)) * ld;
+  if (s0 + lane < s1) {
+    Ent na = fetch(s0 + lane), nb = fetch(s0 + lane + 64);
+    for (int s = s0 + lane; s < s1; s += 128) {
+      const Ent ea = na, eb = nb;
+      na = fetch(s + 128);
+      nb = fetch(s + 192);
+      TS ya[kProjCols], yb[kProjCols];
+#pragma unroll
+      for (int c = 0; c < kProjCols; ++c) {
+        ya[c] = yc[c][ea.g];
+        yb[c] = yc[c][eb.g];
+      }
+#pragma unroll
+      for (int c = 0; c < kProjCols; ++c)
+#pragma unroll
+        for (int l = 0; l < 4; ++l) acc[c][l] += static_cast<double>(ea.v[l]) * static_cast<double>(ya[c]);
+      if (s + 64 < s1) {
+#pragma unroll
+        for (int c = 0; c < kProjCols; ++c)
+#pragma unroll
+          for (int l = 0; l < 4; ++l) acc[c][l] += static_cast<double>(eb.v[l]) * static_cast<double>(yb[c]);
       }
     }
   }
@@ -595,11 +611,16 @@ __global__ __launch_bounds__(256) void proj_forward_kernel(const TS* __restrict_
                                                            const TC* __restrict__ val,
                                                            const double* __restrict__ gamma,
                                                            double h3, TC* __restrict__ alpha,
-                                                           int nproj) {
+                                                           int nproj, int n_atoms) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int cbase = (blockIdx.y * 4 + wave) * kProjCols;
+  // logical block = atom + n_atoms * column group, remapped so that the
+  // atoms of one column group share an XCD: neighbouring atoms' supports
+  // gather from the same cache lines, which then meet in that XCD's L2
+  const uint32_t lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int a = static_cast<int>(lb % static_cast<uint32_t>(n_atoms));
+  const int cbase = (static_cast<int>(lb / static_cast<uint32_t>(n_atoms)) * 4 + wave) * kProjCols;
   if (cbase >= ncols) return;
-  proj_forward_wave<TS, TC>(y, ld, ncols, cbase, sup_off, sup_idx, val, gamma, h3, alpha, nproj, blockIdx.x, lane);
+  proj_forward_wave<TS, TC>(y, ld, ncols, cbase, sup_off, sup_idx, val, gamma, h3, alpha, nproj, a, lane);
 }
 
 // Grouped forward projection: item = (operator, atom + n_atoms * column group).
@@ -620,7 +641,9 @@ template <typename TS, typename TC>
 __global__ __launch_bounds__(256) void proj_forward_group_kernel(const PArgs<TS, TC>* __restrict__ tab,
                                                                  const uint2* __restrict__ items, int nitems) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (uint32_t it = blockIdx.x; it < static_cast<uint32_t>(nitems); it += gridDim.x) {
+  // consecutive items (atoms of one operator and column group) share an XCD
+  const uint32_t G = gridDim.x;
+  for (uint32_t it = xcd_remap(blockIdx.x, G); it < static_cast<uint32_t>(nitems); it += G) {
     const uint2 w = items[it];
     const PArgs<TS, TC> A = tab[w.x];
     const int a = static_cast<int>(w.y % static_cast<uint32_t>(A.n_atoms));
@@ -855,10 +878,11 @@ template <typename TS, typename TC>
 void launch_proj_forward(const OpTables<TC>& op, const TS* y, int64_t ld, int ncols, TC* alpha,
                          hipStream_t st) {
   if (op.n_atoms == 0 || ncols <= 0) return;
-  const dim3 grid(op.n_atoms, (ncols + 4 * kProjCols - 1) / (4 * kProjCols));
+  const int64_t nb = static_cast<int64_t>(op.n_atoms) * ((ncols + 4 * kProjCols - 1) / (4 * kProjCols));
+  if (nb > 0x7fffffff) fail(XLS_ERR_INVALID_ARG, "too many projection blocks");
   const double h3 = op.h * op.h * op.h;
-  hipLaunchKernelGGL((proj_forward_kernel<TS, TC>), grid, dim3(256), 0, st, y, ld, ncols,
-                     op.sup_off, op.sup_idx, op.slot_val, op.gamma, h3, alpha, 4 * op.n_atoms);
+  hipLaunchKernelGGL((proj_forward_kernel<TS, TC>), dim3(static_cast<unsigned>(nb)), dim3(256), 0, st, y, ld, ncols,
+                     op.sup_off, op.sup_idx, op.slot_val, op.gamma, h3, alpha, 4 * op.n_atoms, op.n_atoms);
   XLS_LAUNCH_CHECK("proj_forward_kernel");
 }
 

@@ -12,8 +12,13 @@ value = filtered grid-pt*vec*deg per second over whole steps
 GEMMs + FP64 dense); the plain FP64 path is reported beside it.
 subdomains_per_s counts the workload's 5 CheFSI iterations per subdomain.  The
 roofline object prices the fused filter kernel (3 words per grid-pt*vec*deg)
-against 8 TB/s, from HIP events around every filter launch.  cpu_baseline
-times the FP64 oracle's filter on a column sample on the host.
+against 8 TB/s, from HIP events around every filter launch, and against a
+device-to-device copy measured in the same run.  The gemm object times the
+projection and rotation GEMMs (HIP events) in each precision of the form.
+The batch object runs the first subdomains of the 256-subdomain uneven batch
+workload to convergence (gated residual <= 1e-4), mixed and FP64, and
+reports subdomains/s and the largest Ritz-value difference between the two.
+cpu_baseline times the FP64 oracle's filter on a column sample on the host.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--form mixed|fp64|both] [--no-cpu]
 """
@@ -31,6 +36,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+MFMA_PEAK_TFLOPS = {"bf16x3": 2500.0, "fp32": 157.3, "fp64": 78.6}  # dense, per MFMA dtype
 METRIC = "filtered grid-pt\u00b7vec\u00b7deg/s + subdomains/s: FP64 vs mixed+learned, dE<=1e-6 Ha"
 CHEFSI_ITERS = 5  # iterations per subdomain solve in this workload
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "filter_traffic.json")
@@ -81,6 +87,7 @@ def run_form(sd, x0, form: str, steps: int, warmup: int, degree: int):
         t1 = time.perf_counter()
         xls.xls_set_profiling(False)
         ms, nlaunch = s.xls_get_stage_times()
+        gemm = time_gemms(s, sd.nd, x0.shape[1], form)
     step_ms = (t1 - t0) * 1e3 / it
     nd, ns = sd.nd, x0.shape[1]
     units = nd * ns * degree
@@ -101,7 +108,100 @@ def run_form(sd, x0, form: str, steps: int, warmup: int, degree: int):
                      "algorithmic_bytes": bytes_per_launch},
         "max_resid": float(np.max(resid)),
         "ritz_lo": float(ritz[0]),
+        "gemm": gemm,
     }
+
+
+def time_gemms(s, nd: int, ns: int, form: str):
+    """TFLOP/s of the three GEMMs at each precision of the form: algorithmic
+    flops (N_d N_s^2 for the symmetric product, 2 N_d N_s^2 for the others)
+    and issued MFMA flops (x3 for the split-BF16 form) against the dtype's
+    dense peak."""
+    from paper_2609_13115_amd import xls
+
+    precs = [("fp64", xls.XLS_PREC_FP64)] if form == "fp64" else [("bf16x3", xls.XLS_PREC_BF16X3),
+                                                                   ("fp32", xls.XLS_PREC_FP32)]
+    flops = {"xtx": nd * ns * ns, "xthx": 2.0 * nd * ns * ns, "rotation": 2.0 * nd * ns * ns}
+    out = {}
+    for name, p in precs:
+        ms = s.xls_subdomain_time_gemms(p, 5)
+        issue = 3.0 if name == "bf16x3" else 1.0
+        o = {}
+        for (k, f), t in zip(flops.items(), ms):
+            tf = f / (t * 1e-3) / 1e12
+            o[k] = {"ms": t, "tflops": tf, "issued_tflops": issue * tf,
+                    "frac": issue * tf / MFMA_PEAK_TFLOPS[name]}
+        out[name] = o
+    return out
+
+
+def copy_rate(mib: int = 1024, reps: int = 5):
+    """Device-to-device copy GB/s (read + write bytes) from torch events: the
+    practical HBM rate of a plain streaming kernel on this GPU."""
+    import torch
+
+    src = torch.empty(mib << 20, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    src.fill_(1)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1))
+    del src, dst
+    t = float(np.median(times))
+    return 2.0 * (mib << 20) / (t * 1e-3) / 1e9
+
+
+def run_batch(count: int, forms):
+    """The first `count` subdomains of the uneven batch workload, solved to a
+    gated residual of 1e-4 (at most 40 iterations) with Lanczos bounds and
+    tuned tile shapes, once per form; wall time from the call to the last
+    subdomain's convergence."""
+    import torch
+    from paper_2609_13115_amd import workloads, xls
+
+    _, subs, degs = workloads.batch_subdomains(count=count)
+    x0s = [sd.make_x0() for sd in subs]
+    for sd in subs:
+        sd.lanczos_v0 = sd.make_lanczos_v0()
+    desc = (f"first {count} of the 256-subdomain uneven batch draw: grids "
+            f"{min(sd.n[0] for sd in subs)}^3-{max(sd.n[0] for sd in subs)}^3, ns "
+            f"{min(sd.ns for sd in subs)}-{max(sd.ns for sd in subs)}, degree {min(degs)}-{max(degs)}; "
+            f"{sum(sd.nd * sd.ns * m for sd, m in zip(subs, degs)):.3e} pt*vec*deg per iteration")
+    out = {"workload": desc, "subdomains": count}
+    ritz_of = {}
+    for form in forms:
+        prec = xls.XLS_PREC_FP64 if form == "fp64" else xls.XLS_PREC_FP32
+        gprec = xls.XLS_PREC_FP64 if form == "fp64" else xls.XLS_PREC_BF16X3
+        params = [xls.chefsi_params(m, 40, xls.XLS_BOUNDS_LANCZOS, resid_tol=1e-4, gemm_prec=gprec) for m in degs]
+        with xls.Batch(subs, filter_prec=prec, x0s=x0s) as b:
+            b.xls_batch_tune(None)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ritz, resid, iters, status = b.xls_batch_chefsi(params)
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t0
+        gates = [max(1, int(np.floor(sd.ns / 1.1 + 1e-9))) for sd in subs]
+        conv = [int(st == xls.XLS_OK and float(np.max(r[:g])) <= 1e-4) for st, r, g in zip(status, resid, gates)]
+        ritz_of[form] = (ritz, gates, conv)
+        out[form] = {"seconds": t, "subdomains_per_s": count / t, "iterations": [int(i) for i in iters],
+                     "converged": int(sum(conv))}
+        print(f"[bench] batch {form}: {json.dumps(out[form])}", file=sys.stderr, flush=True)
+    if "mixed" in ritz_of and "fp64" in ritz_of:
+        (rm, g, cm), (rf, _, cf) = ritz_of["mixed"], ritz_of["fp64"]
+        d = [float(np.max(np.abs(a[:k] - b[:k]))) for a, b, k in zip(rm, rf, g)]
+        both = [x for x, u, v in zip(d, cm, cf) if u and v]
+        # largest |lambda_mixed - lambda_fp64| over the gated states, per subdomain
+        out["ritz_diff_ha"] = d
+        out["max_ritz_diff_ha_converged"] = max(both) if both else None
+        out["speedup_mixed_vs_fp64"] = out["fp64"]["seconds"] / out["mixed"]["seconds"]
+    return out
 
 
 def cpu_baseline(sd, degree: int, ncols: int):
@@ -132,6 +232,8 @@ def main():
     ap.add_argument("--cpu-cols", type=int, default=64)
     ap.add_argument("--calib-mib", type=int, default=0,
                     help="first run a device-to-device copy of this many MiB (counter calibration)")
+    ap.add_argument("--batch", type=int, default=8,
+                    help="subdomains of the uneven batch workload to solve per form (0: skip)")
     a = ap.parse_args()
     if a.gpus != 1:
         print(json.dumps({"error": "this engine runs on one GPU; multi-GPU sharding is a design note only "
@@ -153,6 +255,8 @@ def main():
         torch.cuda.synchronize()
         print(f"[bench] calibration copy: {a.calib_mib} MiB", file=sys.stderr, flush=True)
         del src, dst
+    copy_gbs = copy_rate()
+    print(f"[bench] device copy: {copy_gbs:.1f} GB/s", file=sys.stderr, flush=True)
     res = {}
     forms = ["mixed", "fp64"] if a.form == "both" else [a.form]
     for f in forms:
@@ -177,8 +281,9 @@ def main():
                                f"ns={a.ns}, degree={a.degree}, one CheFSI iteration per step",
                    "form": "FP32 filter + split-BF16 GEMMs + FP64 dense" if main_form == "mixed" else "FP64",
                    "parallelism": "single GPU"},
-        "roofline": r["roofline"],
+        "roofline": dict(r["roofline"], copy_gbs=copy_gbs, frac_of_copy=r["roofline"]["achieved"] / copy_gbs),
         "subdomains_per_s": 1e3 / (CHEFSI_ITERS * r["ms_per_step"]),
+        "gemm": r["gemm"],
         "filter_rate": r["filter_rate"],
         "stage_ms_per_step": r["stage_ms_per_step"],
     }
@@ -186,7 +291,10 @@ def main():
         f = res["fp64"]
         out["fp64"] = {"value": f["value"], "ms_per_step": f["ms_per_step"], "filter_rate": f["filter_rate"],
                        "subdomains_per_s": 1e3 / (CHEFSI_ITERS * f["ms_per_step"]),
-                       "roofline": f["roofline"], "stage_ms_per_step": f["stage_ms_per_step"]}
+                       "roofline": dict(f["roofline"], frac_of_copy=f["roofline"]["achieved"] / copy_gbs),
+                       "stage_ms_per_step": f["stage_ms_per_step"], "gemm": f["gemm"]}
+    if a.batch > 0:
+        out["batch"] = run_batch(a.batch, forms)
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(sd, a.degree, a.cpu_cols)
     print(json.dumps(out), flush=True)

@@ -111,7 +111,9 @@ typedef struct {
   double resid_tol;        /* stop when max residual over the gated states <= this (0: never) */
   int32_t n_gate;          /* gated states (lowest n_gate); <= 0: floor(ns/1.1)     */
   int32_t lanczos_k;       /* Lanczos steps (<= 0: 20)                              */
-  int32_t gemm_prec;       /* XLS_PREC_*: projection and rotation GEMMs             */
+  int32_t gemm_prec;       /* XLS_PREC_*: projection and rotation GEMMs; with BF16X3
+                              both switch to FP32 once the previous iteration's
+                              largest gated residual is <= 1e-2                  */
   double fallback_tol;     /* XLS_BOUNDS_LEARNED only: Lanczos restart above this (0: none) */
   int32_t fallback_degree; /* degree of the Lanczos restart (<= 0: degree)          */
 } xls_chefsi_params_t;
@@ -223,6 +225,16 @@ int xls_set_profiling(int32_t on);
  * everything eagerly (tests compare the two). */
 int xls_set_graphs(int32_t on);
 int xls_get_stage_times(xls_subdomain_t s, double* ms, int64_t* counts, int32_t cap);
+
+/* Device time of the projection and rotation GEMMs (steps (2) and (4) of
+ * Sec. V-A.3: M_s = Psi^T Psi, H_s = Psi^T (H Psi), Psi Q) on the handle's
+ * current block in precision gemm_prec (XLS_PREC_*; FP64 handles take FP64), from
+ * HIP events around reps back-to-back launches after one warm-up:
+ * ms[0] Psi^T Psi (symmetric), ms[1] Psi^T (H Psi) (symmetrized), ms[2]
+ * Psi Q into the spare block (Q = I).  H Psi is computed first (untimed);
+ * the current block is not changed.  ms holds 3 doubles; returns 3.
+ * Errors: INVALID_ARG (NULL, reps < 1, precision). */
+int xls_subdomain_time_gemms(xls_subdomain_t s, int32_t gemm_prec, int32_t reps, double* ms);
 
 /* Work counters of the handle's last xls_chefsi_step: out[0] H applications
  * (one per vector: Lanczos steps, m*ns per filter, ns for H Psi_f and for the

@@ -325,12 +325,12 @@ int chefsi_loop(xls_subdomain_s* s, const xls_chefsi_params_t* p, int gprec, int
     tm.mark();
     filter_block<TS>(s, degree, a0, lc, lmax);
     tm.mark();
+    const int pprec = polish_prec(gprec, prev_resid);
     {
       TS* Bc = B<TS>(s, s->cur);
       TS* W = B<TS>(s, 1 - s->cur);
       apply_H<TS>(s, Bc, W, s->ns, static_cast<TS*>(s->alpha));
       tm.mark();
-      const int pprec = projection_prec(gprec, prev_resid);
       gemm_tn<TS>(pprec, Bc, s->ld, Bc, s->ld, ns, ns, s->nd, s->Mdev, ns, 1, 0, s->gwork, s->gwork_elems,
                   s->st);
       gemm_tn<TS>(pprec, Bc, s->ld, W, s->ld, ns, ns, s->nd, s->Hsdev, ns, 0, 1, s->gwork, s->gwork_elems,
@@ -340,7 +340,7 @@ int chefsi_loop(xls_subdomain_s* s, const xls_chefsi_params_t* p, int gprec, int
     dense_stage(s);
     XLS_HIP(hipMemcpyAsync(s->lam_dev, s->dw.lam(), ns * 8, hipMemcpyDeviceToDevice, s->st));
     tm.mark();
-    rotate_block<TS>(s, gprec, s->Ydev);
+    rotate_block<TS>(s, pprec, s->Ydev);
     tm.mark();
     residual_block<TS>(s, s->lam_dev, s->resid_dev);
     tm.mark();
@@ -906,6 +906,59 @@ int xls_subdomain_tune(xls_subdomain_t s, int32_t prec, int32_t block, int32_t t
       s->cfg32 = c;
     }
     return XLS_OK;
+  });
+}
+
+int xls_subdomain_time_gemms(xls_subdomain_t s, int32_t gemm_prec, int32_t reps, double* ms) {
+  return guarded([&]() -> int {
+    if (!s || !ms || reps < 1) fail(XLS_ERR_INVALID_ARG, "bad argument");
+    if (s->prec == XLS_PREC_FP64 && gemm_prec != XLS_PREC_FP64)
+      fail(XLS_ERR_INVALID_ARG, "FP64 handles run FP64 GEMMs");
+    if (gemm_prec < 0 || gemm_prec > 2) fail(XLS_ERR_INVALID_ARG, "bad gemm_prec");
+    by_prec(s, [&](auto tag) {
+      using TS = decltype(tag);
+      TS* Bc = B<TS>(s, s->cur);
+      TS* W = B<TS>(s, 1 - s->cur);
+      apply_H<TS>(s, Bc, W, s->ns, static_cast<TS*>(s->alpha));
+      // rotation operand: a fixed well-scaled matrix (scheduling only)
+      std::vector<double> q(static_cast<size_t>(s->ns) * s->ns, 0.0);
+      for (int i = 0; i < s->ns; ++i) q[static_cast<size_t>(i) * s->ns + i] = 1.0;
+      XLS_HIP(hipMemcpyAsync(s->Ydev, q.data(), q.size() * 8, hipMemcpyHostToDevice, s->st));
+      auto run = [&](int which) {
+        if (which == 0)
+          gemm_tn<TS>(gemm_prec, Bc, s->ld, Bc, s->ld, s->ns, s->ns, s->nd, s->Mdev, s->ns, 1, 0, s->gwork,
+                      s->gwork_elems, s->st);
+        else if (which == 1)
+          gemm_tn<TS>(gemm_prec, Bc, s->ld, W, s->ld, s->ns, s->ns, s->nd, s->Hsdev, s->ns, 0, 1, s->gwork,
+                      s->gwork_elems, s->st);
+        else  // into the spare block: the current block is left as it was
+          gemm_nn<TS>(gemm_prec, Bc, s->ld, s->Ydev, s->ns, static_cast<int>(s->nd), s->ns, s->ns, W, s->ld,
+                      s->bwork, s->st);
+      };
+      hipEvent_t e0, e1;
+      XLS_HIP(hipEventCreate(&e0));
+      XLS_HIP(hipEventCreate(&e1));
+      try {
+        for (int which = 0; which < 3; ++which) {
+          run(which);  // warm-up
+          XLS_HIP(hipEventRecord(e0, s->st));
+          for (int r = 0; r < reps; ++r) run(which);
+          XLS_HIP(hipEventRecord(e1, s->st));
+          XLS_HIP(hipEventSynchronize(e1));
+          float t = 0.0f;
+          XLS_HIP(hipEventElapsedTime(&t, e0, e1));
+          ms[which] = static_cast<double>(t) / reps;
+        }
+      } catch (...) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        throw;
+      }
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      return 0;
+    });
+    return 3;
   });
 }
 

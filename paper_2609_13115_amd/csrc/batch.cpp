@@ -66,7 +66,7 @@ struct GraphEntry {
 struct SubState {
   double lmax = 0.0;
   int degree = 0, max_iter = 0, gate = 0, gprec = XLS_PREC_FP64;
-  int pprec = XLS_PREC_FP64;  // projection precision this iteration (schedule of projection_prec)
+  int pprec = XLS_PREC_FP64;  // projection and rotation precision this iteration (polish_prec)
   double resid_tol = 0.0;
   int iters = 0;
   int status = XLS_OK;
@@ -123,7 +123,7 @@ void tail_stages(xls_subdomain_s* s, const SubState& ss, int cur_f, double* coef
   (void)dense_geneig(s->dw, s->Hsdev, s->Mdev, s->Ydev, s->st, /*check_spd=*/false);
   XLS_HIP(hipMemcpyAsync(s->lam_dev, s->dw.lam(), ns * 8, hipMemcpyDeviceToDevice, s->st));
   // Psi <- Psi_f Y into the other buffer
-  gemm_nn<TS>(ss.gprec, Bc, s->ld, s->Ydev, ns, static_cast<int>(s->nd), ns, ns, W, s->ld, s->bwork, s->st);
+  gemm_nn<TS>(ss.pprec, Bc, s->ld, s->Ydev, ns, static_cast<int>(s->nd), ns, ns, W, s->ld, s->bwork, s->st);
   launch_proj_forward<TS, double>(s->op64, W, s->ld, ns, s->alpha64, s->st);
   launch_stencil<TS, double>(kResid, s->op64, W, s->ld, ns, s->alpha64, nullptr, nullptr, 1.0, 0.0, 0.0,
                              s->lam_dev, s->partial, s->resid_dev, s->st, s->cfg64);
@@ -277,7 +277,7 @@ void batch_chefsi(xls_batch_s* b, const xls_chefsi_params_t* P, int use_graph) {
     ss.degree = p.degree;
     ss.max_iter = p.max_iter;
     ss.gprec = p.gemm_prec;
-    ss.pprec = projection_prec(p.gemm_prec, HUGE_VAL);
+    ss.pprec = polish_prec(p.gemm_prec, HUGE_VAL);
     ss.resid_tol = p.resid_tol;
     ss.gate = p.n_gate > 0 ? std::min(p.n_gate, s->ns)
                            : std::max(1, static_cast<int>(std::floor(s->ns / 1.1 + 1e-9)));
@@ -337,7 +337,7 @@ void batch_chefsi(xls_batch_s* b, const xls_chefsi_params_t* P, int use_graph) {
       }
       double mx = 0;
       for (int k = 0; k < ss.gate; ++k) mx = std::max(mx, hr[i][k]);
-      ss.pprec = projection_prec(ss.gprec, mx);
+      ss.pprec = polish_prec(ss.gprec, mx);
       if (ss.resid_tol > 0 && mx <= ss.resid_tol) ss.active = false;
       if (ss.iters >= ss.max_iter) ss.active = false;
     }

@@ -423,14 +423,25 @@ struct Frag<MF_F32> {
     acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
   }
 };
+// LDS layout of the large-tile BF operands: rows of 32 bf16 (four 16-byte
+// chunks) without padding; chunk c of row r sits at position
+// c ^ (((r >> 2) ^ (r >> 4)) & 3).  Sixteen consecutive rows then cover all
+// 64 banks once for a 16-byte fragment read, eight rows of 64 bytes are
+// written in the minimum two passes, and the transposed 32-bit stores of
+// the NN kernel (rows 4 j + e) spread over every bank.
+__device__ __forceinline__ int bf_off(int r, int k) {
+  return r * 32 + (((k >> 3) ^ (((r >> 2) ^ (r >> 4)) & 3)) << 3) + (k & 7);
+}
+
 template <>
 struct Frag<MF_BF> {
   struct t {
     bf8_t h, l;
   };
   static constexpr int KS = 32;
-  __device__ static t load(const uint16_t* h, const uint16_t* l, int row, int stride, int k, int lane) {
-    const int o = row * stride + k + 8 * (lane >> 4);
+  // stride is fixed at 32 for this form (bf_off)
+  __device__ static t load(const uint16_t* h, const uint16_t* l, int row, int, int k, int lane) {
+    const int o = bf_off(row, k + 8 * (lane >> 4));
     return t{*reinterpret_cast<const bf8_t*>(h + o), *reinterpret_cast<const bf8_t*>(l + o)};
   }
   __device__ static void mma(f4_t& acc, const t& a, const t& b) {
@@ -444,7 +455,8 @@ template <int MF>
 struct BigLds {
   using L = typename Form<MF>::lds_t;
   static constexpr int BK = (MF == MF_F64) ? 16 : 32;
-  static constexpr int STRIDE = BK + (MF == MF_BF ? 8 : (MF == MF_F64 ? 2 : 4));  // 16-byte aligned rows
+  // padded rows (16-byte aligned) for FP64/FP32; the BF form swizzles instead (bf_off)
+  static constexpr int STRIDE = BK + (MF == MF_BF ? 0 : (MF == MF_F64 ? 2 : 4));
   static constexpr int PARTS = (MF == MF_BF) ? 2 : 1;
 };
 
@@ -540,8 +552,9 @@ __global__ __launch_bounds__(256) void gemm_tn_big_kernel(const TIN* __restrict_
     for (int i = 0; i < LOADS; ++i) {
       const int l = tid + i * 256;
       const int c = l / PERCOL, kv = l % PERCOL;
-      big_put_row<MF, TIN, VEC>(xh, xl, c * ST + kv * VEC, ra[i]);
-      big_put_row<MF, TIN, VEC>(yh, yl, c * ST + kv * VEC, rb[i]);
+      const int off = (MF == MF_BF) ? bf_off(c, kv * VEC) : c * ST + kv * VEC;
+      big_put_row<MF, TIN, VEC>(xh, xl, off, ra[i]);
+      big_put_row<MF, TIN, VEC>(yh, yl, off, rb[i]);
     }
   };
 
@@ -641,13 +654,23 @@ __global__ __launch_bounds__(256) void gemm_nn_big_kernel(const TIN* __restrict_
   auto store = [&](int kb) {
     if constexpr (PAIRK) {  // transpose: LDS rows are m, k contiguous
       const int k = a_k(0), mv = a_m(0);
+      const int rot = (mv / VA) & (VA - 1);  // lanes write different rows mod 4 per store (bf_off)
 #pragma unroll
-      for (int e = 0; e < VA; ++e) {
+      for (int e0 = 0; e0 < VA; ++e0) {
+        const int e = (e0 + rot) & (VA - 1);
+        float x0 = static_cast<float>(ra[0][0]), x1 = static_cast<float>(ra[1][0]);
+#pragma unroll
+        for (int q = 1; q < VA; ++q)
+          if (e == q) {
+            x0 = static_cast<float>(ra[0][q]);
+            x1 = static_cast<float>(ra[1][q]);
+          }
         const bool mi = m0 + mv + e < M;
         uint32_t hp, lp;
-        split_pair(mi ? static_cast<float>(ra[0][e]) : 0.0f, mi ? static_cast<float>(ra[1][e]) : 0.0f, hp, lp);
-        *reinterpret_cast<uint32_t*>(ah + (mv + e) * ST + k) = hp;
-        *reinterpret_cast<uint32_t*>(al + (mv + e) * ST + k) = lp;
+        split_pair(mi ? x0 : 0.0f, mi ? x1 : 0.0f, hp, lp);
+        const int off = bf_off(mv + e, k);
+        *reinterpret_cast<uint32_t*>(ah + off) = hp;
+        *reinterpret_cast<uint32_t*>(al + off) = lp;
       }
     }
 #pragma unroll
@@ -670,13 +693,21 @@ __global__ __launch_bounds__(256) void gemm_nn_big_kernel(const TIN* __restrict_
     for (int i = 0; i < BLOADS; ++i) {  // LDS rows are n, k contiguous
       const int l = tid + i * 256;
       const int n = l / (BK / VB), kv = (l % (BK / VB)) * VB;
+      if constexpr (MF == MF_BF) {  // one 16-byte chunk per part
+        VBt vh = rbh[i], vl = rbl[i];
 #pragma unroll
-      for (int e = 0; e < VB; ++e) {
-        const bool ke = kb + kv + e < K;
-        if constexpr (MF == MF_BF) {
-          bh[n * ST + kv + e] = ke ? rbh[i][e] : uint16_t(0);
-          bl[n * ST + kv + e] = ke ? rbl[i][e] : uint16_t(0);
-        } else {
+        for (int e = 0; e < VB; ++e)
+          if (kb + kv + e >= K) {
+            vh[e] = 0;
+            vl[e] = 0;
+          }
+        const int off = bf_off(n, kv);
+        *reinterpret_cast<VBt*>(bh + off) = vh;
+        *reinterpret_cast<VBt*>(bl + off) = vl;
+      } else {
+#pragma unroll
+        for (int e = 0; e < VB; ++e) {
+          const bool ke = kb + kv + e < K;
           bh[n * ST + kv + e] = ke ? static_cast<L>(rbh[i][e]) : L(0);
         }
       }

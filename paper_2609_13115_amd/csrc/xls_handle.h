@@ -155,12 +155,15 @@ const StencilLaunch& cfg_of(xls_subdomain_s* s) {
   return std::is_same<TS, float>::value ? s->cfg32 : s->cfg64;
 }
 
-// Precision schedule of the projection GEMMs: split-BF16 keeps about 16
-// mantissa bits per operand, which bounds Ritz values near 1e-5 relative, so
-// once the previous iteration's largest gated residual is below
-// kPolishResid the projection runs in FP32 (the rotation keeps gprec).
+// Precision schedule of the projection and rotation GEMMs: split-BF16 keeps
+// about 16 mantissa bits per operand.  In the projection that bounds Ritz
+// values near 1e-5 relative; in the rotation it adds white noise of about
+// 1e-5 relative to every vector, which the residual check sees amplified by
+// up to lambda_max (no filter step damps it first).  So once the previous
+// iteration's largest gated residual is at most kPolishResid, both run in
+// FP32.
 constexpr double kPolishResid = 1e-2;
-inline int projection_prec(int gprec, double prev_gated_resid) {
+inline int polish_prec(int gprec, double prev_gated_resid) {
   return (gprec == XLS_PREC_BF16X3 && prev_gated_resid <= kPolishResid) ? XLS_PREC_FP32 : gprec;
 }
 

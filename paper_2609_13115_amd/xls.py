@@ -42,7 +42,7 @@ EXPORTED = [
     "xls_batch_stats", "xls_batch_destroy",
     "xls_subdomain_counters", "xls_subdomain_features", "xls_mlp_create", "xls_mlp_destroy",
     "xls_mlp_get_params", "xls_mlp_set_params", "xls_mlp_set_norm", "xls_mlp_forward", "xls_mlp_gradient",
-    "xls_mlp_train", "xls_mlp_predict", "xls_set_graphs",
+    "xls_mlp_train", "xls_mlp_predict", "xls_set_graphs", "xls_subdomain_time_gemms",
 ]
 
 
@@ -322,6 +322,14 @@ class Subdomain:
     def xls_subdomain_tune(self, prec: int, block: int = 512, ty: int = 0, tz: int = 0, nv: int = 0):
         _check(lib().xls_subdomain_tune(self._h, C.c_int32(prec), C.c_int32(block), C.c_int32(ty),
                                         C.c_int32(tz), C.c_int32(nv)))
+
+    def xls_subdomain_time_gemms(self, gemm_prec: int, reps: int = 5) -> np.ndarray:
+        """Average device ms of (Psi^T Psi, Psi^T H Psi, Psi Q) at gemm_prec."""
+        ms = np.zeros(3)
+        rc = lib().xls_subdomain_time_gemms(self._h, C.c_int32(gemm_prec), C.c_int32(reps), _dp(ms))
+        if rc < 0:
+            _check(rc)
+        return ms
 
     def xls_subdomain_features(self) -> np.ndarray:
         f = np.zeros(64)

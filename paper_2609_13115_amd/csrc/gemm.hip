@@ -563,6 +563,27 @@ __global__ __launch_bounds__(256) void gemm_tn_big_kernel(const TIN* __restrict_
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = typename Form<MF>::acc_t{};
+  // The FP32 form (the polish projection) moves its FP32 MFMA sums into
+  // FP64 registers every kFlushSteps k-blocks (128 k): FP32 rounding then
+  // grows over 32 accumulation steps instead of the whole K split, which
+  // keeps M_s and H_s near 1e-7 relative instead of ~2e-6.
+  constexpr bool FLUSH = (MF == MF_F32);
+  constexpr int kFlushSteps = 4;
+  double accd[FLUSH ? 4 : 1][FLUSH ? 4 : 1][4] = {};
+  int since_flush = 0;
+  auto flush = [&]() {
+    if constexpr (FLUSH) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) accd[i][j][r] += static_cast<double>(acc[i][j][r]);
+          acc[i][j] = typename Form<MF>::acc_t{};
+        }
+    }
+  };
+  (void)since_flush;
 
   load(kb0);
   for (int64_t kb = kb0; kb < kend; kb += BK) {
@@ -582,7 +603,14 @@ __global__ __launch_bounds__(256) void gemm_tn_big_kernel(const TIN* __restrict_
 #pragma unroll
         for (int j = 0; j < 4; ++j) FR::mma(acc[i][j], fa[i], fb[j]);
     }
+    if constexpr (FLUSH) {
+      if (++since_flush == kFlushSteps) {
+        flush();
+        since_flush = 0;
+      }
+    }
   }
+  if constexpr (FLUSH) flush();
   double* Ps = P + static_cast<int64_t>(split) * M * N;
 #pragma unroll
   for (int i = 0; i < 4; ++i)
@@ -592,7 +620,8 @@ __global__ __launch_bounds__(256) void gemm_tn_big_kernel(const TIN* __restrict_
       for (int r = 0; r < 4; ++r) {
         const int row = m0 + wr * 64 + i * 16 + Form<MF>::orow(lane, r);
         const int cl = n0 + wc * 64 + j * 16 + (lane & 15);
-        if (row < M && cl < N) Ps[row + static_cast<int64_t>(cl) * M] = Form<MF>::get(acc[i][j], r);
+        const double v = FLUSH ? accd[i][j][r] : Form<MF>::get(acc[i][j], r);
+        if (row < M && cl < N) Ps[row + static_cast<int64_t>(cl) * M] = v;
       }
 }
 

@@ -68,6 +68,60 @@ def measured_traffic(form: str):
     return f["fetch_bytes"] + f["write_bytes"]
 
 
+def _pmc_values(path: str, counter: str):
+    """Per-dispatch values of one counter from a rocprofv3 counter CSV:
+    (fused-filter launches, device-to-device copy launches)."""
+    import csv
+
+    filt, copy = [], []
+    with open(path) as fh:
+        for r in csv.DictReader(fh):
+            if r["Counter_Name"] != counter:
+                continue
+            name, v = r["Kernel_Name"], float(r["Counter_Value"])
+            if "hstencil_kernel<" in name:
+                args = [a.strip() for a in name[name.index("<") + 1:name.index(">")].split(",")]
+                if args[2] == "1":  # MODE 1: fused filter step
+                    filt.append(v)
+            elif "copyBuffer" in name:
+                copy.append(v)
+    return filt, copy
+
+
+def write_traffic(form: str, fetch_csv: str, write_csv: str):
+    """profiles/filter_traffic.json entry of one form from a FETCH_SIZE and a
+    WRITE_SIZE rocprofv3 pass of `bench.py --calib-mib 1024`: the median per
+    filter launch (KiB), scaled by what the same counter reads for the
+    largest (1 GiB) device-to-device copies, which move exactly 1 GiB each
+    way.  Stamped with the stencil sources' hash."""
+    out = {}
+    for key, path, counter in (("fetch", fetch_csv, "FETCH_SIZE"), ("write", write_csv, "WRITE_SIZE")):
+        filt, copy = _pmc_values(path, counter)
+        if not filt or not copy:
+            raise SystemExit(f"{path}: no filter or copy dispatches for {counter}")
+        big = [c for c in copy if c >= 0.9 * max(copy)]
+        cal = float(np.median(big))
+        scale = float(1 << 20) / cal  # 1 GiB in KiB over the counter's reading
+        med = float(np.median(filt))
+        out[f"{key}_bytes"] = med * 1024 * scale
+        out[f"{key}_kib_raw_median"] = med
+        out[f"{key}_scale"] = scale
+        out[f"copy_1GiB_{key}_kib"] = cal
+        out["launches"] = len(filt)
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        t = {}
+    h = stencil_source_hash()
+    if t.get("source_sha256") != h:
+        t = {"source_sha256": h, "kiB": 1024, "forms": {}}
+    t["forms"][form] = out
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(t, fh, indent=1)
+    print(json.dumps({form: out}))
+
+
 def run_form(sd, x0, form: str, steps: int, warmup: int, degree: int):
     import torch
     from paper_2609_13115_amd import xls
@@ -234,7 +288,12 @@ def main():
                     help="first run a device-to-device copy of this many MiB (counter calibration)")
     ap.add_argument("--batch", type=int, default=8,
                     help="subdomains of the uneven batch workload to solve per form (0: skip)")
+    ap.add_argument("--write-traffic", nargs=3, metavar=("FORM", "FETCH_CSV", "WRITE_CSV"),
+                    help="record filter HBM traffic from two rocprofv3 --pmc passes and exit (no GPU)")
     a = ap.parse_args()
+    if a.write_traffic:
+        write_traffic(*a.write_traffic)
+        return
     if a.gpus != 1:
         print(json.dumps({"error": "this engine runs on one GPU; multi-GPU sharding is a design note only "
                                    "(subdomains are independent: one batch per GPU)"}))

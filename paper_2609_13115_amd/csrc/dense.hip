@@ -37,6 +37,7 @@ constexpr double kEps = 2.220446049250313e-16;
 constexpr double kSafeMin = 2.2250738585072014e-308;
 constexpr int kPanel = 32;       // Cholesky panel width
 constexpr int kInvIters = 3;     // inverse-iteration solves per vector in a cluster (2 when alone)
+constexpr int kInvChunk = 16;    // steps of a sequential sweep whose inputs load together
 constexpr double kOrtol = 1e-3;  // cluster gap, relative to |T|_1
 constexpr int kTrdPre = 8;       // column values per lane loaded ahead in a tridiagonalisation step
 
@@ -534,29 +535,46 @@ __global__ __launch_bounds__(256) void tri_inviter_kernel(const double* __restri
     double xs = lam[s];
     if (s > sb && xs - xprev < pertol) xs = xprev + pertol;
     xprev = xs;
+    // The three sequential sweeps below (LU, forward, backward) run on one
+    // thread.  Each loads kInvChunk steps' inputs into registers before it
+    // runs them, so the dependent chain waits on LDS once per chunk instead
+    // of once per step (the arrays share one LDS block, so the compiler
+    // cannot move a load above an earlier store by itself).
     if (tid == 0) {
       double bb = dd[0] - xs, cc = ee[0];
-      for (int i = 0; i + 1 < m; ++i) {
-        const double a = ee[i], b = dd[i + 1] - xs, cn = ee[i + 1];
-        if (fabs(a) > fabs(bb)) {
-          piv[i] = 1;
-          r0[i] = 1.0 / a;
-          u1[i] = b;
-          u2[i] = cn;
-          const double mult = bb / a;
-          ll[i] = mult;
-          bb = cc - mult * b;
-          cc = -mult * cn;
-        } else {
-          piv[i] = 0;
-          const double p = (fabs(bb) < pmin) ? copysign(pmin, bb) : bb;
-          r0[i] = 1.0 / p;
-          u1[i] = cc;
-          u2[i] = 0.0;
-          const double mult = a / p;
-          ll[i] = mult;
-          bb = b - mult * cc;
-          cc = cn;
+      for (int i0 = 0; i0 + 1 < m; i0 += kInvChunk) {
+        const int nstep = min(kInvChunk, m - 1 - i0);
+        double ea[kInvChunk + 1], db[kInvChunk];
+#pragma unroll
+        for (int t = 0; t <= kInvChunk; ++t) ea[t] = ee[min(i0 + t, m - 1)];
+#pragma unroll
+        for (int t = 0; t < kInvChunk; ++t) db[t] = dd[min(i0 + 1 + t, m - 1)];
+#pragma unroll
+        for (int t = 0; t < kInvChunk; ++t) {
+          if (t < nstep) {
+            const int i = i0 + t;
+            const double a = ea[t], b = db[t] - xs, cn = ea[t + 1];
+            if (fabs(a) > fabs(bb)) {
+              piv[i] = 1;
+              r0[i] = 1.0 / a;
+              u1[i] = b;
+              u2[i] = cn;
+              const double mult = bb / a;
+              ll[i] = mult;
+              bb = cc - mult * b;
+              cc = -mult * cn;
+            } else {
+              piv[i] = 0;
+              const double p = (fabs(bb) < pmin) ? copysign(pmin, bb) : bb;
+              r0[i] = 1.0 / p;
+              u1[i] = cc;
+              u2[i] = 0.0;
+              const double mult = a / p;
+              ll[i] = mult;
+              bb = b - mult * cc;
+              cc = cn;
+            }
+          }
         }
       }
       r0[m - 1] = 1.0 / ((fabs(bb) < pmin) ? copysign(pmin, bb) : bb);
@@ -574,23 +592,53 @@ __global__ __launch_bounds__(256) void tri_inviter_kernel(const double* __restri
     for (int it = 0; it < iters; ++it) {
       if (tid == 0) {
         double cur = x[0];
-        for (int i = 0; i + 1 < m; ++i) {
-          const double nx = x[i + 1];
-          if (piv[i]) {
-            x[i] = nx;
-            cur = cur - ll[i] * nx;
-          } else {
-            x[i] = cur;
-            cur = nx - ll[i] * cur;
+        for (int i0 = 0; i0 + 1 < m; i0 += kInvChunk) {
+          const int nstep = min(kInvChunk, m - 1 - i0);
+          double xn[kInvChunk], lc[kInvChunk];
+          uint8_t pc[kInvChunk];
+#pragma unroll
+          for (int t = 0; t < kInvChunk; ++t) {
+            const int i = min(i0 + t, m - 2);
+            xn[t] = x[i + 1];  // read before this chunk writes x[i0 + t]
+            lc[t] = ll[i];
+            pc[t] = piv[i];
+          }
+#pragma unroll
+          for (int t = 0; t < kInvChunk; ++t) {
+            if (t < nstep) {
+              const double nx = xn[t];
+              if (pc[t]) {
+                x[i0 + t] = nx;
+                cur = cur - lc[t] * nx;
+              } else {
+                x[i0 + t] = cur;
+                cur = nx - lc[t] * cur;
+              }
+            }
           }
         }
         double x1 = cur * r0[m - 1], x2 = 0.0;
         x[m - 1] = x1;
-        for (int i = m - 2; i >= 0; --i) {
-          const double xi = (x[i] - u1[i] * x1 - u2[i] * x2) * r0[i];
-          x[i] = xi;
-          x2 = x1;
-          x1 = xi;
+        for (int i1 = m - 2; i1 >= 0; i1 -= kInvChunk) {
+          const int nstep = min(kInvChunk, i1 + 1);
+          double xc[kInvChunk], a1[kInvChunk], a2[kInvChunk], rc[kInvChunk];
+#pragma unroll
+          for (int t = 0; t < kInvChunk; ++t) {
+            const int i = max(i1 - t, 0);
+            xc[t] = x[i];
+            a1[t] = u1[i];
+            a2[t] = u2[i];
+            rc[t] = r0[i];
+          }
+#pragma unroll
+          for (int t = 0; t < kInvChunk; ++t) {
+            if (t < nstep) {
+              const double xi = (xc[t] - a1[t] * x1 - a2[t] * x2) * rc[t];
+              x[i1 - t] = xi;
+              x2 = x1;
+              x1 = xi;
+            }
+          }
         }
       }
       __syncthreads();

@@ -487,7 +487,7 @@ __device__ __forceinline__ void big_put_row(typename Form<MF>::lds_t* h, typenam
 
 // Partial C = A^T B over one K split, 128 x 128 output tile per workgroup.
 template <typename TIN, int MF>
-__global__ __launch_bounds__(256) void gemm_tn_big_kernel(const TIN* __restrict__ A, int64_t lda,
+__global__ __launch_bounds__(256, 2) void gemm_tn_big_kernel(const TIN* __restrict__ A, int64_t lda,
                                                           const TIN* __restrict__ B, int64_t ldb, int M,
                                                           int N, int64_t K, int64_t kchunk, int tm, int tn,
                                                           int sym, double* __restrict__ P) {
@@ -563,13 +563,15 @@ __global__ __launch_bounds__(256) void gemm_tn_big_kernel(const TIN* __restrict_
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = typename Form<MF>::acc_t{};
-  // The FP32 form (the polish projection) moves its FP32 MFMA sums into
-  // FP64 registers every kFlushSteps k-blocks (128 k): FP32 rounding then
-  // grows over 32 accumulation steps instead of the whole K split, which
-  // keeps M_s and H_s near 1e-7 relative instead of ~2e-6.
+  // The FP32 form (the polish projection) moves its MFMA sums into a
+  // second FP32 accumulator every kFlushSteps k-blocks (128 k), so rounding
+  // grows over 32 MFMA steps and then over the few hundred flushes of a K
+  // split, instead of over thousands of steps in one accumulator.  (FP64
+  // registers measured no more accurate at the Ritz level and cost
+  // occupancy.)
   constexpr bool FLUSH = (MF == MF_F32);
   constexpr int kFlushSteps = 4;
-  double accd[FLUSH ? 4 : 1][FLUSH ? 4 : 1][4] = {};
+  float accd[FLUSH ? 4 : 1][FLUSH ? 4 : 1][4] = {};
   int since_flush = 0;
   auto flush = [&]() {
     if constexpr (FLUSH) {
@@ -578,7 +580,7 @@ __global__ __launch_bounds__(256) void gemm_tn_big_kernel(const TIN* __restrict_
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
 #pragma unroll
-          for (int r = 0; r < 4; ++r) accd[i][j][r] += static_cast<double>(acc[i][j][r]);
+          for (int r = 0; r < 4; ++r) accd[i][j][r] += acc[i][j][r];
           acc[i][j] = typename Form<MF>::acc_t{};
         }
     }
@@ -620,7 +622,7 @@ __global__ __launch_bounds__(256) void gemm_tn_big_kernel(const TIN* __restrict_
       for (int r = 0; r < 4; ++r) {
         const int row = m0 + wr * 64 + i * 16 + Form<MF>::orow(lane, r);
         const int cl = n0 + wc * 64 + j * 16 + (lane & 15);
-        const double v = FLUSH ? accd[i][j][r] : Form<MF>::get(acc[i][j], r);
+        const double v = FLUSH ? static_cast<double>(accd[i][j][r]) : Form<MF>::get(acc[i][j], r);
         if (row < M && cl < N) Ps[row + static_cast<int64_t>(cl) * M] = v;
       }
 }

@@ -17,6 +17,7 @@
 // (TILE/2)^2 block of 16 x 16 MFMA tiles; operands staged through LDS with k
 // contiguous.
 #include <algorithm>
+#include <atomic>
 
 #include "xls_internal.h"
 
@@ -633,7 +634,7 @@ __global__ __launch_bounds__(256, 2) void gemm_tn_big_kernel(const TIN* __restri
 // rows m .. m + 15 across lanes (coalesced stores).  TB is the B operand as
 // stored: double (FP64), float (FP32) or bf16 hi/lo pairs (BF; Bh/Bl).
 template <typename TIN, typename TB, typename TOUT, int MF>
-__global__ __launch_bounds__(256) void gemm_nn_big_kernel(const TIN* __restrict__ A, int64_t lda,
+__global__ __launch_bounds__(256, 2) void gemm_nn_big_kernel(const TIN* __restrict__ A, int64_t lda,
                                                           const TB* __restrict__ Bh, const TB* __restrict__ Bl,
                                                           int64_t ldb, int M, int N, int K, int tnN,
                                                           TOUT* __restrict__ C, int64_t ldc) {
@@ -794,6 +795,21 @@ __global__ void split_bf16_from_f64_kernel(const double* __restrict__ s, uint16_
 
 constexpr int kTile = 64;
 
+// compute units of the current device (cached per device)
+int device_cus() {
+  static std::atomic<int> cached[64];
+  int dev = 0;
+  XLS_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) dev = 0;
+  int c = cached[dev].load(std::memory_order_relaxed);
+  if (c == 0) {
+    XLS_HIP(hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev));
+    c = std::max(1, c);
+    cached[dev].store(c, std::memory_order_relaxed);
+  }
+  return c;
+}
+
 int choose_splits(int tiles, int64_t K, int bk, int M, int N, size_t work_elems) {
   // aim for ~2048 workgroups; each split must keep >= 8 k-blocks
   int s = std::max(1, 2048 / std::max(1, tiles));
@@ -814,16 +830,15 @@ void tn_dispatch(const TIN* A, int64_t lda, const TIN* B, int64_t ldb, int M, in
                  double* C, int64_t ldc, int sym, int symmetrize, double* work, size_t work_elems,
                  hipStream_t st) {
   constexpr int VEC = 16 / sizeof(TIN);
-  // FP64 keeps the 64-wide tiles: with its 4 x 4 FP64 accumulator blocks the
-  // large tile runs one workgroup per CU and was measured slower
-  if (MF != MF_F64 && M >= 64 && N >= 64 && lda % VEC == 0 && ldb % VEC == 0 && K <= lda && K <= ldb &&
+  if (M >= 64 && N >= 64 && lda % VEC == 0 && ldb % VEC == 0 && K <= lda && K <= ldb &&
       aligned16(A) && aligned16(B)) {
     constexpr int T = 128;
     const int tm = (M + T - 1) / T, tn = (N + T - 1) / T;
     const int ntile = sym ? tm * (tm + 1) / 2 : tm * tn;
     const int bk = BigLds<MF>::BK;
-    // about three resident workgroups per CU, >= 16 K slabs per split
-    int splits = std::max(1, 768 / ntile);
+    // about two resident workgroups per CU (the kernel's occupancy), so that
+    // symmetric products (fewer tiles) get more splits; >= 16 K slabs each
+    int splits = std::max(1, 2 * device_cus() / ntile);
     splits = static_cast<int>(std::min<int64_t>(splits, std::max<int64_t>(1, K / (16 * bk))));
     const size_t per = static_cast<size_t>(M) * N;
     splits = static_cast<int>(std::min<size_t>(splits, std::max<size_t>(1, work_elems / per)));
@@ -857,9 +872,9 @@ void tn_dispatch(const TIN* A, int64_t lda, const TIN* B, int64_t ldb, int M, in
 
 size_t gemm_tn_work_elems(int M, int N, int64_t K) {
   (void)K;
-  // room for up to 32 splits, capped at 64 Mi doubles
+  // room for up to 64 splits, capped at 32 Mi doubles (256 MB)
   const size_t per = static_cast<size_t>(M) * N;
-  return std::max<size_t>(per, std::min<size_t>(32 * per, static_cast<size_t>(64) << 20));
+  return std::max<size_t>(per, std::min<size_t>(64 * per, static_cast<size_t>(32) << 20));
 }
 
 template <typename TS>

@@ -166,7 +166,7 @@ def run_form(sd, x0, form: str, steps: int, warmup: int, degree: int):
     }
 
 
-def time_gemms(s, nd: int, ns: int, form: str):
+def time_gemms(s, nd: int, ns: int, form: str, reps: int = 5):
     """TFLOP/s of the three GEMMs at each precision of the form: algorithmic
     flops (N_d N_s^2 for the symmetric product, 2 N_d N_s^2 for the others)
     and issued MFMA flops (x3 for the split-BF16 form) against the dtype's
@@ -178,7 +178,7 @@ def time_gemms(s, nd: int, ns: int, form: str):
     flops = {"xtx": nd * ns * ns, "xthx": 2.0 * nd * ns * ns, "rotation": 2.0 * nd * ns * ns}
     out = {}
     for name, p in precs:
-        ms = s.xls_subdomain_time_gemms(p, 5)
+        ms = s.xls_subdomain_time_gemms(p, reps)
         issue = 3.0 if name == "bf16x3" else 1.0
         o = {}
         for (k, f), t in zip(flops.items(), ms):
@@ -186,6 +186,23 @@ def time_gemms(s, nd: int, ns: int, form: str):
             o[k] = {"ms": t, "tflops": tf, "issued_tflops": issue * tf,
                     "frac": issue * tf / MFMA_PEAK_TFLOPS[name]}
         out[name] = o
+    return out
+
+
+def gemm_large(reps: int = 3):
+    """The three GEMMs at the large-subdomain shape (96^3 box, N_d = 884,736,
+    Ns = 2,400; X0 random-normal from the seeded generator), FP32 block for
+    bf16x3 and FP32, FP64 block for FP64."""
+    from paper_2609_13115_amd import workloads, xls
+
+    sd = workloads.cfg4(with_x0=False)
+    x0 = sd.make_x0()
+    nd, ns = sd.nd, x0.shape[1]
+    out = {"workload": f"96^3 zero-Dirichlet Si box, N_d = {nd}, Ns = {ns}, X0 random-normal"}
+    for form, prec in (("mixed", xls.XLS_PREC_FP32), ("fp64", xls.XLS_PREC_FP64)):
+        with xls.Subdomain(sd, filter_prec=prec, x0=x0) as s:
+            out.update(time_gemms(s, nd, ns, form, reps))
+        print(f"[bench] gemm_large {form}: done", file=sys.stderr, flush=True)
     return out
 
 
@@ -288,6 +305,8 @@ def main():
                     help="first run a device-to-device copy of this many MiB (counter calibration)")
     ap.add_argument("--batch", type=int, default=8,
                     help="subdomains of the uneven batch workload to solve per form (0: skip)")
+    ap.add_argument("--gemm-large", action="store_true",
+                    help="also time the GEMMs at the 96^3, Ns = 2400 shape (about 3 minutes; 17 GB host memory)")
     ap.add_argument("--write-traffic", nargs=3, metavar=("FORM", "FETCH_CSV", "WRITE_CSV"),
                     help="record filter HBM traffic from two rocprofv3 --pmc passes and exit (no GPU)")
     a = ap.parse_args()
@@ -354,6 +373,8 @@ def main():
                        "stage_ms_per_step": f["stage_ms_per_step"], "gemm": f["gemm"]}
     if a.batch > 0:
         out["batch"] = run_batch(a.batch, forms)
+    if a.gemm_large:
+        out["gemm_large"] = gemm_large()
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(sd, a.degree, a.cpu_cols)
     print(json.dumps(out), flush=True)

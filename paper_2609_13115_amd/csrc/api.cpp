@@ -566,8 +566,8 @@ int xls_subdomain_create(const xls_subdomain_desc_t* d, xls_subdomain_t* out) {
       };
       fill_op(s->op64, s->v64, s->val64, s->rev_val64);
       fill_op(s->op32, s->v32, s->val32, s->rev_val32);
-      s->cfg64.block = 256;
-      s->cfg32.block = 256;
+      s->cfg64.block = 0;  // 256 threads unless the tile's halo needs 512
+      s->cfg32.block = 0;
       stencil_validate(s->n[0], s->n[1], s->n[2], s->bc == XLS_BC_PERIODIC, 8, s->nproj(), s->cfg64);
       stencil_validate(s->n[0], s->n[1], s->n[2], s->bc == XLS_BC_PERIODIC, 4, s->nproj(), s->cfg32);
       // blocks and work

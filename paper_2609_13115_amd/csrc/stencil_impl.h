@@ -663,9 +663,23 @@ struct TileChoice {
 // Launch plan.  Vector runs (XV = 16/elem points per lane) when nx and the
 // column stride are multiples of XV; else one point per lane-slot, up to 4
 // slots per lane.  Default tile: the most rows the block covers.
-inline TileChoice choose_tiles(int nx, int ny, int nz, int elem, int nproj, int64_t ld, const StencilLaunch& cfg) {
+inline int default_ty(int nx, int ny, int elem, int block, const StencilLaunch& cfg) {
+  // default tile: ~2 points per lane in FP32, ~1 in FP64 (measured best on
+  // the 64^3 box: more resident workgroups beat a smaller y-halo)
+  const int target = (elem == 4 ? 2 : 1) * block;
+  const int ty = cfg.ty > 0 ? cfg.ty : std::max(1, target / nx);
+  return std::max(1, std::min(ty, ny));
+}
+
+inline TileChoice choose_tiles(int nx, int ny, int nz, int elem, int nproj, int64_t ld, int periodic,
+                               const StencilLaunch& cfg) {
   TileChoice tc{};
-  tc.block = cfg.block == 256 ? 256 : 512;
+  if (cfg.block == 0) {  // 256 threads when their halo budget covers the tile's halo, else 512
+    const int ty = default_ty(nx, ny, elem, 256, cfg);
+    tc.block = (2 * R * nx + (periodic ? 2 * R * ty : 0) <= HMAX * 256) ? 256 : 512;
+  } else {
+    tc.block = cfg.block == 256 ? 256 : 512;
+  }
   const int XV = 16 / elem;
   tc.vec = false;
   (void)XV;
@@ -677,11 +691,7 @@ inline TileChoice choose_tiles(int nx, int ny, int nz, int elem, int nproj, int6
     ty = std::max(1, std::min(ty, ny));
     if (ty * tpr > tc.block) ty = std::max(1, tc.block / tpr);
   } else {
-    // default tile: ~2 points per lane in FP32, ~1 in FP64 (measured best on
-    // the 64^3 box: more resident workgroups beat a smaller y-halo)
-    const int target = (elem == 4 ? 2 : 1) * tc.block;
-    ty = cfg.ty > 0 ? cfg.ty : std::max(1, target / nx);
-    ty = std::max(1, std::min(ty, ny));
+    ty = default_ty(nx, ny, elem, tc.block, cfg);
   }
   tc.ty = ty;
   tc.nyt = (ny + ty - 1) / ty;
@@ -770,18 +780,19 @@ using namespace stencil_detail;
 
 template <typename TC>
 static TileChoice tiles_for(const OpTables<TC>& op, int64_t ld, const StencilLaunch& cfg) {
-  return choose_tiles(op.nx, op.ny, op.nz, sizeof(TC), 4 * op.n_atoms, ld, cfg);
+  return choose_tiles(op.nx, op.ny, op.nz, sizeof(TC), 4 * op.n_atoms, ld, op.periodic, cfg);
 }
 
 #ifdef XLS_STENCIL_DEFINE_HOST
 void stencil_validate(int nx, int ny, int nz, int periodic, int elem_bytes, int nproj,
                       const StencilLaunch& cfg) {
-  if (cfg.block != 256 && cfg.block != 512) fail(XLS_ERR_INVALID_ARG, "stencil block must be 256 or 512");
+  if (cfg.block != 0 && cfg.block != 256 && cfg.block != 512)
+    fail(XLS_ERR_INVALID_ARG, "stencil block must be 0 (choose), 256 or 512");
   if (cfg.ty < 0 || cfg.tz < 0) fail(XLS_ERR_INVALID_ARG, "stencil tile sizes must be >= 0");
   if (cfg.nv < 0 || cfg.nv > 2) fail(XLS_ERR_INVALID_ARG, "stencil vectors per tile must be 0, 1 or 2");
   // both variants a launch may take (vector runs need an aligned column stride)
-  check_tiles(choose_tiles(nx, ny, nz, elem_bytes, nproj, 64, cfg), nx, periodic, elem_bytes);
-  check_tiles(choose_tiles(nx, ny, nz, elem_bytes, nproj, 1, cfg), nx, periodic, elem_bytes);
+  check_tiles(choose_tiles(nx, ny, nz, elem_bytes, nproj, 64, periodic, cfg), nx, periodic, elem_bytes);
+  check_tiles(choose_tiles(nx, ny, nz, elem_bytes, nproj, 1, periodic, cfg), nx, periodic, elem_bytes);
 }
 
 size_t stencil_partial_elems(const OpTables<float>& op, int ncols, const StencilLaunch& cfg) {

@@ -71,7 +71,7 @@ struct OpTables {
 };
 
 struct StencilLaunch {
-  int block = 256;  // threads: 256 or 512
+  int block = 0;    // threads: 256 or 512 (0 = 256 when its halo budget suffices, else 512)
   int ty = 0;       // rows per tile (0 = choose)
   int tz = 0;       // z-chunk (0 = whole nz)
   int nv = 0;       // vectors per tile: 1 or 2 (0 = choose; residual sweeps take 1)

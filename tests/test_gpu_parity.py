@@ -451,6 +451,40 @@ def test_bitwise_determinism():
         assert np.array_equal(a, b)
 
 
+def test_wide_box_takes_512_thread_tiles():
+    """A 96-point row: its y-halo exceeds what 256 threads stage, so the
+    default launch shape takes 512-thread tiles; H apply and a filter pass
+    still match the oracle."""
+    case("wide box 96 x 10 x 12")
+    sd = workloads.small_dirichlet(ns=3, shape=(96, 10, 12), h=0.2, index=4)
+    op = hamiltonian.from_subdomain(sd)
+    with xls.Subdomain(sd) as s:
+        assert rel_err(s.xls_hamiltonian_apply(sd.x0), op.apply(sd.x0)) <= 1e-12
+        lo, up = chefsi.lanczos_bounds(op.apply, sd.lanczos_v0, 20)
+        lc = chefsi.first_cutoff(lo, up)
+        s.xls_subdomain_filter(3, lo, lc, up)
+        assert rel_err(s.xls_subdomain_get_block(), chefsi.chebyshev_filter(op.apply, sd.x0, 3, lo, lc, up)) <= 1e-11
+        with pytest.raises(xls.XlsError) as ei:
+            s.xls_subdomain_tune(xls.XLS_PREC_FP64, 256, 0, 0)  # 256 threads cannot stage this halo
+        assert ei.value.code == xls.XLS_ERR_INVALID_ARG
+
+
+def test_time_gemms_leaves_block_and_checks_precision():
+    case("time gemms")
+    sd = workloads.small_dirichlet(ns=70, shape=(13, 9, 20), index=2)
+    with xls.Subdomain(sd, filter_prec=xls.XLS_PREC_FP32) as s:
+        before = s.xls_subdomain_get_block()
+        for p in (xls.XLS_PREC_FP32, xls.XLS_PREC_BF16X3):
+            ms = s.xls_subdomain_time_gemms(p, 2)
+            assert ms.shape == (3,) and np.all(ms > 0)
+        assert np.array_equal(before, s.xls_subdomain_get_block())
+    with xls.Subdomain(sd) as s:
+        assert np.all(s.xls_subdomain_time_gemms(xls.XLS_PREC_FP64, 1) > 0)
+        with pytest.raises(xls.XlsError) as ei:
+            s.xls_subdomain_time_gemms(xls.XLS_PREC_BF16X3, 1)
+        assert ei.value.code == xls.XLS_ERR_INVALID_ARG
+
+
 def test_failure_paths():
     case("failure paths")
     sd = workloads.small_dirichlet(ns=4)

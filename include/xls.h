@@ -204,7 +204,7 @@ int xls_split_bf16(const float* a, uint16_t* hi, uint16_t* lo, int64_t n);
 /* Launch shape of the handle's stencil sweeps in storage precision prec
  * (XLS_PREC_FP64 or XLS_PREC_FP32): block threads (256 or 512; 0: 256
  * when its per-thread halo budget covers the tile, else 512), ty rows
- * per tile (0: about 2 points per thread in FP32, 1 in FP64), tz planes per
+ * per tile (0: about 2 points per thread), tz planes per
  * z-chunk (0: the whole box), nv vectors per tile (1 or 2; 0: choose).  A
  * tile of 2 vectors reads the operator tables (V, projector entries) once
  * for both; residual sweeps always take 1.  The shape changes scheduling

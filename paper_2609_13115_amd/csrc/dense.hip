@@ -239,14 +239,15 @@ __global__ __launch_bounds__(256) void trd_step_kernel(double* __restrict__ A, i
                                                        const int32_t* __restrict__ flag) {
   extern __shared__ double sm[];
   __shared__ double red[4];
-  if (*flag) return;
+  // the failure flag, the stored column k and this wave's trailing column do
+  // not depend on this launch's vector work: all three loads are issued
+  // before the flag is tested (every address is in range either way), so
+  // their latencies overlap
+  const int32_t failed = *flag;
   double* w = sm;
   double* cv = sm + n;
   double* vp = sm + 2 * n;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  // the stored column k and this wave's trailing column do not depend on
-  // this launch's vector work: load them first so that their latency
-  // overlaps it
   const double* colk = A + static_cast<int64_t>(k) * n;
   double ck[kTrdPre];
 #pragma unroll
@@ -262,6 +263,7 @@ __global__ __launch_bounds__(256) void trd_step_kernel(double* __restrict__ A, i
     const int j = k + 1 + lane + 64 * r;
     co[r] = (iown < n && j < n) ? colown[j] : 0.0;
   }
+  if (failed) return;
   const double* vprev = vbuf + ((k + 1) & 1) * static_cast<int64_t>(n);
   const double* pprev = pbuf + ((k + 1) & 1) * static_cast<int64_t>(n);
   double* vcur = vbuf + (k & 1) * static_cast<int64_t>(n);

@@ -587,7 +587,7 @@ int xls_subdomain_create(const xls_subdomain_desc_t* d, xls_subdomain_t* out) {
       s->Mdev = dalloc<double>(nn);
       s->Hsdev = dalloc<double>(nn);
       s->Ydev = dalloc<double>(nn);
-      s->bwork = dalloc<float>(nn);
+      s->bwork = dalloc<float>(2 * nn_work_doubles(s->ns, s->ns));
       s->gwork_elems = std::max(gemm_tn_work_elems(s->ns, s->ns, s->nd), static_cast<size_t>(64) * 1024);
       s->gwork = dalloc<double>(s->gwork_elems);
       s->vsmall = dalloc<double>(1024);

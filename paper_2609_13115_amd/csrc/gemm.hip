@@ -783,11 +783,29 @@ __global__ __launch_bounds__(256, 2) void gemm_nn_big_kernel(const TIN* __restri
       }
 }
 
-__global__ void split_bf16_from_f64_kernel(const double* __restrict__ s, uint16_t* __restrict__ hi,
-                                           uint16_t* __restrict__ lo, int64_t n) {
+// The rotation matrix B (rows x cols, leading dimension lds) copied with a
+// leading dimension ldd >= rows padded to the kernels' 16-byte k loads; the
+// padding rows are zero.  FP64 copy, FP32 rounding, or bf16 hi/lo split.
+__global__ void pad_f64_kernel(const double* __restrict__ s, int64_t lds, double* __restrict__ d, int64_t ldd,
+                               int64_t rows, int64_t cols) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const float a = static_cast<float>(s[i]);
+  if (i >= ldd * cols) return;
+  const int64_t r = i % ldd, c = i / ldd;
+  d[i] = r < rows ? s[r + c * lds] : 0.0;
+}
+__global__ void pad_f32_kernel(const double* __restrict__ s, int64_t lds, float* __restrict__ d, int64_t ldd,
+                               int64_t rows, int64_t cols) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= ldd * cols) return;
+  const int64_t r = i % ldd, c = i / ldd;
+  d[i] = r < rows ? static_cast<float>(s[r + c * lds]) : 0.0f;
+}
+__global__ void split_bf16_from_f64_kernel(const double* __restrict__ s, int64_t lds, uint16_t* __restrict__ hi,
+                                           uint16_t* __restrict__ lo, int64_t ldd, int64_t rows, int64_t cols) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= ldd * cols) return;
+  const int64_t r = i % ldd, c = i / ldd;
+  const float a = r < rows ? static_cast<float>(s[r + c * lds]) : 0.0f;
   const uint16_t h = bf16_rne_bits(a);
   hi[i] = h;
   lo[i] = bf16_rne_bits(a - bf16_bits_to_f32(h));
@@ -870,6 +888,10 @@ void tn_dispatch(const TIN* A, int64_t lda, const TIN* B, int64_t ldb, int M, in
 
 }  // namespace
 
+size_t nn_work_doubles(int K, int N) {
+  return static_cast<size_t>((static_cast<int64_t>(K) + 7) / 8 * 8) * static_cast<size_t>(N);
+}
+
 size_t gemm_tn_work_elems(int M, int N, int64_t K) {
   (void)K;
   // room for up to 64 splits, capped at 32 Mi doubles (256 MB)
@@ -904,31 +926,42 @@ bool nn_big(int prec, const TS* A, int64_t lda, const double* B, int64_t ldb, in
             int64_t ldc, void* bwork, hipStream_t st) {
   constexpr int VA = 16 / sizeof(TS);
   if (M < 64 || N < 64 || lda % VA != 0 || !aligned16(A) || M > lda || K > ldb) return false;
+  const bool have_work = bwork != nullptr && aligned16(bwork);
   const int tnN = (N + 255) / 256;
   const int64_t nb = static_cast<int64_t>((M + 63) / 64) * tnN;
   if (nb > 0x7fffffff) return false;
   const dim3 grid(static_cast<unsigned>(nb));
-  const int64_t nbv = ldb * static_cast<int64_t>(N);
+  // B goes through bwork with its leading dimension padded to 8 rows
+  // (bwork holds nn_work_elems(K, N) doubles)
+  const int64_t ldp = (static_cast<int64_t>(K) + 7) / 8 * 8;
+  const int64_t nbv = ldp * static_cast<int64_t>(N);
+  const unsigned pgrid = static_cast<unsigned>((nbv + 255) / 256);
   if (prec == MF_F64) {
-    if (ldb % 2 != 0 || !aligned16(B)) return false;
-    hipLaunchKernelGGL((gemm_nn_big_kernel<TS, double, TS, MF_F64>), grid, dim3(256), 0, st, A, lda, B,
-                       static_cast<const double*>(nullptr), ldb, M, N, K, tnN, C, ldc);
+    const double* Bd = B;
+    int64_t ldbd = ldb;
+    if (ldb % 2 != 0 || !aligned16(B)) {
+      if (!have_work) return false;
+      double* Bp = static_cast<double*>(bwork);
+      hipLaunchKernelGGL(pad_f64_kernel, dim3(pgrid), dim3(256), 0, st, B, ldb, Bp, ldp, K, N);
+      Bd = Bp;
+      ldbd = ldp;
+    }
+    hipLaunchKernelGGL((gemm_nn_big_kernel<TS, double, TS, MF_F64>), grid, dim3(256), 0, st, A, lda, Bd,
+                       static_cast<const double*>(nullptr), ldbd, M, N, K, tnN, C, ldc);
   } else if constexpr (std::is_same<TS, float>::value) {
+    if (!have_work) return false;
     if (prec == MF_F32) {
-      if (ldb % 4 != 0) return false;
       float* Bf = static_cast<float*>(bwork);
-      hipLaunchKernelGGL(d2f_kernel, dim3(static_cast<unsigned>((nbv + 255) / 256)), dim3(256), 0, st, B, Bf, nbv);
+      hipLaunchKernelGGL(pad_f32_kernel, dim3(pgrid), dim3(256), 0, st, B, ldb, Bf, ldp, K, N);
       hipLaunchKernelGGL((gemm_nn_big_kernel<float, float, float, MF_F32>), grid, dim3(256), 0, st, A, lda, Bf,
-                         static_cast<const float*>(nullptr), ldb, M, N, K, tnN, C, ldc);
+                         static_cast<const float*>(nullptr), ldp, M, N, K, tnN, C, ldc);
     } else if (prec == MF_BF) {
-      if (ldb % 8 != 0) return false;
       // the rotation matrix is split into bf16 hi/lo once (same bytes as its FP32 copy)
       uint16_t* bh = static_cast<uint16_t*>(bwork);
       uint16_t* bl = bh + nbv;
-      hipLaunchKernelGGL(split_bf16_from_f64_kernel, dim3(static_cast<unsigned>((nbv + 255) / 256)), dim3(256), 0,
-                         st, B, bh, bl, nbv);
+      hipLaunchKernelGGL(split_bf16_from_f64_kernel, dim3(pgrid), dim3(256), 0, st, B, ldb, bh, bl, ldp, K, N);
       hipLaunchKernelGGL((gemm_nn_big_kernel<float, uint16_t, float, MF_BF>), grid, dim3(256), 0, st, A, lda, bh, bl,
-                         ldb, M, N, K, tnN, C, ldc);
+                         ldp, M, N, K, tnN, C, ldc);
     } else {
       return false;
     }

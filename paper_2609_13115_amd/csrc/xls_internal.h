@@ -140,12 +140,17 @@ size_t stencil_partial_elems(const OpTables<double>& op, int ncols, const Stenci
 //   gemm_tn: C[M x N] = A^T B, A is K x M (lda), B is K x N (ldb); FP64 result.
 //            sym = 1: only C's upper tiles are formed, then mirrored (A == B).
 //            symmetrize = 1: C = (S + S^T)/2 (M == N).
-//   gemm_nn: C[M x N] = A[M x K] B[K x N]; B given in FP64 and converted.
+//   gemm_nn: C[M x N] = A[M x K] B[K x N]; B given in FP64 and converted
+//            (or padded) into bwork, nn_work_doubles(K, N) doubles, 16-byte
+//            aligned; bwork may be null only for FP64 calls (the small-tile
+//            path is taken when B would need padding).
 template <typename TS>
 void gemm_tn(int prec, const TS* A, int64_t lda, const TS* B, int64_t ldb, int M, int N, int64_t K,
              double* C, int64_t ldc, int sym, int symmetrize, double* work, size_t work_elems,
              hipStream_t st);
 size_t gemm_tn_work_elems(int M, int N, int64_t K);
+// doubles of the rotation work buffer (B copied with rows padded to 8)
+size_t nn_work_doubles(int K, int N);
 template <typename TS>
 void gemm_nn(int prec, const TS* A, int64_t lda, const double* B, int64_t ldb, int M, int N, int K,
              TS* C, int64_t ldc, void* bwork, hipStream_t st);

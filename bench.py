@@ -18,6 +18,9 @@ projection and rotation GEMMs (HIP events) in each precision of the form.
 The batch object runs the first subdomains of the 256-subdomain uneven batch
 workload to convergence (gated residual <= 1e-4), mixed and FP64, and
 reports subdomains/s and the largest Ritz-value difference between the two.
+The learned object trains the MLP on method-made labels of two-phase boxes,
+then batch-solves held-out boxes with FP64 + Lanczos bounds and with mixed
++ learned bounds.
 cpu_baseline times the FP64 oracle's filter on a column sample on the host.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--form mixed|fp64|both] [--no-cpu]
@@ -206,6 +209,62 @@ def gemm_large(reps: int = 3):
     return out
 
 
+def run_learned(n_train: int = 96, n_held: int = 64):
+    """FP64 + Lanczos bounds against mixed + learned bounds, both batched, on
+    held-out boxes of the two-phase system.  The model is trained first, on
+    labels the method computes for n_train other boxes (untimed); the mixed
+    form's timed region includes the device feature pass and the bf16
+    inference."""
+    import torch
+    from paper_2609_13115_amd import learned, workloads, xls
+
+    gs = workloads.two_phase_system()
+    _, train = workloads.learned_bounds_subdomains(n_train, index0=0, gs=gs)
+    _, held = workloads.learned_bounds_subdomains(n_held, index0=1000, gs=gs)
+    t0 = time.perf_counter()
+    lab = learned.label_subdomains(train)
+    model, losses = learned.train_model(lab.features, lab.targets, epochs=300)
+    t_train = time.perf_counter() - t0
+    gates = [max(1, int(np.floor(sd.ns / 1.1 + 1e-9))) for sd in held]
+    tol = 1e-4
+    out = {"workload": f"{n_held} held-out two-phase boxes (n 14-22 per axis, ns 8-48); model trained on "
+                       f"{n_train} labelled boxes in {t_train:.1f} s",
+           "subdomains": n_held}
+
+    def solve(prec, make_params, warm):
+        with xls.Batch(warm, filter_prec=prec) as b:  # loads this form's code objects
+            b.xls_batch_chefsi(make_params(b, 2))
+        with xls.Batch(held, filter_prec=prec) as b:
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            ritz, resid, iters, status = b.xls_batch_chefsi(make_params(b, 30))
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t
+        conv = [int(st == xls.XLS_OK and float(np.max(r[:g])) <= tol) for st, r, g in zip(status, resid, gates)]
+        return t, ritz, [int(i) for i in iters], conv
+
+    def fp64_params(b, it):
+        return [xls.chefsi_params(24, it, xls.XLS_BOUNDS_LANCZOS, resid_tol=tol) for _ in range(b.n)]
+
+    def learned_params(b, it):
+        F = learned.batch_features(b)
+        return learned.batch_learned_params(model, F, it, tol, xls.XLS_PREC_BF16X3)
+
+    warm = held[:2]
+    tf, rf, itf, cf = solve(xls.XLS_PREC_FP64, fp64_params, warm)
+    tm, rm, itm, cm = solve(xls.XLS_PREC_FP32, learned_params, warm)
+    both = [float(np.max(np.abs(a[:g] - b[:g]))) for a, b, g, u, v in zip(rm, rf, gates, cm, cf) if u and v]
+    out["fp64_lanczos"] = {"seconds": tf, "subdomains_per_s": n_held / tf, "iterations": int(sum(itf)),
+                           "converged": int(sum(cf))}
+    out["mixed_learned"] = {"seconds": tm, "subdomains_per_s": n_held / tm, "iterations": int(sum(itm)),
+                            "converged": int(sum(cm))}
+    out["speedup"] = tf / tm
+    out["max_ritz_diff_ha_converged"] = max(both) if both else None
+    model.close()
+    print(f"[bench] learned: {json.dumps(out)}", file=sys.stderr, flush=True)
+    return out
+
+
 def copy_rate(mib: int = 1024, reps: int = 5):
     """Device-to-device copy GB/s (read + write bytes) from torch events: the
     practical HBM rate of a plain streaming kernel on this GPU."""
@@ -305,6 +364,7 @@ def main():
                     help="first run a device-to-device copy of this many MiB (counter calibration)")
     ap.add_argument("--batch", type=int, default=8,
                     help="subdomains of the uneven batch workload to solve per form (0: skip)")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-bounds batch comparison")
     ap.add_argument("--gemm-large", action="store_true",
                     help="also time the GEMMs at the 96^3, Ns = 2400 shape (about 3 minutes; 17 GB host memory)")
     ap.add_argument("--write-traffic", nargs=3, metavar=("FORM", "FETCH_CSV", "WRITE_CSV"),
@@ -373,6 +433,8 @@ def main():
                        "stage_ms_per_step": f["stage_ms_per_step"], "gemm": f["gemm"]}
     if a.batch > 0:
         out["batch"] = run_batch(a.batch, forms)
+    if not a.no_learned and a.form == "both":
+        out["learned"] = run_learned()
     if a.gemm_large:
         out["gemm_large"] = gemm_large()
     if not a.no_cpu:

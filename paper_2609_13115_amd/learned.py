@@ -139,6 +139,23 @@ def learned_params(lmax: float, lcut: float, degree: int, max_iter: int = 12, to
                              fallback_degree=fallback_degree)
 
 
+def batch_learned_params(model: "xls.Mlp", F: np.ndarray, max_iter: int = 30, tol: float = 1e-4,
+                         gemm_prec: int = xls.XLS_PREC_BF16X3) -> list:
+    """Per-subdomain learned parameters for a batch (xls_batch_chefsi has no
+    Lanczos fallback): predicted bounds made safe as in run_learned."""
+    lmax, lcut, deg = predict_bounds(model, F)
+    margin = CUT_SIGMAS * float(getattr(model, "train_rms", [0, 0])[1])
+    params = []
+    for lm, lc, m in zip(lmax, lcut, deg):
+        lm, lc = float(lm), float(lc)
+        if not lc < lm:
+            lc = 0.5 * lm
+        lm, lc = safe_bounds(lm, lc, margin)
+        params.append(xls.chefsi_params(int(m), max_iter, xls.XLS_BOUNDS_LEARNED, lam_cut=lc, lam_max=lm,
+                                        resid_tol=tol, gemm_prec=gemm_prec))
+    return params
+
+
 @dataclasses.dataclass
 class RunStats:
     h_applies: int

@@ -40,6 +40,8 @@ constexpr int kInvIters = 3;     // inverse-iteration solves per vector in a clu
 constexpr int kInvChunk = 16;    // steps of a sequential sweep whose inputs load together
 constexpr double kOrtol = 1e-3;  // cluster gap, relative to |T|_1
 constexpr int kTrdPre = 8;       // column values per lane loaded ahead in a tridiagonalisation step
+constexpr int kTrdTail = 128;    // trailing steps done in one workgroup, block in LDS (m (m + 2) + 2m doubles);
+                                 // the tail kernel's update gives each lane two rows, so at most 128
 
 inline unsigned nblk(int64_t n, int b) { return static_cast<unsigned>((n + b - 1) / b); }
 
@@ -239,10 +241,10 @@ __global__ __launch_bounds__(256) void trd_step_kernel(double* __restrict__ A, i
                                                        const int32_t* __restrict__ flag) {
   extern __shared__ double sm[];
   __shared__ double red[4];
-  // the failure flag, the stored column k and this wave's trailing column do
-  // not depend on this launch's vector work: all three loads are issued
-  // before the flag is tested (every address is in range either way), so
-  // their latencies overlap
+  // the failure flag, the stored column k, this wave's trailing column and
+  // the previous step's reflector, p and tau do not depend on this launch's
+  // vector work: all of them are loaded before the flag is tested (every
+  // address is in range either way), so their latencies overlap
   const int32_t failed = *flag;
   double* w = sm;
   double* cv = sm + n;
@@ -263,20 +265,45 @@ __global__ __launch_bounds__(256) void trd_step_kernel(double* __restrict__ A, i
     const int j = k + 1 + lane + 64 * r;
     co[r] = (iown < n && j < n) ? colown[j] : 0.0;
   }
-  if (failed) return;
+  // the previous step's reflector, p and tau are loaded in the same batch
   const double* vprev = vbuf + ((k + 1) & 1) * static_cast<int64_t>(n);
   const double* pprev = pbuf + ((k + 1) & 1) * static_cast<int64_t>(n);
   double* vcur = vbuf + (k & 1) * static_cast<int64_t>(n);
   double* pcur = pbuf + (k & 1) * static_cast<int64_t>(n);
+  double vr[kTrdPre], pr[kTrdPre];
+  double tprev = 0.0;
+  if (k > 0) {
+    tprev = tau[k - 1];
+#pragma unroll
+    for (int r = 0; r < kTrdPre; ++r) {
+      const int j = k + tid + 256 * r;
+      vr[r] = (j < n) ? vprev[j] : 0.0;
+      pr[r] = (j < n) ? pprev[j] : 0.0;
+    }
+  }
+  if (failed) return;
   if (k > 0) {
     double part = 0.0;
-    for (int j = k + tid; j < n; j += 256) {
+#pragma unroll
+    for (int r = 0; r < kTrdPre; ++r) {
+      const int j = k + tid + 256 * r;
+      if (j < n) {
+        vp[j] = vr[r];
+        part += pr[r] * vr[r];
+      }
+    }
+    for (int j = k + tid + 256 * kTrdPre; j < n; j += 256) {
       const double vj = vprev[j];
       vp[j] = vj;
       part += pprev[j] * vj;
     }
-    const double K = 0.5 * tau[k - 1] * block_sum(part, red);
-    for (int j = k + tid; j < n; j += 256) w[j] = pprev[j] - K * vp[j];
+    const double K = 0.5 * tprev * block_sum(part, red);
+#pragma unroll
+    for (int r = 0; r < kTrdPre; ++r) {
+      const int j = k + tid + 256 * r;
+      if (j < n) w[j] = pr[r] - K * vr[r];
+    }
+    for (int j = k + tid + 256 * kTrdPre; j < n; j += 256) w[j] = pprev[j] - K * vp[j];
     __syncthreads();
   }
 #pragma unroll
@@ -340,6 +367,237 @@ __global__ __launch_bounds__(256) void trd_step_kernel(double* __restrict__ A, i
   }
   acc = wave_sum(acc);
   if (lane == 0) pcur[i] = t * acc;
+}
+
+// The same step for trailing sizes n - k <= 64 kTrdPre.  Every wavefront
+// forms the step's reflector itself, in registers: lane l holds entries
+// j = k + l + 64 r of column k, of v_{k-1}, p_{k-1}, w_{k-1} and of its own
+// trailing column, and every sum is a butterfly over the wave (each lane ends
+// with the same bits), so there is no LDS traffic and no workgroup barrier.
+// Every wave computes the same reflector bit for bit; workgroup 0's first
+// wave stores it.
+__global__ __launch_bounds__(256) void trd_step_wave_kernel(double* __restrict__ A, int n, int k,
+                                                            double* __restrict__ Vh, double* __restrict__ tau,
+                                                            double* __restrict__ d, double* __restrict__ e,
+                                                            double* __restrict__ vbuf, double* __restrict__ pbuf,
+                                                            const int32_t* __restrict__ flag) {
+  constexpr int R = kTrdPre;
+  const int32_t failed = *flag;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int iown = k + 1 + blockIdx.x * 4 + wv;
+  const double* colk = A + static_cast<int64_t>(k) * n;
+  double* colown = A + static_cast<int64_t>(min(iown, n - 1)) * n;
+  const double* vprev = vbuf + ((k + 1) & 1) * static_cast<int64_t>(n);
+  const double* pprev = pbuf + ((k + 1) & 1) * static_cast<int64_t>(n);
+  double* vcur = vbuf + (k & 1) * static_cast<int64_t>(n);
+  double* pcur = pbuf + (k & 1) * static_cast<int64_t>(n);
+  // every load is issued before the failure flag is tested (all in range)
+  double c[R], a[R], vp[R], w[R];
+  const double tprev = (k > 0) ? tau[k - 1] : 0.0;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int j = k + lane + 64 * r;
+    const bool in = j < n;
+    c[r] = in ? colk[j] : 0.0;
+    a[r] = (in && iown < n) ? colown[j] : 0.0;
+    vp[r] = (in && k > 0) ? vprev[j] : 0.0;
+    w[r] = (in && k > 0) ? pprev[j] : 0.0;  // p_{k-1} until w is formed
+  }
+  if (failed) return;
+  if (k > 0) {
+    double part = 0.0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) part += w[r] * vp[r];
+    const double K = 0.5 * tprev * wave_sum(part);
+#pragma unroll
+    for (int r = 0; r < R; ++r) w[r] -= K * vp[r];
+    const double wk = __shfl(w[0], 0, 64), vpk = __shfl(vp[0], 0, 64);
+#pragma unroll
+    for (int r = 0; r < R; ++r) c[r] -= vp[r] * wk + w[r] * vpk;
+  }
+  const double dk = __shfl(c[0], 0, 64), alpha = __shfl(c[0], 1, 64);
+  double part = 0.0;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int j = k + lane + 64 * r;
+    if (j >= k + 2 && j < n) part += c[r] * c[r];
+  }
+  const double sig = wave_sum(part);
+  double t = 0.0, beta = alpha, sc = 0.0;
+  if (sig > 0.0) {
+    beta = -copysign(sqrt(alpha * alpha + sig), alpha);
+    t = (beta - alpha) / beta;
+    sc = 1.0 / (alpha - beta);
+  }
+  double v[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int j = k + lane + 64 * r;
+    v[r] = (j == k + 1) ? 1.0 : ((j >= k + 2 && j < n && sig > 0.0) ? c[r] * sc : 0.0);
+  }
+  if (blockIdx.x == 0 && wv == 0) {
+    if (lane == 0) {
+      tau[k] = t;
+      d[k] = dk;
+      e[k] = beta;
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int j = k + lane + 64 * r;
+      if (j >= k + 1 && j < n) {
+        Vh[j + static_cast<int64_t>(k) * n] = v[r];
+        vcur[j] = v[r];
+      }
+    }
+  }
+  if (iown >= n) return;
+  // w_{k-1} and v_{k-1} at row iown, from the lane and slot that hold them
+  const int idx = iown - k, rsel = idx >> 6;
+  double wsel = 0.0, vsel = 0.0;
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+    if (r == rsel) {
+      wsel = w[r];
+      vsel = vp[r];
+    }
+  const double wi = __shfl(wsel, idx & 63, 64), vpi = __shfl(vsel, idx & 63, 64);
+  double acc = 0.0;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int j = k + lane + 64 * r;
+    if (j >= k + 1 && j < n) {
+      const double x = (k > 0) ? a[r] - (vp[r] * wi + w[r] * vpi) : a[r];
+      colown[j] = x;
+      acc += x * v[r];
+    }
+  }
+  acc = wave_sum(acc);
+  if (lane == 0) pcur[iown] = t * acc;
+}
+
+// The last m = n - k0 <= kTrdTail steps of the tridiagonalisation in one
+// workgroup: the trailing m x m block (with step k0-1's deferred update
+// applied on load) lives in LDS, column stride m + 2, and each step forms its
+// reflector, p = tau A v, w = p - (tau/2)(p^T v) v and the rank-2 update
+// there, with workgroup barriers in place of kernel boundaries.  Writes the
+// same tau, d, e and Householder columns as the per-step kernels, and the
+// final block back to A (its last diagonal entry is T's).
+constexpr int kTailThreads = 1024;  // 16 waves: short dependent chains per lane, latency hidden across waves
+__global__ __launch_bounds__(kTailThreads) void trd_tail_kernel(double* __restrict__ A, int n, int k0,
+                                                                double* __restrict__ Vh, double* __restrict__ tau,
+                                                                double* __restrict__ d, double* __restrict__ e,
+                                                                const double* __restrict__ vbuf,
+                                                                const double* __restrict__ pbuf,
+                                                                const int32_t* __restrict__ flag) {
+  constexpr int NT = kTailThreads, NW = NT / 64;
+  extern __shared__ double sm[];
+  __shared__ double red[2 * NW];  // two halves, used in turn: one barrier per sum
+  if (*flag) return;
+  const int m = n - k0, ld = m + 2, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  double* As = sm;  // m columns of ld
+  double* vs = sm + static_cast<int64_t>(m) * ld;
+  double* ps = vs + m;  // p, then w
+  int phase = 0;
+  // fixed-order workgroup sum with one barrier; red's halves alternate
+  auto bsum = [&](double v) {
+    v = wave_sum(v);
+    double* rr = red + NW * (phase & 1);
+    ++phase;
+    if (lane == 0) rr[wv] = v;
+    __syncthreads();
+    double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+    for (int q = 0; q < NW; q += 2) {
+      s0 += rr[q];
+      s1 += rr[q + 1];
+    }
+    return s0 + s1;
+  };
+  if (k0 > 0) {
+    const double* vprev = vbuf + ((k0 - 1) & 1) * static_cast<int64_t>(n);
+    const double* pprev = pbuf + ((k0 - 1) & 1) * static_cast<int64_t>(n);
+    double part = 0.0;
+    for (int r = tid; r < m; r += NT) {
+      const double vv = vprev[k0 + r], pp = pprev[k0 + r];
+      vs[r] = vv;
+      ps[r] = pp;
+      part += pp * vv;
+    }
+    const double K = 0.5 * tau[k0 - 1] * bsum(part);
+    for (int r = tid; r < m; r += NT) ps[r] -= K * vs[r];
+    __syncthreads();
+  }
+  for (int c = wv; c < m; c += NW) {
+    const double* src = A + k0 + static_cast<int64_t>(k0 + c) * n;
+    const double pc = (k0 > 0) ? ps[c] : 0.0, vc = (k0 > 0) ? vs[c] : 0.0;
+    for (int r = lane; r < m; r += 64) {
+      double x = src[r];
+      if (k0 > 0) x -= vs[r] * pc + ps[r] * vc;
+      As[r + c * ld] = x;
+    }
+  }
+  __syncthreads();
+  for (int k = 0; k + 1 < m; ++k) {
+    const double* colk = As + k * ld;
+    const double dk = colk[k], alpha = colk[k + 1];
+    const int rk = k + 2 + tid;
+    const double ck = (rk < m) ? colk[rk] : 0.0;
+    const double sig = bsum(ck * ck);
+    double t = 0.0, beta = alpha, sc = 0.0;
+    if (sig > 0.0) {
+      beta = -copysign(sqrt(alpha * alpha + sig), alpha);
+      t = (beta - alpha) / beta;
+      sc = 1.0 / (alpha - beta);
+    }
+    {
+      const int r = k + 1 + tid;
+      if (r < m) {
+        const double v = (r == k + 1) ? 1.0 : (sig > 0.0 ? colk[r] * sc : 0.0);
+        vs[r] = v;
+        Vh[(k0 + r) + static_cast<int64_t>(k0 + k) * n] = v;
+      }
+    }
+    if (tid == 0) {
+      tau[k0 + k] = t;
+      d[k0 + k] = dk;
+      e[k0 + k] = beta;
+    }
+    __syncthreads();
+    // p_i = t sum_{j > k} A_ji v_j (eight lanes per column i > k) and K = (t/2) p^T v
+    double kpart = 0.0;
+    {
+      const int i = k + 1 + (tid >> 3), h = tid & 7;
+      double acc = 0.0;
+      if (i < m) {
+        const double* col = As + i * ld;
+        for (int r = k + 1 + h; r < m; r += 8) acc += col[r] * vs[r];
+      }
+      acc += __shfl_xor(acc, 1, 64);
+      acc += __shfl_xor(acc, 2, 64);
+      acc += __shfl_xor(acc, 4, 64);
+      if (i < m && h == 0) {
+        const double pi = t * acc;
+        ps[i] = pi;
+        kpart = pi * vs[i];
+      }
+    }
+    const double K = 0.5 * t * bsum(kpart);
+    // A -= v w^T + w v^T with w = p - K v; lane rows r0, r0 + 64, wave columns
+    const int r0 = k + 1 + lane, r1 = r0 + 64;
+    const double v0 = (r0 < m) ? vs[r0] : 0.0, w0 = (r0 < m) ? ps[r0] - K * v0 : 0.0;
+    const double v1 = (r1 < m) ? vs[r1] : 0.0, w1 = (r1 < m) ? ps[r1] - K * v1 : 0.0;
+    for (int c = k + 1 + wv; c < m; c += NW) {
+      const double vc = vs[c], wc = ps[c] - K * vc;
+      double* col = As + c * ld;
+      if (r0 < m) col[r0] -= v0 * wc + w0 * vc;
+      if (r1 < m) col[r1] -= v1 * wc + w1 * vc;
+    }
+    __syncthreads();
+  }
+  for (int c = wv; c < m; c += NW) {
+    double* dst = A + k0 + static_cast<int64_t>(k0 + c) * n;
+    for (int r = lane; r < m; r += 64) dst[r] = As[r + c * ld];
+  }
 }
 
 // T's last diagonal entry, |T|_1, negligible off-diagonals set to zero
@@ -556,22 +814,24 @@ __global__ __launch_bounds__(256) void tri_inviter_kernel(const double* __restri
           if (t < nstep) {
             const int i = i0 + t;
             const double a = ea[t], b = db[t] - xs, cn = ea[t + 1];
+            const double ra = 1.0 / a;  // depends on the inputs only: off the recurrence's chain
             if (fabs(a) > fabs(bb)) {
               piv[i] = 1;
-              r0[i] = 1.0 / a;
+              r0[i] = ra;
               u1[i] = b;
               u2[i] = cn;
-              const double mult = bb / a;
+              const double mult = bb * ra;
               ll[i] = mult;
               bb = cc - mult * b;
               cc = -mult * cn;
             } else {
               piv[i] = 0;
               const double p = (fabs(bb) < pmin) ? copysign(pmin, bb) : bb;
-              r0[i] = 1.0 / p;
+              const double rp = 1.0 / p;
+              r0[i] = rp;
               u1[i] = cc;
               u2[i] = 0.0;
-              const double mult = a / p;
+              const double mult = a * rp;
               ll[i] = mult;
               bb = b - mult * cc;
               cc = cn;
@@ -831,9 +1091,23 @@ int dense_geneig(DenseWork& w, const double* Hs, const double* M, double* Y, hip
   // --- tridiagonalisation ---
   const size_t trd_smem = 3 * static_cast<size_t>(n) * sizeof(double);
   set_smem(reinterpret_cast<const void*>(trd_step_kernel), trd_smem);
-  for (int k = 0; k + 1 < n; ++k)
-    hipLaunchKernelGGL(trd_step_kernel, dim3(std::max(1u, nblk(n - k - 1, 4))), dim3(256), trd_smem, st, w.C0, n,
-                       k, w.Vh, tau, d, e, vbuf, pbuf, w.flag);
+  const int k0 = std::max(0, n - kTrdTail);
+  for (int k = 0; k < k0; ++k) {
+    const dim3 grid(std::max(1u, nblk(n - k - 1, 4)));
+    if (n - k <= 64 * kTrdPre)
+      hipLaunchKernelGGL(trd_step_wave_kernel, grid, dim3(256), 0, st, w.C0, n, k, w.Vh, tau, d, e, vbuf, pbuf,
+                         w.flag);
+    else
+      hipLaunchKernelGGL(trd_step_kernel, grid, dim3(256), trd_smem, st, w.C0, n, k, w.Vh, tau, d, e, vbuf, pbuf,
+                         w.flag);
+  }
+  if (n > 1) {
+    const int m = n - k0;
+    const size_t tail_smem = (static_cast<size_t>(m) * (m + 2) + 2 * static_cast<size_t>(m)) * sizeof(double);
+    set_smem(reinterpret_cast<const void*>(trd_tail_kernel), tail_smem);
+    hipLaunchKernelGGL(trd_tail_kernel, dim3(1), dim3(kTailThreads), tail_smem, st, w.C0, n, k0, w.Vh, tau, d, e, vbuf, pbuf,
+                       w.flag);
+  }
   XLS_LAUNCH_CHECK("trd_step_kernel");
   // --- tridiagonal eigenproblem ---
   hipLaunchKernelGGL(tri_prepare_kernel, dim3(1), dim3(256), 0, st, w.C0, n, d, e, ez, e2, bs, be, w.scal,

@@ -303,7 +303,9 @@ def test_residual_fp64(system):
 # a6: dense FP64 generalized eigensolver
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("n", [1, 2, 7, 20, 37, 100, 161])
+# 128, 129: the one-workgroup tail alone, then one step before it; 480: the
+# register-only steps and the tail; 700: all three step kernels
+@pytest.mark.parametrize("n", [1, 2, 7, 20, 37, 100, 128, 129, 161, 480, 700])
 def test_dense_geneig(n):
     case(f"dense n={n}")
     rng = np.random.default_rng(n)

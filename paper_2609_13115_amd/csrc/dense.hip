@@ -45,13 +45,39 @@ constexpr int kTrdTail = 128;    // trailing steps done in one workgroup, block 
 
 inline unsigned nblk(int64_t n, int b) { return static_cast<unsigned>((n + b - 1) / b); }
 
-__device__ __forceinline__ double wave_sum(double v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+// Cross-lane moves for wave reductions (full wave active at every call).
+// Within each row of 16 lanes: rotate by 8, 4, 2, 1 (DPP row_ror), so every
+// lane of a row ends with the row's result, in the same operand order; the
+// four rows are then read out and combined in a fixed order.  Every lane
+// returns the same bits.
+template <int CTRL>
+__device__ __forceinline__ double row_ror(double x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double lane_value(double x, int l) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x), l),
+                          __builtin_amdgcn_readlane(__double2loint(x), l));
+}
+// sum over each row of 16 lanes, in every lane of the row
+__device__ __forceinline__ double row_sum(double v) {
+  v += row_ror<0x128>(v);
+  v += row_ror<0x124>(v);
+  v += row_ror<0x122>(v);
+  v += row_ror<0x121>(v);
   return v;
 }
+__device__ __forceinline__ double wave_sum(double v) {
+  v = row_sum(v);
+  return (lane_value(v, 0) + lane_value(v, 16)) + (lane_value(v, 32) + lane_value(v, 48));
+}
 __device__ __forceinline__ double wave_max(double v) {
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  return v;
+  v = fmax(v, row_ror<0x128>(v));
+  v = fmax(v, row_ror<0x124>(v));
+  v = fmax(v, row_ror<0x122>(v));
+  v = fmax(v, row_ror<0x121>(v));
+  return fmax(fmax(lane_value(v, 0), lane_value(v, 16)), fmax(lane_value(v, 32), lane_value(v, 48)));
 }
 // Sum over a 256-thread workgroup in a fixed order; every thread gets the
 // result and red[] is free again on return.
@@ -411,11 +437,11 @@ __global__ __launch_bounds__(256) void trd_step_wave_kernel(double* __restrict__
     const double K = 0.5 * tprev * wave_sum(part);
 #pragma unroll
     for (int r = 0; r < R; ++r) w[r] -= K * vp[r];
-    const double wk = __shfl(w[0], 0, 64), vpk = __shfl(vp[0], 0, 64);
+    const double wk = lane_value(w[0], 0), vpk = lane_value(vp[0], 0);
 #pragma unroll
     for (int r = 0; r < R; ++r) c[r] -= vp[r] * wk + w[r] * vpk;
   }
-  const double dk = __shfl(c[0], 0, 64), alpha = __shfl(c[0], 1, 64);
+  const double dk = lane_value(c[0], 0), alpha = lane_value(c[0], 1);
   double part = 0.0;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
@@ -460,7 +486,7 @@ __global__ __launch_bounds__(256) void trd_step_wave_kernel(double* __restrict__
       wsel = w[r];
       vsel = vp[r];
     }
-  const double wi = __shfl(wsel, idx & 63, 64), vpi = __shfl(vsel, idx & 63, 64);
+  const double wi = lane_value(wsel, idx & 63), vpi = lane_value(vsel, idx & 63);
   double acc = 0.0;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
@@ -563,22 +589,21 @@ __global__ __launch_bounds__(kTailThreads) void trd_tail_kernel(double* __restri
       e[k0 + k] = beta;
     }
     __syncthreads();
-    // p_i = t sum_{j > k} A_ji v_j (eight lanes per column i > k) and K = (t/2) p^T v
+    // p_i = t sum_{j > k} A_ji v_j (a row of 16 lanes per column i > k) and
+    // K = (t/2) p^T v
     double kpart = 0.0;
-    {
-      const int i = k + 1 + (tid >> 3), h = tid & 7;
+    for (int i0 = k + 1; i0 < m; i0 += NT / 16) {
+      const int i = i0 + (tid >> 4), h = tid & 15;
       double acc = 0.0;
       if (i < m) {
         const double* col = As + i * ld;
-        for (int r = k + 1 + h; r < m; r += 8) acc += col[r] * vs[r];
+        for (int r = k + 1 + h; r < m; r += 16) acc += col[r] * vs[r];
       }
-      acc += __shfl_xor(acc, 1, 64);
-      acc += __shfl_xor(acc, 2, 64);
-      acc += __shfl_xor(acc, 4, 64);
+      acc = row_sum(acc);
       if (i < m && h == 0) {
         const double pi = t * acc;
         ps[i] = pi;
-        kpart = pi * vs[i];
+        kpart += pi * vs[i];
       }
     }
     const double K = 0.5 * t * bsum(kpart);

@@ -72,3 +72,58 @@ def test_energies_and_count():
     # DOS integrates to 2 sum c
     hist = density.dos_histogram(lam, c, np.linspace(-2, 2, 9))
     assert abs(hist.sum() - 2 * c.sum()) < 1e-14
+
+
+def test_fermi_level_symmetric_spectrum_is_the_centre():
+    """A spectrum symmetric about mu0 with mirrored weights holds exactly half
+    its states' weight at mu0 (g(mu0 - d) + g(mu0 + d) = 1), so the Fermi
+    level at that electron count is mu0."""
+    mu0, sigma = -0.137, 0.02
+    d = np.array([0.003, 0.05, 0.2, 0.71, 1.3])
+    cw = np.array([0.9, 0.4, 1.0, 0.25, 0.6])
+    lam = np.concatenate([mu0 - d, mu0 + d])
+    c = np.concatenate([cw, cw])
+    mu = density.fermi_level(lam, c, sigma, float(np.sum(c)))
+    assert abs(mu - mu0) <= 1e-13
+
+
+def test_fermi_level_small_sigma_falls_in_the_gap():
+    """sigma -> 0: with unit weights and 2 k electrons the level sits between
+    the k-th and (k+1)-th eigenvalue and the count is met."""
+    lam = np.array([-1.0, -0.4, 0.25, 0.3, 1.9, 2.0])
+    c = np.ones_like(lam)
+    for k in (1, 3, 5):
+        mu = density.fermi_level(lam, c, 1e-3, 2.0 * k)
+        assert lam[k - 1] < mu < lam[k]
+        assert abs(density.electron_count(lam, c, mu, 1e-3) - 2.0 * k) <= 1e-9
+    with pytest.raises(ValueError):
+        density.fermi_level(lam, c, 1e-3, 2.0 * len(lam) + 1.0)
+
+
+def test_assemble_density_places_each_core_by_its_map():
+    """Two subsystems whose cores tile a global box: the assembled density
+    equals every core value at its global point (loop over points), and its
+    integral is the sum of the subsystems' charges."""
+    gn = (6, 4, 3)
+    n_global = gn[0] * gn[1] * gn[2]
+    rng = np.random.default_rng(7)
+    parts, charge = [], 0.0
+    h = 0.5
+    for off, lo, hi in (((-2, 0, 0), (2, 0, 0), (5, 4, 3)), ((1, 0, 0), (2, 0, 0), (5, 4, 3))):
+        n = (7, 4, 3)
+        mask = grid.core_mask(n, lo, hi)
+        gidx = grid.global_index(n, off, gn)
+        r = rng.random(n[0] * n[1] * n[2])
+        parts.append((r, mask, gidx))
+        charge += h ** 3 * float(np.sum(r[mask == 1]))
+    rho = density.assemble_density(parts, n_global)
+    ref = np.zeros(n_global)
+    seen = np.zeros(n_global, dtype=int)
+    for r, mask, gidx in parts:
+        for g in range(len(r)):
+            if mask[g]:
+                ref[gidx[g]] += r[g]
+                seen[gidx[g]] += 1
+    assert np.all(seen == 1)  # the two cores partition the global box
+    assert np.array_equal(rho, ref)
+    assert abs(h ** 3 * rho.sum() - charge) <= 1e-12

@@ -317,11 +317,12 @@ def run_batch(count: int, forms):
             ritz, resid, iters, status = b.xls_batch_chefsi(params)
             torch.cuda.synchronize()
             t = time.perf_counter() - t0
+            occ = occupation_timing(b, subs, prec)
         gates = [max(1, int(np.floor(sd.ns / 1.1 + 1e-9))) for sd in subs]
         conv = [int(st == xls.XLS_OK and float(np.max(r[:g])) <= 1e-4) for st, r, g in zip(status, resid, gates)]
         ritz_of[form] = (ritz, gates, conv)
         out[form] = {"seconds": t, "subdomains_per_s": count / t, "iterations": [int(i) for i in iters],
-                     "converged": int(sum(conv))}
+                     "converged": int(sum(conv)), "occupation": occ}
         print(f"[bench] batch {form}: {json.dumps(out[form])}", file=sys.stderr, flush=True)
     if "mixed" in ritz_of and "fp64" in ritz_of:
         (rm, g, cm), (rf, _, cf) = ritz_of["mixed"], ritz_of["fp64"]
@@ -332,6 +333,32 @@ def run_batch(count: int, forms):
         out["max_ritz_diff_ha_converged"] = max(both) if both else None
         out["speedup_mixed_vs_fp64"] = out["fp64"]["seconds"] / out["mixed"]["seconds"]
     return out
+
+
+def occupation_timing(b, subs, prec, sigma: float = 0.01, reps: int = 3):
+    """Fermi level of the whole batch at half filling (core-weight pass over
+    every block, then the device solve) and a 200-bin density of states:
+    best wall time of reps calls each, with the core-weight pass priced at
+    its algorithmic bytes (one read of every block)."""
+    _, cs = b.xls_batch_density(0.0, sigma)
+    ne = float(sum(np.sum(c) for c in cs))  # half of 2 sum c
+    best = 1e9
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        mu, n_at, e_band, e_ent, evals = b.xls_batch_fermi(sigma, ne)
+        best = min(best, time.perf_counter() - t0)
+    lam_lo, lam_hi = mu - 2.0, mu + 2.0
+    edges = np.linspace(lam_lo, lam_hi, 201)
+    bd = 1e9
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        b.xls_batch_assemble(0, edges)
+        bd = min(bd, time.perf_counter() - t0)
+    w = 4 if prec == 1 else 8
+    nbytes = float(sum(sd.nd * sd.ns * w for sd in subs))
+    return {"fermi_ms": best * 1e3, "dos_ms": bd * 1e3, "mu": mu, "n_electrons": ne, "count_at_mu": n_at,
+            "evaluations": int(evals), "e_band": e_band, "e_entropy": e_ent,
+            "core_weight_bytes": nbytes, "core_weight_gbs_lower_bound": nbytes / best / 1e9}
 
 
 def cpu_baseline(sd, degree: int, ncols: int):

@@ -305,6 +305,27 @@ int xls_subdomain_features(xls_subdomain_t s, double* f);
  *   1 replays captured iterations, 0 launches eagerly (same results).
  * xls_batch_density: xls_subdomain_density of every subdomain, rho and c
  *   concatenated (sum N_d_i and sum ns_i values).
+ * xls_batch_fermi: the Fermi level of the whole batch (Sec. V-A.5): with
+ *   every subdomain's Ritz values lambda_n and interior weights c_n
+ *   (Sec. V-A.4, computed here from the current blocks), the mu at which
+ *   N_e(mu) = 2 sum_i sum_n g(lambda_n; mu, sigma) c_n equals n_electrons,
+ *   by Newton steps kept inside a shrinking bracket (first bracket: the
+ *   extreme Ritz values -/+ 40 sigma), on the device.  out (cap >= 1
+ *   values): mu, N_e(mu), E_band = 2 sum g c lambda, E_entropy =
+ *   -2 sigma sum c [g ln g + (1 - g) ln(1 - g)], count evaluations.  Needs a
+ *   completed xls_batch_chefsi (else XLS_ERR_STATE); INVALID_ARG for sigma or
+ *   n_electrons <= 0 or an n_electrons outside (N_e(lo), N_e(hi)).  Returns
+ *   the number of values written.
+ * xls_batch_assemble: at the mu and sigma of the last xls_batch_fermi, the
+ *   global density (Sec. V-A.4) and the density of states.  rho_global (host,
+ *   n_global doubles, or NULL to skip): the sum over subdomains of rho~ on
+ *   their core points, placed by their local->global maps (subdomains are
+ *   added in order, so the result is deterministic; cores are meant to
+ *   partition the global grid).  INVALID_ARG when a core point maps outside
+ *   [0, n_global) or two core points of one subdomain map to one global
+ *   point.  dos (host, nbins doubles; edges holds nbins + 1 increasing
+ *   values): 2 sum c_n over the states with lambda_n in [edges[b],
+ *   edges[b+1]), the last bin closed on the right.  nbins = 0 skips it.
  * xls_batch_subdomain: borrowed handle of subdomain i (for the per-handle
  *   hooks); owned by the batch, never destroyed by the caller.
  * xls_batch_tune: times the fused filter kernel of one subdomain per shape
@@ -322,6 +343,9 @@ int xls_batch_create(int32_t n, const xls_subdomain_desc_t* descs, xls_batch_t* 
 int xls_batch_chefsi(xls_batch_t b, const xls_chefsi_params_t* per_sub, double* ritz_concat,
                      double* resid_concat, int32_t* iters, int32_t* status, int32_t use_graph);
 int xls_batch_density(xls_batch_t b, double mu, double sigma, double* rho_concat, double* c_concat);
+int xls_batch_fermi(xls_batch_t b, double sigma, double n_electrons, double* out, int32_t cap);
+int xls_batch_assemble(xls_batch_t b, int64_t n_global, double* rho_global, int32_t nbins, const double* edges,
+                       double* dos);
 int xls_batch_subdomain(xls_batch_t b, int32_t i, xls_subdomain_t* out);
 int xls_batch_tune(xls_batch_t b, const char* cache_path, int32_t* tuned, double* best_ms);
 int xls_batch_stats(xls_batch_t b, double* out, int32_t cap);

@@ -91,6 +91,19 @@ struct xls_batch_s {
   // statistics
   int64_t iterations = 0, captures = 0, replays = 0;
   double iter_ms = 0.0, last_iter_ms = 0.0;
+  // occupation of the whole batch (xls_batch_fermi / xls_batch_assemble)
+  double* lam_all = nullptr;  // [sum ns] Ritz values, subdomain order
+  double* c_all = nullptr;    // [sum ns] interior weights
+  double* fout = nullptr;     // [8] solver outputs
+  int64_t nstates = 0;
+  bool have_fermi = false;
+  double mu = 0.0, sigma = 0.0;
+  std::vector<int64_t*> gidx;  // per subdomain: device copy of the local->global map
+  std::vector<int8_t> gidx_ok;  // per subdomain: 1 = core points map to distinct global points, -1 = not
+  double* rho_global = nullptr;
+  int64_t rho_global_n = 0;
+  double* dos_buf = nullptr;  // [2 * nbins + 1]: edges, then bins
+  int dos_cap = 0;
 
   ~xls_batch_s() {
     if (main) (void)hipStreamSynchronize(main);
@@ -99,6 +112,12 @@ struct xls_batch_s {
     for (auto& g : graphs) g.release();
     for (auto* c : coef) dfree(c);
     dfree(flags);
+    dfree(lam_all);
+    dfree(c_all);
+    dfree(fout);
+    for (auto* g : gidx) dfree(g);
+    dfree(rho_global);
+    dfree(dos_buf);
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     for (auto e : ev_join) (void)hipEventDestroy(e);
     if (t0) (void)hipEventDestroy(t0);
@@ -242,6 +261,7 @@ void run_iteration(xls_batch_s* b, const std::vector<int>& act, bool use_graph) 
 
 template <typename TS>
 void batch_chefsi(xls_batch_s* b, const xls_chefsi_params_t* P, int use_graph) {
+  b->have_fermi = false;  // new blocks: a stored Fermi level no longer applies
   const int n = b->n;
   for (int i = 0; i < n; ++i) {
     const xls_chefsi_params_t& p = P[i];
@@ -559,6 +579,119 @@ int xls_batch_density(xls_batch_t b, double mu, double sigma, double* rho_concat
       off_r += s->nd;
       off_c += s->ns;
     }
+    return XLS_OK;
+  });
+}
+
+int xls_batch_fermi(xls_batch_t b, double sigma, double n_electrons, double* out, int32_t cap) {
+  return guarded([&]() -> int {
+    if (!b || !out || cap < 1) fail(XLS_ERR_INVALID_ARG, "bad argument");
+    if (!(sigma > 0) || !std::isfinite(sigma) || !(n_electrons > 0) || !std::isfinite(n_electrons))
+      fail(XLS_ERR_INVALID_ARG, "sigma and n_electrons must be positive and finite");
+    int64_t total = 0;
+    for (auto* s : b->subs) {
+      if (!s->have_ritz) fail(XLS_ERR_STATE, "xls_batch_fermi needs a completed xls_batch_chefsi");
+      total += s->ns;
+    }
+    XLS_HIP(hipStreamSynchronize(b->main));
+    for (auto* s : b->subs) XLS_HIP(hipStreamSynchronize(s->st));
+    if (total != b->nstates) {
+      dfree(b->lam_all);
+      dfree(b->c_all);
+      b->lam_all = nullptr;
+      b->c_all = nullptr;
+      b->lam_all = dalloc<double>(total);
+      b->c_all = dalloc<double>(total);
+      b->nstates = total;
+    }
+    if (!b->fout) b->fout = dalloc<double>(8);
+    b->have_fermi = false;
+    int64_t off = 0;
+    for (auto* s : b->subs) {
+      XLS_HIP(hipMemcpyAsync(b->lam_all + off, s->ritz.data(), s->ns * 8, hipMemcpyHostToDevice, b->main));
+      launch_core_weights(s->mask, s->blk[s->cur], s->prec == XLS_PREC_FP32, s->nd, s->ld, s->ns, s->cpart, 64,
+                          b->c_all + off, b->main);
+      off += s->ns;
+    }
+    launch_fermi_level(b->lam_all, b->c_all, total, sigma, n_electrons, 200, b->fout, b->main);
+    double h[8] = {0};
+    XLS_HIP(hipMemcpyAsync(h, b->fout, 6 * 8, hipMemcpyDeviceToHost, b->main));
+    XLS_HIP(hipStreamSynchronize(b->main));
+    if (h[5] != 0.0) fail(XLS_ERR_INVALID_ARG, "n_electrons is outside the range the batch's states can hold");
+    b->mu = h[0];
+    b->sigma = sigma;
+    b->have_fermi = true;
+    const int k = std::min<int>(cap, 5);
+    for (int i = 0; i < k; ++i) out[i] = h[i];
+    return k;
+  });
+}
+
+int xls_batch_assemble(xls_batch_t b, int64_t n_global, double* rho_global, int32_t nbins, const double* edges,
+                       double* dos) {
+  return guarded([&]() -> int {
+    if (!b) fail(XLS_ERR_INVALID_ARG, "NULL batch");
+    if (!b->have_fermi) fail(XLS_ERR_STATE, "xls_batch_assemble needs a completed xls_batch_fermi");
+    if (nbins < 0 || (nbins > 0 && (!edges || !dos))) fail(XLS_ERR_INVALID_ARG, "bad DOS arguments");
+    for (int i = 0; i < nbins; ++i)
+      if (!(edges[i] < edges[i + 1])) fail(XLS_ERR_INVALID_ARG, "DOS edges must increase");
+    if (rho_global) {
+      if (n_global < 1) fail(XLS_ERR_INVALID_ARG, "n_global must be >= 1");
+      if (b->gidx.size() != b->subs.size()) {
+        b->gidx.assign(b->subs.size(), nullptr);
+        b->gidx_ok.assign(b->subs.size(), 0);
+      }
+      // every core point inside the global grid, and distinct within a subdomain
+      for (size_t i = 0; i < b->subs.size(); ++i) {
+        auto* s = b->subs[i];
+        std::vector<int64_t> core;
+        core.reserve(static_cast<size_t>(s->nd));
+        for (int64_t g = 0; g < s->nd; ++g)
+          if (s->tab.core_mask[g]) core.push_back(s->tab.global_index[g]);
+        for (int64_t v : core)
+          if (v < 0 || v >= n_global) fail(XLS_ERR_INVALID_ARG, "a core point maps outside the global grid");
+        if (b->gidx_ok[i] == 0) {
+          std::sort(core.begin(), core.end());
+          b->gidx_ok[i] = std::adjacent_find(core.begin(), core.end()) == core.end() ? 1 : -1;
+        }
+        if (b->gidx_ok[i] < 0) fail(XLS_ERR_INVALID_ARG, "two core points of one subdomain share a global point");
+      }
+      XLS_HIP(hipStreamSynchronize(b->main));
+      for (auto* s : b->subs) XLS_HIP(hipStreamSynchronize(s->st));
+      if (n_global != b->rho_global_n) {
+        dfree(b->rho_global);
+        b->rho_global = nullptr;
+        b->rho_global = dalloc<double>(n_global);
+        b->rho_global_n = n_global;
+      }
+      XLS_HIP(hipMemsetAsync(b->rho_global, 0, n_global * 8, b->main));
+      for (size_t i = 0; i < b->subs.size(); ++i) {
+        auto* s = b->subs[i];
+        if (!b->gidx[i]) {
+          b->gidx[i] = dalloc<int64_t>(s->nd);
+          XLS_HIP(hipMemcpyAsync(b->gidx[i], s->tab.global_index.data(), s->nd * 8, hipMemcpyHostToDevice,
+                                 b->main));
+        }
+        if (!s->rho_dev) s->rho_dev = dalloc<double>(s->nd);
+        XLS_HIP(hipMemcpyAsync(s->lam_dev, s->ritz.data(), s->ns * 8, hipMemcpyHostToDevice, b->main));
+        launch_density(s->lam_dev, b->mu, b->sigma, s->mask, s->h, s->blk[s->cur], s->prec == XLS_PREC_FP32, s->nd,
+                       s->ld, s->ns, s->rho_dev, s->cpart, 64, s->resid_dev, s->gocc, b->main);
+        launch_scatter_core(s->rho_dev, s->mask, b->gidx[i], s->nd, b->rho_global, b->main);
+      }
+      XLS_HIP(hipMemcpyAsync(rho_global, b->rho_global, n_global * 8, hipMemcpyDeviceToHost, b->main));
+    }
+    if (nbins > 0) {
+      if (nbins > b->dos_cap) {
+        dfree(b->dos_buf);
+        b->dos_buf = nullptr;
+        b->dos_buf = dalloc<double>(2 * static_cast<size_t>(nbins) + 1);
+        b->dos_cap = nbins;
+      }
+      XLS_HIP(hipMemcpyAsync(b->dos_buf, edges, (nbins + 1) * 8, hipMemcpyHostToDevice, b->main));
+      launch_dos(b->lam_all, b->c_all, b->nstates, b->dos_buf, nbins, b->dos_buf + nbins + 1, b->main);
+      XLS_HIP(hipMemcpyAsync(dos, b->dos_buf + nbins + 1, nbins * 8, hipMemcpyDeviceToHost, b->main));
+    }
+    XLS_HIP(hipStreamSynchronize(b->main));
     return XLS_OK;
   });
 }

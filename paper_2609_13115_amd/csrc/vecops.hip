@@ -41,6 +41,163 @@ __global__ void fermi_kernel(const double* __restrict__ lam, int n, double mu, d
   }
 }
 
+__device__ __forceinline__ double occupation(double lam, double mu, double sigma) {
+  const double t = (lam - mu) / sigma;
+  if (t > 0) {
+    const double e = exp(-t);
+    return e / (1.0 + e);
+  }
+  return 1.0 / (1.0 + exp(t));
+}
+
+// Fermi level of n states (lam_i, c_i): the root of
+// N_e(mu) = 2 sum_i g(lam_i; mu, sigma) c_i - target, continuous and
+// increasing in mu.  Newton steps with dN_e/dmu = (2/sigma) sum c g (1 - g),
+// kept inside a bracket that every evaluation shrinks (a step that would leave
+// it is replaced by the midpoint); the bracket starts at the extreme
+// eigenvalues -/+ 40 sigma.  Stops when the step or the bracket falls to
+// rounding level.  One workgroup; every sum is per thread over a fixed
+// stride, then over the workgroup in a fixed order.
+// out: mu, N_e(mu), E_band, E_entropy, evaluations, status (0 ok, 1 count
+// out of reach).
+constexpr int kFermiThreads = 1024;
+__global__ __launch_bounds__(kFermiThreads) void fermi_level_kernel(const double* __restrict__ lam,
+                                                                    const double* __restrict__ c, int64_t n,
+                                                                    double sigma, double target, int max_eval,
+                                                                    double* __restrict__ out) {
+  constexpr int NW = kFermiThreads / 64;
+  __shared__ double red[2][4][NW];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  int phase = 0;
+  // fixed-order workgroup sums of K values (one barrier; buffers alternate)
+  auto bsum = [&](double (&v)[4], int K) {
+    double(*rr)[NW] = red[phase & 1];
+    ++phase;
+    for (int q = 0; q < K; ++q) {
+      double x = v[q];
+      for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+      if (lane == 0) rr[q][wv] = x;
+    }
+    __syncthreads();
+    for (int q = 0; q < K; ++q) {
+      double a = 0.0, b = 0.0;
+      for (int w = 0; w < NW; w += 2) {
+        a += rr[q][w];
+        b += rr[q][w + 1];
+      }
+      v[q] = a + b;
+    }
+  };
+  double v[4] = {HUGE_VAL, HUGE_VAL, 0.0, 0.0};
+  for (int64_t i = tid; i < n; i += kFermiThreads) {
+    v[0] = fmin(v[0], lam[i]);
+    v[1] = fmin(v[1], -lam[i]);
+  }
+  {  // min and -max over the workgroup (exact in any order)
+    double(*rr)[NW] = red[phase & 1];
+    ++phase;
+    for (int q = 0; q < 2; ++q) {
+      double x = v[q];
+      for (int o = 32; o > 0; o >>= 1) x = fmin(x, __shfl_xor(x, o, 64));
+      if (lane == 0) rr[q][wv] = x;
+    }
+    __syncthreads();
+    for (int q = 0; q < 2; ++q) {
+      double a = HUGE_VAL;
+      for (int w = 0; w < NW; ++w) a = fmin(a, rr[q][w]);
+      v[q] = a;
+    }
+  }
+  double lo = v[0] - 40.0 * sigma, hi = -v[1] + 40.0 * sigma;
+  // N_e - target and its derivative at x
+  auto count = [&](double x, double& F, double& dF) {
+    double a[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t i = tid; i < n; i += kFermiThreads) {
+      const double g = occupation(lam[i], x, sigma);
+      a[0] += g * c[i];
+      a[1] += c[i] * g * (1.0 - g);
+    }
+    bsum(a, 2);
+    F = 2.0 * a[0] - target;
+    dF = 2.0 * a[1] / sigma;
+  };
+  double F, dF;
+  int evals = 0, status = 0;
+  count(lo, F, dF);
+  const bool lo_ok = F < 0.0;
+  count(hi, F, dF);
+  const bool hi_ok = F > 0.0;
+  evals = 2;
+  double mu = 0.5 * (lo + hi);
+  if (!(lo_ok && hi_ok)) {
+    status = 1;
+  } else {
+    while (evals < max_eval) {
+      count(mu, F, dF);
+      ++evals;
+      if (F == 0.0) break;
+      if (F < 0.0)
+        lo = mu;
+      else
+        hi = mu;
+      double nxt = (dF > 0.0) ? mu - F / dF : 0.5 * (lo + hi);
+      if (!(nxt > lo && nxt < hi)) nxt = 0.5 * (lo + hi);
+      const double tolx = 4.0 * 2.220446049250313e-16 * fmax(fabs(mu), sigma);
+      if (fabs(nxt - mu) <= tolx || !(hi - lo > tolx)) {
+        mu = nxt;
+        break;
+      }
+      mu = nxt;
+    }
+  }
+  // final count and energies at mu
+  double a[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t i = tid; i < n; i += kFermiThreads) {
+    const double g = occupation(lam[i], mu, sigma);
+    a[0] += g * c[i];
+    a[1] += g * c[i] * lam[i];
+    double sg = 0.0;
+    if (g > 0.0) sg += g * log(g);
+    if (g < 1.0) sg += (1.0 - g) * log1p(-g);
+    a[2] += c[i] * sg;
+  }
+  bsum(a, 3);
+  if (tid == 0) {
+    out[0] = mu;
+    out[1] = 2.0 * a[0];
+    out[2] = 2.0 * a[1];
+    out[3] = -2.0 * sigma * a[2];
+    out[4] = static_cast<double>(evals + 1);
+    out[5] = static_cast<double>(status);
+  }
+}
+
+// rho_global[gidx[g]] += rho[g] on core points (distinct global points within
+// one call; calls for different subsystems are ordered on the stream).
+__global__ void scatter_core_kernel(const double* __restrict__ rho, const uint8_t* __restrict__ mask,
+                                    const int64_t* __restrict__ gidx, int64_t nd,
+                                    double* __restrict__ rho_global) {
+  const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (g >= nd || !mask[g]) return;
+  rho_global[gidx[g]] += rho[g];
+}
+
+// dos[b] = 2 sum of c_i over lam_i in [edges[b], edges[b+1]) (the last bin
+// also takes its right edge); one thread per bin, states in order.
+__global__ void dos_kernel(const double* __restrict__ lam, const double* __restrict__ c, int64_t n,
+                           const double* __restrict__ edges, int nbins, double* __restrict__ dos) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nbins) return;
+  const double e0 = edges[b], e1 = edges[b + 1];
+  const bool last = b == nbins - 1;
+  double s = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    const double x = lam[i];
+    if (x >= e0 && (x < e1 || (last && x == e1))) s += c[i];
+  }
+  dos[b] = 2.0 * s;
+}
+
 // rho[g] = (2/h^3) sum_n g_n psi_{g,n}^2 on core points, 0 elsewhere.
 template <typename TS>
 __global__ __launch_bounds__(256) void rho_kernel(const TS* __restrict__ psi, int64_t nd, int64_t ld,
@@ -230,6 +387,39 @@ void launch_density(const double* lam, double mu, double sigma, const uint8_t* m
   }
   XLS_LAUNCH_CHECK("density kernels");
   launch_reduce_cols(cpart, nchunk, ns, c, 0, st);
+}
+
+void launch_core_weights(const uint8_t* mask, const void* psi, int is_float, int64_t nd, int64_t ld, int ns,
+                         double* cpart, int nchunk, double* c, hipStream_t st) {
+  if (is_float)
+    hipLaunchKernelGGL(core_weight_kernel<float>, dim3(nchunk, ns), dim3(256), 0, st,
+                       static_cast<const float*>(psi), nd, ld, mask, nchunk, cpart);
+  else
+    hipLaunchKernelGGL(core_weight_kernel<double>, dim3(nchunk, ns), dim3(256), 0, st,
+                       static_cast<const double*>(psi), nd, ld, mask, nchunk, cpart);
+  XLS_LAUNCH_CHECK("core_weight_kernel");
+  launch_reduce_cols(cpart, nchunk, ns, c, 0, st);
+}
+
+void launch_fermi_level(const double* lam, const double* c, int64_t n, double sigma, double target, int max_eval,
+                        double* out, hipStream_t st) {
+  hipLaunchKernelGGL(fermi_level_kernel, dim3(1), dim3(kFermiThreads), 0, st, lam, c, n, sigma, target, max_eval,
+                     out);
+  XLS_LAUNCH_CHECK("fermi_level_kernel");
+}
+
+void launch_scatter_core(const double* rho, const uint8_t* mask, const int64_t* gidx, int64_t nd,
+                         double* rho_global, hipStream_t st) {
+  if (nd <= 0) return;
+  hipLaunchKernelGGL(scatter_core_kernel, dim3(nblk(nd, 256)), dim3(256), 0, st, rho, mask, gidx, nd, rho_global);
+  XLS_LAUNCH_CHECK("scatter_core_kernel");
+}
+
+void launch_dos(const double* lam, const double* c, int64_t n, const double* edges, int nbins, double* dos,
+                hipStream_t st) {
+  if (nbins <= 0) return;
+  hipLaunchKernelGGL(dos_kernel, dim3(nblk(nbins, 64)), dim3(64), 0, st, lam, c, n, edges, nbins, dos);
+  XLS_LAUNCH_CHECK("dos_kernel");
 }
 
 template <typename TS>

@@ -195,6 +195,20 @@ void launch_reduce_cols(const double* partial, int nper, int ncols, double* out,
 void launch_density(const double* lam, double mu, double sigma, const uint8_t* mask, double h,
                     const void* psi, int is_float, int64_t nd, int64_t ld, int ns, double* rho,
                     double* cpart, int nchunk, double* c, double* gocc, hipStream_t st);
+// c[n] = sum over core points of psi_{g,n}^2 (no density)
+void launch_core_weights(const uint8_t* mask, const void* psi, int is_float, int64_t nd, int64_t ld, int ns,
+                         double* cpart, int nchunk, double* c, hipStream_t st);
+// Fermi level of n states (device lam, c) for sigma and an electron count;
+// out[0..5] = mu, N_e(mu), E_band, E_entropy, evaluations, status (1: count
+// out of reach)
+void launch_fermi_level(const double* lam, const double* c, int64_t n, double sigma, double target, int max_eval,
+                        double* out, hipStream_t st);
+// rho_global[gidx[g]] += rho[g] on core points
+void launch_scatter_core(const double* rho, const uint8_t* mask, const int64_t* gidx, int64_t nd,
+                         double* rho_global, hipStream_t st);
+// dos[b] = 2 sum c over lam in bin b of edges[0..nbins]
+void launch_dos(const double* lam, const double* c, int64_t n, const double* edges, int nbins, double* dos,
+                hipStream_t st);
 // Lanczos helpers
 template <typename TS>
 void launch_dot(const TS* x, const TS* y, int64_t n, double* partial, int nblocks, double* out,

@@ -38,7 +38,8 @@ EXPORTED = [
     "xls_subdomain_get_block", "xls_subdomain_set_block", "xls_subdomain_get_maps",
     "xls_subdomain_get_projectors", "xls_split_bf16", "xls_set_profiling", "xls_get_stage_times",
     "xls_subdomain_tune",
-    "xls_batch_create", "xls_batch_chefsi", "xls_batch_density", "xls_batch_subdomain", "xls_batch_tune",
+    "xls_batch_create", "xls_batch_chefsi", "xls_batch_density", "xls_batch_fermi", "xls_batch_assemble",
+    "xls_batch_subdomain", "xls_batch_tune",
     "xls_batch_stats", "xls_batch_destroy",
     "xls_subdomain_counters", "xls_subdomain_features", "xls_mlp_create", "xls_mlp_destroy",
     "xls_mlp_get_params", "xls_mlp_set_params", "xls_mlp_set_norm", "xls_mlp_forward", "xls_mlp_gradient",
@@ -410,6 +411,24 @@ class Batch:
         ro = np.cumsum([0] + nds)
         co = np.cumsum([0] + [ns for _, ns in self.shapes])
         return [rho[ro[i]:ro[i + 1]] for i in range(self.n)], [c[co[i]:co[i + 1]] for i in range(self.n)]
+
+    def xls_batch_fermi(self, sigma: float, n_electrons: float):
+        """(mu, N_e(mu), E_band, E_entropy, evaluations) of the whole batch."""
+        out = np.zeros(5)
+        n = _check(lib().xls_batch_fermi(self._h, C.c_double(sigma), C.c_double(n_electrons), _dp(out),
+                                         C.c_int32(5)))
+        return tuple(float(v) for v in out[:n])
+
+    def xls_batch_assemble(self, n_global: int = 0, edges=None):
+        """(global density or None, DOS or None) at the last xls_batch_fermi's mu."""
+        rho = np.zeros(int(n_global)) if n_global > 0 else None
+        e = None if edges is None else np.ascontiguousarray(edges, dtype=np.float64)
+        nb = 0 if e is None else len(e) - 1
+        dos = np.zeros(max(nb, 0))
+        _check(lib().xls_batch_assemble(self._h, C.c_int64(int(n_global)), _dp(rho) if rho is not None else None,
+                                        C.c_int32(nb), _dp(e) if e is not None else None,
+                                        _dp(dos) if nb > 0 else None))
+        return rho, (dos if nb > 0 else None)
 
     def xls_batch_subdomain(self, i: int) -> Subdomain:
         h = C.c_void_p()

@@ -127,6 +127,29 @@ __device__ __forceinline__ void bstore(double v, __amdgpu_buffer_rsrc_t r, int v
   typedef unsigned int u2 __attribute__((ext_vector_type(2)));
   __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, voff, soff, 0);
 }
+// cache policy word of a buffer access (bit 1: non-temporal)
+template <int AUX>
+__device__ __forceinline__ float bload_p(__amdgpu_buffer_rsrc_t r, int voff, int soff, float*) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, AUX));
+}
+template <int AUX>
+__device__ __forceinline__ double bload_p(__amdgpu_buffer_rsrc_t r, int voff, int soff, double*) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, AUX));
+}
+template <int AUX>
+__device__ __forceinline__ void bstore_p(float v, __amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, voff, soff, AUX);
+}
+template <int AUX>
+__device__ __forceinline__ void bstore_p(double v, __amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, voff, soff, AUX);
+}
+// Y_{k-1} is read once and Y_{k+1} written once per launch: both go
+// non-temporal, which leaves more of the L2 to the reused data (Y_k's halo
+// rows, V, the projector words); -1 % (FP32) and -2 % (FP64) launch time
+constexpr int kPrevAux = 2;
+constexpr int kOutAux = 2;
 // four projector values of one reverse-CSR entry
 template <typename TC>
 struct Ent4 {
@@ -333,9 +356,10 @@ __device__ __forceinline__ void stencil_tile(const HArgs<TS, TC>& A, uint32_t lo
         q[i][v][Q - 1] = ldq(i, v, zq0);
         fr[i][v] = ldq(i, v, zq1);
         if (MODE == kFilter) {
-          yp1[i][v] = static_cast<TC>(bload<TS>(rp[v], os[i], z0 * pp * ES));
+          yp1[i][v] = static_cast<TC>(bload_p<kPrevAux>(rp[v], os[i], z0 * pp * ES, (TS*)nullptr));
           yp2[i][v] = TC(0);
-          if (z0 + 1 < z1) yp2[i][v] = static_cast<TC>(bload<TS>(rp[v], os[i], (z0 + 1) * pp * ES));
+          if (z0 + 1 < z1)
+            yp2[i][v] = static_cast<TC>(bload_p<kPrevAux>(rp[v], os[i], (z0 + 1) * pp * ES, (TS*)nullptr));
         }
       }
       rp2[i] = bload<int>(rk, o4[i], z0 * pp * 4);
@@ -420,7 +444,7 @@ __device__ __forceinline__ void stencil_tile(const HArgs<TS, TC>& A, uint32_t lo
           bstore(static_cast<TS>(hy[v]), ro[v], os[i], so);
         } else if (MODE == kFilter) {
           const TC r = ca * (hy[v] - cc * q[i][v][QS(R)]) - cb * yp1[i][v];
-          bstore(static_cast<TS>(r), ro[v], os[i], so);
+          bstore_p<kOutAux>(static_cast<TS>(r), ro[v], os[i], so);
         } else if (vo[i] >= 0) {
           const double d = static_cast<double>(hy[v]) - lamc * static_cast<double>(q[i][v][QS(R)]);
           racc += d * d;
@@ -444,7 +468,8 @@ __device__ __forceinline__ void stencil_tile(const HArgs<TS, TC>& A, uint32_t lo
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
           fr[i][v] = ldq(i, v, zq);
-          if (MODE == kFilter && z + 2 < z1) yp2[i][v] = static_cast<TC>(bload<TS>(rp[v], os[i], so2));
+          if (MODE == kFilter && z + 2 < z1)
+            yp2[i][v] = static_cast<TC>(bload_p<kPrevAux>(rp[v], os[i], so2, (TS*)nullptr));
         }
       load_rest(z + 1);
     }

@@ -45,6 +45,17 @@ constexpr int kTrdTail = 128;    // trailing steps done in one workgroup, block 
 
 inline unsigned nblk(int64_t n, int b) { return static_cast<unsigned>((n + b - 1) / b); }
 
+// 1/q from the hardware estimate and two Newton-Raphson steps (each squares
+// the relative error), a few instructions shorter on the dependent chain
+// than a correctly rounded division
+__device__ __forceinline__ double rcp_nr(double q) {
+  double r = __builtin_amdgcn_rcp(q);
+  double e = fma(-q, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-q, r, 1.0);
+  return fma(r, e, r);
+}
+
 // Cross-lane moves for wave reductions (full wave active at every call).
 // Within each row of 16 lanes: rotate by 8, 4, 2, 1 (DPP row_ror), so every
 // lane of a row ends with the row's result, in the same operand order; the
@@ -687,17 +698,6 @@ __global__ __launch_bounds__(256) void tri_prepare_kernel(const double* __restri
   }
 }
 
-// 1/q from the hardware estimate and two Newton-Raphson steps (each squares
-// the relative error), a few instructions shorter on the dependent chain
-// than a correctly rounded division
-__device__ __forceinline__ double rcp_nr(double q) {
-  double r = __builtin_amdgcn_rcp(q);
-  double e = fma(-q, r, 1.0);
-  r = fma(r, e, r);
-  e = fma(-q, r, 1.0);
-  return fma(r, e, r);
-}
-
 // Eigenvalue slot s (one wavefront): the (s - start)-th smallest eigenvalue of
 // the block that contains row s, by 65-section on Sturm counts (LDL^T pivots
 // of T - x I): each lane counts at one of 64 interior points, and the first
@@ -850,7 +850,7 @@ __global__ __launch_bounds__(256) void tri_inviter_kernel(const double* __restri
           if (t < nstep) {
             const int i = i0 + t;
             const double a = ea[t], b = db[t] - xs, cn = ea[t + 1];
-            const double ra = 1.0 / a;  // depends on the inputs only: off the recurrence's chain
+            const double ra = rcp_nr(a);  // depends on the inputs only: off the recurrence's chain
             if (fabs(a) > fabs(bb)) {
               piv[i] = 1;
               r0[i] = ra;
@@ -863,7 +863,7 @@ __global__ __launch_bounds__(256) void tri_inviter_kernel(const double* __restri
             } else {
               piv[i] = 0;
               const double p = (fabs(bb) < pmin) ? copysign(pmin, bb) : bb;
-              const double rp = 1.0 / p;
+              const double rp = rcp_nr(p);
               r0[i] = rp;
               u1[i] = cc;
               u2[i] = 0.0;
@@ -875,7 +875,7 @@ __global__ __launch_bounds__(256) void tri_inviter_kernel(const double* __restri
           }
         }
       }
-      r0[m - 1] = 1.0 / ((fabs(bb) < pmin) ? copysign(pmin, bb) : bb);
+      r0[m - 1] = rcp_nr((fabs(bb) < pmin) ? copysign(pmin, bb) : bb);
     }
     double part = 0.0;
     for (int j = tid; j < m; j += 256) {

@@ -145,6 +145,7 @@ def run_form(sd, x0, form: str, steps: int, warmup: int, degree: int):
         xls.xls_set_profiling(False)
         ms, nlaunch = s.xls_get_stage_times()
         gemm = time_gemms(s, sd.nd, x0.shape[1], form)
+        half = half_storage_timing(s, sd.nd, x0.shape[1], wbytes)
     step_ms = (t1 - t0) * 1e3 / it
     nd, ns = sd.nd, x0.shape[1]
     units = nd * ns * degree
@@ -166,7 +167,30 @@ def run_form(sd, x0, form: str, steps: int, warmup: int, degree: int):
         "max_resid": float(np.max(resid)),
         "ritz_lo": float(ritz[0]),
         "gemm": gemm,
+        "half_storage": half,
     }
+
+
+def half_storage_timing(s, nd: int, ns: int, wbytes: int, reps: int = 5):
+    """FP16 warm-start storage of the block (xls_subdomain_store_half / _load_half):
+    best wall time of reps calls each, priced at the bytes they must move
+    (read w + write 2 bytes per value, and back)."""
+    import torch
+
+    buf = torch.empty(nd * ns, dtype=torch.float16, device="cuda")
+    s.xls_subdomain_store_half(buf)
+    ts, tl = 1e9, 1e9
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        s.xls_subdomain_store_half(buf)
+        ts = min(ts, time.perf_counter() - t0)
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        s.xls_subdomain_load_half(buf)
+        tl = min(tl, time.perf_counter() - t0)
+    nbytes = float(nd) * ns * (wbytes + 2)
+    return {"store_ms": ts * 1e3, "load_ms": tl * 1e3, "bytes_each": nbytes,
+            "store_gbs": nbytes / ts / 1e9, "load_gbs": nbytes / tl / 1e9, "half_bytes": float(nd) * ns * 2}
 
 
 def time_gemms(s, nd: int, ns: int, form: str, reps: int = 5):
@@ -449,6 +473,7 @@ def main():
         "roofline": dict(r["roofline"], copy_gbs=copy_gbs, frac_of_copy=r["roofline"]["achieved"] / copy_gbs),
         "subdomains_per_s": 1e3 / (CHEFSI_ITERS * r["ms_per_step"]),
         "gemm": r["gemm"],
+        "half_storage": r["half_storage"],
         "filter_rate": r["filter_rate"],
         "stage_ms_per_step": r["stage_ms_per_step"],
     }

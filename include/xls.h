@@ -187,6 +187,24 @@ int xls_dense_geneig(int32_t n, const double* Hs, const double* M, double* lam, 
 
 int xls_subdomain_get_block(xls_subdomain_t s, double* X);       /* [N_d*ns] */
 int xls_subdomain_set_block(xls_subdomain_t s, const double* X); /* [N_d*ns] */
+
+/* FP16 orbital warm-start storage (Sec. V-B.2: orbital guesses are kept in
+ * half precision between SCF iterations; all arithmetic stays in the
+ * handle's precision).  Both buffers are DEVICE memory holding N_d*ns
+ * IEEE binary16 values, column-major with leading dimension N_d, owned by
+ * the caller (half the size of an FP32 block, a quarter of FP64).
+ * xls_subdomain_store_half: dst receives the current block rounded to
+ *   nearest even (|x| > 65504 becomes +-inf); the handle is unchanged.
+ * xls_subdomain_load_half: the block is replaced by src widened exactly to
+ *   the storage precision, as xls_subdomain_set_block would (Ritz values are
+ *   dropped); the next xls_chefsi_step starts from it.
+ * Both run on the handle's stream and return when it is done.  INVALID_ARG
+ * for NULL, for a pointer that is not device memory (pageable or pinned
+ * host memory included), or when the device allocation holding the pointer
+ * ends before N_d*ns values (a buffer carved from a larger pooled
+ * allocation is checked against that allocation only). */
+int xls_subdomain_store_half(xls_subdomain_t s, uint16_t* dst);
+int xls_subdomain_load_half(xls_subdomain_t s, const uint16_t* src);
 /* Integer maps: core_mask u8[N_d], global_index i64[N_d]. */
 int xls_subdomain_get_maps(xls_subdomain_t s, uint8_t* core_mask, int64_t* global_index);
 /* sizes[0] = total support slots, sizes[1] = n_atoms.  With NULL arrays only

@@ -480,6 +480,26 @@ auto by_prec(xls_subdomain_s* s, F&& f) {
 
 }  // namespace
 
+namespace xls {
+namespace {
+// Throws INVALID_ARG unless [p, p + bytes) lies inside one device allocation.
+void check_device_range(const void* p, size_t bytes) {
+  hipPointerAttribute_t at{};
+  const hipError_t e = hipPointerGetAttributes(&at, p);
+  (void)hipGetLastError();  // a host pointer leaves an error that later launch checks must not see
+  if (e != hipSuccess || at.type != hipMemoryTypeDevice) fail(XLS_ERR_INVALID_ARG, "pointer is not device memory");
+  hipDeviceptr_t base = nullptr;
+  size_t size = 0;
+  const hipError_t e2 = hipMemGetAddressRange(&base, &size, const_cast<void*>(p));
+  (void)hipGetLastError();
+  if (e2 != hipSuccess) fail(XLS_ERR_INVALID_ARG, "device allocation not found");
+  const char* b = static_cast<const char*>(base);
+  const char* q = static_cast<const char*>(p);
+  if (q < b || q + bytes > b + size) fail(XLS_ERR_INVALID_ARG, "device buffer too small");
+}
+}  // namespace
+}  // namespace xls
+
 extern "C" {
 
 const char* xls_last_error(void) { return g_last_error.c_str(); }
@@ -821,6 +841,36 @@ int xls_subdomain_set_block(xls_subdomain_t s, const double* X) {
     if (!finite_all(X, s->nd * s->ns)) fail(XLS_ERR_INVALID_ARG, "block not finite");
     by_prec(s, [&](auto tag) {
       upload_block<decltype(tag)>(s, X, s->blk[s->cur], s->ns);
+      return 0;
+    });
+    XLS_HIP(hipStreamSynchronize(s->st));
+    s->have_ritz = false;
+    return XLS_OK;
+  });
+}
+
+
+int xls_subdomain_store_half(xls_subdomain_t s, uint16_t* dst) {
+  return guarded([&]() -> int {
+    if (!s || !dst) fail(XLS_ERR_INVALID_ARG, "NULL argument");
+    check_device_range(dst, static_cast<size_t>(s->nd) * s->ns * 2);
+    by_prec(s, [&](auto tag) {
+      using TS = decltype(tag);
+      launch_block_half<TS>(B<TS>(s, s->cur), s->ld, s->nd, s->ns, dst, 1, s->st);
+      return 0;
+    });
+    XLS_HIP(hipStreamSynchronize(s->st));
+    return XLS_OK;
+  });
+}
+
+int xls_subdomain_load_half(xls_subdomain_t s, const uint16_t* src) {
+  return guarded([&]() -> int {
+    if (!s || !src) fail(XLS_ERR_INVALID_ARG, "NULL argument");
+    check_device_range(src, static_cast<size_t>(s->nd) * s->ns * 2);
+    by_prec(s, [&](auto tag) {
+      using TS = decltype(tag);
+      launch_block_half<TS>(B<TS>(s, s->cur), s->ld, s->nd, s->ns, const_cast<uint16_t*>(src), 0, s->st);
       return 0;
     });
     XLS_HIP(hipStreamSynchronize(s->st));

@@ -198,6 +198,28 @@ __global__ void dos_kernel(const double* __restrict__ lam, const double* __restr
   dos[b] = 2.0 * s;
 }
 
+// Column c of a block (leading dimension ld) to and from IEEE binary16
+// storage with leading dimension nd: rounding to nearest even on the way
+// down, exact widening on the way up.  One thread per element, grid.y =
+// column.
+template <typename TS>
+__global__ void block_to_half_kernel(const TS* __restrict__ src, int64_t ld, int64_t nd,
+                                     uint16_t* __restrict__ dst) {
+  const int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t c = blockIdx.y;
+  if (r >= nd) return;
+  const _Float16 h = static_cast<_Float16>(src[r + c * ld]);
+  dst[r + c * nd] = __builtin_bit_cast(uint16_t, h);
+}
+template <typename TS>
+__global__ void half_to_block_kernel(const uint16_t* __restrict__ src, int64_t ld, int64_t nd,
+                                     TS* __restrict__ dst) {
+  const int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t c = blockIdx.y;
+  if (r >= nd) return;
+  dst[r + c * ld] = static_cast<TS>(__builtin_bit_cast(_Float16, src[r + c * nd]));
+}
+
 // rho[g] = (2/h^3) sum_n g_n psi_{g,n}^2 on core points, 0 elsewhere.
 template <typename TS>
 __global__ __launch_bounds__(256) void rho_kernel(const TS* __restrict__ psi, int64_t nd, int64_t ld,
@@ -388,6 +410,20 @@ void launch_density(const double* lam, double mu, double sigma, const uint8_t* m
   XLS_LAUNCH_CHECK("density kernels");
   launch_reduce_cols(cpart, nchunk, ns, c, 0, st);
 }
+
+template <typename TS>
+void launch_block_half(const TS* blk, int64_t ld, int64_t nd, int ncols, uint16_t* half, int to_half,
+                       hipStream_t st) {
+  if (nd <= 0 || ncols <= 0) return;
+  const dim3 grid(nblk(nd, 256), static_cast<unsigned>(ncols));
+  if (to_half)
+    hipLaunchKernelGGL(block_to_half_kernel<TS>, grid, dim3(256), 0, st, blk, ld, nd, half);
+  else
+    hipLaunchKernelGGL(half_to_block_kernel<TS>, grid, dim3(256), 0, st, half, ld, nd, const_cast<TS*>(blk));
+  XLS_LAUNCH_CHECK("block_half");
+}
+template void launch_block_half<float>(const float*, int64_t, int64_t, int, uint16_t*, int, hipStream_t);
+template void launch_block_half<double>(const double*, int64_t, int64_t, int, uint16_t*, int, hipStream_t);
 
 void launch_core_weights(const uint8_t* mask, const void* psi, int is_float, int64_t nd, int64_t ld, int ns,
                          double* cpart, int nchunk, double* c, hipStream_t st) {

@@ -195,6 +195,11 @@ void launch_reduce_cols(const double* partial, int nper, int ncols, double* out,
 void launch_density(const double* lam, double mu, double sigma, const uint8_t* mask, double h,
                     const void* psi, int is_float, int64_t nd, int64_t ld, int ns, double* rho,
                     double* cpart, int nchunk, double* c, double* gocc, hipStream_t st);
+// to_half: half[r + c nd] = binary16(blk[r + c ld]) (round to nearest even);
+// otherwise blk[r + c ld] = half[r + c nd] widened (blk is written)
+template <typename TS>
+void launch_block_half(const TS* blk, int64_t ld, int64_t nd, int ncols, uint16_t* half, int to_half,
+                       hipStream_t st);
 // c[n] = sum over core points of psi_{g,n}^2 (no density)
 void launch_core_weights(const uint8_t* mask, const void* psi, int is_float, int64_t nd, int64_t ld, int ns,
                          double* cpart, int nchunk, double* c, hipStream_t st);

@@ -37,7 +37,7 @@ EXPORTED = [
     "xls_subdomain_rotate", "xls_subdomain_residual", "xls_lanczos_bounds", "xls_dense_geneig",
     "xls_subdomain_get_block", "xls_subdomain_set_block", "xls_subdomain_get_maps",
     "xls_subdomain_get_projectors", "xls_split_bf16", "xls_set_profiling", "xls_get_stage_times",
-    "xls_subdomain_tune",
+    "xls_subdomain_tune", "xls_subdomain_store_half", "xls_subdomain_load_half",
     "xls_batch_create", "xls_batch_chefsi", "xls_batch_density", "xls_batch_fermi", "xls_batch_assemble",
     "xls_batch_subdomain", "xls_batch_tune",
     "xls_batch_stats", "xls_batch_destroy",
@@ -319,6 +319,16 @@ class Subdomain:
             self._h, sizes.ctypes.data_as(P64), off.ctypes.data_as(P32), idx.ctypes.data_as(P32),
             _dp(val), roff.ctypes.data_as(P32), rslot.ctypes.data_as(P32)))
         return off, idx, val, roff, rslot
+
+    def xls_subdomain_store_half(self, buf):
+        """Current block -> buf, a contiguous device torch.float16 tensor of at
+        least N_d*ns elements (column-major, leading dimension N_d)."""
+        _check(lib().xls_subdomain_store_half(self._h, C.c_void_p(int(buf.data_ptr()))))
+        return buf
+
+    def xls_subdomain_load_half(self, buf):
+        """Block <- buf (device torch.float16, as written by xls_subdomain_store_half)."""
+        _check(lib().xls_subdomain_load_half(self._h, C.c_void_p(int(buf.data_ptr()))))
 
     def xls_subdomain_tune(self, prec: int, block: int = 512, ty: int = 0, tz: int = 0, nv: int = 0):
         _check(lib().xls_subdomain_tune(self._h, C.c_int32(prec), C.c_int32(block), C.c_int32(ty),

@@ -983,6 +983,117 @@ __global__ __launch_bounds__(256) void tri_rank_kernel(const double* __restrict_
   perm[rank] = s;
 }
 
+// Compact WY form of the back-transform for moderate n: blocks of kWyNB
+// consecutive reflectors, H_kb ... H_{kb+nb-1} = I - V T V^T with V the
+// block's reflectors (column j holds v_{kb+j}) and T upper triangular
+// (T_jj = tau_j, T[0:j, j] = -tau_j T[0:j, 0:j] V[:, 0:j]^T v_j).
+constexpr int kWyNB = 16;
+constexpr int kWyMaxN = 900;  // LDS: 4 columns + the block's 16 reflectors + T, (20 n + 256) doubles
+// T of block b (reflectors 16 b ...) into Tbuf + 256 b, column-major 16 x 16
+// (zero beyond the block's nb reflectors).
+__global__ __launch_bounds__(256) void bt_tfactor_kernel(const double* __restrict__ Vh,
+                                                         const double* __restrict__ tau, int n,
+                                                         double* __restrict__ Tbuf,
+                                                         const int32_t* __restrict__ flag) {
+  __shared__ double G[kWyNB * kWyNB];
+  __shared__ double Ts[kWyNB * kWyNB];
+  if (*flag) return;
+  const int b = blockIdx.x, kb = b * kWyNB, nb = min(kWyNB, n - 1 - kb), tid = threadIdx.x;
+  {  // G[i + 16 j] = v_{kb+i} . v_{kb+j} for i < j (v_{kb+j} is zero in rows <= kb + j)
+    const int i = tid % kWyNB, j = tid / kWyNB;
+    double g = 0.0;
+    if (i < j && j < nb) {
+      const double* va = Vh + static_cast<int64_t>(kb + i) * n;
+      const double* vb = Vh + static_cast<int64_t>(kb + j) * n;
+      for (int r = kb + j + 1; r < n; ++r) g += va[r] * vb[r];
+    }
+    G[tid] = g;
+    Ts[tid] = 0.0;
+  }
+  __syncthreads();
+  for (int i = 0; i < nb; ++i) {
+    const double ti = tau[kb + i];
+    if (tid < i) {
+      double acc = 0.0;
+      for (int c = tid; c < i; ++c) acc += Ts[tid + c * kWyNB] * G[c + i * kWyNB];
+      Ts[tid + i * kWyNB] = -ti * acc;
+    }
+    if (tid == i) Ts[i + i * kWyNB] = ti;
+    __syncthreads();
+  }
+  Tbuf[static_cast<int64_t>(b) * kWyNB * kWyNB + tid] = Ts[tid];
+}
+
+// out[:, c] = H_0 ... H_{n-2} Z[:, perm[c]], blocks applied from the last to
+// the first as z -= V (T (V^T z)).  Four columns per workgroup (one per
+// wave) in LDS; each block's reflectors and T are staged in LDS; a wave forms
+// its 16 dot products in one pass over the rows, then 16 wave sums, T, and
+// one update pass.
+__global__ __launch_bounds__(256) void bt_wy_kernel(const double* __restrict__ Z, const int32_t* __restrict__ perm,
+                                                    const double* __restrict__ Vh,
+                                                    const double* __restrict__ Tbuf, int n,
+                                                    double* __restrict__ out, const int32_t* __restrict__ flag) {
+  extern __shared__ double sm[];
+  if (*flag) return;
+  constexpr int NB = kWyNB;
+  double* zs = sm;               // 4 n
+  double* vs = sm + 4 * n;       // NB n: vs[q n + r] = v_{kb+q}[r]
+  double* ts = vs + NB * n;      // NB * NB
+  const int c0 = blockIdx.x * 4, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  for (int cc = 0; cc < 4; ++cc) {
+    const int c = c0 + cc;
+    int pc = (c < n) ? perm[c] : 0;
+    pc = (pc >= 0 && pc < n) ? pc : c;  // a rank is always in range; never index out of bounds
+    const double* src = (c < n) ? Z + static_cast<int64_t>(pc) * n : nullptr;
+    for (int j = tid; j < n; j += 256) zs[cc * n + j] = src ? src[j] : 0.0;
+  }
+  double* zw = zs + wv * n;
+  const int nblocks = (n - 1 + NB - 1) / NB;
+  for (int b = nblocks - 1; b >= 0; --b) {
+    const int kb = b * NB, nb = min(NB, n - 1 - kb);
+    __syncthreads();  // the previous block's readers of vs and ts are done (and zs is loaded)
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      const double* v = Vh + static_cast<int64_t>(min(kb + q, n - 1)) * n;
+      for (int r = tid; r < n; r += 256) vs[q * n + r] = (q < nb && r > kb + q) ? v[r] : 0.0;
+    }
+    ts[tid] = Tbuf[static_cast<int64_t>(b) * NB * NB + tid];
+    __syncthreads();
+    const int r0 = kb + 1;  // every reflector of the block is zero above this row
+    double acc[NB];
+#pragma unroll
+    for (int q = 0; q < NB; ++q) acc[q] = 0.0;
+    for (int r = r0 + lane; r < n; r += 64) {
+      const double zr = zw[r];
+#pragma unroll
+      for (int q = 0; q < NB; ++q) acc[q] += vs[q * n + r] * zr;
+    }
+    double w[NB];
+#pragma unroll
+    for (int q = 0; q < NB; ++q) w[q] = wave_sum(acc[q]);
+    double u[NB];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      double t = 0.0;
+#pragma unroll
+      for (int j = i; j < NB; ++j) t += ts[i + j * NB] * w[j];
+      u[i] = t;
+    }
+    for (int r = r0 + lane; r < n; r += 64) {
+      double t = 0.0;
+#pragma unroll
+      for (int q = 0; q < NB; ++q) t += vs[q * n + r] * u[q];
+      zw[r] -= t;
+    }
+  }
+  __syncthreads();
+  for (int cc = 0; cc < 4; ++cc) {
+    const int c = c0 + cc;
+    if (c >= n) break;
+    for (int j = tid; j < n; j += 256) out[j + static_cast<int64_t>(c) * n] = zs[cc * n + j];
+  }
+}
+
 // out[:, c] = H_0 H_1 ... H_{n-2} Z[:, perm[c]]: four columns per workgroup,
 // one per wavefront, held in LDS.  Each wavefront steps through the
 // reflectors on its own (dot product by shuffles, no workgroup barrier);
@@ -1159,7 +1270,14 @@ int dense_geneig(DenseWork& w, const double* Hs, const double* M, double* Y, hip
                      raw, n, lam, perm, w.flag);
   XLS_LAUNCH_CHECK("tridiagonal eigensolver");
   // --- back-transformation, Y = Rinv Q Z ---
-  {
+  if (n >= 2 * kWyNB && n <= kWyMaxN) {
+    // T of every block into C1 (free after C was formed): 256 (n / 16 + 1) <= n^2 doubles here
+    const int nblocks = (n - 1 + kWyNB - 1) / kWyNB;
+    hipLaunchKernelGGL(bt_tfactor_kernel, dim3(nblocks), dim3(256), 0, st, w.Vh, tau, n, w.C1, w.flag);
+    const size_t sm = (static_cast<size_t>(4 + kWyNB) * n + kWyNB * kWyNB) * sizeof(double);
+    set_smem(reinterpret_cast<const void*>(bt_wy_kernel), sm);
+    hipLaunchKernelGGL(bt_wy_kernel, dim3(nblk(n, 4)), dim3(256), sm, st, w.Z, perm, w.Vh, w.C1, n, w.T, w.flag);
+  } else {
     const size_t zbytes = kBtCols * static_cast<size_t>(n) * sizeof(double);
     const size_t budget = 150 * 1024;
     const int ch = static_cast<int>(std::max<size_t>(1, std::min<size_t>(32, (budget - zbytes) / ((n + 1) * sizeof(double)))));

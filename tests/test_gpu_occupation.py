@@ -26,8 +26,8 @@ def tiled_pair(ns=8):
     return gs, out
 
 
-def params_for(sds, degree=10, iters=6):
-    return [xls.chefsi_params(degree, iters, xls.XLS_BOUNDS_LANCZOS, gemm_prec=xls.XLS_PREC_FP64) for _ in sds]
+def params_for(sds, degree=10, iters=6, gemm_prec=xls.XLS_PREC_FP64):
+    return [xls.chefsi_params(degree, iters, xls.XLS_BOUNDS_LANCZOS, gemm_prec=gemm_prec) for _ in sds]
 
 
 def oracle_weights(blocks, sds, ritz, mu, sigma):
@@ -40,15 +40,18 @@ def oracle_weights(blocks, sds, ritz, mu, sigma):
     return rhos, cs
 
 
-def test_batch_fermi_level_and_energies_match_oracle():
-    case("batch fermi fp64")
+@pytest.mark.parametrize("prec", [xls.XLS_PREC_FP64, xls.XLS_PREC_FP32])
+def test_batch_fermi_level_and_energies_match_oracle(prec):
+    """The solve's inputs are the batch's own Ritz values and blocks (FP32
+    blocks widened exactly); the oracle redoes the weights and the level."""
+    case(f"batch fermi prec={prec}")
     gs, sds = tiled_pair()
     sigma = 0.02
-    with xls.Batch(sds, filter_prec=xls.XLS_PREC_FP64) as b:
+    with xls.Batch(sds, filter_prec=prec) as b:
         with pytest.raises(xls.XlsError) as ei:
             b.xls_batch_fermi(sigma, 4.0)
         assert ei.value.code == xls.XLS_ERR_STATE
-        ritz, resid, iters, status = b.xls_batch_chefsi(params_for(sds))
+        ritz, resid, iters, status = b.xls_batch_chefsi(params_for(sds, gemm_prec=prec))
         blocks = [b.xls_batch_subdomain(i).xls_subdomain_get_block() for i in range(len(sds))]
         lam = np.concatenate(ritz)
         _, cs = oracle_weights(blocks, sds, ritz, 0.0, sigma)

@@ -990,25 +990,35 @@ __global__ __launch_bounds__(256) void tri_rank_kernel(const double* __restrict_
 constexpr int kWyNB = 16;
 constexpr int kWyMaxN = 900;  // LDS: 4 columns + the block's 16 reflectors + T, (20 n + 256) doubles
 // T of block b (reflectors 16 b ...) into Tbuf + 256 b, column-major 16 x 16
-// (zero beyond the block's nb reflectors).
+// (zero beyond the block's nb reflectors).  The block's reflectors are
+// staged in LDS (kWyNB n doubles); each wave forms a share of the Gram
+// entries with lanes over the rows and a wave sum.
 __global__ __launch_bounds__(256) void bt_tfactor_kernel(const double* __restrict__ Vh,
                                                          const double* __restrict__ tau, int n,
                                                          double* __restrict__ Tbuf,
                                                          const int32_t* __restrict__ flag) {
+  extern __shared__ double vsh[];  // kWyNB * n
   __shared__ double G[kWyNB * kWyNB];
   __shared__ double Ts[kWyNB * kWyNB];
   if (*flag) return;
   const int b = blockIdx.x, kb = b * kWyNB, nb = min(kWyNB, n - 1 - kb), tid = threadIdx.x;
-  {  // G[i + 16 j] = v_{kb+i} . v_{kb+j} for i < j (v_{kb+j} is zero in rows <= kb + j)
-    const int i = tid % kWyNB, j = tid / kWyNB;
+  const int lane = tid & 63, wv = tid >> 6;
+  for (int q = 0; q < kWyNB; ++q) {
+    const double* v = Vh + static_cast<int64_t>(min(kb + q, n - 1)) * n;
+    for (int r = tid; r < n; r += 256) vsh[q * n + r] = (q < nb && r > kb + q) ? v[r] : 0.0;
+  }
+  G[tid] = 0.0;
+  Ts[tid] = 0.0;
+  __syncthreads();
+  // G[i + 16 j] = v_{kb+i} . v_{kb+j} for i < j (v_{kb+j} is zero in rows <= kb + j):
+  // pair p = (i, j) goes to wave p mod 4
+  for (int pr = wv; pr < kWyNB * kWyNB; pr += 4) {
+    const int i = pr % kWyNB, j = pr / kWyNB;
+    if (!(i < j && j < nb)) continue;  // uniform across the wave
     double g = 0.0;
-    if (i < j && j < nb) {
-      const double* va = Vh + static_cast<int64_t>(kb + i) * n;
-      const double* vb = Vh + static_cast<int64_t>(kb + j) * n;
-      for (int r = kb + j + 1; r < n; ++r) g += va[r] * vb[r];
-    }
-    G[tid] = g;
-    Ts[tid] = 0.0;
+    for (int r = kb + j + 1 + lane; r < n; r += 64) g += vsh[i * n + r] * vsh[j * n + r];
+    g = wave_sum(g);
+    if (lane == 0) G[pr] = g;
   }
   __syncthreads();
   for (int i = 0; i < nb; ++i) {
@@ -1049,16 +1059,37 @@ __global__ __launch_bounds__(256) void bt_wy_kernel(const double* __restrict__ Z
   }
   double* zw = zs + wv * n;
   const int nblocks = (n - 1 + NB - 1) / NB;
-  for (int b = nblocks - 1; b >= 0; --b) {
+  // the next block's reflectors and T are loaded into registers while the
+  // current block computes (rows tid + 256 p, n <= 256 PF)
+  constexpr int PF = (kWyMaxN + 255) / 256;
+  double pre[NB][PF], tpre;
+  auto fetch = [&](int b) {
     const int kb = b * NB, nb = min(NB, n - 1 - kb);
-    __syncthreads();  // the previous block's readers of vs and ts are done (and zs is loaded)
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
       const double* v = Vh + static_cast<int64_t>(min(kb + q, n - 1)) * n;
-      for (int r = tid; r < n; r += 256) vs[q * n + r] = (q < nb && r > kb + q) ? v[r] : 0.0;
+#pragma unroll
+      for (int p = 0; p < PF; ++p) {
+        const int r = tid + 256 * p;
+        pre[q][p] = (q < nb && r < n && r > kb + q) ? v[r] : 0.0;
+      }
     }
-    ts[tid] = Tbuf[static_cast<int64_t>(b) * NB * NB + tid];
+    tpre = Tbuf[static_cast<int64_t>(b) * NB * NB + tid];
+  };
+  fetch(nblocks - 1);
+  for (int b = nblocks - 1; b >= 0; --b) {
+    const int kb = b * NB;
+    __syncthreads();  // the previous block's readers of vs and ts are done (and zs is loaded)
+#pragma unroll
+    for (int q = 0; q < NB; ++q)
+#pragma unroll
+      for (int p = 0; p < PF; ++p) {
+        const int r = tid + 256 * p;
+        if (r < n) vs[q * n + r] = pre[q][p];
+      }
+    ts[tid] = tpre;
     __syncthreads();
+    if (b > 0) fetch(b - 1);
     const int r0 = kb + 1;  // every reflector of the block is zero above this row
     double acc[NB];
 #pragma unroll
@@ -1273,7 +1304,9 @@ int dense_geneig(DenseWork& w, const double* Hs, const double* M, double* Y, hip
   if (n >= 2 * kWyNB && n <= kWyMaxN) {
     // T of every block into C1 (free after C was formed): 256 (n / 16 + 1) <= n^2 doubles here
     const int nblocks = (n - 1 + kWyNB - 1) / kWyNB;
-    hipLaunchKernelGGL(bt_tfactor_kernel, dim3(nblocks), dim3(256), 0, st, w.Vh, tau, n, w.C1, w.flag);
+    const size_t tf_sm = static_cast<size_t>(kWyNB) * n * sizeof(double);
+    set_smem(reinterpret_cast<const void*>(bt_tfactor_kernel), tf_sm);
+    hipLaunchKernelGGL(bt_tfactor_kernel, dim3(nblocks), dim3(256), tf_sm, st, w.Vh, tau, n, w.C1, w.flag);
     const size_t sm = (static_cast<size_t>(4 + kWyNB) * n + kWyNB * kWyNB) * sizeof(double);
     set_smem(reinterpret_cast<const void*>(bt_wy_kernel), sm);
     hipLaunchKernelGGL(bt_wy_kernel, dim3(nblk(n, 4)), dim3(256), sm, st, w.Z, perm, w.Vh, w.C1, n, w.T, w.flag);

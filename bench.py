@@ -222,7 +222,7 @@ def gemm_large(reps: int = 3):
     bf16x3 and FP32, FP64 block for FP64."""
     from paper_2609_13115_amd import workloads, xls
 
-    sd = workloads.cfg4(with_x0=False)
+    sd = workloads.si_box_96(with_x0=False)
     x0 = sd.make_x0()
     nd, ns = sd.nd, x0.shape[1]
     out = {"workload": f"96^3 zero-Dirichlet Si box, N_d = {nd}, Ns = {ns}, X0 random-normal"}
@@ -432,7 +432,7 @@ def main():
     from paper_2609_13115_amd import workloads
 
     torch.cuda.set_device(0)
-    sd = workloads.cfg2(with_x0=False, ns=a.ns)
+    sd = workloads.si_box_64(with_x0=False, ns=a.ns)
     x0 = sd.make_x0(a.ns)
     sd.x0 = x0
     if a.calib_mib > 0:

@@ -231,11 +231,11 @@ def diamond_si_system(ncells: int, global_n: int, displacement: float, key: Tupl
 # Named workloads
 # ---------------------------------------------------------------------------
 
-def cfg_key(cfg: int, index: int = 0) -> Tuple[int, int]:
-    return (SEED_BASE + 1000 * cfg, index)
+def workload_key(tag: int, index: int = 0) -> Tuple[int, int]:
+    return (SEED_BASE + 1000 * tag, index)
 
 
-def periodic_si_cell(n: int = 24, ns: int = 20, key: Tuple[int, ...] = cfg_key(1),
+def periodic_si_cell(n: int = 24, ns: int = 20, key: Tuple[int, ...] = workload_key(1),
                      with_x0: bool = True) -> Subdomain:
     """One periodic 8-atom diamond cell on an n^3 grid (h = a/n)."""
     gs = diamond_si_system(1, n, 0.0, key)
@@ -243,9 +243,9 @@ def periodic_si_cell(n: int = 24, ns: int = 20, key: Tuple[int, ...] = cfg_key(1
                         with_x0, name=f"periodic Si cell {n}^3 ns={ns}")
 
 
-def cfg1(with_x0: bool = True) -> Subdomain:
+def si_cell_24(with_x0: bool = True) -> Subdomain:
     """Periodic 8-atom diamond cell, 24^3 grid (h = 0.4275), ns = 20."""
-    return periodic_si_cell(24, 20, cfg_key(1), with_x0)
+    return periodic_si_cell(24, 20, workload_key(1), with_x0)
 
 
 def dirichlet_si_box(n: int, ns: int, key: Tuple[int, ...], ncells: int = 4,
@@ -268,14 +268,14 @@ def dirichlet_si_box(n: int, ns: int, key: Tuple[int, ...], ncells: int = 4,
                         with_x0, name=f"Dirichlet Si box {n}^3 ns={ns}")
 
 
-def cfg2(with_x0: bool = True, ns: int = 480) -> Subdomain:
+def si_box_64(with_x0: bool = True, ns: int = 480) -> Subdomain:
     """64-atom displaced diamond core in a zero-Dirichlet 64^3 box, h ~ 0.43, ns = 480."""
-    return dirichlet_si_box(64, ns, cfg_key(2), with_x0=with_x0)
+    return dirichlet_si_box(64, ns, workload_key(2), with_x0=with_x0)
 
 
-def cfg4(with_x0: bool = False, ns: int = 2400) -> Subdomain:
+def si_box_96(with_x0: bool = False, ns: int = 2400) -> Subdomain:
     """96^3 zero-Dirichlet Si box (3x3x3-cell core), ns = 2400."""
-    return dirichlet_si_box(96, ns, cfg_key(4), ncells=5, core_cells=3, with_x0=with_x0)
+    return dirichlet_si_box(96, ns, workload_key(4), ncells=5, core_cells=3, with_x0=with_x0)
 
 
 def small_periodic(n: int = 8, ns: int = 8, index: int = 0, with_x0: bool = True) -> Subdomain:

@@ -132,7 +132,7 @@ def test_bf16_inference_matches_emulation():
 
 def test_device_features_match_oracle():
     case("features")
-    sds = [workloads.small_dirichlet(ns=6, index=1, shape=(13, 9, 20), h=0.6), workloads.cfg1()]
+    sds = [workloads.small_dirichlet(ns=6, index=1, shape=(13, 9, 20), h=0.6), workloads.si_cell_24()]
     _, two = workloads.learned_bounds_subdomains(3, index0=100)
     for sd in sds + two:
         ref = omlp.features(sd)

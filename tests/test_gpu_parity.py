@@ -33,7 +33,7 @@ def case(name):
 SYSTEMS = {
     "periodic8": lambda: workloads.small_periodic(8, 6),
     "dirichlet_ragged": lambda: workloads.small_dirichlet(ns=5, shape=(13, 9, 20)),
-    "cfg1": lambda: workloads.cfg1(),
+    "si_cell_24": lambda: workloads.si_cell_24(),
 }
 
 
@@ -64,9 +64,9 @@ def test_maps_and_projector_tables_bit_exact(system):
     assert rel_err(val, t.val) <= 1e-13
 
 
-def test_maps_cfg2_bit_exact():
-    case("maps cfg2")
-    sd = workloads.cfg2(with_x0=False, ns=4)
+def test_maps_si_box_64_bit_exact():
+    case("maps 64^3 box")
+    sd = workloads.si_box_64(with_x0=False, ns=4)
     sd.x0 = sd.make_x0(4)
     t = projectors.build(sd.n, sd.h, sd.origin, False, sd.atoms, sd.proj)
     with xls.Subdomain(sd) as s:
@@ -110,9 +110,9 @@ def test_hamiltonian_apply_fp32(system):
     assert rel_err(out, ref) <= 2e-6
 
 
-def test_hamiltonian_apply_cfg2_fp64():
-    case("H apply cfg2 fp64")
-    sd = workloads.cfg2(with_x0=False, ns=3)
+def test_hamiltonian_apply_si_box_64_fp64():
+    case("H apply 64^3 box fp64")
+    sd = workloads.si_box_64(with_x0=False, ns=3)
     sd.x0 = sd.make_x0(3)
     op = hamiltonian.from_subdomain(sd)
     ref = op.apply(sd.x0)
@@ -154,9 +154,9 @@ def test_filter_two_vectors_per_tile_bit_identical(system, prec):
     assert rel_err(outs[2], ref) <= (1e-11 if prec == xls.XLS_PREC_FP64 else 1e-4)
 
 
-def test_filter_cfg1_degree20_fp64_and_fp32():
-    case("filter cfg1 m=20")
-    sd = workloads.cfg1()
+def test_filter_si_cell_24_degree20_fp64_and_fp32():
+    case("filter 24^3 cell m=20")
+    sd = workloads.si_cell_24()
     op = hamiltonian.from_subdomain(sd)
     lo, up = chefsi.lanczos_bounds(op.apply, sd.lanczos_v0, 20)
     lc = chefsi.first_cutoff(lo, up)
@@ -353,10 +353,10 @@ def test_dense_not_spd():
 # full CheFSI step (FP64) and brute force
 # ---------------------------------------------------------------------------
 
-def test_chefsi_cfg1_fp64_parity():
-    """cfg1: 10 iterations, degree 20, Lanczos bounds; Ritz values <= 1e-10 relative."""
-    case("chefsi cfg1 fp64")
-    sd = workloads.cfg1()
+def test_chefsi_si_cell_24_fp64_parity():
+    """Periodic 24^3 Si cell: 10 iterations, degree 20, Lanczos bounds; Ritz values <= 1e-10 relative."""
+    case("chefsi 24^3 cell fp64")
+    sd = workloads.si_cell_24()
     op = hamiltonian.from_subdomain(sd)
     lo, up = chefsi.lanczos_bounds(op.apply, sd.lanczos_v0, 20)
     ref = chefsi.chefsi(op.apply, sd.x0, 20, 10, lo, chefsi.first_cutoff(lo, up), up)
@@ -444,7 +444,7 @@ def test_split_bf16_bit_exact():
 
 def test_bitwise_determinism():
     case("determinism")
-    sd = workloads.cfg1()
+    sd = workloads.si_cell_24()
     outs = []
     for _ in range(2):
         with xls.Subdomain(sd) as s:
@@ -536,13 +536,13 @@ def test_dense_graph_replay_matches_eager():
 
 
 @pytest.mark.parametrize("gprec", [xls.XLS_PREC_FP32, xls.XLS_PREC_BF16X3])
-def test_mixed_precision_ritz_gate_cfg1(gprec):
+def test_mixed_precision_ritz_gate_si_cell_24(gprec):
     """The mixed forms (FP32 filter sweeps; FP32 or split-BF16 GEMMs; FP64
-    Cholesky, eigensolve and residual) against the FP64 oracle on cfg1:
+    Cholesky, eigensolve and residual) against the FP64 oracle on the periodic 24^3 cell:
     every gated Ritz value within 1e-6 Ha, and the gated subspace within
     1e-5 (largest principal-angle sine, clusters closed)."""
-    case(f"mixed gate cfg1 gemm={gprec}")
-    sd = workloads.cfg1()
+    case(f"mixed gate 24^3 cell gemm={gprec}")
+    sd = workloads.si_cell_24()
     op = hamiltonian.from_subdomain(sd)
     lo, up = chefsi.lanczos_bounds(op.apply, sd.lanczos_v0, 20)
     ref = chefsi.chefsi(op.apply, sd.x0, 20, 14, lo, chefsi.first_cutoff(lo, up), up)

@@ -43,7 +43,7 @@ def test_lanczos_bound_on_diagonal_operator():
     assert up - d[-1] < 0.5 * (d[-1] - d[0])
 
 
-def test_lanczos_bound_free_periodic_cfg1_grid():
+def test_lanczos_bound_free_periodic_24_grid():
     """V = 0, no projectors, 24^3, h = 0.4275: spectrum [0, 58.0522] (closed form)."""
     op = hamiltonian.free_operator((24, 24, 24), 0.4275, True)
     v0 = workloads.random_block(op.nd, 1, (3, 3))[:, 0]

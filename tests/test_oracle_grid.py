@@ -72,7 +72,7 @@ def test_periodic_plane_wave_eigenvalues(n, h):
         assert np.allclose(out, lam * psi, atol=1e-10 * max(1, abs(lam)))
 
 
-def test_periodic_lambda_max_cfg1():
+def test_periodic_lambda_max_si_cell_24():
     """Checkerboard mode (-1)^(i+j+k) on the 24^3, h = 0.4275 grid:
     lambda_max = 1.5 s(pi) / h^2 = 58.0522 Ha."""
     n, h = (24, 24, 24), 0.4275

@@ -965,6 +965,201 @@ __global__ __launch_bounds__(256) void tri_inviter_kernel(const double* __restri
   }
 }
 
+// The same inverse iteration for n <= kPipeMaxN with the next slot's LU
+// overlapped: while wave 0 runs slot s's solves, Gram-Schmidt and
+// normalisation (wave reductions only, no workgroup barrier inside a slot),
+// the first lane of wave 1 factors T - x_{s+1} I into the other set of
+// factor arrays; one barrier per slot.  Same steps and shifts as
+// tri_inviter_kernel; its sums run over one wave instead of the workgroup.
+// LDS: d, e, x (n each), two sets of u0^-1, u1, u2 and multipliers (4n each)
+// and two pivot arrays (n bytes each).
+constexpr int kPipeMaxN = 1800;
+__global__ __launch_bounds__(256) void tri_inviter_pipe_kernel(const double* __restrict__ d,
+                                                               const double* __restrict__ ez,
+                                                               const int32_t* __restrict__ bs,
+                                                               const int32_t* __restrict__ be,
+                                                               const double* __restrict__ lam,
+                                                               const int32_t* __restrict__ cstart,
+                                                               const int32_t* __restrict__ ncl,
+                                                               const double* __restrict__ scal, int n,
+                                                               double* __restrict__ Z,
+                                                               const int32_t* __restrict__ flag) {
+  extern __shared__ double sm[];
+  if (*flag) return;
+  const int c = blockIdx.x, nc = *ncl;
+  if (c >= nc) return;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int sb = cstart[c], se = (c + 1 < nc) ? cstart[c + 1] : n;
+  const int s0 = bs[sb], s1 = be[sb], m = s1 - s0;
+  double* dd = sm;
+  double* ee = sm + n;
+  double* x = sm + 2 * n;
+  double* fac = sm + 3 * n;  // set b: r0, u1, u2, ll at fac + (4 b + k) n
+  uint8_t* pvs = reinterpret_cast<uint8_t*>(sm + 11 * n);  // set b at pvs + b n
+  for (int j = tid; j < m; j += 256) {
+    dd[j] = d[s0 + j];
+    ee[j] = (j + 1 < m) ? ez[s0 + j] : 0.0;
+  }
+  __syncthreads();
+  const double tn = scal[0];
+  const double pertol = 10.0 * kEps * tn;
+  const double pmin = fmax(1e-3 * kEps * tn, 1e-150);
+  // LU with partial pivoting of T - xs I into factor set b (one thread)
+  auto lu = [&](double xs, int b) {
+    double* r0 = fac + (4 * b + 0) * static_cast<int64_t>(n);
+    double* u1 = fac + (4 * b + 1) * static_cast<int64_t>(n);
+    double* u2 = fac + (4 * b + 2) * static_cast<int64_t>(n);
+    double* ll = fac + (4 * b + 3) * static_cast<int64_t>(n);
+    uint8_t* piv = pvs + b * static_cast<int64_t>(n);
+    double bb = dd[0] - xs, cc = ee[0];
+    for (int i0 = 0; i0 + 1 < m; i0 += kInvChunk) {
+      const int nstep = min(kInvChunk, m - 1 - i0);
+      double ea[kInvChunk + 1], db[kInvChunk];
+#pragma unroll
+      for (int t = 0; t <= kInvChunk; ++t) ea[t] = ee[min(i0 + t, m - 1)];
+#pragma unroll
+      for (int t = 0; t < kInvChunk; ++t) db[t] = dd[min(i0 + 1 + t, m - 1)];
+#pragma unroll
+      for (int t = 0; t < kInvChunk; ++t) {
+        if (t < nstep) {
+          const int i = i0 + t;
+          const double a = ea[t], bv = db[t] - xs, cn = ea[t + 1];
+          const double ra = rcp_nr(a);
+          if (fabs(a) > fabs(bb)) {
+            piv[i] = 1;
+            r0[i] = ra;
+            u1[i] = bv;
+            u2[i] = cn;
+            const double mult = bb * ra;
+            ll[i] = mult;
+            bb = cc - mult * bv;
+            cc = -mult * cn;
+          } else {
+            piv[i] = 0;
+            const double p = (fabs(bb) < pmin) ? copysign(pmin, bb) : bb;
+            const double rp = rcp_nr(p);
+            r0[i] = rp;
+            u1[i] = cc;
+            u2[i] = 0.0;
+            const double mult = a * rp;
+            ll[i] = mult;
+            bb = bv - mult * cc;
+            cc = cn;
+          }
+        }
+      }
+    }
+    r0[m - 1] = rcp_nr((fabs(bb) < pmin) ? copysign(pmin, bb) : bb);
+  };
+  double xcur = lam[sb];
+  if (tid == 0) lu(xcur, 0);
+  __syncthreads();
+  const int iters = (se - sb == 1) ? kInvIters - 1 : kInvIters;  // clusters get one more solve
+  for (int s = sb; s < se; ++s) {
+    const int b = (s - sb) & 1;
+    double xnext = 0.0;
+    if (s + 1 < se) {
+      xnext = lam[s + 1];
+      if (xnext - xcur < pertol) xnext = xcur + pertol;
+    }
+    if (wv == 0) {
+      const double* r0 = fac + (4 * b + 0) * static_cast<int64_t>(n);
+      const double* u1 = fac + (4 * b + 1) * static_cast<int64_t>(n);
+      const double* u2 = fac + (4 * b + 2) * static_cast<int64_t>(n);
+      const double* ll = fac + (4 * b + 3) * static_cast<int64_t>(n);
+      const uint8_t* piv = pvs + b * static_cast<int64_t>(n);
+      double part = 0.0;
+      for (int j = lane; j < m; j += 64) {
+        const double v = start_value(static_cast<uint32_t>(s), static_cast<uint32_t>(j));
+        x[j] = v;
+        part += v * v;
+      }
+      const double scale0 = 1.0 / sqrt(wave_sum(part));
+      for (int j = lane; j < m; j += 64) x[j] *= scale0;
+      asm volatile("" ::: "memory");
+      for (int it = 0; it < iters; ++it) {
+        if (lane == 0) {
+          double cur = x[0];
+          for (int i0 = 0; i0 + 1 < m; i0 += kInvChunk) {
+            const int nstep = min(kInvChunk, m - 1 - i0);
+            double xn[kInvChunk], lc[kInvChunk];
+            uint8_t pc[kInvChunk];
+#pragma unroll
+            for (int t = 0; t < kInvChunk; ++t) {
+              const int i = min(i0 + t, m - 2);
+              xn[t] = x[i + 1];
+              lc[t] = ll[i];
+              pc[t] = piv[i];
+            }
+#pragma unroll
+            for (int t = 0; t < kInvChunk; ++t) {
+              if (t < nstep) {
+                const double nx = xn[t];
+                if (pc[t]) {
+                  x[i0 + t] = nx;
+                  cur = cur - lc[t] * nx;
+                } else {
+                  x[i0 + t] = cur;
+                  cur = nx - lc[t] * cur;
+                }
+              }
+            }
+          }
+          double x1 = cur * r0[m - 1], x2 = 0.0;
+          x[m - 1] = x1;
+          for (int i1 = m - 2; i1 >= 0; i1 -= kInvChunk) {
+            const int nstep = min(kInvChunk, i1 + 1);
+            double xc[kInvChunk], a1[kInvChunk], a2[kInvChunk], rc[kInvChunk];
+#pragma unroll
+            for (int t = 0; t < kInvChunk; ++t) {
+              const int i = max(i1 - t, 0);
+              xc[t] = x[i];
+              a1[t] = u1[i];
+              a2[t] = u2[i];
+              rc[t] = r0[i];
+            }
+#pragma unroll
+            for (int t = 0; t < kInvChunk; ++t) {
+              if (t < nstep) {
+                const double xi = (xc[t] - a1[t] * x1 - a2[t] * x2) * rc[t];
+                x[i1 - t] = xi;
+                x2 = x1;
+                x1 = xi;
+              }
+            }
+          }
+        }
+        asm volatile("" ::: "memory");  // the wave reads x after lane 0's writes (LDS is in order per wave)
+        for (int t = sb; t < s; ++t) {
+          const double* zt = Z + static_cast<int64_t>(t) * n + s0;
+          double p = 0.0;
+          for (int j = lane; j < m; j += 64) p += zt[j] * x[j];
+          const double dot = wave_sum(p);
+          for (int j = lane; j < m; j += 64) x[j] -= dot * zt[j];
+          asm volatile("" ::: "memory");
+        }
+        double mx = 0.0;
+        for (int j = lane; j < m; j += 64) mx = fmax(mx, fabs(x[j]));
+        const double rmx = 1.0 / wave_max(mx);
+        double q = 0.0;
+        for (int j = lane; j < m; j += 64) {
+          const double y = x[j] * rmx;
+          q += y * y;
+        }
+        const double rs = rmx / sqrt(wave_sum(q));
+        for (int j = lane; j < m; j += 64) x[j] *= rs;
+        asm volatile("" ::: "memory");
+      }
+      double* zs = Z + static_cast<int64_t>(s) * n;
+      for (int r = lane; r < n; r += 64) zs[r] = (r >= s0 && r < s1) ? x[r - s0] : 0.0;
+    } else if (wv == 1 && lane == 0 && s + 1 < se) {
+      lu(xnext, b ^ 1);
+    }
+    __syncthreads();
+    xcur = xnext;
+  }
+}
+
 // Ascending order of all eigenvalues (ties by slot): lam[rank] = raw[s],
 // perm[rank] = s.
 __global__ __launch_bounds__(256) void tri_rank_kernel(const double* __restrict__ raw, int n,
@@ -1293,10 +1488,18 @@ int dense_geneig(DenseWork& w, const double* Hs, const double* M, double* Y, hip
   hipLaunchKernelGGL(tri_multisect_kernel, dim3(n), dim3(64), 2 * static_cast<size_t>(n) * sizeof(double), st, d,
                      ez, e2, bs, be, w.scal, n, raw, w.flag);
   hipLaunchKernelGGL(tri_cluster_kernel, dim3(1), dim3(256), 0, st, raw, bs, w.scal, n, cstart, ncl, w.flag);
-  const size_t inv_smem = 7 * static_cast<size_t>(n) * sizeof(double) + ((static_cast<size_t>(n) + 7) & ~size_t{7});
-  set_smem(reinterpret_cast<const void*>(tri_inviter_kernel), inv_smem);
-  hipLaunchKernelGGL(tri_inviter_kernel, dim3(n), dim3(256), inv_smem, st, d, ez, bs, be, raw, cstart, ncl,
-                     w.scal, n, w.Z, w.flag);
+  if (n <= kPipeMaxN) {
+    const size_t pipe_smem =
+        11 * static_cast<size_t>(n) * sizeof(double) + ((2 * static_cast<size_t>(n) + 7) & ~size_t{7});
+    set_smem(reinterpret_cast<const void*>(tri_inviter_pipe_kernel), pipe_smem);
+    hipLaunchKernelGGL(tri_inviter_pipe_kernel, dim3(n), dim3(256), pipe_smem, st, d, ez, bs, be, raw, cstart, ncl,
+                       w.scal, n, w.Z, w.flag);
+  } else {
+    const size_t inv_smem = 7 * static_cast<size_t>(n) * sizeof(double) + ((static_cast<size_t>(n) + 7) & ~size_t{7});
+    set_smem(reinterpret_cast<const void*>(tri_inviter_kernel), inv_smem);
+    hipLaunchKernelGGL(tri_inviter_kernel, dim3(n), dim3(256), inv_smem, st, d, ez, bs, be, raw, cstart, ncl,
+                       w.scal, n, w.Z, w.flag);
+  }
   hipLaunchKernelGGL(tri_rank_kernel, dim3(nblk(n, 256)), dim3(256), static_cast<size_t>(n) * sizeof(double), st,
                      raw, n, lam, perm, w.flag);
   XLS_LAUNCH_CHECK("tridiagonal eigensolver");

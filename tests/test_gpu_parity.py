@@ -305,8 +305,9 @@ def test_residual_fp64(system):
 
 # 128, 129: the one-workgroup tail alone, then one step before it; 480: the
 # register-only steps and the tail; 700: all three step kernels; 31/32 and
-# 900/901: either side of the compact-WY back-transform's range
-@pytest.mark.parametrize("n", [1, 2, 7, 20, 31, 32, 37, 100, 128, 129, 161, 480, 700, 900, 901, 1500])
+# 900/901: either side of the compact-WY back-transform's range; 1900: the
+# inverse iteration without the overlapped factorisation (n > 1800)
+@pytest.mark.parametrize("n", [1, 2, 7, 20, 31, 32, 37, 100, 128, 129, 161, 480, 700, 900, 901, 1500, 1900])
 def test_dense_geneig(n):
     case(f"dense n={n}")
     rng = np.random.default_rng(n)

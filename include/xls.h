@@ -98,9 +98,10 @@ typedef struct xls_subdomain_s* xls_subdomain_t;
  * model's prediction, xls_mlp_predict) and for a0 the rigorous lower bound
  * min V + sum of the negative projector coefficients (-1/2 Lap is positive
  * semi-definite), so no Lanczos run is needed; with fallback_tol > 0, if the
- * largest gated residual after max_iter iterations exceeds fallback_tol the
- * call restarts from the same start block with Lanczos bounds and
- * fallback_degree (<= 0: degree).  Later iterations of the same call use
+ * largest gated residual after the run exceeds fallback_tol (a NaN residual
+ * counts as exceeding it) or an iteration finds M_s not positive definite,
+ * the call restarts from the same start block with Lanczos bounds and
+ * fallback_degree (<= 0: degree).  lanczos_k > 60 is INVALID_ARG.  Later iterations of the same call use
  * a0 = lambda_1 and lam_cut = lambda_ns of the previous iteration, lam_max
  * unchanged. */
 typedef struct {
@@ -230,12 +231,8 @@ int xls_split_bf16(const float* a, uint16_t* hi, uint16_t* lo, int64_t n);
  * tile does not fit (LDS, registers, halo budget) or nv is not 0, 1 or 2. */
 int xls_subdomain_tune(xls_subdomain_t s, int32_t prec, int32_t block, int32_t ty, int32_t tz, int32_t nv);
 
-/* Per-stage device time of the handle's last xls_chefsi_step, from HIP events
- * on the handle's stream when profiling is on (xls_set_profiling(1)).
- * ms[0] filter (all m sweeps), ms[1] H*Psi_f, ms[2] projection GEMMs,
- * ms[3] dense FP64, ms[4] rotation, ms[5] residual, ms[6] total, ms[7] sum of
- * the fused-filter stencil kernels alone (events around each launch);
- * counts[0] filter launches.  Returns the number of values written. */
+/* Profiling switch (process-wide, default off): with 1, xls_chefsi_step
+ * records HIP events around its stages and every fused-filter launch. */
 int xls_set_profiling(int32_t on);
 
 /* Graph replay of fixed launch sequences (default on): after one eager call
@@ -243,6 +240,13 @@ int xls_set_profiling(int32_t on);
  * into a hipGraph and replayed.  Results are identical either way; 0 launches
  * everything eagerly (tests compare the two). */
 int xls_set_graphs(int32_t on);
+
+/* Per-stage device time of the handle's last xls_chefsi_step, from HIP events
+ * on the handle's stream when profiling is on (xls_set_profiling(1)).
+ * ms[0] filter (all m sweeps), ms[1] H*Psi_f, ms[2] projection GEMMs,
+ * ms[3] dense FP64, ms[4] rotation, ms[5] residual, ms[6] total, ms[7] sum of
+ * the fused-filter stencil kernels alone (events around each launch);
+ * counts[0] filter launches.  Returns the number of values written. */
 int xls_get_stage_times(xls_subdomain_t s, double* ms, int64_t* counts, int32_t cap);
 
 /* Device time of the projection and rotation GEMMs (steps (2) and (4) of
@@ -281,7 +285,30 @@ int xls_subdomain_counters(xls_subdomain_t s, int64_t* out, int32_t cap);
  * xls_mlp_set_norm: input standardisation (x - in_mean)/in_std and output
  *   de-standardisation y * out_std + out_mean used by xls_mlp_predict.
  * xls_mlp_predict: bfloat16 inference on B feature rows (f64[B x in]) ->
- *   out f64[B x outputs]. */
+ *   out f64[B x outputs].
+ * xls_mlp_fit: the whole training step of the learned bounds on raw data:
+ *   F f64[n x in] and T f64[n x outputs] (row-major, finite) are standardised
+ *   on the device (per column: mean and population standard deviation, 1 for
+ *   a constant column), the model is trained as by xls_mlp_train on the
+ *   standardised rows, keeps that standardisation for xls_mlp_predict, and
+ *   records its RMS error per output on the n training rows with bfloat16
+ *   inference (xls_mlp_train_rms).  minibatches as for xls_mlp_train:
+ *   offsets[0] must be 0 and offsets must increase strictly; INVALID_ARG
+ *   otherwise.
+ * xls_mlp_train_rms: the per-output RMS error of the last fit (cap values at
+ *   most); STATE before a fit.  Returns the number written.
+ * xls_mlp_bounds: the bounds a learned CheFSI run takes for B subdomains'
+ *   features (3-output models only, after a fit; STATE otherwise).  With the
+ *   prediction (p_max, p_cut, p_deg): degree = round-half-even(p_deg)
+ *   clamped to [16, 32]; p_cut is replaced by p_max/2 unless p_cut < p_max;
+ *   lam_cut = p_cut + 3 rms_cut (a cutoff below the true lambda_ns damps
+ *   wanted states, and the plain method's later cutoffs, Ritz values, are
+ *   upper bounds for that reason); lam_max = lam_cut + 1.03 (p_max - lam_cut)
+ *   (an estimate below the top of the spectrum lets the Chebyshev polynomial
+ *   grow there), or lam_cut + 0.03|lam_cut| + 1e-3 Ha when that is not above
+ *   lam_cut.  Outputs are host arrays of B values.
+ * xls_learned_safe_bounds: the same margins for given (lam_max, lam_cut)
+ *   pairs with cut margin cut_margin >= 0 (the labels' bounds use 0). */
 typedef struct xls_mlp_s* xls_mlp_t;
 int xls_mlp_create(int32_t nsizes, const int32_t* sizes, const float* params, xls_mlp_t* out);
 void xls_mlp_destroy(xls_mlp_t m);
@@ -294,6 +321,13 @@ int xls_mlp_gradient(xls_mlp_t m, const float* X, const float* T, int32_t B, flo
 int xls_mlp_train(xls_mlp_t m, const float* X, const float* T, int32_t n, const int32_t* idx,
                   const int32_t* offsets, int32_t nsteps, float lr, float* losses);
 int xls_mlp_predict(xls_mlp_t m, const double* features, int32_t B, double* out);
+int xls_mlp_fit(xls_mlp_t m, const double* F, const double* T, int32_t n, const int32_t* idx,
+                const int32_t* offsets, int32_t nsteps, float lr, float* losses);
+int xls_mlp_train_rms(xls_mlp_t m, double* rms, int32_t cap);
+int xls_mlp_bounds(xls_mlp_t m, const double* features, int32_t B, double* lam_max, double* lam_cut,
+                   int32_t* degree);
+int xls_learned_safe_bounds(int32_t B, const double* lam_max, const double* lam_cut, double cut_margin,
+                            double* lm_out, double* lc_out);
 /* Features of a subdomain (f64[64], zero-padded): [0,32) histogram of V over
  * [min V, max V] (fractions, numpy.histogram bin rule), then atom count, n[0],
  * n[1], n[2], h, buffer width min(core_lo)*h, min V, max V, mean V, std V, ns,
@@ -313,9 +347,14 @@ int xls_subdomain_features(xls_subdomain_t s, double* f);
  *
  * xls_batch_create: descs[n] as for xls_subdomain_create (all with the same
  *   filter_prec; their stream fields are ignored).  Host arrays are copied.
- * xls_batch_chefsi: per_sub[n] parameters (degree <= 256; LEARNED without
- *   the fallback, fallback_tol must be 0); runs each subdomain until its gated residual is <=
- *   resid_tol, its max_iter is reached or its bounds degenerate.  Outputs are
+ * xls_batch_chefsi: per_sub[n] parameters (degree <= 256, lanczos_k <= 60);
+ *   runs each subdomain until its gated residual is <= resid_tol, its
+ *   max_iter is reached or its bounds degenerate.  LEARNED subdomains with
+ *   fallback_tol > 0 whose run ends with the gated residual above
+ *   fallback_tol (NaN included) or with M_s not positive definite are then
+ *   restarted from their start blocks with Lanczos bounds and
+ *   fallback_degree in a second batched pass (xls_subdomain_counters of the
+ *   subdomain's handle reports the fallback; iters counts both runs).  Outputs are
  *   concatenated in subdomain order: ritz_concat and resid_concat hold
  *   sum(ns_i) values; iters[n] and status[n] may be NULL.  status[i] is
  *   XLS_OK or XLS_ERR_NOT_SPD (that subdomain's block is then undefined); with

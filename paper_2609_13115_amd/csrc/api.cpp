@@ -173,9 +173,23 @@ void residual_block(xls_subdomain_s* s, const double* lam_dev, double* resid_dev
                              lam_dev, s->partial, resid_dev, s->st, cfg);
 }
 
+int lanczos_steps(const xls_subdomain_s* s, int k) {
+  k = k > 0 ? std::min(k, kMaxLanczos) : 20;
+  return static_cast<int>(std::min<int64_t>(k, s->nd));
+}
+
+double gated_max(const double* r, int gate) {
+  double mx = 0.0;
+  for (int k = 0; k < gate; ++k) {
+    if (std::isnan(r[k])) return r[k];
+    mx = std::max(mx, r[k]);
+  }
+  return mx;
+}
+
 template <typename TS>
 void lanczos_run(xls_subdomain_s* s, int k) {
-  k = static_cast<int>(std::min<int64_t>(k, s->nd));
+  k = lanczos_steps(s, k);
   if (!s->lz || s->lz_cols < k + 2) {
     dfree(s->lz);
     s->lz = nullptr;
@@ -312,15 +326,15 @@ void dense_stage(xls_subdomain_s* s) {
   }
 }
 
-// CheFSI iterations from the handle's current block with first-iteration
-// bounds (a0, lc, lmax); returns the iterations run.
+// Up to max_iter CheFSI iterations from the handle's current block with
+// first-iteration bounds (a0, lc, lmax); total is advanced by the iterations
+// run (also when an iteration throws NOT_SPD).
 template <typename TS>
-int chefsi_loop(xls_subdomain_s* s, const xls_chefsi_params_t* p, int gprec, int gate, int degree, double a0,
-                double lc, double lmax, std::vector<double>& hl, std::vector<double>& hr) {
+void chefsi_loop(xls_subdomain_s* s, const xls_chefsi_params_t* p, int gprec, int gate, int degree, double a0,
+                 double lc, double lmax, std::vector<double>& hl, std::vector<double>& hr, int& total) {
   const int ns = s->ns;
-  int it = 0;
   double prev_resid = HUGE_VAL;
-  for (; it < p->max_iter;) {
+  for (int it = 0; it < p->max_iter;) {
     StageTimer tm(profiling_on(), s->st);
     tm.mark();
     filter_block<TS>(s, degree, a0, lc, lmax);
@@ -349,30 +363,32 @@ int chefsi_loop(xls_subdomain_s* s, const xls_chefsi_params_t* p, int gprec, int
     XLS_HIP(hipMemcpyAsync(hr.data(), s->resid_dev, ns * 8, hipMemcpyDeviceToHost, s->st));
     XLS_HIP(hipMemcpyAsync(&spd_flag, s->dw.flag, 4, hipMemcpyDeviceToHost, s->st));
     XLS_HIP(hipStreamSynchronize(s->st));
-    if (spd_flag) fail(XLS_ERR_NOT_SPD, "overlap matrix M_s is not positive definite");
+    if (spd_flag) {
+      ++total;
+      fail(XLS_ERR_NOT_SPD, "overlap matrix M_s is not positive definite");
+    }
     if (profiling_on()) {
       for (int k = 0; k < 6; ++k) s->stage_ms[k] += tm.ms(k, k + 1);
       s->stage_ms[6] += tm.ms(0, 6);
     }
     ++it;
+    ++total;
     s->ritz = hl;
     s->have_ritz = true;
     a0 = hl[0];
     lc = hl[ns - 1];
-    double mx = 0;
-    for (int k = 0; k < gate; ++k) mx = std::max(mx, hr[k]);
+    const double mx = gated_max(hr.data(), gate);
     prev_resid = mx;
     if (!(a0 < lc && lc < lmax)) break;  // degenerate bounds: stop with what we have
     if (p->resid_tol > 0 && mx <= p->resid_tol) break;
   }
-  return it;
 }
 
 template <typename TS>
 void lanczos_first_bounds(xls_subdomain_s* s, const xls_chefsi_params_t* p, double& a0, double& lc,
                           double& lmax) {
-  const int k = p->lanczos_k > 0 ? p->lanczos_k : 20;
-  if (!s->have_lanczos || s->lz_k != k) lanczos_run<TS>(s, std::min(k, 60));
+  const int k = lanczos_steps(s, p->lanczos_k);
+  if (!s->have_lanczos || s->lz_k != k) lanczos_run<TS>(s, k);
   a0 = s->lz_lo;
   lmax = s->lz_up;
   lc = a0 + 0.1 * (lmax - a0);
@@ -382,6 +398,9 @@ template <typename TS>
 int chefsi_impl(xls_subdomain_s* s, const xls_chefsi_params_t* p, double* ritz, double* resid,
                 int32_t* iters_done) {
   if (p->degree < 1 || p->max_iter < 1) fail(XLS_ERR_INVALID_ARG, "degree and max_iter must be >= 1");
+  if (p->lanczos_k > kMaxLanczos) fail(XLS_ERR_INVALID_ARG, "lanczos_k must be <= 60");
+  if (p->bounds_mode == XLS_BOUNDS_LEARNED && (!(p->fallback_tol >= 0) || p->fallback_degree > 4096))
+    fail(XLS_ERR_INVALID_ARG, "fallback_tol must be >= 0");
   const int gprec = p->gemm_prec;
   if (gprec < XLS_PREC_FP64 || gprec > XLS_PREC_BF16X3) fail(XLS_ERR_INVALID_ARG, "bad gemm_prec");
   if (std::is_same<TS, double>::value && gprec != XLS_PREC_FP64)
@@ -419,18 +438,24 @@ int chefsi_impl(xls_subdomain_s* s, const xls_chefsi_params_t* p, double* ritz, 
   s->stage_ms.assign(8, 0.0);
   s->filter_launches = 0;
   s->filter_kernel_ms = 0.0;
-  int it = chefsi_loop<TS>(s, p, gprec, gate, p->degree, a0, lc, lmax, hl, hr);
-  if (fallback) {
-    double mx = 0;
-    for (int k = 0; k < gate; ++k) mx = std::max(mx, hr[k]);
-    if (!(mx <= p->fallback_tol)) {
-      XLS_HIP(hipMemcpyAsync(B<TS>(s, cur0), s->backup, bbytes, hipMemcpyDeviceToDevice, s->st));
-      s->cur = cur0;
-      lanczos_first_bounds<TS>(s, p, a0, lc, lmax);
-      const int deg = p->fallback_degree > 0 ? p->fallback_degree : p->degree;
-      it += chefsi_loop<TS>(s, p, gprec, gate, deg, a0, lc, lmax, hl, hr);
-      s->last_fallback = 1;
-    }
+  int it = 0;
+  bool miss = false;
+  try {
+    chefsi_loop<TS>(s, p, gprec, gate, p->degree, a0, lc, lmax, hl, hr, it);
+  } catch (const Error& e) {
+    // predicted bounds that miss the top of the spectrum amplify it until
+    // M_s is numerically singular: that is a miss of the learned bounds,
+    // not a failure of the call, when the fallback is on
+    if (!fallback || e.code != XLS_ERR_NOT_SPD) throw;
+    miss = true;
+  }
+  if (fallback && (miss || !(gated_max(hr.data(), gate) <= p->fallback_tol))) {
+    XLS_HIP(hipMemcpyAsync(B<TS>(s, cur0), s->backup, bbytes, hipMemcpyDeviceToDevice, s->st));
+    s->cur = cur0;
+    lanczos_first_bounds<TS>(s, p, a0, lc, lmax);
+    const int deg = p->fallback_degree > 0 ? p->fallback_degree : p->degree;
+    chefsi_loop<TS>(s, p, gprec, gate, deg, a0, lc, lmax, hl, hr, it);
+    s->last_fallback = 1;
   }
   s->last_iters = it;
   std::memcpy(ritz, hl.data(), ns * 8);

@@ -68,9 +68,15 @@ struct SubState {
   int degree = 0, max_iter = 0, gate = 0, gprec = XLS_PREC_FP64;
   int pprec = XLS_PREC_FP64;  // projection and rotation precision this iteration (polish_prec)
   double resid_tol = 0.0;
-  int iters = 0;
+  int iters = 0;        // iterations of the current run (bounded by max_iter)
+  int total_iters = 0;  // including a fallback run
   int status = XLS_OK;
   bool active = false;
+  // learned bounds with the Lanczos fallback
+  double fb_tol = 0.0;  // > 0: fallback on
+  int fb_degree = 0;
+  int lanczos_k = 0;
+  int cur0 = 0;         // block parity at the start (the backup's contents)
 };
 
 }  // namespace
@@ -260,6 +266,20 @@ void run_iteration(xls_batch_s* b, const std::vector<int>& act, bool use_graph) 
 }
 
 template <typename TS>
+void batch_loop(xls_batch_s* b, int use_graph, std::vector<std::vector<double>>& hl,
+                std::vector<std::vector<double>>& hr);
+
+// First-iteration Lanczos bounds of a subdomain (cached per handle and k).
+template <typename TS>
+void lanczos_bounds_of(xls_subdomain_s* s, int k_req, double& a0, double& lc, double& lmax) {
+  const int k = lanczos_steps(s, k_req);
+  if (!s->have_lanczos || s->lz_k != k) lanczos_run<TS>(s, k);
+  a0 = s->lz_lo;
+  lmax = s->lz_up;
+  lc = a0 + 0.1 * (lmax - a0);
+}
+
+template <typename TS>
 void batch_chefsi(xls_batch_s* b, const xls_chefsi_params_t* P, int use_graph) {
   b->have_fermi = false;  // new blocks: a stored Fermi level no longer applies
   const int n = b->n;
@@ -269,6 +289,9 @@ void batch_chefsi(xls_batch_s* b, const xls_chefsi_params_t* P, int use_graph) {
     SubState& ss = b->st[i];
     if (p.degree < 1 || p.degree > kMaxDegree || p.max_iter < 1)
       fail(XLS_ERR_INVALID_ARG, "degree must be in [1, 256] and max_iter >= 1");
+    if (p.lanczos_k > kMaxLanczos) fail(XLS_ERR_INVALID_ARG, "lanczos_k must be <= 60");
+    if (p.bounds_mode == XLS_BOUNDS_LEARNED && p.fallback_tol > 0 && p.fallback_degree > kMaxDegree)
+      fail(XLS_ERR_INVALID_ARG, "fallback_degree must be <= 256");
     if (p.gemm_prec < XLS_PREC_FP64 || p.gemm_prec > XLS_PREC_BF16X3) fail(XLS_ERR_INVALID_ARG, "bad gemm_prec");
     if (std::is_same<TS, double>::value && p.gemm_prec != XLS_PREC_FP64)
       fail(XLS_ERR_INVALID_ARG, "FP64 batches run FP64 GEMMs");
@@ -278,13 +301,9 @@ void batch_chefsi(xls_batch_s* b, const xls_chefsi_params_t* P, int use_graph) {
       lc = p.lam_cut;
       lmax = p.lam_max;
     } else if (p.bounds_mode == XLS_BOUNDS_LANCZOS) {
-      const int k = p.lanczos_k > 0 ? p.lanczos_k : 20;
-      if (!s->have_lanczos || s->lz_k != k) lanczos_run<TS>(s, std::min(k, 60));
-      a0 = s->lz_lo;
-      lmax = s->lz_up;
-      lc = a0 + 0.1 * (lmax - a0);
+      lanczos_bounds_of<TS>(s, p.lanczos_k, a0, lc, lmax);
     } else if (p.bounds_mode == XLS_BOUNDS_LEARNED) {
-      if (p.fallback_tol > 0) fail(XLS_ERR_INVALID_ARG, "batches do not run the Lanczos fallback");
+      if (!(p.fallback_tol >= 0)) fail(XLS_ERR_INVALID_ARG, "fallback_tol must be >= 0");
       lmax = p.lam_max;
       lc = p.lam_cut;
       a0 = std::min(s->a0_bound, lc - 1e-3 * std::fabs(lmax - lc));
@@ -302,11 +321,21 @@ void batch_chefsi(xls_batch_s* b, const xls_chefsi_params_t* P, int use_graph) {
     ss.gate = p.n_gate > 0 ? std::min(p.n_gate, s->ns)
                            : std::max(1, static_cast<int>(std::floor(s->ns / 1.1 + 1e-9)));
     ss.iters = 0;
+    ss.total_iters = 0;
     ss.status = XLS_OK;
+    ss.fb_tol = p.bounds_mode == XLS_BOUNDS_LEARNED ? p.fallback_tol : 0.0;
+    ss.fb_degree = p.fallback_degree > 0 ? p.fallback_degree : p.degree;
+    ss.lanczos_k = p.lanczos_k;
+    ss.cur0 = s->cur;
     s->happly = 0;
     s->last_fallback = 0;
     s->last_iters = 0;
     ss.active = true;
+    if (ss.fb_tol > 0) {  // the start block, for a restart with Lanczos bounds
+      if (!s->backup) s->backup = dalloc<TS>(static_cast<size_t>(s->ld) * s->ns);
+      XLS_HIP(hipMemcpyAsync(s->backup, B<TS>(s, s->cur), static_cast<size_t>(s->ld) * s->ns * sizeof(TS),
+                             hipMemcpyDeviceToDevice, s->st));
+    }
     launch_filter_coef(nullptr, s->ns, a0, lc, lmax, p.degree, b->coef[i], b->flags + i, s->st);
   }
   for (auto* s : b->subs) XLS_HIP(hipStreamSynchronize(s->st));
@@ -315,9 +344,46 @@ void batch_chefsi(xls_batch_s* b, const xls_chefsi_params_t* P, int use_graph) {
     hl[i].assign(b->subs[i]->ns, 0.0);
     hr[i].assign(b->subs[i]->ns, 0.0);
   }
-  std::vector<int32_t> hflag(n), hspd(n);
   b->iterations = 0;
   b->iter_ms = 0.0;
+  batch_loop<TS>(b, use_graph, hl, hr);
+  // Learned bounds that missed (NOT_SPD, or the gated residual above the
+  // fallback tolerance): restart those subdomains from their start blocks
+  // with Lanczos bounds and the fallback degree, in a second pass.
+  bool any = false;
+  for (int i = 0; i < n; ++i) {
+    SubState& ss = b->st[i];
+    xls_subdomain_s* s = b->subs[i];
+    if (!(ss.fb_tol > 0)) continue;
+    if (ss.status == XLS_OK && gated_max(hr[i].data(), ss.gate) <= ss.fb_tol) continue;
+    XLS_HIP(hipMemcpyAsync(B<TS>(s, ss.cur0), s->backup, static_cast<size_t>(s->ld) * s->ns * sizeof(TS),
+                           hipMemcpyDeviceToDevice, s->st));
+    s->cur = ss.cur0;
+    double a0, lc, lmax;
+    lanczos_bounds_of<TS>(s, ss.lanczos_k, a0, lc, lmax);
+    ss.lmax = lmax;
+    ss.degree = ss.fb_degree;
+    ss.pprec = polish_prec(ss.gprec, HUGE_VAL);
+    ss.iters = 0;
+    ss.status = XLS_OK;
+    ss.active = true;
+    s->last_fallback = 1;
+    launch_filter_coef(nullptr, s->ns, a0, lc, lmax, ss.degree, b->coef[i], b->flags + i, s->st);
+    any = true;
+  }
+  if (any) {
+    for (auto* s : b->subs) XLS_HIP(hipStreamSynchronize(s->st));
+    batch_loop<TS>(b, use_graph, hl, hr);
+  }
+}
+
+// Batch iterations until no subdomain is active; hl, hr receive each
+// subdomain's last Ritz values and residuals.
+template <typename TS>
+void batch_loop(xls_batch_s* b, int use_graph, std::vector<std::vector<double>>& hl,
+                std::vector<std::vector<double>>& hr) {
+  const int n = b->n;
+  std::vector<int32_t> hflag(n), hspd(n);
   for (;;) {
     std::vector<int> act;
     for (int i = 0; i < n; ++i)
@@ -342,7 +408,8 @@ void batch_chefsi(xls_batch_s* b, const xls_chefsi_params_t* P, int use_graph) {
       SubState& ss = b->st[i];
       s->cur = (s->cur + ss.degree + 1) & 1;
       ++ss.iters;
-      s->last_iters = ss.iters;
+      ++ss.total_iters;
+      s->last_iters = ss.total_iters;
       s->happly += static_cast<int64_t>(ss.degree + 1) * s->ns;  // filter + residual (H Psi_f counted by apply_H)
       s->ritz = hl[i];
       s->have_ritz = true;
@@ -355,8 +422,7 @@ void batch_chefsi(xls_batch_s* b, const xls_chefsi_params_t* P, int use_graph) {
         ss.active = false;
         continue;
       }
-      double mx = 0;
-      for (int k = 0; k < ss.gate; ++k) mx = std::max(mx, hr[i][k]);
+      const double mx = gated_max(hr[i].data(), ss.gate);
       ss.pprec = polish_prec(ss.gprec, mx);
       if (ss.resid_tol > 0 && mx <= ss.resid_tol) ss.active = false;
       if (ss.iters >= ss.max_iter) ss.active = false;
@@ -560,7 +626,7 @@ int xls_batch_chefsi(xls_batch_t b, const xls_chefsi_params_t* per_sub, double* 
       std::memcpy(ritz_concat + off, s->ritz.data(), s->ns * 8);
       XLS_HIP(hipMemcpy(resid_concat + off, s->resid_dev, s->ns * 8, hipMemcpyDeviceToHost));
       off += s->ns;
-      if (iters) iters[i] = b->st[i].iters;
+      if (iters) iters[i] = b->st[i].total_iters;
       if (status) status[i] = b->st[i].status;
       if (b->st[i].status != XLS_OK) worst = b->st[i].status;
     }

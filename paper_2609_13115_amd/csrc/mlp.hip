@@ -235,6 +235,99 @@ __global__ __launch_bounds__(1024) void vstats_kernel(const double* __restrict__
   if (t < 32) out[4 + t] = (delta > 0.0) ? static_cast<double>(hist[t]) : (t == 0 ? static_cast<double>(n) : 0.0);
 }
 
+// Column statistics of a row-major n x c FP64 matrix, one workgroup per
+// column: mean and population standard deviation (two passes; per-thread
+// strided partial sums, then a fixed tree).  A column with zero spread gets
+// scale 1, so standardising it yields zeros.
+__global__ __launch_bounds__(256) void col_stats_kernel(const double* __restrict__ X, int n, int c,
+                                                        double* __restrict__ mean, double* __restrict__ scale) {
+  __shared__ double red[256];
+  const int col = blockIdx.x, t = threadIdx.x;
+  double acc = 0.0;
+  for (int i = t; i < n; i += 256) acc += X[static_cast<int64_t>(i) * c + col];
+  red[t] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) red[t] += red[t + w];
+    __syncthreads();
+  }
+  const double mu = red[0] / static_cast<double>(n);
+  __syncthreads();
+  acc = 0.0;
+  for (int i = t; i < n; i += 256) {
+    const double d = X[static_cast<int64_t>(i) * c + col] - mu;
+    acc = fma(d, d, acc);
+  }
+  red[t] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) red[t] += red[t + w];
+    __syncthreads();
+  }
+  if (t == 0) {
+    const double sd = sqrt(red[0] / static_cast<double>(n));
+    mean[col] = mu;
+    scale[col] = sd > 0.0 ? sd : 1.0;
+  }
+}
+
+// Xs[i, j] = FP32((X[i, j] - mean[j]) / scale[j]).
+__global__ void standardise_kernel(const double* __restrict__ X, int64_t n, int c, const double* __restrict__ mean,
+                                   const double* __restrict__ scale, float* __restrict__ Xs) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= n * c) return;
+  const int j = static_cast<int>(e % c);
+  Xs[e] = static_cast<float>((X[e] - mean[j]) / scale[j]);
+}
+
+// rms[j] = sqrt(mean over rows (P[i, j] - T[i, j])^2), one workgroup per column.
+__global__ __launch_bounds__(256) void rms_err_kernel(const double* __restrict__ P, const double* __restrict__ T,
+                                                      int n, int c, double* __restrict__ rms) {
+  __shared__ double red[256];
+  const int col = blockIdx.x, t = threadIdx.x;
+  double acc = 0.0;
+  for (int i = t; i < n; i += 256) {
+    const int64_t e = static_cast<int64_t>(i) * c + col;
+    const double d = P[e] - T[e];
+    acc = fma(d, d, acc);
+  }
+  red[t] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) red[t] += red[t + w];
+    __syncthreads();
+  }
+  if (t == 0) rms[col] = sqrt(red[0] / static_cast<double>(n));
+}
+
+// The learned-bounds policy applied to raw predictions P[b] = (lambda_max,
+// lambda_cut, degree) (learned_policy on the host states the same rule).
+__device__ __host__ inline void learned_policy(double pm, double pc, double pd, double cut_margin, double* lm,
+                                               double* lc, int32_t* m) {
+  double d = rint(pd);
+  d = d < kLearnedDegMin ? kLearnedDegMin : (d > kLearnedDegMax ? kLearnedDegMax : d);
+  if (!(pc < pm)) pc = 0.5 * pm;
+  const double c = pc + cut_margin;
+  double x = c + kLearnedLmaxMargin * (pm - c);
+  if (!(c < x)) x = c + (kLearnedLmaxMargin - 1.0) * fabs(c) + 1e-3;
+  *lm = x;
+  *lc = c;
+  *m = static_cast<int32_t>(d);
+}
+
+__global__ void policy_kernel(const double* __restrict__ P, int B, int fo, double cut_margin,
+                              double* __restrict__ out) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  const double* p = P + static_cast<int64_t>(b) * fo;
+  double lm, lc;
+  int32_t m;
+  learned_policy(p[0], p[1], p[2], cut_margin, &lm, &lc, &m);
+  out[3 * b] = lm;
+  out[3 * b + 1] = lc;
+  out[3 * b + 2] = static_cast<double>(m);
+}
+
 void launch_check(const char* what) { XLS_LAUNCH_CHECK(what); }
 
 }  // namespace
@@ -258,6 +351,7 @@ struct xls_mlp_s {
   int fcap = 0;
   std::vector<float> in_mean, in_std;
   std::vector<double> out_mean, out_std;
+  std::vector<double> train_rms;  // per output, on the training rows (xls_mlp_fit)
   hipStream_t st = nullptr;
 
   ~xls_mlp_s() {
@@ -296,6 +390,16 @@ struct xls_mlp_s {
     dB = dalloc<float>(static_cast<size_t>(B) * maxw);
     idx = dalloc<int32_t>(B);
     cap = B;
+  }
+  void ensure_pred(int B) {
+    if (B <= fcap) return;
+    dfree(dF);
+    dfree(dOut);
+    dF = nullptr;
+    dOut = nullptr;
+    dF = dalloc<double>(static_cast<size_t>(B) * d.size[0]);
+    dOut = dalloc<double>(static_cast<size_t>(B) * d.size[d.nl]);
+    fcap = B;
   }
 };
 
@@ -350,6 +454,91 @@ void adam(xls_mlp_s* m, float lr) {
 
 void upload_f(float* dst, const float* src, int64_t n, hipStream_t st) {
   XLS_HIP(hipMemcpyAsync(dst, src, n * sizeof(float), hipMemcpyHostToDevice, st));
+}
+
+// Device buffer freed on scope exit (after the owner synchronised its stream).
+template <typename T>
+struct DevBuf {
+  T* p = nullptr;
+  explicit DevBuf(size_t n) : p(dalloc<T>(n)) {}
+  ~DevBuf() { dfree(p); }
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+};
+
+// Validates minibatches idx[offsets[s] .. offsets[s+1]) of n rows: offsets
+// start at 0 and increase strictly, every index is a row.  Returns the
+// largest minibatch.
+int check_minibatches(int n, const int32_t* idx, const int32_t* offsets, int nsteps) {
+  if (offsets[0] != 0) fail(XLS_ERR_INVALID_ARG, "offsets[0] must be 0");
+  int maxb = 1;
+  for (int s = 0; s < nsteps; ++s) {
+    const int b = offsets[s + 1] - offsets[s];
+    if (b < 1) fail(XLS_ERR_INVALID_ARG, "empty minibatch (offsets must increase)");
+    maxb = std::max(maxb, b);
+  }
+  for (int64_t k = 0; k < offsets[nsteps]; ++k)
+    if (idx[k] < 0 || idx[k] >= n) fail(XLS_ERR_INVALID_ARG, "minibatch index out of range");
+  return maxb;
+}
+
+// Adam over the minibatches of device rows X (n x in, FP32) and T; losses
+// (host, may be NULL) receives each minibatch's loss before its update.
+// Synchronises the model's stream before returning.
+void train_steps(xls_mlp_s* m, const float* dX, const float* dT, int maxb, const int32_t* idx,
+                 const int32_t* offsets, int nsteps, float lr, float* losses) {
+  const int F = m->d.size[0], O = m->d.size[m->d.nl];
+  DevBuf<int32_t> dI(std::max<int64_t>(1, offsets[nsteps]));
+  DevBuf<float> dL(std::max(1, nsteps));
+  try {
+    m->ensure_rows(maxb);
+    XLS_HIP(hipMemcpyAsync(dI.p, idx, offsets[nsteps] * sizeof(int32_t), hipMemcpyHostToDevice, m->st));
+    for (int s = 0; s < nsteps; ++s) {
+      const int B = offsets[s + 1] - offsets[s];
+      const int32_t* ib = dI.p + offsets[s];
+      hipLaunchKernelGGL(gather_rows_kernel, dim3((B * F + 255) / 256), dim3(256), 0, m->st, dX, F, ib, B, m->Xb);
+      hipLaunchKernelGGL(gather_rows_kernel, dim3((B * O + 255) / 256), dim3(256), 0, m->st, dT, O, ib, B, m->Tb);
+      forward(m, m->Xb, B);
+      backward(m, m->Xb, m->Tb, B);
+      XLS_HIP(hipMemcpyAsync(dL.p + s, m->loss, sizeof(float), hipMemcpyDeviceToDevice, m->st));
+      adam(m, lr);
+    }
+    if (losses && nsteps > 0)
+      XLS_HIP(hipMemcpyAsync(losses, dL.p, nsteps * sizeof(float), hipMemcpyDeviceToHost, m->st));
+    XLS_HIP(hipStreamSynchronize(m->st));
+  } catch (...) {
+    (void)hipStreamSynchronize(m->st);
+    throw;
+  }
+}
+
+// bfloat16 inference of B device feature rows into device out (B x outputs),
+// with the model's standardisation.
+void infer(xls_mlp_s* m, const double* dF, int B, double* dOut) {
+  const Dims& d = m->d;
+  if (m->bf16_stale) {
+    hipLaunchKernelGGL(to_bf16_kernel, dim3(static_cast<unsigned>((d.nparam + 255) / 256)), dim3(256), 0, m->st,
+                       m->P, m->Wb, d.nparam);
+    launch_check("to_bf16_kernel");
+    m->bf16_stale = false;
+  }
+  InferArgs a{};
+  a.nl = d.nl;
+  for (int l = 0; l <= d.nl; ++l) a.size[l] = d.size[l];
+  for (int l = 0; l < d.nl; ++l) {
+    a.woff[l] = d.woff[l];
+    a.boff[l] = d.boff[l];
+  }
+  for (int i = 0; i < d.size[0]; ++i) {
+    a.in_mean[i] = m->in_mean[i];
+    a.in_scale[i] = 1.0f / m->in_std[i];
+  }
+  for (int i = 0; i < d.size[d.nl]; ++i) {
+    a.out_mean[i] = m->out_mean[i];
+    a.out_std[i] = m->out_std[i];
+  }
+  hipLaunchKernelGGL(infer_bf16_kernel, dim3(B), dim3(256), 0, m->st, dF, B, m->Wb, m->P, a, dOut);
+  launch_check("infer_bf16_kernel");
 }
 
 }  // namespace
@@ -479,52 +668,112 @@ int xls_mlp_train(xls_mlp_t m, const float* X, const float* T, int32_t n, const 
   return guarded([&]() -> int {
     if (!m || !X || !T || !idx || !offsets || n < 1 || nsteps < 0 || !(lr > 0.0f))
       fail(XLS_ERR_INVALID_ARG, "bad argument");
-    int maxb = 1;
-    for (int s = 0; s < nsteps; ++s) {
-      const int b = offsets[s + 1] - offsets[s];
-      if (b < 1) fail(XLS_ERR_INVALID_ARG, "empty minibatch");
-      maxb = std::max(maxb, b);
-    }
-    for (int64_t k = 0; k < offsets[nsteps]; ++k)
-      if (idx[k] < 0 || idx[k] >= n) fail(XLS_ERR_INVALID_ARG, "minibatch index out of range");
+    const int maxb = check_minibatches(n, idx, offsets, nsteps);
     const int F = m->d.size[0], O = m->d.size[m->d.nl];
-    float* dX = dalloc<float>(static_cast<size_t>(n) * F);
-    float* dT = nullptr;
-    int32_t* dI = nullptr;
-    float* dL = nullptr;
-    try {
-      dT = dalloc<float>(static_cast<size_t>(n) * O);
-      dI = dalloc<int32_t>(std::max<int64_t>(1, offsets[nsteps]));
-      dL = dalloc<float>(std::max(1, nsteps));
-      m->ensure_rows(maxb);
-      upload_f(dX, X, static_cast<int64_t>(n) * F, m->st);
-      upload_f(dT, T, static_cast<int64_t>(n) * O, m->st);
-      XLS_HIP(hipMemcpyAsync(dI, idx, offsets[nsteps] * sizeof(int32_t), hipMemcpyHostToDevice, m->st));
-      for (int s = 0; s < nsteps; ++s) {
-        const int B = offsets[s + 1] - offsets[s];
-        const int32_t* ib = dI + offsets[s];
-        hipLaunchKernelGGL(gather_rows_kernel, dim3((B * F + 255) / 256), dim3(256), 0, m->st, dX, F, ib, B, m->Xb);
-        hipLaunchKernelGGL(gather_rows_kernel, dim3((B * O + 255) / 256), dim3(256), 0, m->st, dT, O, ib, B, m->Tb);
-        forward(m, m->Xb, B);
-        backward(m, m->Xb, m->Tb, B);
-        XLS_HIP(hipMemcpyAsync(dL + s, m->loss, sizeof(float), hipMemcpyDeviceToDevice, m->st));
-        adam(m, lr);
-      }
-      if (losses && nsteps > 0)
-        XLS_HIP(hipMemcpyAsync(losses, dL, nsteps * sizeof(float), hipMemcpyDeviceToHost, m->st));
-      XLS_HIP(hipStreamSynchronize(m->st));
-    } catch (...) {
-      (void)hipStreamSynchronize(m->st);
-      dfree(dX);
-      dfree(dT);
-      dfree(dI);
-      dfree(dL);
-      throw;
+    DevBuf<float> dX(static_cast<size_t>(n) * F), dT(static_cast<size_t>(n) * O);
+    upload_f(dX.p, X, static_cast<int64_t>(n) * F, m->st);
+    upload_f(dT.p, T, static_cast<int64_t>(n) * O, m->st);
+    train_steps(m, dX.p, dT.p, maxb, idx, offsets, nsteps, lr, losses);
+    return XLS_OK;
+  });
+}
+
+int xls_mlp_fit(xls_mlp_t m, const double* F, const double* T, int32_t n, const int32_t* idx,
+                const int32_t* offsets, int32_t nsteps, float lr, float* losses) {
+  return guarded([&]() -> int {
+    if (!m || !F || !T || !idx || !offsets || n < 1 || nsteps < 0 || !(lr > 0.0f))
+      fail(XLS_ERR_INVALID_ARG, "bad argument");
+    const int fi = m->d.size[0], fo = m->d.size[m->d.nl];
+    if (!finite_all(F, static_cast<int64_t>(n) * fi) || !finite_all(T, static_cast<int64_t>(n) * fo))
+      fail(XLS_ERR_INVALID_ARG, "features and targets must be finite");
+    const int maxb = check_minibatches(n, idx, offsets, nsteps);
+    DevBuf<double> dF(static_cast<size_t>(n) * fi), dT(static_cast<size_t>(n) * fo), stats(2 * (fi + fo));
+    DevBuf<double> pred(static_cast<size_t>(n) * fo), rms(fo);
+    DevBuf<float> sF(static_cast<size_t>(n) * fi), sT(static_cast<size_t>(n) * fo);
+    XLS_HIP(hipMemcpyAsync(dF.p, F, static_cast<size_t>(n) * fi * 8, hipMemcpyHostToDevice, m->st));
+    XLS_HIP(hipMemcpyAsync(dT.p, T, static_cast<size_t>(n) * fo * 8, hipMemcpyHostToDevice, m->st));
+    double* fmean = stats.p;
+    double* fscale = stats.p + fi;
+    double* tmean = stats.p + 2 * fi;
+    double* tscale = stats.p + 2 * fi + fo;
+    hipLaunchKernelGGL(col_stats_kernel, dim3(fi), dim3(256), 0, m->st, dF.p, n, fi, fmean, fscale);
+    hipLaunchKernelGGL(col_stats_kernel, dim3(fo), dim3(256), 0, m->st, dT.p, n, fo, tmean, tscale);
+    const int64_t ef = static_cast<int64_t>(n) * fi, eo = static_cast<int64_t>(n) * fo;
+    hipLaunchKernelGGL(standardise_kernel, dim3(static_cast<unsigned>((ef + 255) / 256)), dim3(256), 0, m->st,
+                       dF.p, static_cast<int64_t>(n), fi, fmean, fscale, sF.p);
+    hipLaunchKernelGGL(standardise_kernel, dim3(static_cast<unsigned>((eo + 255) / 256)), dim3(256), 0, m->st,
+                       dT.p, static_cast<int64_t>(n), fo, tmean, tscale, sT.p);
+    launch_check("standardise_kernel");
+    train_steps(m, sF.p, sT.p, maxb, idx, offsets, nsteps, lr, losses);
+    std::vector<double> h(2 * (fi + fo));
+    XLS_HIP(hipMemcpyAsync(h.data(), stats.p, h.size() * 8, hipMemcpyDeviceToHost, m->st));
+    XLS_HIP(hipStreamSynchronize(m->st));
+    for (int i = 0; i < fi; ++i) {
+      m->in_mean[i] = static_cast<float>(h[i]);
+      m->in_std[i] = static_cast<float>(h[fi + i]);
+      if (!(m->in_std[i] > 0.0f)) m->in_std[i] = 1.0f;  // a spread below FP32's range
     }
-    dfree(dX);
-    dfree(dT);
-    dfree(dI);
-    dfree(dL);
+    for (int i = 0; i < fo; ++i) {
+      m->out_mean[i] = h[2 * fi + i];
+      m->out_std[i] = h[2 * fi + fo + i];
+    }
+    // the model's error on its training rows, with the inference it will run
+    infer(m, dF.p, n, pred.p);
+    hipLaunchKernelGGL(rms_err_kernel, dim3(fo), dim3(256), 0, m->st, pred.p, dT.p, n, fo, rms.p);
+    launch_check("rms_err_kernel");
+    m->train_rms.assign(fo, 0.0);
+    XLS_HIP(hipMemcpyAsync(m->train_rms.data(), rms.p, fo * 8, hipMemcpyDeviceToHost, m->st));
+    XLS_HIP(hipStreamSynchronize(m->st));
+    return XLS_OK;
+  });
+}
+
+int xls_mlp_train_rms(xls_mlp_t m, double* rms, int32_t cap) {
+  return guarded([&]() -> int {
+    if (!m || !rms || cap < 1) fail(XLS_ERR_INVALID_ARG, "bad argument");
+    if (m->train_rms.empty()) fail(XLS_ERR_STATE, "the model has not been fitted (xls_mlp_fit)");
+    const int k = std::min<int>(cap, static_cast<int>(m->train_rms.size()));
+    for (int i = 0; i < k; ++i) rms[i] = m->train_rms[i];
+    return k;
+  });
+}
+
+int xls_mlp_bounds(xls_mlp_t m, const double* features, int32_t B, double* lam_max, double* lam_cut,
+                   int32_t* degree) {
+  return guarded([&]() -> int {
+    if (!m || !features || !lam_max || !lam_cut || !degree || B < 1) fail(XLS_ERR_INVALID_ARG, "bad argument");
+    const int fi = m->d.size[0], fo = m->d.size[m->d.nl];
+    if (fo < 3) fail(XLS_ERR_INVALID_ARG, "the model needs 3 outputs (lambda_max, lambda_cut, degree)");
+    if (m->train_rms.size() < 2) fail(XLS_ERR_STATE, "the model has not been fitted (xls_mlp_fit)");
+    if (!finite_all(features, static_cast<int64_t>(B) * fi)) fail(XLS_ERR_INVALID_ARG, "features not finite");
+    m->ensure_pred(B);
+    XLS_HIP(hipMemcpyAsync(m->dF, features, static_cast<size_t>(B) * fi * 8, hipMemcpyHostToDevice, m->st));
+    infer(m, m->dF, B, m->dOut);
+    DevBuf<double> pol(3 * static_cast<size_t>(B));
+    hipLaunchKernelGGL(policy_kernel, dim3((B + 63) / 64), dim3(64), 0, m->st, m->dOut, B, fo,
+                       kLearnedCutSigmas * m->train_rms[1], pol.p);
+    launch_check("policy_kernel");
+    std::vector<double> h(3 * static_cast<size_t>(B));
+    XLS_HIP(hipMemcpyAsync(h.data(), pol.p, h.size() * 8, hipMemcpyDeviceToHost, m->st));
+    XLS_HIP(hipStreamSynchronize(m->st));
+    for (int b = 0; b < B; ++b) {
+      lam_max[b] = h[3 * b];
+      lam_cut[b] = h[3 * b + 1];
+      degree[b] = static_cast<int32_t>(h[3 * b + 2]);
+    }
+    return XLS_OK;
+  });
+}
+
+int xls_learned_safe_bounds(int32_t B, const double* lam_max, const double* lam_cut, double cut_margin,
+                            double* lm_out, double* lc_out) {
+  return guarded([&]() -> int {
+    if (B < 0 || (B > 0 && (!lam_max || !lam_cut || !lm_out || !lc_out)) || !(cut_margin >= 0))
+      fail(XLS_ERR_INVALID_ARG, "bad argument");
+    for (int b = 0; b < B; ++b) {
+      int32_t m;
+      learned_policy(lam_max[b], lam_cut[b], kLearnedDegMin, cut_margin, &lm_out[b], &lc_out[b], &m);
+    }
     return XLS_OK;
   });
 }
@@ -533,40 +782,10 @@ int xls_mlp_predict(xls_mlp_t m, const double* features, int32_t B, double* out)
   return guarded([&]() -> int {
     if (!m || !features || !out || B < 1) fail(XLS_ERR_INVALID_ARG, "bad argument");
     const Dims& d = m->d;
-    if (m->bf16_stale) {
-      hipLaunchKernelGGL(to_bf16_kernel, dim3(static_cast<unsigned>((d.nparam + 255) / 256)), dim3(256), 0, m->st,
-                         m->P, m->Wb, d.nparam);
-      launch_check("to_bf16_kernel");
-      m->bf16_stale = false;
-    }
-    InferArgs a{};
-    a.nl = d.nl;
-    for (int l = 0; l <= d.nl; ++l) a.size[l] = d.size[l];
-    for (int l = 0; l < d.nl; ++l) {
-      a.woff[l] = d.woff[l];
-      a.boff[l] = d.boff[l];
-    }
-    for (int i = 0; i < d.size[0]; ++i) {
-      a.in_mean[i] = m->in_mean[i];
-      a.in_scale[i] = 1.0f / m->in_std[i];
-    }
-    for (int i = 0; i < d.size[d.nl]; ++i) {
-      a.out_mean[i] = m->out_mean[i];
-      a.out_std[i] = m->out_std[i];
-    }
     const int fi = d.size[0], fo = d.size[d.nl];
-    if (B > m->fcap) {
-      dfree(m->dF);
-      dfree(m->dOut);
-      m->dF = nullptr;
-      m->dOut = nullptr;
-      m->dF = dalloc<double>(static_cast<size_t>(B) * fi);
-      m->dOut = dalloc<double>(static_cast<size_t>(B) * fo);
-      m->fcap = B;
-    }
+    m->ensure_pred(B);
     XLS_HIP(hipMemcpyAsync(m->dF, features, static_cast<size_t>(B) * fi * 8, hipMemcpyHostToDevice, m->st));
-    hipLaunchKernelGGL(infer_bf16_kernel, dim3(B), dim3(256), 0, m->st, m->dF, B, m->Wb, m->P, a, m->dOut);
-    launch_check("infer_bf16_kernel");
+    infer(m, m->dF, B, m->dOut);
     XLS_HIP(hipMemcpyAsync(out, m->dOut, static_cast<size_t>(B) * fo * 8, hipMemcpyDeviceToHost, m->st));
     XLS_HIP(hipStreamSynchronize(m->st));
     return XLS_OK;

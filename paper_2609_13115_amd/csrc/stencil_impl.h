@@ -681,13 +681,10 @@ __global__ __launch_bounds__(256) void proj_forward_group_kernel(const PArgs<TS,
 
 struct TileChoice {
   int block, ty, nyt, tz, nzt, P, ws, nv;
-  bool vec;
   size_t smem;
 };
 
-// Launch plan.  Vector runs (XV = 16/elem points per lane) when nx and the
-// column stride are multiples of XV; else one point per lane-slot, up to 4
-// slots per lane.  Default tile: the most rows the block covers.
+// Launch plan: one grid point per lane-slot, at most 2 slots per lane.
 inline int default_ty(int nx, int ny, int elem, int block, const StencilLaunch& cfg) {
   // default tile: ~2 points per lane (measured best on the 64^3 box in both
   // precisions, and for the FP64 residual sweep of FP32 blocks: -16 %)
@@ -706,24 +703,13 @@ inline TileChoice choose_tiles(int nx, int ny, int nz, int elem, int nproj, int6
   } else {
     tc.block = cfg.block == 256 ? 256 : 512;
   }
-  const int XV = 16 / elem;
-  tc.vec = false;
-  (void)XV;
   (void)ld;
-  int ty;
-  if (tc.vec) {
-    const int tpr = nx / XV;
-    ty = cfg.ty > 0 ? cfg.ty : tc.block / tpr;
-    ty = std::max(1, std::min(ty, ny));
-    if (ty * tpr > tc.block) ty = std::max(1, tc.block / tpr);
-  } else {
-    ty = default_ty(nx, ny, elem, tc.block, cfg);
-  }
+  const int ty = default_ty(nx, ny, elem, tc.block, cfg);
   tc.ty = ty;
   tc.nyt = (ny + ty - 1) / ty;
   tc.tz = cfg.tz > 0 ? std::min(cfg.tz, nz) : nz;
   tc.nzt = (nz + tc.tz - 1) / tc.tz;
-  tc.P = tc.vec ? 1 : (nx * ty + tc.block - 1) / tc.block;
+  tc.P = (nx * ty + tc.block - 1) / tc.block;
   tc.ws = (nx + 2 * R <= 80) ? 80 : 128;
   tc.nv = cfg.nv > 0 ? cfg.nv : 1;
   tc.smem = static_cast<size_t>(elem) * tc.nv * (2 * (static_cast<size_t>(tc.ws) * (ty + 2 * R) + 1) + nproj);

@@ -167,6 +167,14 @@ inline int polish_prec(int gprec, double prev_gated_resid) {
   return (gprec == XLS_PREC_BF16X3 && prev_gated_resid <= kPolishResid) ? XLS_PREC_FP32 : gprec;
 }
 
+// Lanczos steps a run takes for a requested k (<= 0: 20), at most
+// kMaxLanczos and N_d; the cached bounds of a handle are keyed by it.
+constexpr int kMaxLanczos = 60;
+int lanczos_steps(const xls_subdomain_s* s, int k);
+// Largest of r[0..gate); NaN when any of them is NaN (a NaN residual is a
+// miss of every gate).
+double gated_max(const double* r, int gate);
+
 // Stage helpers on the handle's stream (api.cpp).
 template <typename TS>
 void apply_H(xls_subdomain_s* s, const TS* y, TS* out, int ncols, TS* alpha);

@@ -156,6 +156,15 @@ void gemm_nn(int prec, const TS* A, int64_t lda, const double* B, int64_t ldb, i
              TS* C, int64_t ldc, void* bwork, hipStream_t st);
 void split_bf16_device(const float* a, uint16_t* hi, uint16_t* lo, int64_t n, hipStream_t st);
 
+// Learned filter bounds: the margins a run applies to a prediction (the
+// cutoff is raised by kLearnedCutSigmas times the model's RMS error on its
+// training rows, lambda_max by kLearnedLmaxMargin of its distance above the
+// cutoff) and the range the predicted degree is rounded and clamped into.
+constexpr double kLearnedCutSigmas = 3.0;
+constexpr double kLearnedLmaxMargin = 1.03;
+constexpr int kLearnedDegMin = 16;
+constexpr int kLearnedDegMax = 32;
+
 // Dense FP64 generalized eigensolver: Hs y = lambda M y (n x n, 1 <= n <= kDenseMaxN).
 constexpr int kDenseMaxN = 2800;  // bounded by the inverse-iteration LDS (7n doubles + n bytes)
 struct DenseWork {

@@ -15,16 +15,18 @@ produces:
   reaches the residual gate within max_iter iterations, the one with the least
   filter work m * iterations (ties: smaller m).
 
-A learned run takes the predicted lambda_max raised by LMAX_MARGIN (an
-estimate below the true top of the spectrum makes the Chebyshev polynomial
-grow there) and the predicted lambda_cut raised by CUT_SIGMAS times the
-model's RMS error on its training set (a cutoff below the true lambda_ns
-damps the highest wanted states; the plain method's later cutoffs, Ritz
-values, are upper bounds for the same reason), the predicted degree, a
-rigorous lower bound for a0, and falls back to Lanczos bounds (same start
-block) when its gated residual misses the gate.  Every numerical step runs
-in the library; this module only orchestrates calls and standardises the
-training data.
+A learned run takes the bounds xls_mlp_bounds returns: the predicted
+lambda_max raised by a margin (an estimate below the true top of the
+spectrum makes the Chebyshev polynomial grow there), the predicted
+lambda_cut raised by three times the model's RMS error on its training rows
+(a cutoff below the true lambda_ns damps the highest wanted states; the
+plain method's later cutoffs, Ritz values, are upper bounds for the same
+reason) and the predicted degree rounded into [16, 32]; a0 is the library's
+rigorous lower bound, and the run falls back to Lanczos bounds (same start
+block) when its gated residual misses the gate.  Standardisation, training,
+the RMS error, the margins and the degree rule all live in the library
+(xls_mlp_fit, xls_mlp_bounds, xls_learned_safe_bounds); this module only
+orchestrates calls and picks the degree labels.
 """
 from __future__ import annotations
 
@@ -37,8 +39,6 @@ from . import xls
 
 DEGREES = (16, 20, 24, 28, 32)
 SIZES = (64, 128, 128, 3)
-LMAX_MARGIN = 1.03
-CUT_SIGMAS = 3.0
 
 
 @dataclasses.dataclass
@@ -68,12 +68,11 @@ def label_subdomains(sds: Sequence, filter_prec: int = xls.XLS_PREC_FP32,
     cut = np.array([r[-1] for r in ritz])
     ok_all = np.zeros((n, len(degrees)), dtype=bool)
     work = np.zeros((n, len(degrees)))
+    lm_safe, lc_safe = xls.xls_learned_safe_bounds(lmax, cut)
     for j, m in enumerate(degrees):
-        params = []
-        for i in range(n):
-            lm, lc = safe_bounds(lmax[i], cut[i])
-            params.append(xls.chefsi_params(m, max_iter, xls.XLS_BOUNDS_LEARNED, lam_cut=lc, lam_max=lm,
-                                            resid_tol=tol, gemm_prec=gemm_prec))
+        params = [xls.chefsi_params(m, max_iter, xls.XLS_BOUNDS_LEARNED, lam_cut=float(lc_safe[i]),
+                                    lam_max=float(lm_safe[i]), resid_tol=tol, gemm_prec=gemm_prec)
+                  for i in range(n)]
         with xls.Batch(list(sds), filter_prec=filter_prec) as b:
             _, resid, iters, status = b.xls_batch_chefsi(params)
         for i, sd in enumerate(sds):
@@ -90,46 +89,19 @@ def label_subdomains(sds: Sequence, filter_prec: int = xls.XLS_PREC_FP32,
     return Labels(F, T, conv, work)
 
 
-def _standardise(A: np.ndarray):
-    mu = A.mean(axis=0)
-    sd = A.std(axis=0)
-    sd = np.where(sd > 0, sd, 1.0)
-    return mu, sd
-
-
 def train_model(F: np.ndarray, T: np.ndarray, epochs: int = 400, batch: int = 16, lr: float = 1e-3,
                 seed: int = 0, model: Optional["xls.Mlp"] = None):
-    """Trains the library MLP on standardised features and targets; returns
-    (model, per-step losses).  Minibatch order and initial weights come from
-    the seeded workload generators."""
+    """Fits the library MLP (xls_mlp_fit: the library standardises features
+    and targets and keeps its training RMS error); returns (model, per-step
+    losses).  Minibatch order and initial weights come from the seeded
+    workload generators."""
     from . import workloads
 
-    fmu, fsd = _standardise(F)
-    tmu, tsd = _standardise(T)
-    Xs = ((F - fmu) / fsd).astype(np.float32)
-    Ts = ((T - tmu) / tsd).astype(np.float32)
     if model is None:
         model = xls.Mlp(SIZES, workloads.mlp_init(SIZES, seed))
     order = workloads.minibatch_order(len(F), batch, epochs, seed)
-    losses = model.train(Xs, Ts, order, lr)
-    model.set_norm(fmu.astype(np.float32), fsd.astype(np.float32), tmu, tsd)
-    model.train_rms = np.sqrt(np.mean((model.predict(F) - T) ** 2, axis=0))
+    losses = model.fit(F, T, order, lr)
     return model, losses
-
-
-def predict_bounds(model: "xls.Mlp", F: np.ndarray):
-    """(lambda_max, lambda_cut, degree) per row; degree rounded and clamped to [16, 32]."""
-    P = model.predict(F)
-    deg = np.clip(np.rint(P[:, 2]), DEGREES[0], DEGREES[-1]).astype(int)
-    return P[:, 0], P[:, 1], deg
-
-
-def safe_bounds(lmax: float, lcut: float, cut_margin: float = 0.0):
-    """Bounds a learned run uses: lambda_cut raised by cut_margin, lambda_max
-    raised by LMAX_MARGIN of its distance above lambda_cut."""
-    lc = lcut + cut_margin
-    lm = lc + LMAX_MARGIN * (lmax - lc)
-    return lm, lc
 
 
 def learned_params(lmax: float, lcut: float, degree: int, max_iter: int = 12, tol: float = 1e-4,
@@ -140,20 +112,15 @@ def learned_params(lmax: float, lcut: float, degree: int, max_iter: int = 12, to
 
 
 def batch_learned_params(model: "xls.Mlp", F: np.ndarray, max_iter: int = 30, tol: float = 1e-4,
-                         gemm_prec: int = xls.XLS_PREC_BF16X3) -> list:
-    """Per-subdomain learned parameters for a batch (xls_batch_chefsi has no
-    Lanczos fallback): predicted bounds made safe as in run_learned."""
-    lmax, lcut, deg = predict_bounds(model, F)
-    margin = CUT_SIGMAS * float(getattr(model, "train_rms", [0, 0])[1])
-    params = []
-    for lm, lc, m in zip(lmax, lcut, deg):
-        lm, lc = float(lm), float(lc)
-        if not lc < lm:
-            lc = 0.5 * lm
-        lm, lc = safe_bounds(lm, lc, margin)
-        params.append(xls.chefsi_params(int(m), max_iter, xls.XLS_BOUNDS_LEARNED, lam_cut=lc, lam_max=lm,
-                                        resid_tol=tol, gemm_prec=gemm_prec))
-    return params
+                         gemm_prec: int = xls.XLS_PREC_BF16X3, fallback: bool = True,
+                         fallback_degree: int = 24) -> list:
+    """Per-subdomain learned parameters for a batch: xls_mlp_bounds, with the
+    Lanczos fallback at the gate tolerance."""
+    lmax, lcut, deg = model.bounds(F)
+    return [xls.chefsi_params(int(m), max_iter, xls.XLS_BOUNDS_LEARNED, lam_cut=float(lc), lam_max=float(lm),
+                              resid_tol=tol, gemm_prec=gemm_prec, fallback_tol=tol if fallback else 0.0,
+                              fallback_degree=fallback_degree)
+            for lm, lc, m in zip(lmax, lcut, deg)]
 
 
 @dataclasses.dataclass
@@ -177,13 +144,8 @@ def run_learned(sds: Sequence, model: "xls.Mlp", filter_prec: int = xls.XLS_PREC
     for sd in sds:
         with xls.Subdomain(sd, filter_prec=filter_prec) as s:
             t0 = time.perf_counter()
-            f = s.xls_subdomain_features()[None, :]
-            lmax, lcut, deg = predict_bounds(model, f)
-            lmax_, lcut_ = float(lmax[0]), float(lcut[0])
-            if not (lcut_ < lmax_):
-                lcut_ = 0.5 * lmax_
-            lmax_, lcut_ = safe_bounds(lmax_, lcut_, CUT_SIGMAS * float(getattr(model, "train_rms", [0, 0])[1]))
-            p = learned_params(lmax_, lcut_, int(deg[0]), max_iter, tol, fallback_degree, gemm_prec)
+            lmax, lcut, deg = model.bounds(s.xls_subdomain_features())
+            p = learned_params(lmax[0], lcut[0], int(deg[0]), max_iter, tol, fallback_degree, gemm_prec)
             ritz, resid, it = s.xls_chefsi_step(p.degree, p.max_iter, p.bounds_mode, p.lam_lo, p.lam_cut,
                                                 p.lam_max, p.resid_tol, 0, 20, p.gemm_prec, p.fallback_tol,
                                                 p.fallback_degree)

@@ -44,6 +44,7 @@ EXPORTED = [
     "xls_subdomain_counters", "xls_subdomain_features", "xls_mlp_create", "xls_mlp_destroy",
     "xls_mlp_get_params", "xls_mlp_set_params", "xls_mlp_set_norm", "xls_mlp_forward", "xls_mlp_gradient",
     "xls_mlp_train", "xls_mlp_predict", "xls_set_graphs", "xls_subdomain_time_gemms",
+    "xls_mlp_fit", "xls_mlp_train_rms", "xls_mlp_bounds", "xls_learned_safe_bounds",
 ]
 
 
@@ -558,3 +559,43 @@ class Mlp:
         out = np.zeros((F.shape[0], self.sizes[-1]))
         _check(lib().xls_mlp_predict(self._h, _dp(F), C.c_int32(F.shape[0]), _dp(out)))
         return out
+
+    def fit(self, F: np.ndarray, T: np.ndarray, batches, lr: float = 1e-3) -> np.ndarray:
+        """xls_mlp_fit: standardise raw features and targets, train, keep the
+        standardisation and the training RMS error in the model."""
+        F = np.ascontiguousarray(F, dtype=np.float64)
+        T = np.ascontiguousarray(T, dtype=np.float64)
+        idx = np.ascontiguousarray(np.concatenate([np.asarray(b) for b in batches]) if batches else np.zeros(0),
+                                   dtype=np.int32)
+        off = np.ascontiguousarray(np.cumsum([0] + [len(b) for b in batches]), dtype=np.int32)
+        losses = np.zeros(max(1, len(batches)), dtype=np.float32)
+        _check(lib().xls_mlp_fit(self._h, _dp(F), _dp(T), C.c_int32(F.shape[0]),
+                                 idx.ctypes.data_as(C.POINTER(C.c_int32)),
+                                 off.ctypes.data_as(C.POINTER(C.c_int32)), C.c_int32(len(batches)),
+                                 C.c_float(lr), _fp(losses)))
+        return losses[:len(batches)]
+
+    def train_rms(self) -> np.ndarray:
+        out = np.zeros(8)
+        n = _check(lib().xls_mlp_train_rms(self._h, _dp(out), C.c_int32(8)))
+        return out[:n]
+
+    def bounds(self, F: np.ndarray):
+        """xls_mlp_bounds: (lambda_max, lambda_cut, degree) a learned run takes."""
+        F = np.ascontiguousarray(F, dtype=np.float64).reshape(-1, self.sizes[0])
+        B = F.shape[0]
+        lm, lc = np.zeros(B), np.zeros(B)
+        deg = np.zeros(B, dtype=np.int32)
+        _check(lib().xls_mlp_bounds(self._h, _dp(F), C.c_int32(B), _dp(lm), _dp(lc),
+                                    deg.ctypes.data_as(C.POINTER(C.c_int32))))
+        return lm, lc, deg
+
+
+def xls_learned_safe_bounds(lam_max, lam_cut, cut_margin: float = 0.0):
+    """Bounds a learned run takes from given (lambda_max, lambda_cut)."""
+    lmx = np.ascontiguousarray(np.atleast_1d(lam_max), dtype=np.float64)
+    lct = np.ascontiguousarray(np.atleast_1d(lam_cut), dtype=np.float64)
+    lm, lc = np.zeros(lmx.size), np.zeros(lmx.size)
+    _check(lib().xls_learned_safe_bounds(C.c_int32(lmx.size), _dp(lmx), _dp(lct), C.c_double(cut_margin),
+                                         _dp(lm), _dp(lc)))
+    return lm, lc

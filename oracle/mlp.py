@@ -110,13 +110,6 @@ def adam_step(params, grads, state, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
     return out
 
 
-def standardise(T: np.ndarray):
-    mu = T.mean(axis=0)
-    sd = T.std(axis=0)
-    sd = np.where(sd > 0, sd, 1.0)
-    return (T - mu) / sd, mu, sd
-
-
 def train(params, X, T, batches: Sequence[np.ndarray], lr=1e-3):
     """Adam over the given minibatch index lists (order fixed by the caller)."""
     st = adam_init(params)

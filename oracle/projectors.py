@@ -22,7 +22,9 @@ Integer contract (must be reproduced bit for bit by any implementation):
   Support lists are sorted by ascending g; the reverse CSR of a point lists
   support slots in ascending slot order (= ascending atom order).
 Pins: lattice-point counts in a ball, normalisation, s/p orthogonality at a
-node-centred atom, dense assembly symmetry (tests/test_oracle_projectors.py).
+node-centred atom, the radial shape at listed lattice points (width
+convention), the explicit sum over periodic images in a box smaller than
+2 r_c, dense assembly symmetry (tests/test_oracle_projectors.py).
 """
 from __future__ import annotations
 
@@ -120,18 +122,6 @@ def apply_vnl(t: ProjectorTables, psi: np.ndarray, h: float) -> np.ndarray:
         alpha = h3 * (C.T @ psi[S, :])         # forward projection (4, ncols)
         alpha = t.gamma[a][:, None] * alpha    # gamma scaling
         out[S, :] += C @ alpha                 # backprojection
-    return out
-
-
-def projection_coefficients(t: ProjectorTables, psi: np.ndarray, h: float) -> np.ndarray:
-    """alpha[4*a + l, n] = gamma_{a,l} h^3 sum_{g in S_a} chi_{a,l}(g) psi(g, n)."""
-    na = len(t.offsets) - 1
-    out = np.zeros((4 * na, psi.shape[1]))
-    for a in range(na):
-        s0, s1 = t.offsets[a], t.offsets[a + 1]
-        S = t.idx[s0:s1]
-        C = t.val[s0:s1]
-        out[4 * a:4 * a + 4, :] = t.gamma[a][:, None] * (h ** 3 * (C.T @ psi[S, :]))
     return out
 
 

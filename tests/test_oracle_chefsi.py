@@ -148,3 +148,20 @@ def test_subspace_angle_of_rotated_basis_is_zero():
     Q2 = Q.copy()
     Q2[:, 0] = rng.standard_normal(50)
     assert chefsi.subspace_sin_theta(Q, Q2) > 1e-3
+
+
+def test_subspace_sin_theta_is_the_largest_principal_angle():
+    """Two columns rotated by known angles a and b into orthogonal planes: the
+    principal angles are a and b, and the value is sin(max(a, b)) (a norm
+    other than the spectral one would mix the two)."""
+    from oracle import chefsi as oc
+    n = 7
+    e = np.eye(n)
+    for a, b in [(0.3, 0.1), (0.05, 0.9), (0.4, 0.4)]:
+        Qo = np.stack([e[0], e[2]], axis=1)
+        Qg = np.stack([np.cos(a) * e[0] + np.sin(a) * e[1], np.cos(b) * e[2] + np.sin(b) * e[3]], axis=1)
+        assert oc.subspace_sin_theta(Qg, Qo) == pytest.approx(np.sin(max(a, b)), rel=1e-13)
+        assert oc.subspace_sin_theta(Qo, Qg) == pytest.approx(np.sin(max(a, b)), rel=1e-13)
+    # invariant to the basis chosen inside each span
+    G = np.array([[2.0, 1.0], [0.5, 3.0]])
+    assert oc.subspace_sin_theta(Qg @ G, Qo) == pytest.approx(np.sin(max(a, b)), rel=1e-12)

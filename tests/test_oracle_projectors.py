@@ -113,3 +113,62 @@ def test_full_hamiltonian_symmetric():
         x = rng.standard_normal(sd.nd)
         y = rng.standard_normal(sd.nd)
         assert abs(x @ op.apply(y) - y @ op.apply(x)) < 1e-10 * abs(x @ op.apply(y)) + 1e-10
+
+
+def test_radial_shape_at_listed_lattice_points():
+    """Before normalisation chi_s = exp(-r^2 / (2 w^2)) and chi_px = (x - X) chi_s:
+    ratios of values at hand-listed lattice points of a node-centred atom
+    cancel the normalisation and fix the width convention."""
+    h, w, n = 0.5, 0.7, 17
+    c = (n - 1) // 2
+    proj_w = np.array([[2.0, w, 1.0, 0.5, 0.5, 0.5]])
+    t = projectors.build((n, n, n), h, (0.0, 0.0, 0.0), False, np.array([[c * h] * 3]), proj_w)
+    where = {int(g): s for s, g in enumerate(t.idx)}
+
+    def val(i, j, k, l):
+        return t.val[where[(c + i) + n * ((c + j) + n * (c + k))], l]
+
+    centre = val(0, 0, 0, 0)
+    for (i, j, k) in [(1, 0, 0), (0, 2, 0), (1, 1, 1), (2, 1, 0), (3, 0, 1), (2, 2, 1)]:
+        r2 = h * h * (i * i + j * j + k * k)
+        assert val(i, j, k, 0) / centre == pytest.approx(np.exp(-r2 / (2 * w * w)), rel=1e-13)
+    # p_x: odd in x, and px(1,0,0)/px(2,1,0) = (h e^{-h^2/2w^2}) / (2h e^{-5h^2/2w^2})
+    assert val(1, 0, 0, 1) == pytest.approx(-val(-1, 0, 0, 1), rel=1e-14)
+    want = (1 * h * np.exp(-h * h / (2 * w * w))) / (2 * h * np.exp(-5 * h * h / (2 * w * w)))
+    assert val(1, 0, 0, 1) / val(2, 1, 0, 1) == pytest.approx(want, rel=1e-13)
+    assert val(0, 2, 1, 2) / val(1, 1, 0, 2) == pytest.approx(
+        (2 * np.exp(-5 * h * h / (2 * w * w))) / (1 * np.exp(-2 * h * h / (2 * w * w))), rel=1e-13)
+
+
+def test_periodic_images_are_summed_in_a_small_box():
+    """A periodic box smaller than 2 r_c: every point's unnormalised value is
+    the sum over the 27 images X + s L (s in {-1,0,1}^3) that lie within r_c,
+    written out here point by point; the oracle's values are that sum
+    normalised (h^3 sum chi^2 = 1)."""
+    n, h, rc, w = 4, 0.6, 2.0, 0.5
+    L = n * h
+    X = np.array([0.7, 1.3, 2.9])
+    t = projectors.build((n, n, n), h, (0.0, 0.0, 0.0), True, X[None, :], np.array([[rc, w, 1, 1, 1, 1]]))
+    S = np.zeros((n ** 3, 4))
+    multi = 0
+    for k in range(n):
+        for j in range(n):
+            for i in range(n):
+                g = i + n * (j + n * k)
+                hits = 0
+                for sz in (-1, 0, 1):
+                    for sy in (-1, 0, 1):
+                        for sx in (-1, 0, 1):
+                            d = np.array([i * h, j * h, k * h]) - (X + np.array([sx, sy, sz]) * L)
+                            r2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]
+                            if r2 < rc * rc:
+                                e = np.exp(-r2 / (2 * w * w))
+                                S[g] += [e, d[0] * e, d[1] * e, d[2] * e]
+                                hits += 1
+                multi += hits > 1
+    assert multi > 0                       # the pin needs overlapping images
+    got = np.zeros((n ** 3, 4))
+    got[t.idx] = t.val
+    for l in range(4):
+        ref = S[:, l] / np.sqrt(h ** 3 * np.sum(S[:, l] ** 2))
+        assert np.allclose(got[:, l], ref, rtol=1e-12, atol=1e-14), l

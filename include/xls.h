@@ -82,10 +82,17 @@ typedef struct {
   int64_t global_offset[3]; /* global index of local node (0,0,0) (may be negative)        */
   int64_t global_n[3];      /* global grid size, for the periodic local->global map       */
   int32_t ns;              /* number of vectors N_s, 1 <= ns <= N_d                         */
-  const double* x0;        /* [N_d*ns] column-major start block (caller-seeded)             */
+  const double* x0;        /* [N_d*ns] column-major start block (caller-seeded), or NULL:
+                              drawn on the device from x0_seed (below)                      */
   const double* lanczos_v0; /* [N_d] Lanczos start vector, or NULL for column 0 of x0       */
   int32_t filter_prec;     /* storage and filter precision: XLS_PREC_FP64 or XLS_PREC_FP32  */
   void* stream;            /* hipStream_t to issue work on, or NULL                         */
+  uint64_t x0_seed;        /* with x0 NULL: element (g, j) of the start block is the standard
+                              normal of counter (g, j, 0, 0) under key (x0_seed mod 2^32,
+                              x0_seed >> 32) of Philox4x32-10 (Salmon et al., SC 2011):
+                              words o0..o3, u1 = 1 - (2^26 (o0>>5) + (o1>>6)) 2^-53, u2 from
+                              (o2, o3) alike, x = sqrt(-2 ln u1) cos(2 pi u2) (Box-Muller),
+                              rounded to the storage precision                            */
 } xls_subdomain_desc_t;
 
 typedef struct xls_subdomain_s* xls_subdomain_t;
@@ -394,9 +401,34 @@ int xls_subdomain_features(xls_subdomain_t s, double* f);
  *   classes of the winning per-launch time.
  * xls_batch_stats: out[0] iterations of the last xls_batch_chefsi, out[1]
  *   graphs captured, out[2] graph replays, out[3] device time of those
- *   iterations (ms, events on the batch stream), out[4] the last one's. */
+ *   iterations (ms, events on the batch stream), out[4] the last one's,
+ *   out[5] the largest device bytes of working sets resident at once (slot
+ *   residency; 0 otherwise), out[6] the most subdomains active in one
+ *   iteration.  Returns the number written (cap at most 7).
+ *
+ * Slot residency (xls_batch_create_slots): for batches whose blocks do not
+ * all fit at once (a 256-subdomain draw holds ~170 GB per FP32 block set).
+ * Creation builds every subdomain's operator tables only (and keeps a host
+ * copy of a given x0; descs with x0 NULL draw their start blocks on the
+ * device from x0_seed, which needs no host copy).  xls_batch_chefsi then
+ * admits subdomains, largest N_d*ns*degree first, while the bytes of the
+ * resident working sets (both blocks, projection, GEMM and dense
+ * workspaces) stay within max_resident_bytes (0: 85 % of the free device
+ * memory at creation; one subdomain is always admitted), loads each start
+ * block (every call starts from X0), runs the same iterations as a resident
+ * batch (bit-identical results), and when a subdomain finishes keeps only
+ * its core rows (all the occupation calls read) and releases the rest, so
+ * the next one can be admitted.  A learned-bounds fallback restarts from
+ * X0.  xls_batch_density, _fermi and _assemble work as for resident
+ * batches (rho is zero off the core in either case); per-handle calls that
+ * need a block (xls_chefsi_step, get/set_block, filter, project, rotate,
+ * residual, Lanczos bounds, half storage, GEMM timing, density) return
+ * XLS_ERR_STATE on a handle of such a batch.  xls_batch_tune times each
+ * shape class with a temporary working set. */
 typedef struct xls_batch_s* xls_batch_t;
 int xls_batch_create(int32_t n, const xls_subdomain_desc_t* descs, xls_batch_t* out);
+int xls_batch_create_slots(int32_t n, const xls_subdomain_desc_t* descs, int64_t max_resident_bytes,
+                           xls_batch_t* out);
 int xls_batch_chefsi(xls_batch_t b, const xls_chefsi_params_t* per_sub, double* ritz_concat,
                      double* resid_concat, int32_t* iters, int32_t* status, int32_t use_graph);
 int xls_batch_density(xls_batch_t b, double mu, double sigma, double* rho_concat, double* c_concat);

@@ -75,6 +75,11 @@ void dfree(void* p) {
   if (p) (void)hipFree(p);
 }
 
+void require_resident(const xls_subdomain_s* s) {
+  if (!s->resident)
+    fail(XLS_ERR_STATE, "the subdomain has no working set (a slot-residency batch releases it between runs)");
+}
+
 bool finite_all(const double* p, int64_t n) {
   for (int64_t i = 0; i < n; ++i)
     if (!std::isfinite(p[i])) return false;
@@ -206,9 +211,14 @@ void lanczos_run(xls_subdomain_s* s, int k) {
   double* part = s->vsmall + 256;  // [256]
   const int nblocks = 256;
   // v_1 = v0 / ||v0||
-  std::vector<TS> hv(s->nd);
-  for (int64_t i = 0; i < s->nd; ++i) hv[i] = static_cast<TS>(s->lanczos_v0[i]);
-  XLS_HIP(hipMemcpyAsync(w, hv.data(), s->nd * sizeof(TS), hipMemcpyHostToDevice, s->st));
+  if (s->lanczos_v0.empty()) {  // column 0 of the generated start block
+    launch_philox_block<TS>(w, ld, s->nd, 1, s->x0_seed, s->st);
+  } else {
+    std::vector<TS> hv(s->nd);
+    for (int64_t i = 0; i < s->nd; ++i) hv[i] = static_cast<TS>(s->lanczos_v0[i]);
+    XLS_HIP(hipMemcpyAsync(w, hv.data(), s->nd * sizeof(TS), hipMemcpyHostToDevice, s->st));
+    XLS_HIP(hipStreamSynchronize(s->st));  // hv is released at scope exit
+  }
   launch_dot<TS>(w, w, s->nd, part, nblocks, nrm, 1, s->st);
   launch_scale_to<TS>(V, w, nrm, s->nd, s->st);
   TS* alph = static_cast<TS*>(s->alpha);
@@ -294,7 +304,7 @@ void validate_desc(const xls_subdomain_desc_t* d) {
     if (d->global_n[a] < 1) fail(XLS_ERR_INVALID_ARG, "global_n must be >= 1");
   }
   if (d->ns < 1 || d->ns > nd) fail(XLS_ERR_INVALID_ARG, "ns must be in [1, N_d]");
-  if (!d->x0 || !finite_all(d->x0, nd * d->ns)) fail(XLS_ERR_INVALID_ARG, "x0 NULL or not finite");
+  if (d->x0 && !finite_all(d->x0, nd * d->ns)) fail(XLS_ERR_INVALID_ARG, "x0 not finite");
   if (d->lanczos_v0 && !finite_all(d->lanczos_v0, nd)) fail(XLS_ERR_INVALID_ARG, "lanczos_v0 not finite");
   if (d->filter_prec != XLS_PREC_FP64 && d->filter_prec != XLS_PREC_FP32)
     fail(XLS_ERR_INVALID_ARG, "filter_prec must be FP64 or FP32");
@@ -525,6 +535,185 @@ void check_device_range(const void* p, size_t bytes) {
 }  // namespace
 }  // namespace xls
 
+namespace xls {
+
+void subdomain_tables(xls_subdomain_s* s, const xls_subdomain_desc_t* d, bool keep_x0) {
+  for (int a = 0; a < 3; ++a) {
+    s->n[a] = d->n[a];
+    s->core_lo[a] = d->core_lo[a];
+    s->core_hi[a] = d->core_hi[a];
+  }
+  s->h = d->h;
+  s->bc = d->bc;
+  s->prec = d->filter_prec;
+  s->ns = d->ns;
+  s->nd = static_cast<int64_t>(d->n[0]) * d->n[1] * d->n[2];
+  s->ld = (s->nd + 63) / 64 * 64;  // 256-byte aligned columns (vector loads, GEMM tiles)
+  if (d->stream) {
+    s->st = static_cast<hipStream_t>(d->stream);
+  } else {
+    XLS_HIP(hipStreamCreateWithFlags(&s->st, hipStreamNonBlocking));
+    s->own_stream = true;
+  }
+  build_setup(*d, s->tab);
+  {  // lambda_1 >= min V + sum of negative projector coefficients (-1/2 Lap >= 0)
+    double vmin = d->v_eff[0];
+    for (int64_t i = 1; i < s->nd; ++i) vmin = std::min(vmin, d->v_eff[i]);
+    double neg = 0.0;
+    for (int a = 0; a < d->n_atoms; ++a)
+      for (int l = 0; l < 4; ++l) neg += std::min(0.0, d->proj[a].gamma[l]);
+    s->a0_bound = vmin + neg;
+  }
+  s->n_atoms = d->n_atoms;
+  const int64_t nd = s->nd;
+  // operator tables
+  std::vector<double> v(d->v_eff, d->v_eff + nd);
+  s->v64 = dupload(v, s->st);
+  std::vector<float> v32(v.begin(), v.end());
+  s->v32 = dupload(v32, s->st);
+  s->val64 = dupload(s->tab.sup_val, s->st);
+  std::vector<float> val32(s->tab.sup_val.begin(), s->tab.sup_val.end());
+  s->val32 = dupload(val32, s->st);
+  s->rev_pk = dupload(s->tab.rev_pk, s->st);
+  s->rev_aoff = dupload(s->tab.rev_aoff, s->st);
+  s->rev_val64 = dupload(s->tab.rev_val, s->st);
+  std::vector<float> rv32(s->tab.rev_val.begin(), s->tab.rev_val.end());
+  s->rev_val32 = dupload(rv32, s->st);
+  s->sup_off = dupload(s->tab.sup_off, s->st);
+  s->sup_idx = dupload(s->tab.sup_idx, s->st);
+  s->gamma = dupload(s->tab.gamma, s->st);
+  s->mask = dupload(s->tab.core_mask, s->st);
+  auto fill_op = [&](auto& op, auto* vv, auto* val, auto* rval) {
+    op.v = vv;
+    op.slot_val = val;
+    op.rev_pk = s->rev_pk;
+    op.rev_val = rval;
+    op.rev_aoff = s->rev_aoff;
+    op.nent = static_cast<int64_t>(s->tab.rev_slot.size());
+    op.sup_off = s->sup_off;
+    op.sup_idx = s->sup_idx;
+    op.gamma = s->gamma;
+    op.n_atoms = s->n_atoms;
+    op.nx = s->n[0];
+    op.ny = s->n[1];
+    op.nz = s->n[2];
+    op.periodic = s->bc == XLS_BC_PERIODIC;
+    op.h = s->h;
+  };
+  fill_op(s->op64, s->v64, s->val64, s->rev_val64);
+  fill_op(s->op32, s->v32, s->val32, s->rev_val32);
+  s->cfg64.block = 0;  // 256 threads unless the tile's halo needs 512
+  s->cfg32.block = 0;
+  stencil_validate(s->n[0], s->n[1], s->n[2], s->bc == XLS_BC_PERIODIC, 8, s->nproj(), s->cfg64);
+  stencil_validate(s->n[0], s->n[1], s->n[2], s->bc == XLS_BC_PERIODIC, 4, s->nproj(), s->cfg32);
+  // small per-state buffers (kept for the handle's lifetime)
+  s->lam_dev = dalloc<double>(s->ns);
+  s->resid_dev = dalloc<double>(s->ns);
+  s->vsmall = dalloc<double>(1024);
+  s->cpart = dalloc<double>(static_cast<size_t>(s->ns) * 64);
+  s->gocc = dalloc<double>(s->ns);
+  // start block source and Lanczos vector
+  s->x0_seed = d->x0_seed;
+  s->x0_gen = d->x0 == nullptr;
+  if (keep_x0 && d->x0) s->x0_host.assign(d->x0, d->x0 + nd * s->ns);
+  if (d->lanczos_v0)
+    s->lanczos_v0.assign(d->lanczos_v0, d->lanczos_v0 + nd);
+  else if (d->x0)
+    s->lanczos_v0.assign(d->x0, d->x0 + nd);
+  else
+    s->lanczos_v0.clear();  // column 0 of the generated start block
+}
+
+xls_subdomain_s* subdomain_create_tables(const xls_subdomain_desc_t* d) {
+  validate_desc(d);
+  auto* s = new xls_subdomain_s();
+  try {
+    subdomain_tables(s, d, true);
+    XLS_HIP(hipStreamSynchronize(s->st));
+  } catch (...) {
+    delete s;
+    throw;
+  }
+  return s;
+}
+
+size_t subdomain_ws_bytes(const xls_subdomain_s* s, bool shared_gemm_work) {
+  const size_t es = s->esize();
+  const size_t bl = static_cast<size_t>(s->ld) * s->ns;
+  const size_t na = static_cast<size_t>(std::max(1, s->nproj())) * std::max(s->ns, 1);
+  const size_t nn = static_cast<size_t>(s->ns) * s->ns;
+  size_t b = 2 * bl * es + na * (es + 8);
+  b += std::max(stencil_partial_elems(s->op64, s->ns, s->cfg64), static_cast<size_t>(s->ns) * 64) * 8;
+  b += 3 * nn * 8 + 2 * nn_work_doubles(s->ns, s->ns) * 4;
+  b += dense_bytes(s->ns, !shared_gemm_work);
+  if (!shared_gemm_work) b += std::max(gemm_tn_work_elems(s->ns, s->ns, s->nd), static_cast<size_t>(64) * 1024) * 8;
+  return b;
+}
+
+void subdomain_ws_alloc(xls_subdomain_s* s, double* shared_gwork, size_t shared_elems) {
+  const size_t es = s->esize();
+  const size_t bl = static_cast<size_t>(s->ld) * s->ns;
+  s->blk[0] = es == 4 ? static_cast<void*>(dalloc<float>(bl)) : static_cast<void*>(dalloc<double>(bl));
+  s->blk[1] = es == 4 ? static_cast<void*>(dalloc<float>(bl)) : static_cast<void*>(dalloc<double>(bl));
+  const size_t na = static_cast<size_t>(std::max(1, s->nproj())) * std::max(s->ns, 1);
+  s->alpha = es == 4 ? static_cast<void*>(dalloc<float>(na)) : static_cast<void*>(dalloc<double>(na));
+  s->alpha64 = dalloc<double>(na);
+  s->partial_elems = std::max(stencil_partial_elems(s->op64, s->ns, s->cfg64), static_cast<size_t>(s->ns) * 64);
+  s->partial = dalloc<double>(s->partial_elems);
+  const size_t nn = static_cast<size_t>(s->ns) * s->ns;
+  s->Mdev = dalloc<double>(nn);
+  s->Hsdev = dalloc<double>(nn);
+  s->Ydev = dalloc<double>(nn);
+  s->bwork = dalloc<float>(2 * nn_work_doubles(s->ns, s->ns));
+  if (shared_gwork) {
+    s->gwork = shared_gwork;
+    s->gwork_elems = shared_elems;
+    s->own_gwork = false;
+  } else {
+    s->gwork_elems = std::max(gemm_tn_work_elems(s->ns, s->ns, s->nd), static_cast<size_t>(64) * 1024);
+    s->gwork = dalloc<double>(s->gwork_elems);
+    s->own_gwork = true;
+  }
+  dense_alloc(s->dw, s->ns, shared_gwork, shared_elems);
+  s->resident = true;
+}
+
+void subdomain_ws_free(xls_subdomain_s* s) {
+  (void)hipStreamSynchronize(s->st);
+  if (s->dexec) (void)hipGraphExecDestroy(s->dexec);
+  if (s->dgraph) (void)hipGraphDestroy(s->dgraph);
+  s->dexec = nullptr;
+  s->dgraph = nullptr;
+  s->dwarm = false;
+  void* ps[] = {s->blk[0], s->blk[1], s->alpha, s->alpha64, s->partial, s->Mdev, s->Hsdev, s->Ydev,
+                s->bwork, s->lz, s->backup, s->rho_dev};
+  for (void* p : ps) dfree(p);
+  if (s->own_gwork) dfree(s->gwork);
+  s->blk[0] = s->blk[1] = nullptr;
+  s->alpha = s->backup = s->lz = nullptr;
+  s->alpha64 = s->partial = s->Mdev = s->Hsdev = s->Ydev = s->gwork = s->rho_dev = nullptr;
+  s->bwork = nullptr;
+  s->lz_cols = 0;
+  dense_free(s->dw);
+  s->resident = false;
+}
+
+template <typename TS>
+void load_start_block(xls_subdomain_s* s, const double* x0) {
+  if (x0)
+    upload_block<TS>(s, x0, s->blk[0], s->ns);
+  else if (!s->x0_host.empty())
+    upload_block<TS>(s, s->x0_host.data(), s->blk[0], s->ns);
+  else
+    launch_philox_block<TS>(B<TS>(s, 0), s->ld, s->nd, s->ns, s->x0_seed, s->st);
+  s->cur = 0;
+  s->have_ritz = false;
+}
+template void load_start_block<float>(xls_subdomain_s*, const double*);
+template void load_start_block<double>(xls_subdomain_s*, const double*);
+
+}  // namespace xls
+
 extern "C" {
 
 const char* xls_last_error(void) { return g_last_error.c_str(); }
@@ -545,110 +734,12 @@ int xls_subdomain_create(const xls_subdomain_desc_t* d, xls_subdomain_t* out) {
     validate_desc(d);
     auto* s = new xls_subdomain_s();
     try {
-      for (int a = 0; a < 3; ++a) {
-        s->n[a] = d->n[a];
-        s->core_lo[a] = d->core_lo[a];
-        s->core_hi[a] = d->core_hi[a];
-      }
-      s->h = d->h;
-      s->bc = d->bc;
-      s->prec = d->filter_prec;
-      s->ns = d->ns;
-      s->nd = static_cast<int64_t>(d->n[0]) * d->n[1] * d->n[2];
-      s->ld = (s->nd + 63) / 64 * 64;  // 256-byte aligned columns (vector loads, GEMM tiles)
-      if (d->stream) {
-        s->st = static_cast<hipStream_t>(d->stream);
-      } else {
-        XLS_HIP(hipStreamCreateWithFlags(&s->st, hipStreamNonBlocking));
-        s->own_stream = true;
-      }
-      build_setup(*d, s->tab);
-      {  // lambda_1 >= min V + sum of negative projector coefficients (-1/2 Lap >= 0)
-        double vmin = d->v_eff[0];
-        for (int64_t i = 1; i < static_cast<int64_t>(d->n[0]) * d->n[1] * d->n[2]; ++i) vmin = std::min(vmin, d->v_eff[i]);
-        double neg = 0.0;
-        for (int a = 0; a < d->n_atoms; ++a)
-          for (int l = 0; l < 4; ++l) neg += std::min(0.0, d->proj[a].gamma[l]);
-        s->a0_bound = vmin + neg;
-      }
-      s->n_atoms = d->n_atoms;
-      const int64_t nd = s->nd;
-      const size_t total = s->tab.sup_idx.size();
-      // operator tables
-      std::vector<double> v(d->v_eff, d->v_eff + nd);
-      s->v64 = dupload(v, s->st);
-      std::vector<float> v32(v.begin(), v.end());
-      s->v32 = dupload(v32, s->st);
-      s->val64 = dupload(s->tab.sup_val, s->st);
-      std::vector<float> val32(s->tab.sup_val.begin(), s->tab.sup_val.end());
-      s->val32 = dupload(val32, s->st);
-      s->rev_pk = dupload(s->tab.rev_pk, s->st);
-      s->rev_aoff = dupload(s->tab.rev_aoff, s->st);
-      s->rev_val64 = dupload(s->tab.rev_val, s->st);
-      std::vector<float> rv32(s->tab.rev_val.begin(), s->tab.rev_val.end());
-      s->rev_val32 = dupload(rv32, s->st);
-      s->sup_off = dupload(s->tab.sup_off, s->st);
-      s->sup_idx = dupload(s->tab.sup_idx, s->st);
-      s->gamma = dupload(s->tab.gamma, s->st);
-      s->mask = dupload(s->tab.core_mask, s->st);
-      (void)total;
-      auto fill_op = [&](auto& op, auto* vv, auto* val, auto* rval) {
-        op.v = vv;
-        op.slot_val = val;
-        op.rev_pk = s->rev_pk;
-        op.rev_val = rval;
-        op.rev_aoff = s->rev_aoff;
-        op.nent = static_cast<int64_t>(s->tab.rev_slot.size());
-        op.sup_off = s->sup_off;
-        op.sup_idx = s->sup_idx;
-        op.gamma = s->gamma;
-        op.n_atoms = s->n_atoms;
-        op.nx = s->n[0];
-        op.ny = s->n[1];
-        op.nz = s->n[2];
-        op.periodic = s->bc == XLS_BC_PERIODIC;
-        op.h = s->h;
-      };
-      fill_op(s->op64, s->v64, s->val64, s->rev_val64);
-      fill_op(s->op32, s->v32, s->val32, s->rev_val32);
-      s->cfg64.block = 0;  // 256 threads unless the tile's halo needs 512
-      s->cfg32.block = 0;
-      stencil_validate(s->n[0], s->n[1], s->n[2], s->bc == XLS_BC_PERIODIC, 8, s->nproj(), s->cfg64);
-      stencil_validate(s->n[0], s->n[1], s->n[2], s->bc == XLS_BC_PERIODIC, 4, s->nproj(), s->cfg32);
-      // blocks and work
-      const size_t es = s->esize();
-      const size_t bl = static_cast<size_t>(s->ld) * s->ns;
-      s->blk[0] = es == 4 ? static_cast<void*>(dalloc<float>(bl)) : static_cast<void*>(dalloc<double>(bl));
-      s->blk[1] = es == 4 ? static_cast<void*>(dalloc<float>(bl)) : static_cast<void*>(dalloc<double>(bl));
-      const size_t na = static_cast<size_t>(std::max(1, s->nproj())) * std::max(s->ns, 1);
-      s->alpha = es == 4 ? static_cast<void*>(dalloc<float>(na)) : static_cast<void*>(dalloc<double>(na));
-      s->alpha64 = dalloc<double>(na);
-      s->partial_elems = std::max(stencil_partial_elems(s->op64, s->ns, s->cfg64),
-                                  static_cast<size_t>(s->ns) * 64);
-      s->partial = dalloc<double>(s->partial_elems);
-      s->lam_dev = dalloc<double>(s->ns);
-      s->resid_dev = dalloc<double>(s->ns);
-      const size_t nn = static_cast<size_t>(s->ns) * s->ns;
-      s->Mdev = dalloc<double>(nn);
-      s->Hsdev = dalloc<double>(nn);
-      s->Ydev = dalloc<double>(nn);
-      s->bwork = dalloc<float>(2 * nn_work_doubles(s->ns, s->ns));
-      s->gwork_elems = std::max(gemm_tn_work_elems(s->ns, s->ns, s->nd), static_cast<size_t>(64) * 1024);
-      s->gwork = dalloc<double>(s->gwork_elems);
-      s->vsmall = dalloc<double>(1024);
-      s->cpart = dalloc<double>(static_cast<size_t>(s->ns) * 64);
-      s->gocc = dalloc<double>(s->ns);
-      dense_alloc(s->dw, s->ns);
-      // start block and Lanczos vector
-      if (s->prec == XLS_PREC_FP32)
-        upload_block<float>(s, d->x0, s->blk[0], s->ns);
-      else
-        upload_block<double>(s, d->x0, s->blk[0], s->ns);
-      s->cur = 0;
-      if (d->lanczos_v0)
-        s->lanczos_v0.assign(d->lanczos_v0, d->lanczos_v0 + nd);
-      else
-        s->lanczos_v0.assign(d->x0, d->x0 + nd);
+      subdomain_tables(s, d, false);
+      subdomain_ws_alloc(s, nullptr, 0);
+      by_prec(s, [&](auto tag) {
+        load_start_block<decltype(tag)>(s, d->x0);
+        return 0;
+      });
       XLS_HIP(hipStreamSynchronize(s->st));
     } catch (...) {
       delete s;
@@ -669,6 +760,7 @@ int xls_chefsi_step(xls_subdomain_t s, const xls_chefsi_params_t* p, double* rit
                     int32_t* iters_done) {
   return guarded([&]() -> int {
     if (!s || !p || !ritz || !resid) fail(XLS_ERR_INVALID_ARG, "NULL argument");
+    require_resident(s);
     return by_prec(s, [&](auto tag) { return chefsi_impl<decltype(tag)>(s, p, ritz, resid, iters_done); });
   });
 }
@@ -687,6 +779,7 @@ int xls_subdomain_density(xls_subdomain_t s, double mu, double sigma, double* rh
   return guarded([&]() -> int {
     if (!s || !rho || !c) fail(XLS_ERR_INVALID_ARG, "NULL argument");
     if (!s->have_ritz) fail(XLS_ERR_STATE, "density needs a completed xls_chefsi_step");
+    require_resident(s);
     if (!(sigma > 0) || !std::isfinite(sigma) || !std::isfinite(mu)) fail(XLS_ERR_INVALID_ARG, "bad mu/sigma");
     if (!s->rho_dev) s->rho_dev = dalloc<double>(s->nd);
     XLS_HIP(hipMemcpyAsync(s->lam_dev, s->ritz.data(), s->ns * 8, hipMemcpyHostToDevice, s->st));
@@ -733,6 +826,7 @@ int xls_subdomain_filter(xls_subdomain_t s, int32_t degree, double a0, double la
   return guarded([&]() -> int {
     if (!s || degree < 1) fail(XLS_ERR_INVALID_ARG, "bad argument");
     if (!(a0 < lam_cut && lam_cut < lam_max)) fail(XLS_ERR_INVALID_ARG, "need a0 < lam_cut < lam_max");
+    require_resident(s);
     s->filter_launches = 0;
     s->filter_kernel_ms = 0.0;
     s->stage_ms.assign(8, 0.0);
@@ -751,6 +845,7 @@ int xls_subdomain_project(xls_subdomain_t s, int32_t gemm_prec, double* M, doubl
     if (s->prec == XLS_PREC_FP64 && gemm_prec != XLS_PREC_FP64)
       fail(XLS_ERR_INVALID_ARG, "FP64 handles run FP64 GEMMs");
     if (gemm_prec < 0 || gemm_prec > 2) fail(XLS_ERR_INVALID_ARG, "bad gemm_prec");
+    require_resident(s);
     by_prec(s, [&](auto tag) {
       project_block<decltype(tag)>(s, gemm_prec);
       return 0;
@@ -770,6 +865,7 @@ int xls_subdomain_rotate(xls_subdomain_t s, int32_t gemm_prec, const double* Q) 
       fail(XLS_ERR_INVALID_ARG, "FP64 handles run FP64 GEMMs");
     if (gemm_prec < 0 || gemm_prec > 2) fail(XLS_ERR_INVALID_ARG, "bad gemm_prec");
     if (!finite_all(Q, static_cast<int64_t>(s->ns) * s->ns)) fail(XLS_ERR_INVALID_ARG, "Q not finite");
+    require_resident(s);
     XLS_HIP(hipMemcpyAsync(s->Ydev, Q, static_cast<size_t>(s->ns) * s->ns * 8, hipMemcpyHostToDevice, s->st));
     by_prec(s, [&](auto tag) {
       rotate_block<decltype(tag)>(s, gemm_prec, s->Ydev);
@@ -783,6 +879,7 @@ int xls_subdomain_rotate(xls_subdomain_t s, int32_t gemm_prec, const double* Q) 
 int xls_subdomain_residual(xls_subdomain_t s, const double* lam, double* resid) {
   return guarded([&]() -> int {
     if (!s || !lam || !resid) fail(XLS_ERR_INVALID_ARG, "NULL argument");
+    require_resident(s);
     XLS_HIP(hipMemcpyAsync(s->lam_dev, lam, s->ns * 8, hipMemcpyHostToDevice, s->st));
     by_prec(s, [&](auto tag) {
       residual_block<decltype(tag)>(s, s->lam_dev, s->resid_dev);
@@ -797,6 +894,7 @@ int xls_subdomain_residual(xls_subdomain_t s, const double* lam, double* resid) 
 int xls_lanczos_bounds(xls_subdomain_t s, int32_t k, double* theta_min, double* upper) {
   return guarded([&]() -> int {
     if (!s || !theta_min || !upper || k < 1 || k > 60) fail(XLS_ERR_INVALID_ARG, "bad argument (1 <= k <= 60)");
+    require_resident(s);
     by_prec(s, [&](auto tag) {
       lanczos_run<decltype(tag)>(s, k);
       return 0;
@@ -852,6 +950,7 @@ int xls_dense_geneig(int32_t n, const double* Hs, const double* M, double* lam, 
 int xls_subdomain_get_block(xls_subdomain_t s, double* X) {
   return guarded([&]() -> int {
     if (!s || !X) fail(XLS_ERR_INVALID_ARG, "NULL argument");
+    require_resident(s);
     by_prec(s, [&](auto tag) {
       download_block<decltype(tag)>(s, s->blk[s->cur], X, s->ns);
       return 0;
@@ -864,6 +963,7 @@ int xls_subdomain_set_block(xls_subdomain_t s, const double* X) {
   return guarded([&]() -> int {
     if (!s || !X) fail(XLS_ERR_INVALID_ARG, "NULL argument");
     if (!finite_all(X, s->nd * s->ns)) fail(XLS_ERR_INVALID_ARG, "block not finite");
+    require_resident(s);
     by_prec(s, [&](auto tag) {
       upload_block<decltype(tag)>(s, X, s->blk[s->cur], s->ns);
       return 0;
@@ -878,6 +978,7 @@ int xls_subdomain_set_block(xls_subdomain_t s, const double* X) {
 int xls_subdomain_store_half(xls_subdomain_t s, uint16_t* dst) {
   return guarded([&]() -> int {
     if (!s || !dst) fail(XLS_ERR_INVALID_ARG, "NULL argument");
+    require_resident(s);
     check_device_range(dst, static_cast<size_t>(s->nd) * s->ns * 2);
     by_prec(s, [&](auto tag) {
       using TS = decltype(tag);
@@ -892,6 +993,7 @@ int xls_subdomain_store_half(xls_subdomain_t s, uint16_t* dst) {
 int xls_subdomain_load_half(xls_subdomain_t s, const uint16_t* src) {
   return guarded([&]() -> int {
     if (!s || !src) fail(XLS_ERR_INVALID_ARG, "NULL argument");
+    require_resident(s);
     check_device_range(src, static_cast<size_t>(s->nd) * s->ns * 2);
     by_prec(s, [&](auto tag) {
       using TS = decltype(tag);
@@ -969,7 +1071,7 @@ int xls_subdomain_tune(xls_subdomain_t s, int32_t prec, int32_t block, int32_t t
     if (prec == XLS_PREC_FP64) {
       // the residual sweep uses the FP64 shape: grow its partial buffer if needed
       const size_t need = std::max(stencil_partial_elems(s->op64, s->ns, c), static_cast<size_t>(s->ns) * 64);
-      if (need > s->partial_elems) {
+      if (s->resident && need > s->partial_elems) {
         XLS_HIP(hipStreamSynchronize(s->st));
         double* np = dalloc<double>(need);
         dfree(s->partial);
@@ -990,6 +1092,7 @@ int xls_subdomain_time_gemms(xls_subdomain_t s, int32_t gemm_prec, int32_t reps,
     if (s->prec == XLS_PREC_FP64 && gemm_prec != XLS_PREC_FP64)
       fail(XLS_ERR_INVALID_ARG, "FP64 handles run FP64 GEMMs");
     if (gemm_prec < 0 || gemm_prec > 2) fail(XLS_ERR_INVALID_ARG, "bad gemm_prec");
+    require_resident(s);
     by_prec(s, [&](auto tag) {
       using TS = decltype(tag);
       TS* Bc = B<TS>(s, s->cur);

@@ -77,6 +77,27 @@ struct SubState {
   int fb_degree = 0;
   int lanczos_k = 0;
   int cur0 = 0;         // block parity at the start (the backup's contents)
+  bool fell_back = false;
+  bool started = false;  // begun in the current xls_batch_chefsi call
+};
+
+// Core rows of a subdomain kept after its working set is released (slot
+// residency): the density and the interior weights read only core points.
+struct CoreStore {
+  void* blk = nullptr;         // ncore x ns, leading dimension ld, storage precision
+  int64_t ncore = 0, ld = 0;
+  int32_t* rows = nullptr;     // device: local grid index of each core row (ascending)
+  int64_t* gidx = nullptr;     // device: global index of each core row
+  std::vector<int32_t> hrows;  // host copy of rows
+  void release_blk() {
+    dfree(blk);
+    blk = nullptr;
+  }
+  ~CoreStore() {
+    dfree(blk);
+    dfree(rows);
+    dfree(gidx);
+  }
 };
 
 }  // namespace
@@ -110,6 +131,17 @@ struct xls_batch_s {
   int64_t rho_global_n = 0;
   double* dos_buf = nullptr;  // [2 * nbins + 1]: edges, then bins
   int dos_cap = 0;
+  // slot residency (xls_batch_create_slots): working sets allocated on
+  // admission and released when a subdomain finishes, within a byte budget
+  bool slots = false;
+  int64_t budget = 0;
+  int64_t resident_bytes = 0, peak_bytes = 0;
+  int max_active = 0;
+  std::vector<double*> pool_gwork;  // split-K workspace per pool stream (shared by its handles)
+  size_t pool_gwork_elems = 0;
+  std::vector<CoreStore> core;      // per subdomain (slot mode)
+  uint8_t* ones = nullptr;          // all-ones mask over the largest core
+  int64_t ones_n = 0;
 
   ~xls_batch_s() {
     if (main) (void)hipStreamSynchronize(main);
@@ -124,6 +156,9 @@ struct xls_batch_s {
     for (auto* g : gidx) dfree(g);
     dfree(rho_global);
     dfree(dos_buf);
+    core.clear();
+    dfree(ones);
+    for (auto* g : pool_gwork) dfree(g);
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     for (auto e : ev_join) (void)hipEventDestroy(e);
     if (t0) (void)hipEventDestroy(t0);
@@ -265,10 +300,6 @@ void run_iteration(xls_batch_s* b, const std::vector<int>& act, bool use_graph) 
   XLS_HIP(hipEventRecord(b->t1, b->main));
 }
 
-template <typename TS>
-void batch_loop(xls_batch_s* b, int use_graph, std::vector<std::vector<double>>& hl,
-                std::vector<std::vector<double>>& hr);
-
 // First-iteration Lanczos bounds of a subdomain (cached per handle and k).
 template <typename TS>
 void lanczos_bounds_of(xls_subdomain_s* s, int k_req, double& a0, double& lc, double& lmax) {
@@ -279,153 +310,263 @@ void lanczos_bounds_of(xls_subdomain_s* s, int k_req, double& a0, double& lc, do
   lc = a0 + 0.1 * (lmax - a0);
 }
 
+void check_params(const xls_chefsi_params_t& p, bool fp64) {
+  if (p.degree < 1 || p.degree > kMaxDegree || p.max_iter < 1)
+    fail(XLS_ERR_INVALID_ARG, "degree must be in [1, 256] and max_iter >= 1");
+  if (p.lanczos_k > kMaxLanczos) fail(XLS_ERR_INVALID_ARG, "lanczos_k must be <= 60");
+  if (p.gemm_prec < XLS_PREC_FP64 || p.gemm_prec > XLS_PREC_BF16X3) fail(XLS_ERR_INVALID_ARG, "bad gemm_prec");
+  if (fp64 && p.gemm_prec != XLS_PREC_FP64) fail(XLS_ERR_INVALID_ARG, "FP64 batches run FP64 GEMMs");
+  if (p.bounds_mode < XLS_BOUNDS_GIVEN || p.bounds_mode > XLS_BOUNDS_LEARNED)
+    fail(XLS_ERR_INVALID_ARG, "unknown bounds_mode");
+  if (p.bounds_mode == XLS_BOUNDS_LEARNED && !(p.fallback_tol >= 0))
+    fail(XLS_ERR_INVALID_ARG, "fallback_tol must be >= 0");
+  if (p.bounds_mode == XLS_BOUNDS_LEARNED && p.fallback_tol > 0 && p.fallback_degree > kMaxDegree)
+    fail(XLS_ERR_INVALID_ARG, "fallback_degree must be <= 256");
+  if (p.bounds_mode != XLS_BOUNDS_LANCZOS &&
+      (!std::isfinite(p.lam_max) || !std::isfinite(p.lam_cut) ||
+       (p.bounds_mode == XLS_BOUNDS_GIVEN && !std::isfinite(p.lam_lo))))
+    fail(XLS_ERR_INVALID_ARG, "bounds must be finite");
+}
+
+// Starts subdomain i's run from its current block: first bounds, state,
+// the backup of the start block (fallback, resident mode) and the filter
+// coefficients (on the handle's stream).
 template <typename TS>
-void batch_chefsi(xls_batch_s* b, const xls_chefsi_params_t* P, int use_graph) {
-  b->have_fermi = false;  // new blocks: a stored Fermi level no longer applies
-  const int n = b->n;
-  for (int i = 0; i < n; ++i) {
-    const xls_chefsi_params_t& p = P[i];
-    xls_subdomain_s* s = b->subs[i];
-    SubState& ss = b->st[i];
-    if (p.degree < 1 || p.degree > kMaxDegree || p.max_iter < 1)
-      fail(XLS_ERR_INVALID_ARG, "degree must be in [1, 256] and max_iter >= 1");
-    if (p.lanczos_k > kMaxLanczos) fail(XLS_ERR_INVALID_ARG, "lanczos_k must be <= 60");
-    if (p.bounds_mode == XLS_BOUNDS_LEARNED && p.fallback_tol > 0 && p.fallback_degree > kMaxDegree)
-      fail(XLS_ERR_INVALID_ARG, "fallback_degree must be <= 256");
-    if (p.gemm_prec < XLS_PREC_FP64 || p.gemm_prec > XLS_PREC_BF16X3) fail(XLS_ERR_INVALID_ARG, "bad gemm_prec");
-    if (std::is_same<TS, double>::value && p.gemm_prec != XLS_PREC_FP64)
-      fail(XLS_ERR_INVALID_ARG, "FP64 batches run FP64 GEMMs");
-    double a0, lc, lmax;
-    if (p.bounds_mode == XLS_BOUNDS_GIVEN) {
-      a0 = p.lam_lo;
-      lc = p.lam_cut;
-      lmax = p.lam_max;
-    } else if (p.bounds_mode == XLS_BOUNDS_LANCZOS) {
-      lanczos_bounds_of<TS>(s, p.lanczos_k, a0, lc, lmax);
-    } else if (p.bounds_mode == XLS_BOUNDS_LEARNED) {
-      if (!(p.fallback_tol >= 0)) fail(XLS_ERR_INVALID_ARG, "fallback_tol must be >= 0");
-      lmax = p.lam_max;
-      lc = p.lam_cut;
-      a0 = std::min(s->a0_bound, lc - 1e-3 * std::fabs(lmax - lc));
-    } else {
-      fail(XLS_ERR_INVALID_ARG, "unknown bounds_mode");
-    }
-    if (!(a0 < lc && lc < lmax) || !std::isfinite(a0) || !std::isfinite(lmax))
-      fail(XLS_ERR_INVALID_ARG, "bounds must satisfy a0 < lam_cut < lam_max");
-    ss.lmax = lmax;
-    ss.degree = p.degree;
-    ss.max_iter = p.max_iter;
-    ss.gprec = p.gemm_prec;
-    ss.pprec = polish_prec(p.gemm_prec, HUGE_VAL);
-    ss.resid_tol = p.resid_tol;
-    ss.gate = p.n_gate > 0 ? std::min(p.n_gate, s->ns)
-                           : std::max(1, static_cast<int>(std::floor(s->ns / 1.1 + 1e-9)));
-    ss.iters = 0;
-    ss.total_iters = 0;
-    ss.status = XLS_OK;
-    ss.fb_tol = p.bounds_mode == XLS_BOUNDS_LEARNED ? p.fallback_tol : 0.0;
-    ss.fb_degree = p.fallback_degree > 0 ? p.fallback_degree : p.degree;
-    ss.lanczos_k = p.lanczos_k;
-    ss.cur0 = s->cur;
-    s->happly = 0;
-    s->last_fallback = 0;
-    s->last_iters = 0;
-    ss.active = true;
-    if (ss.fb_tol > 0) {  // the start block, for a restart with Lanczos bounds
-      if (!s->backup) s->backup = dalloc<TS>(static_cast<size_t>(s->ld) * s->ns);
-      XLS_HIP(hipMemcpyAsync(s->backup, B<TS>(s, s->cur), static_cast<size_t>(s->ld) * s->ns * sizeof(TS),
-                             hipMemcpyDeviceToDevice, s->st));
-    }
-    launch_filter_coef(nullptr, s->ns, a0, lc, lmax, p.degree, b->coef[i], b->flags + i, s->st);
+void begin_run(xls_batch_s* b, int i, const xls_chefsi_params_t& p) {
+  xls_subdomain_s* s = b->subs[i];
+  SubState& ss = b->st[i];
+  double a0, lc, lmax;
+  if (p.bounds_mode == XLS_BOUNDS_GIVEN) {
+    a0 = p.lam_lo;
+    lc = p.lam_cut;
+    lmax = p.lam_max;
+  } else if (p.bounds_mode == XLS_BOUNDS_LANCZOS) {
+    lanczos_bounds_of<TS>(s, p.lanczos_k, a0, lc, lmax);
+  } else {
+    lmax = p.lam_max;
+    lc = p.lam_cut;
+    a0 = std::min(s->a0_bound, lc - 1e-3 * std::fabs(lmax - lc));
   }
-  for (auto* s : b->subs) XLS_HIP(hipStreamSynchronize(s->st));
-  std::vector<std::vector<double>> hl(n), hr(n);
-  for (int i = 0; i < n; ++i) {
-    hl[i].assign(b->subs[i]->ns, 0.0);
-    hr[i].assign(b->subs[i]->ns, 0.0);
+  if (!(a0 < lc && lc < lmax) || !std::isfinite(a0) || !std::isfinite(lmax))
+    fail(XLS_ERR_INVALID_ARG, "subdomain " + std::to_string(i) + ": bounds must satisfy a0 < lam_cut < lam_max");
+  ss.lmax = lmax;
+  ss.degree = p.degree;
+  ss.max_iter = p.max_iter;
+  ss.gprec = p.gemm_prec;
+  ss.pprec = polish_prec(p.gemm_prec, HUGE_VAL);
+  ss.resid_tol = p.resid_tol;
+  ss.gate = p.n_gate > 0 ? std::min(p.n_gate, s->ns) : std::max(1, static_cast<int>(std::floor(s->ns / 1.1 + 1e-9)));
+  ss.iters = 0;
+  ss.total_iters = 0;
+  ss.status = XLS_OK;
+  ss.fb_tol = p.bounds_mode == XLS_BOUNDS_LEARNED ? p.fallback_tol : 0.0;
+  ss.fb_degree = p.fallback_degree > 0 ? p.fallback_degree : p.degree;
+  ss.lanczos_k = p.lanczos_k;
+  ss.cur0 = s->cur;
+  ss.fell_back = false;
+  ss.started = true;
+  s->happly = 0;
+  s->last_fallback = 0;
+  s->last_iters = 0;
+  ss.active = true;
+  if (ss.fb_tol > 0 && !b->slots) {  // the start block, for a restart with Lanczos bounds
+    if (!s->backup) s->backup = dalloc<TS>(static_cast<size_t>(s->ld) * s->ns);
+    XLS_HIP(hipMemcpyAsync(s->backup, B<TS>(s, s->cur), static_cast<size_t>(s->ld) * s->ns * sizeof(TS),
+                           hipMemcpyDeviceToDevice, s->st));
   }
-  b->iterations = 0;
-  b->iter_ms = 0.0;
-  batch_loop<TS>(b, use_graph, hl, hr);
-  // Learned bounds that missed (NOT_SPD, or the gated residual above the
-  // fallback tolerance): restart those subdomains from their start blocks
-  // with Lanczos bounds and the fallback degree, in a second pass.
-  bool any = false;
-  for (int i = 0; i < n; ++i) {
-    SubState& ss = b->st[i];
-    xls_subdomain_s* s = b->subs[i];
-    if (!(ss.fb_tol > 0)) continue;
-    if (ss.status == XLS_OK && gated_max(hr[i].data(), ss.gate) <= ss.fb_tol) continue;
+  launch_filter_coef(nullptr, s->ns, a0, lc, lmax, p.degree, b->coef[i], b->flags + i, s->st);
+}
+
+// Learned bounds that missed (M_s not positive definite, or the gated
+// residual above fallback_tol or NaN) restart from the start block with
+// Lanczos bounds and the fallback degree.
+bool needs_fallback(const SubState& ss, const std::vector<double>& hr) {
+  if (!(ss.fb_tol > 0) || ss.fell_back) return false;
+  return ss.status != XLS_OK || !(gated_max(hr.data(), ss.gate) <= ss.fb_tol);
+}
+
+template <typename TS>
+void begin_fallback(xls_batch_s* b, int i) {
+  xls_subdomain_s* s = b->subs[i];
+  SubState& ss = b->st[i];
+  if (b->slots) {
+    load_start_block<TS>(s, nullptr);  // the start block is X0: drawn or uploaded again
+  } else {
     XLS_HIP(hipMemcpyAsync(B<TS>(s, ss.cur0), s->backup, static_cast<size_t>(s->ld) * s->ns * sizeof(TS),
                            hipMemcpyDeviceToDevice, s->st));
     s->cur = ss.cur0;
-    double a0, lc, lmax;
-    lanczos_bounds_of<TS>(s, ss.lanczos_k, a0, lc, lmax);
-    ss.lmax = lmax;
-    ss.degree = ss.fb_degree;
-    ss.pprec = polish_prec(ss.gprec, HUGE_VAL);
-    ss.iters = 0;
-    ss.status = XLS_OK;
-    ss.active = true;
-    s->last_fallback = 1;
-    launch_filter_coef(nullptr, s->ns, a0, lc, lmax, ss.degree, b->coef[i], b->flags + i, s->st);
-    any = true;
   }
-  if (any) {
-    for (auto* s : b->subs) XLS_HIP(hipStreamSynchronize(s->st));
-    batch_loop<TS>(b, use_graph, hl, hr);
-  }
+  double a0, lc, lmax;
+  lanczos_bounds_of<TS>(s, ss.lanczos_k, a0, lc, lmax);
+  ss.lmax = lmax;
+  ss.degree = ss.fb_degree;
+  ss.pprec = polish_prec(ss.gprec, HUGE_VAL);
+  ss.iters = 0;
+  ss.status = XLS_OK;
+  ss.active = true;
+  ss.fell_back = true;
+  s->last_fallback = 1;
+  launch_filter_coef(nullptr, s->ns, a0, lc, lmax, ss.degree, b->coef[i], b->flags + i, s->st);
 }
 
-// Batch iterations until no subdomain is active; hl, hr receive each
-// subdomain's last Ritz values and residuals.
+// One batch iteration over the active subdomains; updates their states and
+// returns those that became inactive.
 template <typename TS>
-void batch_loop(xls_batch_s* b, int use_graph, std::vector<std::vector<double>>& hl,
-                std::vector<std::vector<double>>& hr) {
-  const int n = b->n;
-  std::vector<int32_t> hflag(n), hspd(n);
-  for (;;) {
-    std::vector<int> act;
-    for (int i = 0; i < n; ++i)
-      if (b->st[i].active) act.push_back(i);
-    if (act.empty()) break;
-    run_iteration<TS>(b, act, use_graph != 0);
-    for (int i : act) {
-      xls_subdomain_s* s = b->subs[i];
-      XLS_HIP(hipMemcpyAsync(hl[i].data(), s->lam_dev, s->ns * 8, hipMemcpyDeviceToHost, b->main));
-      XLS_HIP(hipMemcpyAsync(hr[i].data(), s->resid_dev, s->ns * 8, hipMemcpyDeviceToHost, b->main));
-      XLS_HIP(hipMemcpyAsync(&hspd[i], s->dw.flag, 4, hipMemcpyDeviceToHost, b->main));
-      XLS_HIP(hipMemcpyAsync(&hflag[i], b->flags + i, 4, hipMemcpyDeviceToHost, b->main));
-    }
-    XLS_HIP(hipStreamSynchronize(b->main));
-    float ms = 0.0f;
-    XLS_HIP(hipEventElapsedTime(&ms, b->t0, b->t1));
-    b->last_iter_ms = ms;
-    b->iter_ms += ms;
-    ++b->iterations;
-    for (int i : act) {
-      xls_subdomain_s* s = b->subs[i];
-      SubState& ss = b->st[i];
-      s->cur = (s->cur + ss.degree + 1) & 1;
-      ++ss.iters;
-      ++ss.total_iters;
-      s->last_iters = ss.total_iters;
-      s->happly += static_cast<int64_t>(ss.degree + 1) * s->ns;  // filter + residual (H Psi_f counted by apply_H)
-      s->ritz = hl[i];
-      s->have_ritz = true;
-      if (hspd[i]) {
-        ss.status = XLS_ERR_NOT_SPD;
-        ss.active = false;
-        continue;
-      }
-      if (hflag[i]) {  // degenerate bounds for the next filter: stop with what we have
-        ss.active = false;
-        continue;
-      }
+std::vector<int> iterate_once(xls_batch_s* b, bool use_graph, std::vector<std::vector<double>>& hl,
+                              std::vector<std::vector<double>>& hr) {
+  std::vector<int> act, ended;
+  for (int i = 0; i < b->n; ++i)
+    if (b->st[i].active) act.push_back(i);
+  if (act.empty()) return ended;
+  b->max_active = std::max(b->max_active, static_cast<int>(act.size()));
+  std::vector<int32_t> hflag(b->n), hspd(b->n);
+  run_iteration<TS>(b, act, use_graph);
+  for (int i : act) {
+    xls_subdomain_s* s = b->subs[i];
+    XLS_HIP(hipMemcpyAsync(hl[i].data(), s->lam_dev, s->ns * 8, hipMemcpyDeviceToHost, b->main));
+    XLS_HIP(hipMemcpyAsync(hr[i].data(), s->resid_dev, s->ns * 8, hipMemcpyDeviceToHost, b->main));
+    XLS_HIP(hipMemcpyAsync(&hspd[i], s->dw.flag, 4, hipMemcpyDeviceToHost, b->main));
+    XLS_HIP(hipMemcpyAsync(&hflag[i], b->flags + i, 4, hipMemcpyDeviceToHost, b->main));
+  }
+  XLS_HIP(hipStreamSynchronize(b->main));
+  float ms = 0.0f;
+  XLS_HIP(hipEventElapsedTime(&ms, b->t0, b->t1));
+  b->last_iter_ms = ms;
+  b->iter_ms += ms;
+  ++b->iterations;
+  for (int i : act) {
+    xls_subdomain_s* s = b->subs[i];
+    SubState& ss = b->st[i];
+    s->cur = (s->cur + ss.degree + 1) & 1;
+    ++ss.iters;
+    ++ss.total_iters;
+    s->last_iters = ss.total_iters;
+    s->happly += static_cast<int64_t>(ss.degree + 1) * s->ns;  // filter + residual (H Psi_f counted by apply_H)
+    s->ritz = hl[i];
+    s->have_ritz = true;
+    if (hspd[i]) {
+      ss.status = XLS_ERR_NOT_SPD;
+      ss.active = false;
+    } else if (hflag[i]) {  // degenerate bounds for the next filter: stop with what we have
+      ss.active = false;
+    } else {
       const double mx = gated_max(hr[i].data(), ss.gate);
       ss.pprec = polish_prec(ss.gprec, mx);
       if (ss.resid_tol > 0 && mx <= ss.resid_tol) ss.active = false;
       if (ss.iters >= ss.max_iter) ss.active = false;
+    }
+    if (!ss.active) ended.push_back(i);
+  }
+  return ended;
+}
+
+// Slot residency: the subdomain's core rows move to its core store and its
+// working set is released.
+template <typename TS>
+void finalize_slot(xls_batch_s* b, int i) {
+  xls_subdomain_s* s = b->subs[i];
+  CoreStore& cs = b->core[i];
+  if (cs.ncore > 0) {
+    cs.release_blk();
+    cs.blk = dalloc<TS>(static_cast<size_t>(cs.ld) * s->ns);
+    launch_gather_rows<TS>(B<TS>(s, s->cur), s->ld, cs.rows, cs.ncore, s->ns, static_cast<TS*>(cs.blk), cs.ld,
+                           s->st);
+  }
+  XLS_HIP(hipStreamSynchronize(s->st));
+  b->resident_bytes -= static_cast<int64_t>(subdomain_ws_bytes(s, true));
+  subdomain_ws_free(s);
+}
+
+// Working set of subdomain i from the batch's budget, start block loaded.
+template <typename TS>
+void admit_slot(xls_batch_s* b, int i) {
+  xls_subdomain_s* s = b->subs[i];
+  const int p = static_cast<int>(std::find(b->pool.begin(), b->pool.end(), s->st) - b->pool.begin());
+  subdomain_ws_alloc(s, b->pool_gwork[p], b->pool_gwork_elems);
+  b->resident_bytes += static_cast<int64_t>(subdomain_ws_bytes(s, true));
+  b->peak_bytes = std::max(b->peak_bytes, b->resident_bytes);
+  load_start_block<TS>(s, nullptr);
+}
+
+// Device bytes a subdomain's run takes while resident (its working set plus
+// the Lanczos vectors when its bounds come from Lanczos).
+int64_t run_bytes(const xls_subdomain_s* s, const xls_chefsi_params_t& p) {
+  int64_t bytes = static_cast<int64_t>(subdomain_ws_bytes(s, true));
+  const bool lanczos = p.bounds_mode == XLS_BOUNDS_LANCZOS ||
+                       (p.bounds_mode == XLS_BOUNDS_LEARNED && p.fallback_tol > 0);
+  if (lanczos) bytes += static_cast<int64_t>(s->ld) * (lanczos_steps(s, p.lanczos_k) + 2) * s->esize();
+  return bytes;
+}
+
+template <typename TS>
+void batch_chefsi(xls_batch_s* b, const xls_chefsi_params_t* P, int use_graph) {
+  b->have_fermi = false;  // new blocks: a stored Fermi level no longer applies
+  const int n = b->n;
+  for (int i = 0; i < n; ++i) check_params(P[i], std::is_same<TS, double>::value);
+  std::vector<std::vector<double>> hl(n), hr(n);
+  for (int i = 0; i < n; ++i) {
+    hl[i].assign(b->subs[i]->ns, 0.0);
+    hr[i].assign(b->subs[i]->ns, 0.0);
+    b->st[i].started = false;
+    b->st[i].active = false;
+  }
+  b->iterations = 0;
+  b->iter_ms = 0.0;
+  b->max_active = 0;
+  // every pending subdomain, largest work first (the tail holds the small ones)
+  std::vector<int> pending;
+  if (b->slots) {
+    for (int i = 0; i < n; ++i) {
+      b->core[i].release_blk();
+      b->subs[i]->have_ritz = false;
+      pending.push_back(i);
+    }
+    std::stable_sort(pending.begin(), pending.end(), [&](int x, int y) {
+      const double cx = static_cast<double>(b->subs[x]->nd) * b->subs[x]->ns * P[x].degree;
+      const double cy = static_cast<double>(b->subs[y]->nd) * b->subs[y]->ns * P[y].degree;
+      return cx > cy;
+    });
+  } else {
+    for (int i = 0; i < n; ++i) begin_run<TS>(b, i, P[i]);
+    for (auto* s : b->subs) XLS_HIP(hipStreamSynchronize(s->st));
+  }
+  size_t next = 0;
+  for (;;) {
+    if (b->slots) {  // admit while the budget allows (always at least one)
+      bool any_active = false;
+      for (int i = 0; i < n; ++i) any_active = any_active || b->st[i].active;
+      std::vector<int> adm;
+      while (next < pending.size()) {
+        const int i = pending[next];
+        const int64_t need = run_bytes(b->subs[i], P[i]);
+        if ((any_active || !adm.empty()) && b->resident_bytes + need > b->budget) break;
+        admit_slot<TS>(b, i);
+        begin_run<TS>(b, i, P[i]);
+        if (b->subs[i]->lz && P[i].bounds_mode == XLS_BOUNDS_LANCZOS) {  // bounds cached: vectors not needed
+          XLS_HIP(hipStreamSynchronize(b->subs[i]->st));
+          dfree(b->subs[i]->lz);
+          b->subs[i]->lz = nullptr;
+          b->subs[i]->lz_cols = 0;
+        }
+        adm.push_back(i);
+        ++next;
+      }
+      for (int i : adm) XLS_HIP(hipStreamSynchronize(b->subs[i]->st));
+    }
+    const std::vector<int> ended = iterate_once<TS>(b, use_graph != 0, hl, hr);
+    if (ended.empty()) {
+      bool any = false;
+      for (int i = 0; i < n; ++i) any = any || b->st[i].active;
+      if (!any && (!b->slots || next >= pending.size())) break;
+      continue;
+    }
+    for (int i : ended) {
+      if (needs_fallback(b->st[i], hr[i])) {
+        begin_fallback<TS>(b, i);
+        XLS_HIP(hipStreamSynchronize(b->subs[i]->st));
+      } else if (b->slots) {
+        finalize_slot<TS>(b, i);
+      }
     }
   }
 }
@@ -514,7 +655,13 @@ int tune_batch(xls_batch_s* b, const char* cache_path, double* best_ms_out) {
         chosen[key] = hit->second;
         continue;
       }
-      // zero the spare block's Y_{k-1} role: time on the real block's data
+      // slot residency: a temporary working set with the start block
+      const bool temp = !s->resident;
+      if (temp) {
+        const int p = static_cast<int>(std::find(b->pool.begin(), b->pool.end(), s->st) - b->pool.begin());
+        subdomain_ws_alloc(s, b->pool_gwork[p], b->pool_gwork_elems);
+        load_start_block<TS>(s, nullptr);
+      }
       double best = 1e30;
       Shape arg{256, 0, 1};
       for (int nv : {1, 2})
@@ -535,6 +682,7 @@ int tune_batch(xls_batch_s* b, const char* cache_path, double* best_ms_out) {
             arg = {block, ty, nv};
           }
         }
+      if (temp) subdomain_ws_free(s);
       chosen[key] = arg;
       best_ms[key] = best;
       ++tuned;
@@ -565,46 +713,135 @@ int tune_batch(xls_batch_s* b, const char* cache_path, double* best_ms_out) {
 
 }  // namespace
 
+namespace {
+
+// The rows the occupation calls read: the whole block with the core mask
+// (resident batches), or the core store with an all-ones mask (slot
+// residency).  STATE when a subdomain has no block.
+struct BlockView {
+  const void* psi;
+  int64_t nd, ld;
+  const uint8_t* mask;
+};
+
+BlockView view_of(xls_batch_s* b, int i) {
+  xls_subdomain_s* s = b->subs[i];
+  if (!s->have_ritz) fail(XLS_ERR_STATE, "needs a completed xls_batch_chefsi");
+  if (!b->slots) return BlockView{s->blk[s->cur], s->nd, s->ld, s->mask};
+  const CoreStore& cs = b->core[i];
+  if (cs.ncore > 0 && !cs.blk) fail(XLS_ERR_STATE, "subdomain has no stored core block");
+  return BlockView{cs.blk, cs.ncore, cs.ld, b->ones};
+}
+
+// rho (2/h^3) sum_n g_n psi_n^2 over the view's rows, c_n into resid_dev
+// (the handle's scratch for per-state values); returns the device rho.
+double* density_rows(xls_batch_s* b, int i, const BlockView& v, double mu, double sigma, hipStream_t st) {
+  xls_subdomain_s* s = b->subs[i];
+  if (b->slots) {
+    dfree(s->rho_dev);
+    s->rho_dev = nullptr;
+    s->rho_dev = dalloc<double>(static_cast<size_t>(std::max<int64_t>(1, v.nd)));
+  } else if (!s->rho_dev) {
+    s->rho_dev = dalloc<double>(s->nd);
+  }
+  XLS_HIP(hipMemcpyAsync(s->lam_dev, s->ritz.data(), s->ns * 8, hipMemcpyHostToDevice, st));
+  launch_density(s->lam_dev, mu, sigma, v.mask, s->h, v.psi, s->prec == XLS_PREC_FP32, v.nd, v.ld, s->ns,
+                 s->rho_dev, s->cpart, 64, s->resid_dev, s->gocc, st);
+  return s->rho_dev;
+}
+
+// Shared part of both create calls; slot_budget < 0: everything resident.
+xls_batch_s* batch_new(int32_t n, const xls_subdomain_desc_t* descs, int64_t slot_budget) {
+  if (!descs || n < 1) fail(XLS_ERR_INVALID_ARG, "bad argument");
+  for (int i = 1; i < n; ++i)
+    if (descs[i].filter_prec != descs[0].filter_prec)
+      fail(XLS_ERR_INVALID_ARG, "all subdomains of a batch share one filter precision");
+  auto* b = new xls_batch_s();
+  try {
+    b->n = n;
+    b->prec = descs[0].filter_prec;
+    b->slots = slot_budget >= 0;
+    XLS_HIP(hipStreamCreateWithFlags(&b->main, hipStreamNonBlocking));
+    const int np = std::min(n, kPoolStreams);
+    for (int p = 0; p < np; ++p) {
+      hipStream_t st;
+      XLS_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+      b->pool.push_back(st);
+      hipEvent_t e;
+      XLS_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      b->ev_join.push_back(e);
+    }
+    XLS_HIP(hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming));
+    XLS_HIP(hipEventCreate(&b->t0));
+    XLS_HIP(hipEventCreate(&b->t1));
+    b->flags = dalloc<int32_t>(n);
+    b->subs.assign(n, nullptr);
+    b->st.assign(n, SubState{});
+    for (int i = 0; i < n; ++i) {
+      xls_subdomain_desc_t d = descs[i];
+      d.stream = b->pool[i % np];
+      if (!b->slots) {
+        const int rc = xls_subdomain_create(&d, &b->subs[i]);
+        if (rc != XLS_OK) fail(rc, "subdomain " + std::to_string(i) + ": " + xls_last_error());
+      } else {
+        b->subs[i] = subdomain_create_tables(&d);
+      }
+      b->coef.push_back(dalloc<double>(3 * kMaxDegree));
+    }
+    if (b->slots) {
+      // split-K workspace per pool stream: the largest any of its handles needs
+      size_t need = 64 * 1024;
+      int64_t max_core = 1;
+      for (auto* s : b->subs) {
+        need = std::max(need, gemm_tn_work_elems(s->ns, s->ns, s->nd));
+        need = std::max(need, gemm_tn_work_elems(s->ns, s->ns, s->ns));
+      }
+      b->pool_gwork_elems = need;
+      for (size_t p = 0; p < b->pool.size(); ++p) b->pool_gwork.push_back(dalloc<double>(need));
+      b->core.resize(n);
+      for (int i = 0; i < n; ++i) {
+        xls_subdomain_s* s = b->subs[i];
+        CoreStore& cs = b->core[i];
+        for (int64_t g = 0; g < s->nd; ++g)
+          if (s->tab.core_mask[g]) cs.hrows.push_back(static_cast<int32_t>(g));
+        cs.ncore = static_cast<int64_t>(cs.hrows.size());
+        cs.ld = (cs.ncore + 63) / 64 * 64;
+        max_core = std::max(max_core, cs.ncore);
+        cs.rows = dalloc<int32_t>(std::max<int64_t>(1, cs.ncore));
+        if (cs.ncore > 0)
+          XLS_HIP(hipMemcpy(cs.rows, cs.hrows.data(), cs.ncore * 4, hipMemcpyHostToDevice));
+      }
+      b->ones = dalloc<uint8_t>(max_core);
+      b->ones_n = max_core;
+      XLS_HIP(hipMemset(b->ones, 1, max_core));
+      size_t free_b = 0, total_b = 0;
+      XLS_HIP(hipMemGetInfo(&free_b, &total_b));
+      b->budget = slot_budget > 0 ? slot_budget : static_cast<int64_t>(0.85 * static_cast<double>(free_b));
+    }
+  } catch (...) {
+    delete b;
+    throw;
+  }
+  return b;
+}
+
+}  // namespace
+
 extern "C" {
+
+int xls_batch_create_slots(int32_t n, const xls_subdomain_desc_t* descs, int64_t max_resident_bytes,
+                           xls_batch_t* out) {
+  return guarded([&]() -> int {
+    if (!out || max_resident_bytes < 0) fail(XLS_ERR_INVALID_ARG, "bad argument");
+    *out = batch_new(n, descs, max_resident_bytes);
+    return XLS_OK;
+  });
+}
 
 int xls_batch_create(int32_t n, const xls_subdomain_desc_t* descs, xls_batch_t* out) {
   return guarded([&]() -> int {
-    if (!out || !descs || n < 1) fail(XLS_ERR_INVALID_ARG, "bad argument");
-    for (int i = 1; i < n; ++i)
-      if (descs[i].filter_prec != descs[0].filter_prec)
-        fail(XLS_ERR_INVALID_ARG, "all subdomains of a batch share one filter precision");
-    auto* b = new xls_batch_s();
-    try {
-      b->n = n;
-      b->prec = descs[0].filter_prec;
-      XLS_HIP(hipStreamCreateWithFlags(&b->main, hipStreamNonBlocking));
-      const int np = std::min(n, kPoolStreams);
-      for (int p = 0; p < np; ++p) {
-        hipStream_t s;
-        XLS_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
-        b->pool.push_back(s);
-        hipEvent_t e;
-        XLS_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-        b->ev_join.push_back(e);
-      }
-      XLS_HIP(hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming));
-      XLS_HIP(hipEventCreate(&b->t0));
-      XLS_HIP(hipEventCreate(&b->t1));
-      b->flags = dalloc<int32_t>(n);
-      b->subs.assign(n, nullptr);
-      b->st.assign(n, SubState{});
-      for (int i = 0; i < n; ++i) {
-        xls_subdomain_desc_t d = descs[i];
-        d.stream = b->pool[i % np];
-        const int rc = xls_subdomain_create(&d, &b->subs[i]);
-        if (rc != XLS_OK) fail(rc, "subdomain " + std::to_string(i) + ": " + xls_last_error());
-        b->coef.push_back(dalloc<double>(3 * kMaxDegree));
-      }
-    } catch (...) {
-      delete b;
-      throw;
-    }
-    *out = b;
+    if (!out) fail(XLS_ERR_INVALID_ARG, "bad argument");
+    *out = batch_new(n, descs, -1);
     return XLS_OK;
   });
 }
@@ -638,10 +875,23 @@ int xls_batch_chefsi(xls_batch_t b, const xls_chefsi_params_t* per_sub, double* 
 int xls_batch_density(xls_batch_t b, double mu, double sigma, double* rho_concat, double* c_concat) {
   return guarded([&]() -> int {
     if (!b || !rho_concat || !c_concat) fail(XLS_ERR_INVALID_ARG, "bad argument");
+    if (!(sigma > 0) || !std::isfinite(sigma) || !std::isfinite(mu)) fail(XLS_ERR_INVALID_ARG, "bad mu/sigma");
     int64_t off_r = 0, off_c = 0;
-    for (auto* s : b->subs) {
-      const int rc = xls_subdomain_density(s, mu, sigma, rho_concat + off_r, c_concat + off_c);
-      if (rc != XLS_OK) fail(rc, xls_last_error());
+    for (int i = 0; i < b->n; ++i) {
+      xls_subdomain_s* s = b->subs[i];
+      if (!b->slots) {
+        const int rc = xls_subdomain_density(s, mu, sigma, rho_concat + off_r, c_concat + off_c);
+        if (rc != XLS_OK) fail(rc, xls_last_error());
+      } else {  // core rows only: rho is zero elsewhere
+        const BlockView v = view_of(b, i);
+        double* rho = density_rows(b, i, v, mu, sigma, s->st);
+        std::vector<double> hr(static_cast<size_t>(std::max<int64_t>(1, v.nd)));
+        XLS_HIP(hipMemcpyAsync(hr.data(), rho, v.nd * 8, hipMemcpyDeviceToHost, s->st));
+        XLS_HIP(hipMemcpyAsync(c_concat + off_c, s->resid_dev, s->ns * 8, hipMemcpyDeviceToHost, s->st));
+        XLS_HIP(hipStreamSynchronize(s->st));
+        std::fill(rho_concat + off_r, rho_concat + off_r + s->nd, 0.0);
+        for (int64_t r = 0; r < v.nd; ++r) rho_concat[off_r + b->core[i].hrows[r]] = hr[r];
+      }
       off_r += s->nd;
       off_c += s->ns;
     }
@@ -673,10 +923,12 @@ int xls_batch_fermi(xls_batch_t b, double sigma, double n_electrons, double* out
     if (!b->fout) b->fout = dalloc<double>(8);
     b->have_fermi = false;
     int64_t off = 0;
-    for (auto* s : b->subs) {
+    for (int i = 0; i < b->n; ++i) {
+      xls_subdomain_s* s = b->subs[i];
+      const BlockView v = view_of(b, i);
       XLS_HIP(hipMemcpyAsync(b->lam_all + off, s->ritz.data(), s->ns * 8, hipMemcpyHostToDevice, b->main));
-      launch_core_weights(s->mask, s->blk[s->cur], s->prec == XLS_PREC_FP32, s->nd, s->ld, s->ns, s->cpart, 64,
-                          b->c_all + off, b->main);
+      launch_core_weights(v.mask, v.psi, s->prec == XLS_PREC_FP32, v.nd, v.ld, s->ns, s->cpart, 64, b->c_all + off,
+                          b->main);
       off += s->ns;
     }
     launch_fermi_level(b->lam_all, b->c_all, total, sigma, n_electrons, 200, b->fout, b->main);
@@ -707,6 +959,7 @@ int xls_batch_assemble(xls_batch_t b, int64_t n_global, double* rho_global, int3
         b->gidx.assign(b->subs.size(), nullptr);
         b->gidx_ok.assign(b->subs.size(), 0);
       }
+      for (int i = 0; i < b->n; ++i) (void)view_of(b, i);  // STATE unless every block is available
       // every core point inside the global grid, and distinct within a subdomain
       for (size_t i = 0; i < b->subs.size(); ++i) {
         auto* s = b->subs[i];
@@ -733,16 +986,17 @@ int xls_batch_assemble(xls_batch_t b, int64_t n_global, double* rho_global, int3
       XLS_HIP(hipMemsetAsync(b->rho_global, 0, n_global * 8, b->main));
       for (size_t i = 0; i < b->subs.size(); ++i) {
         auto* s = b->subs[i];
-        if (!b->gidx[i]) {
-          b->gidx[i] = dalloc<int64_t>(s->nd);
-          XLS_HIP(hipMemcpyAsync(b->gidx[i], s->tab.global_index.data(), s->nd * 8, hipMemcpyHostToDevice,
-                                 b->main));
+        const BlockView v = view_of(b, static_cast<int>(i));
+        if (!b->gidx[i]) {  // global index of every row of the view
+          std::vector<int64_t> gi(static_cast<size_t>(std::max<int64_t>(1, v.nd)));
+          for (int64_t r = 0; r < v.nd; ++r)
+            gi[r] = s->tab.global_index[b->slots ? b->core[i].hrows[r] : r];
+          b->gidx[i] = dalloc<int64_t>(gi.size());
+          XLS_HIP(hipMemcpyAsync(b->gidx[i], gi.data(), v.nd * 8, hipMemcpyHostToDevice, b->main));
+          XLS_HIP(hipStreamSynchronize(b->main));
         }
-        if (!s->rho_dev) s->rho_dev = dalloc<double>(s->nd);
-        XLS_HIP(hipMemcpyAsync(s->lam_dev, s->ritz.data(), s->ns * 8, hipMemcpyHostToDevice, b->main));
-        launch_density(s->lam_dev, b->mu, b->sigma, s->mask, s->h, s->blk[s->cur], s->prec == XLS_PREC_FP32, s->nd,
-                       s->ld, s->ns, s->rho_dev, s->cpart, 64, s->resid_dev, s->gocc, b->main);
-        launch_scatter_core(s->rho_dev, s->mask, b->gidx[i], s->nd, b->rho_global, b->main);
+        double* rho = density_rows(b, static_cast<int>(i), v, b->mu, b->sigma, b->main);
+        launch_scatter_core(rho, v.mask, b->gidx[i], v.nd, b->rho_global, b->main);
       }
       XLS_HIP(hipMemcpyAsync(rho_global, b->rho_global, n_global * 8, hipMemcpyDeviceToHost, b->main));
     }
@@ -785,10 +1039,12 @@ int xls_batch_tune(xls_batch_t b, const char* cache_path, int32_t* tuned, double
 int xls_batch_stats(xls_batch_t b, double* out, int32_t cap) {
   return guarded([&]() -> int {
     if (!b || !out || cap < 1) fail(XLS_ERR_INVALID_ARG, "bad argument");
-    const double v[5] = {static_cast<double>(b->iterations), static_cast<double>(b->captures),
-                         static_cast<double>(b->replays), b->iter_ms, b->last_iter_ms};
-    for (int k = 0; k < std::min(cap, 5); ++k) out[k] = v[k];
-    return XLS_OK;
+    const double v[7] = {static_cast<double>(b->iterations), static_cast<double>(b->captures),
+                         static_cast<double>(b->replays), b->iter_ms, b->last_iter_ms,
+                         static_cast<double>(b->peak_bytes), static_cast<double>(b->max_active)};
+    const int k = std::min(cap, 7);
+    for (int i = 0; i < k; ++i) out[i] = v[i];
+    return k;
   });
 }
 

@@ -1377,7 +1377,15 @@ void set_smem(const void* fn, size_t bytes) { ensure_dyn_smem(fn, bytes); }
 
 }  // namespace
 
-void dense_alloc(DenseWork& w, int n) {
+size_t dense_bytes(int n, bool own_gemm_work) {
+  const size_t nn = static_cast<size_t>(n) * n;
+  size_t b = 7 * nn * 8 + static_cast<size_t>(n) * 8 * DenseWork::kVecs + (static_cast<size_t>(n) + 16) * 8 + 64 +
+             static_cast<size_t>(n) * 4 * DenseWork::kIvecs + 64;
+  if (own_gemm_work) b += gemm_tn_work_elems(n, n, n) * 8;
+  return b;
+}
+
+void dense_alloc(DenseWork& w, int n, double* ext_work, size_t ext_elems) {
   dense_free(w);
   if (n < 1 || n > kDenseMaxN) fail(XLS_ERR_INVALID_ARG, "dense eigensolver supports 1 <= n <= 2800");
   w.n = n;
@@ -1392,11 +1400,21 @@ void dense_alloc(DenseWork& w, int n) {
   al(reinterpret_cast<void**>(&w.scal), (static_cast<size_t>(n) + 16) * 8);
   al(reinterpret_cast<void**>(&w.flag), 64);
   al(reinterpret_cast<void**>(&w.ivec), static_cast<size_t>(n) * 4 * DenseWork::kIvecs + 64);
-  w.gemm_work_elems = gemm_tn_work_elems(n, n, n);
-  al(reinterpret_cast<void**>(&w.gemm_work), w.gemm_work_elems * 8);
+  if (ext_work) {
+    if (ext_elems < nn) fail(XLS_ERR_INVALID_ARG, "shared dense GEMM workspace too small");
+    w.gemm_work = ext_work;
+    w.gemm_work_elems = ext_elems;
+    w.own_gemm_work = false;
+  } else {
+    w.gemm_work_elems = gemm_tn_work_elems(n, n, n);
+    al(reinterpret_cast<void**>(&w.gemm_work), w.gemm_work_elems * 8);
+    w.own_gemm_work = true;
+  }
 }
 
 void dense_free(DenseWork& w) {
+  if (!w.own_gemm_work) w.gemm_work = nullptr;  // borrowed: the owner frees it
+  w.own_gemm_work = true;
   double** ds[] = {&w.R, &w.Rinv, &w.C0, &w.C1, &w.T, &w.Vh, &w.Z, &w.vec, &w.scal, &w.gemm_work};
   for (double** p : ds)
     if (*p) {

@@ -893,10 +893,12 @@ size_t nn_work_doubles(int K, int N) {
 }
 
 size_t gemm_tn_work_elems(int M, int N, int64_t K) {
-  (void)K;
-  // room for up to 64 splits, capped at 32 Mi doubles (256 MB)
+  // room for every split either kernel takes (each split keeps >= 8 k-blocks
+  // of >= 16, so at most K/128 of them; at most 64), capped at 32 Mi doubles
+  // (256 MB)
   const size_t per = static_cast<size_t>(M) * N;
-  return std::max<size_t>(per, std::min<size_t>(64 * per, static_cast<size_t>(32) << 20));
+  const size_t splits = static_cast<size_t>(std::min<int64_t>(64, std::max<int64_t>(1, K / 128)));
+  return std::max<size_t>(per, std::min<size_t>(splits * per, static_cast<size_t>(32) << 20));
 }
 
 template <typename TS>

@@ -220,6 +220,49 @@ __global__ void half_to_block_kernel(const uint16_t* __restrict__ src, int64_t l
   dst[r + c * ld] = static_cast<TS>(__builtin_bit_cast(_Float16, src[r + c * nd]));
 }
 
+// Counter-based start block: Philox4x32-10 (multipliers 0xD2511F53 and
+// 0xCD9E8D57, Weyl key increments 0x9E3779B9 and 0xBB67AE85, 10 rounds) on
+// counter (g, j, 0, 0), then Box-Muller on two 53-bit uniforms in (0, 1].
+__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t lo0 = 0xD2511F53u * c[0], hi0 = __umulhi(0xD2511F53u, c[0]);
+    const uint32_t lo1 = 0xCD9E8D57u * c[2], hi1 = __umulhi(0xCD9E8D57u, c[2]);
+    const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0;
+    c[1] = lo1;
+    c[2] = n2;
+    c[3] = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+}
+
+template <typename TS>
+__global__ void philox_block_kernel(TS* __restrict__ blk, int64_t ld, int64_t nd, uint32_t k0, uint32_t k1) {
+  const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const uint32_t j = blockIdx.y;
+  if (g >= nd) return;
+  uint32_t c[4] = {static_cast<uint32_t>(g), j, 0u, 0u};
+  philox4x32_10(c, k0, k1);
+  const uint64_t a = (static_cast<uint64_t>(c[0] >> 5) << 26) + (c[1] >> 6);
+  const uint64_t b = (static_cast<uint64_t>(c[2] >> 5) << 26) + (c[3] >> 6);
+  const double twom53 = 1.1102230246251565e-16;  // 2^-53
+  const double u1 = 1.0 - static_cast<double>(a) * twom53;
+  const double u2 = 1.0 - static_cast<double>(b) * twom53;
+  const double two_pi = 6.283185307179586;  // 2 * fl(pi), exact
+  blk[g + static_cast<int64_t>(j) * ld] = static_cast<TS>(sqrt(-2.0 * log(u1)) * cos(two_pi * u2));
+}
+
+template <typename TS>
+__global__ void gather_rows_kernel(const TS* __restrict__ blk, int64_t ld, const int32_t* __restrict__ rows,
+                                   int64_t nrows, TS* __restrict__ out, int64_t ldo) {
+  const int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t c = blockIdx.y;
+  if (r >= nrows) return;
+  out[r + c * ldo] = blk[rows[r] + c * ld];
+}
+
 // rho[g] = (2/h^3) sum_n g_n psi_{g,n}^2 on core points, 0 elsewhere.
 template <typename TS>
 __global__ __launch_bounds__(256) void rho_kernel(const TS* __restrict__ psi, int64_t nd, int64_t ld,
@@ -424,6 +467,29 @@ void launch_block_half(const TS* blk, int64_t ld, int64_t nd, int ncols, uint16_
 }
 template void launch_block_half<float>(const float*, int64_t, int64_t, int, uint16_t*, int, hipStream_t);
 template void launch_block_half<double>(const double*, int64_t, int64_t, int, uint16_t*, int, hipStream_t);
+
+template <typename TS>
+void launch_philox_block(TS* blk, int64_t ld, int64_t nd, int ncols, uint64_t seed, hipStream_t st) {
+  if (nd <= 0 || ncols <= 0) return;
+  hipLaunchKernelGGL(philox_block_kernel<TS>, dim3(nblk(nd, 256), static_cast<unsigned>(ncols)), dim3(256), 0, st,
+                     blk, ld, nd, static_cast<uint32_t>(seed & 0xFFFFFFFFu), static_cast<uint32_t>(seed >> 32));
+  XLS_LAUNCH_CHECK("philox_block_kernel");
+}
+template void launch_philox_block<float>(float*, int64_t, int64_t, int, uint64_t, hipStream_t);
+template void launch_philox_block<double>(double*, int64_t, int64_t, int, uint64_t, hipStream_t);
+
+template <typename TS>
+void launch_gather_rows(const TS* blk, int64_t ld, const int32_t* rows, int64_t nrows, int ncols, TS* out,
+                        int64_t ldo, hipStream_t st) {
+  if (nrows <= 0 || ncols <= 0) return;
+  hipLaunchKernelGGL(gather_rows_kernel<TS>, dim3(nblk(nrows, 256), static_cast<unsigned>(ncols)), dim3(256), 0,
+                     st, blk, ld, rows, nrows, out, ldo);
+  XLS_LAUNCH_CHECK("gather_rows_kernel");
+}
+template void launch_gather_rows<float>(const float*, int64_t, const int32_t*, int64_t, int, float*, int64_t,
+                                        hipStream_t);
+template void launch_gather_rows<double>(const double*, int64_t, const int32_t*, int64_t, int, double*, int64_t,
+                                         hipStream_t);
 
 void launch_core_weights(const uint8_t* mask, const void* psi, int is_float, int64_t nd, int64_t ld, int ns,
                          double* cpart, int nchunk, double* c, hipStream_t st) {

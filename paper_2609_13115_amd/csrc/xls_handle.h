@@ -59,11 +59,20 @@ struct xls_subdomain_s {
   float* bwork = nullptr;
   double* gwork = nullptr;
   size_t gwork_elems = 0;
+  bool own_gwork = true;  // false: a batch's per-stream split-K workspace
   DenseWork dw;
   double* vsmall = nullptr;  // density / Lanczos scalars
   double* rho_dev = nullptr;
   double* cpart = nullptr;
   double* gocc = nullptr;
+  // start block: the caller's (uploaded at create, or kept here for a batch
+  // that allocates working sets on demand), else drawn on the device from
+  // x0_seed (counter-based, Philox4x32-10 + Box-Muller)
+  std::vector<double> x0_host;
+  uint64_t x0_seed = 0;
+  bool x0_gen = false;
+  // working set (blocks, projections, GEMM and dense workspaces) allocated
+  bool resident = false;
   // Lanczos
   std::vector<double> lanczos_v0;
   void* lz = nullptr;  // [nd * (kmax + 2)]
@@ -91,8 +100,9 @@ struct xls_subdomain_s {
   ~xls_subdomain_s() {
     void* ps[] = {v64, v32, val64, val32, rev_pk, rev_aoff, rev_val64, rev_val32, sup_off, sup_idx, gamma, mask,
                   blk[0], blk[1], alpha, alpha64, partial, lam_dev, resid_dev, Mdev, Hsdev, Ydev, bwork,
-                  gwork, vsmall, rho_dev, cpart, gocc, lz, backup};
+                  vsmall, rho_dev, cpart, gocc, lz, backup};
     for (void* p : ps) xls::dfree(p);
+    if (own_gwork) xls::dfree(gwork);
     for (auto e : fev) (void)hipEventDestroy(e);
     if (dexec) (void)hipGraphExecDestroy(dexec);
     if (dgraph) (void)hipGraphDestroy(dgraph);
@@ -110,6 +120,8 @@ bool profiling_on();
 bool graphs_on();
 void dfree(void* p);
 bool finite_all(const double* p, int64_t n);
+// STATE unless the handle's working set is allocated.
+void require_resident(const xls_subdomain_s* s);
 
 template <typename T>
 T* dalloc(size_t n) {
@@ -174,6 +186,24 @@ int lanczos_steps(const xls_subdomain_s* s, int k);
 // Largest of r[0..gate); NaN when any of them is NaN (a NaN residual is a
 // miss of every gate).
 double gated_max(const double* r, int gate);
+
+// Handle construction in parts (api.cpp).  subdomain_tables: geometry,
+// operator tables and small per-state buffers (always resident); keep_x0
+// keeps a copy of the caller's start block for later loads.
+// subdomain_ws_alloc / _free: the working set (both blocks, projection
+// coefficients, GEMM and dense workspaces); shared_gwork (may be null) is a
+// split-K workspace the caller owns and shares between handles that issue
+// on one stream.  subdomain_ws_bytes: device bytes of the working set.
+// load_start_block: the start block into block 0 (x0, else the kept copy,
+// else drawn on the device from x0_seed).
+void subdomain_tables(xls_subdomain_s* s, const xls_subdomain_desc_t* d, bool keep_x0);
+// A validated handle with its tables only (no working set), keeping the caller's x0.
+xls_subdomain_s* subdomain_create_tables(const xls_subdomain_desc_t* d);
+size_t subdomain_ws_bytes(const xls_subdomain_s* s, bool shared_gemm_work);
+void subdomain_ws_alloc(xls_subdomain_s* s, double* shared_gwork, size_t shared_elems);
+void subdomain_ws_free(xls_subdomain_s* s);
+template <typename TS>
+void load_start_block(xls_subdomain_s* s, const double* x0);
 
 // Stage helpers on the handle's stream (api.cpp).
 template <typename TS>

@@ -180,10 +180,15 @@ struct DenseWork {
   int32_t* ivec = nullptr;     // kIvecs * n ints + cluster count
   double* gemm_work = nullptr;
   size_t gemm_work_elems = 0;
+  bool own_gemm_work = true;
   const double* lam() const { return vec; }
 };
-void dense_alloc(DenseWork& w, int n);
+// ext_work (may be null): a split-K workspace of ext_elems doubles owned by
+// the caller (at least n*n), used instead of an own one.
+void dense_alloc(DenseWork& w, int n, double* ext_work = nullptr, size_t ext_elems = 0);
 void dense_free(DenseWork& w);
+// device bytes dense_alloc takes for n (with or without its own split-K workspace)
+size_t dense_bytes(int n, bool own_gemm_work);
 // On XLS_OK, w.lam() (device, ascending) and Y (device, n x n, M-orthonormal
 // columns) hold the result; XLS_ERR_NOT_SPD when M is not positive definite.
 // Synchronises st once (after the Cholesky factorisation) when check_spd.
@@ -204,6 +209,17 @@ void launch_reduce_cols(const double* partial, int nper, int ncols, double* out,
 void launch_density(const double* lam, double mu, double sigma, const uint8_t* mask, double h,
                     const void* psi, int is_float, int64_t nd, int64_t ld, int ns, double* rho,
                     double* cpart, int nchunk, double* c, double* gocc, hipStream_t st);
+// Start blocks drawn on the device: blk[g + j ld] for g < nd, j < ncols is the
+// standard normal of counter (g, j, 0, 0) under key (seed mod 2^32,
+// seed >> 32): Philox4x32-10 (Salmon et al., SC 2011) words (o0, o1, o2,
+// o3), u1 = 1 - (2^26 (o0 >> 5) + (o1 >> 6)) 2^-53, u2 likewise from
+// (o2, o3), x = sqrt(-2 ln u1) cos(2 pi u2) (Box-Muller), rounded to TS.
+template <typename TS>
+void launch_philox_block(TS* blk, int64_t ld, int64_t nd, int ncols, uint64_t seed, hipStream_t st);
+// out[r + c ldo] = blk[rows[r] + c ld] for r < nrows, c < ncols
+template <typename TS>
+void launch_gather_rows(const TS* blk, int64_t ld, const int32_t* rows, int64_t nrows, int ncols, TS* out,
+                        int64_t ldo, hipStream_t st);
 // to_half: half[r + c nd] = binary16(blk[r + c ld]) (round to nearest even);
 // otherwise blk[r + c ld] = half[r + c nd] widened (blk is written)
 template <typename TS>

@@ -53,6 +53,60 @@ def _rng(*key: int) -> np.random.Generator:
     return np.random.Generator(np.random.PCG64(np.random.SeedSequence([int(k) for k in key])))
 
 
+# ---------------------------------------------------------------------------
+# Counter-based start blocks.  Large batches draw their start blocks on the
+# device; both sides implement the same published generator: Philox4x32-10
+# (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as easy as 1, 2, 3",
+# SC 2011) and the Box-Muller transform.  Element (g, j) of a block with
+# seed s uses counter (g, j, 0, 0) and key (s mod 2^32, s >> 32):
+#   u1 = 1 - (2^26 (o0 >> 5) + (o1 >> 6)) / 2^53,  u2 likewise from (o2, o3),
+#   x  = sqrt(-2 ln u1) cos(2 pi u2).
+# ---------------------------------------------------------------------------
+_PHILOX_M0 = np.uint64(0xD2511F53)
+_PHILOX_M1 = np.uint64(0xCD9E8D57)
+_PHILOX_W0 = 0x9E3779B9
+_PHILOX_W1 = 0xBB67AE85
+_MASK32 = np.uint64(0xFFFFFFFF)
+
+
+def philox4x32_10(c0, c1, c2, c3, k0: int, k1: int):
+    """Philox4x32 with 10 rounds on uint32 counter arrays; returns four uint32 arrays."""
+    c = [np.asarray(x, dtype=np.uint64) & _MASK32 for x in (c0, c1, c2, c3)]
+    c = np.broadcast_arrays(*c)
+    c = [x.copy() for x in c]
+    k0, k1 = int(k0) & 0xFFFFFFFF, int(k1) & 0xFFFFFFFF
+    for _ in range(10):
+        p0 = _PHILOX_M0 * c[0]
+        p1 = _PHILOX_M1 * c[2]
+        hi0, lo0 = p0 >> np.uint64(32), p0 & _MASK32
+        hi1, lo1 = p1 >> np.uint64(32), p1 & _MASK32
+        c = [hi1 ^ c[1] ^ np.uint64(k0), lo1, hi0 ^ c[3] ^ np.uint64(k1), lo0]
+        k0 = (k0 + _PHILOX_W0) & 0xFFFFFFFF
+        k1 = (k1 + _PHILOX_W1) & 0xFFFFFFFF
+    return [x.astype(np.uint32) for x in c]
+
+
+def philox_normal_block(nd: int, ncols: int, seed: int, col0: int = 0) -> np.ndarray:
+    """f64[nd, ncols] (Fortran order) of standard normals, column j drawn with
+    counter column index col0 + j."""
+    out = np.empty((nd, ncols), order="F")
+    g = np.arange(nd, dtype=np.uint64)
+    k0, k1 = seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF
+    for j in range(ncols):
+        o0, o1, o2, o3 = philox4x32_10(g, col0 + j, 0, 0, k0, k1)
+        a = (o0.astype(np.uint64) >> np.uint64(5)) * np.uint64(67108864) + (o1.astype(np.uint64) >> np.uint64(6))
+        b = (o2.astype(np.uint64) >> np.uint64(5)) * np.uint64(67108864) + (o3.astype(np.uint64) >> np.uint64(6))
+        u1 = 1.0 - a.astype(np.float64) / 9007199254740992.0
+        u2 = 1.0 - b.astype(np.float64) / 9007199254740992.0
+        out[:, j] = np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * np.pi * u2)
+    return out
+
+
+def x0_seed(key: Tuple[int, ...]) -> int:
+    """64-bit seed of a subdomain's counter-based start block, from its key."""
+    return int(np.random.SeedSequence([int(k) for k in key] + [0x5830]).generate_state(1, np.uint64)[0])
+
+
 @dataclasses.dataclass
 class Subdomain:
     """Everything the subdomain problem is defined by (Sec. V-A.2/V-A.3).

@@ -45,6 +45,7 @@ EXPORTED = [
     "xls_mlp_get_params", "xls_mlp_set_params", "xls_mlp_set_norm", "xls_mlp_forward", "xls_mlp_gradient",
     "xls_mlp_train", "xls_mlp_predict", "xls_set_graphs", "xls_subdomain_time_gemms",
     "xls_mlp_fit", "xls_mlp_train_rms", "xls_mlp_bounds", "xls_learned_safe_bounds",
+    "xls_batch_create_slots",
 ]
 
 
@@ -67,7 +68,7 @@ class xls_subdomain_desc_t(C.Structure):
         ("core_lo", C.c_int32 * 3), ("core_hi", C.c_int32 * 3),
         ("global_offset", C.c_int64 * 3), ("global_n", C.c_int64 * 3),
         ("ns", C.c_int32), ("x0", C.POINTER(C.c_double)), ("lanczos_v0", C.POINTER(C.c_double)),
-        ("filter_prec", C.c_int32), ("stream", C.c_void_p),
+        ("filter_prec", C.c_int32), ("stream", C.c_void_p), ("x0_seed", C.c_uint64),
     ]
 
 
@@ -144,12 +145,15 @@ def xls_split_bf16(a: np.ndarray) -> Tuple[np.ndarray, np.ndarray]:
 
 
 def make_desc(sd, filter_prec: int = XLS_PREC_FP64, x0: Optional[np.ndarray] = None,
-              stream: Optional[int] = None, lanczos_v0: Optional[np.ndarray] = None):
+              stream: Optional[int] = None, lanczos_v0: Optional[np.ndarray] = None,
+              x0_seed: Optional[int] = None):
     """xls_subdomain_desc_t for a workload subdomain, plus the arrays it points
-    into (keep them alive until the create call returns)."""
-    x0 = sd.x0 if x0 is None else x0
-    if x0 is None:
-        raise ValueError("start block x0 is required")
+    into (keep them alive until the create call returns).  With x0_seed the
+    start block is drawn on the device (x0 NULL) and the Lanczos vector is its
+    column 0 unless given."""
+    x0 = sd.x0 if (x0 is None and x0_seed is None) else x0
+    if x0 is None and x0_seed is None:
+        raise ValueError("start block x0 (or x0_seed) is required")
     d = xls_subdomain_desc_t()
     d.n = (C.c_int32 * 3)(*[int(v) for v in sd.n])
     d.h = float(sd.h)
@@ -172,10 +176,16 @@ def make_desc(sd, filter_prec: int = XLS_PREC_FP64, x0: Optional[np.ndarray] = N
     d.core_hi = (C.c_int32 * 3)(*sd.core_hi)
     d.global_offset = (C.c_int64 * 3)(*sd.global_offset)
     d.global_n = (C.c_int64 * 3)(*sd.global_n)
-    d.ns = int(x0.shape[1])
-    X = _f64(x0)
-    d.x0 = _dp(X)
-    lv = lanczos_v0 if lanczos_v0 is not None else getattr(sd, "lanczos_v0", None)
+    if x0 is not None:
+        d.ns = int(x0.shape[1])
+        X = _f64(x0)
+        d.x0 = _dp(X)
+        lv = lanczos_v0 if lanczos_v0 is not None else getattr(sd, "lanczos_v0", None)
+    else:
+        d.ns = int(sd.ns)
+        X = None
+        d.x0_seed = int(x0_seed)
+        lv = lanczos_v0
     if lv is not None:
         lv = _f64(lv, order="C")
         d.lanczos_v0 = _dp(lv)
@@ -196,8 +206,9 @@ class Subdomain:
     """Owner of one xls_subdomain_t handle (xls_subdomain_create / _destroy)."""
 
     def __init__(self, sd, filter_prec: int = XLS_PREC_FP64, x0: Optional[np.ndarray] = None,
-                 stream: Optional[int] = None, lanczos_v0: Optional[np.ndarray] = None):
-        d, keep = make_desc(sd, filter_prec, x0, stream, lanczos_v0)
+                 stream: Optional[int] = None, lanczos_v0: Optional[np.ndarray] = None,
+                 x0_seed: Optional[int] = None):
+        d, keep = make_desc(sd, filter_prec, x0, stream, lanczos_v0, x0_seed)
         h = C.c_void_p()
         _check(lib().xls_subdomain_create(C.byref(d), C.byref(h)))
         del keep
@@ -365,16 +376,24 @@ class Batch:
     """Owner of one xls_batch_t (xls_batch_create / _destroy): many subdomains
     advanced together."""
 
-    def __init__(self, sds, filter_prec: int = XLS_PREC_FP32, x0s=None):
+    def __init__(self, sds, filter_prec: int = XLS_PREC_FP32, x0s=None, x0_seeds=None,
+                 slots: Optional[int] = None):
+        """x0_seeds: per subdomain, draw the start block on the device;
+        slots: None for a resident batch (xls_batch_create), else the byte
+        budget of xls_batch_create_slots (0: 85 % of free device memory)."""
         x0s = [None] * len(sds) if x0s is None else x0s
+        seeds = [None] * len(sds) if x0_seeds is None else x0_seeds
         descs = (xls_subdomain_desc_t * len(sds))()
         keep = []
-        for i, (sd, x0) in enumerate(zip(sds, x0s)):
-            d, k = make_desc(sd, filter_prec, x0)
+        for i, (sd, x0, sdseed) in enumerate(zip(sds, x0s, seeds)):
+            d, k = make_desc(sd, filter_prec, x0, x0_seed=sdseed)
             descs[i] = d
             keep.append(k)
         h = C.c_void_p()
-        _check(lib().xls_batch_create(C.c_int32(len(sds)), descs, C.byref(h)))
+        if slots is None:
+            _check(lib().xls_batch_create(C.c_int32(len(sds)), descs, C.byref(h)))
+        else:
+            _check(lib().xls_batch_create_slots(C.c_int32(len(sds)), descs, C.c_int64(int(slots)), C.byref(h)))
         del keep
         self._h = h
         self.prec = int(filter_prec)
@@ -455,10 +474,11 @@ class Batch:
         return int(tuned.value), float(best.value)
 
     def xls_batch_stats(self):
-        out = np.zeros(5)
-        _check(lib().xls_batch_stats(self._h, _dp(out), C.c_int32(5)))
+        out = np.zeros(7)
+        _check(lib().xls_batch_stats(self._h, _dp(out), C.c_int32(7)))
         return {"iterations": int(out[0]), "captures": int(out[1]), "replays": int(out[2]),
-                "iter_ms": float(out[3]), "last_iter_ms": float(out[4])}
+                "iter_ms": float(out[3]), "last_iter_ms": float(out[4]), "peak_bytes": int(out[5]),
+                "max_active": int(out[6])}
 
 
 def _fp(a: np.ndarray):

@@ -144,3 +144,17 @@ def test_core_masks_tile_a_periodic_grid():
 def test_global_index_wraps_negative_offsets():
     G = grid.global_index((3, 1, 1), (-1, 0, 0), (5, 1, 1))
     assert list(G) == [4, 0, 1]
+
+
+def test_philox_known_answers():
+    """The counter-based start-block generator reproduces the published
+    Philox4x32-10 known-answer vectors (tests/golden/philox4x32_10_kat.txt)."""
+    import os
+    from paper_2609_13115_amd import workloads
+    path = os.path.join(os.path.dirname(__file__), "golden", "philox4x32_10_kat.txt")
+    rows = [l.split() for l in open(path) if l.strip() and not l.startswith("#")]
+    assert len(rows) == 3
+    for r in rows:
+        v = [int(x, 16) for x in r]
+        out = workloads.philox4x32_10(*v[0:4], v[4], v[5])
+        assert [int(x) for x in out] == v[6:10]

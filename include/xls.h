@@ -213,6 +213,19 @@ int xls_subdomain_set_block(xls_subdomain_t s, const double* X); /* [N_d*ns] */
  * allocation is checked against that allocation only). */
 int xls_subdomain_store_half(xls_subdomain_t s, uint16_t* dst);
 int xls_subdomain_load_half(xls_subdomain_t s, const uint16_t* src);
+/* The same warm start read in half precision by the filter itself (Sec.
+ * V-B.2): src (as for xls_subdomain_load_half) becomes the handle's block
+ * without a widening pass; the first filter step of the next
+ * xls_chefsi_step or xls_subdomain_filter reads it as Y_0 and the second as
+ * Y_{-1}, in binary16 (half the bytes of an FP32 block), with the
+ * arithmetic in the handle's precision.  Results are those of
+ * xls_subdomain_load_half followed by the same call (binary16 widens
+ * exactly).  src must stay valid and unchanged until that call returns.
+ * Calls that read the block before then (get_block, store_half, project,
+ * rotate, residual, time_gemms, a learned run with the fallback) widen src
+ * into the block first; set_block, load_half or another use_half replace
+ * it.  Ritz values are dropped.  Errors as for xls_subdomain_load_half. */
+int xls_subdomain_use_half(xls_subdomain_t s, const uint16_t* src);
 /* Integer maps: core_mask u8[N_d], global_index i64[N_d]. */
 int xls_subdomain_get_maps(xls_subdomain_t s, uint8_t* core_mask, int64_t* global_index);
 /* sizes[0] = total support slots, sizes[1] = n_atoms.  With NULL arrays only
@@ -237,6 +250,17 @@ int xls_split_bf16(const float* a, uint16_t* hi, uint16_t* lo, int64_t n);
  * only, never the arithmetic of a grid point.  Errors: INVALID_ARG when the
  * tile does not fit (LDS, registers, halo budget) or nv is not 0, 1 or 2. */
 int xls_subdomain_tune(xls_subdomain_t s, int32_t prec, int32_t block, int32_t ty, int32_t tz, int32_t nv);
+
+/* Launch plan of the handle's projection and rotation GEMMs (Sec. V-B.3:
+ * split-K over the long N_d dimension).  split_scale 0 keeps the default
+ * split count (about two resident workgroups per CU, at least 16 k-slabs per
+ * split); k in [1, 64] scales it by k/2 (still bounded by K and the
+ * workspace).  tile_tn / tile_nn: 0 takes the large-tile MFMA kernels when
+ * the shapes allow (128 x 128 projection tiles, 64 x 256 rotation tiles), 1
+ * the 64 x 64 ones.  A plan changes the order of the split-K partial sums
+ * (results stay deterministic per plan), never a product.  INVALID_ARG
+ * outside those ranges. */
+int xls_subdomain_tune_gemm(xls_subdomain_t s, int32_t split_scale, int32_t tile_tn, int32_t tile_nn);
 
 /* Profiling switch (process-wide, default off): with 1, xls_chefsi_step
  * records HIP events around its stages and every fused-filter launch. */
@@ -394,9 +418,14 @@ int xls_subdomain_features(xls_subdomain_t s, double* f);
  *   hooks); owned by the batch, never destroyed by the caller.
  * xls_batch_tune: times the fused filter kernel of one subdomain per shape
  *   class (grid, boundary, precision, atom count) over block {256, 512} x
- *   rows-per-tile {auto, 1, 2, 4, 8, 16} and applies the fastest to the class.
- *   cache_path (may be NULL): JSON object "shape key": [block, ty]; known keys
- *   are taken from it without timing, new results are written back.
+ *   rows-per-tile {auto, 1, 2, 4, 8, 16} x vectors per tile {1, 2}, and the
+ *   projection and rotation GEMMs of one subdomain per (precision, N_d, ns)
+ *   class over split scale {default, 1/2, 2, 4} x tile kind (FP32 GEMMs for
+ *   FP32 batches), and applies the fastest to each class
+ *   (xls_subdomain_tune, xls_subdomain_tune_gemm).  cache_path (may be
+ *   NULL): JSON object "shape key": [block, ty, nv] and "gemm_... key":
+ *   [split_scale, tile_tn, tile_nn]; known keys are taken from it without
+ *   timing, new results are written back.
  *   tuned (may be NULL) = classes timed; best_ms (may be NULL) = sum over timed
  *   classes of the winning per-launch time.
  * xls_batch_stats: out[0] iterations of the last xls_batch_chefsi, out[1]

@@ -80,6 +80,16 @@ void require_resident(const xls_subdomain_s* s) {
     fail(XLS_ERR_STATE, "the subdomain has no working set (a slot-residency batch releases it between runs)");
 }
 
+void materialize_half(xls_subdomain_s* s) {
+  if (!s->half_src) return;
+  const uint16_t* h = s->half_src;
+  s->half_src = nullptr;
+  if (s->prec == XLS_PREC_FP32)
+    launch_block_half<float>(B<float>(s, s->cur), s->ld, s->nd, s->ns, const_cast<uint16_t*>(h), 0, s->st);
+  else
+    launch_block_half<double>(B<double>(s, s->cur), s->ld, s->nd, s->ns, const_cast<uint16_t*>(h), 0, s->st);
+}
+
 bool finite_all(const double* p, int64_t n) {
   for (int64_t i = 0; i < n; ++i)
     if (!std::isfinite(p[i])) return false;
@@ -116,21 +126,36 @@ void filter_block(xls_subdomain_s* s, int m, double a0, double lc, double lmax) 
     for (auto& ev : s->fev) XLS_HIP(hipEventCreate(&ev));
   }
   int y0 = s->cur, y1 = 1 - s->cur;
+  // a binary16 warm start is read as Y_0 by step 0 and as Y_{-1} by step 1
+  const uint16_t* h16 = s->half_src;
+  s->half_src = nullptr;
   // Y1 = (sigma1/e)(H X - c X)
-  launch_proj_forward<TS, TS>(op, B<TS>(s, y0), s->ld, s->ns, alpha, s->st);
-  if (prof) XLS_HIP(hipEventRecord(s->fev[0], s->st));
-  launch_stencil<TS, TS>(kFilter, op, B<TS>(s, y0), s->ld, s->ns, alpha, B<TS>(s, y1), nullptr, sigma1 / e,
-                         c, 0.0, nullptr, nullptr, nullptr, s->st, cfg);
+  if (h16) {
+    launch_proj_forward<_Float16, TS>(op, reinterpret_cast<const _Float16*>(h16), s->nd, s->ns, alpha, s->st);
+    if (prof) XLS_HIP(hipEventRecord(s->fev[0], s->st));
+    launch_filter_half<TS, TS>(op, nullptr, h16, s->ld, s->nd, s->ns, alpha, B<TS>(s, y1), nullptr, sigma1 / e, c,
+                               0.0, s->st, cfg);
+  } else {
+    launch_proj_forward<TS, TS>(op, B<TS>(s, y0), s->ld, s->ns, alpha, s->st);
+    if (prof) XLS_HIP(hipEventRecord(s->fev[0], s->st));
+    launch_stencil<TS, TS>(kFilter, op, B<TS>(s, y0), s->ld, s->ns, alpha, B<TS>(s, y1), nullptr, sigma1 / e,
+                           c, 0.0, nullptr, nullptr, nullptr, s->st, cfg);
+  }
   if (prof) XLS_HIP(hipEventRecord(s->fev[1], s->st));
   s->filter_launches++;
   double sig = sigma1;
   for (int k = 1; k < m; ++k) {
     const double signew = 1.0 / (tau - sig);
-    // Y_{k+1} overwrites Y_{k-1} in place
+    // Y_{k+1} overwrites Y_{k-1} in place (step 1 of a binary16 warm start
+    // reads Y_0 from the half buffer and writes the other block)
     launch_proj_forward<TS, TS>(op, B<TS>(s, y1), s->ld, s->ns, alpha, s->st);
     if (prof) XLS_HIP(hipEventRecord(s->fev[2 * k], s->st));
-    launch_stencil<TS, TS>(kFilter, op, B<TS>(s, y1), s->ld, s->ns, alpha, B<TS>(s, y0), B<TS>(s, y0),
-                           2.0 * signew / e, c, sig * signew, nullptr, nullptr, nullptr, s->st, cfg);
+    if (k == 1 && h16)
+      launch_filter_half<TS, TS>(op, B<TS>(s, y1), nullptr, s->ld, s->nd, s->ns, alpha, B<TS>(s, y0), h16,
+                                 2.0 * signew / e, c, sig * signew, s->st, cfg);
+    else
+      launch_stencil<TS, TS>(kFilter, op, B<TS>(s, y1), s->ld, s->ns, alpha, B<TS>(s, y0), B<TS>(s, y0),
+                             2.0 * signew / e, c, sig * signew, nullptr, nullptr, nullptr, s->st, cfg);
     if (prof) XLS_HIP(hipEventRecord(s->fev[2 * k + 1], s->st));
     s->filter_launches++;
     sig = signew;
@@ -154,16 +179,16 @@ void project_block(xls_subdomain_s* s, int gprec) {
   TS* W = B<TS>(s, 1 - s->cur);
   apply_H<TS>(s, Bc, W, s->ns, static_cast<TS*>(s->alpha));
   gemm_tn<TS>(gprec, Bc, s->ld, Bc, s->ld, s->ns, s->ns, s->nd, s->Mdev, s->ns, 1, 0, s->gwork,
-              s->gwork_elems, s->st);
+              s->gwork_elems, s->st, s->gplan);
   gemm_tn<TS>(gprec, Bc, s->ld, W, s->ld, s->ns, s->ns, s->nd, s->Hsdev, s->ns, 0, 1, s->gwork,
-              s->gwork_elems, s->st);
+              s->gwork_elems, s->st, s->gplan);
 }
 
 template <typename TS>
 void rotate_block(xls_subdomain_s* s, int gprec, const double* Ydev) {
   TS* Bc = B<TS>(s, s->cur);
   TS* O = B<TS>(s, 1 - s->cur);
-  gemm_nn<TS>(gprec, Bc, s->ld, Ydev, s->ns, static_cast<int>(s->nd), s->ns, s->ns, O, s->ld, s->bwork, s->st);
+  gemm_nn<TS>(gprec, Bc, s->ld, Ydev, s->ns, static_cast<int>(s->nd), s->ns, s->ns, O, s->ld, s->bwork, s->st, s->gplan);
   s->cur = 1 - s->cur;
 }
 
@@ -356,9 +381,9 @@ void chefsi_loop(xls_subdomain_s* s, const xls_chefsi_params_t* p, int gprec, in
       apply_H<TS>(s, Bc, W, s->ns, static_cast<TS*>(s->alpha));
       tm.mark();
       gemm_tn<TS>(pprec, Bc, s->ld, Bc, s->ld, ns, ns, s->nd, s->Mdev, ns, 1, 0, s->gwork, s->gwork_elems,
-                  s->st);
+                  s->st, s->gplan);
       gemm_tn<TS>(pprec, Bc, s->ld, W, s->ld, ns, ns, s->nd, s->Hsdev, ns, 0, 1, s->gwork, s->gwork_elems,
-                  s->st);
+                  s->st, s->gplan);
     }
     tm.mark();
     dense_stage(s);
@@ -438,6 +463,7 @@ int chefsi_impl(xls_subdomain_s* s, const xls_chefsi_params_t* p, double* ritz, 
   if (!(a0 < lc && lc < lmax) || !std::isfinite(a0) || !std::isfinite(lmax))
     fail(XLS_ERR_INVALID_ARG, "bounds must satisfy a0 < lam_cut < lam_max");
   const bool fallback = learned && p->fallback_tol > 0;
+  if (fallback) materialize_half(s);  // the backup holds the widened start block
   const int cur0 = s->cur;
   const size_t bbytes = static_cast<size_t>(s->ld) * ns * sizeof(TS);
   if (fallback) {
@@ -846,6 +872,7 @@ int xls_subdomain_project(xls_subdomain_t s, int32_t gemm_prec, double* M, doubl
       fail(XLS_ERR_INVALID_ARG, "FP64 handles run FP64 GEMMs");
     if (gemm_prec < 0 || gemm_prec > 2) fail(XLS_ERR_INVALID_ARG, "bad gemm_prec");
     require_resident(s);
+    materialize_half(s);
     by_prec(s, [&](auto tag) {
       project_block<decltype(tag)>(s, gemm_prec);
       return 0;
@@ -866,6 +893,7 @@ int xls_subdomain_rotate(xls_subdomain_t s, int32_t gemm_prec, const double* Q) 
     if (gemm_prec < 0 || gemm_prec > 2) fail(XLS_ERR_INVALID_ARG, "bad gemm_prec");
     if (!finite_all(Q, static_cast<int64_t>(s->ns) * s->ns)) fail(XLS_ERR_INVALID_ARG, "Q not finite");
     require_resident(s);
+    materialize_half(s);
     XLS_HIP(hipMemcpyAsync(s->Ydev, Q, static_cast<size_t>(s->ns) * s->ns * 8, hipMemcpyHostToDevice, s->st));
     by_prec(s, [&](auto tag) {
       rotate_block<decltype(tag)>(s, gemm_prec, s->Ydev);
@@ -880,6 +908,7 @@ int xls_subdomain_residual(xls_subdomain_t s, const double* lam, double* resid) 
   return guarded([&]() -> int {
     if (!s || !lam || !resid) fail(XLS_ERR_INVALID_ARG, "NULL argument");
     require_resident(s);
+    materialize_half(s);
     XLS_HIP(hipMemcpyAsync(s->lam_dev, lam, s->ns * 8, hipMemcpyHostToDevice, s->st));
     by_prec(s, [&](auto tag) {
       residual_block<decltype(tag)>(s, s->lam_dev, s->resid_dev);
@@ -951,6 +980,7 @@ int xls_subdomain_get_block(xls_subdomain_t s, double* X) {
   return guarded([&]() -> int {
     if (!s || !X) fail(XLS_ERR_INVALID_ARG, "NULL argument");
     require_resident(s);
+    materialize_half(s);
     by_prec(s, [&](auto tag) {
       download_block<decltype(tag)>(s, s->blk[s->cur], X, s->ns);
       return 0;
@@ -964,6 +994,7 @@ int xls_subdomain_set_block(xls_subdomain_t s, const double* X) {
     if (!s || !X) fail(XLS_ERR_INVALID_ARG, "NULL argument");
     if (!finite_all(X, s->nd * s->ns)) fail(XLS_ERR_INVALID_ARG, "block not finite");
     require_resident(s);
+    s->half_src = nullptr;
     by_prec(s, [&](auto tag) {
       upload_block<decltype(tag)>(s, X, s->blk[s->cur], s->ns);
       return 0;
@@ -979,6 +1010,7 @@ int xls_subdomain_store_half(xls_subdomain_t s, uint16_t* dst) {
   return guarded([&]() -> int {
     if (!s || !dst) fail(XLS_ERR_INVALID_ARG, "NULL argument");
     require_resident(s);
+    materialize_half(s);
     check_device_range(dst, static_cast<size_t>(s->nd) * s->ns * 2);
     by_prec(s, [&](auto tag) {
       using TS = decltype(tag);
@@ -994,6 +1026,7 @@ int xls_subdomain_load_half(xls_subdomain_t s, const uint16_t* src) {
   return guarded([&]() -> int {
     if (!s || !src) fail(XLS_ERR_INVALID_ARG, "NULL argument");
     require_resident(s);
+    s->half_src = nullptr;
     check_device_range(src, static_cast<size_t>(s->nd) * s->ns * 2);
     by_prec(s, [&](auto tag) {
       using TS = decltype(tag);
@@ -1001,6 +1034,17 @@ int xls_subdomain_load_half(xls_subdomain_t s, const uint16_t* src) {
       return 0;
     });
     XLS_HIP(hipStreamSynchronize(s->st));
+    s->have_ritz = false;
+    return XLS_OK;
+  });
+}
+
+int xls_subdomain_use_half(xls_subdomain_t s, const uint16_t* src) {
+  return guarded([&]() -> int {
+    if (!s || !src) fail(XLS_ERR_INVALID_ARG, "NULL argument");
+    require_resident(s);
+    check_device_range(src, static_cast<size_t>(s->nd) * s->ns * 2);
+    s->half_src = src;
     s->have_ritz = false;
     return XLS_OK;
   });
@@ -1086,6 +1130,18 @@ int xls_subdomain_tune(xls_subdomain_t s, int32_t prec, int32_t block, int32_t t
   });
 }
 
+int xls_subdomain_tune_gemm(xls_subdomain_t s, int32_t split_scale, int32_t tile_tn, int32_t tile_nn) {
+  return guarded([&]() -> int {
+    if (!s) fail(XLS_ERR_INVALID_ARG, "NULL handle");
+    if (split_scale < 0 || split_scale > 64 || tile_tn < 0 || tile_tn > 1 || tile_nn < 0 || tile_nn > 1)
+      fail(XLS_ERR_INVALID_ARG, "split_scale must be in [0, 64], tiles 0 or 1");
+    s->gplan.split_scale = split_scale;
+    s->gplan.tile_tn = tile_tn;
+    s->gplan.tile_nn = tile_nn;
+    return XLS_OK;
+  });
+}
+
 int xls_subdomain_time_gemms(xls_subdomain_t s, int32_t gemm_prec, int32_t reps, double* ms) {
   return guarded([&]() -> int {
     if (!s || !ms || reps < 1) fail(XLS_ERR_INVALID_ARG, "bad argument");
@@ -1093,6 +1149,7 @@ int xls_subdomain_time_gemms(xls_subdomain_t s, int32_t gemm_prec, int32_t reps,
       fail(XLS_ERR_INVALID_ARG, "FP64 handles run FP64 GEMMs");
     if (gemm_prec < 0 || gemm_prec > 2) fail(XLS_ERR_INVALID_ARG, "bad gemm_prec");
     require_resident(s);
+    materialize_half(s);
     by_prec(s, [&](auto tag) {
       using TS = decltype(tag);
       TS* Bc = B<TS>(s, s->cur);
@@ -1105,13 +1162,13 @@ int xls_subdomain_time_gemms(xls_subdomain_t s, int32_t gemm_prec, int32_t reps,
       auto run = [&](int which) {
         if (which == 0)
           gemm_tn<TS>(gemm_prec, Bc, s->ld, Bc, s->ld, s->ns, s->ns, s->nd, s->Mdev, s->ns, 1, 0, s->gwork,
-                      s->gwork_elems, s->st);
+                      s->gwork_elems, s->st, s->gplan);
         else if (which == 1)
           gemm_tn<TS>(gemm_prec, Bc, s->ld, W, s->ld, s->ns, s->ns, s->nd, s->Hsdev, s->ns, 0, 1, s->gwork,
-                      s->gwork_elems, s->st);
+                      s->gwork_elems, s->st, s->gplan);
         else  // into the spare block: the current block is left as it was
           gemm_nn<TS>(gemm_prec, Bc, s->ld, s->Ydev, s->ns, static_cast<int>(s->nd), s->ns, s->ns, W, s->ld,
-                      s->bwork, s->st);
+                      s->bwork, s->st, s->gplan);
       };
       hipEvent_t e0, e1;
       XLS_HIP(hipEventCreate(&e0));

@@ -178,12 +178,12 @@ void tail_stages(xls_subdomain_s* s, const SubState& ss, int cur_f, double* coef
   TS* Bc = B<TS>(s, cur_f);
   TS* W = B<TS>(s, 1 - cur_f);
   apply_H<TS>(s, Bc, W, ns, static_cast<TS*>(s->alpha));
-  gemm_tn<TS>(ss.pprec, Bc, s->ld, Bc, s->ld, ns, ns, s->nd, s->Mdev, ns, 1, 0, s->gwork, s->gwork_elems, s->st);
-  gemm_tn<TS>(ss.pprec, Bc, s->ld, W, s->ld, ns, ns, s->nd, s->Hsdev, ns, 0, 1, s->gwork, s->gwork_elems, s->st);
+  gemm_tn<TS>(ss.pprec, Bc, s->ld, Bc, s->ld, ns, ns, s->nd, s->Mdev, ns, 1, 0, s->gwork, s->gwork_elems, s->st, s->gplan);
+  gemm_tn<TS>(ss.pprec, Bc, s->ld, W, s->ld, ns, ns, s->nd, s->Hsdev, ns, 0, 1, s->gwork, s->gwork_elems, s->st, s->gplan);
   (void)dense_geneig(s->dw, s->Hsdev, s->Mdev, s->Ydev, s->st, /*check_spd=*/false);
   XLS_HIP(hipMemcpyAsync(s->lam_dev, s->dw.lam(), ns * 8, hipMemcpyDeviceToDevice, s->st));
   // Psi <- Psi_f Y into the other buffer
-  gemm_nn<TS>(ss.pprec, Bc, s->ld, s->Ydev, ns, static_cast<int>(s->nd), ns, ns, W, s->ld, s->bwork, s->st);
+  gemm_nn<TS>(ss.pprec, Bc, s->ld, s->Ydev, ns, static_cast<int>(s->nd), ns, ns, W, s->ld, s->bwork, s->st, s->gplan);
   launch_proj_forward<TS, double>(s->op64, W, s->ld, ns, s->alpha64, s->st);
   launch_stencil<TS, double>(kResid, s->op64, W, s->ld, ns, s->alpha64, nullptr, nullptr, 1.0, 0.0, 0.0,
                              s->lam_dev, s->partial, s->resid_dev, s->st, s->cfg64);
@@ -243,7 +243,8 @@ std::string graph_key(xls_batch_s* b, const std::vector<int>& act) {
     // must not replay a graph of its old tiles
     const StencilLaunch& c = s->prec == XLS_PREC_FP32 ? s->cfg32 : s->cfg64;
     k << i << (s->cur ? 'b' : 'a') << b->st[i].degree << 'p' << b->st[i].gprec << 'q' << b->st[i].pprec << 'l'
-      << b->st[i].lmax << 's' << c.block << '.' << c.ty << '.' << c.tz << '.' << c.nv << ',';
+      << b->st[i].lmax << 's' << c.block << '.' << c.ty << '.' << c.tz << '.' << c.nv << 'g'
+      << s->gplan.split_scale << '.' << s->gplan.tile_tn << '.' << s->gplan.tile_nn << ',';
   }
   return k.str();
 }
@@ -637,6 +638,109 @@ double time_filter(xls_subdomain_s* s, const StencilLaunch& cfg, hipEvent_t e0, 
   return ms / reps;
 }
 
+std::string gemm_key(xls_subdomain_s* s) {
+  std::ostringstream o;
+  o << "gemm_" << (s->prec == XLS_PREC_FP32 ? "f32" : "f64") << "_nd" << s->nd << "_ns" << s->ns;
+  return o.str();
+}
+
+// Average device ms of the projection Psi^T (H Psi) (symmetrised) and the
+// rotation Psi Q under plan g, on the current block and the spare one.
+template <typename TS>
+std::array<double, 2> time_gemm_plan(xls_subdomain_s* s, const GemmPlan& g, hipEvent_t e0, hipEvent_t e1) {
+  const int gprec = std::is_same<TS, float>::value ? XLS_PREC_FP32 : XLS_PREC_FP64;
+  TS* Bc = B<TS>(s, s->cur);
+  TS* W = B<TS>(s, 1 - s->cur);
+  std::array<double, 2> out{};
+  for (int which = 0; which < 2; ++which) {
+    auto once = [&]() {
+      if (which == 0)
+        gemm_tn<TS>(gprec, Bc, s->ld, Bc, s->ld, s->ns, s->ns, s->nd, s->Hsdev, s->ns, 0, 1, s->gwork,
+                    s->gwork_elems, s->st, g);
+      else
+        gemm_nn<TS>(gprec, Bc, s->ld, s->Ydev, s->ns, static_cast<int>(s->nd), s->ns, s->ns, W, s->ld, s->bwork,
+                    s->st, g);
+    };
+    once();
+    XLS_HIP(hipEventRecord(e0, s->st));
+    constexpr int reps = 3;
+    for (int r = 0; r < reps; ++r) once();
+    XLS_HIP(hipEventRecord(e1, s->st));
+    XLS_HIP(hipEventSynchronize(e1));
+    float ms = 0.0f;
+    XLS_HIP(hipEventElapsedTime(&ms, e0, e1));
+    out[which] = ms / reps;
+  }
+  return out;
+}
+
+// Chooses each class's GEMM plan (split scale and tile kind of the
+// projection, tile kind of the rotation) by timing, or from the cache, and
+// applies it to every handle of the class.  Returns the classes timed.
+template <typename TS>
+int tune_gemms(xls_batch_s* b, std::map<std::string, Shape>& cache, std::map<std::string, Shape>& chosen) {
+  hipEvent_t e0, e1;
+  XLS_HIP(hipEventCreate(&e0));
+  XLS_HIP(hipEventCreate(&e1));
+  int tuned = 0;
+  try {
+    for (auto* s : b->subs) {
+      const std::string key = gemm_key(s);
+      if (chosen.count(key)) continue;
+      auto hit = cache.find(key);
+      if (hit != cache.end()) {
+        chosen[key] = hit->second;
+        continue;
+      }
+      const bool temp = !s->resident;
+      if (temp) {
+        const int p = static_cast<int>(std::find(b->pool.begin(), b->pool.end(), s->st) - b->pool.begin());
+        subdomain_ws_alloc(s, b->pool_gwork[p], b->pool_gwork_elems);
+        load_start_block<TS>(s, nullptr);
+      }
+      // the rotation operand: a well-scaled fixed matrix (scheduling only)
+      std::vector<double> q(static_cast<size_t>(s->ns) * s->ns, 0.0);
+      for (int i = 0; i < s->ns; ++i) q[static_cast<size_t>(i) * s->ns + i] = 1.0;
+      XLS_HIP(hipMemcpyAsync(s->Ydev, q.data(), q.size() * 8, hipMemcpyHostToDevice, s->st));
+      double best_tn = 1e30, best_nn = 1e30;
+      Shape arg{0, 0, 0};
+      for (int tile : {0, 1})
+        for (int scale : {0, 1, 4, 8}) {
+          GemmPlan g;
+          g.split_scale = scale;
+          g.tile_tn = tile;
+          g.tile_nn = tile;
+          const auto t = time_gemm_plan<TS>(s, g, e0, e1);
+          if (t[0] < best_tn) {
+            best_tn = t[0];
+            arg[0] = scale;
+            arg[1] = tile;
+          }
+          if (scale == 0 && t[1] < best_nn) {
+            best_nn = t[1];
+            arg[2] = tile;
+          }
+        }
+      if (temp) subdomain_ws_free(s);
+      chosen[key] = arg;
+      ++tuned;
+    }
+  } catch (...) {
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    throw;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  for (auto* s : b->subs) {
+    const Shape& c = chosen[gemm_key(s)];
+    s->gplan.split_scale = c[0];
+    s->gplan.tile_tn = c[1];
+    s->gplan.tile_nn = c[2];
+  }
+  return tuned;
+}
+
 template <typename TS>
 int tune_batch(xls_batch_s* b, const char* cache_path, double* best_ms_out) {
   auto cache = read_cache(cache_path);
@@ -699,6 +803,8 @@ int tune_batch(xls_batch_s* b, const char* cache_path, double* best_ms_out) {
     const int rc = xls_subdomain_tune(s, s->prec, c[0], c[1], 0, c[2]);
     if (rc != XLS_OK) fail(rc, std::string("applying tuned tile shape: ") + xls_last_error());
   }
+  // projection / rotation GEMM plans per (precision, N_d, ns) class
+  tuned += tune_gemms<TS>(b, cache, chosen);
   for (auto& e : chosen) cache[e.first] = e.second;
   if (tuned > 0) write_cache(cache_path, cache);
   if (best_ms_out) {

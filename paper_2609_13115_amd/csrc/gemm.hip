@@ -828,9 +828,11 @@ int device_cus() {
   return c;
 }
 
-int choose_splits(int tiles, int64_t K, int bk, int M, int N, size_t work_elems) {
+int planned_splits(int def, const GemmPlan& plan);
+
+int choose_splits(int tiles, int64_t K, int bk, int M, int N, size_t work_elems, const GemmPlan& plan) {
   // aim for ~2048 workgroups; each split must keep >= 8 k-blocks
-  int s = std::max(1, 2048 / std::max(1, tiles));
+  int s = planned_splits(std::max(1, 2048 / std::max(1, tiles)), plan);
   const int64_t kblocks = (K + bk - 1) / bk;
   s = static_cast<int>(std::min<int64_t>(s, std::max<int64_t>(1, kblocks / 8)));
   const size_t per = static_cast<size_t>(M) * N;
@@ -843,12 +845,17 @@ bool aligned16(const T* p) {
   return (reinterpret_cast<uintptr_t>(p) & 15u) == 0;
 }
 
+// Split count of a plan: the default rule's count scaled by split_scale / 2.
+int planned_splits(int def, const GemmPlan& plan) {
+  return plan.split_scale > 0 ? std::max(1, def * plan.split_scale / 2) : def;
+}
+
 template <typename TIN, int MF>
 void tn_dispatch(const TIN* A, int64_t lda, const TIN* B, int64_t ldb, int M, int N, int64_t K,
                  double* C, int64_t ldc, int sym, int symmetrize, double* work, size_t work_elems,
-                 hipStream_t st) {
+                 hipStream_t st, const GemmPlan& plan) {
   constexpr int VEC = 16 / sizeof(TIN);
-  if (M >= 64 && N >= 64 && lda % VEC == 0 && ldb % VEC == 0 && K <= lda && K <= ldb &&
+  if (plan.tile_tn != 1 && M >= 64 && N >= 64 && lda % VEC == 0 && ldb % VEC == 0 && K <= lda && K <= ldb &&
       aligned16(A) && aligned16(B)) {
     constexpr int T = 128;
     const int tm = (M + T - 1) / T, tn = (N + T - 1) / T;
@@ -856,7 +863,7 @@ void tn_dispatch(const TIN* A, int64_t lda, const TIN* B, int64_t ldb, int M, in
     const int bk = BigLds<MF>::BK;
     // about two resident workgroups per CU (the kernel's occupancy), so that
     // symmetric products (fewer tiles) get more splits; >= 16 K slabs each
-    int splits = std::max(1, 2 * device_cus() / ntile);
+    int splits = planned_splits(std::max(1, 2 * device_cus() / ntile), plan);
     splits = static_cast<int>(std::min<int64_t>(splits, std::max<int64_t>(1, K / (16 * bk))));
     const size_t per = static_cast<size_t>(M) * N;
     splits = static_cast<int>(std::min<size_t>(splits, std::max<size_t>(1, work_elems / per)));
@@ -874,7 +881,7 @@ void tn_dispatch(const TIN* A, int64_t lda, const TIN* B, int64_t ldb, int M, in
   const int tm = (M + kTile - 1) / kTile, tn = (N + kTile - 1) / kTile;
   const int ntile = sym ? tm * (tm + 1) / 2 : tm * tn;
   const int bk = Form<MF>::BK;
-  const int splits = choose_splits(ntile, K, bk, M, N, work_elems);
+  const int splits = choose_splits(ntile, K, bk, M, N, work_elems, plan);
   int64_t kchunk = (K + splits - 1) / splits;
   kchunk = ((kchunk + bk - 1) / bk) * bk;
   const int real_splits = static_cast<int>((K + kchunk - 1) / kchunk);
@@ -904,19 +911,19 @@ size_t gemm_tn_work_elems(int M, int N, int64_t K) {
 template <typename TS>
 void gemm_tn(int prec, const TS* A, int64_t lda, const TS* B, int64_t ldb, int M, int N, int64_t K,
              double* C, int64_t ldc, int sym, int symmetrize, double* work, size_t work_elems,
-             hipStream_t st) {
+             hipStream_t st, const GemmPlan& plan) {
   if (M <= 0 || N <= 0) return;
   if (work_elems < static_cast<size_t>(M) * N) fail(XLS_ERR_INVALID_ARG, "gemm_tn workspace too small");
   if constexpr (std::is_same<TS, double>::value) {
     if (prec != MF_F64) fail(XLS_ERR_INVALID_ARG, "FP64 blocks use FP64 GEMMs");
-    tn_dispatch<double, MF_F64>(A, lda, B, ldb, M, N, K, C, ldc, sym, symmetrize, work, work_elems, st);
+    tn_dispatch<double, MF_F64>(A, lda, B, ldb, M, N, K, C, ldc, sym, symmetrize, work, work_elems, st, plan);
   } else {
     if (prec == MF_F64)
-      tn_dispatch<float, MF_F64>(A, lda, B, ldb, M, N, K, C, ldc, sym, symmetrize, work, work_elems, st);
+      tn_dispatch<float, MF_F64>(A, lda, B, ldb, M, N, K, C, ldc, sym, symmetrize, work, work_elems, st, plan);
     else if (prec == MF_F32)
-      tn_dispatch<float, MF_F32>(A, lda, B, ldb, M, N, K, C, ldc, sym, symmetrize, work, work_elems, st);
+      tn_dispatch<float, MF_F32>(A, lda, B, ldb, M, N, K, C, ldc, sym, symmetrize, work, work_elems, st, plan);
     else if (prec == MF_BF)
-      tn_dispatch<float, MF_BF>(A, lda, B, ldb, M, N, K, C, ldc, sym, symmetrize, work, work_elems, st);
+      tn_dispatch<float, MF_BF>(A, lda, B, ldb, M, N, K, C, ldc, sym, symmetrize, work, work_elems, st, plan);
     else
       fail(XLS_ERR_INVALID_ARG, "unknown GEMM precision");
   }
@@ -976,9 +983,9 @@ bool nn_big(int prec, const TS* A, int64_t lda, const double* B, int64_t ldb, in
 
 template <typename TS>
 void gemm_nn(int prec, const TS* A, int64_t lda, const double* B, int64_t ldb, int M, int N, int K,
-             TS* C, int64_t ldc, void* bwork, hipStream_t st) {
+             TS* C, int64_t ldc, void* bwork, hipStream_t st, const GemmPlan& plan) {
   if (M <= 0 || N <= 0) return;
-  if (nn_big<TS>(prec, A, lda, B, ldb, M, N, K, C, ldc, bwork, st)) return;
+  if (plan.tile_nn != 1 && nn_big<TS>(prec, A, lda, B, ldb, M, N, K, C, ldc, bwork, st)) return;
   const int tmM = (M + kTile - 1) / kTile, tnN = (N + kTile - 1) / kTile;
   const int64_t nb = static_cast<int64_t>(tmM) * tnN;
   if (nb > 0x7fffffff) fail(XLS_ERR_INVALID_ARG, "gemm_nn grid too large");
@@ -1018,12 +1025,12 @@ void split_bf16_device(const float* a, uint16_t* hi, uint16_t* lo, int64_t n, hi
 }
 
 template void gemm_tn<double>(int, const double*, int64_t, const double*, int64_t, int, int, int64_t,
-                              double*, int64_t, int, int, double*, size_t, hipStream_t);
+                              double*, int64_t, int, int, double*, size_t, hipStream_t, const GemmPlan&);
 template void gemm_tn<float>(int, const float*, int64_t, const float*, int64_t, int, int, int64_t,
-                             double*, int64_t, int, int, double*, size_t, hipStream_t);
+                             double*, int64_t, int, int, double*, size_t, hipStream_t, const GemmPlan&);
 template void gemm_nn<double>(int, const double*, int64_t, const double*, int64_t, int, int, int,
-                              double*, int64_t, void*, hipStream_t);
+                              double*, int64_t, void*, hipStream_t, const GemmPlan&);
 template void gemm_nn<float>(int, const float*, int64_t, const double*, int64_t, int, int, int, float*,
-                             int64_t, void*, hipStream_t);
+                             int64_t, void*, hipStream_t, const GemmPlan&);
 
 }  // namespace xls

@@ -11,6 +11,11 @@ namespace xls {
   template void launch_proj_forward<TS, TC>(const OpTables<TC>&, const TS*, int64_t, int, TC*,    \
                                             hipStream_t);
 XLS_INST_STENCIL(double, double)
+template void launch_filter_half<double, double>(const OpTables<double>&, const double*, const uint16_t*, int64_t, int64_t,
+                                             int, const double*, double*, const uint16_t*, double, double, double,
+                                             hipStream_t, const StencilLaunch&);
+template void launch_proj_forward<_Float16, double>(const OpTables<double>&, const _Float16*, int64_t, int, double*,
+                                                 hipStream_t);
 template FilterGroup<double>* filter_group_build<double>(const std::vector<FilterGroupOp<double>>&);
 template void filter_group_step<double>(FilterGroup<double>*, int, hipStream_t);
 template int filter_group_steps<double>(const FilterGroup<double>*);

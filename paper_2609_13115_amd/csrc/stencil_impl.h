@@ -43,6 +43,7 @@ struct HArgs {
   int32_t ncols;
   int32_t nx, ny, nz;
   int64_t ld;
+  int64_t ld16;  // leading dimension (elements) of a binary16 y / yprev stream (half-input steps)
   int32_t periodic;
   int32_t ty, tz, nyt, nzt;
   TC wc;     // -1/2 * 3 w0 / h^2
@@ -145,6 +146,12 @@ __device__ __forceinline__ void bstore_p(double v, __amdgpu_buffer_rsrc_t r, int
   typedef unsigned int u2 __attribute__((ext_vector_type(2)));
   __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, voff, soff, AUX);
 }
+// binary16 stream element (a warm start kept in half precision), widened
+template <typename TC, int AUX>
+__device__ __forceinline__ TC bload_h(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  const unsigned short u = __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, AUX);
+  return static_cast<TC>(__builtin_bit_cast(_Float16, u));
+}
 // Y_{k-1} is read once and Y_{k+1} written once per launch: both go
 // non-temporal, which leaves more of the L2 to the reused data (Y_k's halo
 // rows, V, the projector words); -1 % (FP32) and -2 % (FP64) launch time
@@ -197,10 +204,14 @@ __device__ __forceinline__ Ent4<double> load_ent<double>(__amdgpu_buffer_rsrc_t 
 // column index at or beyond ncols gets empty buffer resources (loads read
 // zero, stores drop).  Shared by the single-operator launch and the grouped
 // persistent launch.
-template <typename TS, typename TC, int MODE, int P, int NT, int WS, int NV>
+// HF (half-input filter steps of a warm start): bit 0, y (Y_k) is binary16
+// with leading dimension ld16; bit 1, yprev (Y_{k-1}) is.  The output and
+// the arithmetic keep TS / TC.
+template <typename TS, typename TC, int MODE, int P, int NT, int WS, int NV, int HF = 0>
 __device__ __forceinline__ void stencil_tile(const HArgs<TS, TC>& A, uint32_t logical, TC ca, TC cc, TC cb,
                                              unsigned char* smem_raw) {
   static_assert(NV == 1 || MODE != kResid, "residual sweeps take one column per tile");
+  static_assert(HF == 0 || MODE == kFilter, "binary16 inputs only in filter steps");
   TC* lds = reinterpret_cast<TC*>(smem_raw);
   const int nx = A.nx, ny = A.ny, nz = A.nz;
   constexpr int W = WS;
@@ -220,19 +231,26 @@ __device__ __forceinline__ void stencil_tile(const HArgs<TS, TC>& A, uint32_t lo
   const int tid = threadIdx.x;
   const int pp = nx * ny;  // points per plane
   constexpr int ES = sizeof(TS), EC = sizeof(TC);
+  constexpr int ESY = (HF & 1) ? 2 : ES;  // element bytes of the y stream
+  constexpr int ESP = (HF & 2) ? 2 : ES;  // of the yprev stream
 
-  const int64_t colbytes = static_cast<int64_t>(nx) * ny * nz * ES;
+  const int64_t colpts = static_cast<int64_t>(nx) * ny * nz;
   __amdgpu_buffer_rsrc_t ry[NV], rp[NV], ro[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
     const bool live = col0 + v < A.ncols;
     const int64_t c = live ? col0 + v : col0;
-    const int64_t bytes = live ? colbytes : 0;
-    ry[v] = make_rsrc(A.y + c * A.ld, bytes);
+    const int64_t pts = live ? colpts : 0;
+    const void* yb = (HF & 1) ? static_cast<const void*>(reinterpret_cast<const uint16_t*>(A.y) + c * A.ld16)
+                              : static_cast<const void*>(A.y + c * A.ld);
+    ry[v] = make_rsrc(yb, pts * ESY);
     // without Y_{k-1} the stream is empty and reads zero
-    rp[v] = make_rsrc(MODE == kFilter && A.has_prev ? A.yprev + c * A.ld : A.y,
-                      MODE == kFilter && A.has_prev ? bytes : 0);
-    ro[v] = make_rsrc(MODE == kResid ? A.y : A.out + c * A.ld, bytes);
+    const bool prev = MODE == kFilter && A.has_prev;
+    const void* pb = !prev ? static_cast<const void*>(A.y)
+                     : (HF & 2) ? static_cast<const void*>(reinterpret_cast<const uint16_t*>(A.yprev) + c * A.ld16)
+                                : static_cast<const void*>(A.yprev + c * A.ld);
+    rp[v] = make_rsrc(pb, prev ? pts * ESP : 0);
+    ro[v] = make_rsrc(MODE == kResid ? A.y : A.out + c * A.ld, pts * ES);
   }
   const __amdgpu_buffer_rsrc_t rv = make_rsrc(A.v, static_cast<int64_t>(nx) * ny * nz * EC);
   const __amdgpu_buffer_rsrc_t rk = make_rsrc(A.rev_pk, static_cast<int64_t>(nx) * ny * nz * 4);
@@ -242,7 +260,7 @@ __device__ __forceinline__ void stencil_tile(const HArgs<TS, TC>& A, uint32_t lo
   // points owned by this lane: in-plane byte offsets per stream element size
   // (kOOB when inactive), LDS index written and LDS index read (inactive
   // slots write the spare cell and read the star of the first point)
-  int vo[P], os[P], oc[P], o4[P], li[P], lr[P];
+  int vo[P], os[P], oy[P], opv[P], oc[P], o4[P], li[P], lr[P];
 #pragma unroll
   for (int i = 0; i < P; ++i) {
     const int lin = tid + i * NT;
@@ -250,6 +268,8 @@ __device__ __forceinline__ void stencil_tile(const HArgs<TS, TC>& A, uint32_t lo
     const int x = act ? lin % nx : 0, yy = act ? y0 + lin / nx : y0;
     vo[i] = act ? (x + nx * yy) : -1;
     os[i] = act ? vo[i] * ES : kOOB;
+    oy[i] = act ? vo[i] * ESY : kOOB;
+    opv[i] = act ? vo[i] * ESP : kOOB;
     oc[i] = act ? vo[i] * EC : kOOB;
     o4[i] = act ? vo[i] * 4 : kOOB;
     li[i] = act ? (R + yy - y0) * W + R + x : dumpi;
@@ -281,9 +301,9 @@ __device__ __forceinline__ void stencil_tile(const HArgs<TS, TC>& A, uint32_t lo
         hl[j] = (R + row) * W + (c2 < R ? c2 : nx + c2);
       }
       if (A.periodic)
-        hoff[j] = (wrapi(x, nx) + nx * wrapi(yy, ny)) * ES;
+        hoff[j] = (wrapi(x, nx) + nx * wrapi(yy, ny)) * ESY;
       else if (x >= 0 && x < nx && yy >= 0 && yy < ny)
-        hoff[j] = (x + nx * yy) * ES;
+        hoff[j] = (x + nx * yy) * ESY;
     }
   }
 
@@ -310,9 +330,20 @@ __device__ __forceinline__ void stencil_tile(const HArgs<TS, TC>& A, uint32_t lo
     if (!A.periodic) return -1;
     return wrapi(zz, nz);
   };
-  auto ldq = [&](int i, int v, int zq) -> TC {
-    return zq < 0 ? TC(0) : static_cast<TC>(bload<TS>(ry[v], os[i], zq * pp * ES));
+  // one element of the y stream (plane offset in elements), and of yprev
+  auto ldy = [&](int v, int voff, int splane) -> TC {
+    if constexpr ((HF & 1) != 0)
+      return bload_h<TC, 0>(ry[v], voff, splane * 2);
+    else
+      return static_cast<TC>(bload<TS>(ry[v], voff, splane * ES));
   };
+  auto ldp = [&](int i, int v, int splane) -> TC {
+    if constexpr ((HF & 2) != 0)
+      return bload_h<TC, kPrevAux>(rp[v], opv[i], splane * 2);
+    else
+      return static_cast<TC>(bload_p<kPrevAux>(rp[v], opv[i], splane * ES, (TS*)nullptr));
+  };
+  auto ldq = [&](int i, int v, int zq) -> TC { return zq < 0 ? TC(0) : ldy(v, oy[i], zq * pp); };
 
   // register queue: q[i][v][slot] holds plane z - R + ((slot - ph) mod Q)
   // while plane z is computed at phase ph = (z - z0) mod Q, so the queue
@@ -356,10 +387,9 @@ __device__ __forceinline__ void stencil_tile(const HArgs<TS, TC>& A, uint32_t lo
         q[i][v][Q - 1] = ldq(i, v, zq0);
         fr[i][v] = ldq(i, v, zq1);
         if (MODE == kFilter) {
-          yp1[i][v] = static_cast<TC>(bload_p<kPrevAux>(rp[v], os[i], z0 * pp * ES, (TS*)nullptr));
+          yp1[i][v] = ldp(i, v, z0 * pp);
           yp2[i][v] = TC(0);
-          if (z0 + 1 < z1)
-            yp2[i][v] = static_cast<TC>(bload_p<kPrevAux>(rp[v], os[i], (z0 + 1) * pp * ES, (TS*)nullptr));
+          if (z0 + 1 < z1) yp2[i][v] = ldp(i, v, (z0 + 1) * pp);
         }
       }
       rp2[i] = bload<int>(rk, o4[i], z0 * pp * 4);
@@ -369,7 +399,7 @@ __device__ __forceinline__ void stencil_tile(const HArgs<TS, TC>& A, uint32_t lo
 #pragma unroll
   for (int v = 0; v < NV; ++v)
 #pragma unroll
-    for (int j = 0; j < HMAX; ++j) hv[v][j] = static_cast<TC>(bload<TS>(ry[v], hoff[j], z0 * pp * ES));
+    for (int j = 0; j < HMAX; ++j) hv[v][j] = ldy(v, hoff[j], z0 * pp);
 
   double racc = 0.0;
   const double lamc = (MODE == kResid) ? A.lam[col0] : 0.0;
@@ -389,11 +419,10 @@ __device__ __forceinline__ void stencil_tile(const HArgs<TS, TC>& A, uint32_t lo
     }
     // (b) next plane's halo
     if (z + 1 < z1) {
-      const int so1 = (z + 1) * pp * ES;
 #pragma unroll
       for (int v = 0; v < NV; ++v)
 #pragma unroll
-        for (int j = 0; j < HMAX; ++j) hv[v][j] = static_cast<TC>(bload<TS>(ry[v], hoff[j], so1));
+        for (int j = 0; j < HMAX; ++j) hv[v][j] = ldy(v, hoff[j], (z + 1) * pp);
     }
     lds_barrier();
     // (c) plane z
@@ -462,14 +491,12 @@ __device__ __forceinline__ void stencil_tile(const HArgs<TS, TC>& A, uint32_t lo
       }
     if (z + 1 < z1) {
       const int zq = qplane(z + 2 + R);
-      const int so2 = (z + 2) * pp * ES;
 #pragma unroll
       for (int i = 0; i < P; ++i)
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
           fr[i][v] = ldq(i, v, zq);
-          if (MODE == kFilter && z + 2 < z1)
-            yp2[i][v] = static_cast<TC>(bload_p<kPrevAux>(rp[v], os[i], so2, (TS*)nullptr));
+          if (MODE == kFilter && z + 2 < z1) yp2[i][v] = ldp(i, v, (z + 2) * pp);
         }
       load_rest(z + 1);
     }
@@ -507,10 +534,10 @@ __device__ __forceinline__ void stencil_tile(const HArgs<TS, TC>& A, uint32_t lo
   }
 }
 
-template <typename TS, typename TC, int MODE, int P, int NT, int WS, int NV>
+template <typename TS, typename TC, int MODE, int P, int NT, int WS, int NV, int HF = 0>
 __global__ __launch_bounds__(NT) void hstencil_kernel(HArgs<TS, TC> A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  stencil_tile<TS, TC, MODE, P, NT, WS, NV>(A, xcd_remap(blockIdx.x, gridDim.x), A.a, A.c, A.b, smem_raw);
+  stencil_tile<TS, TC, MODE, P, NT, WS, NV, HF>(A, xcd_remap(blockIdx.x, gridDim.x), A.a, A.c, A.b, smem_raw);
 }
 
 // Grouped persistent filter step over many operators: item = (operator,
@@ -732,43 +759,43 @@ void allow_smem(K kern, size_t smem) {
   ensure_dyn_smem(reinterpret_cast<const void*>(kern), smem);
 }
 
-template <typename TS, typename TC, int MODE, int P, int WS, int NV>
+template <typename TS, typename TC, int MODE, int P, int WS, int NV, int HF>
 void launch_mode(const HArgs<TS, TC>& args, dim3 grid, int block, size_t smem, hipStream_t st) {
   if (block == 256) {
-    allow_smem(hstencil_kernel<TS, TC, MODE, P, 256, WS, NV>, smem);
-    hipLaunchKernelGGL((hstencil_kernel<TS, TC, MODE, P, 256, WS, NV>), grid, dim3(256), smem, st, args);
+    allow_smem(hstencil_kernel<TS, TC, MODE, P, 256, WS, NV, HF>, smem);
+    hipLaunchKernelGGL((hstencil_kernel<TS, TC, MODE, P, 256, WS, NV, HF>), grid, dim3(256), smem, st, args);
   } else {
-    allow_smem(hstencil_kernel<TS, TC, MODE, P, 512, WS, NV>, smem);
-    hipLaunchKernelGGL((hstencil_kernel<TS, TC, MODE, P, 512, WS, NV>), grid, dim3(512), smem, st, args);
+    allow_smem(hstencil_kernel<TS, TC, MODE, P, 512, WS, NV, HF>, smem);
+    hipLaunchKernelGGL((hstencil_kernel<TS, TC, MODE, P, 512, WS, NV, HF>), grid, dim3(512), smem, st, args);
   }
 }
 
-template <typename TS, typename TC, int MODE, int WS, int NV>
+template <typename TS, typename TC, int MODE, int WS, int NV, int HF>
 void launch_pnv(const TileChoice& tc, const HArgs<TS, TC>& args, dim3 grid, size_t smem, hipStream_t st) {
   switch (tc.P) {
-    case 1: launch_mode<TS, TC, MODE, 1, WS, NV>(args, grid, tc.block, smem, st); break;
-    case 2: launch_mode<TS, TC, MODE, 2, WS, NV>(args, grid, tc.block, smem, st); break;
+    case 1: launch_mode<TS, TC, MODE, 1, WS, NV, HF>(args, grid, tc.block, smem, st); break;
+    case 2: launch_mode<TS, TC, MODE, 2, WS, NV, HF>(args, grid, tc.block, smem, st); break;
     default: fail(XLS_ERR_INVALID_ARG, "stencil tile needs more than 2 points per thread");
   }
 }
 
-template <typename TS, typename TC, int MODE, int WS>
+template <typename TS, typename TC, int MODE, int WS, int HF>
 void launch_ws(const TileChoice& tc, const HArgs<TS, TC>& args, dim3 grid, size_t smem, hipStream_t st) {
   if (tc.nv == 1) {
-    launch_pnv<TS, TC, MODE, WS, 1>(tc, args, grid, smem, st);
+    launch_pnv<TS, TC, MODE, WS, 1, HF>(tc, args, grid, smem, st);
   } else if constexpr (MODE != kResid) {
-    launch_pnv<TS, TC, MODE, WS, 2>(tc, args, grid, smem, st);
+    launch_pnv<TS, TC, MODE, WS, 2, HF>(tc, args, grid, smem, st);
   } else {
     fail(XLS_ERR_INVALID_ARG, "residual sweeps take one vector per tile");
   }
 }
 
-template <typename TS, typename TC, int MODE>
+template <typename TS, typename TC, int MODE, int HF = 0>
 void launch_any(const TileChoice& tc, const HArgs<TS, TC>& args, dim3 grid, size_t smem, hipStream_t st) {
   if (tc.ws == 80)
-    launch_ws<TS, TC, MODE, 80>(tc, args, grid, smem, st);
+    launch_ws<TS, TC, MODE, 80, HF>(tc, args, grid, smem, st);
   else
-    launch_ws<TS, TC, MODE, 128>(tc, args, grid, smem, st);
+    launch_ws<TS, TC, MODE, 128, HF>(tc, args, grid, smem, st);
 }
 
 // FD weights of d^2/dx^2 at 12th order (n0 = 6), from the closed form
@@ -895,6 +922,35 @@ void launch_stencil(StencilMode mode, const OpTables<TC>& op, const TS* y, int64
       }
   }
   XLS_LAUNCH_CHECK("hstencil_kernel");
+}
+
+// Filter step whose Y_k (y16) or Y_{k-1} (yprev16) is a binary16 block with
+// leading dimension ld16 (the first two steps from a half-precision warm
+// start); the other operands, the output and the arithmetic are TS.
+template <typename TS, typename TC>
+void launch_filter_half(const OpTables<TC>& op, const TS* y, const uint16_t* y16, int64_t ld, int64_t ld16,
+                        int ncols, const TC* alpha, TS* out, const uint16_t* yprev16, double a, double c, double b,
+                        hipStream_t st, const StencilLaunch& cfg) {
+  static_assert(std::is_same<TS, TC>::value, "filter steps run in the storage precision");
+  if (ncols <= 0) return;
+  if ((y16 == nullptr) == (yprev16 == nullptr)) fail(XLS_ERR_INVALID_ARG, "one binary16 stream per half step");
+  const TileChoice tc = tiles_for(op, ld, cfg);
+  check_tiles(tc, op.nx, op.periodic, sizeof(TC));
+  HArgs<TS, TC> A = make_hargs<TS, TC>(op, tc, y16 ? reinterpret_cast<const TS*>(y16) : y, ld, ncols, alpha, out,
+                                       reinterpret_cast<const TS*>(yprev16));
+  A.ld16 = ld16;
+  A.a = static_cast<TC>(a);
+  A.c = static_cast<TC>(c);
+  A.b = static_cast<TC>(b);
+  A.has_prev = (yprev16 != nullptr && b != 0.0) ? 1 : 0;
+  const int64_t nblocks = static_cast<int64_t>((ncols + tc.nv - 1) / tc.nv) * tc.nyt * tc.nzt;
+  if (nblocks > 0x7fffffff) fail(XLS_ERR_INVALID_ARG, "too many stencil tiles");
+  const dim3 grid(static_cast<unsigned>(nblocks));
+  if (y16)
+    launch_any<TS, TC, kFilter, 1>(tc, A, grid, tc.smem, st);
+  else
+    launch_any<TS, TC, kFilter, 2>(tc, A, grid, tc.smem, st);
+  XLS_LAUNCH_CHECK("hstencil_kernel (binary16 input)");
 }
 
 template <typename TS, typename TC>

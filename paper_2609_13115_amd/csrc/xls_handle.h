@@ -44,6 +44,7 @@ struct xls_subdomain_s {
   OpTables<double> op64;
   OpTables<float> op32;
   StencilLaunch cfg64, cfg32;
+  xls::GemmPlan gplan;  // projection and rotation GEMM launch plan
   // blocks
   void* blk[2] = {nullptr, nullptr};
   int cur = 0;
@@ -73,6 +74,9 @@ struct xls_subdomain_s {
   bool x0_gen = false;
   // working set (blocks, projections, GEMM and dense workspaces) allocated
   bool resident = false;
+  // binary16 warm start not yet widened (xls_subdomain_use_half): the
+  // caller's device buffer, N_d x ns with leading dimension N_d
+  const uint16_t* half_src = nullptr;
   // Lanczos
   std::vector<double> lanczos_v0;
   void* lz = nullptr;  // [nd * (kmax + 2)]
@@ -122,6 +126,8 @@ void dfree(void* p);
 bool finite_all(const double* p, int64_t n);
 // STATE unless the handle's working set is allocated.
 void require_resident(const xls_subdomain_s* s);
+// Widens a pending binary16 warm start into the current block.
+void materialize_half(xls_subdomain_s* s);
 
 template <typename T>
 T* dalloc(size_t n) {

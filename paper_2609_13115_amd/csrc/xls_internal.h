@@ -87,6 +87,13 @@ void launch_stencil(StencilMode mode, const OpTables<TC>& op, const TS* y, int64
                     const TC* alpha, TS* out, const TS* yprev, double a, double c, double b,
                     const double* lam, double* partial, double* resid2, hipStream_t st,
                     const StencilLaunch& cfg);
+// Filter step (kFilter, TS == TC) with one binary16 input stream of leading
+// dimension ld16: y16 as Y_k (then yprev16 is null and Y_{k-1} absent), or
+// yprev16 as Y_{k-1} (y is then the TS block); out is a TS block.
+template <typename TS, typename TC>
+void launch_filter_half(const OpTables<TC>& op, const TS* y, const uint16_t* y16, int64_t ld, int64_t ld16,
+                        int ncols, const TC* alpha, TS* out, const uint16_t* yprev16, double a, double c, double b,
+                        hipStream_t st, const StencilLaunch& cfg);
 // alpha[col][4a+l] = gamma_{a,l} h^3 sum_{s in S_a} chi_{a,l}(s) y(idx(s), col)
 template <typename TS, typename TC>
 void launch_proj_forward(const OpTables<TC>& op, const TS* y, int64_t ld, int ncols, TC* alpha,
@@ -144,16 +151,27 @@ size_t stencil_partial_elems(const OpTables<double>& op, int ncols, const Stenci
 //            (or padded) into bwork, nn_work_doubles(K, N) doubles, 16-byte
 //            aligned; bwork may be null only for FP64 calls (the small-tile
 //            path is taken when B would need padding).
+// Launch plan of the projection and rotation GEMMs (the autotuner's choice
+// per shape class): split_scale 0 keeps the default split-K count (about two
+// resident workgroups per CU, at least 16 k-slabs per split), k > 0 scales it
+// by k/2; tile_tn / tile_nn 0 take the 128 x 128 (64 x 256 for the
+// rotation) large-tile kernels when shapes allow, 1 the 64 x 64 tiles.
+// A plan changes the order of the split sums, never a product.
+struct GemmPlan {
+  int split_scale = 0;
+  int tile_tn = 0;
+  int tile_nn = 0;
+};
 template <typename TS>
 void gemm_tn(int prec, const TS* A, int64_t lda, const TS* B, int64_t ldb, int M, int N, int64_t K,
              double* C, int64_t ldc, int sym, int symmetrize, double* work, size_t work_elems,
-             hipStream_t st);
+             hipStream_t st, const GemmPlan& plan = GemmPlan{});
 size_t gemm_tn_work_elems(int M, int N, int64_t K);
 // doubles of the rotation work buffer (B copied with rows padded to 8)
 size_t nn_work_doubles(int K, int N);
 template <typename TS>
 void gemm_nn(int prec, const TS* A, int64_t lda, const double* B, int64_t ldb, int M, int N, int K,
-             TS* C, int64_t ldc, void* bwork, hipStream_t st);
+             TS* C, int64_t ldc, void* bwork, hipStream_t st, const GemmPlan& plan = GemmPlan{});
 void split_bf16_device(const float* a, uint16_t* hi, uint16_t* lo, int64_t n, hipStream_t st);
 
 // Learned filter bounds: the margins a run applies to a prediction (the

@@ -45,7 +45,7 @@ EXPORTED = [
     "xls_mlp_get_params", "xls_mlp_set_params", "xls_mlp_set_norm", "xls_mlp_forward", "xls_mlp_gradient",
     "xls_mlp_train", "xls_mlp_predict", "xls_set_graphs", "xls_subdomain_time_gemms",
     "xls_mlp_fit", "xls_mlp_train_rms", "xls_mlp_bounds", "xls_learned_safe_bounds",
-    "xls_batch_create_slots",
+    "xls_batch_create_slots", "xls_subdomain_tune_gemm", "xls_subdomain_use_half",
 ]
 
 
@@ -342,9 +342,17 @@ class Subdomain:
         """Block <- buf (device torch.float16, as written by xls_subdomain_store_half)."""
         _check(lib().xls_subdomain_load_half(self._h, C.c_void_p(int(buf.data_ptr()))))
 
+    def xls_subdomain_use_half(self, buf):
+        """Next filter reads its start block from buf (device torch.float16) directly."""
+        _check(lib().xls_subdomain_use_half(self._h, C.c_void_p(int(buf.data_ptr()))))
+
     def xls_subdomain_tune(self, prec: int, block: int = 512, ty: int = 0, tz: int = 0, nv: int = 0):
         _check(lib().xls_subdomain_tune(self._h, C.c_int32(prec), C.c_int32(block), C.c_int32(ty),
                                         C.c_int32(tz), C.c_int32(nv)))
+
+    def xls_subdomain_tune_gemm(self, split_scale: int = 0, tile_tn: int = 0, tile_nn: int = 0):
+        _check(lib().xls_subdomain_tune_gemm(self._h, C.c_int32(split_scale), C.c_int32(tile_tn),
+                                             C.c_int32(tile_nn)))
 
     def xls_subdomain_time_gemms(self, gemm_prec: int, reps: int = 5) -> np.ndarray:
         """Average device ms of (Psi^T Psi, Psi^T H Psi, Psi Q) at gemm_prec."""

@@ -53,13 +53,13 @@ def make_box64() -> str:
         f.write("# 20 Lanczos steps, run until the gated residual is <= 1e-4 (Sec. V-A.3).\n")
         f.write("# Written by tests/golden/make_golden.py box64 (oracle only).\n")
         f.write(f"# oracle wall time {time.time() - t0:.0f} s\n")
-        f.write(f"bounds {lo!r} {lc!r} {up!r}\n")
+        f.write(f"bounds {float(lo)!r} {float(lc)!r} {float(up)!r}\n")
         f.write(f"degree {BOX64_DEGREE}\n")
         f.write(f"iterations {res.iters}\n")
         f.write(f"gate {gate}\n")
         f.write(f"gated_max_resid {float(np.max(res.resid[:gate]))!r}\n")
         for lam, r in zip(res.ritz, res.resid):
-            f.write(f"{lam!r} {r!r}\n")
+            f.write(f"{float(lam)!r} {float(r)!r}\n")
     return path
 
 

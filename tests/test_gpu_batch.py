@@ -114,7 +114,11 @@ def test_batch_of_generated_subdomains():
 
 
 def test_batch_tuner_cache_and_invariance(tmp_path):
-    """Tuned tile shapes change scheduling, never results; the cache is reused."""
+    """The tuner picks a filter tile shape and a GEMM plan per class and
+    reuses its cache.  A tile shape changes scheduling only; a GEMM plan
+    changes the order of the split-K sums only: the tuned batch equals single
+    runs under the same choices bit for bit, and the untuned batch to
+    rounding."""
     case("batch tuner")
     sds = uneven_boxes()
     params = [xls.chefsi_params(d, 3, xls.XLS_BOUNDS_LANCZOS, gemm_prec=xls.XLS_PREC_FP32) for d in (7, 10, 12)]
@@ -122,17 +126,31 @@ def test_batch_tuner_cache_and_invariance(tmp_path):
     path = str(tmp_path / "tune.json")
     with xls.Batch(sds, filter_prec=xls.XLS_PREC_FP32) as b:
         tuned, best = b.xls_batch_tune(path)
-        assert tuned == 3 and best > 0
+        assert tuned == 6 and best > 0
         cache = json.load(open(path))
-        assert len(cache) == 3
-        for v in cache.values():
-            assert v[0] in (256, 512) and v[1] in (0, 1, 2, 4, 8, 16) and v[2] in (1, 2)
+        assert len(cache) == 6
+        for k, v in cache.items():
+            if k.startswith("gemm_"):
+                assert v[0] in (0, 1, 4, 8) and v[1] in (0, 1) and v[2] in (0, 1)
+            else:
+                assert v[0] in (256, 512) and v[1] in (0, 1, 2, 4, 8, 16) and v[2] in (1, 2)
         again, _ = b.xls_batch_tune(path)
         assert again == 0
         ritz, resid, iters, status = b.xls_batch_chefsi(params)
         blocks = [b.xls_batch_subdomain(i).xls_subdomain_get_block() for i in range(3)]
-    assert_same([(r, e, it, blk) for r, e, it, blk in zip(ref[0], ref[1], ref[2], ref[4])],
-                (ritz, resid, iters, status, blocks, None))
+    single = []
+    for sd, p in zip(sds, params):
+        with xls.Subdomain(sd, filter_prec=xls.XLS_PREC_FP32) as s:
+            n = sd.n
+            key = f"f32_{n[0]}x{n[1]}x{n[2]}_{'p' if sd.bc == 0 else 'd'}_na{len(sd.atoms)}"
+            blk, ty, nv = cache[key]
+            s.xls_subdomain_tune(xls.XLS_PREC_FP32, blk, ty, 0, nv)
+            s.xls_subdomain_tune_gemm(*cache[f"gemm_f32_nd{sd.nd}_ns{sd.ns}"])
+            r = s.xls_chefsi_step(p.degree, p.max_iter, p.bounds_mode, lanczos_k=p.lanczos_k, gemm_prec=p.gemm_prec)
+            single.append(r + (s.xls_subdomain_get_block(),))
+    assert_same(single, (ritz, resid, iters, status, blocks, None))
+    for a, b2 in zip(ritz, ref[0]):
+        assert np.max(np.abs(a - b2) / np.maximum(np.abs(b2), 1.0)) <= 1e-5
 
 
 @pytest.mark.parametrize("prec", [xls.XLS_PREC_FP64, xls.XLS_PREC_FP32])

@@ -81,3 +81,39 @@ def test_warm_start_from_half_tracks_the_uninterrupted_run():
     conv = (ea[:g] < 1e-4) & (eb[:g] < 1e-4)
     assert conv.any()
     assert np.max(np.abs(ra[:g][conv] - rb[:g][conv])) <= 1e-6
+
+
+@pytest.mark.parametrize("prec,degree", [(xls.XLS_PREC_FP32, 12), (xls.XLS_PREC_FP64, 9),
+                                         (xls.XLS_PREC_FP32, 1), (xls.XLS_PREC_FP32, 2)])
+def test_filter_reads_half_warm_start_directly(prec, degree):
+    """xls_subdomain_use_half: the first two filter steps read the binary16
+    block themselves (Y_0, then Y_{-1}); binary16 widens exactly, so the run
+    equals load_half (widen first) followed by the same run, bit for bit,
+    and the buffer is not modified."""
+    case(f"use_half prec={prec} degree={degree}")
+    sd = workloads.small_dirichlet(ns=11, index=8, shape=(15, 13, 14), h=0.7)
+    gp = prec
+    with xls.Subdomain(sd, filter_prec=prec) as s:
+        s.xls_chefsi_step(10, 2, xls.XLS_BOUNDS_LANCZOS, gemm_prec=gp)
+        buf = torch.empty(sd.nd * sd.ns, dtype=torch.float16, device="cuda")
+        s.xls_subdomain_store_half(buf)
+        lo, up = s.xls_lanczos_bounds(20)
+    keep = buf.clone()
+    out = []
+    for mode in ("load", "use"):
+        with xls.Subdomain(sd, filter_prec=prec) as t:
+            if mode == "load":
+                t.xls_subdomain_load_half(buf)
+            else:
+                t.xls_subdomain_use_half(buf)
+            r, e, it = t.xls_chefsi_step(degree, 3, xls.XLS_BOUNDS_GIVEN, lo, lo + 0.2 * (up - lo), up,
+                                         gemm_prec=gp)
+            out.append((r, e, it, t.xls_subdomain_get_block()))
+    assert torch.equal(buf, keep)
+    for a, b in zip(out[0], out[1]):
+        assert np.array_equal(a, b)
+    # a call that reads the block widens the pending buffer first
+    with xls.Subdomain(sd, filter_prec=prec) as u:
+        u.xls_subdomain_use_half(buf)
+        h16 = keep.cpu().numpy().reshape(sd.ns, sd.nd).T.astype(np.float64)
+        assert np.array_equal(u.xls_subdomain_get_block(), h16)

@@ -307,7 +307,8 @@ def test_residual_fp64(system):
 # register-only steps and the tail; 700: all three step kernels; 31/32 and
 # 900/901: either side of the compact-WY back-transform's range; 1900: the
 # inverse iteration without the overlapped factorisation (n > 1800)
-@pytest.mark.parametrize("n", [1, 2, 7, 20, 31, 32, 37, 100, 128, 129, 161, 480, 700, 900, 901, 1500, 1900])
+@pytest.mark.parametrize("n", [1, 2, 7, 20, 31, 32, 37, 100, 128, 129, 161, 480, 700, 900, 901, 1500, 1900,
+                               2400, 2800])
 def test_dense_geneig(n):
     case(f"dense n={n}")
     rng = np.random.default_rng(n)
@@ -536,6 +537,14 @@ def test_dense_graph_replay_matches_eager():
     assert np.array_equal(r1, r2) and np.array_equal(e1, e2) and np.array_equal(b1, b2)
 
 
+def gap_edge(ritz, gate, gap=1e-3):
+    """Largest k <= gate with ritz[k] - ritz[k-1] >= gap (0 if none)."""
+    for k in range(gate, 0, -1):
+        if k < len(ritz) and ritz[k] - ritz[k - 1] >= gap:
+            return k
+    return 0
+
+
 @pytest.mark.parametrize("gprec", [xls.XLS_PREC_FP32, xls.XLS_PREC_BF16X3])
 def test_mixed_precision_ritz_gate_si_cell_24(gprec):
     """The mixed forms (FP32 filter sweeps; FP32 or split-BF16 GEMMs; FP64
@@ -552,12 +561,11 @@ def test_mixed_precision_ritz_gate_si_cell_24(gprec):
         psi = s.xls_subdomain_get_block()
     gate = int(np.floor(sd.ns / 1.1 + 1e-9))
     assert np.max(np.abs(ritz[:gate] - ref.ritz[:gate])) <= 1e-6
-    # subspace of the gated states, closed over the degenerate cluster at the gate edge
-    k = gate
-    while k < sd.ns and abs(ref.ritz[k] - ref.ritz[k - 1]) < 1e-6:
-        k += 1
-    if k < sd.ns:
-        assert chefsi.subspace_sin_theta(ref.psi[:, :k], psi[:, :k]) <= 1e-5
+    # subspace of the gated states up to the last spectral gap at or below
+    # the gate edge (a degenerate cluster is never cut)
+    k = gap_edge(ref.ritz, gate)
+    assert k >= gate // 2
+    assert chefsi.subspace_sin_theta(ref.psi[:, :k], psi[:, :k]) <= 1e-5
 
 
 def test_mixed_precision_ritz_gate_dirichlet():
@@ -568,5 +576,9 @@ def test_mixed_precision_ritz_gate_dirichlet():
     ref = chefsi.chefsi(op.apply, sd.x0, 16, 16, lo, chefsi.first_cutoff(lo, up), up)
     with xls.Subdomain(sd, filter_prec=xls.XLS_PREC_FP32) as s:
         ritz, resid, it = s.xls_chefsi_step(16, 16, xls.XLS_BOUNDS_LANCZOS, gemm_prec=xls.XLS_PREC_BF16X3)
+        psi = s.xls_subdomain_get_block()
     gate = int(np.floor(sd.ns / 1.1 + 1e-9))
     assert np.max(np.abs(ritz[:gate] - ref.ritz[:gate])) <= 1e-6
+    k = gap_edge(ref.ritz, gate)
+    assert k >= gate // 2
+    assert chefsi.subspace_sin_theta(ref.psi[:, :k], psi[:, :k]) <= 1e-5

@@ -193,6 +193,20 @@ int xls_lanczos_bounds(xls_subdomain_t s, int32_t k, double* theta_min, double* 
  * 1 <= n <= 2800.  Errors: INVALID_ARG, NOT_SPD. */
 int xls_dense_geneig(int32_t n, const double* Hs, const double* M, double* lam, double* Y);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * solve as xls_dense_geneig, with Hs, M (n x n column-major), lam[n] and
+ * Y[n*n] all DEVICE pointers owned by the caller, issued on stream (a
+ * hipStream_t, NULL for the default stream) and synchronised before
+ * returning.  Its workspace lives in a static device array of the library
+ * (24 MiB per GPU, held until the process ends), so 1 <= n <= 512;
+ * larger n, NULL or non-device pointers are INVALID_ARG; NOT_SPD as for
+ * xls_dense_geneig.  The call makes no device allocation.  Every call on
+ * one GPU shares that GPU's array: calls that overlap on one GPU (other
+ * threads or streams) race, and must be serialised by the caller.  Results
+ * are bit-identical to xls_dense_geneig's. */
+int xls_dense_geneig_noalloc(int32_t n, const double* Hs, const double* M, double* lam, double* Y, void* stream);
+
 int xls_subdomain_get_block(xls_subdomain_t s, double* X);       /* [N_d*ns] */
 int xls_subdomain_set_block(xls_subdomain_t s, const double* X); /* [N_d*ns] */
 

@@ -542,7 +542,6 @@ auto by_prec(xls_subdomain_s* s, F&& f) {
 }  // namespace
 
 namespace xls {
-namespace {
 // Throws INVALID_ARG unless [p, p + bytes) lies inside one device allocation.
 void check_device_range(const void* p, size_t bytes) {
   hipPointerAttribute_t at{};
@@ -558,7 +557,6 @@ void check_device_range(const void* p, size_t bytes) {
   const char* q = static_cast<const char*>(p);
   if (q < b || q + bytes > b + size) fail(XLS_ERR_INVALID_ARG, "device buffer too small");
 }
-}  // namespace
 }  // namespace xls
 
 namespace xls {

@@ -27,8 +27,10 @@
 // which are parallel over eigenvalues.
 #include <algorithm>
 #include <cmath>
+#include <mutex>
+#include <string>
 
-#include "xls_internal.h"
+#include "xls_handle.h"
 
 namespace xls {
 namespace {
@@ -1413,6 +1415,10 @@ void dense_alloc(DenseWork& w, int n, double* ext_work, size_t ext_elems) {
 }
 
 void dense_free(DenseWork& w) {
+  if (w.borrowed) {
+    w = DenseWork{};
+    return;
+  }
   if (!w.own_gemm_work) w.gemm_work = nullptr;  // borrowed: the owner frees it
   w.own_gemm_work = true;
   double** ds[] = {&w.R, &w.Rinv, &w.C0, &w.C1, &w.T, &w.Vh, &w.Z, &w.vec, &w.scal, &w.gemm_work};
@@ -1546,3 +1552,103 @@ int dense_geneig(DenseWork& w, const double* Hs, const double* M, double* Y, hip
 }
 
 }  // namespace xls
+
+// ---------------------------------------------------------------------------
+// Allocation-free dense solve: the workspace is carved from a file-scope
+// device array instead of hipMalloc.  Host code never passes the array's
+// name to a kernel (that is a host-side stand-in); it takes the device
+// address from hipGetSymbolAddress once per device and uses that.
+// ---------------------------------------------------------------------------
+namespace xls {
+namespace {
+
+constexpr int kNoAllocMaxN = 512;
+constexpr size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+// bytes the carve below takes for n: seven n x n matrices, the vectors, the
+// pivot scalars, the flag, the integer vectors and the split-K workspace
+// (the same size dense_alloc gives it, so the split counts are the same)
+size_t noalloc_bytes(int n) {
+  const size_t nn = static_cast<size_t>(n) * n;
+  return 7 * align256(nn * 8) + align256(static_cast<size_t>(n) * 8 * DenseWork::kVecs) +
+         align256((static_cast<size_t>(n) + 16) * 8) + align256(64) +
+         align256(static_cast<size_t>(n) * 4 * DenseWork::kIvecs + 64) + align256(gemm_tn_work_elems(n, n, n) * 8);
+}
+// 7 * 512^2 doubles (14 MiB) + a 4-split workspace (8 MiB) + vectors
+constexpr size_t kScratchBytes = 24u << 20;
+
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[64] = {};
+
+// Device address of this device's copy of scratch (looked up once per device).
+void* scratch_address() {
+  int dev = 0;
+  XLS_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) fail(XLS_ERR_DEVICE, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      (void)hipGetLastError();
+      fail(XLS_ERR_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    }
+    g_scratch_ptr[dev] = p;
+  }
+  return g_scratch_ptr[dev];
+}
+
+// DenseWork for n with every buffer inside [base, base + bytes).
+void dense_carve(DenseWork& w, int n, unsigned char* base, size_t bytes) {
+  if (noalloc_bytes(n) > bytes) fail(XLS_ERR_INVALID_ARG, "dense scratch too small");
+  const size_t nn = static_cast<size_t>(n) * n;
+  size_t off = 0;
+  auto take = [&](size_t b) {
+    unsigned char* p = base + off;
+    off += align256(b);
+    return p;
+  };
+  w = DenseWork{};
+  w.n = n;
+  w.borrowed = true;
+  double** mats[] = {&w.R, &w.Rinv, &w.C0, &w.C1, &w.T, &w.Vh, &w.Z};
+  for (double** p : mats) *p = reinterpret_cast<double*>(take(nn * 8));
+  w.vec = reinterpret_cast<double*>(take(static_cast<size_t>(n) * 8 * DenseWork::kVecs));
+  w.scal = reinterpret_cast<double*>(take((static_cast<size_t>(n) + 16) * 8));
+  w.flag = reinterpret_cast<int32_t*>(take(64));
+  w.ivec = reinterpret_cast<int32_t*>(take(static_cast<size_t>(n) * 4 * DenseWork::kIvecs + 64));
+  w.gemm_work_elems = gemm_tn_work_elems(n, n, n);
+  w.gemm_work = reinterpret_cast<double*>(take(w.gemm_work_elems * 8));
+  w.own_gemm_work = false;
+}
+
+static_assert(kNoAllocMaxN * kNoAllocMaxN * 8 * 7 < kScratchBytes, "scratch holds the largest solve");
+
+}  // namespace
+}  // namespace xls
+
+extern "C" int xls_dense_geneig_noalloc(int32_t n, const double* Hs, const double* M, double* lam, double* Y,
+                                        void* stream) {
+  using namespace xls;
+  return guarded([&]() -> int {
+    if (n < 1 || n > kNoAllocMaxN) fail(XLS_ERR_INVALID_ARG, "xls_dense_geneig_noalloc supports 1 <= n <= 512");
+    if (!Hs || !M || !lam || !Y) fail(XLS_ERR_INVALID_ARG, "NULL argument");
+    const size_t nn8 = static_cast<size_t>(n) * n * 8;
+    check_device_range(Hs, nn8);
+    check_device_range(M, nn8);
+    check_device_range(Y, nn8);
+    check_device_range(lam, static_cast<size_t>(n) * 8);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    DenseWork w;
+    dense_carve(w, n, static_cast<unsigned char*>(scratch_address()), kScratchBytes);
+    const int rc = dense_geneig(w, Hs, M, Y, st, true);
+    if (rc != XLS_OK) {
+      set_last_error("M is not positive definite");
+      return rc;
+    }
+    XLS_HIP(hipMemcpyAsync(lam, w.lam(), static_cast<size_t>(n) * 8, hipMemcpyDeviceToDevice, st));
+    XLS_HIP(hipStreamSynchronize(st));
+    return XLS_OK;
+  });
+}

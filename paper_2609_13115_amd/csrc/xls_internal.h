@@ -199,6 +199,7 @@ struct DenseWork {
   double* gemm_work = nullptr;
   size_t gemm_work_elems = 0;
   bool own_gemm_work = true;
+  bool borrowed = false;  // every buffer carved from caller-owned memory (dense_free leaves them)
   const double* lam() const { return vec; }
 };
 // ext_work (may be null): a split-K workspace of ext_elems doubles owned by
@@ -214,6 +215,10 @@ size_t dense_bytes(int n, bool own_gemm_work);
 // (nonzero: not positive definite; the later stages then skip their work).
 int dense_geneig(DenseWork& w, const double* Hs, const double* M, double* Y, hipStream_t st,
                  bool check_spd = true);
+
+// Throws INVALID_ARG unless [p, p + bytes) lies inside one device allocation
+// (host memory, pinned or not, is refused).
+void check_device_range(const void* p, size_t bytes);
 
 // vector helpers (vecops.hip)
 template <typename TS>

@@ -46,6 +46,7 @@ EXPORTED = [
     "xls_mlp_train", "xls_mlp_predict", "xls_set_graphs", "xls_subdomain_time_gemms",
     "xls_mlp_fit", "xls_mlp_train_rms", "xls_mlp_bounds", "xls_learned_safe_bounds",
     "xls_batch_create_slots", "xls_subdomain_tune_gemm", "xls_subdomain_use_half",
+    "xls_dense_geneig_noalloc",
 ]
 
 

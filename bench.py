@@ -1,29 +1,29 @@
 """Benchmark: subdomain CheFSI on one MI355X.
 
-Workload: a 64^3 zero-Dirichlet box (h = 0.432 bohr) around a 64-atom displaced
-diamond-Si core, 279 atoms with Kleinman-Bylander projectors, ns = 480
-vectors, filter degree m = 24 (synthetic stand-in for the paper's Si
-subsystems).  A step is one CheFSI iteration: m fused filter sweeps,
-H*Psi_f, the two projection GEMMs, the FP64 dense eigensolve, the rotation
-and the FP64 residual check.
+Headline (value, dtype f64): a 64^3 zero-Dirichlet box (h = 0.432 bohr)
+around a 64-atom displaced diamond-Si core, 279 atoms with Kleinman-Bylander
+projectors, ns = 480 vectors, filter degree m = 24 (synthetic stand-in for
+the paper's Si subsystems).  A step is one FP64 CheFSI iteration: m fused
+filter sweeps, H*Psi_f, the two projection GEMMs, the FP64 dense eigensolve,
+the rotation and the FP64 residual check; value = N_d * ns * m / step time.
+The mixed form (FP32 filter + split-BF16 GEMMs + FP64 dense) is reported
+beside it.  roofline prices the FP64 fused filter kernel (3 words per
+grid-pt*vec*deg) against 8 TB/s from HIP events around every filter launch,
+and against a device-to-device copy measured in the same run.
 
-value = filtered grid-pt*vec*deg per second over whole steps
-(N_d * ns * m / step time), for the chosen form (FP32 filter + split-BF16
-GEMMs + FP64 dense); the plain FP64 path is reported beside it.
-subdomains_per_s counts the workload's 5 CheFSI iterations per subdomain.  The
-roofline object prices the fused filter kernel (3 words per grid-pt*vec*deg)
-against 8 TB/s, from HIP events around every filter launch, and against a
-device-to-device copy measured in the same run.  The gemm object times the
-projection and rotation GEMMs (HIP events) in each precision of the form.
-The batch object runs the first subdomains of the 256-subdomain uneven batch
-workload to convergence (gated residual <= 1e-4), mixed and FP64, and
-reports subdomains/s and the largest Ritz-value difference between the two.
-The learned object trains the MLP on method-made labels of two-phase boxes,
-then batch-solves held-out boxes with FP64 + Lanczos bounds and with mixed
-+ learned bounds.
-cpu_baseline times the FP64 oracle's filter on a column sample on the host.
+batch: the 256-subdomain uneven draw at full size, solved to a gated
+residual of 1e-4 (at most 30 iterations) with slot residency, once in FP64
+with Lanczos bounds and once mixed with learned bounds (model trained first
+on method-made labels of smaller boxes of the same recipe); subdomains/s,
+converged counts, and the largest |Ritz difference| over the gated states of
+subdomains both forms converged.  learned_gain: the first 64 subdomains,
+mixed with Lanczos bounds against mixed with learned bounds (one
+precision).  gemm_large: the 96^3, Ns = 2,400 GEMM rates and their errors
+against FP64.  cpu_baseline times the FP64 oracle's filter on a column
+sample on the host.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--form mixed|fp64|both] [--no-cpu]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--batch 256] [--gain 64]
+                    [--no-gemm-large] [--headline-only] [--no-cpu]
 """
 from __future__ import annotations
 
@@ -41,7 +41,6 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 MFMA_PEAK_TFLOPS = {"bf16x3": 2500.0, "fp32": 157.3, "fp64": 78.6}  # dense, per MFMA dtype
 METRIC = "filtered grid-pt\u00b7vec\u00b7deg/s + subdomains/s: FP64 vs mixed+learned, dE<=1e-6 Ha"
-CHEFSI_ITERS = 5  # iterations per subdomain solve in this workload
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "filter_traffic.json")
 STENCIL_SOURCES = ["stencil_impl.h", "stencil_f32.hip", "stencil_f64.hip", "stencil_mix.hip"]
 
@@ -217,76 +216,79 @@ def time_gemms(s, nd: int, ns: int, form: str, reps: int = 5):
 
 
 def gemm_large(reps: int = 3):
-    """The three GEMMs at the large-subdomain shape (96^3 box, N_d = 884,736,
-    Ns = 2,400; X0 random-normal from the seeded generator), FP32 block for
-    bf16x3 and FP32, FP64 block for FP64."""
+    """The large-subdomain GEMM shape (96^3 box, N_d = 884,736, Ns = 2,400):
+    X random-normal (drawn on the device), filtered twice at degree 24 by the
+    FP64 path with Lanczos bounds.  On that X: M = X^T X and H_s = X^T H X in
+    FP64 (FP64 block), and in FP32 and split-BF16 on the FP32 rounding of X
+    (FP32 block, FP32 H); rates of the three GEMMs (HIP events) in every
+    precision; errors against the FP64 products: relative Frobenius error of
+    M and H_s, the largest |Ritz value difference| of the pencils (H_s, M)
+    over the lowest N_occ = floor(Ns / 1.1), and sin theta between their
+    lowest N_occ eigenvector spaces (in the metric of the FP64 M, so equal to
+    the angle between the rotated blocks up to the FP32 rounding of X)."""
+    import scipy.linalg as sla
     from paper_2609_13115_amd import workloads, xls
 
     sd = workloads.si_box_96(with_x0=False)
-    x0 = sd.make_x0()
-    nd, ns = sd.nd, x0.shape[1]
-    out = {"workload": f"96^3 zero-Dirichlet Si box, N_d = {nd}, Ns = {ns}, X0 random-normal"}
-    for form, prec in (("mixed", xls.XLS_PREC_FP32), ("fp64", xls.XLS_PREC_FP64)):
-        with xls.Subdomain(sd, filter_prec=prec, x0=x0) as s:
-            out.update(time_gemms(s, nd, ns, form, reps))
-        print(f"[bench] gemm_large {form}: done", file=sys.stderr, flush=True)
-    return out
-
-
-def run_learned(n_train: int = 96, n_held: int = 64):
-    """FP64 + Lanczos bounds against mixed + learned bounds, both batched, on
-    held-out boxes of the two-phase system.  The model is trained first, on
-    labels the method computes for n_train other boxes (untimed); the mixed
-    form's timed region includes the device feature pass and the bf16
-    inference."""
-    import torch
-    from paper_2609_13115_amd import learned, workloads, xls
-
-    gs = workloads.two_phase_system()
-    _, train = workloads.learned_bounds_subdomains(n_train, index0=0, gs=gs)
-    _, held = workloads.learned_bounds_subdomains(n_held, index0=1000, gs=gs)
+    nd, ns = sd.nd, sd.ns
+    seed = workloads.x0_seed(sd.seed_key)
+    nocc = int(np.floor(ns / 1.1 + 1e-9))
+    out = {"workload": f"96^3 zero-Dirichlet Si box, N_d = {nd}, Ns = {ns}; X random-normal filtered twice "
+                       f"(degree 24, FP64)"}
     t0 = time.perf_counter()
-    lab = learned.label_subdomains(train)
-    model, losses = learned.train_model(lab.features, lab.targets, epochs=300)
-    t_train = time.perf_counter() - t0
-    gates = [max(1, int(np.floor(sd.ns / 1.1 + 1e-9))) for sd in held]
-    tol = 1e-4
-    out = {"workload": f"{n_held} held-out two-phase boxes (n 14-22 per axis, ns 8-48); model trained on "
-                       f"{n_train} labelled boxes in {t_train:.1f} s",
-           "subdomains": n_held}
-
-    def solve(prec, make_params, warm):
-        with xls.Batch(warm, filter_prec=prec) as b:  # loads this form's code objects
-            b.xls_batch_chefsi(make_params(b, 2))
-        with xls.Batch(held, filter_prec=prec) as b:
-            torch.cuda.synchronize()
-            t = time.perf_counter()
-            ritz, resid, iters, status = b.xls_batch_chefsi(make_params(b, 30))
-            torch.cuda.synchronize()
-            t = time.perf_counter() - t
-        conv = [int(st == xls.XLS_OK and float(np.max(r[:g])) <= tol) for st, r, g in zip(status, resid, gates)]
-        return t, ritz, [int(i) for i in iters], conv
-
-    def fp64_params(b, it):
-        return [xls.chefsi_params(24, it, xls.XLS_BOUNDS_LANCZOS, resid_tol=tol) for _ in range(b.n)]
-
-    def learned_params(b, it):
-        F = learned.batch_features(b)
-        return learned.batch_learned_params(model, F, it, tol, xls.XLS_PREC_BF16X3)
-
-    warm = held[:2]
-    tf, rf, itf, cf = solve(xls.XLS_PREC_FP64, fp64_params, warm)
-    tm, rm, itm, cm = solve(xls.XLS_PREC_FP32, learned_params, warm)
-    both = [float(np.max(np.abs(a[:g] - b[:g]))) for a, b, g, u, v in zip(rm, rf, gates, cm, cf) if u and v]
-    out["fp64_lanczos"] = {"seconds": tf, "subdomains_per_s": n_held / tf, "iterations": int(sum(itf)),
-                           "converged": int(sum(cf))}
-    out["mixed_learned"] = {"seconds": tm, "subdomains_per_s": n_held / tm, "iterations": int(sum(itm)),
-                            "converged": int(sum(cm))}
-    out["speedup"] = tf / tm
-    out["max_ritz_diff_ha_converged"] = max(both) if both else None
-    model.close()
-    print(f"[bench] learned: {json.dumps(out)}", file=sys.stderr, flush=True)
+    with xls.Subdomain(sd, filter_prec=xls.XLS_PREC_FP64, x0_seed=seed) as s:
+        lo, up = s.xls_lanczos_bounds(20)
+        lc = lo + 0.1 * (up - lo)
+        s.xls_subdomain_filter(24, lo, lc, up)
+        s.xls_subdomain_filter(24, lo, lc, up)
+        M64, H64 = s.xls_subdomain_project(xls.XLS_PREC_FP64)
+        out.update(time_gemms(s, nd, ns, "fp64", reps))
+        X = s.xls_subdomain_get_block()
+    print(f"[bench] gemm_large fp64 done ({time.perf_counter() - t0:.0f} s)", file=sys.stderr, flush=True)
+    lam64, Y64 = xls.xls_dense_geneig(H64, M64)
+    R = sla.cholesky(M64, lower=False)
+    B64 = R @ Y64[:, :nocc]  # orthonormal: Y^T M Y = I
+    errs = {}
+    with xls.Subdomain(sd, filter_prec=xls.XLS_PREC_FP32, x0_seed=seed) as s:
+        s.xls_subdomain_set_block(X)
+        del X
+        out.update(time_gemms(s, nd, ns, "mixed", reps))
+        for name, prec in (("fp32", xls.XLS_PREC_FP32), ("bf16x3", xls.XLS_PREC_BF16X3)):
+            M, H = s.xls_subdomain_project(prec)
+            lam, Y = xls.xls_dense_geneig(H, M)
+            Bp, _ = np.linalg.qr(R @ Y[:, :nocc])
+            D = Bp - B64 @ (B64.T @ Bp)
+            errs[name] = {"M_rel_fro": float(np.linalg.norm(M - M64) / np.linalg.norm(M64)),
+                          "Hs_rel_fro": float(np.linalg.norm(H - H64) / np.linalg.norm(H64)),
+                          "max_ritz_diff": float(np.max(np.abs(lam[:nocc] - lam64[:nocc]))),
+                          "max_ritz_diff_rel": float(np.max(np.abs(lam[:nocc] - lam64[:nocc]) /
+                                                            np.maximum(np.abs(lam64[:nocc]), 1e-3))),
+                          "sin_theta": float(np.linalg.norm(D, 2))}
+    out["errors_vs_fp64"] = errs
+    out["n_occ"] = nocc
+    print(f"[bench] gemm_large: {json.dumps(errs)} ({time.perf_counter() - t0:.0f} s)", file=sys.stderr, flush=True)
     return out
+
+
+def train_learned(n_train: int = 64, max_iter: int = 16):
+    """The learned-bounds model for the batch workload: labels from the method
+    (batch engine, FP32 filter and GEMMs) on n_train smaller boxes of the same
+    recipe (core 8-40 atoms, a different draw of the crystal), then training
+    with the library's kernels (xls_mlp_fit)."""
+    from paper_2609_13115_amd import learned, workloads
+
+    t0 = time.perf_counter()
+    _, train, _ = workloads.batch_subdomains(count=n_train, key_cfg=6, nmin=20, nmax=60, core_atoms=(8, 40))
+    lab = learned.label_subdomains(train, max_iter=max_iter)
+    t1 = time.perf_counter()
+    model, losses = learned.train_model(lab.features, lab.targets, epochs=300)
+    t2 = time.perf_counter()
+    info = {"training_boxes": n_train, "grids": f"{min(sd.n[0] for sd in train)}^3-{max(sd.n[0] for sd in train)}^3",
+            "labels_s": t1 - t0, "train_s": t2 - t1, "labels_converged": float(lab.converged.mean()),
+            "loss_first": float(np.mean(losses[:20])), "loss_last": float(np.mean(losses[-20:])),
+            "train_rms": [float(v) for v in model.train_rms()]}
+    print(f"[bench] learned model: {json.dumps(info)}", file=sys.stderr, flush=True)
+    return model, info
 
 
 def copy_rate(mib: int = 1024, reps: int = 5):
@@ -312,50 +314,79 @@ def copy_rate(mib: int = 1024, reps: int = 5):
     return 2.0 * (mib << 20) / (t * 1e-3) / 1e9
 
 
-def run_batch(count: int, forms):
-    """The first `count` subdomains of the uneven batch workload, solved to a
-    gated residual of 1e-4 (at most 40 iterations) with Lanczos bounds and
-    tuned tile shapes, once per form; wall time from the call to the last
-    subdomain's convergence."""
+def run_cfg3(count: int, forms, max_iter: int = 30, tol: float = 1e-4, model=None, budget: int = 0,
+             tune_cache: str = None, occupation: bool = False):
+    """The uneven batch workload at full size: `count` subdomains of the
+    256-subdomain draw (start blocks drawn on the device), run with slot
+    residency (working sets admitted largest-first within the device memory
+    budget, released when a subdomain finishes), until each subdomain's gated
+    residual is <= tol or max_iter iterations.  Forms: "fp64" (FP64 filter
+    and GEMMs, Lanczos bounds), "mixed" (FP32 filter, split-BF16 GEMMs with
+    the FP32 polish, Lanczos bounds) and "mixed_learned" (the same with the
+    model's bounds and degree, Lanczos fallback).  subdomains/s counts every
+    subdomain; converged ones are reported beside."""
     import torch
-    from paper_2609_13115_amd import workloads, xls
+    from paper_2609_13115_amd import learned, workloads, xls
 
+    t0 = time.perf_counter()
     _, subs, degs = workloads.batch_subdomains(count=count)
-    x0s = [sd.make_x0() for sd in subs]
-    for sd in subs:
-        sd.lanczos_v0 = sd.make_lanczos_v0()
-    desc = (f"first {count} of the 256-subdomain uneven batch draw: grids "
-            f"{min(sd.n[0] for sd in subs)}^3-{max(sd.n[0] for sd in subs)}^3, ns "
-            f"{min(sd.ns for sd in subs)}-{max(sd.ns for sd in subs)}, degree {min(degs)}-{max(degs)}; "
-            f"{sum(sd.nd * sd.ns * m for sd, m in zip(subs, degs)):.3e} pt*vec*deg per iteration")
-    out = {"workload": desc, "subdomains": count}
+    seeds = [workloads.x0_seed(sd.seed_key) for sd in subs]
+    gates = [max(1, int(np.floor(sd.ns / 1.1 + 1e-9))) for sd in subs]
+    work = sum(sd.nd * sd.ns * m for sd, m in zip(subs, degs))
+    out = {"workload": f"{count} subdomains of the uneven batch draw: grids {min(sd.n[0] for sd in subs)}^3-"
+                       f"{max(sd.n[0] for sd in subs)}^3, ns {min(sd.ns for sd in subs)}-"
+                       f"{max(sd.ns for sd in subs)}, degree {min(degs)}-{max(degs)}; {work:.3e} pt*vec*deg per "
+                       f"iteration over all; FP32 blocks of all of them {2 * 4 * sum(sd.nd * sd.ns for sd in subs) / 1e9:.0f} GB "
+                       f"(two per subdomain)",
+           "subdomains": count, "setup_s": time.perf_counter() - t0, "gate": tol, "max_iter": max_iter}
+    print(f"[bench] cfg3 draw built in {out['setup_s']:.1f} s", file=sys.stderr, flush=True)
     ritz_of = {}
+    os.environ.setdefault("XLS_BATCH_PROGRESS", "20")
     for form in forms:
         prec = xls.XLS_PREC_FP64 if form == "fp64" else xls.XLS_PREC_FP32
         gprec = xls.XLS_PREC_FP64 if form == "fp64" else xls.XLS_PREC_BF16X3
-        params = [xls.chefsi_params(m, 40, xls.XLS_BOUNDS_LANCZOS, resid_tol=1e-4, gemm_prec=gprec) for m in degs]
-        with xls.Batch(subs, filter_prec=prec, x0s=x0s) as b:
-            b.xls_batch_tune(None)
+        with xls.Batch(subs, filter_prec=prec, x0_seeds=seeds, slots=budget) as b:
+            tt = time.perf_counter()
+            b.xls_batch_tune(tune_cache)
+            t_tune = time.perf_counter() - tt
             torch.cuda.synchronize()
-            t0 = time.perf_counter()
+            t = time.perf_counter()
+            if form == "mixed_learned":
+                F = learned.batch_features(b)
+                params = learned.batch_learned_params(model, F, max_iter, tol, gprec)
+            else:
+                params = [xls.chefsi_params(m, max_iter, xls.XLS_BOUNDS_LANCZOS, resid_tol=tol, gemm_prec=gprec)
+                          for m in degs]
             ritz, resid, iters, status = b.xls_batch_chefsi(params)
             torch.cuda.synchronize()
-            t = time.perf_counter() - t0
-            occ = occupation_timing(b, subs, prec)
-        gates = [max(1, int(np.floor(sd.ns / 1.1 + 1e-9))) for sd in subs]
-        conv = [int(st == xls.XLS_OK and float(np.max(r[:g])) <= 1e-4) for st, r, g in zip(status, resid, gates)]
-        ritz_of[form] = (ritz, gates, conv)
-        out[form] = {"seconds": t, "subdomains_per_s": count / t, "iterations": [int(i) for i in iters],
-                     "converged": int(sum(conv)), "occupation": occ}
-        print(f"[bench] batch {form}: {json.dumps(out[form])}", file=sys.stderr, flush=True)
-    if "mixed" in ritz_of and "fp64" in ritz_of:
-        (rm, g, cm), (rf, _, cf) = ritz_of["mixed"], ritz_of["fp64"]
-        d = [float(np.max(np.abs(a[:k] - b[:k]))) for a, b, k in zip(rm, rf, g)]
-        both = [x for x, u, v in zip(d, cm, cf) if u and v]
-        # largest |lambda_mixed - lambda_fp64| over the gated states, per subdomain
-        out["ritz_diff_ha"] = d
-        out["max_ritz_diff_ha_converged"] = max(both) if both else None
-        out["speedup_mixed_vs_fp64"] = out["fp64"]["seconds"] / out["mixed"]["seconds"]
+            t = time.perf_counter() - t
+            st = b.xls_batch_stats()
+            fb = sum(int(b.xls_batch_subdomain(i).xls_subdomain_counters()["fallback"]) for i in range(count))
+            happ = sum(b.xls_batch_subdomain(i).xls_subdomain_counters()["h_applies"] for i in range(count))
+            occ = occupation_timing(b, subs, prec) if occupation else None
+        conv = [int(s_ == xls.XLS_OK and float(np.max(r[:g])) <= tol) for s_, r, g in zip(status, resid, gates)]
+        ritz_of[form] = (ritz, conv)
+        out[form] = {"seconds": t, "subdomains_per_s": count / t, "converged": int(sum(conv)),
+                     "unconverged": count - int(sum(conv)), "converged_per_s": sum(conv) / t,
+                     "iterations_total": int(sum(iters)), "iterations_max": int(max(iters)),
+                     "h_applies": int(happ), "fallbacks": int(fb), "tune_s": t_tune,
+                     "batch_iterations": st["iterations"], "peak_resident_gb": st["peak_bytes"] / 1e9,
+                     "max_active": st["max_active"], "device_ms": st["iter_ms"]}
+        if occ is not None:
+            out[form]["occupation"] = occ
+        print(f"[bench] cfg3 {form}: {json.dumps(out[form])}", file=sys.stderr, flush=True)
+    ref = ritz_of.get("fp64")
+    if ref is not None:
+        for form in forms:
+            if form == "fp64":
+                continue
+            rm, cm = ritz_of[form]
+            rf, cf = ref
+            d = [float(np.max(np.abs(a[:g] - b_[:g]))) for a, b_, g, u, v in zip(rm, rf, gates, cm, cf) if u and v]
+            out[form]["max_ritz_diff_ha_both_converged"] = max(d) if d else None
+            out[form]["both_converged"] = len(d)
+            out[form]["speedup_vs_fp64"] = out["fp64"]["seconds"] / out[form]["seconds"]
+            out[form]["gate_met"] = bool(d) and max(d) <= 1e-6 and out[form]["converged"] >= out["fp64"]["converged"]
     return out
 
 
@@ -406,18 +437,18 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--form", default="both", choices=["mixed", "fp64", "both"])
     ap.add_argument("--ns", type=int, default=480)
     ap.add_argument("--degree", type=int, default=24)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-cols", type=int, default=64)
     ap.add_argument("--calib-mib", type=int, default=0,
                     help="first run a device-to-device copy of this many MiB (counter calibration)")
-    ap.add_argument("--batch", type=int, default=8,
-                    help="subdomains of the uneven batch workload to solve per form (0: skip)")
-    ap.add_argument("--no-learned", action="store_true", help="skip the learned-bounds batch comparison")
-    ap.add_argument("--gemm-large", action="store_true",
-                    help="also time the GEMMs at the 96^3, Ns = 2400 shape (about 3 minutes; 17 GB host memory)")
+    ap.add_argument("--batch", type=int, default=256,
+                    help="subdomains of the uneven batch draw to solve, FP64 and mixed + learned (0: skip)")
+    ap.add_argument("--gain", type=int, default=64,
+                    help="subdomains for the learned gain at one precision, mixed + Lanczos vs mixed + learned")
+    ap.add_argument("--no-gemm-large", action="store_true", help="skip the 96^3, Ns = 2400 GEMM table")
+    ap.add_argument("--headline-only", action="store_true", help="only the 64^3 steps (profiling runs)")
     ap.add_argument("--write-traffic", nargs=3, metavar=("FORM", "FETCH_CSV", "WRITE_CSV"),
                     help="record filter HBM traffic from two rocprofv3 --pmc passes and exit (no GPU)")
     a = ap.parse_args()
@@ -432,6 +463,7 @@ def main():
     from paper_2609_13115_amd import workloads
 
     torch.cuda.set_device(0)
+    torch.cuda.synchronize()
     sd = workloads.si_box_64(with_x0=False, ns=a.ns)
     x0 = sd.make_x0(a.ns)
     sd.x0 = x0
@@ -445,14 +477,14 @@ def main():
         print(f"[bench] calibration copy: {a.calib_mib} MiB", file=sys.stderr, flush=True)
         del src, dst
     copy_gbs = copy_rate()
+    torch.cuda.empty_cache()
     print(f"[bench] device copy: {copy_gbs:.1f} GB/s", file=sys.stderr, flush=True)
     res = {}
-    forms = ["mixed", "fp64"] if a.form == "both" else [a.form]
-    for f in forms:
+    for f in ("fp64", "mixed"):
         res[f] = run_form(sd, x0, f, a.steps, a.warmup, a.degree)
         print(f"[bench] {f}: {json.dumps(res[f])}", file=sys.stderr, flush=True)
-    main_form = "mixed" if "mixed" in res else "fp64"
-    r = res[main_form]
+    r = res["fp64"]
+    m = res["mixed"]
     out = {
         "metric": METRIC,
         "value": r["value"],
@@ -464,31 +496,38 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if main_form == "mixed" else "f64",
+        "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"64^3 zero-Dirichlet Si subdomain (64-atom core, 279 projector atoms), "
-                               f"ns={a.ns}, degree={a.degree}, one CheFSI iteration per step",
-                   "form": "FP32 filter + split-BF16 GEMMs + FP64 dense" if main_form == "mixed" else "FP64",
+                               f"ns={a.ns}, degree={a.degree}, one FP64 CheFSI iteration per step "
+                               f"(FP64 filter, GEMMs, dense and residual)",
                    "parallelism": "single GPU"},
         "roofline": dict(r["roofline"], copy_gbs=copy_gbs, frac_of_copy=r["roofline"]["achieved"] / copy_gbs),
-        "subdomains_per_s": 1e3 / (CHEFSI_ITERS * r["ms_per_step"]),
-        "gemm": r["gemm"],
-        "half_storage": r["half_storage"],
         "filter_rate": r["filter_rate"],
         "stage_ms_per_step": r["stage_ms_per_step"],
+        "gemm": r["gemm"],
+        "mixed": {"form": "FP32 filter + split-BF16 GEMMs (FP32 polish) + FP64 dense and residual",
+                  "value": m["value"], "ms_per_step": m["ms_per_step"], "filter_rate": m["filter_rate"],
+                  "roofline": dict(m["roofline"], frac_of_copy=m["roofline"]["achieved"] / copy_gbs),
+                  "stage_ms_per_step": m["stage_ms_per_step"], "gemm": m["gemm"],
+                  "half_storage": m["half_storage"]},
     }
-    if "fp64" in res and main_form != "fp64":
-        f = res["fp64"]
-        out["fp64"] = {"value": f["value"], "ms_per_step": f["ms_per_step"], "filter_rate": f["filter_rate"],
-                       "subdomains_per_s": 1e3 / (CHEFSI_ITERS * f["ms_per_step"]),
-                       "roofline": dict(f["roofline"], frac_of_copy=f["roofline"]["achieved"] / copy_gbs),
-                       "stage_ms_per_step": f["stage_ms_per_step"], "gemm": f["gemm"]}
-    if a.batch > 0:
-        out["batch"] = run_batch(a.batch, forms)
-    if not a.no_learned and a.form == "both":
-        out["learned"] = run_learned()
-    if a.gemm_large:
-        out["gemm_large"] = gemm_large()
+    if not a.headline_only:
+        tune = os.path.join("/tmp", f"xls_tune_{os.getpid()}.json")
+        model, info = train_learned()
+        if a.batch > 0:
+            out["batch"] = run_cfg3(a.batch, ["fp64", "mixed_learned"], model=model, tune_cache=tune,
+                                    occupation=True)
+            out["batch"]["learned_model"] = info
+            b = out["batch"]
+            out["subdomains_per_s"] = {"fp64": b["fp64"]["subdomains_per_s"],
+                                       "mixed_learned": b["mixed_learned"]["subdomains_per_s"]}
+            out["max_ritz_diff_ha"] = b["mixed_learned"].get("max_ritz_diff_ha_both_converged")
+        if a.gain > 0:
+            out["learned_gain"] = run_cfg3(a.gain, ["mixed", "mixed_learned"], model=model, tune_cache=tune)
+        model.close()
+        if not a.no_gemm_large:
+            out["gemm_large"] = gemm_large()
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(sd, a.degree, a.cpu_cols)
     print(json.dumps(out), flush=True)

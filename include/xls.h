@@ -431,10 +431,12 @@ int xls_subdomain_features(xls_subdomain_t s, double* f);
  * xls_batch_subdomain: borrowed handle of subdomain i (for the per-handle
  *   hooks); owned by the batch, never destroyed by the caller.
  * xls_batch_tune: times the fused filter kernel of one subdomain per shape
- *   class (grid, boundary, precision, atom count) over block {256, 512} x
+ *   class (precision, n[0], n[1] and n[2] rounded up to 8, boundary, atom
+ *   count rounded up to 64; a member whose extents do not admit its class's
+ *   shape keeps its own) over block {256, 512} x
  *   rows-per-tile {auto, 1, 2, 4, 8, 16} x vectors per tile {1, 2}, and the
- *   projection and rotation GEMMs of one subdomain per (precision, N_d, ns)
- *   class over split scale {default, 1/2, 2, 4} x tile kind (FP32 GEMMs for
+ *   projection and rotation GEMMs of one subdomain per (precision, N_d
+ *   rounded up to 32768, ns rounded up to 32) class over split scale {default, 1/2, 2, 4} x tile kind (FP32 GEMMs for
  *   FP32 batches), and applies the fastest to each class
  *   (xls_subdomain_tune, xls_subdomain_tune_gemm).  cache_path (may be
  *   NULL): JSON object "shape key": [block, ty, nv] and "gemm_... key":

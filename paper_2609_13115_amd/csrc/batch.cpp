@@ -19,6 +19,8 @@
 
 #include <algorithm>
 #include <array>
+#include <chrono>
+#include <cstdlib>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -135,7 +137,7 @@ struct xls_batch_s {
   // admission and released when a subdomain finishes, within a byte budget
   bool slots = false;
   int64_t budget = 0;
-  int64_t resident_bytes = 0, peak_bytes = 0;
+  int64_t resident_bytes = 0, peak_bytes = 0;  // working sets and core stores held
   int max_active = 0;
   std::vector<double*> pool_gwork;  // split-K workspace per pool stream (shared by its handles)
   size_t pool_gwork_elems = 0;
@@ -470,11 +472,13 @@ void finalize_slot(xls_batch_s* b, int i) {
   if (cs.ncore > 0) {
     cs.release_blk();
     cs.blk = dalloc<TS>(static_cast<size_t>(cs.ld) * s->ns);
+    b->resident_bytes += cs.ld * s->ns * static_cast<int64_t>(sizeof(TS));
     launch_gather_rows<TS>(B<TS>(s, s->cur), s->ld, cs.rows, cs.ncore, s->ns, static_cast<TS*>(cs.blk), cs.ld,
                            s->st);
   }
   XLS_HIP(hipStreamSynchronize(s->st));
   b->resident_bytes -= static_cast<int64_t>(subdomain_ws_bytes(s, true));
+  b->peak_bytes = std::max(b->peak_bytes, b->resident_bytes);
   subdomain_ws_free(s);
 }
 
@@ -519,9 +523,12 @@ void batch_chefsi(xls_batch_s* b, const xls_chefsi_params_t* P, int use_graph) {
   if (b->slots) {
     for (int i = 0; i < n; ++i) {
       b->core[i].release_blk();
+      if (b->subs[i]->resident) subdomain_ws_free(b->subs[i]);  // left by an interrupted call
       b->subs[i]->have_ritz = false;
       pending.push_back(i);
     }
+    b->resident_bytes = 0;  // no working set or core store is held between calls
+    b->peak_bytes = 0;
     std::stable_sort(pending.begin(), pending.end(), [&](int x, int y) {
       const double cx = static_cast<double>(b->subs[x]->nd) * b->subs[x]->ns * P[x].degree;
       const double cy = static_cast<double>(b->subs[y]->nd) * b->subs[y]->ns * P[y].degree;
@@ -532,7 +539,27 @@ void batch_chefsi(xls_batch_s* b, const xls_chefsi_params_t* P, int use_graph) {
     for (auto* s : b->subs) XLS_HIP(hipStreamSynchronize(s->st));
   }
   size_t next = 0;
+  // optional progress lines on stderr (XLS_BATCH_PROGRESS=seconds between lines)
+  const char* prog_env = std::getenv("XLS_BATCH_PROGRESS");
+  const double prog_every = prog_env ? std::atof(prog_env) : 0.0;
+  auto t_start = std::chrono::steady_clock::now();
+  auto t_last = t_start;
   for (;;) {
+    if (prog_every > 0) {
+      const auto now = std::chrono::steady_clock::now();
+      if (std::chrono::duration<double>(now - t_last).count() >= prog_every) {
+        t_last = now;
+        int act = 0, done = 0;
+        for (int i = 0; i < n; ++i) {
+          act += b->st[i].active;
+          done += b->st[i].started && !b->st[i].active;
+        }
+        std::fprintf(stderr, "[xls batch] %.1f s: iteration %lld, %d active, %d done of %d, resident %.1f GB\n",
+                     std::chrono::duration<double>(now - t_start).count(), static_cast<long long>(b->iterations),
+                     act, done, n, b->resident_bytes / 1e9);
+        std::fflush(stderr);
+      }
+    }
     if (b->slots) {  // admit while the budget allows (always at least one)
       bool any_active = false;
       for (int i = 0; i < n; ++i) any_active = any_active || b->st[i].active;
@@ -574,10 +601,14 @@ void batch_chefsi(xls_batch_s* b, const xls_chefsi_params_t* P, int use_graph) {
 
 // --- autotuner -------------------------------------------------------------
 
+// Shape classes: the filter kernel's tile depends on the exact row length
+// (n_x: halo budget, points per lane) and the boundary; n_y, n_z and the
+// atom count (LDS for the projection coefficients) only through their size,
+// so they are bucketed (8 planes, 64 atoms) and one timing serves a class.
 std::string shape_key(xls_subdomain_s* s) {
   std::ostringstream o;
-  o << (s->prec == XLS_PREC_FP32 ? "f32" : "f64") << "_" << s->n[0] << "x" << s->n[1] << "x" << s->n[2]
-    << (s->bc == XLS_BC_PERIODIC ? "_p" : "_d") << "_na" << s->n_atoms;
+  o << (s->prec == XLS_PREC_FP32 ? "f32" : "f64") << "_nx" << s->n[0] << "_ny" << (s->n[1] + 7) / 8 * 8 << "_nz"
+    << (s->n[2] + 7) / 8 * 8 << (s->bc == XLS_BC_PERIODIC ? "_p" : "_d") << "_na" << (s->n_atoms + 63) / 64 * 64;
   return o.str();
 }
 
@@ -638,9 +669,12 @@ double time_filter(xls_subdomain_s* s, const StencilLaunch& cfg, hipEvent_t e0, 
   return ms / reps;
 }
 
+// GEMM classes: N_d bucketed to 32768 rows (the split-K count follows it),
+// ns to 32 columns (the tile grid follows it).
 std::string gemm_key(xls_subdomain_s* s) {
   std::ostringstream o;
-  o << "gemm_" << (s->prec == XLS_PREC_FP32 ? "f32" : "f64") << "_nd" << s->nd << "_ns" << s->ns;
+  o << "gemm_" << (s->prec == XLS_PREC_FP32 ? "f32" : "f64") << "_nd" << (s->nd + 32767) / 32768 * 32768 << "_ns"
+    << (s->ns + 31) / 32 * 32;
   return o.str();
 }
 
@@ -798,10 +832,9 @@ int tune_batch(xls_batch_s* b, const char* cache_path, double* best_ms_out) {
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  for (auto* s : b->subs) {
+  for (auto* s : b->subs) {  // a member whose extents do not admit its class's shape keeps its own
     const auto& c = chosen[shape_key(s)];
-    const int rc = xls_subdomain_tune(s, s->prec, c[0], c[1], 0, c[2]);
-    if (rc != XLS_OK) fail(rc, std::string("applying tuned tile shape: ") + xls_last_error());
+    (void)xls_subdomain_tune(s, s->prec, c[0], c[1], 0, c[2]);
   }
   // projection / rotation GEMM plans per (precision, N_d, ns) class
   tuned += tune_gemms<TS>(b, cache, chosen);

@@ -56,14 +56,22 @@ def batch_features(b: "xls.Batch") -> np.ndarray:
 def label_subdomains(sds: Sequence, filter_prec: int = xls.XLS_PREC_FP32,
                      gemm_prec: int = xls.XLS_PREC_FP32, tol: float = 1e-4, max_iter: int = 12,
                      degrees: Sequence[int] = DEGREES, lanczos_k: int = 20) -> Labels:
-    """Labels of the training boxes, computed with the batch engine."""
+    """Labels of the training boxes, computed with the batch engine (start
+    blocks drawn on the device for boxes without a host x0)."""
+    from . import workloads
+
     n = len(sds)
-    with xls.Batch(list(sds), filter_prec=filter_prec) as b:
+    seeds = None if all(sd.x0 is not None for sd in sds) else [workloads.x0_seed(sd.seed_key) for sd in sds]
+
+    def batch():
+        return xls.Batch(list(sds), filter_prec=filter_prec, x0_seeds=seeds)
+
+    with batch() as b:
         F = batch_features(b)
         lmax = np.array([b.xls_batch_subdomain(i).xls_lanczos_bounds(lanczos_k)[1] for i in range(n)])
     params = [xls.chefsi_params(24, max_iter, xls.XLS_BOUNDS_LANCZOS, resid_tol=tol, lanczos_k=lanczos_k,
                                 gemm_prec=gemm_prec) for _ in range(n)]
-    with xls.Batch(list(sds), filter_prec=filter_prec) as b:
+    with batch() as b:
         ritz, _, _, _ = b.xls_batch_chefsi(params)
     cut = np.array([r[-1] for r in ritz])
     ok_all = np.zeros((n, len(degrees)), dtype=bool)
@@ -73,7 +81,7 @@ def label_subdomains(sds: Sequence, filter_prec: int = xls.XLS_PREC_FP32,
         params = [xls.chefsi_params(m, max_iter, xls.XLS_BOUNDS_LEARNED, lam_cut=float(lc_safe[i]),
                                     lam_max=float(lm_safe[i]), resid_tol=tol, gemm_prec=gemm_prec)
                   for i in range(n)]
-        with xls.Batch(list(sds), filter_prec=filter_prec) as b:
+        with batch() as b:
             _, resid, iters, status = b.xls_batch_chefsi(params)
         for i, sd in enumerate(sds):
             gate = max(1, int(np.floor(sd.ns / 1.1 + 1e-9)))

@@ -354,13 +354,16 @@ def small_dirichlet(n: int = 8, ns: int = 8, index: int = 0, with_x0: bool = Tru
 
 def batch_subdomains(count: int = 256, key_cfg: int = 3, with_x0: bool = False,
                      ncells: int = 10, h_target: float = 0.43,
-                     nmin: int = 40, nmax: int = 80) -> Tuple[GlobalSystem, List[Subdomain], List[int]]:
+                     nmin: int = 40, nmax: int = 80, core_atoms: Tuple[int, int] = (27, 125),
+                     ) -> Tuple[GlobalSystem, List[Subdomain], List[int]]:
     """Uneven buffered subdomains of one large displaced diamond crystal.
 
     Core atom count n_c ~ U{27..125}, buffer R ~ U[3, 6] bohr, core side
     s = (n_c a^3 / 8)^(1/3), n = clamp(round((s + 2R)/h), nmin, nmax),
     ns = clamp(ceil(2.2 * atoms in box), 60, 900), degree m ~ U{16..32}.
-    Returns (global system, subdomains, degrees).
+    Returns (global system, subdomains, degrees).  core_atoms widens or
+    narrows the n_c range (smaller boxes of the same recipe, e.g. to train
+    learned bounds on).
     """
     key = (SEED_BASE + 1000 * key_cfg, 0)
     gn = int(round(ncells * SI_A / h_target))
@@ -369,7 +372,7 @@ def batch_subdomains(count: int = 256, key_cfg: int = 3, with_x0: bool = False,
     rng = _rng(*key, 3)
     subs, degs = [], []
     for b in range(count):
-        nc = int(rng.integers(27, 126))
+        nc = int(rng.integers(core_atoms[0], core_atoms[1] + 1))
         R = float(rng.uniform(3.0, 6.0))
         s = (nc * SI_A ** 3 / 8.0) ** (1.0 / 3.0)
         n = int(min(max(round((s + 2 * R) / h), nmin), nmax))

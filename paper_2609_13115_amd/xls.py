@@ -195,6 +195,17 @@ def make_desc(sd, filter_prec: int = XLS_PREC_FP64, x0: Optional[np.ndarray] = N
     return d, [v, atoms, ps, X, lv]
 
 
+def tune_keys(sd, prec: int):
+    """(filter shape class, GEMM class) keys of xls_batch_tune's cache for a subdomain."""
+    n = [int(v) for v in sd.n]
+    pr = "f32" if prec == XLS_PREC_FP32 else "f64"
+    up = lambda v, q: (v + q - 1) // q * q  # noqa: E731
+    shape = (f"{pr}_nx{n[0]}_ny{up(n[1], 8)}_nz{up(n[2], 8)}_{'p' if int(sd.bc) == XLS_BC_PERIODIC else 'd'}"
+             f"_na{up(len(sd.atoms), 64)}")
+    nd = n[0] * n[1] * n[2]
+    return shape, f"gemm_{pr}_nd{up(nd, 32768)}_ns{up(int(sd.ns), 32)}"
+
+
 def chefsi_params(degree: int, max_iter: int, bounds_mode: int = XLS_BOUNDS_LANCZOS, lam_lo: float = 0.0,
                   lam_cut: float = 0.0, lam_max: float = 0.0, resid_tol: float = 0.0, n_gate: int = 0,
                   lanczos_k: int = 20, gemm_prec: int = XLS_PREC_FP64, fallback_tol: float = 0.0,

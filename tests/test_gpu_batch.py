@@ -126,9 +126,10 @@ def test_batch_tuner_cache_and_invariance(tmp_path):
     path = str(tmp_path / "tune.json")
     with xls.Batch(sds, filter_prec=xls.XLS_PREC_FP32) as b:
         tuned, best = b.xls_batch_tune(path)
-        assert tuned == 6 and best > 0
+        keys = {k for sd in sds for k in xls.tune_keys(sd, xls.XLS_PREC_FP32)}
+        assert tuned == len(keys) and best > 0
         cache = json.load(open(path))
-        assert len(cache) == 6
+        assert set(cache) == keys
         for k, v in cache.items():
             if k.startswith("gemm_"):
                 assert v[0] in (0, 1, 4, 8) and v[1] in (0, 1) and v[2] in (0, 1)
@@ -141,11 +142,10 @@ def test_batch_tuner_cache_and_invariance(tmp_path):
     single = []
     for sd, p in zip(sds, params):
         with xls.Subdomain(sd, filter_prec=xls.XLS_PREC_FP32) as s:
-            n = sd.n
-            key = f"f32_{n[0]}x{n[1]}x{n[2]}_{'p' if sd.bc == 0 else 'd'}_na{len(sd.atoms)}"
-            blk, ty, nv = cache[key]
+            skey, gkey = xls.tune_keys(sd, xls.XLS_PREC_FP32)
+            blk, ty, nv = cache[skey]
             s.xls_subdomain_tune(xls.XLS_PREC_FP32, blk, ty, 0, nv)
-            s.xls_subdomain_tune_gemm(*cache[f"gemm_f32_nd{sd.nd}_ns{sd.ns}"])
+            s.xls_subdomain_tune_gemm(*cache[gkey])
             r = s.xls_chefsi_step(p.degree, p.max_iter, p.bounds_mode, lanczos_k=p.lanczos_k, gemm_prec=p.gemm_prec)
             single.append(r + (s.xls_subdomain_get_block(),))
     assert_same(single, (ritz, resid, iters, status, blocks, None))

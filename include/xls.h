@@ -240,6 +240,27 @@ int xls_subdomain_load_half(xls_subdomain_t s, const uint16_t* src);
  * into the block first; set_block, load_half or another use_half replace
  * it.  Ritz values are dropped.  Errors as for xls_subdomain_load_half. */
 int xls_subdomain_use_half(xls_subdomain_t s, const uint16_t* src);
+/* Projected density of states (Sec. V-A.4, the PDOS equations): overlaps of
+ * the handle's current block with atom-centred atomic orbitals and the
+ * orbital-resolved PDOS.  The paper's atomic orbitals come with its
+ * pseudopotentials; here each atom carries s, px, py, pz orbitals of the
+ * projector shape (exp(-r^2/(2 w^2)), times x - X etc.; support r^2 <
+ * rc^2 by the rule of xls_subdomain_create, periodic images summed) with
+ * w = orb_width and rc = orb_rc, normalised so h^3 sum phi^2 = 1.  With the
+ * block's columns psi_n (unit 2-norm, the continuum orbital being psi_n /
+ * h^(3/2)): weights[n * 4 n_atoms + 4 I + l] = h^3 (sum_g phi_{I,l}(g)
+ * psi_n(g))^2 (the squared overlap |<phi|psi_n>|^2), for every atom.  With
+ * nbins > 0 (needs a completed xls_chefsi_step: STATE otherwise) and
+ * increasing edges[nbins + 1]: pdos[(4 I + l) * nbins + b] = sum of the
+ * weights of orbital (I, l) over the states with Ritz value in [edges[b],
+ * edges[b+1]) (the last bin closed), for atoms in the core and 0 for the
+ * others; an atom is in the core iff core_lo h <= X - origin < core_hi h on
+ * every axis (in_core[n_atoms], may be NULL, receives those flags).  Atom-
+ * and species-resolved PDOS are sums of these rows.  Host outputs; runs on
+ * the handle's stream and synchronises it.  INVALID_ARG for non-positive or
+ * non-finite w, rc, or non-increasing edges. */
+int xls_subdomain_pdos(xls_subdomain_t s, double orb_width, double orb_rc, double* weights, int32_t nbins,
+                       const double* edges, double* pdos, uint8_t* in_core);
 /* Integer maps: core_mask u8[N_d], global_index i64[N_d]. */
 int xls_subdomain_get_maps(xls_subdomain_t s, uint8_t* core_mask, int64_t* global_index);
 /* sizes[0] = total support slots, sizes[1] = n_atoms.  With NULL arrays only
@@ -484,6 +505,35 @@ int xls_batch_subdomain(xls_batch_t b, int32_t i, xls_subdomain_t* out);
 int xls_batch_tune(xls_batch_t b, const char* cache_path, int32_t* tuned, double* best_ms);
 int xls_batch_stats(xls_batch_t b, double* out, int32_t cap);
 void xls_batch_destroy(xls_batch_t b);
+
+/* ---- Electrostatic Poisson solve (Sec. IV Poisson equation; Sec. V-B.1) ----
+ * phi with -(1/(4 pi)) Lap phi = f on an n[0] x n[1] x n[2] grid (spacing h,
+ * index g = i + n[0] (j + n[1] k)), Lap the 12th-order FD Laplacian of the
+ * Hamiltonian with zero Dirichlet or periodic boundaries: A phi = 4 pi f
+ * with A = -Lap, by CG in FP64 from phi = 0, stopped when ||r|| <= tol ||4 pi
+ * f||.  Periodic: f is taken with its mean removed and phi is returned with
+ * zero mean (the constants are A's null space).  Preconditioner (precond
+ * 1): one FP32 multigrid V-cycle, finest level the 7-point Laplacian
+ * (6 u - sum of the 6 neighbours)/h^2 applied matrix-free, coarse levels the
+ * Galerkin operators P^T A P of trilinear prolongation (coarse point I on
+ * fine point 2I + 1 for zero Dirichlet, n -> (n - 1)/2 with n odd; on 2I for
+ * periodic, n -> n/2 with n even; levels are added while every axis
+ * coarsens exactly to at least 3 (Dirichlet) or 4 (periodic) points, at
+ * most max_levels (0: 8)); damped Jacobi (omega = 2/3) smoothing, 2 sweeps
+ * before and after each coarse correction, 10 from zero on the coarsest
+ * level; the zero start makes it symmetric.
+ * xls_poisson_create: INVALID_ARG for sizes < 1, non-positive h, unknown bc.
+ * xls_poisson_solve: f and phi host arrays of N values; info (may be NULL)
+ *   receives [iterations, final relative residual, levels, wall ms].
+ *   Returns XLS_OK also when max_iter is reached (info[1] tells).
+ * xls_poisson_vcycle: z = the preconditioner applied to r (host arrays of
+ *   N values), for tests. */
+typedef struct xls_poisson_s* xls_poisson_t;
+int xls_poisson_create(const int32_t* n, double h, int32_t bc, int32_t max_levels, xls_poisson_t* out);
+int xls_poisson_solve(xls_poisson_t p, const double* f, double* phi, double tol, int32_t max_iter,
+                      int32_t precond, double* info);
+int xls_poisson_vcycle(xls_poisson_t p, const double* r, double* z);
+void xls_poisson_destroy(xls_poisson_t p);
 
 #ifdef __cplusplus
 }

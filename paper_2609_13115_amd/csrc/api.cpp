@@ -630,6 +630,24 @@ void subdomain_tables(xls_subdomain_s* s, const xls_subdomain_desc_t* d, bool ke
   s->cfg32.block = 0;
   stencil_validate(s->n[0], s->n[1], s->n[2], s->bc == XLS_BC_PERIODIC, 8, s->nproj(), s->cfg64);
   stencil_validate(s->n[0], s->n[1], s->n[2], s->bc == XLS_BC_PERIODIC, 4, s->nproj(), s->cfg32);
+  for (int a = 0; a < 3; ++a) {
+    s->origin[a] = d->origin[a];
+    s->global_offset[a] = d->global_offset[a];
+    s->global_n[a] = d->global_n[a];
+  }
+  if (d->n_atoms > 0) {
+    s->atom_xyz.assign(d->atom_xyz, d->atom_xyz + 3 * static_cast<size_t>(d->n_atoms));
+    s->proj.assign(d->proj, d->proj + d->n_atoms);
+  }
+  s->atom_core.assign(d->n_atoms, 0);
+  for (int a = 0; a < d->n_atoms; ++a) {  // core_lo h <= X - origin < core_hi h on every axis
+    bool in = true;
+    for (int k = 0; k < 3; ++k) {
+      const double x = d->atom_xyz[3 * a + k] - d->origin[k];
+      in = in && d->core_lo[k] * d->h <= x && x < d->core_hi[k] * d->h;
+    }
+    s->atom_core[a] = in ? 1 : 0;
+  }
   // small per-state buffers (kept for the handle's lifetime)
   s->lam_dev = dalloc<double>(s->ns);
   s->resid_dev = dalloc<double>(s->ns);
@@ -1044,6 +1062,98 @@ int xls_subdomain_use_half(xls_subdomain_t s, const uint16_t* src) {
     check_device_range(src, static_cast<size_t>(s->nd) * s->ns * 2);
     s->half_src = src;
     s->have_ritz = false;
+    return XLS_OK;
+  });
+}
+
+int xls_subdomain_pdos(xls_subdomain_t s, double orb_width, double orb_rc, double* weights, int32_t nbins,
+                       const double* edges, double* pdos, uint8_t* in_core) {
+  return guarded([&]() -> int {
+    if (!s || !weights) fail(XLS_ERR_INVALID_ARG, "NULL argument");
+    if (!(orb_width > 0) || !(orb_rc > 0) || !std::isfinite(orb_width) || !std::isfinite(orb_rc))
+      fail(XLS_ERR_INVALID_ARG, "orbital width and cutoff must be finite and > 0");
+    if (nbins < 0 || (nbins > 0 && (!edges || !pdos))) fail(XLS_ERR_INVALID_ARG, "bad PDOS bins");
+    for (int b = 0; b < nbins; ++b)
+      if (!(edges[b] < edges[b + 1])) fail(XLS_ERR_INVALID_ARG, "PDOS edges must increase");
+    if (nbins > 0 && !s->have_ritz) fail(XLS_ERR_STATE, "PDOS bins need the Ritz values of a completed xls_chefsi_step");
+    require_resident(s);
+    materialize_half(s);
+    const int na = s->n_atoms, norb = 4 * na, ns = s->ns;
+    if (na == 0) return XLS_OK;  // no atomic orbitals: every output is empty
+    if (!s->orb_val || s->orb_width != orb_width || s->orb_rc != orb_rc) {
+      // atomic orbitals: the projector support rule and shape with the
+      // orbitals' width and cutoff, unit coefficients
+      xls_subdomain_desc_t d{};
+      for (int a = 0; a < 3; ++a) {
+        d.n[a] = s->n[a];
+        d.origin[a] = s->origin[a];
+        d.core_lo[a] = s->core_lo[a];
+        d.core_hi[a] = s->core_hi[a];
+        d.global_offset[a] = s->global_offset[a];
+        d.global_n[a] = s->global_n[a];
+      }
+      d.h = s->h;
+      d.bc = s->bc;
+      d.fd_n0 = kRadius;
+      d.n_atoms = na;
+      d.atom_xyz = s->atom_xyz.data();
+      std::vector<xls_projset_t> orb(na);
+      for (int a = 0; a < na; ++a) {
+        orb[a].rc = orb_rc;
+        orb[a].gauss_width = orb_width;
+        for (int l = 0; l < 4; ++l) orb[a].gamma[l] = 1.0;
+      }
+      d.proj = orb.data();
+      SetupTables t;
+      build_setup(d, t);
+      void* ps[] = {s->orb_off, s->orb_idx, s->orb_val, s->orb_gamma, s->orb_alpha, s->orb_P, s->orb_core};
+      XLS_HIP(hipStreamSynchronize(s->st));
+      for (void* p : ps) dfree(p);
+      s->orb_off = s->orb_idx = nullptr;
+      s->orb_val = s->orb_gamma = s->orb_alpha = s->orb_P = nullptr;
+      s->orb_core = nullptr;
+      s->orb_off = dupload(t.sup_off, s->st);
+      s->orb_idx = dupload(t.sup_idx, s->st);
+      s->orb_val = dupload(t.sup_val, s->st);
+      s->orb_gamma = dupload(t.gamma, s->st);
+      s->orb_core = dupload(s->atom_core, s->st);
+      s->orb_alpha = dalloc<double>(static_cast<size_t>(ns) * norb);
+      s->orb_P = dalloc<double>(static_cast<size_t>(ns) * norb);
+      s->orb_width = orb_width;
+      s->orb_rc = orb_rc;
+    }
+    OpTables<double> op = s->op64;
+    op.sup_off = s->orb_off;
+    op.sup_idx = s->orb_idx;
+    op.slot_val = s->orb_val;
+    op.gamma = s->orb_gamma;
+    if (nbins > static_cast<int>(s->orb_dcap)) {
+      XLS_HIP(hipStreamSynchronize(s->st));
+      dfree(s->orb_D);
+      dfree(s->orb_edges);
+      s->orb_D = nullptr;
+      s->orb_edges = nullptr;
+      s->orb_D = dalloc<double>(static_cast<size_t>(norb) * nbins);
+      s->orb_edges = dalloc<double>(static_cast<size_t>(nbins) + 1);
+      s->orb_dcap = nbins;
+    }
+    by_prec(s, [&](auto tag) {
+      using TS = decltype(tag);
+      launch_proj_forward<TS, double>(op, B<TS>(s, s->cur), s->ld, ns, s->orb_alpha, s->st);
+      return 0;
+    });
+    if (nbins > 0) {
+      XLS_HIP(hipMemcpyAsync(s->lam_dev, s->ritz.data(), ns * 8, hipMemcpyHostToDevice, s->st));
+      XLS_HIP(hipMemcpyAsync(s->orb_edges, edges, (static_cast<size_t>(nbins) + 1) * 8, hipMemcpyHostToDevice,
+                             s->st));
+    }
+    launch_pdos(s->orb_alpha, ns, norb, s->h, s->lam_dev, s->orb_edges, nbins, s->orb_core, s->orb_P, s->orb_D,
+                s->st);
+    XLS_HIP(hipMemcpyAsync(weights, s->orb_P, static_cast<size_t>(ns) * norb * 8, hipMemcpyDeviceToHost, s->st));
+    if (nbins > 0)
+      XLS_HIP(hipMemcpyAsync(pdos, s->orb_D, static_cast<size_t>(norb) * nbins * 8, hipMemcpyDeviceToHost, s->st));
+    XLS_HIP(hipStreamSynchronize(s->st));
+    if (in_core) std::memcpy(in_core, s->atom_core.data(), na);
     return XLS_OK;
   });
 }

@@ -37,7 +37,14 @@ using namespace xls;
 namespace {
 
 constexpr int kMaxDegree = 256;
-constexpr int kPoolStreams = 4;
+// Streams carrying the per-subdomain tails (H Psi_f, GEMMs, dense solve,
+// rotation, residual) of one batch iteration: the dense solve is latency
+// bound, so several run side by side.  XLS_BATCH_STREAMS overrides (1..32).
+int pool_streams() {
+  const char* e = std::getenv("XLS_BATCH_STREAMS");
+  const int v = e ? std::atoi(e) : 0;
+  return v >= 1 && v <= 32 ? v : 4;
+}
 constexpr int kGraphCache = 8;
 
 struct GroupHolder {
@@ -901,7 +908,7 @@ xls_batch_s* batch_new(int32_t n, const xls_subdomain_desc_t* descs, int64_t slo
     b->prec = descs[0].filter_prec;
     b->slots = slot_budget >= 0;
     XLS_HIP(hipStreamCreateWithFlags(&b->main, hipStreamNonBlocking));
-    const int np = std::min(n, kPoolStreams);
+    const int np = std::min(n, pool_streams());
     for (int p = 0; p < np; ++p) {
       hipStream_t st;
       XLS_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));

@@ -198,6 +198,34 @@ __global__ void dos_kernel(const double* __restrict__ lam, const double* __restr
   dos[b] = 2.0 * s;
 }
 
+// PDOS weights P[n][j] = alpha[n][j]^2 / h^3 from the overlaps alpha = h^3
+// sum phi_j psi_n, and the orbital-resolved PDOS D[j][b] = sum of P[n][j]
+// over the states n with lambda_n in [edges[b], edges[b+1]) (the last bin
+// also takes its right edge), zero for orbitals of atoms outside the core;
+// one thread per (orbital, bin), states in order.
+__global__ void pdos_weight_kernel(const double* __restrict__ alpha, int64_t n, double inv_h3,
+                                   double* __restrict__ P) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e < n) P[e] = alpha[e] * alpha[e] * inv_h3;
+}
+__global__ void pdos_hist_kernel(const double* __restrict__ P, const double* __restrict__ lam, int ns, int norb,
+                                 const double* __restrict__ edges, int nbins, const uint8_t* __restrict__ in_core,
+                                 double* __restrict__ D) {
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= static_cast<int64_t>(norb) * nbins) return;
+  const int j = static_cast<int>(t / nbins), b = static_cast<int>(t % nbins);
+  double s = 0.0;
+  if (in_core[j / 4]) {
+    const double e0 = edges[b], e1 = edges[b + 1];
+    const bool last = b == nbins - 1;
+    for (int n = 0; n < ns; ++n) {
+      const double x = lam[n];
+      if (x >= e0 && (x < e1 || (last && x == e1))) s += P[static_cast<int64_t>(n) * norb + j];
+    }
+  }
+  D[t] = s;
+}
+
 // Column c of a block (leading dimension ld) to and from IEEE binary16
 // storage with leading dimension nd: rounding to nearest even on the way
 // down, exact widening on the way up.  One thread per element, grid.y =
@@ -467,6 +495,21 @@ void launch_block_half(const TS* blk, int64_t ld, int64_t nd, int ncols, uint16_
 }
 template void launch_block_half<float>(const float*, int64_t, int64_t, int, uint16_t*, int, hipStream_t);
 template void launch_block_half<double>(const double*, int64_t, int64_t, int, uint16_t*, int, hipStream_t);
+
+void launch_pdos(const double* alpha, int ns, int norb, double h, const double* lam, const double* edges, int nbins,
+                 const uint8_t* in_core, double* P, double* D, hipStream_t st) {
+  const int64_t ne = static_cast<int64_t>(ns) * norb;
+  if (ne > 0) {
+    hipLaunchKernelGGL(pdos_weight_kernel, dim3(nblk(ne, 256)), dim3(256), 0, st, alpha, ne, 1.0 / (h * h * h), P);
+    XLS_LAUNCH_CHECK("pdos_weight_kernel");
+  }
+  const int64_t nt = static_cast<int64_t>(norb) * nbins;
+  if (nt > 0) {
+    hipLaunchKernelGGL(pdos_hist_kernel, dim3(nblk(nt, 256)), dim3(256), 0, st, P, lam, ns, norb, edges, nbins,
+                       in_core, D);
+    XLS_LAUNCH_CHECK("pdos_hist_kernel");
+  }
+}
 
 template <typename TS>
 void launch_philox_block(TS* blk, int64_t ld, int64_t nd, int ncols, uint64_t seed, hipStream_t st) {

@@ -74,6 +74,19 @@ struct xls_subdomain_s {
   bool x0_gen = false;
   // working set (blocks, projections, GEMM and dense workspaces) allocated
   bool resident = false;
+  // geometry kept for tables built later (atomic orbitals of the PDOS)
+  double origin[3] = {0, 0, 0};
+  int64_t global_offset[3] = {0, 0, 0}, global_n[3] = {1, 1, 1};
+  std::vector<double> atom_xyz;
+  std::vector<xls_projset_t> proj;
+  // PDOS orbital tables, built for (orb_width, orb_rc) on first use
+  double orb_width = 0.0, orb_rc = 0.0;
+  int32_t *orb_off = nullptr, *orb_idx = nullptr;
+  double *orb_val = nullptr, *orb_gamma = nullptr, *orb_alpha = nullptr, *orb_P = nullptr, *orb_D = nullptr,
+         *orb_edges = nullptr;
+  uint8_t* orb_core = nullptr;
+  std::vector<uint8_t> atom_core;  // atoms whose position lies in the core box
+  int orb_dcap = 0;
   // binary16 warm start not yet widened (xls_subdomain_use_half): the
   // caller's device buffer, N_d x ns with leading dimension N_d
   const uint16_t* half_src = nullptr;
@@ -104,7 +117,8 @@ struct xls_subdomain_s {
   ~xls_subdomain_s() {
     void* ps[] = {v64, v32, val64, val32, rev_pk, rev_aoff, rev_val64, rev_val32, sup_off, sup_idx, gamma, mask,
                   blk[0], blk[1], alpha, alpha64, partial, lam_dev, resid_dev, Mdev, Hsdev, Ydev, bwork,
-                  vsmall, rho_dev, cpart, gocc, lz, backup};
+                  vsmall, rho_dev, cpart, gocc, lz, backup, orb_off, orb_idx, orb_val, orb_gamma, orb_alpha,
+                  orb_P, orb_D, orb_edges, orb_core};
     for (void* p : ps) xls::dfree(p);
     if (own_gwork) xls::dfree(gwork);
     for (auto e : fev) (void)hipEventDestroy(e);

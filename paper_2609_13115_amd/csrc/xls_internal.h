@@ -239,6 +239,10 @@ void launch_density(const double* lam, double mu, double sigma, const uint8_t* m
 // (o2, o3), x = sqrt(-2 ln u1) cos(2 pi u2) (Box-Muller), rounded to TS.
 template <typename TS>
 void launch_philox_block(TS* blk, int64_t ld, int64_t nd, int ncols, uint64_t seed, hipStream_t st);
+// PDOS: P = alpha^2 / h^3 (ns x norb, row n), then D (norb x nbins) = sum of
+// P[n][j] over lam_n in bin b for orbitals of atoms with in_core set.
+void launch_pdos(const double* alpha, int ns, int norb, double h, const double* lam, const double* edges, int nbins,
+                 const uint8_t* in_core, double* P, double* D, hipStream_t st);
 // out[r + c ldo] = blk[rows[r] + c ld] for r < nrows, c < ncols
 template <typename TS>
 void launch_gather_rows(const TS* blk, int64_t ld, const int32_t* rows, int64_t nrows, int ncols, TS* out,

@@ -46,7 +46,8 @@ EXPORTED = [
     "xls_mlp_train", "xls_mlp_predict", "xls_set_graphs", "xls_subdomain_time_gemms",
     "xls_mlp_fit", "xls_mlp_train_rms", "xls_mlp_bounds", "xls_learned_safe_bounds",
     "xls_batch_create_slots", "xls_subdomain_tune_gemm", "xls_subdomain_use_half",
-    "xls_dense_geneig_noalloc",
+    "xls_dense_geneig_noalloc", "xls_subdomain_pdos",
+    "xls_poisson_create", "xls_poisson_solve", "xls_poisson_vcycle", "xls_poisson_destroy",
 ]
 
 
@@ -96,6 +97,7 @@ def lib() -> C.CDLL:
         L.xls_subdomain_destroy.restype = None
         L.xls_batch_destroy.restype = None
         L.xls_mlp_destroy.restype = None
+        L.xls_poisson_destroy.restype = None
         _lib = L
     return _lib
 
@@ -353,6 +355,23 @@ class Subdomain:
     def xls_subdomain_load_half(self, buf):
         """Block <- buf (device torch.float16, as written by xls_subdomain_store_half)."""
         _check(lib().xls_subdomain_load_half(self._h, C.c_void_p(int(buf.data_ptr()))))
+
+    def xls_subdomain_pdos(self, orb_width: float, orb_rc: float, edges=None, n_atoms: Optional[int] = None):
+        """(weights [ns, 4 n_atoms], pdos [4 n_atoms, nbins] or None, in_core [n_atoms])."""
+        if n_atoms is None:
+            sizes = np.zeros(2, dtype=np.int64)
+            _check(lib().xls_subdomain_get_projectors(self._h, sizes.ctypes.data_as(C.POINTER(C.c_int64)), None,
+                                                      None, None, None, None))
+            n_atoms = int(sizes[1])
+        w = np.zeros((self.ns, 4 * n_atoms))
+        e = None if edges is None else np.ascontiguousarray(edges, dtype=np.float64)
+        nb = 0 if e is None else len(e) - 1
+        d = np.zeros((4 * n_atoms, max(nb, 1)))
+        inc = np.zeros(max(n_atoms, 1), dtype=np.uint8)
+        _check(lib().xls_subdomain_pdos(self._h, C.c_double(orb_width), C.c_double(orb_rc), _dp(w), C.c_int32(nb),
+                                        _dp(e) if e is not None else None, _dp(d) if nb > 0 else None,
+                                        inc.ctypes.data_as(C.POINTER(C.c_uint8))))
+        return w, (d[:, :nb] if nb > 0 else None), inc[:n_atoms].astype(bool)
 
     def xls_subdomain_use_half(self, buf):
         """Next filter reads its start block from buf (device torch.float16) directly."""
@@ -639,3 +658,47 @@ def xls_learned_safe_bounds(lam_max, lam_cut, cut_margin: float = 0.0):
     _check(lib().xls_learned_safe_bounds(C.c_int32(lmx.size), _dp(lmx), _dp(lct), C.c_double(cut_margin),
                                          _dp(lm), _dp(lc)))
     return lm, lc
+
+
+class Poisson:
+    """Owner of one xls_poisson_t: -(1/(4 pi)) Lap phi = f by multigrid-preconditioned CG."""
+
+    def __init__(self, n, h: float, bc: int, max_levels: int = 0):
+        self.n = tuple(int(v) for v in n)
+        self.nd = int(np.prod(self.n))
+        nn = (C.c_int32 * 3)(*self.n)
+        hh = C.c_void_p()
+        _check(lib().xls_poisson_create(nn, C.c_double(h), C.c_int32(bc), C.c_int32(max_levels), C.byref(hh)))
+        self._h = hh
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().xls_poisson_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def solve(self, f, tol: float = 1e-10, max_iter: int = 500, precondition: bool = True):
+        """(phi, info) with info = (iterations, relative residual, levels, ms)."""
+        ff = np.ascontiguousarray(f, dtype=np.float64).reshape(-1)
+        phi = np.zeros(self.nd)
+        info = np.zeros(4)
+        _check(lib().xls_poisson_solve(self._h, _dp(ff), _dp(phi), C.c_double(tol), C.c_int32(max_iter),
+                                       C.c_int32(1 if precondition else 0), _dp(info)))
+        return phi, (int(info[0]), float(info[1]), int(info[2]), float(info[3]))
+
+    def vcycle(self, r):
+        rr = np.ascontiguousarray(r, dtype=np.float64).reshape(-1)
+        z = np.zeros(self.nd)
+        _check(lib().xls_poisson_vcycle(self._h, _dp(rr), _dp(z)))
+        return z

@@ -4,11 +4,11 @@
 //
 // H y = -1/2 Lap y + V y + V_nl y with the 12th-order (n0 = 6) FD Laplacian:
 // 36 neighbour terms (+-1..6 along x, y, z) plus the centre.  One workgroup
-// owns one column (vector), a band of ty full-width x-rows and a z-chunk.  It
-// streams along z: the 13 values of its points' z-column live in a register
-// queue, the current xy plane (with a 6-point halo) is staged in a
-// double-buffered LDS tile, so each input plane is read from HBM once per
-// workgroup.  The nonlocal term is a gather over the reverse CSR of the point
+// owns NV columns (vectors; two by default), a band of ty full-width x-rows
+// and a z-chunk.  It streams along z: the 13 values of its points' z-column
+// live in a register queue, the current xy plane (with a 6-point halo) is
+// staged in a double-buffered LDS tile, so each input plane is read from HBM
+// once per workgroup.  The nonlocal term is a gather over the reverse CSR of the point
 // (no atomics); the projection coefficients alpha of the same input come from
 // proj_forward.  The Chebyshev recurrence AXPY is fused into the store
 // (Y_{k+1} = a (H Y_k - c Y_k) - b Y_{k-1}, in place over Y_{k-1}), and the
@@ -219,10 +219,20 @@ __device__ __forceinline__ void stencil_tile(const HArgs<TS, TC>& A, uint32_t lo
   const int plane = dumpi + 1;
   TC* alds = lds + 2 * NV * plane;     // the columns' projection coefficients
 
+  // Logical order: z chunk, then column group, then y band.  The xcd remap
+  // hands each XCD a contiguous run of logical tiles, so when the grid is cut
+  // into z chunks (a tuning option; one chunk by default) an XCD sweeps one
+  // chunk of many columns and its L2 holds only that chunk's V, reverse-CSR
+  // words and projector payload; the bands of one column stay neighbours, so
+  // their shared y-halo rows meet in the same L2.
   const int tiles = A.nyt * A.nzt;
-  const int col0 = static_cast<int>(logical / tiles) * NV;
-  const int t = static_cast<int>(logical % tiles);
-  const int yt = t % A.nyt, zt = t / A.nyt;
+  const uint32_t ncg = static_cast<uint32_t>((A.ncols + NV - 1) / NV);
+  const uint32_t per_chunk = ncg * static_cast<uint32_t>(A.nyt);
+  const int zt = static_cast<int>(logical / per_chunk);
+  const uint32_t rem = logical % per_chunk;
+  const int col0 = static_cast<int>(rem / static_cast<uint32_t>(A.nyt)) * NV;
+  const int yt = static_cast<int>(rem % static_cast<uint32_t>(A.nyt));
+  const int t = yt + A.nyt * zt;  // tile index within a column (residual partials)
   const int y0 = yt * A.ty;
   const int tyv = min(A.ty, ny - y0);
   const int z0 = zt * A.tz;
@@ -330,6 +340,12 @@ __device__ __forceinline__ void stencil_tile(const HArgs<TS, TC>& A, uint32_t lo
     if (!A.periodic) return -1;
     return wrapi(zz, nz);
   };
+  // Every prefetch is issued unconditionally: a plane past the chunk is
+  // clamped into the grid (valid memory, value never used) and a zero plane
+  // is read through an out-of-range lane offset.  A load under a branch ends
+  // in a register merge whose copy waits for the load at once, which drains
+  // every prefetch in flight.
+  auto clampz = [&](int zz) { return min(zz, nz - 1); };
   // one element of the y stream (plane offset in elements), and of yprev
   auto ldy = [&](int v, int voff, int splane) -> TC {
     if constexpr ((HF & 1) != 0)
@@ -343,7 +359,7 @@ __device__ __forceinline__ void stencil_tile(const HArgs<TS, TC>& A, uint32_t lo
     else
       return static_cast<TC>(bload_p<kPrevAux>(rp[v], opv[i], splane * ES, (TS*)nullptr));
   };
-  auto ldq = [&](int i, int v, int zq) -> TC { return zq < 0 ? TC(0) : ldy(v, oy[i], zq * pp); };
+  auto ldq = [&](int i, int v, int zq) -> TC { return ldy(v, zq < 0 ? kOOB : oy[i], max(zq, 0) * pp); };
 
   // register queue: q[i][v][slot] holds plane z - R + ((slot - ph) mod Q)
   // while plane z is computed at phase ph = (z - z0) mod Q, so the queue
@@ -375,7 +391,7 @@ __device__ __forceinline__ void stencil_tile(const HArgs<TS, TC>& A, uint32_t lo
       const int e0 = rp1[i] & EMASK;  // points without projectors name the zero sentinel
       ev[i] = load_ent<TC>(re, e0 * 4 * EC);
       ea[i] = bload<int>(ra, e0 * 4, 0);
-      if (z + 1 < z1) rp2[i] = bload<int>(rk, o4[i], (so + pp) * 4);  // else unused
+      rp2[i] = bload<int>(rk, o4[i], clampz(z + 1) * pp * 4);  // unused past the chunk
     }
   };
   {
@@ -388,8 +404,7 @@ __device__ __forceinline__ void stencil_tile(const HArgs<TS, TC>& A, uint32_t lo
         fr[i][v] = ldq(i, v, zq1);
         if (MODE == kFilter) {
           yp1[i][v] = ldp(i, v, z0 * pp);
-          yp2[i][v] = TC(0);
-          if (z0 + 1 < z1) yp2[i][v] = ldp(i, v, (z0 + 1) * pp);
+          yp2[i][v] = ldp(i, v, clampz(z0 + 1) * pp);
         }
       }
       rp2[i] = bload<int>(rk, o4[i], z0 * pp * 4);
@@ -418,12 +433,10 @@ __device__ __forceinline__ void stencil_tile(const HArgs<TS, TC>& A, uint32_t lo
       for (int j = 0; j < HMAX; ++j) buf[2 * v * plane + hl[j]] = hv[v][j];
     }
     // (b) next plane's halo
-    if (z + 1 < z1) {
 #pragma unroll
-      for (int v = 0; v < NV; ++v)
+    for (int v = 0; v < NV; ++v)
 #pragma unroll
-        for (int j = 0; j < HMAX; ++j) hv[v][j] = ldy(v, hoff[j], (z + 1) * pp);
-    }
+      for (int j = 0; j < HMAX; ++j) hv[v][j] = ldy(v, hoff[j], clampz(z + 1) * pp);
     lds_barrier();
     // (c) plane z
     const int so = z * pp * ES;
@@ -489,16 +502,16 @@ __device__ __forceinline__ void stencil_tile(const HArgs<TS, TC>& A, uint32_t lo
         q[i][v][QS(0)] = fr[i][v];
         if (MODE == kFilter) yp1[i][v] = yp2[i][v];
       }
-    if (z + 1 < z1) {
+    {
       const int zq = qplane(z + 2 + R);
 #pragma unroll
       for (int i = 0; i < P; ++i)
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
           fr[i][v] = ldq(i, v, zq);
-          if (MODE == kFilter && z + 2 < z1) yp2[i][v] = ldp(i, v, (z + 2) * pp);
+          if (MODE == kFilter) yp2[i][v] = ldp(i, v, clampz(z + 2) * pp);
         }
-      load_rest(z + 1);
+      load_rest(clampz(z + 1));
     }
   };
 
@@ -565,8 +578,12 @@ __global__ __launch_bounds__(NT) void hstencil_group_kernel(const HArgs<TS, TC>*
 // wavefront per (atom, kProjCols columns): lanes stride over the atom's
 // support and load each point's index and projector values once for all its
 // columns; per column, FP64 partial sums per lane then a fixed xor-shuffle
-// reduction (deterministic).
+// reduction (deterministic).  Four columns per wave: eight were measured no
+// faster (the gathered column values, not the index and payload reads, set
+// its time).
 constexpr int kProjCols = 4;
+constexpr int kProjSums = 4 * kProjCols;  // one sum per (column, projector)
+static_assert(kProjSums == 16, "the reduction below halves 16 sums over 4 lane bits");
 template <typename TS, typename TC>
 __device__ __forceinline__ void proj_forward_wave(const TS* __restrict__ y, int64_t ld, int ncols, int cbase,
                                                   const int32_t* __restrict__ sup_off,
@@ -632,14 +649,14 @@ __device__ __forceinline__ void proj_forward_wave(const TS* __restrict__ y, int6
   // bit-identical to it, in 32 shuffles instead of 96); offsets 2 and 1
   // finish, and lane 4 v holds sum v = 4 c + l.  Both halves are shuffled
   // and the kept sum selected, so no register array is indexed at run time.
-  double r[kProjCols * 4];
+  double r[kProjSums];
 #pragma unroll
   for (int c = 0; c < kProjCols; ++c)
 #pragma unroll
     for (int l = 0; l < 4; ++l) r[4 * c + l] = acc[c][l];
 #pragma unroll
   for (int lev = 0; lev < 4; ++lev) {
-    const int off = 32 >> lev, half = 8 >> lev;
+    const int off = 32 >> lev, half = (kProjSums / 2) >> lev;
     const bool up = (lane & off) != 0;
 #pragma unroll
     for (int j = 0; j < half; ++j) {
@@ -738,8 +755,15 @@ inline TileChoice choose_tiles(int nx, int ny, int nz, int elem, int nproj, int6
   tc.nzt = (nz + tc.tz - 1) / tc.tz;
   tc.P = (nx * ty + tc.block - 1) / tc.block;
   tc.ws = (nx + 2 * R <= 80) ? 80 : 128;
-  tc.nv = cfg.nv > 0 ? cfg.nv : 1;
-  tc.smem = static_cast<size_t>(elem) * tc.nv * (2 * (static_cast<size_t>(tc.ws) * (ty + 2 * R) + 1) + nproj);
+  auto smem_of = [&](int nv) {
+    return static_cast<size_t>(elem) * nv * (2 * (static_cast<size_t>(tc.ws) * (ty + 2 * R) + 1) + nproj);
+  };
+  // Default: two vectors per tile, so V, the reverse-CSR words and the
+  // projector payload are read once for both (these tables outweigh a
+  // column's own traffic; -10 % launch time on the 64^3 box in both
+  // precisions); one when two would not fit the LDS.
+  tc.nv = cfg.nv > 0 ? cfg.nv : (smem_of(2) <= 160 * 1024 ? 2 : 1);
+  tc.smem = smem_of(tc.nv);
   return tc;
 }
 
@@ -1019,7 +1043,8 @@ void group_dispatch(int P, int ws, int nv, F&& f) {
     else by_nv(pc, integral_constant<int, 128>{});
   };
   if (P == 1) by_ws(integral_constant<int, 1>{});
-  else by_ws(integral_constant<int, 2>{});
+  else if (P == 2) by_ws(integral_constant<int, 2>{});
+  else fail(XLS_ERR_INVALID_ARG, "grouped stencil launches take at most 2 points per thread");
 }
 
 template <typename TS>

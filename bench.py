@@ -12,18 +12,23 @@ grid-pt*vec*deg) against 8 TB/s from HIP events around every filter launch,
 and against a device-to-device copy measured in the same run.
 
 batch: the 256-subdomain uneven draw at full size, solved to a gated
-residual of 1e-4 (at most 30 iterations) with slot residency, once in FP64
-with Lanczos bounds and once mixed with learned bounds (model trained first
-on method-made labels of smaller boxes of the same recipe); subdomains/s,
-converged counts, and the largest |Ritz difference| over the gated states of
-subdomains both forms converged.  learned_gain: the first 64 subdomains,
-mixed with Lanczos bounds against mixed with learned bounds (one
-precision).  gemm_large: the 96^3, Ns = 2,400 GEMM rates and their errors
-against FP64.  cpu_baseline times the FP64 oracle's filter on a column
-sample on the host.
+residual of 5e-5 (at most 45 iterations) with slot residency, once in FP64
+with Lanczos bounds and the draw's degrees, and once mixed with learned
+bounds and degrees (model trained first on method-made labels of smaller
+boxes of the same recipe); subdomains/s, converged counts, and the
+|Ritz difference| over the gated states of subdomains both forms converged
+(largest, 99th percentile, count above 1e-6 Ha).  Two Ritz values converged
+to a residual r differ by up to about r^2 / gap each, so the gate on their
+difference is measured at 5e-5 rather than the 1e-4 convergence test of
+the unit tests.  learned_gain: the first 32 subdomains, mixed with Lanczos
+bounds against mixed with learned bounds (one precision).  gemm_large: the
+96^3, Ns = 2,400 GEMM rates and their errors against FP64.  cpu_baseline
+times the FP64 oracle's filter on a column sample on the host.  The
+optional learned_gain leg is skipped, and the line says so, when the run
+has used more than --budget-s seconds before it.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--batch 256] [--gain 64]
-                    [--no-gemm-large] [--headline-only] [--no-cpu]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--batch 256] [--gain 32]
+                    [--no-gemm-large] [--headline-only] [--no-cpu] [--budget-s 720]
 """
 from __future__ import annotations
 
@@ -43,6 +48,8 @@ MFMA_PEAK_TFLOPS = {"bf16x3": 2500.0, "fp32": 157.3, "fp64": 78.6}  # dense, per
 METRIC = "filtered grid-pt\u00b7vec\u00b7deg/s + subdomains/s: FP64 vs mixed+learned, dE<=1e-6 Ha"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "filter_traffic.json")
 STENCIL_SOURCES = ["stencil_impl.h", "stencil_f32.hip", "stencil_f64.hip", "stencil_mix.hip"]
+BATCH_TOL = 5e-5        # gated residual of the batch legs
+BATCH_MAX_ITER = 45
 
 
 def stencil_source_hash() -> str:
@@ -270,7 +277,7 @@ def gemm_large(reps: int = 3):
     return out
 
 
-def train_learned(n_train: int = 64, max_iter: int = 16):
+def train_learned(n_train: int = 64, max_iter: int = 16, tol: float = BATCH_TOL):
     """The learned-bounds model for the batch workload: labels from the method
     (batch engine, FP32 filter and GEMMs) on n_train smaller boxes of the same
     recipe (core 8-40 atoms, a different draw of the crystal), then training
@@ -279,7 +286,7 @@ def train_learned(n_train: int = 64, max_iter: int = 16):
 
     t0 = time.perf_counter()
     _, train, _ = workloads.batch_subdomains(count=n_train, key_cfg=6, nmin=20, nmax=60, core_atoms=(8, 40))
-    lab = learned.label_subdomains(train, max_iter=max_iter)
+    lab = learned.label_subdomains(train, max_iter=max_iter, tol=tol)
     t1 = time.perf_counter()
     model, losses = learned.train_model(lab.features, lab.targets, epochs=300)
     t2 = time.perf_counter()
@@ -314,8 +321,8 @@ def copy_rate(mib: int = 1024, reps: int = 5):
     return 2.0 * (mib << 20) / (t * 1e-3) / 1e9
 
 
-def run_cfg3(count: int, forms, max_iter: int = 30, tol: float = 1e-4, model=None, budget: int = 0,
-             tune_cache: str = None, occupation: bool = False):
+def run_cfg3(count: int, forms, max_iter: int = BATCH_MAX_ITER, tol: float = BATCH_TOL, model=None,
+             budget: int = 0, tune_cache: str = None, occupation: bool = False):
     """The uneven batch workload at full size: `count` subdomains of the
     256-subdomain draw (start blocks drawn on the device), run with slot
     residency (working sets admitted largest-first within the device memory
@@ -384,6 +391,8 @@ def run_cfg3(count: int, forms, max_iter: int = 30, tol: float = 1e-4, model=Non
             rf, cf = ref
             d = [float(np.max(np.abs(a[:g] - b_[:g]))) for a, b_, g, u, v in zip(rm, rf, gates, cm, cf) if u and v]
             out[form]["max_ritz_diff_ha_both_converged"] = max(d) if d else None
+            out[form]["p99_ritz_diff_ha"] = float(np.percentile(d, 99)) if d else None
+            out[form]["subdomains_ritz_diff_over_1e-6"] = int(sum(v > 1e-6 for v in d))
             out[form]["both_converged"] = len(d)
             out[form]["speedup_vs_fp64"] = out["fp64"]["seconds"] / out[form]["seconds"]
             out[form]["gate_met"] = bool(d) and max(d) <= 1e-6 and out[form]["converged"] >= out["fp64"]["converged"]
@@ -432,6 +441,9 @@ def cpu_baseline(sd, degree: int, ncols: int):
                       f"{len(os.sched_getaffinity(0))} cores)"}
 
 
+T_START = time.perf_counter()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -445,10 +457,12 @@ def main():
                     help="first run a device-to-device copy of this many MiB (counter calibration)")
     ap.add_argument("--batch", type=int, default=256,
                     help="subdomains of the uneven batch draw to solve, FP64 and mixed + learned (0: skip)")
-    ap.add_argument("--gain", type=int, default=64,
+    ap.add_argument("--gain", type=int, default=32,
                     help="subdomains for the learned gain at one precision, mixed + Lanczos vs mixed + learned")
     ap.add_argument("--no-gemm-large", action="store_true", help="skip the 96^3, Ns = 2400 GEMM table")
     ap.add_argument("--headline-only", action="store_true", help="only the 64^3 steps (profiling runs)")
+    ap.add_argument("--budget-s", type=float, default=720.0,
+                    help="skip the optional learned_gain leg once this many seconds have passed")
     ap.add_argument("--write-traffic", nargs=3, metavar=("FORM", "FETCH_CSV", "WRITE_CSV"),
                     help="record filter HBM traffic from two rocprofv3 --pmc passes and exit (no GPU)")
     a = ap.parse_args()
@@ -512,7 +526,21 @@ def main():
                   "stage_ms_per_step": m["stage_ms_per_step"], "gemm": m["gemm"],
                   "half_storage": m["half_storage"]},
     }
+    if not a.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(sd, a.degree, a.cpu_cols)
     if not a.headline_only:
+        skipped = []
+
+        def over_budget(leg):
+            if time.perf_counter() - T_START > a.budget_s:
+                skipped.append(leg)
+                print(f"[bench] {leg} skipped: {time.perf_counter() - T_START:.0f} s used of the "
+                      f"{a.budget_s:.0f} s budget", file=sys.stderr, flush=True)
+                return True
+            return False
+
+        if not a.no_gemm_large:
+            out["gemm_large"] = gemm_large()
         tune = os.path.join("/tmp", f"xls_tune_{os.getpid()}.json")
         model, info = train_learned()
         if a.batch > 0:
@@ -523,13 +551,13 @@ def main():
             out["subdomains_per_s"] = {"fp64": b["fp64"]["subdomains_per_s"],
                                        "mixed_learned": b["mixed_learned"]["subdomains_per_s"]}
             out["max_ritz_diff_ha"] = b["mixed_learned"].get("max_ritz_diff_ha_both_converged")
-        if a.gain > 0:
+            out["gate_met"] = b["mixed_learned"].get("gate_met")
+        if a.gain > 0 and not over_budget("learned_gain"):
             out["learned_gain"] = run_cfg3(a.gain, ["mixed", "mixed_learned"], model=model, tune_cache=tune)
         model.close()
-        if not a.no_gemm_large:
-            out["gemm_large"] = gemm_large()
-    if not a.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(sd, a.degree, a.cpu_cols)
+        if skipped:
+            out["skipped_legs"] = skipped
+    out["wall_s"] = time.perf_counter() - T_START
     print(json.dumps(out), flush=True)
 
 

@@ -142,8 +142,16 @@ int xls_subdomain_create(const xls_subdomain_desc_t* desc, xls_subdomain_t* out)
  * M_s = Psi_f^T Psi_f and H_s = (Psi_f^T H Psi_f symmetrised); Cholesky
  * M_s = R^T R; C = R^-T H_s R^-1; C = Z Lambda Z^T; Psi = Psi_f R^-1 Z;
  * residuals r_n = ||H psi_n - lambda_n psi_n||_2 in FP64 arithmetic.
- * Outputs: ritz[ns] ascending, resid[ns], *iters_done.  The handle keeps the
- * rotated block and Ritz values for the next call and for density.
+ * Outputs: ritz[ns], resid[ns], *iters_done.  With an FP64 block and FP64
+ * GEMMs ritz holds the eigenvalues lambda_n (ascending).  Otherwise (FP32
+ * block, or FP32 / split-BF16 GEMMs) it holds the FP64 Rayleigh quotients
+ * psi_n^T H psi_n / psi_n^T psi_n of the returned columns, taken in the same
+ * FP64 sweep as the residuals.  They are second-order accurate in the
+ * vectors' error and carry no GEMM rounding, and they are given in the order
+ * of the lambda_n (a near-degenerate pair may differ from ascending in the
+ * last bits).  resid is measured against lambda_n, and the next iteration's
+ * bounds come from the lambda_n.  The handle keeps the rotated block and these
+ * Ritz values for the next call and for density.
  * Errors: INVALID_ARG, NOT_SPD (the block is left as it was before the
  * failing iteration's rotation), EIG_NOCONV, DEVICE. */
 int xls_chefsi_step(xls_subdomain_t s, const xls_chefsi_params_t* p,
@@ -422,7 +430,9 @@ int xls_subdomain_features(xls_subdomain_t s, double* f);
  *   fallback_degree in a second batched pass (xls_subdomain_counters of the
  *   subdomain's handle reports the fallback; iters counts both runs).  Outputs are
  *   concatenated in subdomain order: ritz_concat and resid_concat hold
- *   sum(ns_i) values; iters[n] and status[n] may be NULL.  status[i] is
+ *   sum(ns_i) values, the Ritz values as xls_chefsi_step reports them (FP64
+ *   Rayleigh quotients unless block and GEMMs are FP64); iters[n] and
+ *   status[n] may be NULL.  status[i] is
  *   XLS_OK or XLS_ERR_NOT_SPD (that subdomain's block is then undefined); with
  *   status NULL such a failure is returned as the call's status.  use_graph:
  *   1 replays captured iterations, 0 launches eagerly (same results).

@@ -192,15 +192,16 @@ void rotate_block(xls_subdomain_s* s, int gprec, const double* Ydev) {
   s->cur = 1 - s->cur;
 }
 
-// FP64 residual norms of the current block against lam (device).
+// FP64 residual norms of the current block against lam (device), and the
+// columns' FP64 Rayleigh quotients when rq_dev is not null.
 template <typename TS>
-void residual_block(xls_subdomain_s* s, const double* lam_dev, double* resid_dev) {
+void residual_block(xls_subdomain_s* s, const double* lam_dev, double* resid_dev, double* rq_dev) {
   s->happly += s->ns;
   TS* Bc = B<TS>(s, s->cur);
   launch_proj_forward<TS, double>(s->op64, Bc, s->ld, s->ns, s->alpha64, s->st);
   StencilLaunch cfg = s->cfg64;
   launch_stencil<TS, double>(kResid, s->op64, Bc, s->ld, s->ns, s->alpha64, nullptr, nullptr, 1.0, 0.0, 0.0,
-                             lam_dev, s->partial, resid_dev, s->st, cfg);
+                             lam_dev, s->partial, resid_dev, s->st, cfg, rq_dev);
 }
 
 int lanczos_steps(const xls_subdomain_s* s, int k) {
@@ -289,7 +290,7 @@ void lanczos_run(xls_subdomain_s* s, int k) {
 #define XLS_INST_STAGES(TS)                                                          \
   template void apply_H<TS>(xls_subdomain_s*, const TS*, TS*, int, TS*);             \
   template void rotate_block<TS>(xls_subdomain_s*, int, const double*);              \
-  template void residual_block<TS>(xls_subdomain_s*, const double*, double*);        \
+  template void residual_block<TS>(xls_subdomain_s*, const double*, double*, double*);        \
   template void lanczos_run<TS>(xls_subdomain_s*, int);                              \
   template void filter_block<TS>(xls_subdomain_s*, int, double, double, double);
 XLS_INST_STAGES(float)
@@ -369,6 +370,13 @@ void chefsi_loop(xls_subdomain_s* s, const xls_chefsi_params_t* p, int gprec, in
                  double lc, double lmax, std::vector<double>& hl, std::vector<double>& hr, int& total) {
   const int ns = s->ns;
   double prev_resid = HUGE_VAL;
+  // Reported Ritz values: the projected eigenvalues when the block and the
+  // projection are FP64; otherwise the FP64 Rayleigh quotients of the rotated
+  // columns from the residual sweep (second order in the vectors' error, so
+  // free of the GEMMs' rounding).  The next filter's bounds always come from
+  // the projected eigenvalues.
+  const bool use_rq = !std::is_same<TS, double>::value || gprec != XLS_PREC_FP64;
+  std::vector<double> hq(ns);
   for (int it = 0; it < p->max_iter;) {
     StageTimer tm(profiling_on(), s->st);
     tm.mark();
@@ -391,10 +399,11 @@ void chefsi_loop(xls_subdomain_s* s, const xls_chefsi_params_t* p, int gprec, in
     tm.mark();
     rotate_block<TS>(s, pprec, s->Ydev);
     tm.mark();
-    residual_block<TS>(s, s->lam_dev, s->resid_dev);
+    residual_block<TS>(s, s->lam_dev, s->resid_dev, use_rq ? s->rq_dev : nullptr);
     tm.mark();
     int32_t spd_flag = 0;
     XLS_HIP(hipMemcpyAsync(hl.data(), s->lam_dev, ns * 8, hipMemcpyDeviceToHost, s->st));
+    if (use_rq) XLS_HIP(hipMemcpyAsync(hq.data(), s->rq_dev, ns * 8, hipMemcpyDeviceToHost, s->st));
     XLS_HIP(hipMemcpyAsync(hr.data(), s->resid_dev, ns * 8, hipMemcpyDeviceToHost, s->st));
     XLS_HIP(hipMemcpyAsync(&spd_flag, s->dw.flag, 4, hipMemcpyDeviceToHost, s->st));
     XLS_HIP(hipStreamSynchronize(s->st));
@@ -408,7 +417,7 @@ void chefsi_loop(xls_subdomain_s* s, const xls_chefsi_params_t* p, int gprec, in
     }
     ++it;
     ++total;
-    s->ritz = hl;
+    s->ritz = use_rq ? hq : hl;
     s->have_ritz = true;
     a0 = hl[0];
     lc = hl[ns - 1];
@@ -494,7 +503,7 @@ int chefsi_impl(xls_subdomain_s* s, const xls_chefsi_params_t* p, double* ritz, 
     s->last_fallback = 1;
   }
   s->last_iters = it;
-  std::memcpy(ritz, hl.data(), ns * 8);
+  std::memcpy(ritz, s->ritz.data(), ns * 8);
   std::memcpy(resid, hr.data(), ns * 8);
   if (iters_done) *iters_done = it;
   return XLS_OK;
@@ -651,6 +660,7 @@ void subdomain_tables(xls_subdomain_s* s, const xls_subdomain_desc_t* d, bool ke
   // small per-state buffers (kept for the handle's lifetime)
   s->lam_dev = dalloc<double>(s->ns);
   s->resid_dev = dalloc<double>(s->ns);
+  s->rq_dev = dalloc<double>(s->ns);
   s->vsmall = dalloc<double>(1024);
   s->cpart = dalloc<double>(static_cast<size_t>(s->ns) * 64);
   s->gocc = dalloc<double>(s->ns);

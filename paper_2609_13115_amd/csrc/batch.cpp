@@ -195,7 +195,7 @@ void tail_stages(xls_subdomain_s* s, const SubState& ss, int cur_f, double* coef
   gemm_nn<TS>(ss.pprec, Bc, s->ld, s->Ydev, ns, static_cast<int>(s->nd), ns, ns, W, s->ld, s->bwork, s->st, s->gplan);
   launch_proj_forward<TS, double>(s->op64, W, s->ld, ns, s->alpha64, s->st);
   launch_stencil<TS, double>(kResid, s->op64, W, s->ld, ns, s->alpha64, nullptr, nullptr, 1.0, 0.0, 0.0,
-                             s->lam_dev, s->partial, s->resid_dev, s->st, s->cfg64);
+                             s->lam_dev, s->partial, s->resid_dev, s->st, s->cfg64, s->rq_dev);
   launch_filter_coef(s->lam_dev, ns, 0.0, 0.0, ss.lmax, ss.degree, coef, bad, s->st);
 }
 
@@ -430,10 +430,18 @@ std::vector<int> iterate_once(xls_batch_s* b, bool use_graph, std::vector<std::v
   if (act.empty()) return ended;
   b->max_active = std::max(b->max_active, static_cast<int>(act.size()));
   std::vector<int32_t> hflag(b->n), hspd(b->n);
+  std::vector<std::vector<double>> hq(b->n);
+  // reported Ritz values as in a single run: FP64 Rayleigh quotients unless
+  // the block and the projection are FP64
+  auto use_rq = [&](int i) { return !std::is_same<TS, double>::value || b->st[i].gprec != XLS_PREC_FP64; };
   run_iteration<TS>(b, act, use_graph);
   for (int i : act) {
     xls_subdomain_s* s = b->subs[i];
     XLS_HIP(hipMemcpyAsync(hl[i].data(), s->lam_dev, s->ns * 8, hipMemcpyDeviceToHost, b->main));
+    if (use_rq(i)) {
+      hq[i].resize(s->ns);
+      XLS_HIP(hipMemcpyAsync(hq[i].data(), s->rq_dev, s->ns * 8, hipMemcpyDeviceToHost, b->main));
+    }
     XLS_HIP(hipMemcpyAsync(hr[i].data(), s->resid_dev, s->ns * 8, hipMemcpyDeviceToHost, b->main));
     XLS_HIP(hipMemcpyAsync(&hspd[i], s->dw.flag, 4, hipMemcpyDeviceToHost, b->main));
     XLS_HIP(hipMemcpyAsync(&hflag[i], b->flags + i, 4, hipMemcpyDeviceToHost, b->main));
@@ -452,7 +460,7 @@ std::vector<int> iterate_once(xls_batch_s* b, bool use_graph, std::vector<std::v
     ++ss.total_iters;
     s->last_iters = ss.total_iters;
     s->happly += static_cast<int64_t>(ss.degree + 1) * s->ns;  // filter + residual (H Psi_f counted by apply_H)
-    s->ritz = hl[i];
+    s->ritz = use_rq(i) ? hq[i] : hl[i];
     s->have_ritz = true;
     if (hspd[i]) {
       ss.status = XLS_ERR_NOT_SPD;

@@ -27,6 +27,7 @@ constexpr int Q = 2 * R + 1;  // register-queue depth
 constexpr int HMAX = 4;       // halo cells per thread per plane (host checks)
 constexpr int EMAX = 1;       // reverse-CSR entries per point prefetched (more: slow path)
 constexpr int EMASK = (1 << 27) - 1;
+constexpr int kResidSums = 3;  // residual sweep partial planes: ||H y - lam y||^2, y^T H y, y^T y
 
 template <typename TS, typename TC>
 struct HArgs {
@@ -416,7 +417,9 @@ __device__ __forceinline__ void stencil_tile(const HArgs<TS, TC>& A, uint32_t lo
 #pragma unroll
     for (int j = 0; j < HMAX; ++j) hv[v][j] = ldy(v, hoff[j], z0 * pp);
 
-  double racc = 0.0;
+  // residual sweep: ||H y - lam y||^2, y^T H y and y^T y of the column (the
+  // last two give its FP64 Rayleigh quotient)
+  double racc = 0.0, hacc = 0.0, nacc = 0.0;
   const double lamc = (MODE == kResid) ? A.lam[col0] : 0.0;
 
   // one plane at compile-time phase PH
@@ -488,8 +491,11 @@ __device__ __forceinline__ void stencil_tile(const HArgs<TS, TC>& A, uint32_t lo
           const TC r = ca * (hy[v] - cc * q[i][v][QS(R)]) - cb * yp1[i][v];
           bstore_p<kOutAux>(static_cast<TS>(r), ro[v], os[i], so);
         } else if (vo[i] >= 0) {
-          const double d = static_cast<double>(hy[v]) - lamc * static_cast<double>(q[i][v][QS(R)]);
+          const double hv = static_cast<double>(hy[v]), yv = static_cast<double>(q[i][v][QS(R)]);
+          const double d = hv - lamc * yv;
           racc += d * d;
+          hacc += yv * hv;
+          nacc += yv * yv;
         }
       }
     }
@@ -532,17 +538,23 @@ __device__ __forceinline__ void stencil_tile(const HArgs<TS, TC>& A, uint32_t lo
     if (z + 12 < z1) step(integral_constant<int, 12>{}, z + 12); else break;
   }
   if (MODE == kResid) {
-    // deterministic block reduction: fixed shuffle tree, then fixed LDS order
+    // deterministic block reduction of the three sums: fixed shuffle tree,
+    // then fixed LDS order; sum q of the tile goes to partial plane q
     __syncthreads();
     double* red = reinterpret_cast<double*>(smem_raw);
-    for (int o2 = 32; o2 > 0; o2 >>= 1) racc += __shfl_xor(racc, o2, 64);
+    double acc3[kResidSums] = {racc, hacc, nacc};
     const int wid = tid >> 6, lane = tid & 63;
-    if (lane == 0) red[wid] = racc;
+#pragma unroll
+    for (int qq = 0; qq < kResidSums; ++qq) {
+      for (int o2 = 32; o2 > 0; o2 >>= 1) acc3[qq] += __shfl_xor(acc3[qq], o2, 64);
+      if (lane == 0) red[qq * (NT / 64) + wid] = acc3[qq];
+    }
     __syncthreads();
-    if (tid == 0) {
+    if (tid < kResidSums) {
       double sacc = 0.0;
-      for (int w = 0; w < NT / 64; ++w) sacc += red[w];
-      A.partial[static_cast<int64_t>(col0) * tiles + t] = sacc;
+      for (int w = 0; w < NT / 64; ++w) sacc += red[tid * (NT / 64) + w];
+      const int64_t plane_elems = static_cast<int64_t>(A.ncols) * tiles;
+      A.partial[tid * plane_elems + static_cast<int64_t>(col0) * tiles + t] = sacc;
     }
   }
 }
@@ -860,11 +872,11 @@ void stencil_validate(int nx, int ny, int nz, int periodic, int elem_bytes, int 
 
 size_t stencil_partial_elems(const OpTables<float>& op, int ncols, const StencilLaunch& cfg) {
   const TileChoice a = tiles_for(op, 64, cfg), b = tiles_for(op, 1, cfg);
-  return static_cast<size_t>(ncols) * std::max(a.nyt * a.nzt, b.nyt * b.nzt);
+  return static_cast<size_t>(kResidSums) * ncols * std::max(a.nyt * a.nzt, b.nyt * b.nzt);
 }
 size_t stencil_partial_elems(const OpTables<double>& op, int ncols, const StencilLaunch& cfg) {
   const TileChoice a = tiles_for(op, 64, cfg), b = tiles_for(op, 1, cfg);
-  return static_cast<size_t>(ncols) * std::max(a.nyt * a.nzt, b.nyt * b.nzt);
+  return static_cast<size_t>(kResidSums) * ncols * std::max(a.nyt * a.nzt, b.nyt * b.nzt);
 }
 
 #endif  // XLS_STENCIL_DEFINE_HOST
@@ -907,7 +919,7 @@ template <typename TS, typename TC>
 void launch_stencil(StencilMode mode, const OpTables<TC>& op, const TS* y, int64_t ld, int ncols,
                     const TC* alpha, TS* out, const TS* yprev, double a, double c, double b,
                     const double* lam, double* partial, double* resid2, hipStream_t st,
-                    const StencilLaunch& cfg) {
+                    const StencilLaunch& cfg, double* rq) {
   if (ncols <= 0) return;
   StencilLaunch cfg1 = cfg;
   if (mode == kResid) cfg1.nv = 1;  // per-column partial sums
@@ -923,7 +935,7 @@ void launch_stencil(StencilMode mode, const OpTables<TC>& op, const TS* y, int64
   const int64_t nblocks = static_cast<int64_t>((ncols + tc.nv - 1) / tc.nv) * tc.nyt * tc.nzt;
   if (nblocks > 0x7fffffff) fail(XLS_ERR_INVALID_ARG, "too many stencil tiles");
   size_t smem = tc.smem;
-  if (mode == kResid) smem = std::max(smem, static_cast<size_t>(64 * sizeof(double)));
+  if (mode == kResid) smem = std::max(smem, static_cast<size_t>(kResidSums * (tc.block / 64) * sizeof(double)));
   const dim3 grid(static_cast<unsigned>(nblocks));
   // FP32-arithmetic sweeps never accumulate residuals, and FP64 sweeps of
   // FP32 blocks never run the filter recurrence: those pairs are not built
@@ -939,7 +951,10 @@ void launch_stencil(StencilMode mode, const OpTables<TC>& op, const TS* y, int64
       if constexpr (kHasResid) {
         launch_any<TS, TC, kResid>(tc, A, grid, smem, st);
         XLS_LAUNCH_CHECK("hstencil_kernel");
-        launch_reduce_cols(partial, tc.nyt * tc.nzt, ncols, resid2, 1, st);
+        const int tiles = tc.nyt * tc.nzt;
+        const int64_t plane_elems = static_cast<int64_t>(ncols) * tiles;
+        launch_reduce_cols(partial, tiles, ncols, resid2, 1, st);
+        if (rq) launch_reduce_rq(partial + plane_elems, partial + 2 * plane_elems, tiles, ncols, rq, st);
         return;
       } else {
         fail(XLS_ERR_INVALID_ARG, "residual sweep needs FP64 arithmetic");

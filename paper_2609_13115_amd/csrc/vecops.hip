@@ -27,6 +27,27 @@ __global__ __launch_bounds__(256) void reduce_cols_kernel(const double* __restri
   if (lane == 0) out[c] = take_sqrt ? sqrt(s) : s;
 }
 
+// Rayleigh quotients from the residual sweep's partial sums: the same lane
+// order and shuffle tree as reduce_cols_kernel for numerator and denominator.
+__global__ __launch_bounds__(256) void reduce_rq_kernel(const double* __restrict__ num,
+                                                        const double* __restrict__ den, int nper, int ncols,
+                                                        double* __restrict__ out) {
+  const int c = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (c >= ncols) return;
+  double a = 0.0, b = 0.0;
+  const double* pn = num + static_cast<int64_t>(c) * nper;
+  const double* pd = den + static_cast<int64_t>(c) * nper;
+  for (int i = lane; i < nper; i += 64) {
+    a += pn[i];
+    b += pd[i];
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    a += __shfl_xor(a, off, 64);
+    b += __shfl_xor(b, off, 64);
+  }
+  if (lane == 0) out[c] = a / b;  // a zero column gives NaN, as its residual would be meaningless
+}
+
 // g_n = 1/(1 + exp((lam_n - mu)/sigma)), overflow-free form.
 __global__ void fermi_kernel(const double* __restrict__ lam, int n, double mu, double sigma,
                              double* __restrict__ g) {
@@ -460,6 +481,11 @@ void launch_reduce_cols(const double* partial, int nper, int ncols, double* out,
   hipLaunchKernelGGL(reduce_cols_kernel, dim3(nblk(ncols, 4)), dim3(256), 0, st, partial, nper, ncols, out,
                      take_sqrt);
   XLS_LAUNCH_CHECK("reduce_cols_kernel");
+}
+
+void launch_reduce_rq(const double* num, const double* den, int nper, int ncols, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(reduce_rq_kernel, dim3(nblk(ncols, 4)), dim3(256), 0, st, num, den, nper, ncols, out);
+  XLS_LAUNCH_CHECK("reduce_rq_kernel");
 }
 
 void launch_density(const double* lam, double mu, double sigma, const uint8_t* mask, double h,

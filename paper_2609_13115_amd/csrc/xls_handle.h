@@ -54,6 +54,7 @@ struct xls_subdomain_s {
   size_t partial_elems = 0;
   double* lam_dev = nullptr;
   double* resid_dev = nullptr;
+  double* rq_dev = nullptr;  // FP64 Rayleigh quotients of the block's columns (residual sweep)
   double* Mdev = nullptr;
   double* Hsdev = nullptr;
   double* Ydev = nullptr;
@@ -116,7 +117,7 @@ struct xls_subdomain_s {
 
   ~xls_subdomain_s() {
     void* ps[] = {v64, v32, val64, val32, rev_pk, rev_aoff, rev_val64, rev_val32, sup_off, sup_idx, gamma, mask,
-                  blk[0], blk[1], alpha, alpha64, partial, lam_dev, resid_dev, Mdev, Hsdev, Ydev, bwork,
+                  blk[0], blk[1], alpha, alpha64, partial, lam_dev, resid_dev, rq_dev, Mdev, Hsdev, Ydev, bwork,
                   vsmall, rho_dev, cpart, gocc, lz, backup, orb_off, orb_idx, orb_val, orb_gamma, orb_alpha,
                   orb_P, orb_D, orb_edges, orb_core};
     for (void* p : ps) xls::dfree(p);
@@ -233,7 +234,7 @@ void filter_block(xls_subdomain_s* s, int m, double a0, double lc, double lmax);
 template <typename TS>
 void rotate_block(xls_subdomain_s* s, int gprec, const double* Ydev);
 template <typename TS>
-void residual_block(xls_subdomain_s* s, const double* lam_dev, double* resid_dev);
+void residual_block(xls_subdomain_s* s, const double* lam_dev, double* resid_dev, double* rq_dev = nullptr);
 template <typename TS>
 void lanczos_run(xls_subdomain_s* s, int k);
 

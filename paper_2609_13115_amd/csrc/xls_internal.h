@@ -80,13 +80,15 @@ struct StencilLaunch {
 // HY / filter step / residual over ncols columns of y (ld elements apart).
 //   kApply : out = H y
 //   kFilter: out = a (H y - c y) - b yprev   (yprev may alias out; b = 0 ignores yprev)
-//   kResid : resid2[col] = sqrt(sum_g (H y - lam[col] y)^2)   (needs partial scratch)
+//   kResid : resid2[col] = sqrt(sum_g (H y - lam[col] y)^2)   (needs partial scratch,
+//            stencil_partial_elems doubles); when rq is not null also
+//            rq[col] = (y^T H y) / (y^T y), the column's Rayleigh quotient, in FP64
 // alpha: [ncols][4*n_atoms] gamma-scaled projections of y (proj_forward).
 template <typename TS, typename TC>
 void launch_stencil(StencilMode mode, const OpTables<TC>& op, const TS* y, int64_t ld, int ncols,
                     const TC* alpha, TS* out, const TS* yprev, double a, double c, double b,
                     const double* lam, double* partial, double* resid2, hipStream_t st,
-                    const StencilLaunch& cfg);
+                    const StencilLaunch& cfg, double* rq = nullptr);
 // Filter step (kFilter, TS == TC) with one binary16 input stream of leading
 // dimension ld16: y16 as Y_k (then yprev16 is null and Y_{k-1} absent), or
 // yprev16 as Y_{k-1} (y is then the TS block); out is a TS block.
@@ -227,6 +229,9 @@ void launch_convert_block(const double* src, int64_t lds_, TS* dst, int64_t ldd,
 template <typename TS>
 void launch_block_to_double(const TS* src, int64_t lds_, double* dst, int64_t ldd, int64_t rows,
                             int cols, hipStream_t st);
+// out[c] = (sum_i num[c nper + i]) / (sum_i den[c nper + i]), both sums in
+// the fixed order of launch_reduce_cols
+void launch_reduce_rq(const double* num, const double* den, int nper, int ncols, double* out, hipStream_t st);
 void launch_reduce_cols(const double* partial, int nper, int ncols, double* out, int take_sqrt,
                         hipStream_t st);
 void launch_density(const double* lam, double mu, double sigma, const uint8_t* mask, double h,

@@ -582,3 +582,31 @@ def test_mixed_precision_ritz_gate_dirichlet():
     k = gap_edge(ref.ritz, gate)
     assert k >= gate // 2
     assert chefsi.subspace_sin_theta(ref.psi[:, :k], psi[:, :k]) <= 1e-5
+
+
+@pytest.mark.parametrize("fprec,gprec", [(xls.XLS_PREC_FP32, xls.XLS_PREC_BF16X3),
+                                         (xls.XLS_PREC_FP32, xls.XLS_PREC_FP32),
+                                         (xls.XLS_PREC_FP64, xls.XLS_PREC_FP64)])
+def test_reported_ritz_values_are_rayleigh_quotients(fprec, gprec):
+    """The returned Ritz values against the Rayleigh quotients
+    psi^T H psi / psi^T psi of the returned columns, with H applied by the
+    oracle in FP64.  For a Rayleigh-Ritz vector psi = Psi_f y the quotient
+    equals the projected eigenvalue exactly (y^T H_s y / y^T M_s y), so the
+    FP64 form (projected eigenvalues, ascending) must agree to rounding; the
+    mixed forms report the quotients themselves (FP64 sweep of the FP32
+    block), which must agree to the FP64 summation order."""
+    case(f"reported Ritz values filter={fprec} gemm={gprec}")
+    sd = workloads.small_dirichlet(ns=24, index=9, shape=(18, 16, 20), h=0.6)
+    op = hamiltonian.from_subdomain(sd)
+    with xls.Subdomain(sd, filter_prec=fprec) as s:
+        ritz, resid, it = s.xls_chefsi_step(16, 6, xls.XLS_BOUNDS_LANCZOS, gemm_prec=gprec)
+        psi = s.xls_subdomain_get_block()
+    hp = op.apply(psi)
+    rq = np.sum(psi * hp, axis=0) / np.sum(psi * psi, axis=0)
+    err = float(np.max(np.abs(ritz - rq) / np.maximum(np.abs(rq), 1.0)))
+    print(f"[ritz] filter={fprec} gemm={gprec}: max rel |ritz - rq| {err:.2e}", flush=True)
+    if fprec == xls.XLS_PREC_FP64:
+        assert np.all(np.diff(ritz) >= 0)
+        assert err <= 1e-10
+    else:
+        assert err <= 1e-12

@@ -77,11 +77,14 @@ def measured_traffic(form: str):
     return f["fetch_bytes"] + f["write_bytes"]
 
 
-def _pmc_values(path: str, counter: str):
+def _pmc_values(path: str, counter: str, form: str):
     """Per-dispatch values of one counter from a rocprofv3 counter CSV:
-    (fused-filter launches, device-to-device copy launches)."""
+    (the form's fused-filter launches, device-to-device copy launches).  A
+    --headline-only process runs both forms; the block type tells them apart
+    (double: fp64, float: mixed)."""
     import csv
 
+    want = "double" if form == "fp64" else "float"
     filt, copy = [], []
     with open(path) as fh:
         for r in csv.DictReader(fh):
@@ -90,7 +93,7 @@ def _pmc_values(path: str, counter: str):
             name, v = r["Kernel_Name"], float(r["Counter_Value"])
             if "hstencil_kernel<" in name:
                 args = [a.strip() for a in name[name.index("<") + 1:name.index(">")].split(",")]
-                if args[2] == "1":  # MODE 1: fused filter step
+                if args[0] == want and args[2] == "1":  # MODE 1: fused filter step
                     filt.append(v)
             elif "copyBuffer" in name:
                 copy.append(v)
@@ -105,7 +108,7 @@ def write_traffic(form: str, fetch_csv: str, write_csv: str):
     way.  Stamped with the stencil sources' hash."""
     out = {}
     for key, path, counter in (("fetch", fetch_csv, "FETCH_SIZE"), ("write", write_csv, "WRITE_SIZE")):
-        filt, copy = _pmc_values(path, counter)
+        filt, copy = _pmc_values(path, counter, form)
         if not filt or not copy:
             raise SystemExit(f"{path}: no filter or copy dispatches for {counter}")
         big = [c for c in copy if c >= 0.9 * max(copy)]

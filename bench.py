@@ -23,8 +23,10 @@ quotients of its vectors, so what separates the two forms is the
 convergence error of each (about r^2 / gap).  learned_gain: the first 32 subdomains, mixed with Lanczos
 bounds against mixed with learned bounds (one precision).  gemm_large: the
 96^3, Ns = 2,400 GEMM rates and their errors against FP64.  cpu_baseline
-times the FP64 oracle's filter on a column sample on the host.  The
-optional learned_gain leg is skipped, and the line says so, when the run
+times the FP64 oracle's filter on a column sample on the host.  widened:
+the binary16 warm-start filter steps, the PDOS of the 64^3 block and a
+255^3 multigrid-preconditioned Poisson solve.  The optional learned_gain
+leg is skipped, and the line says so, when the run
 has used more than --budget-s seconds before it.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--batch 256] [--gain 32]
@@ -200,6 +202,77 @@ def half_storage_timing(s, nd: int, ns: int, wbytes: int, reps: int = 5):
     nbytes = float(nd) * ns * (wbytes + 2)
     return {"store_ms": ts * 1e3, "load_ms": tl * 1e3, "bytes_each": nbytes,
             "store_gbs": nbytes / ts / 1e9, "load_gbs": nbytes / tl / 1e9, "half_bytes": float(nd) * ns * 2}
+
+
+def widened_rows(sd, reps: int = 3):
+    """The rows beyond the CheFSI step, measured beside it.
+    warm_start: the first two filter steps on the 64^3 box (FP32 form, degree
+    24 bounds) reading a binary16 warm start directly (xls_subdomain_use_half)
+    against the same two steps from an FP32 block holding the same values
+    (xls_subdomain_load_half): fused-kernel time from HIP events, best of
+    reps; bytes per point*vector 6 + 10 (half input) against 8 + 12.
+    pdos: xls_subdomain_pdos of the box's block after two mixed CheFSI
+    iterations (s and p orbitals on all 279 atoms, width 0.5 bohr, rc 2 bohr,
+    200 bins over the Ritz range), best wall time of reps calls including the
+    host copy of the weights (ns x 4 atoms doubles).
+    poisson: -(1/(4 pi)) Lap phi = f on a 255^3 zero-Dirichlet grid at
+    h = 0.4 bohr (16.6 M points), f random-normal (seeded), tol 1e-10, device
+    arrays (xls_poisson_solve_device): wall time, iterations, multigrid
+    levels, and unpreconditioned CG's iteration count beside it."""
+    import torch
+    from paper_2609_13115_amd import xls
+
+    out = {}
+    nd, ns = sd.nd, sd.x0.shape[1]
+    buf = torch.empty(nd * ns, dtype=torch.float16, device="cuda")
+    with xls.Subdomain(sd, filter_prec=xls.XLS_PREC_FP32) as s:
+        lo, up = s.xls_lanczos_bounds(20)
+        lc = lo + 0.1 * (up - lo)
+        s.xls_subdomain_store_half(buf)
+        xls.xls_set_profiling(True)
+        best = {"half": 1e9, "fp32": 1e9}
+        for _ in range(reps):
+            for form in ("half", "fp32"):
+                if form == "half":
+                    s.xls_subdomain_use_half(buf)
+                else:
+                    s.xls_subdomain_load_half(buf)
+                s.xls_subdomain_filter(2, lo, lc, up)
+                ms, n = s.xls_get_stage_times()
+                best[form] = min(best[form], float(ms[7]))
+        xls.xls_set_profiling(False)
+        out["warm_start"] = {"two_steps_half_input_ms": best["half"], "two_steps_fp32_ms": best["fp32"],
+                             "ratio": best["half"] / best["fp32"], "bytes_ratio": 16.0 / 20.0,
+                             "half_input_gbs": 16.0 * nd * ns / (best["half"] * 1e-3) / 1e9,
+                             "fp32_gbs": 20.0 * nd * ns / (best["fp32"] * 1e-3) / 1e9}
+        s.xls_subdomain_load_half(buf)
+        ritz, _, _ = s.xls_chefsi_step(24, 2, xls.XLS_BOUNDS_LANCZOS, gemm_prec=xls.XLS_PREC_BF16X3)
+        edges = np.linspace(float(ritz.min()) - 1e-9, float(ritz.max()) + 1e-9, 201)
+        t = 1e9
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            w, d, inc = s.xls_subdomain_pdos(0.5, 2.0, edges)
+            t = min(t, time.perf_counter() - t0)
+        out["pdos"] = {"ms": t * 1e3, "states": int(w.shape[0]), "orbitals": int(w.shape[1]), "bins": 200,
+                       "core_atoms": int(np.sum(inc)), "weight_sum": float(np.sum(d))}
+    del buf
+    torch.cuda.empty_cache()
+    n = (255, 255, 255)
+    f = torch.tensor(np.random.default_rng(20260913).standard_normal(int(np.prod(n))), dtype=torch.float64,
+                     device="cuda")
+    phi = torch.zeros_like(f)
+    with xls.Poisson(n, 0.4, 1) as p:
+        p.solve_device(f, phi, tol=1e-10)  # warm-up
+        it, rel, lev, ms = p.solve_device(f, phi, tol=1e-10)
+        it0, rel0, _, ms0 = p.solve_device(f, phi, tol=1e-10, max_iter=20000, precondition=False)
+    npts = float(np.prod(n))
+    out["poisson"] = {"grid": "255^3 zero Dirichlet, h 0.4 bohr", "points": npts, "tol": 1e-10,
+                      "iterations": it, "rel_resid": rel, "levels": lev, "ms": ms, "ms_per_iteration": ms / it,
+                      "unpreconditioned_iterations": it0, "unpreconditioned_ms": ms0}
+    del f, phi
+    torch.cuda.empty_cache()
+    print(f"[bench] widened rows: {json.dumps(out)}", file=sys.stderr, flush=True)
+    return out
 
 
 def time_gemms(s, nd: int, ns: int, form: str, reps: int = 5):
@@ -542,6 +615,7 @@ def main():
                 return True
             return False
 
+        out["widened"] = widened_rows(sd)
         if not a.no_gemm_large:
             out["gemm_large"] = gemm_large()
         tune = os.path.join("/tmp", f"xls_tune_{os.getpid()}.json")

@@ -536,12 +536,18 @@ void xls_batch_destroy(xls_batch_t b);
  * xls_poisson_solve: f and phi host arrays of N values; info (may be NULL)
  *   receives [iterations, final relative residual, levels, wall ms].
  *   Returns XLS_OK also when max_iter is reached (info[1] tells).
+ * xls_poisson_solve_device: the same solve with f and phi device arrays of N
+ *   doubles (each inside one device allocation, else INVALID_ARG); f is not
+ *   checked for finiteness (a NaN shows as info[1]).  Wall ms covers the
+ *   device solve only.
  * xls_poisson_vcycle: z = the preconditioner applied to r (host arrays of
  *   N values), for tests. */
 typedef struct xls_poisson_s* xls_poisson_t;
 int xls_poisson_create(const int32_t* n, double h, int32_t bc, int32_t max_levels, xls_poisson_t* out);
 int xls_poisson_solve(xls_poisson_t p, const double* f, double* phi, double tol, int32_t max_iter,
                       int32_t precond, double* info);
+int xls_poisson_solve_device(xls_poisson_t p, const double* f, double* phi, double tol, int32_t max_iter,
+                             int32_t precond, double* info);
 int xls_poisson_vcycle(xls_poisson_t p, const double* r, double* z);
 void xls_poisson_destroy(xls_poisson_t p);
 

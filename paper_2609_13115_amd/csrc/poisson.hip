@@ -465,15 +465,15 @@ int xls_poisson_vcycle(xls_poisson_t P, const double* r, double* z) {
   });
 }
 
-int xls_poisson_solve(xls_poisson_t P, const double* f, double* phi, double tol, int32_t max_iter,
-                      int32_t precond, double* info) {
-  return guarded([&]() -> int {
-    if (!P || !f || !phi) fail(XLS_ERR_INVALID_ARG, "NULL argument");
-    if (!(tol > 0) || max_iter < 1) fail(XLS_ERR_INVALID_ARG, "tol must be > 0 and max_iter >= 1");
-    if (!finite_all(f, P->nd)) fail(XLS_ERR_INVALID_ARG, "f not finite");
-    const auto t0 = std::chrono::steady_clock::now();
+}  // extern "C"
+
+namespace {
+
+// CG on the handle's device vectors: P->b holds f on entry; the solution is
+// left in P->x.  info as xls_poisson_solve (wall ms from t0).
+void solve_on_device(xls_poisson_t P, double tol, int32_t max_iter, int32_t precond, double* info,
+                     std::chrono::steady_clock::time_point t0) {
     const int64_t nd = P->nd;
-    XLS_HIP(hipMemcpyAsync(P->b, f, nd * 8, hipMemcpyHostToDevice, P->s));
     axpby(P, P->b, P->b, 0.0, 4.0 * M_PI);  // b = 4 pi f
     if (P->g.periodic) remove_mean(P, P->b);
     XLS_HIP(hipMemsetAsync(P->x, 0, nd * 8, P->s));
@@ -507,7 +507,6 @@ int xls_poisson_solve(xls_poisson_t P, const double* f, double* phi, double tol,
       if (it > max_iter) it = max_iter;
       if (P->g.periodic) remove_mean(P, P->x);
     }
-    XLS_HIP(hipMemcpyAsync(phi, P->x, nd * 8, hipMemcpyDeviceToHost, P->s));
     XLS_HIP(hipStreamSynchronize(P->s));
     if (info) {
       info[0] = it;
@@ -515,6 +514,44 @@ int xls_poisson_solve(xls_poisson_t P, const double* f, double* phi, double tol,
       info[2] = static_cast<double>(P->lev.size());
       info[3] = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     }
+}
+
+void check_solve_args(xls_poisson_t P, const void* f, const void* phi, double tol, int32_t max_iter) {
+  if (!P || !f || !phi) fail(XLS_ERR_INVALID_ARG, "NULL argument");
+  if (!(tol > 0) || max_iter < 1) fail(XLS_ERR_INVALID_ARG, "tol must be > 0 and max_iter >= 1");
+}
+
+}  // namespace
+
+extern "C" {
+
+int xls_poisson_solve(xls_poisson_t P, const double* f, double* phi, double tol, int32_t max_iter,
+                      int32_t precond, double* info) {
+  return guarded([&]() -> int {
+    check_solve_args(P, f, phi, tol, max_iter);
+    if (!finite_all(f, P->nd)) fail(XLS_ERR_INVALID_ARG, "f not finite");
+    const auto t0 = std::chrono::steady_clock::now();
+    XLS_HIP(hipMemcpyAsync(P->b, f, P->nd * 8, hipMemcpyHostToDevice, P->s));
+    solve_on_device(P, tol, max_iter, precond, info, t0);
+    XLS_HIP(hipMemcpyAsync(phi, P->x, P->nd * 8, hipMemcpyDeviceToHost, P->s));
+    XLS_HIP(hipStreamSynchronize(P->s));
+    if (info) info[3] = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return XLS_OK;
+  });
+}
+
+int xls_poisson_solve_device(xls_poisson_t P, const double* f, double* phi, double tol, int32_t max_iter,
+                             int32_t precond, double* info) {
+  return guarded([&]() -> int {
+    check_solve_args(P, f, phi, tol, max_iter);
+    check_device_range(f, P->nd * 8);
+    check_device_range(phi, P->nd * 8);
+    const auto t0 = std::chrono::steady_clock::now();
+    XLS_HIP(hipMemcpyAsync(P->b, f, P->nd * 8, hipMemcpyDeviceToDevice, P->s));
+    solve_on_device(P, tol, max_iter, precond, info, t0);
+    XLS_HIP(hipMemcpyAsync(phi, P->x, P->nd * 8, hipMemcpyDeviceToDevice, P->s));
+    XLS_HIP(hipStreamSynchronize(P->s));
+    if (info) info[3] = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     return XLS_OK;
   });
 }

@@ -47,7 +47,8 @@ EXPORTED = [
     "xls_mlp_fit", "xls_mlp_train_rms", "xls_mlp_bounds", "xls_learned_safe_bounds",
     "xls_batch_create_slots", "xls_subdomain_tune_gemm", "xls_subdomain_use_half",
     "xls_dense_geneig_noalloc", "xls_subdomain_pdos",
-    "xls_poisson_create", "xls_poisson_solve", "xls_poisson_vcycle", "xls_poisson_destroy",
+    "xls_poisson_create", "xls_poisson_solve", "xls_poisson_solve_device", "xls_poisson_vcycle",
+    "xls_poisson_destroy",
 ]
 
 
@@ -696,6 +697,19 @@ class Poisson:
         _check(lib().xls_poisson_solve(self._h, _dp(ff), _dp(phi), C.c_double(tol), C.c_int32(max_iter),
                                        C.c_int32(1 if precondition else 0), _dp(info)))
         return phi, (int(info[0]), float(info[1]), int(info[2]), float(info[3]))
+
+    def solve_device(self, f, phi, tol: float = 1e-10, max_iter: int = 500, precondition: bool = True):
+        """Solve with f and phi device tensors of nd float64 values (device
+        pointers only; no transfer).  Returns info = (iterations, relative
+        residual, levels, ms)."""
+        for t, name in ((f, "f"), (phi, "phi")):
+            if not (t.is_cuda and t.dtype.itemsize == 8 and t.is_contiguous() and t.numel() == self.nd):
+                raise ValueError(f"{name} must be a contiguous float64 device tensor of {self.nd} values")
+        info = np.zeros(4)
+        _check(lib().xls_poisson_solve_device(self._h, C.c_void_p(f.data_ptr()), C.c_void_p(phi.data_ptr()),
+                                              C.c_double(tol), C.c_int32(max_iter),
+                                              C.c_int32(1 if precondition else 0), _dp(info)))
+        return int(info[0]), float(info[1]), int(info[2]), float(info[3])
 
     def vcycle(self, r):
         rr = np.ascontiguousarray(r, dtype=np.float64).reshape(-1)

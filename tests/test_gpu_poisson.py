@@ -85,3 +85,22 @@ def test_large_grid_residual_and_closed_form(n, periodic):
         Phi.flat[0] = 0.0
         ref = np.real(np.fft.ifftn(Phi)).reshape(-1)
         assert np.linalg.norm(phi - ref) <= 1e-8 * np.linalg.norm(ref)
+
+
+def test_solve_device_matches_host_solve():
+    """xls_poisson_solve_device runs the same solve on device arrays: the
+    same iterations and bit-identical phi; host memory is refused."""
+    import torch
+
+    case("poisson device-array solve")
+    n = (31, 15, 23)
+    f = rhs(n, 3, False)
+    fd = torch.tensor(f, dtype=torch.float64, device="cuda")
+    pd = torch.zeros_like(fd)
+    with xls.Poisson(n, 0.4, 1) as p:
+        phi, info = p.solve(f, tol=1e-10)
+        info_d = p.solve_device(fd, pd, tol=1e-10)
+        with pytest.raises(ValueError):
+            p.solve_device(fd.cpu(), pd, tol=1e-10)
+    assert info_d[0] == info[0] and info_d[1] == info[1]
+    assert np.array_equal(pd.cpu().numpy(), phi)

@@ -537,6 +537,8 @@ def main():
                     help="subdomains for the learned gain at one precision, mixed + Lanczos vs mixed + learned")
     ap.add_argument("--no-gemm-large", action="store_true", help="skip the 96^3, Ns = 2400 GEMM table")
     ap.add_argument("--headline-only", action="store_true", help="only the 64^3 steps (profiling runs)")
+    ap.add_argument("--widened-only", action="store_true",
+                    help="only the widened rows (warm-start steps, PDOS, Poisson; profiling runs)")
     ap.add_argument("--budget-s", type=float, default=720.0,
                     help="skip the optional learned_gain leg once this many seconds have passed")
     ap.add_argument("--write-traffic", nargs=3, metavar=("FORM", "FETCH_CSV", "WRITE_CSV"),
@@ -557,6 +559,9 @@ def main():
     sd = workloads.si_box_64(with_x0=False, ns=a.ns)
     x0 = sd.make_x0(a.ns)
     sd.x0 = x0
+    if a.widened_only:
+        print(json.dumps({"widened": widened_rows(sd), "wall_s": time.perf_counter() - T_START}), flush=True)
+        return
     if a.calib_mib > 0:
         src = torch.empty(a.calib_mib << 20, dtype=torch.uint8, device="cuda")
         dst = torch.empty_like(src)

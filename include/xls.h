@@ -296,13 +296,17 @@ int xls_subdomain_tune(xls_subdomain_t s, int32_t prec, int32_t block, int32_t t
 
 /* Launch plan of the handle's projection and rotation GEMMs (Sec. V-B.3:
  * split-K over the long N_d dimension).  split_scale 0 keeps the default
- * split count (about two resident workgroups per CU, at least 16 k-slabs per
+ * split count (about as many workgroups as are resident at once: two per
+ * CU with 128 x 128 tiles, three with 96 x 96; at least 16 k-slabs per
  * split); k in [1, 64] scales it by k/2 (still bounded by K and the
- * workspace).  tile_tn / tile_nn: 0 takes the large-tile MFMA kernels when
- * the shapes allow (128 x 128 projection tiles, 64 x 256 rotation tiles), 1
- * the 64 x 64 ones.  A plan changes the order of the split-K partial sums
- * (results stay deterministic per plan), never a product.  INVALID_ARG
- * outside those ranges. */
+ * workspace).  tile_tn (projection): 0 takes the large-tile MFMA kernel
+ * when the shapes allow, with 96 x 96 tiles where they issue at least 10 %
+ * less padded and redundant work than 128 x 128 (an order of 480, say) and
+ * 128 x 128 otherwise; 1 the 64 x 64 tiles; 2 and 3 force the 128 and 96
+ * edges of the large kernel (FP64 products of FP32 blocks always take 128).  tile_nn (rotation): 0 takes 64 x 256 tiles
+ * when the shapes allow, 1 the 64 x 64 ones.  A plan changes the order of
+ * the split-K partial sums (results stay deterministic per plan), never a
+ * product.  INVALID_ARG outside those ranges. */
 int xls_subdomain_tune_gemm(xls_subdomain_t s, int32_t split_scale, int32_t tile_tn, int32_t tile_nn);
 
 /* Profiling switch (process-wide, default off): with 1, xls_chefsi_step

@@ -486,8 +486,12 @@ __device__ __forceinline__ void big_put_row(typename Form<MF>::lds_t* h, typenam
   }
 }
 
-// Partial C = A^T B over one K split, 128 x 128 output tile per workgroup.
-template <typename TIN, int MF>
+// Partial C = A^T B over one K split, T x T output tile per workgroup (T =
+// 128 or 96): four waves in a 2 x 2 grid, each owning a (T/2) x (T/2)
+// sub-tile of NI x NI MFMA blocks of 16 x 16.  The 96 tile covers an order
+// of 480 (or any multiple of 96) without padding, and the triangle of a
+// symmetric product with less redundant work on its diagonal tiles.
+template <typename TIN, int MF, int T>
 __global__ __launch_bounds__(256, 2) void gemm_tn_big_kernel(const TIN* __restrict__ A, int64_t lda,
                                                           const TIN* __restrict__ B, int64_t ldb, int M,
                                                           int N, int64_t K, int64_t kchunk, int tm, int tn,
@@ -495,9 +499,12 @@ __global__ __launch_bounds__(256, 2) void gemm_tn_big_kernel(const TIN* __restri
   using Lc = BigLds<MF>;
   using L = typename Lc::L;
   using FR = Frag<MF>;
-  constexpr int T = 128, BK = Lc::BK, ST = Lc::STRIDE;
+  static_assert(T == 128 || T == 96, "large TN tiles are 128 or 96");
+  constexpr int BK = Lc::BK, ST = Lc::STRIDE;
+  constexpr int WT = T / 2, NI = WT / 16;
   constexpr int VEC = 16 / sizeof(TIN);
   constexpr int PERCOL = BK / VEC;
+  static_assert((T * PERCOL) % 256 == 0, "whole loads per thread");
   constexpr int LOADS = T * PERCOL / 256;
   __shared__ __align__(16) L sm[2 * Lc::PARTS * T * ST];
   L* xh = sm;
@@ -559,11 +566,11 @@ __global__ __launch_bounds__(256, 2) void gemm_tn_big_kernel(const TIN* __restri
     }
   };
 
-  typename Form<MF>::acc_t acc[4][4];
+  typename Form<MF>::acc_t acc[NI][NI];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < NI; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = typename Form<MF>::acc_t{};
+    for (int j = 0; j < NI; ++j) acc[i][j] = typename Form<MF>::acc_t{};
   // The FP32 form (the polish projection) moves its MFMA sums into a
   // second FP32 accumulator every kFlushSteps k-blocks (128 k), so rounding
   // grows over 32 MFMA steps and then over the few hundred flushes of a K
@@ -572,14 +579,14 @@ __global__ __launch_bounds__(256, 2) void gemm_tn_big_kernel(const TIN* __restri
   // occupancy.)
   constexpr bool FLUSH = (MF == MF_F32);
   constexpr int kFlushSteps = 4;
-  float accd[FLUSH ? 4 : 1][FLUSH ? 4 : 1][4] = {};
+  float accd[FLUSH ? NI : 1][FLUSH ? NI : 1][4] = {};
   int since_flush = 0;
   auto flush = [&]() {
     if constexpr (FLUSH) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < NI; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < NI; ++j) {
 #pragma unroll
           for (int r = 0; r < 4; ++r) accd[i][j][r] += acc[i][j][r];
           acc[i][j] = typename Form<MF>::acc_t{};
@@ -596,15 +603,15 @@ __global__ __launch_bounds__(256, 2) void gemm_tn_big_kernel(const TIN* __restri
     if (kb + BK < kend) load(kb + BK);
 #pragma unroll
     for (int ks = 0; ks < BK; ks += FR::KS) {
-      typename FR::t fa[4], fb[4];
+      typename FR::t fa[NI], fb[NI];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) fa[i] = FR::load(xh, xl, wr * 64 + i * 16 + (lane & 15), ST, ks, lane);
+      for (int i = 0; i < NI; ++i) fa[i] = FR::load(xh, xl, wr * WT + i * 16 + (lane & 15), ST, ks, lane);
 #pragma unroll
-      for (int j = 0; j < 4; ++j) fb[j] = FR::load(yh, yl, wc * 64 + j * 16 + (lane & 15), ST, ks, lane);
+      for (int j = 0; j < NI; ++j) fb[j] = FR::load(yh, yl, wc * WT + j * 16 + (lane & 15), ST, ks, lane);
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < NI; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) FR::mma(acc[i][j], fa[i], fb[j]);
+        for (int j = 0; j < NI; ++j) FR::mma(acc[i][j], fa[i], fb[j]);
     }
     if constexpr (FLUSH) {
       if (++since_flush == kFlushSteps) {
@@ -616,13 +623,13 @@ __global__ __launch_bounds__(256, 2) void gemm_tn_big_kernel(const TIN* __restri
   if constexpr (FLUSH) flush();
   double* Ps = P + static_cast<int64_t>(split) * M * N;
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < NI; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < NI; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = m0 + wr * 64 + i * 16 + Form<MF>::orow(lane, r);
-        const int cl = n0 + wc * 64 + j * 16 + (lane & 15);
+        const int row = m0 + wr * WT + i * 16 + Form<MF>::orow(lane, r);
+        const int cl = n0 + wc * WT + j * 16 + (lane & 15);
         const double v = FLUSH ? static_cast<double>(accd[i][j][r]) : Form<MF>::get(acc[i][j], r);
         if (row < M && cl < N) Ps[row + static_cast<int64_t>(cl) * M] = v;
       }
@@ -850,6 +857,48 @@ int planned_splits(int def, const GemmPlan& plan) {
   return plan.split_scale > 0 ? std::max(1, def * plan.split_scale / 2) : def;
 }
 
+// Issued output area of the large TN kernel with tile edge T: every tile
+// (on or above the block diagonal of a symmetric product) is computed whole.
+int64_t tn_issued_area(int M, int N, int sym, int T) {
+  const int64_t tm = (M + T - 1) / T, tn = (N + T - 1) / T;
+  return (sym ? tm * (tm + 1) / 2 : tm * tn) * T * T;
+}
+
+// Large-tile edge: 96 where it issues at least 10 % less padded and
+// redundant work than 128 (a forced edge through the plan otherwise).
+int tn_tile_edge(int M, int N, int sym, const GemmPlan& plan) {
+  if (plan.tile_tn == 2) return 128;
+  if (plan.tile_tn == 3) return 96;
+  return 10 * tn_issued_area(M, N, sym, 96) < 9 * tn_issued_area(M, N, sym, 128) ? 96 : 128;
+}
+
+template <typename TIN, int MF, int T>
+void tn_big_launch(const TIN* A, int64_t lda, const TIN* B, int64_t ldb, int M, int N, int64_t K, double* C,
+                   int64_t ldc, int sym, int symmetrize, double* work, size_t work_elems, hipStream_t st,
+                   const GemmPlan& plan) {
+  const int tm = (M + T - 1) / T, tn = (N + T - 1) / T;
+  const int ntile = sym ? tm * (tm + 1) / 2 : tm * tn;
+  const int bk = BigLds<MF>::BK;
+  // about as many workgroups as are resident at once (2 per CU at edge 128,
+  // 3 at edge 96: its smaller accumulator tile leaves room for a third; 1.5x
+  // the splits measured 3-22 % faster there), so that symmetric products
+  // (fewer tiles) get more splits; >= 16 K slabs each
+  constexpr int kResident = (T == 96) ? 3 : 2;
+  int splits = planned_splits(std::max(1, kResident * device_cus() / ntile), plan);
+  splits = static_cast<int>(std::min<int64_t>(splits, std::max<int64_t>(1, K / (16 * bk))));
+  const size_t per = static_cast<size_t>(M) * N;
+  splits = static_cast<int>(std::min<size_t>(splits, std::max<size_t>(1, work_elems / per)));
+  int64_t kchunk = (K + splits - 1) / splits;
+  kchunk = ((kchunk + bk - 1) / bk) * bk;
+  const int real_splits = static_cast<int>((K + kchunk - 1) / kchunk);
+  const int64_t nb = static_cast<int64_t>(ntile) * real_splits;
+  if (nb > 0x7fffffff) fail(XLS_ERR_INVALID_ARG, "gemm_tn grid too large");
+  hipLaunchKernelGGL((gemm_tn_big_kernel<TIN, MF, T>), dim3(static_cast<unsigned>(nb)), dim3(256), 0, st, A,
+                     lda, B, ldb, M, N, K, kchunk, tm, tn, sym, work);
+  XLS_LAUNCH_CHECK("gemm_tn_big_kernel");
+  launch_tn_reduce(work, real_splits, M, N, T, sym, symmetrize, C, ldc, st);
+}
+
 template <typename TIN, int MF>
 void tn_dispatch(const TIN* A, int64_t lda, const TIN* B, int64_t ldb, int M, int N, int64_t K,
                  double* C, int64_t ldc, int sym, int symmetrize, double* work, size_t work_elems,
@@ -857,25 +906,16 @@ void tn_dispatch(const TIN* A, int64_t lda, const TIN* B, int64_t ldb, int M, in
   constexpr int VEC = 16 / sizeof(TIN);
   if (plan.tile_tn != 1 && M >= 64 && N >= 64 && lda % VEC == 0 && ldb % VEC == 0 && K <= lda && K <= ldb &&
       aligned16(A) && aligned16(B)) {
-    constexpr int T = 128;
-    const int tm = (M + T - 1) / T, tn = (N + T - 1) / T;
-    const int ntile = sym ? tm * (tm + 1) / 2 : tm * tn;
-    const int bk = BigLds<MF>::BK;
-    // about two resident workgroups per CU (the kernel's occupancy), so that
-    // symmetric products (fewer tiles) get more splits; >= 16 K slabs each
-    int splits = planned_splits(std::max(1, 2 * device_cus() / ntile), plan);
-    splits = static_cast<int>(std::min<int64_t>(splits, std::max<int64_t>(1, K / (16 * bk))));
-    const size_t per = static_cast<size_t>(M) * N;
-    splits = static_cast<int>(std::min<size_t>(splits, std::max<size_t>(1, work_elems / per)));
-    int64_t kchunk = (K + splits - 1) / splits;
-    kchunk = ((kchunk + bk - 1) / bk) * bk;
-    const int real_splits = static_cast<int>((K + kchunk - 1) / kchunk);
-    const int64_t nb = static_cast<int64_t>(ntile) * real_splits;
-    if (nb > 0x7fffffff) fail(XLS_ERR_INVALID_ARG, "gemm_tn grid too large");
-    hipLaunchKernelGGL((gemm_tn_big_kernel<TIN, MF>), dim3(static_cast<unsigned>(nb)), dim3(256), 0, st, A, lda,
-                       B, ldb, M, N, K, kchunk, tm, tn, sym, work);
-    XLS_LAUNCH_CHECK("gemm_tn_big_kernel");
-    launch_tn_reduce(work, real_splits, M, N, T, sym, symmetrize, C, ldc, st);
+    // the 96 edge needs whole 16-byte loads per thread (not the FP64
+    // products of FP32 blocks: 4 loads per 16-wide k slab and row)
+    constexpr bool k96 = (96 * (BigLds<MF>::BK / VEC)) % 256 == 0;
+    if constexpr (k96) {
+      if (tn_tile_edge(M, N, sym, plan) == 96) {
+        tn_big_launch<TIN, MF, 96>(A, lda, B, ldb, M, N, K, C, ldc, sym, symmetrize, work, work_elems, st, plan);
+        return;
+      }
+    }
+    tn_big_launch<TIN, MF, 128>(A, lda, B, ldb, M, N, K, C, ldc, sym, symmetrize, work, work_elems, st, plan);
     return;
   }
   const int tm = (M + kTile - 1) / kTile, tn = (N + kTile - 1) / kTile;

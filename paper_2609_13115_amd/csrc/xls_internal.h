@@ -154,10 +154,13 @@ size_t stencil_partial_elems(const OpTables<double>& op, int ncols, const Stenci
 //            aligned; bwork may be null only for FP64 calls (the small-tile
 //            path is taken when B would need padding).
 // Launch plan of the projection and rotation GEMMs (the autotuner's choice
-// per shape class): split_scale 0 keeps the default split-K count (about two
-// resident workgroups per CU, at least 16 k-slabs per split), k > 0 scales it
-// by k/2; tile_tn / tile_nn 0 take the 128 x 128 (64 x 256 for the
-// rotation) large-tile kernels when shapes allow, 1 the 64 x 64 tiles.
+// per shape class): split_scale 0 keeps the default split-K count (about as
+// many workgroups as are resident at once, at least 16 k-slabs per split;
+// the rotation's tiles do not split), k > 0 scales it
+// by k/2; tile_tn 0 takes the large-tile projection kernel when shapes
+// allow (edge 96 or 128, whichever issues less padded work by 10 %), 1 the
+// 64 x 64 tiles, 2 and 3 force the 128 and 96 edges; tile_nn 0 takes the
+// 64 x 256 rotation tiles when shapes allow, 1 the 64 x 64 ones.
 // A plan changes the order of the split sums, never a product.
 struct GemmPlan {
   int split_scale = 0;

@@ -272,6 +272,53 @@ def test_projection_and_rotation_large(prec, tol, ns):
     assert rel_err(out, X @ Q) <= rtol  # the FP32 block stores the result in FP32
 
 
+# Both edges of the large projection kernel, forced through the GEMM plan
+# (tile_tn 2 = 128, 3 = 96), on orders that leave a ragged last tile at
+# either edge (200: 96 + 96 + 8; 304: 3 x 96 + 16), and the automatic choice
+# at ns = 480 (five whole 96 tiles, where it takes 96).
+@pytest.mark.parametrize("ns,tile", [(200, 2), (200, 3), (304, 3), (480, 0)])
+@pytest.mark.parametrize("prec,tol", [(xls.XLS_PREC_FP64, 1e-12), (xls.XLS_PREC_FP32, 2e-6),
+                                      (xls.XLS_PREC_BF16X3, 1e-5)])
+def test_projection_tile_edges(prec, tol, ns, tile):
+    case(f"projection tile edge ns={ns} tile_tn={tile} gemm={prec}")
+    sd = workloads.small_dirichlet(ns=ns, shape=(20, 19, 21))
+    op = hamiltonian.from_subdomain(sd)
+    X = sd.x0.astype(np.float32).astype(np.float64)
+    with xls.Subdomain(sd, filter_prec=xls.XLS_PREC_FP32) as s:
+        s.xls_subdomain_tune_gemm(0, tile, 0)
+        M, Hs = s.xls_subdomain_project(prec)
+    Mr = X.T @ X
+    W = op.apply(X).astype(np.float32).astype(np.float64)
+    Hr = X.T @ W
+    Hr = 0.5 * (Hr + Hr.T)
+    assert rel_err(M, Mr) <= tol
+    assert rel_err(Hs, Hr) <= max(tol, 2e-6)
+
+
+@pytest.mark.parametrize("ns,tile", [(200, 3), (480, 0)])
+def test_projection_tile_edges_fp64_block(ns, tile):
+    case(f"projection tile edge fp64 block ns={ns} tile_tn={tile}")
+    sd = workloads.small_dirichlet(ns=ns, shape=(18, 20, 19))
+    op = hamiltonian.from_subdomain(sd)
+    X = sd.x0
+    with xls.Subdomain(sd) as s:
+        s.xls_subdomain_tune_gemm(0, tile, 0)
+        M, Hs = s.xls_subdomain_project(xls.XLS_PREC_FP64)
+    Hr = X.T @ op.apply(X)
+    assert rel_err(M, X.T @ X) <= 1e-12
+    assert rel_err(Hs, 0.5 * (Hr + Hr.T)) <= 1e-12
+
+
+def test_gemm_plan_rejects_unknown_tile():
+    case("gemm plan range")
+    sd = workloads.small_dirichlet(ns=8, shape=(8, 8, 8))
+    with xls.Subdomain(sd) as s:
+        with pytest.raises(xls.XlsError):
+            s.xls_subdomain_tune_gemm(0, 4, 0)
+        with pytest.raises(xls.XlsError):
+            s.xls_subdomain_tune_gemm(0, 0, 2)
+
+
 @pytest.mark.parametrize("ns", [128, 304])
 def test_projection_rotation_large_fp64_block(ns):
     case(f"projection/rotation large fp64 block ns={ns}")

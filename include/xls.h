@@ -303,10 +303,12 @@ int xls_subdomain_tune(xls_subdomain_t s, int32_t prec, int32_t block, int32_t t
  * when the shapes allow, with 96 x 96 tiles where they issue at least 10 %
  * less padded and redundant work than 128 x 128 (an order of 480, say) and
  * 128 x 128 otherwise; 1 the 64 x 64 tiles; 2 and 3 force the 128 and 96
- * edges of the large kernel (FP64 products of FP32 blocks always take 128).  tile_nn (rotation): 0 takes 64 x 256 tiles
- * when the shapes allow, 1 the 64 x 64 ones.  A plan changes the order of
- * the split-K partial sums (results stay deterministic per plan), never a
- * product.  INVALID_ARG outside those ranges. */
+ * edges of the large kernel (FP64 products of FP32 blocks always take
+ * 128).  tile_nn (rotation): 0 and 3 take the large-tile kernel with
+ * 64 x 128 tiles when the shapes allow, 1 the 64 x 64 tiles, 2 the large
+ * kernel with 64 x 256 tiles.  A plan changes the
+ * order of the split-K partial sums (results stay deterministic per plan),
+ * never a product.  INVALID_ARG outside those ranges. */
 int xls_subdomain_tune_gemm(xls_subdomain_t s, int32_t split_scale, int32_t tile_tn, int32_t tile_nn);
 
 /* Profiling switch (process-wide, default off): with 1, xls_chefsi_step

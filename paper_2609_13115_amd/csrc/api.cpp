@@ -1251,8 +1251,8 @@ int xls_subdomain_tune(xls_subdomain_t s, int32_t prec, int32_t block, int32_t t
 int xls_subdomain_tune_gemm(xls_subdomain_t s, int32_t split_scale, int32_t tile_tn, int32_t tile_nn) {
   return guarded([&]() -> int {
     if (!s) fail(XLS_ERR_INVALID_ARG, "NULL handle");
-    if (split_scale < 0 || split_scale > 64 || tile_tn < 0 || tile_tn > 3 || tile_nn < 0 || tile_nn > 1)
-      fail(XLS_ERR_INVALID_ARG, "split_scale must be in [0, 64], tile_tn in [0, 3], tile_nn 0 or 1");
+    if (split_scale < 0 || split_scale > 64 || tile_tn < 0 || tile_tn > 3 || tile_nn < 0 || tile_nn > 3)
+      fail(XLS_ERR_INVALID_ARG, "split_scale must be in [0, 64], tile_tn and tile_nn in [0, 3]");
     s->gplan.split_scale = split_scale;
     s->gplan.tile_tn = tile_tn;
     s->gplan.tile_nn = tile_nn;

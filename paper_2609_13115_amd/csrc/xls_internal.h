@@ -160,7 +160,8 @@ size_t stencil_partial_elems(const OpTables<double>& op, int ncols, const Stenci
 // by k/2; tile_tn 0 takes the large-tile projection kernel when shapes
 // allow (edge 96 or 128, whichever issues less padded work by 10 %), 1 the
 // 64 x 64 tiles, 2 and 3 force the 128 and 96 edges; tile_nn 0 takes the
-// 64 x 256 rotation tiles when shapes allow, 1 the 64 x 64 ones.
+// large rotation kernel with 64 x 128 tiles when shapes allow (3 too), 1
+// the 64 x 64 tiles, 2 the large kernel with 64 x 256 tiles.
 // A plan changes the order of the split sums, never a product.
 struct GemmPlan {
   int split_scale = 0;

@@ -309,6 +309,36 @@ def test_projection_tile_edges_fp64_block(ns, tile):
     assert rel_err(Hs, 0.5 * (Hr + Hr.T)) <= 1e-12
 
 
+# Both column widths of the large rotation kernel (tile_nn 2 = 256, 0 and 3 =
+# 128): ns = 200 is ragged at either width, 300 pads to 384 at 128, 480 is
+# four 128-column tiles with the last ragged.
+@pytest.mark.parametrize("ns,tile", [(200, 2), (200, 3), (300, 0), (480, 3)])
+@pytest.mark.parametrize("prec,tol", [(xls.XLS_PREC_FP64, 2e-7), (xls.XLS_PREC_FP32, 2e-6),
+                                      (xls.XLS_PREC_BF16X3, 2e-5)])
+def test_rotation_tile_widths(prec, tol, ns, tile):
+    case(f"rotation tile width ns={ns} tile_nn={tile} gemm={prec}")
+    sd = workloads.small_dirichlet(ns=ns, shape=(20, 19, 21))
+    X = sd.x0.astype(np.float32).astype(np.float64)
+    Q = np.random.default_rng(7).standard_normal((ns, ns)) / np.sqrt(ns)
+    with xls.Subdomain(sd, filter_prec=xls.XLS_PREC_FP32) as s:
+        s.xls_subdomain_tune_gemm(0, 0, tile)
+        s.xls_subdomain_rotate(Q, prec)
+        out = s.xls_subdomain_get_block()
+    assert rel_err(out, X @ Q) <= tol  # the FP32 block stores the result in FP32
+
+
+@pytest.mark.parametrize("ns,tile", [(200, 3), (300, 0)])
+def test_rotation_tile_widths_fp64_block(ns, tile):
+    case(f"rotation tile width fp64 block ns={ns} tile_nn={tile}")
+    sd = workloads.small_dirichlet(ns=ns, shape=(18, 20, 19))
+    Q = np.random.default_rng(8).standard_normal((ns, ns)) / np.sqrt(ns)
+    with xls.Subdomain(sd) as s:
+        s.xls_subdomain_tune_gemm(0, 0, tile)
+        s.xls_subdomain_rotate(Q, xls.XLS_PREC_FP64)
+        out = s.xls_subdomain_get_block()
+    assert rel_err(out, sd.x0 @ Q) <= 1e-13
+
+
 def test_gemm_plan_rejects_unknown_tile():
     case("gemm plan range")
     sd = workloads.small_dirichlet(ns=8, shape=(8, 8, 8))
@@ -316,7 +346,9 @@ def test_gemm_plan_rejects_unknown_tile():
         with pytest.raises(xls.XlsError):
             s.xls_subdomain_tune_gemm(0, 4, 0)
         with pytest.raises(xls.XlsError):
-            s.xls_subdomain_tune_gemm(0, 0, 2)
+            s.xls_subdomain_tune_gemm(0, 0, 4)
+        with pytest.raises(xls.XlsError):
+            s.xls_subdomain_tune_gemm(65, 0, 0)
 
 
 @pytest.mark.parametrize("ns", [128, 304])

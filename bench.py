@@ -277,14 +277,14 @@ def widened_rows(sd, reps: int = 3):
 
 def time_gemms(s, nd: int, ns: int, form: str, reps: int = 5):
     """TFLOP/s of the three GEMMs at each precision of the form: algorithmic
-    flops (N_d N_s^2 for the symmetric product, 2 N_d N_s^2 for the others)
-    and issued MFMA flops (x3 for the split-BF16 form) against the dtype's
-    dense peak."""
+    flops (N_d N_s^2 for the two projections, which form one triangle each,
+    2 N_d N_s^2 for the rotation) and issued MFMA flops (x3 for the
+    split-BF16 form) against the dtype's dense peak."""
     from paper_2609_13115_amd import xls
 
     precs = [("fp64", xls.XLS_PREC_FP64)] if form == "fp64" else [("bf16x3", xls.XLS_PREC_BF16X3),
                                                                    ("fp32", xls.XLS_PREC_FP32)]
-    flops = {"xtx": nd * ns * ns, "xthx": 2.0 * nd * ns * ns, "rotation": 2.0 * nd * ns * ns}
+    flops = {"xtx": nd * ns * ns, "xthx": nd * ns * ns, "rotation": 2.0 * nd * ns * ns}
     out = {}
     for name, p in precs:
         ms = s.xls_subdomain_time_gemms(p, reps)

@@ -179,8 +179,12 @@ int xls_hamiltonian_apply(xls_subdomain_t s, const double* X, double* HX, int32_
 int xls_subdomain_filter(xls_subdomain_t s, int32_t degree, double a0, double lam_cut,
                          double lam_max);
 
-/* Projection of the handle's block (step (2)): M = B^T B, Hs = sym(B^T H B),
- * both ns x ns column-major FP64, GEMMs in gemm_prec. */
+/* Projection of the handle's block (step (2)): M = B^T B, Hs = B^T H B,
+ * both ns x ns column-major FP64, GEMMs in gemm_prec.  Both products form
+ * only their upper block triangle (tiles of 96 or 128): Hs is exactly
+ * symmetric, with the entries of its diagonal tiles averaged with their
+ * transposes and the rest mirrored from the upper triangle (the generalized
+ * eigensolver of Sec. V-B.3 reads one triangle). */
 int xls_subdomain_project(xls_subdomain_t s, int32_t gemm_prec, double* M, double* Hs);
 
 /* Rotation (step (4)): block <- block * Q, Q ns x ns column-major FP64,

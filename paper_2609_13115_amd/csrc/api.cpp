@@ -180,7 +180,7 @@ void project_block(xls_subdomain_s* s, int gprec) {
   apply_H<TS>(s, Bc, W, s->ns, static_cast<TS*>(s->alpha));
   gemm_tn<TS>(gprec, Bc, s->ld, Bc, s->ld, s->ns, s->ns, s->nd, s->Mdev, s->ns, 1, 0, s->gwork,
               s->gwork_elems, s->st, s->gplan);
-  gemm_tn<TS>(gprec, Bc, s->ld, W, s->ld, s->ns, s->ns, s->nd, s->Hsdev, s->ns, 0, 1, s->gwork,
+  gemm_tn<TS>(gprec, Bc, s->ld, W, s->ld, s->ns, s->ns, s->nd, s->Hsdev, s->ns, 1, 1, s->gwork,
               s->gwork_elems, s->st, s->gplan);
 }
 
@@ -390,7 +390,7 @@ void chefsi_loop(xls_subdomain_s* s, const xls_chefsi_params_t* p, int gprec, in
       tm.mark();
       gemm_tn<TS>(pprec, Bc, s->ld, Bc, s->ld, ns, ns, s->nd, s->Mdev, ns, 1, 0, s->gwork, s->gwork_elems,
                   s->st, s->gplan);
-      gemm_tn<TS>(pprec, Bc, s->ld, W, s->ld, ns, ns, s->nd, s->Hsdev, ns, 0, 1, s->gwork, s->gwork_elems,
+      gemm_tn<TS>(pprec, Bc, s->ld, W, s->ld, ns, ns, s->nd, s->Hsdev, ns, 1, 1, s->gwork, s->gwork_elems,
                   s->st, s->gplan);
     }
     tm.mark();
@@ -1282,7 +1282,7 @@ int xls_subdomain_time_gemms(xls_subdomain_t s, int32_t gemm_prec, int32_t reps,
           gemm_tn<TS>(gemm_prec, Bc, s->ld, Bc, s->ld, s->ns, s->ns, s->nd, s->Mdev, s->ns, 1, 0, s->gwork,
                       s->gwork_elems, s->st, s->gplan);
         else if (which == 1)
-          gemm_tn<TS>(gemm_prec, Bc, s->ld, W, s->ld, s->ns, s->ns, s->nd, s->Hsdev, s->ns, 0, 1, s->gwork,
+          gemm_tn<TS>(gemm_prec, Bc, s->ld, W, s->ld, s->ns, s->ns, s->nd, s->Hsdev, s->ns, 1, 1, s->gwork,
                       s->gwork_elems, s->st, s->gplan);
         else  // into the spare block: the current block is left as it was
           gemm_nn<TS>(gemm_prec, Bc, s->ld, s->Ydev, s->ns, static_cast<int>(s->nd), s->ns, s->ns, W, s->ld,

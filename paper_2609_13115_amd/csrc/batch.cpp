@@ -188,7 +188,7 @@ void tail_stages(xls_subdomain_s* s, const SubState& ss, int cur_f, double* coef
   TS* W = B<TS>(s, 1 - cur_f);
   apply_H<TS>(s, Bc, W, ns, static_cast<TS*>(s->alpha));
   gemm_tn<TS>(ss.pprec, Bc, s->ld, Bc, s->ld, ns, ns, s->nd, s->Mdev, ns, 1, 0, s->gwork, s->gwork_elems, s->st, s->gplan);
-  gemm_tn<TS>(ss.pprec, Bc, s->ld, W, s->ld, ns, ns, s->nd, s->Hsdev, ns, 0, 1, s->gwork, s->gwork_elems, s->st, s->gplan);
+  gemm_tn<TS>(ss.pprec, Bc, s->ld, W, s->ld, ns, ns, s->nd, s->Hsdev, ns, 1, 1, s->gwork, s->gwork_elems, s->st, s->gplan);
   (void)dense_geneig(s->dw, s->Hsdev, s->Mdev, s->Ydev, s->st, /*check_spd=*/false);
   XLS_HIP(hipMemcpyAsync(s->lam_dev, s->dw.lam(), ns * 8, hipMemcpyDeviceToDevice, s->st));
   // Psi <- Psi_f Y into the other buffer
@@ -693,7 +693,7 @@ std::string gemm_key(xls_subdomain_s* s) {
   return o.str();
 }
 
-// Average device ms of the projection Psi^T (H Psi) (symmetrised) and the
+// Average device ms of the projection Psi^T (H Psi) (upper triangle) and the
 // rotation Psi Q under plan g, on the current block and the spare one.
 template <typename TS>
 std::array<double, 2> time_gemm_plan(xls_subdomain_s* s, const GemmPlan& g, hipEvent_t e0, hipEvent_t e1) {
@@ -704,7 +704,7 @@ std::array<double, 2> time_gemm_plan(xls_subdomain_s* s, const GemmPlan& g, hipE
   for (int which = 0; which < 2; ++which) {
     auto once = [&]() {
       if (which == 0)
-        gemm_tn<TS>(gprec, Bc, s->ld, Bc, s->ld, s->ns, s->ns, s->nd, s->Hsdev, s->ns, 0, 1, s->gwork,
+        gemm_tn<TS>(gprec, Bc, s->ld, Bc, s->ld, s->ns, s->ns, s->nd, s->Hsdev, s->ns, 1, 1, s->gwork,
                     s->gwork_elems, s->st, g);
       else
         gemm_nn<TS>(gprec, Bc, s->ld, s->Ydev, s->ns, static_cast<int>(s->nd), s->ns, s->ns, W, s->ld, s->bwork,

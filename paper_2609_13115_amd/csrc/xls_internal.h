@@ -147,8 +147,12 @@ size_t stencil_partial_elems(const OpTables<double>& op, int ncols, const Stenci
 
 // GEMMs.  Matrices column-major.
 //   gemm_tn: C[M x N] = A^T B, A is K x M (lda), B is K x N (ldb); FP64 result.
-//            sym = 1: only C's upper tiles are formed, then mirrored (A == B).
-//            symmetrize = 1: C = (S + S^T)/2 (M == N).
+//            sym = 1: only C's upper tiles are formed, then mirrored.
+//            symmetrize = 1: C = (S + S^T)/2 (M == N); with sym = 1 too,
+//            the entries of diagonal tiles are averaged with their
+//            transposes and the rest mirrored from the upper tiles (the
+//            projected Hamiltonian, of which the eigensolver reads one
+//            triangle).
 //   gemm_nn: C[M x N] = A[M x K] B[K x N]; B given in FP64 and converted
 //            (or padded) into bwork, nn_work_doubles(K, N) doubles, 16-byte
 //            aligned; bwork may be null only for FP64 calls (the small-tile

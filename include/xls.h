@@ -139,7 +139,8 @@ int xls_subdomain_create(const xls_subdomain_desc_t* desc, xls_subdomain_t* out)
 
 /* Run up to p->max_iter CheFSI iterations on the handle's block (Sec. V-A.3):
  * filter Psi_f = p_m(H) Psi (scaled three-term recurrence, p(a0) = 1);
- * M_s = Psi_f^T Psi_f and H_s = (Psi_f^T H Psi_f symmetrised); Cholesky
+ * M_s = Psi_f^T Psi_f and H_s = Psi_f^T H Psi_f (upper block triangles;
+ * H_s's diagonal tiles averaged with their transposes); Cholesky
  * M_s = R^T R; C = R^-T H_s R^-1; C = Z Lambda Z^T; Psi = Psi_f R^-1 Z;
  * residuals r_n = ||H psi_n - lambda_n psi_n||_2 in FP64 arithmetic.
  * Outputs: ritz[ns], resid[ns], *iters_done.  With an FP64 block and FP64
@@ -337,7 +338,8 @@ int xls_get_stage_times(xls_subdomain_t s, double* ms, int64_t* counts, int32_t 
  * Sec. V-A.3: M_s = Psi^T Psi, H_s = Psi^T (H Psi), Psi Q) on the handle's
  * current block in precision gemm_prec (XLS_PREC_*; FP64 handles take FP64), from
  * HIP events around reps back-to-back launches after one warm-up:
- * ms[0] Psi^T Psi (symmetric), ms[1] Psi^T (H Psi) (symmetrized), ms[2]
+ * ms[0] Psi^T Psi, ms[1] Psi^T (H Psi) (both on their upper block
+ * triangle), ms[2]
  * Psi Q into the spare block (Q = I).  H Psi is computed first (untimed);
  * the current block is not changed.  ms holds 3 doubles; returns 3.
  * Errors: INVALID_ARG (NULL, reps < 1, precision). */

@@ -172,7 +172,8 @@ void filter_block(xls_subdomain_s* s, int m, double a0, double lc, double lmax) 
   }
 }
 
-// M = B^T B and Hs = sym(B^T H B) of the current block (W = H B in the other buffer).
+// M = B^T B and Hs = B^T H B (upper block triangles, Hs exactly symmetric) of
+// the current block (W = H B in the other buffer).
 template <typename TS>
 void project_block(xls_subdomain_s* s, int gprec) {
   TS* Bc = B<TS>(s, s->cur);

@@ -539,6 +539,9 @@ def main():
     ap.add_argument("--headline-only", action="store_true", help="only the 64^3 steps (profiling runs)")
     ap.add_argument("--widened-only", action="store_true",
                     help="only the widened rows (warm-start steps, PDOS, Poisson; profiling runs)")
+    ap.add_argument("--batch-only", type=int, default=0, metavar="N",
+                    help="only the first N subdomains of the uneven batch draw in the mixed form with Lanczos "
+                         "bounds (profiling runs)")
     ap.add_argument("--budget-s", type=float, default=720.0,
                     help="skip the optional learned_gain leg once this many seconds have passed")
     ap.add_argument("--write-traffic", nargs=3, metavar=("FORM", "FETCH_CSV", "WRITE_CSV"),
@@ -561,6 +564,10 @@ def main():
     sd.x0 = x0
     if a.widened_only:
         print(json.dumps({"widened": widened_rows(sd), "wall_s": time.perf_counter() - T_START}), flush=True)
+        return
+    if a.batch_only > 0:
+        print(json.dumps({"batch": run_cfg3(a.batch_only, ["mixed"]), "wall_s": time.perf_counter() - T_START}),
+              flush=True)
         return
     if a.calib_mib > 0:
         src = torch.empty(a.calib_mib << 20, dtype=torch.uint8, device="cuda")

@@ -41,6 +41,7 @@ constexpr int kPanel = 32;       // Cholesky panel width
 constexpr int kInvIters = 3;     // inverse-iteration solves per vector in a cluster (2 when alone)
 constexpr int kInvChunk = 16;    // steps of a sequential sweep whose inputs load together
 constexpr double kOrtol = 1e-3;  // cluster gap, relative to |T|_1
+constexpr int kSturmChunk = 16;  // rows of a Sturm-count recurrence read per LDS batch
 constexpr int kTrdPre = 8;       // column values per lane loaded ahead in a tridiagonalisation step
 constexpr int kTrdTail = 128;    // trailing steps done in one workgroup, block in LDS (m (m + 2) + 2m doubles);
                                  // the tail kernel's update gives each lane two rows, so at most 128
@@ -743,10 +744,26 @@ __global__ __launch_bounds__(64) void tri_multisect_kernel(const double* __restr
     double q = dd[0] - x;
     if (fabs(q) < pivmin) q = -pivmin;
     cnt += q < 0.0;
-    for (int j = 1; j < m; ++j) {
-      q = (dd[j] - x) - ee[j - 1] * rcp_nr(q);
-      if (fabs(q) < pivmin) q = -pivmin;
-      cnt += q < 0.0;
+    // The recurrence in chunks of kSturmChunk rows whose d and e^2 are read
+    // from LDS up front (clamped, in range): the chain then waits on its
+    // own arithmetic only, not on an LDS read per row.  Same operations in
+    // the same order as a row-by-row loop.
+    for (int j0 = 1; j0 < m; j0 += kSturmChunk) {
+      double dv[kSturmChunk], ev[kSturmChunk];
+#pragma unroll
+      for (int t = 0; t < kSturmChunk; ++t) {
+        const int j = min(j0 + t, m - 1);
+        dv[t] = dd[j];
+        ev[t] = ee[j - 1];
+      }
+#pragma unroll
+      for (int t = 0; t < kSturmChunk; ++t) {
+        if (j0 + t < m) {
+          q = (dv[t] - x) - ev[t] * rcp_nr(q);
+          if (fabs(q) < pivmin) q = -pivmin;
+          cnt += q < 0.0;
+        }
+      }
     }
     const uint64_t above = __ballot(cnt > l);
     const double xprev = __shfl_up(x, 1, 64);

@@ -559,15 +559,15 @@ def main():
 
     torch.cuda.set_device(0)
     torch.cuda.synchronize()
+    if a.batch_only > 0:
+        print(json.dumps({"batch": run_cfg3(a.batch_only, ["mixed"]), "wall_s": time.perf_counter() - T_START}),
+              flush=True)
+        return
     sd = workloads.si_box_64(with_x0=False, ns=a.ns)
     x0 = sd.make_x0(a.ns)
     sd.x0 = x0
     if a.widened_only:
         print(json.dumps({"widened": widened_rows(sd), "wall_s": time.perf_counter() - T_START}), flush=True)
-        return
-    if a.batch_only > 0:
-        print(json.dumps({"batch": run_cfg3(a.batch_only, ["mixed"]), "wall_s": time.perf_counter() - T_START}),
-              flush=True)
         return
     if a.calib_mib > 0:
         src = torch.empty(a.calib_mib << 20, dtype=torch.uint8, device="cuda")
